@@ -1,0 +1,92 @@
+"""Structured triangulations and Taylor-Hood P2/P1 node numbering (oracle side).
+
+Meshes are the "regular triangular meshes" of Section 4: every square cell
+[x_i, x_i+h] x [y_k, y_k+h] is cut by its rising diagonal into the triangles
+(v00, v10, v11) and (v00, v11, v01), both counter-clockwise.
+
+Numbering (the oracle's own, unrelated to the GPU library's):
+  * vertices in row-major order of the vertex grid (y slowest), only those
+    that belong to a kept cell;
+  * P2 nodes = all vertices, then one node per edge in order of first
+    appearance while walking the elements and their edges (01, 12, 20);
+  * P1 (pressure) nodes = vertices, same numbers as their P2 node.
+Element connectivity: (v0, v1, v2, m01, m12, m20) with m_ab the edge midpoint.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+
+@dataclass
+class Mesh:
+    xy: np.ndarray          # (nP2, 2) node coordinates; first nV rows are the vertices
+    tri: np.ndarray         # (n_el, 6) P2 connectivity
+    nV: int                 # number of vertices = P1 nodes
+    bnd: np.ndarray         # sorted P2 node ids on the boundary
+
+    @property
+    def n_el(self):
+        return len(self.tri)
+
+    @property
+    def nP2(self):
+        return len(self.xy)
+
+    @property
+    def nP1(self):
+        return self.nV
+
+    @property
+    def n(self):
+        return 2 * self.nP2 + self.nV
+
+
+def _build(nx, ny, h, keep, x0=0.0, y0=0.0):
+    """Cells (i,k), 0<=i<nx, 0<=k<ny with keep(i,k) True, spacing h."""
+    vid = -np.ones((ny + 1, nx + 1), dtype=np.int64)
+    cells = [(i, k) for k in range(ny) for i in range(nx) if keep(i, k)]
+    used = np.zeros((ny + 1, nx + 1), dtype=bool)
+    for i, k in cells:
+        used[k:k + 2, i:i + 2] = True
+    ks, is_ = np.nonzero(used)            # row-major: k slowest
+    vid[ks, is_] = np.arange(len(ks))
+    vxy = np.stack([x0 + is_ * h, y0 + ks * h], axis=1).astype(float)
+    tris = []
+    for i, k in cells:
+        a, b, c, d = vid[k, i], vid[k, i + 1], vid[k + 1, i + 1], vid[k + 1, i]
+        tris.append((a, b, c))
+        tris.append((a, c, d))
+    tris = np.array(tris, dtype=np.int64)
+    nV = len(vxy)
+    edge_id = {}
+    edge_count = {}
+    conn = np.zeros((len(tris), 6), dtype=np.int64)
+    conn[:, :3] = tris
+    for e, (a, b, c) in enumerate(tris):
+        for slot, (p, q) in zip((3, 4, 5), ((a, b), (b, c), (c, a))):
+            key = (min(p, q), max(p, q))
+            if key not in edge_id:
+                edge_id[key] = len(edge_id)
+                edge_count[key] = 0
+            edge_count[key] += 1
+            conn[e, slot] = nV + edge_id[key]
+    keys = sorted(edge_id, key=edge_id.get)
+    mid = np.array([(vxy[p] + vxy[q]) / 2 for p, q in keys])
+    xy = np.vstack([vxy, mid])
+    bset = set()
+    for key in keys:
+        if edge_count[key] == 1:
+            bset.update((key[0], key[1], nV + edge_id[key]))
+    return Mesh(xy=xy, tri=conn, nV=nV, bnd=np.array(sorted(bset), dtype=np.int64))
+
+
+def unit_square(N: int) -> Mesh:
+    """N x N cells on the unit square, h = 1/N."""
+    return _build(N, N, 1.0 / N, lambda i, k: True)
+
+
+def step_channel(m: int = 16) -> Mesh:
+    """[0,30] x [0,10] minus [0,1] x [0,1] with h = 1/m."""
+    return _build(30 * m, 10 * m, 1.0 / m, lambda i, k: not (i < m and k < m))
