@@ -133,11 +133,12 @@ class Ensemble:
         J = x.shape[1]
         Z = x[:2 * nP2].reshape(nP2, 2, J)
         p = x[2 * nP2:]
-        p = p - (self.mP1 @ p) / self.mP1.sum()
+        if self.pin is not None:      # pressure determined up to a constant: report zero mean
+            p = p - (self.mP1 @ p) / self.mP1.sum()
         return Z, p
 
     def step(self, V, W, t_next, shared_lu=False, members=None):
-        """Algorithm 1, one step: returns V^{n+1}, W^{n+1}, q^{n+1}, r^{n+1} (zero-mean)."""
+        """Algorithm 1, one step: returns V^{n+1}, W^{n+1}, q^{n+1}, r^{n+1} (zero mean when pinned)."""
         xy = self.mesh.xy
         F1, F2 = self.pb.forcing(t_next, xy)
         Gv, Gw = self.pb.bc(t_next, xy)
