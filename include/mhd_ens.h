@@ -1,0 +1,233 @@
+/*
+ * mhd_ens.h -- C ABI of the MI355X ensemble MHD time-step library (libmhd_ens.so).
+ *
+ * The library computes one time step of the decoupled ensemble scheme for the
+ * Elsasser variables v = u + sqrt(s) B, w = u - sqrt(s) B (paper, Section 1,
+ * (els1)-(els3)), fully discretised as Algorithm 1 of Section 3 ((weaknew1),
+ * (weaknew2)) with Taylor-Hood P2-P1 elements on structured triangulations.
+ * In each step the v-subproblem and the w-subproblem have ONE coefficient
+ * matrix shared by all J members (Section 1: A [x_1|...|x_J] = [b_1|...|b_J]),
+ * assembled from the ensemble mean of the other variable, the mean
+ * viscosities and the mixing-length eddy viscosity nu_T = mu dt l^2,
+ * l(x) = max_j |z_j'(x)|; the J right-hand sides carry each member's explicit
+ * fluctuation terms.
+ *
+ * Conventions for every call:
+ *  - Return value: mhd_status.  MHD_OK on success; on failure a message is
+ *    available from mhd_ens_last_error() (thread-local).  Argument checks
+ *    happen on the host before any device work is enqueued.
+ *  - Device arrays are plain device pointers (hipMalloc'd or from a tensor
+ *    allocator) owned by the caller; they must stay valid until the work
+ *    enqueued on the given stream has completed.  Host arrays are marked
+ *    "host".  Opaque handles are owned by the library and freed by their
+ *    *_free call.
+ *  - Member blocks are row-major with the member index fastest:
+ *      vector P2 field  (nP2, 2, J):  z[(i*2 + c)*J + j]
+ *      scalar P1 field  (nP1, J):     p[k*J + j]
+ *      unknown block    (n, J):       velocity rows 2*i + c (i P2 node,
+ *                                     c component) then pressure rows
+ *                                     2*nP2 + k, n = 2 nP2 + nP1.
+ *  - Node numbering: P2 nodes are the points of the (2 nx + 1) x (2 ny + 1)
+ *    half-step grid of the cell grid that belong to a kept cell, in row-major
+ *    order (y slowest); P1 nodes are the vertices (even half-step grid points)
+ *    in the same order.  mhd_ens_mesh_coords returns the coordinates.
+ *  - All device work is asynchronous on the caller's stream (0 = the null
+ *    stream).  Calls that fill host statistics synchronise that stream.
+ *  - No call after creation allocates device memory: every workspace is
+ *    sized at creation time from (mesh, J_max, restart).
+ */
+#ifndef MHD_ENS_H
+#define MHD_ENS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int mhd_status;
+#define MHD_OK        0
+#define MHD_EINVAL   (-1)   /* invalid argument (null pointer, bad size, bad enum)   */
+#define MHD_ENOMEM   (-2)   /* device or host allocation failed                      */
+#define MHD_EHIP     (-3)   /* a HIP runtime call failed (message names it)          */
+#define MHD_ENOCONV  (-4)   /* solver hit maxit: best iterate written, stats filled  */
+#define MHD_ESHAPE   (-5)   /* J larger than the handle was created for, or mesh mismatch */
+
+typedef enum { MHD_FP64 = 0, MHD_FP32_IR = 1 } mhd_precision;
+typedef enum { MHD_MESH_UNIT_SQUARE = 0, MHD_MESH_STEP_CHANNEL = 1 } mhd_mesh_kind;
+typedef enum { MHD_V_PROBLEM = 0, MHD_W_PROBLEM = 1 } mhd_which;
+
+typedef void* mhd_stream_t;            /* a hipStream_t */
+typedef struct mhd_mesh_s*   mhd_mesh;
+typedef struct mhd_shared_s* mhd_shared;
+typedef struct mhd_ctx_s*    mhd_ctx;
+
+/* Mesh description (paper, Section 4: regular triangulations; every square
+ * cell is cut by its rising diagonal).
+ *   MHD_MESH_UNIT_SQUARE: [0,1]^2 with nx = ny = N cells per side.
+ *   MHD_MESH_STEP_CHANNEL: [0,30]x[0,10] minus [0,1]x[0,1], h = 1/m with
+ *     nx = m (cells per unit length); outflow x = 30.
+ * natural_outflow: 1 = do-nothing condition on x = 30 (step channel only),
+ *   0 = Dirichlet on the whole boundary.  With a fully Dirichlet boundary the
+ *   pressure is pinned at the vertex (0,0) (identity row) because it is
+ *   determined only up to a constant (Section 2, Q = L^2_0). */
+typedef struct {
+    int kind;
+    int nx;
+    int natural_outflow;
+} mhd_mesh_desc;
+
+typedef struct {
+    int64_t n_el, nP2, nP1, n_u, n;     /* n_u = 2 nP2, n = n_u + nP1            */
+    int64_t nnz_A, nnz_B;               /* scalar P2-P2 pattern, P1-P2 pattern   */
+    int64_t nnz;                        /* nonzeros of the full saddle-point CSR */
+    int64_t n_bd, n_dir;                /* boundary P2 nodes, Dirichlet P2 nodes */
+    int32_t pin;                        /* pinned pressure node, -1 if none      */
+    int32_t mg_levels;                  /* pressure multigrid levels             */
+} mhd_mesh_info;
+
+/* Host-only: counts of a mesh without creating it (no device needed). */
+mhd_status mhd_ens_mesh_counts(const mhd_mesh_desc* d, mhd_mesh_info* info);
+
+/* Builds the mesh, the CSR patterns of the saddle-point operator, the
+ * element-to-slot maps and the pressure multigrid hierarchy, and uploads
+ * them to the current device.  info (host) may be NULL. */
+mhd_status mhd_ens_mesh(const mhd_mesh_desc* d, mhd_mesh* out, mhd_mesh_info* info);
+
+/* Host copies: xy_p2 (nP2*2 doubles, may be NULL), dir_nodes (n_dir int32:
+ * the Dirichlet P2 nodes in the order bc arrays use, may be NULL). */
+mhd_status mhd_ens_mesh_coords(mhd_mesh m, double* xy_p2, int32_t* dir_nodes);
+mhd_status mhd_ens_mesh_free(mhd_mesh m);
+
+/* Coefficients of one subproblem (Algorithm 1): time step dt, eddy tuning
+ * mu (nu_T = mu dt l^2), mean viscosity nu_bar and diffusivity num_bar
+ * ((nu_bar + num_bar)/2 multiplies the implicit Laplacian), convective form:
+ * 0 = skew-symmetric b*(u,v,w) = (b(u,v,w) - b(u,w,v))/2, 1 = b(u,v,w) as
+ * written in Section 2. */
+typedef struct {
+    double dt, mu, nu_bar, num_bar;
+    int convective;
+} mhd_coeffs;
+
+/* Shared-matrix handle: the CSR values of one subproblem's saddle-point
+ * matrix S = [[A (x) I_2, B^T], [B, D_p]] (FP64 master + FP32 shadow) and the
+ * solver workspace for up to J_max right-hand sides and a Krylov restart
+ * length `restart`. */
+mhd_status mhd_ens_shared_create(mhd_mesh m, int J_max, int restart, mhd_shared* out);
+mhd_status mhd_ens_shared_free(mhd_shared A);
+
+/* (Algorithm 1, left-hand sides of (weaknew1)/(weaknew2)) Assembles
+ *   A = M/dt + b*(<z>, ., .) + (nu_bar+num_bar)/2 K + K[2 mu dt l_z^2]
+ * from the OTHER variable's members z_other (device, (nP2,2,J) FP64):
+ * computes the ensemble mean <z> and l_z^2 = max_j |z_j - <z>|^2 at the 7
+ * quadrature points of every element, then the element matrices, gathered
+ * into the CSR values deterministically (no atomics).  Dirichlet rows
+ * become identity rows; the pinned pressure row becomes an identity row. */
+mhd_status mhd_ens_assemble_shared(mhd_mesh m, const mhd_coeffs* c, const double* z_other,
+                                   int J, mhd_shared A, mhd_stream_t s);
+
+/* Borrowed device views of the assembled operator (valid until the next
+ * assemble or free).  Scalar P2 block A: rowptr_A (nP2+1), col_A (nnz_A),
+ * val_A (nnz_A, FP64).  B^T: rowptr_Bt (nP2+1), col_Bt (P1 ids), val_Bt
+ * (2 per entry: x then y component).  B: rowptr_B (nP1+1), col_B (P2 ids),
+ * val_B (2 per entry).  D_p: (nP1) pressure diagonal (1 at the pin, else 0). */
+typedef struct {
+    const int32_t *rowptr_A, *col_A, *rowptr_Bt, *col_Bt, *rowptr_B, *col_B;
+    const double *val_A, *val_Bt, *val_B, *diag_p;
+    const float* val_A32;
+    int64_t nP2, nP1, nnz_A, nnz_Bt, nnz_B;
+} mhd_csr_view;
+mhd_status mhd_ens_shared_csr(mhd_shared A, mhd_csr_view* view);
+
+/* (Algorithm 1, right-hand sides of (weaknew1)/(weaknew2)) For which =
+ * MHD_V_PROBLEM (self = v, other = w, forcing f_1) or MHD_W_PROBLEM
+ * (self = w, other = v, forcing f_2), for every member j:
+ *   b_j = M (self_j/dt + f_j) - b*(other_j - <other>, self_j, .)
+ *         - (nu_j - num_j)/2 K other_j - (nu_j' + num_j')/2 K self_j
+ * on velocity rows; Dirichlet rows take bc_vals; pressure rows 0.
+ *   self_n, other_n: device (nP2,2,J) FP64 at t^n
+ *   nu, nu_m:        device (J) FP64 member viscosities / diffusivities
+ *   forcing:         device (nP2,2,J) FP64 nodal f at t^{n+1}, or NULL (= 0)
+ *   bc_vals:         device (n_dir,2,J) FP64 Dirichlet values at t^{n+1},
+ *                    in mhd_ens_mesh_coords' dir_nodes order
+ *   rhs:             device (n,J) FP64 output
+ * The forcing functional (f, chi) is taken as M times the nodal interpolant. */
+mhd_status mhd_ens_assemble_rhs(mhd_mesh m, const mhd_coeffs* c, int which, int J,
+                                const double* self_n, const double* other_n,
+                                const double* nu, const double* nu_m,
+                                const double* forcing, const double* bc_vals,
+                                double* rhs, mhd_stream_t s);
+
+/* Solver options.  precision: MHD_FP64 (all Krylov work in FP64) or
+ * MHD_FP32_IR (FP32 SpMM/preconditioner/Krylov vectors inside FP64 iterative
+ * refinement: r = b - S x in FP64, S d = r in FP32, x += d).  rtol: target
+ * per member ||b_j - S x_j||_2 / ||b_j||_2.  inner_rtol: reduction asked of
+ * each inner Krylov cycle.  maxit: total inner iterations.  restart: Krylov
+ * length per cycle (<= the handle's restart). */
+typedef struct {
+    int precision;
+    double rtol;
+    double inner_rtol;
+    int maxit;
+    int restart;
+    int jacobi_sweeps;        /* velocity-block smoothing sweeps in the preconditioner */
+    int check_every;          /* inner iterations between convergence checks (>= 1)    */
+} mhd_solver_opts;
+
+typedef struct {
+    int iters;                /* total inner Krylov iterations                        */
+    int cycles;               /* outer refinement / restart cycles                    */
+    double max_relres;        /* max over members of the final relative residual      */
+    int converged;            /* 1 if every member reached rtol                       */
+} mhd_solve_stats;
+
+/* (Section 1: A [x_1|...|x_J] = [b_1|...|b_J]) Solves S X = B for the J
+ * member columns with the assembled shared matrix: right-preconditioned
+ * restarted GMRES with one Arnoldi process per member, one SpMM over all J
+ * columns per iteration, block-triangular preconditioner (Jacobi sweeps on
+ * A, Cahouet-Chabard Schur approximation with a multigrid V-cycle on the P1
+ * pressure Laplacian).  rhs (n,J) FP64 device; x (n,J) FP64 device: initial
+ * guess in, solution out.  st (host) may be NULL; if non-NULL the stream is
+ * synchronised.  Returns MHD_ENOCONV (x = best iterate) if maxit is hit. */
+mhd_status mhd_ens_solve(mhd_shared A, const double* rhs, double* x, int J,
+                         const mhd_solver_opts* o, mhd_solve_stats* st, mhd_stream_t s);
+
+/* Full-step context: owns both subproblems' shared matrices, right-hand
+ * sides and solver workspace for up to J_max members. */
+typedef struct {
+    mhd_coeffs coeffs;        /* nu_bar/num_bar are recomputed from nu, nu_m each step */
+    mhd_solver_opts solver;
+    int J_max;
+} mhd_ctx_desc;
+mhd_status mhd_ens_ctx_create(mhd_mesh m, const mhd_ctx_desc* d, mhd_ctx* out);
+mhd_status mhd_ens_ctx_free(mhd_ctx ctx);
+
+typedef struct {
+    const double *nu, *nu_m;      /* host (J) member parameters (read at call time)        */
+    const double *f1, *f2;        /* device (nP2,2,J) forcing at t^{n+1}, or NULL          */
+    const double *g_v, *g_w;      /* device (n_dir,2,J) Dirichlet data at t^{n+1}          */
+    int J;
+} mhd_step_inputs;
+
+typedef struct {
+    mhd_solve_stats v, w;
+    double energy;                /* E_h^{n+1} = (||<v>||^2 + ||<w>||^2)/2 (Section 4.2)   */
+} mhd_step_stats;
+
+/* (Algorithm 1, one step n -> n+1 for all members) V, W: device (nP2,2,J)
+ * FP64, in: t^n, out: t^{n+1}.  Q, R: device (nP1,J) FP64, in: pressure of
+ * t^n (initial guess), out: pressures of t^{n+1} (zero mean when the pressure
+ * is pinned).  st (host) may be NULL (then no synchronisation). */
+mhd_status mhd_ens_step(mhd_ctx ctx, double* V, double* W, double* Q, double* R,
+                        const mhd_step_inputs* in, mhd_step_stats* st, mhd_stream_t s);
+
+/* Last error message of the calling thread ("" if none). */
+const char* mhd_ens_last_error(void);
+
+/* Library version string. */
+const char* mhd_ens_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MHD_ENS_H */

@@ -1,0 +1,230 @@
+"""ctypes binding of libmhd_ens.so (argument marshalling only).
+
+Every function here forwards to the C entry point of the same name declared
+in include/mhd_ens.h; all numerical work happens in the library's HIP
+kernels.  Device arrays are passed as raw pointers taken from torch tensors,
+streams as the raw hipStream_t of a torch stream.  If the library is missing
+the import fails loudly: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libmhd_ens.so")
+
+MHD_OK, MHD_EINVAL, MHD_ENOMEM, MHD_EHIP, MHD_ENOCONV, MHD_ESHAPE = 0, -1, -2, -3, -4, -5
+MHD_FP64, MHD_FP32_IR = 0, 1
+MHD_MESH_UNIT_SQUARE, MHD_MESH_STEP_CHANNEL = 0, 1
+MHD_V_PROBLEM, MHD_W_PROBLEM = 0, 1
+
+# Public symbols of include/mhd_ens.h (checked by the CPU test-suite).
+EXPORTS = (
+    "mhd_ens_mesh_counts", "mhd_ens_mesh", "mhd_ens_mesh_coords", "mhd_ens_mesh_free",
+    "mhd_ens_shared_create", "mhd_ens_shared_free", "mhd_ens_assemble_shared", "mhd_ens_shared_csr",
+    "mhd_ens_assemble_rhs", "mhd_ens_solve", "mhd_ens_ctx_create", "mhd_ens_ctx_free", "mhd_ens_step",
+    "mhd_ens_last_error", "mhd_ens_version",
+)
+
+
+class MeshDesc(C.Structure):
+    _fields_ = [("kind", C.c_int), ("nx", C.c_int), ("natural_outflow", C.c_int)]
+
+
+class MeshInfo(C.Structure):
+    _fields_ = [("n_el", C.c_int64), ("nP2", C.c_int64), ("nP1", C.c_int64), ("n_u", C.c_int64),
+                ("n", C.c_int64), ("nnz_A", C.c_int64), ("nnz_B", C.c_int64), ("nnz", C.c_int64),
+                ("n_bd", C.c_int64), ("n_dir", C.c_int64), ("pin", C.c_int32), ("mg_levels", C.c_int32)]
+
+
+class Coeffs(C.Structure):
+    _fields_ = [("dt", C.c_double), ("mu", C.c_double), ("nu_bar", C.c_double), ("num_bar", C.c_double),
+                ("convective", C.c_int)]
+
+
+class CSRView(C.Structure):
+    _fields_ = [("rowptr_A", C.c_void_p), ("col_A", C.c_void_p), ("rowptr_Bt", C.c_void_p),
+                ("col_Bt", C.c_void_p), ("rowptr_B", C.c_void_p), ("col_B", C.c_void_p),
+                ("val_A", C.c_void_p), ("val_Bt", C.c_void_p), ("val_B", C.c_void_p), ("diag_p", C.c_void_p),
+                ("val_A32", C.c_void_p),
+                ("nP2", C.c_int64), ("nP1", C.c_int64), ("nnz_A", C.c_int64), ("nnz_Bt", C.c_int64),
+                ("nnz_B", C.c_int64)]
+
+
+class SolverOpts(C.Structure):
+    _fields_ = [("precision", C.c_int), ("rtol", C.c_double), ("inner_rtol", C.c_double), ("maxit", C.c_int),
+                ("restart", C.c_int), ("jacobi_sweeps", C.c_int), ("check_every", C.c_int)]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("iters", C.c_int), ("cycles", C.c_int), ("max_relres", C.c_double), ("converged", C.c_int)]
+
+
+class CtxDesc(C.Structure):
+    _fields_ = [("coeffs", Coeffs), ("solver", SolverOpts), ("J_max", C.c_int)]
+
+
+class StepInputs(C.Structure):
+    _fields_ = [("nu", C.POINTER(C.c_double)), ("nu_m", C.POINTER(C.c_double)), ("f1", C.c_void_p),
+                ("f2", C.c_void_p), ("g_v", C.c_void_p), ("g_w", C.c_void_p), ("J", C.c_int)]
+
+
+class StepStats(C.Structure):
+    _fields_ = [("v", SolveStats), ("w", SolveStats), ("energy", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Loads libmhd_ens.so (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIBPATH):
+            raise RuntimeError(f"{LIBPATH} is missing: build it with python -m paper_2108_05110_amd.build")
+        L = C.CDLL(LIBPATH)
+        P, I, D = C.c_void_p, C.c_int, C.c_double
+        sig = {
+            "mhd_ens_mesh_counts": [C.POINTER(MeshDesc), C.POINTER(MeshInfo)],
+            "mhd_ens_mesh": [C.POINTER(MeshDesc), C.POINTER(P), C.POINTER(MeshInfo)],
+            "mhd_ens_mesh_coords": [P, P, P],
+            "mhd_ens_mesh_free": [P],
+            "mhd_ens_shared_create": [P, I, I, C.POINTER(P)],
+            "mhd_ens_shared_free": [P],
+            "mhd_ens_assemble_shared": [P, C.POINTER(Coeffs), P, I, P, P],
+            "mhd_ens_shared_csr": [P, C.POINTER(CSRView)],
+            "mhd_ens_assemble_rhs": [P, C.POINTER(Coeffs), I, I, P, P, P, P, P, P, P, P],
+            "mhd_ens_solve": [P, P, P, I, C.POINTER(SolverOpts), C.POINTER(SolveStats), P],
+            "mhd_ens_ctx_create": [P, C.POINTER(CtxDesc), C.POINTER(P)],
+            "mhd_ens_ctx_free": [P],
+            "mhd_ens_step": [P, P, P, P, P, C.POINTER(StepInputs), C.POINTER(StepStats), P],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = C.c_int
+        L.mhd_ens_last_error.restype = C.c_char_p
+        L.mhd_ens_last_error.argtypes = []
+        L.mhd_ens_version.restype = C.c_char_p
+        L.mhd_ens_version.argtypes = []
+        _ = D
+        _lib = L
+    return _lib
+
+
+class MhdError(RuntimeError):
+    def __init__(self, name, status):
+        msg = lib().mhd_ens_last_error().decode()
+        super().__init__(f"{name} -> {status}: {msg}")
+        self.status = status
+
+
+def check(name, status, allow=(MHD_OK,)):
+    if status not in allow:
+        raise MhdError(name, status)
+    return status
+
+
+def ptr(t):
+    """Raw device (or host) pointer of a tensor / None."""
+    if t is None:
+        return None
+    return C.c_void_p(t.data_ptr())
+
+
+def stream_ptr(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+# ------------------------------------------------------------------ same-name wrappers
+def mhd_ens_mesh_counts(kind, nx, natural_outflow=0):
+    d = MeshDesc(kind, nx, natural_outflow)
+    info = MeshInfo()
+    check("mhd_ens_mesh_counts", lib().mhd_ens_mesh_counts(C.byref(d), C.byref(info)))
+    return info
+
+
+def mhd_ens_mesh(kind, nx, natural_outflow=0):
+    d = MeshDesc(kind, nx, natural_outflow)
+    h = C.c_void_p()
+    info = MeshInfo()
+    check("mhd_ens_mesh", lib().mhd_ens_mesh(C.byref(d), C.byref(h), C.byref(info)))
+    return h, info
+
+
+def mhd_ens_mesh_coords(mesh, info):
+    import numpy as np
+    xy = np.zeros((info.nP2, 2), dtype=np.float64)
+    dn = np.zeros(max(info.n_dir, 1), dtype=np.int32)
+    check("mhd_ens_mesh_coords", lib().mhd_ens_mesh_coords(mesh, xy.ctypes.data_as(C.c_void_p),
+                                                           dn.ctypes.data_as(C.c_void_p)))
+    return xy, dn[:info.n_dir].copy()
+
+
+def mhd_ens_mesh_free(mesh):
+    check("mhd_ens_mesh_free", lib().mhd_ens_mesh_free(mesh))
+
+
+def mhd_ens_shared_create(mesh, J_max, restart):
+    h = C.c_void_p()
+    check("mhd_ens_shared_create", lib().mhd_ens_shared_create(mesh, J_max, restart, C.byref(h)))
+    return h
+
+
+def mhd_ens_shared_free(A):
+    check("mhd_ens_shared_free", lib().mhd_ens_shared_free(A))
+
+
+def mhd_ens_assemble_shared(mesh, coeffs, z_other, J, A, stream=None):
+    check("mhd_ens_assemble_shared",
+          lib().mhd_ens_assemble_shared(mesh, C.byref(coeffs), ptr(z_other), J, A, stream_ptr(stream)))
+
+
+def mhd_ens_shared_csr(A):
+    v = CSRView()
+    check("mhd_ens_shared_csr", lib().mhd_ens_shared_csr(A, C.byref(v)))
+    return v
+
+
+def mhd_ens_assemble_rhs(mesh, coeffs, which, J, self_n, other_n, nu, nu_m, forcing, bc_vals, rhs, stream=None):
+    check("mhd_ens_assemble_rhs",
+          lib().mhd_ens_assemble_rhs(mesh, C.byref(coeffs), which, J, ptr(self_n), ptr(other_n), ptr(nu),
+                                     ptr(nu_m), ptr(forcing), ptr(bc_vals), ptr(rhs), stream_ptr(stream)))
+
+
+def mhd_ens_solve(A, rhs, x, J, opts, stream=None, allow_noconv=False):
+    st = SolveStats()
+    allow = (MHD_OK, MHD_ENOCONV) if allow_noconv else (MHD_OK,)
+    rc = check("mhd_ens_solve", lib().mhd_ens_solve(A, ptr(rhs), ptr(x), J, C.byref(opts), C.byref(st),
+                                                    stream_ptr(stream)), allow)
+    return st, rc
+
+
+def mhd_ens_ctx_create(mesh, desc):
+    h = C.c_void_p()
+    check("mhd_ens_ctx_create", lib().mhd_ens_ctx_create(mesh, C.byref(desc), C.byref(h)))
+    return h
+
+
+def mhd_ens_ctx_free(ctx):
+    check("mhd_ens_ctx_free", lib().mhd_ens_ctx_free(ctx))
+
+
+def mhd_ens_step(ctx, V, W, Q, R, inputs, stats=True, stream=None, allow_noconv=False):
+    st = StepStats() if stats else None
+    allow = (MHD_OK, MHD_ENOCONV) if allow_noconv else (MHD_OK,)
+    check("mhd_ens_step", lib().mhd_ens_step(ctx, ptr(V), ptr(W), ptr(Q), ptr(R), C.byref(inputs),
+                                             C.byref(st) if st is not None else None, stream_ptr(stream)), allow)
+    return st
+
+
+def solver_opts(precision=MHD_FP64, rtol=None, inner_rtol=None, maxit=2000, restart=30, jacobi_sweeps=2,
+                check_every=1):
+    if rtol is None:
+        rtol = 1e-12 if precision == MHD_FP64 else 1e-11
+    if inner_rtol is None:
+        inner_rtol = 1e-8 if precision == MHD_FP64 else 1e-4
+    return SolverOpts(precision, rtol, inner_rtol, maxit, restart, jacobi_sweeps, check_every)

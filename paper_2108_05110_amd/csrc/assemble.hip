@@ -1,0 +1,463 @@
+// Assembly kernels of libmhd_ens (gfx950):
+//   ensemble statistics (mean over members, eddy-viscosity length l^2 at the
+//   quadrature points), shared saddle-point matrix of one subproblem, constant
+//   mass/stiffness/divergence matrices, and the batched per-member right-hand
+//   sides of Algorithm 1 (paper, Section 3, (weaknew1)/(weaknew2)).
+//
+// Layouts: member blocks are row-major with the member index fastest, so the
+// J values of one node component are contiguous and a group of JP lanes
+// (JP = power of two >= min(J, 64)) reads them coalesced.  All reductions are
+// fixed-order (lane butterflies, per-slot gather lists): results are
+// bitwise reproducible run to run; there are no floating-point atomics.
+#include <hip/hip_runtime.h>
+
+#include "device.h"
+
+namespace mhd {
+
+__constant__ RefTables c_ref;
+
+void upload_ref_tables(const RefTables& t) { (void)hipMemcpyToSymbol(HIP_SYMBOL(c_ref), &t, sizeof(RefTables)); }
+
+namespace {
+
+constexpr int kBlock = 256;
+
+// Hardware dispatches workgroup b to XCD b % 8.  Give XCD x a contiguous range
+// of logical blocks so neighbouring rows (which share gathered operands) are
+// served from the same L2.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t G) {
+    int64_t q = G >> 3, r = G & 7, x = b & 7, s = b >> 3;
+    return x * q + (x < r ? x : r) + s;
+}
+
+struct Lanes {
+    int JP, sub, j0;
+    int64_t unit;
+};
+
+__device__ __forceinline__ Lanes lanes(int JP) {
+    Lanes L;
+    int lane = threadIdx.x & 63;
+    int wave = threadIdx.x >> 6;
+    int rpw = 64 / JP;
+    L.JP = JP;
+    L.sub = lane / JP;
+    L.j0 = lane % JP;
+    int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    L.unit = (blk * (kBlock / 64) + wave) * rpw + L.sub;
+    return L;
+}
+
+template <typename T>
+__device__ __forceinline__ T group_sum(T v, int JP) {
+    for (int off = JP >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ double group_max(double v, int JP) {
+    for (int off = JP >> 1; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+inline int pick_jp(int J) {
+    int p = 1;
+    while (p < J && p < 64) p <<= 1;
+    return p;
+}
+
+inline unsigned grid_for(int64_t units, int JP) {
+    int64_t per_block = (kBlock / 64) * (64 / JP);
+    return (unsigned)((units + per_block - 1) / per_block);
+}
+
+// -------------------------------------------------------------- (a1) ensemble mean
+__global__ void __launch_bounds__(kBlock) k_mean(const double* __restrict__ z, double* __restrict__ zbar,
+                                                 int64_t rows, int J, int JP) {
+    Lanes L = lanes(JP);
+    double acc = 0.0;
+    if (L.unit < rows)
+        for (int j = L.j0; j < J; j += JP) acc += z[L.unit * J + j];
+    acc = group_sum(acc, JP);
+    if (L.unit < rows && L.j0 == 0) zbar[L.unit] = acc / (double)J;
+}
+
+// -------------------------------------------------------------- (a1) l^2 = max_j |z_j'(x_q)|^2
+__global__ void __launch_bounds__(kBlock) k_eddy_l2(const int32_t* __restrict__ tri, const double* __restrict__ z,
+                                                    const double* __restrict__ zbar, double* __restrict__ l2,
+                                                    int n_el, int J, int JP) {
+    Lanes L = lanes(JP);
+    double mx[7];
+#pragma unroll
+    for (int q = 0; q < 7; ++q) mx[q] = 0.0;
+    if (L.unit < n_el) {
+        int t[6];
+        double zb[6][2];
+#pragma unroll
+        for (int a = 0; a < 6; ++a) {
+            t[a] = tri[L.unit * 6 + a];
+            zb[a][0] = zbar[2 * t[a]];
+            zb[a][1] = zbar[2 * t[a] + 1];
+        }
+        for (int j = L.j0; j < J; j += JP) {
+            double zv[6][2];
+#pragma unroll
+            for (int a = 0; a < 6; ++a) {
+                zv[a][0] = z[(int64_t)(2 * t[a]) * J + j] - zb[a][0];
+                zv[a][1] = z[(int64_t)(2 * t[a] + 1) * J + j] - zb[a][1];
+            }
+#pragma unroll
+            for (int q = 0; q < 7; ++q) {
+                double ux = 0.0, uy = 0.0;
+#pragma unroll
+                for (int a = 0; a < 6; ++a) {
+                    ux += c_ref.phi[q][a] * zv[a][0];
+                    uy += c_ref.phi[q][a] * zv[a][1];
+                }
+                mx[q] = fmax(mx[q], ux * ux + uy * uy);
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 7; ++q) mx[q] = group_max(mx[q], JP);
+    if (L.unit < n_el && L.j0 == 0)
+        for (int q = 0; q < 7; ++q) l2[L.unit * 7 + q] = mx[q];
+}
+
+// -------------------------------------------------------------- element geometry helpers
+struct Geo {
+    double det, Ji[2][2], G[2][2];
+};
+
+__device__ __forceinline__ Geo load_geo(const double* geo, int64_t e) {
+    Geo g;
+    g.det = geo[e * 6];
+    g.Ji[0][0] = geo[e * 6 + 1];
+    g.Ji[0][1] = geo[e * 6 + 2];
+    g.Ji[1][0] = geo[e * 6 + 3];
+    g.Ji[1][1] = geo[e * 6 + 4];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) g.G[a][b] = g.Ji[a][0] * g.Ji[b][0] + g.Ji[a][1] * g.Ji[b][1];
+    return g;
+}
+
+// -------------------------------------------------------------- (a2) element matrices of A
+// A_e = M_e/dt + nu_c K_e + N_e(<z>) + K_e[2 mu dt l^2]   (6 x 6 scalar, per element)
+__global__ void __launch_bounds__(kBlock) k_elem_A(const int32_t* __restrict__ tri, const double* __restrict__ geo,
+                                                   const double* __restrict__ zbar, const double* __restrict__ l2,
+                                                   double* __restrict__ elem, int n_el, double inv_dt, double nu_c,
+                                                   double eddy_c, int convective) {
+    int64_t e = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (e >= n_el) return;
+    Geo g = load_geo(geo, e);
+    double zh[6][2];
+    for (int b = 0; b < 6; ++b) {
+        int t = tri[e * 6 + b];
+        double z0 = zbar[2 * t], z1 = zbar[2 * t + 1];
+        zh[b][0] = g.det * (g.Ji[0][0] * z0 + g.Ji[0][1] * z1);
+        zh[b][1] = g.det * (g.Ji[1][0] * z0 + g.Ji[1][1] * z1);
+    }
+    double kap[7];
+    for (int q = 0; q < 7; ++q) kap[q] = 0.5 * g.det * c_ref.w[q] * eddy_c * l2[e * 7 + q];
+    for (int a = 0; a < 6; ++a)
+        for (int c = 0; c < 6; ++c) {
+            double v = g.det * c_ref.Mhat[a][c] * inv_dt;
+            double k = 0.0;
+            for (int p = 0; p < 2; ++p)
+                for (int r = 0; r < 2; ++r) k += c_ref.Khat[a][c][p][r] * g.G[p][r];
+            v += nu_c * g.det * k;
+            double cv = 0.0;
+            for (int b = 0; b < 6; ++b)
+                for (int p = 0; p < 2; ++p)
+                    cv += (convective ? c_ref.That[a][b][c][p] : c_ref.Shat[a][b][c][p]) * zh[b][p];
+            v += cv;
+            double ed = 0.0;
+            for (int q = 0; q < 7; ++q) {
+                double s = 0.0;
+                for (int p = 0; p < 2; ++p)
+                    for (int r = 0; r < 2; ++r) s += c_ref.dphi[q][a][p] * c_ref.dphi[q][c][r] * g.G[p][r];
+                ed += kap[q] * s;
+            }
+            elem[e * 36 + a * 6 + c] = v + ed;
+        }
+}
+
+// Deterministic gather of element contributions into the CSR values of A;
+// Dirichlet rows become identity rows.  Also records 1/diag(A).
+__global__ void __launch_bounds__(kBlock) k_gather_A(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                                                     const int32_t* __restrict__ gptr, const int32_t* __restrict__ gidx,
+                                                     const uint8_t* __restrict__ dir, const double* __restrict__ elem,
+                                                     double* __restrict__ val, float* __restrict__ val32,
+                                                     double* __restrict__ dinv, float* __restrict__ dinv32, int nrows) {
+    int64_t r = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (r >= nrows) return;
+    bool d = dir[r] != 0;
+    for (int32_t p = rowptr[r]; p < rowptr[r + 1]; ++p) {
+        double v = 0.0;
+        if (d) {
+            v = (col[p] == r) ? 1.0 : 0.0;
+        } else {
+            for (int32_t q = gptr[p]; q < gptr[p + 1]; ++q) v += elem[gidx[q]];
+        }
+        val[p] = v;
+        val32[p] = (float)v;
+        if (col[p] == r) {
+            dinv[r] = 1.0 / v;
+            dinv32[r] = (float)(1.0 / v);
+        }
+    }
+}
+
+// -------------------------------------------------------------- constant matrices (once per mesh)
+// elembuf per element: [0,36) mass, [36,72) stiffness, [72,108) divergence (k*12 + a*2 + d)
+__global__ void __launch_bounds__(kBlock) k_elem_const(const double* __restrict__ geo, double* __restrict__ eb, int n_el) {
+    int64_t e = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (e >= n_el) return;
+    Geo g = load_geo(geo, e);
+    for (int a = 0; a < 6; ++a)
+        for (int c = 0; c < 6; ++c) {
+            eb[e * 108 + a * 6 + c] = g.det * c_ref.Mhat[a][c];
+            double k = 0.0;
+            for (int p = 0; p < 2; ++p)
+                for (int r = 0; r < 2; ++r) k += c_ref.Khat[a][c][p][r] * g.G[p][r];
+            eb[e * 108 + 36 + a * 6 + c] = g.det * k;
+        }
+    for (int k = 0; k < 3; ++k)
+        for (int a = 0; a < 6; ++a)
+            for (int d = 0; d < 2; ++d) {
+                double v = 0.0;
+                for (int p = 0; p < 2; ++p) v += c_ref.Bhat[k][a][p] * g.Ji[p][d];
+                eb[e * 108 + 72 + (k * 6 + a) * 2 + d] = g.det * v;
+            }
+}
+
+__global__ void __launch_bounds__(kBlock) k_gather_MK(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ gptr,
+                                                      const int32_t* __restrict__ gidx, const double* __restrict__ eb,
+                                                      double* __restrict__ valM, double* __restrict__ valK, int nrows) {
+    int64_t r = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (r >= nrows) return;
+    for (int32_t p = rowptr[r]; p < rowptr[r + 1]; ++p) {
+        double m = 0.0, k = 0.0;
+        for (int32_t q = gptr[p]; q < gptr[p + 1]; ++q) {
+            int32_t c = gidx[q];
+            int64_t e = c / 36, ab = c % 36;
+            m += eb[e * 108 + ab];
+            k += eb[e * 108 + 36 + ab];
+        }
+        valM[p] = m;
+        valK[p] = k;
+    }
+}
+
+// gather of divergence contributions; rows flagged in `zero_row` are zeroed
+__global__ void __launch_bounds__(kBlock) k_gather_B(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ gptr,
+                                                     const int32_t* __restrict__ gidx, const double* __restrict__ eb,
+                                                     const uint8_t* __restrict__ zero_row, int pin_row,
+                                                     double* __restrict__ val, float* __restrict__ val32, int nrows) {
+    int64_t r = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (r >= nrows) return;
+    bool z = (zero_row && zero_row[r]) || (r == pin_row);
+    for (int32_t p = rowptr[r]; p < rowptr[r + 1]; ++p) {
+        double v0 = 0.0, v1 = 0.0;
+        if (!z)
+            for (int32_t q = gptr[p]; q < gptr[p + 1]; ++q) {
+                int32_t c = gidx[q];
+                int64_t e = c / 18, ka = c % 18;
+                v0 += eb[e * 108 + 72 + ka * 2];
+                v1 += eb[e * 108 + 72 + ka * 2 + 1];
+            }
+        val[2 * p] = v0;
+        val[2 * p + 1] = v1;
+        val32[2 * p] = (float)v0;
+        val32[2 * p + 1] = (float)v1;
+    }
+}
+
+// -------------------------------------------------------------- (a3) batched right-hand sides
+// coef[j] = (nu_j - nu_m,j)/2, coef[J + j] = (nu_j' + nu_m,j')/2
+__global__ void k_member_coefs(const double* __restrict__ nu, const double* __restrict__ nu_m, int J,
+                               double* __restrict__ coef) {
+    __shared__ double s_nu, s_nm;
+    if (threadIdx.x == 0) {
+        double a = 0.0, b = 0.0;
+        for (int j = 0; j < J; ++j) {
+            a += nu[j];
+            b += nu_m[j];
+        }
+        s_nu = a / J;
+        s_nm = b / J;
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < J; j += blockDim.x) {
+        coef[j] = 0.5 * (nu[j] - nu_m[j]);
+        coef[J + j] = 0.5 * ((nu[j] - s_nu) + (nu_m[j] - s_nm));
+    }
+}
+
+// One P2 node per group of JP lanes; lanes over members.
+//   b = M (self/dt + f) - cm K other - cp K self - b*(other - <other>, self, .)
+__global__ void __launch_bounds__(kBlock) k_rhs(
+    const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col, const double* __restrict__ valM,
+    const double* __restrict__ valK, const int32_t* __restrict__ inc_ptr, const int32_t* __restrict__ inc,
+    const int32_t* __restrict__ tri, const double* __restrict__ geo, const int32_t* __restrict__ dir_index,
+    const double* __restrict__ self, const double* __restrict__ other, const double* __restrict__ obar,
+    const double* __restrict__ coef, const double* __restrict__ F, const double* __restrict__ G,
+    double* __restrict__ b, int nP2, int nP1, int J, int JP, double inv_dt, int convective) {
+    Lanes L = lanes(JP);
+    int64_t i = L.unit;
+    if (i >= (int64_t)nP2 + nP1) return;
+    if (i >= nP2) {   // pressure rows: zero
+        int64_t k = i - nP2;
+        for (int j = L.j0; j < J; j += JP) b[(2 * (int64_t)nP2 + k) * J + j] = 0.0;
+        return;
+    }
+    int di = dir_index[i];
+    if (di >= 0) {
+        for (int j = L.j0; j < J; j += JP) {
+            b[(2 * i) * J + j] = G[(2 * (int64_t)di) * J + j];
+            b[(2 * i + 1) * J + j] = G[(2 * (int64_t)di + 1) * J + j];
+        }
+        return;
+    }
+    const int32_t p0 = rowptr[i], p1 = rowptr[i + 1];
+    const int32_t q0 = inc_ptr[i], q1 = inc_ptr[i + 1];
+    for (int j = L.j0; j < J; j += JP) {
+        const double cm = coef[j], cp = coef[J + j];
+        double acc0 = 0.0, acc1 = 0.0;
+        for (int32_t p = p0; p < p1; ++p) {
+            const int64_t k = col[p];
+            const double m = valM[p], kk = valK[p];
+            const double s0 = self[(2 * k) * J + j], s1 = self[(2 * k + 1) * J + j];
+            const double o0 = other[(2 * k) * J + j], o1 = other[(2 * k + 1) * J + j];
+            double f0 = 0.0, f1 = 0.0;
+            if (F) {
+                f0 = F[(2 * k) * J + j];
+                f1 = F[(2 * k + 1) * J + j];
+            }
+            acc0 += m * (s0 * inv_dt + f0) - kk * (cm * o0 + cp * s0);
+            acc1 += m * (s1 * inv_dt + f1) - kk * (cm * o1 + cp * s1);
+        }
+        for (int32_t q = q0; q < q1; ++q) {
+            const int32_t ea = inc[q];
+            const int64_t e = ea >> 3;
+            const int a = ea & 7;
+            Geo g = load_geo(geo, e);
+            int t[6];
+            double uh[6][2];
+#pragma unroll
+            for (int bb = 0; bb < 6; ++bb) {
+                t[bb] = tri[e * 6 + bb];
+                const double u0 = other[(int64_t)(2 * t[bb]) * J + j] - obar[2 * t[bb]];
+                const double u1 = other[(int64_t)(2 * t[bb] + 1) * J + j] - obar[2 * t[bb] + 1];
+                uh[bb][0] = g.det * (g.Ji[0][0] * u0 + g.Ji[0][1] * u1);
+                uh[bb][1] = g.det * (g.Ji[1][0] * u0 + g.Ji[1][1] * u1);
+            }
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                double cf = 0.0;
+#pragma unroll
+                for (int bb = 0; bb < 6; ++bb) {
+                    if (convective)
+                        cf += c_ref.That[a][bb][c][0] * uh[bb][0] + c_ref.That[a][bb][c][1] * uh[bb][1];
+                    else
+                        cf += c_ref.Shat[a][bb][c][0] * uh[bb][0] + c_ref.Shat[a][bb][c][1] * uh[bb][1];
+                }
+                acc0 -= cf * self[(int64_t)(2 * t[c]) * J + j];
+                acc1 -= cf * self[(int64_t)(2 * t[c] + 1) * J + j];
+            }
+        }
+        b[(2 * i) * J + j] = acc0;
+        b[(2 * i + 1) * J + j] = acc1;
+    }
+}
+
+// per-node partial of vbar^T M vbar (both components); partial per block
+__global__ void __launch_bounds__(kBlock) k_energy(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                                                   const double* __restrict__ valM, const double* __restrict__ vb,
+                                                   double* __restrict__ out, int nrows) {
+    __shared__ double red[kBlock];
+    int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    double acc = 0.0;
+    if (r < nrows) {
+        double s0 = 0.0, s1 = 0.0;
+        for (int32_t p = rowptr[r]; p < rowptr[r + 1]; ++p) {
+            s0 += valM[p] * vb[2 * col[p]];
+            s1 += valM[p] * vb[2 * col[p] + 1];
+        }
+        acc = vb[2 * r] * s0 + vb[2 * r + 1] * s1;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+hipError_t launch_mean(const double* z, double* zbar, int64_t rows, int J, hipStream_t s) {
+    int JP = pick_jp(J);
+    hipLaunchKernelGGL(k_mean, dim3(grid_for(rows, JP)), dim3(kBlock), 0, s, z, zbar, rows, J, JP);
+    return hipGetLastError();
+}
+
+hipError_t launch_eddy_l2(const DevMesh& m, const double* z, const double* zbar, double* l2, int J, hipStream_t s) {
+    int JP = pick_jp(J);
+    hipLaunchKernelGGL(k_eddy_l2, dim3(grid_for(m.n_el, JP)), dim3(kBlock), 0, s, m.tri, z, zbar, l2, m.n_el, J, JP);
+    return hipGetLastError();
+}
+
+hipError_t launch_assemble_A(const DevMesh& m, const mhd_coeffs& c, const double* zbar, const double* l2, double* elem,
+                             double* valA, float* valA32, double* dinvA, float* dinvA32, hipStream_t s) {
+    double nu_c = 0.5 * (c.nu_bar + c.num_bar);
+    double eddy_c = 2.0 * c.mu * c.dt;
+    hipLaunchKernelGGL(k_elem_A, dim3((m.n_el + kBlock - 1) / kBlock), dim3(kBlock), 0, s, m.tri, m.geo, zbar, l2,
+                       elem, m.n_el, 1.0 / c.dt, nu_c, eddy_c, c.convective);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_gather_A, dim3((m.nP2 + kBlock - 1) / kBlock), dim3(kBlock), 0, s, m.A_rowptr, m.A_col,
+                       m.gA_ptr, m.gA_idx, m.dir, elem, valA, valA32, dinvA, dinvA32, m.nP2);
+    return hipGetLastError();
+}
+
+hipError_t launch_const_assembly(DevMesh& m, double* eb, hipStream_t s) {
+    hipLaunchKernelGGL(k_elem_const, dim3((m.n_el + kBlock - 1) / kBlock), dim3(kBlock), 0, s, m.geo, eb, m.n_el);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_gather_MK, dim3((m.nP2 + kBlock - 1) / kBlock), dim3(kBlock), 0, s, m.A_rowptr, m.gA_ptr,
+                       m.gA_idx, eb, m.valM, m.valK, m.nP2);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_gather_B, dim3((m.nP2 + kBlock - 1) / kBlock), dim3(kBlock), 0, s, m.Bt_rowptr, m.gBt_ptr,
+                       m.gBt_idx, eb, m.dir, -1, m.valBt, m.valBt32, m.nP2);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_gather_B, dim3((m.nP1 + kBlock - 1) / kBlock), dim3(kBlock), 0, s, m.B_rowptr, m.gB_ptr,
+                       m.gB_idx, eb, (const uint8_t*)nullptr, m.pin, m.valB, m.valB32, m.nP1);
+    return hipGetLastError();
+}
+
+hipError_t launch_member_coefs(const double* nu, const double* nu_m, int J, double* coef, hipStream_t s) {
+    hipLaunchKernelGGL(k_member_coefs, dim3(1), dim3(256), 0, s, nu, nu_m, J, coef);
+    return hipGetLastError();
+}
+
+hipError_t launch_rhs(const DevMesh& m, const mhd_coeffs& c, int J, const double* self_n, const double* other_n,
+                      const double* obar, const double* coef, const double* forcing, const double* bc, double* rhs,
+                      hipStream_t s) {
+    int JP = pick_jp(J);
+    int64_t units = (int64_t)m.nP2 + m.nP1;
+    hipLaunchKernelGGL(k_rhs, dim3(grid_for(units, JP)), dim3(kBlock), 0, s, m.A_rowptr, m.A_col, m.valM, m.valK,
+                       m.inc_ptr, m.inc, m.tri, m.geo, m.dir_index, self_n, other_n, obar, coef, forcing, bc, rhs,
+                       m.nP2, m.nP1, J, JP, 1.0 / c.dt, c.convective);
+    return hipGetLastError();
+}
+
+hipError_t launch_energy_partial(const DevMesh& m, const double* vbar, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_energy, dim3((m.nP2 + kBlock - 1) / kBlock), dim3(kBlock), 0, s, m.A_rowptr, m.A_col,
+                       m.valM, vbar, out, m.nP2);
+    return hipGetLastError();
+}
+
+}  // namespace mhd

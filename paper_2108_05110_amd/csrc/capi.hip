@@ -1,0 +1,540 @@
+// C ABI of libmhd_ens: handle management, uploads, argument checks and the
+// entry points declared in include/mhd_ens.h.  Every entry point validates its
+// arguments on the host before it enqueues device work.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "device.h"
+
+struct mhd_mesh_s {
+    mhd::DevMesh d;
+};
+struct mhd_shared_s {
+    mhd::DevShared d;
+};
+struct mhd_ctx_s {
+    mhd_mesh mesh = nullptr;
+    mhd_shared Av = nullptr, Aw = nullptr;
+    mhd_ctx_desc desc{};
+    double *bv = nullptr, *bw = nullptr;    // right-hand sides (n x Jmax)
+    double *Xv = nullptr, *Xw = nullptr;    // solution blocks [velocity; pressure]
+    double* coef = nullptr;                 // 2 Jmax member coefficients
+    double* host_coef = nullptr;            // pinned staging, 2 Jmax
+    double* partial = nullptr;              // reductions
+    std::vector<void*> allocs;
+};
+
+namespace mhd {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+namespace {
+
+template <typename T>
+mhd_status dev_alloc(std::vector<void*>& list, T** p, size_t count) {
+    hipError_t e = hipMalloc((void**)p, std::max<size_t>(count * sizeof(T), 256));
+    if (e != hipSuccess) {
+        set_error(std::string("hipMalloc(") + std::to_string(count * sizeof(T)) + "): " + hipGetErrorString(e));
+        return MHD_ENOMEM;
+    }
+    list.push_back((void*)*p);
+    return MHD_OK;
+}
+
+template <typename T>
+mhd_status upload(std::vector<void*>& list, T** p, const std::vector<T>& h) {
+    mhd_status rc = dev_alloc(list, p, h.size());
+    if (rc) return rc;
+    if (!h.empty()) MHD_HIP(hipMemcpy(*p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+    return MHD_OK;
+}
+
+mhd_status upload_csr(std::vector<void*>& list, DevCSR<double>& d, const HostCSR& h) {
+    d.nrows = h.nrows;
+    d.ncols = h.ncols;
+    d.nnz = h.nnz();
+    mhd_status rc;
+    if ((rc = upload(list, &d.rowptr, h.rowptr))) return rc;
+    if ((rc = upload(list, &d.col, h.col))) return rc;
+    if ((rc = upload(list, &d.val, h.val))) return rc;
+    std::vector<float> v32(h.val.begin(), h.val.end());
+    if ((rc = upload(list, &d.val32, v32))) return rc;
+    return MHD_OK;
+}
+
+void free_list(std::vector<void*>& list) {
+    for (void* p : list) (void)hipFree(p);
+    list.clear();
+}
+
+hipStream_t as_stream(mhd_stream_t s) { return (hipStream_t)s; }
+
+#define CHECK_ARG(cond, msg)         \
+    do {                             \
+        if (!(cond)) {               \
+            ::mhd::set_error(msg);   \
+            return MHD_EINVAL;       \
+        }                            \
+    } while (0)
+
+mhd_status build_device_mesh(DevMesh& D) {
+    HostMesh& h = D.host;
+    auto& L = D.allocs;
+    D.nP2 = h.nP2;
+    D.nP1 = h.nP1;
+    D.n_el = h.n_el;
+    D.n = 2 * (int64_t)h.nP2 + h.nP1;
+    D.n_dir = (int)h.dir_nodes.size();
+    D.pin = h.pin;
+    RefTables t;
+    make_ref_tables(t);
+    upload_ref_tables(t);
+    MHD_HIP(hipGetLastError());
+    // element geometry: detJ and the inverse Jacobian of the affine map from the reference triangle
+    std::vector<double> geo((size_t)h.n_el * 6, 0.0);
+    for (int e = 0; e < h.n_el; ++e) {
+        const double* p0 = &h.xy[2 * h.tri[(size_t)e * 6]];
+        const double* p1 = &h.xy[2 * h.tri[(size_t)e * 6 + 1]];
+        const double* p2 = &h.xy[2 * h.tri[(size_t)e * 6 + 2]];
+        double a = p1[0] - p0[0], b = p2[0] - p0[0], c = p1[1] - p0[1], d = p2[1] - p0[1];
+        double det = a * d - b * c;
+        double* g = &geo[(size_t)e * 6];
+        g[0] = det;
+        g[1] = d / det;
+        g[2] = -b / det;
+        g[3] = -c / det;
+        g[4] = a / det;
+    }
+    mhd_status rc;
+    if ((rc = upload(L, &D.geo, geo))) return rc;
+    if ((rc = upload(L, &D.xy, h.xy))) return rc;
+    if ((rc = upload(L, &D.tri, h.tri))) return rc;
+    if ((rc = upload(L, &D.tri1, h.tri1))) return rc;
+    if ((rc = upload(L, &D.dir, h.dir))) return rc;
+    std::vector<int32_t> dir_index(h.nP2, -1);
+    for (size_t i = 0; i < h.dir_nodes.size(); ++i) dir_index[h.dir_nodes[i]] = (int32_t)i;
+    if ((rc = upload(L, &D.dir_index, dir_index))) return rc;
+    if ((rc = upload(L, &D.dir_nodes, h.dir_nodes))) return rc;
+    if ((rc = upload(L, &D.A_rowptr, h.A.rowptr))) return rc;
+    if ((rc = upload(L, &D.A_col, h.A.col))) return rc;
+    if ((rc = upload(L, &D.Bt_rowptr, h.Bt.rowptr))) return rc;
+    if ((rc = upload(L, &D.Bt_col, h.Bt.col))) return rc;
+    if ((rc = upload(L, &D.B_rowptr, h.B.rowptr))) return rc;
+    if ((rc = upload(L, &D.B_col, h.B.col))) return rc;
+    D.nnzA = h.A.nnz();
+    D.nnzBt = h.Bt.nnz();
+    D.nnzB = h.B.nnz();
+    if ((rc = upload(L, &D.gA_ptr, h.gA_ptr))) return rc;
+    if ((rc = upload(L, &D.gA_idx, h.gA_idx))) return rc;
+    if ((rc = upload(L, &D.gB_ptr, h.gB_ptr))) return rc;
+    if ((rc = upload(L, &D.gB_idx, h.gB_idx))) return rc;
+    if ((rc = upload(L, &D.gBt_ptr, h.gBt_ptr))) return rc;
+    if ((rc = upload(L, &D.gBt_idx, h.gBt_idx))) return rc;
+    if ((rc = upload(L, &D.inc_ptr, h.inc_ptr))) return rc;
+    if ((rc = upload(L, &D.inc, h.inc))) return rc;
+    if ((rc = dev_alloc(L, &D.valM, D.nnzA))) return rc;
+    if ((rc = dev_alloc(L, &D.valK, D.nnzA))) return rc;
+    if ((rc = dev_alloc(L, &D.valB, 2 * D.nnzB))) return rc;
+    if ((rc = dev_alloc(L, &D.valB32, 2 * D.nnzB))) return rc;
+    if ((rc = dev_alloc(L, &D.valBt, 2 * D.nnzBt))) return rc;
+    if ((rc = dev_alloc(L, &D.valBt32, 2 * D.nnzBt))) return rc;
+    std::vector<double> dp(h.nP1, 0.0);
+    if (h.pin >= 0) dp[h.pin] = 1.0;
+    if ((rc = upload(L, &D.diagp, dp))) return rc;
+    std::vector<float> dp32(dp.begin(), dp.end());
+    if ((rc = upload(L, &D.diagp32, dp32))) return rc;
+    if ((rc = upload(L, &D.mp, h.mp))) return rc;
+    std::vector<double> mpi(h.mp.size());
+    for (size_t i = 0; i < mpi.size(); ++i) mpi[i] = 1.0 / h.mp[i];
+    if ((rc = upload(L, &D.mp_inv, mpi))) return rc;
+    if ((rc = upload(L, &D.pfix, h.pfix))) return rc;
+    if ((rc = dev_alloc(L, &D.scratch_coef, 2 * kMaxJ))) return rc;
+    if ((rc = dev_alloc(L, &D.scratch_mean, 2 * (size_t)h.nP2))) return rc;
+    // pressure multigrid hierarchy
+    D.levels.resize(h.levels.size());
+    for (size_t l = 0; l < h.levels.size(); ++l) {
+        const HostLevel& H = h.levels[l];
+        DevLevel& G = D.levels[l];
+        G.n = H.n;
+        if ((rc = upload_csr(L, G.L, H.L))) return rc;
+        if ((rc = upload(L, &G.dinv, H.dinv))) return rc;
+        std::vector<float> di32(H.dinv.begin(), H.dinv.end());
+        if ((rc = upload(L, &G.dinv32, di32))) return rc;
+        if (l + 1 < h.levels.size()) {
+            if ((rc = upload_csr(L, G.P, H.P))) return rc;
+            if ((rc = upload_csr(L, G.R, H.R))) return rc;
+        } else {
+            if ((rc = upload(L, &G.cinv, H.cinv))) return rc;
+            std::vector<float> c32(H.cinv.begin(), H.cinv.end());
+            if ((rc = upload(L, &G.cinv32, c32))) return rc;
+        }
+    }
+    // constant matrices (mass, stiffness, divergence) assembled on the device
+    double* eb = nullptr;
+    MHD_HIP(hipMalloc((void**)&eb, sizeof(double) * 108 * std::max(1, h.n_el)));
+    hipError_t e = launch_const_assembly(D, eb, 0);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    (void)hipFree(eb);
+    if (e != hipSuccess) {
+        set_error(std::string("constant assembly: ") + hipGetErrorString(e));
+        return MHD_EHIP;
+    }
+    return MHD_OK;
+}
+
+mhd_status make_shared(DevMesh* m, int J_max, int restart, DevShared& S) {
+    S.mesh = m;
+    S.Jmax = J_max;
+    auto& L = S.allocs;
+    mhd_status rc;
+    if ((rc = dev_alloc(L, &S.valA, m->nnzA))) return rc;
+    if ((rc = dev_alloc(L, &S.valA32, m->nnzA))) return rc;
+    if ((rc = dev_alloc(L, &S.dinvA, m->nP2))) return rc;
+    if ((rc = dev_alloc(L, &S.dinvA32, m->nP2))) return rc;
+    if ((rc = dev_alloc(L, &S.zbar, 2 * (size_t)m->nP2))) return rc;
+    if ((rc = dev_alloc(L, &S.l2, 7 * (size_t)m->n_el))) return rc;
+    if ((rc = dev_alloc(L, &S.elem, 36 * (size_t)m->n_el))) return rc;
+    return alloc_gmres(S, restart);
+}
+
+void free_shared(DevShared& S) {
+    free_list(S.allocs);
+    if (S.gw.host_res) (void)hipHostFree(S.gw.host_res);
+    S.gw.host_res = nullptr;
+}
+
+mhd_status check_coeffs(const mhd_coeffs* c) {
+    CHECK_ARG(c, "null coefficients");
+    CHECK_ARG(std::isfinite(c->dt) && c->dt > 0, "dt must be positive and finite");
+    CHECK_ARG(std::isfinite(c->mu) && c->mu >= 0, "mu must be non-negative");
+    CHECK_ARG(std::isfinite(c->nu_bar) && c->nu_bar >= 0, "nu_bar must be non-negative");
+    CHECK_ARG(std::isfinite(c->num_bar) && c->num_bar >= 0, "num_bar must be non-negative");
+    CHECK_ARG(c->convective == 0 || c->convective == 1, "convective must be 0 or 1");
+    return MHD_OK;
+}
+
+mhd_status assemble_shared_impl(DevMesh& m, const mhd_coeffs& c, const double* z, int J, DevShared& S, hipStream_t s) {
+    hipError_t e = launch_mean(z, S.zbar, 2 * (int64_t)m.nP2, J, s);
+    if (e == hipSuccess) e = launch_eddy_l2(m, z, S.zbar, S.l2, J, s);
+    if (e == hipSuccess) e = launch_assemble_A(m, c, S.zbar, S.l2, S.elem, S.valA, S.valA32, S.dinvA, S.dinvA32, s);
+    if (e != hipSuccess) {
+        set_error(std::string("assemble_shared: ") + hipGetErrorString(e));
+        return MHD_EHIP;
+    }
+    S.coeffs = c;
+    S.assembled = true;
+    return MHD_OK;
+}
+
+mhd_status check_solver_opts(const mhd_solver_opts* o) {
+    CHECK_ARG(o, "null solver options");
+    CHECK_ARG(o->precision == MHD_FP64 || o->precision == MHD_FP32_IR, "precision must be MHD_FP64 or MHD_FP32_IR");
+    CHECK_ARG(std::isfinite(o->rtol) && o->rtol > 0 && o->rtol < 1, "rtol must be in (0,1)");
+    CHECK_ARG(std::isfinite(o->inner_rtol) && o->inner_rtol > 0 && o->inner_rtol < 1, "inner_rtol must be in (0,1)");
+    CHECK_ARG(o->maxit >= 1, "maxit must be >= 1");
+    CHECK_ARG(o->restart >= 1 && o->restart <= kMaxRestart, "restart must be in [1, 40]");
+    CHECK_ARG(o->jacobi_sweeps >= 1 && o->jacobi_sweeps <= 16, "jacobi_sweeps must be in [1, 16]");
+    return MHD_OK;
+}
+
+}  // namespace
+}  // namespace mhd
+
+using namespace mhd;
+
+extern "C" {
+
+const char* mhd_ens_last_error(void) { return g_last_error.c_str(); }
+
+const char* mhd_ens_version(void) { return "mhd_ens 0.1 (gfx950)"; }
+
+mhd_status mhd_ens_mesh_counts(const mhd_mesh_desc* d, mhd_mesh_info* info) {
+    CHECK_ARG(info, "mhd_ens_mesh_counts: null info");
+    HostMesh m;
+    mhd_status rc = build_mesh(d, m, true);
+    if (rc) return rc;
+    mesh_counts(m, info);
+    return MHD_OK;
+}
+
+mhd_status mhd_ens_mesh(const mhd_mesh_desc* d, mhd_mesh* out, mhd_mesh_info* info) {
+    CHECK_ARG(out, "mhd_ens_mesh: null output handle");
+    *out = nullptr;
+    mhd_mesh m = new (std::nothrow) mhd_mesh_s;
+    if (!m) {
+        set_error("mhd_ens_mesh: host allocation failed");
+        return MHD_ENOMEM;
+    }
+    mhd_status rc = build_mesh(d, m->d.host, true);
+    if (rc == MHD_OK) rc = build_device_mesh(m->d);
+    if (rc != MHD_OK) {
+        free_list(m->d.allocs);
+        delete m;
+        return rc;
+    }
+    if (info) mesh_counts(m->d.host, info);
+    *out = m;
+    return MHD_OK;
+}
+
+mhd_status mhd_ens_mesh_coords(mhd_mesh m, double* xy_p2, int32_t* dir_nodes) {
+    CHECK_ARG(m, "mhd_ens_mesh_coords: null mesh");
+    if (xy_p2) std::memcpy(xy_p2, m->d.host.xy.data(), sizeof(double) * m->d.host.xy.size());
+    if (dir_nodes)
+        std::memcpy(dir_nodes, m->d.host.dir_nodes.data(), sizeof(int32_t) * m->d.host.dir_nodes.size());
+    return MHD_OK;
+}
+
+mhd_status mhd_ens_mesh_free(mhd_mesh m) {
+    if (!m) return MHD_OK;
+    free_list(m->d.allocs);
+    for (auto& l : m->d.levels) (void)l;
+    delete m;
+    return MHD_OK;
+}
+
+mhd_status mhd_ens_shared_create(mhd_mesh m, int J_max, int restart, mhd_shared* out) {
+    CHECK_ARG(out, "mhd_ens_shared_create: null output handle");
+    *out = nullptr;
+    CHECK_ARG(m, "mhd_ens_shared_create: null mesh");
+    CHECK_ARG(J_max >= 1 && J_max <= kMaxJ, "mhd_ens_shared_create: J_max must be in [1, 4096]");
+    CHECK_ARG(restart >= 1 && restart <= kMaxRestart, "mhd_ens_shared_create: restart must be in [1, 40]");
+    mhd_shared A = new (std::nothrow) mhd_shared_s;
+    if (!A) return MHD_ENOMEM;
+    mhd_status rc = make_shared(&m->d, J_max, restart, A->d);
+    if (rc) {
+        free_shared(A->d);
+        delete A;
+        return rc;
+    }
+    *out = A;
+    return MHD_OK;
+}
+
+mhd_status mhd_ens_shared_free(mhd_shared A) {
+    if (!A) return MHD_OK;
+    free_shared(A->d);
+    delete A;
+    return MHD_OK;
+}
+
+mhd_status mhd_ens_assemble_shared(mhd_mesh m, const mhd_coeffs* c, const double* z_other, int J, mhd_shared A,
+                                   mhd_stream_t s) {
+    CHECK_ARG(m && A, "mhd_ens_assemble_shared: null handle");
+    CHECK_ARG(A->d.mesh == &m->d, "mhd_ens_assemble_shared: shared handle belongs to another mesh");
+    CHECK_ARG(z_other, "mhd_ens_assemble_shared: null z_other");
+    mhd_status rc = check_coeffs(c);
+    if (rc) return rc;
+    if (J < 1 || J > A->d.Jmax) {
+        set_error("mhd_ens_assemble_shared: J outside [1, J_max]");
+        return MHD_ESHAPE;
+    }
+    return assemble_shared_impl(m->d, *c, z_other, J, A->d, as_stream(s));
+}
+
+mhd_status mhd_ens_shared_csr(mhd_shared A, mhd_csr_view* v) {
+    CHECK_ARG(A && v, "mhd_ens_shared_csr: null argument");
+    DevMesh& m = *A->d.mesh;
+    v->rowptr_A = m.A_rowptr;
+    v->col_A = m.A_col;
+    v->val_A = A->d.valA;
+    v->val_A32 = A->d.valA32;
+    v->rowptr_Bt = m.Bt_rowptr;
+    v->col_Bt = m.Bt_col;
+    v->val_Bt = m.valBt;
+    v->rowptr_B = m.B_rowptr;
+    v->col_B = m.B_col;
+    v->val_B = m.valB;
+    v->diag_p = m.diagp;
+    v->nP2 = m.nP2;
+    v->nP1 = m.nP1;
+    v->nnz_A = m.nnzA;
+    v->nnz_Bt = m.nnzBt;
+    v->nnz_B = m.nnzB;
+    return MHD_OK;
+}
+
+mhd_status mhd_ens_assemble_rhs(mhd_mesh m, const mhd_coeffs* c, int which, int J, const double* self_n,
+                                const double* other_n, const double* nu, const double* nu_m, const double* forcing,
+                                const double* bc_vals, double* rhs, mhd_stream_t s) {
+    CHECK_ARG(m, "mhd_ens_assemble_rhs: null mesh");
+    mhd_status rc = check_coeffs(c);
+    if (rc) return rc;
+    CHECK_ARG(which == MHD_V_PROBLEM || which == MHD_W_PROBLEM, "mhd_ens_assemble_rhs: which must be V or W");
+    CHECK_ARG(J >= 1 && J <= kMaxJ, "mhd_ens_assemble_rhs: J must be in [1, 4096]");
+    CHECK_ARG(self_n && other_n && nu && nu_m && rhs, "mhd_ens_assemble_rhs: null array");
+    CHECK_ARG(bc_vals || m->d.n_dir == 0, "mhd_ens_assemble_rhs: null bc_vals with Dirichlet nodes");
+    hipStream_t st = as_stream(s);
+    DevMesh& D = m->d;
+    hipError_t e = launch_member_coefs(nu, nu_m, J, D.scratch_coef, st);
+    if (e == hipSuccess) e = launch_mean(other_n, D.scratch_mean, 2 * (int64_t)D.nP2, J, st);
+    if (e == hipSuccess)
+        e = launch_rhs(D, *c, J, self_n, other_n, D.scratch_mean, D.scratch_coef, forcing, bc_vals, rhs, st);
+    if (e != hipSuccess) {
+        set_error(std::string("mhd_ens_assemble_rhs: ") + hipGetErrorString(e));
+        return MHD_EHIP;
+    }
+    return MHD_OK;
+}
+
+mhd_status mhd_ens_solve(mhd_shared A, const double* rhs, double* x, int J, const mhd_solver_opts* o,
+                         mhd_solve_stats* st, mhd_stream_t s) {
+    CHECK_ARG(A, "mhd_ens_solve: null handle");
+    CHECK_ARG(rhs && x, "mhd_ens_solve: null array");
+    mhd_status rc = check_solver_opts(o);
+    if (rc) return rc;
+    if (J < 1 || J > A->d.Jmax) {
+        set_error("mhd_ens_solve: J outside [1, J_max]");
+        return MHD_ESHAPE;
+    }
+    CHECK_ARG(o->restart <= A->d.gw.restart, "mhd_ens_solve: restart larger than the handle's");
+    CHECK_ARG(A->d.assembled, "mhd_ens_solve: matrix not assembled");
+    return solve_shared(A->d, rhs, x, J, *o, st, as_stream(s));
+}
+
+mhd_status mhd_ens_ctx_create(mhd_mesh m, const mhd_ctx_desc* d, mhd_ctx* out) {
+    CHECK_ARG(out, "mhd_ens_ctx_create: null output handle");
+    *out = nullptr;
+    CHECK_ARG(m && d, "mhd_ens_ctx_create: null argument");
+    mhd_status rc = check_coeffs(&d->coeffs);
+    if (rc) return rc;
+    if ((rc = check_solver_opts(&d->solver))) return rc;
+    CHECK_ARG(d->J_max >= 1 && d->J_max <= kMaxJ, "mhd_ens_ctx_create: J_max must be in [1, 4096]");
+    mhd_ctx c = new (std::nothrow) mhd_ctx_s;
+    if (!c) return MHD_ENOMEM;
+    c->mesh = m;
+    c->desc = *d;
+    auto fail = [&](mhd_status r) {
+        if (c->Av) mhd_ens_shared_free(c->Av);
+        if (c->Aw) mhd_ens_shared_free(c->Aw);
+        free_list(c->allocs);
+        if (c->host_coef) (void)hipHostFree(c->host_coef);
+        delete c;
+        return r;
+    };
+    if ((rc = mhd_ens_shared_create(m, d->J_max, d->solver.restart, &c->Av))) return fail(rc);
+    if ((rc = mhd_ens_shared_create(m, d->J_max, d->solver.restart, &c->Aw))) return fail(rc);
+    size_t blk = (size_t)m->d.n * d->J_max;
+    if ((rc = dev_alloc(c->allocs, &c->bv, blk))) return fail(rc);
+    if ((rc = dev_alloc(c->allocs, &c->bw, blk))) return fail(rc);
+    if ((rc = dev_alloc(c->allocs, &c->Xv, blk))) return fail(rc);
+    if ((rc = dev_alloc(c->allocs, &c->Xw, blk))) return fail(rc);
+    if ((rc = dev_alloc(c->allocs, &c->coef, 2 * (size_t)d->J_max))) return fail(rc);
+    if ((rc = dev_alloc(c->allocs, &c->partial, (size_t)2048 * d->J_max + 1024))) return fail(rc);
+    if (hipHostMalloc((void**)&c->host_coef, sizeof(double) * 2 * d->J_max, hipHostMallocDefault) != hipSuccess)
+        return fail(MHD_ENOMEM);
+    *out = c;
+    return MHD_OK;
+}
+
+mhd_status mhd_ens_ctx_free(mhd_ctx c) {
+    if (!c) return MHD_OK;
+    mhd_ens_shared_free(c->Av);
+    mhd_ens_shared_free(c->Aw);
+    free_list(c->allocs);
+    if (c->host_coef) (void)hipHostFree(c->host_coef);
+    delete c;
+    return MHD_OK;
+}
+
+mhd_status mhd_ens_step(mhd_ctx ctx, double* V, double* W, double* Q, double* R, const mhd_step_inputs* in,
+                        mhd_step_stats* st, mhd_stream_t s) {
+    CHECK_ARG(ctx && in, "mhd_ens_step: null argument");
+    CHECK_ARG(V && W && Q && R, "mhd_ens_step: null state array");
+    CHECK_ARG(in->nu && in->nu_m, "mhd_ens_step: null nu / nu_m");
+    const int J = in->J;
+    if (J < 1 || J > ctx->desc.J_max) {
+        set_error("mhd_ens_step: J outside [1, J_max]");
+        return MHD_ESHAPE;
+    }
+    DevMesh& D = ctx->mesh->d;
+    CHECK_ARG((in->g_v && in->g_w) || D.n_dir == 0, "mhd_ens_step: null Dirichlet data");
+    hipStream_t stv = as_stream(s);
+    // mean viscosities and member coefficients (host, FP64)
+    double nub = 0, numb = 0;
+    for (int j = 0; j < J; ++j) {
+        CHECK_ARG(std::isfinite(in->nu[j]) && std::isfinite(in->nu_m[j]), "mhd_ens_step: non-finite nu");
+        nub += in->nu[j];
+        numb += in->nu_m[j];
+    }
+    nub /= J;
+    numb /= J;
+    for (int j = 0; j < J; ++j) {
+        ctx->host_coef[j] = 0.5 * (in->nu[j] - in->nu_m[j]);
+        ctx->host_coef[J + j] = 0.5 * ((in->nu[j] - nub) + (in->nu_m[j] - numb));
+    }
+    MHD_HIP(hipMemcpyAsync(ctx->coef, ctx->host_coef, sizeof(double) * 2 * J, hipMemcpyHostToDevice, stv));
+    mhd_coeffs c = ctx->desc.coeffs;
+    c.nu_bar = nub;
+    c.num_bar = numb;
+    DevShared& Av = ctx->Av->d;
+    DevShared& Aw = ctx->Aw->d;
+    mhd_status rc;
+    // v-problem convected by <w>, w-problem by <v>; both from time level n
+    if ((rc = assemble_shared_impl(D, c, W, J, Av, stv))) return rc;
+    if ((rc = assemble_shared_impl(D, c, V, J, Aw, stv))) return rc;
+    hipError_t e = launch_rhs(D, c, J, V, W, Av.zbar, ctx->coef, in->f1, in->g_v, ctx->bv, stv);
+    if (e == hipSuccess) e = launch_rhs(D, c, J, W, V, Aw.zbar, ctx->coef, in->f2, in->g_w, ctx->bw, stv);
+    if (e != hipSuccess) {
+        set_error(std::string("mhd_ens_step rhs: ") + hipGetErrorString(e));
+        return MHD_EHIP;
+    }
+    const size_t vel = sizeof(double) * 2 * (size_t)D.nP2 * J;
+    const size_t prs = sizeof(double) * (size_t)D.nP1 * J;
+    const int64_t poff = 2 * (int64_t)D.nP2 * J;
+    MHD_HIP(hipMemcpyAsync(ctx->Xv, V, vel, hipMemcpyDeviceToDevice, stv));
+    MHD_HIP(hipMemcpyAsync(ctx->Xv + poff, Q, prs, hipMemcpyDeviceToDevice, stv));
+    MHD_HIP(hipMemcpyAsync(ctx->Xw, W, vel, hipMemcpyDeviceToDevice, stv));
+    MHD_HIP(hipMemcpyAsync(ctx->Xw + poff, R, prs, hipMemcpyDeviceToDevice, stv));
+    mhd_solve_stats sv{}, sw{};
+    mhd_status rv = solve_shared(Av, ctx->bv, ctx->Xv, J, ctx->desc.solver, &sv, stv);
+    if (rv != MHD_OK && rv != MHD_ENOCONV) return rv;
+    mhd_status rw = solve_shared(Aw, ctx->bw, ctx->Xw, J, ctx->desc.solver, &sw, stv);
+    if (rw != MHD_OK && rw != MHD_ENOCONV) return rw;
+    MHD_HIP(hipMemcpyAsync(V, ctx->Xv, vel, hipMemcpyDeviceToDevice, stv));
+    MHD_HIP(hipMemcpyAsync(Q, ctx->Xv + poff, prs, hipMemcpyDeviceToDevice, stv));
+    MHD_HIP(hipMemcpyAsync(W, ctx->Xw, vel, hipMemcpyDeviceToDevice, stv));
+    MHD_HIP(hipMemcpyAsync(R, ctx->Xw + poff, prs, hipMemcpyDeviceToDevice, stv));
+    if (D.pin >= 0) {
+        e = launch_pressure_zero_mean(D, Q, J, ctx->partial, stv);
+        if (e == hipSuccess) e = launch_pressure_zero_mean(D, R, J, ctx->partial, stv);
+        if (e != hipSuccess) {
+            set_error(std::string("pressure normalisation: ") + hipGetErrorString(e));
+            return MHD_EHIP;
+        }
+    }
+    if (st) {
+        st->v = sv;
+        st->w = sw;
+        // E = (||<v>||^2 + ||<w>||^2)/2 with the P2 mass matrix
+        double E = 0.0;
+        int nblk = (D.nP2 + 255) / 256;
+        std::vector<double> hp(nblk);
+        for (int var = 0; var < 2; ++var) {
+            e = launch_mean(var == 0 ? V : W, Av.zbar, 2 * (int64_t)D.nP2, J, stv);
+            if (e == hipSuccess) e = launch_energy_partial(D, Av.zbar, ctx->partial, stv);
+            if (e == hipSuccess) e = hipMemcpyAsync(hp.data(), ctx->partial, sizeof(double) * nblk,
+                                                    hipMemcpyDeviceToHost, stv);
+            if (e == hipSuccess) e = hipStreamSynchronize(stv);
+            if (e != hipSuccess) {
+                set_error(std::string("energy: ") + hipGetErrorString(e));
+                return MHD_EHIP;
+            }
+            for (double v : hp) E += v;
+        }
+        st->energy = 0.5 * E;
+    }
+    if (rv == MHD_ENOCONV || rw == MHD_ENOCONV) {
+        set_error("mhd_ens_step: a subproblem solve hit maxit");
+        return MHD_ENOCONV;
+    }
+    return MHD_OK;
+}
+
+}  // extern "C"

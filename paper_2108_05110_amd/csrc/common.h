@@ -1,0 +1,86 @@
+// Internal definitions of libmhd_ens: host mesh structures, device mirrors,
+// launcher prototypes.  Not part of the public ABI (include/mhd_ens.h is).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/mhd_ens.h"
+
+namespace mhd {
+
+// ------------------------------------------------------------------ errors
+void set_error(const std::string& msg);
+std::string hip_error_string(int code);
+
+// ------------------------------------------------------------------ host CSR
+struct HostCSR {
+    int64_t nrows = 0, ncols = 0;
+    std::vector<int32_t> rowptr, col;
+    std::vector<double> val;
+    int64_t nnz() const { return (int64_t)col.size(); }
+};
+
+// One level of the pressure multigrid hierarchy (P1 Laplacian of the level's
+// triangulation, its inverse diagonal, interpolation from the next coarser
+// level and its transpose).
+struct HostLevel {
+    int nx = 0, ny = 0;          // cells of this level
+    double h = 0;
+    int n = 0;                   // active vertices
+    HostCSR L;                   // stiffness with fixed rows replaced by identity
+    std::vector<double> dinv;    // 1 / diag(L)
+    HostCSR P;                   // (n x n_coarse) interpolation from level+1 (empty on coarsest)
+    HostCSR R;                   // transpose of P
+    std::vector<double> cinv;    // dense inverse of L (coarsest level only), row-major
+};
+
+// Structured triangulation of a union of square cells, Taylor-Hood P2/P1 numbering.
+struct HostMesh {
+    mhd_mesh_desc desc{};
+    int nx = 0, ny = 0;          // cell grid
+    double h = 0, x0 = 0, y0 = 0, xmax = 0;
+    int nP2 = 0, nP1 = 0, n_el = 0;
+    std::vector<double> xy;      // nP2 x 2
+    std::vector<int32_t> tri;    // n_el x 6 P2 ids (v0,v1,v2,m01,m12,m20)
+    std::vector<int32_t> tri1;   // n_el x 3 P1 ids
+    std::vector<int32_t> p1_of_p2;  // P2 node -> P1 id (vertices) or -1
+    std::vector<uint8_t> bnd;    // per P2 node: on the boundary
+    std::vector<uint8_t> dir;    // per P2 node: Dirichlet
+    std::vector<int32_t> dir_nodes;
+    std::vector<uint8_t> pfix;   // per P1 node: fixed row of the pressure Laplacian (pin / outflow)
+    int32_t pin = -1;
+    // patterns of the saddle-point operator
+    HostCSR A;                   // scalar P2 x P2 (pattern only)
+    HostCSR Bt;                  // P2 x P1
+    HostCSR B;                   // P1 x P2
+    // element -> CSR slot maps and slot -> element contributions (deterministic gathers)
+    std::vector<int32_t> slotA;  // n_el x 36
+    std::vector<int32_t> gA_ptr, gA_idx;     // nnz_A + 1, contributions e*36 + a*6 + b
+    std::vector<int32_t> gB_ptr, gB_idx;     // nnz_B + 1, contributions e*18 + k*6 + a
+    std::vector<int32_t> gBt_ptr, gBt_idx;   // nnz_Bt + 1, contributions e*18 + k*6 + a
+    // P2 node -> (element, local index) incidence, sorted by element
+    std::vector<int32_t> inc_ptr, inc;       // inc entry = e*8 + a
+    std::vector<double> mp;      // lumped P1 mass (integral of each P1 basis function)
+    std::vector<HostLevel> levels;
+};
+
+mhd_status build_mesh(const mhd_mesh_desc* d, HostMesh& m, bool full);
+void mesh_counts(const HostMesh& m, mhd_mesh_info* info);
+
+// reference-element tables (host computed, uploaded to constant memory)
+struct RefTables {
+    double w[7];            // quadrature weights summing to 1
+    double phi[7][6];       // P2 values at the points
+    double dphi[7][6][2];   // reference gradients
+    double psi[7][3];       // P1 values
+    double Mhat[6][6];      // int_ref phi_a phi_b (area 1/2)
+    double Khat[6][6][2][2];// int_ref d_e phi_a d_f phi_b
+    double That[6][6][6][2];// int_ref phi_a phi_b d_e phi_c
+    double Shat[6][6][6][2];// (That[a][b][c] - That[c][b][a]) / 2
+    double Bhat[3][6][2];   // -int_ref psi_k d_e phi_a
+};
+void make_ref_tables(RefTables& t);
+
+}  // namespace mhd

@@ -1,0 +1,142 @@
+// Device-side data of libmhd_ens and launcher prototypes (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "common.h"
+
+#define MHD_HIP(call)                                                              \
+    do {                                                                           \
+        hipError_t e_ = (call);                                                    \
+        if (e_ != hipSuccess) {                                                    \
+            ::mhd::set_error(std::string(#call) + ": " + hipGetErrorString(e_));   \
+            return MHD_EHIP;                                                       \
+        }                                                                          \
+    } while (0)
+
+namespace mhd {
+
+constexpr int kMaxRestart = 40;    // Krylov basis length limit
+constexpr int kMaxJ = 4096;        // member count limit of one handle
+
+template <typename T>
+struct DevCSR {
+    int64_t nrows = 0, ncols = 0, nnz = 0;
+    int32_t* rowptr = nullptr;
+    int32_t* col = nullptr;
+    double* val = nullptr;
+    float* val32 = nullptr;
+};
+
+struct DevLevel {
+    int n = 0;
+    DevCSR<double> L, P, R;
+    double* dinv = nullptr;
+    float* dinv32 = nullptr;
+    double* cinv = nullptr;       // coarsest only
+    float* cinv32 = nullptr;
+};
+
+struct DevMesh {
+    HostMesh host;
+    int nP2 = 0, nP1 = 0, n_el = 0, n_dir = 0, pin = -1;
+    int64_t n = 0;
+    double* xy = nullptr;
+    double* geo = nullptr;        // n_el x 6: detJ, Jinv[2][2], pad
+    int32_t* tri = nullptr;       // n_el x 6
+    int32_t* tri1 = nullptr;      // n_el x 3
+    uint8_t* dir = nullptr;       // nP2
+    int32_t* dir_index = nullptr; // nP2: position in dir_nodes or -1
+    int32_t* dir_nodes = nullptr;
+    int32_t *A_rowptr = nullptr, *A_col = nullptr, *A_row = nullptr;
+    int32_t *Bt_rowptr = nullptr, *Bt_col = nullptr;
+    int32_t *B_rowptr = nullptr, *B_col = nullptr;
+    int64_t nnzA = 0, nnzBt = 0, nnzB = 0;
+    int32_t *gA_ptr = nullptr, *gA_idx = nullptr;
+    int32_t *gB_ptr = nullptr, *gB_idx = nullptr;
+    int32_t *gBt_ptr = nullptr, *gBt_idx = nullptr;
+    int32_t *inc_ptr = nullptr, *inc = nullptr;
+    double *valM = nullptr, *valK = nullptr;      // scalar P2 mass / stiffness
+    double *valB = nullptr, *valBt = nullptr;     // 2 values per entry, BC rows applied
+    float *valB32 = nullptr, *valBt32 = nullptr;
+    double* diagp = nullptr;
+    float* diagp32 = nullptr;
+    double* mp = nullptr;                         // lumped P1 mass
+    double* mp_inv = nullptr;
+    uint8_t* pfix = nullptr;                      // nP1: fixed rows of the pressure Laplacian
+    std::vector<DevLevel> levels;
+    // small scratch for the stand-alone RHS call (member coefficients, means)
+    double* scratch_coef = nullptr;               // 2 * kMaxJ
+    double* scratch_mean = nullptr;               // 2 nP2
+    std::vector<void*> allocs;
+};
+
+struct GmresWork {
+    int restart = 0;
+    int64_t nrows = 0;
+    int Jmax = 0;
+    void* basis = nullptr;        // (restart+1) blocks of nrows*Jmax (sized for double)
+    void* zbuf = nullptr;         // preconditioned vector
+    void* wbuf = nullptr;         // product / work
+    void* tbuf = nullptr;         // velocity right-hand side inside the preconditioner
+    void* z2buf = nullptr;        // Jacobi ping-pong
+    double* r64 = nullptr;        // fp64 residual (n x J)
+    double* H = nullptr;          // (restart+1) x restart x J
+    double* cs = nullptr;         // restart x J
+    double* sn = nullptr;
+    double* g = nullptr;          // (restart+1) x J
+    double* y = nullptr;          // restart x J
+    double* beta = nullptr;       // J
+    double* bnorm = nullptr;      // J
+    double* hcol = nullptr;       // (restart+1) x J current column
+    double* res = nullptr;        // J residual estimates
+    double* partial = nullptr;    // reduction partials
+    int64_t partial_len = 0;
+    double* host_res = nullptr;   // pinned host copy (J)
+    std::vector<void*> mg_x, mg_x2, mg_b, mg_r;   // per level (n_l x Jmax, sized for double)
+    void** dptrs = nullptr;       // device array of the basis block pointers
+};
+
+struct DevShared {
+    DevMesh* mesh = nullptr;
+    int Jmax = 0;
+    double* valA = nullptr;       // nnzA
+    float* valA32 = nullptr;
+    double* dinvA = nullptr;      // nP2 inverse diagonal of A
+    float* dinvA32 = nullptr;
+    double* zbar = nullptr;       // 2 nP2
+    double* l2 = nullptr;         // n_el x 7
+    double* elem = nullptr;       // n_el x 36
+    mhd_coeffs coeffs{};
+    bool assembled = false;
+    GmresWork gw;
+    std::vector<void*> allocs;
+};
+
+// ---------------------------------------------------------------- launchers (assemble.hip)
+void upload_ref_tables(const RefTables& t);
+hipError_t launch_const_assembly(DevMesh& m, double* elembuf, hipStream_t s);
+hipError_t launch_mean(const double* z, double* zbar, int64_t rows, int J, hipStream_t s);
+hipError_t launch_eddy_l2(const DevMesh& m, const double* z, const double* zbar, double* l2, int J,
+                          hipStream_t s);
+hipError_t launch_assemble_A(const DevMesh& m, const mhd_coeffs& c, const double* zbar, const double* l2,
+                             double* elem, double* valA, float* valA32, double* dinvA, float* dinvA32,
+                             hipStream_t s);
+hipError_t launch_member_coefs(const double* nu, const double* nu_m, int J, double* coef, hipStream_t s);
+hipError_t launch_rhs(const DevMesh& m, const mhd_coeffs& c, int J, const double* self_n,
+                      const double* other_n, const double* obar, const double* coef, const double* forcing,
+                      const double* bc, double* rhs, hipStream_t s);
+hipError_t launch_energy_partial(const DevMesh& m, const double* vbar, double* out, hipStream_t s);
+
+// ---------------------------------------------------------------- solver (solve.hip)
+mhd_status alloc_gmres(DevShared& S, int restart);
+mhd_status solve_shared(DevShared& S, const double* rhs, double* x, int J, const mhd_solver_opts& o,
+                        mhd_solve_stats* st, hipStream_t s);
+mhd_status saddle_residual64(DevShared& S, const double* b, const double* x, double* r, int J, hipStream_t s);
+
+// pressure post-processing: p -= (sum_k m_k p_k) / sum_k m_k per member
+hipError_t launch_pressure_zero_mean(const DevMesh& m, double* p, int J, double* partial, hipStream_t s);
+
+}  // namespace mhd

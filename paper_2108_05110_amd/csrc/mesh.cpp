@@ -1,0 +1,524 @@
+// Host side of libmhd_ens: structured triangulations, Taylor-Hood P2/P1
+// numbering, CSR patterns of the saddle-point operator, deterministic
+// element-to-slot gather lists, the pressure multigrid hierarchy and the
+// reference-element tables.  Pure integer/geometry work done once per mesh.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "common.h"
+
+namespace mhd {
+
+namespace {
+
+// Which square cells of the cell grid belong to the domain.
+struct CellDomain {
+    int kind;
+    int per_unit;   // cells per unit length (step channel); N for the unit square
+    bool kept(int i, int k) const {
+        if (kind == MHD_MESH_STEP_CHANNEL) return !(i < per_unit && k < per_unit);
+        return true;
+    }
+};
+
+struct Grid {
+    int nx, ny;
+    double h, x0, y0;
+    CellDomain dom;
+    bool cell(int i, int k) const {
+        if (i < 0 || k < 0 || i >= nx || k >= ny) return false;
+        return dom.kept(i, k);
+    }
+    // vertex (i,k) is active if any of its 4 cells is kept
+    int vertex_cells(int i, int k) const {
+        return (int)cell(i - 1, k - 1) + (int)cell(i, k - 1) + (int)cell(i - 1, k) + (int)cell(i, k);
+    }
+};
+
+Grid make_grid(const mhd_mesh_desc* d, int level) {
+    Grid g{};
+    int s = 1 << level;
+    if (d->kind == MHD_MESH_UNIT_SQUARE) {
+        g.nx = g.ny = d->nx / s;
+        g.h = 1.0 / g.nx;
+        g.dom = {d->kind, g.nx};
+    } else {
+        int m = d->nx / s;
+        g.nx = 30 * m;
+        g.ny = 10 * m;
+        g.h = 1.0 / m;
+        g.dom = {d->kind, m};
+    }
+    g.x0 = g.y0 = 0.0;
+    return g;
+}
+
+// P1 vertex numbering of a grid: row-major over active vertices.
+std::vector<int32_t> vertex_ids(const Grid& g, int& count) {
+    std::vector<int32_t> id((size_t)(g.nx + 1) * (g.ny + 1), -1);
+    count = 0;
+    for (int k = 0; k <= g.ny; ++k)
+        for (int i = 0; i <= g.nx; ++i)
+            if (g.vertex_cells(i, k) > 0) id[(size_t)k * (g.nx + 1) + i] = count++;
+    return id;
+}
+
+void grad_bary(const double* p0, const double* p1, const double* p2, double gl[3][2], double& area) {
+    double two_a = (p1[0] - p0[0]) * (p2[1] - p0[1]) - (p2[0] - p0[0]) * (p1[1] - p0[1]);
+    const double* p[3] = {p0, p1, p2};
+    for (int i = 0; i < 3; ++i) {
+        const double* a = p[(i + 1) % 3];
+        const double* b = p[(i + 2) % 3];
+        gl[i][0] = (a[1] - b[1]) / two_a;
+        gl[i][1] = (b[0] - a[0]) / two_a;
+    }
+    area = 0.5 * std::fabs(two_a);
+}
+
+// rows of (row, col, val) triplets -> CSR with summed duplicates, sorted columns
+HostCSR triplets_to_csr(int64_t nrows, int64_t ncols, std::vector<std::vector<std::pair<int32_t, double>>>& rows) {
+    HostCSR c;
+    c.nrows = nrows;
+    c.ncols = ncols;
+    c.rowptr.assign(nrows + 1, 0);
+    for (int64_t r = 0; r < nrows; ++r) {
+        auto& v = rows[r];
+        std::sort(v.begin(), v.end(), [](auto& a, auto& b) { return a.first < b.first; });
+        int32_t last = -1;
+        for (auto& e : v) {
+            if (e.first == last) {
+                c.val.back() += e.second;
+            } else {
+                c.col.push_back(e.first);
+                c.val.push_back(e.second);
+                last = e.first;
+            }
+        }
+        c.rowptr[r + 1] = (int32_t)c.col.size();
+    }
+    return c;
+}
+
+HostCSR transpose(const HostCSR& a) {
+    std::vector<std::vector<std::pair<int32_t, double>>> rows(a.ncols);
+    for (int64_t r = 0; r < a.nrows; ++r)
+        for (int32_t p = a.rowptr[r]; p < a.rowptr[r + 1]; ++p) rows[a.col[p]].push_back({(int32_t)r, a.val[p]});
+    return triplets_to_csr(a.ncols, a.nrows, rows);
+}
+
+bool invert_dense(std::vector<double>& a, int n) {
+    std::vector<double> inv((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) inv[(size_t)i * n + i] = 1.0;
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < n; ++r)
+            if (std::fabs(a[(size_t)r * n + c]) > std::fabs(a[(size_t)piv * n + c])) piv = r;
+        if (std::fabs(a[(size_t)piv * n + c]) < 1e-300) return false;
+        if (piv != c)
+            for (int k = 0; k < n; ++k) {
+                std::swap(a[(size_t)c * n + k], a[(size_t)piv * n + k]);
+                std::swap(inv[(size_t)c * n + k], inv[(size_t)piv * n + k]);
+            }
+        double d = 1.0 / a[(size_t)c * n + c];
+        for (int k = 0; k < n; ++k) {
+            a[(size_t)c * n + k] *= d;
+            inv[(size_t)c * n + k] *= d;
+        }
+        for (int r = 0; r < n; ++r) {
+            if (r == c) continue;
+            double f = a[(size_t)r * n + c];
+            if (f == 0.0) continue;
+            for (int k = 0; k < n; ++k) {
+                a[(size_t)r * n + k] -= f * a[(size_t)c * n + k];
+                inv[(size_t)r * n + k] -= f * inv[(size_t)c * n + k];
+            }
+        }
+    }
+    a.swap(inv);
+    return true;
+}
+
+// P1 stiffness of a grid level with fixed rows (pin / outflow) as identity rows.
+void build_level(const mhd_mesh_desc* d, int level, HostLevel& L, std::vector<uint8_t>& fixed,
+                 std::vector<int32_t>& vid) {
+    Grid g = make_grid(d, level);
+    L.nx = g.nx;
+    L.ny = g.ny;
+    L.h = g.h;
+    int nv = 0;
+    vid = vertex_ids(g, nv);
+    L.n = nv;
+    std::vector<std::array<double, 2>> xy(nv);
+    for (int k = 0; k <= g.ny; ++k)
+        for (int i = 0; i <= g.nx; ++i) {
+            int id = vid[(size_t)k * (g.nx + 1) + i];
+            if (id >= 0) xy[id] = {g.x0 + i * g.h, g.y0 + k * g.h};
+        }
+    fixed.assign(nv, 0);
+    double xmax = g.x0 + g.nx * g.h;
+    if (d->kind == MHD_MESH_STEP_CHANNEL && d->natural_outflow) {
+        for (int v = 0; v < nv; ++v)
+            if (std::fabs(xy[v][0] - xmax) < 1e-9 * (1 + xmax)) fixed[v] = 1;
+    } else {
+        fixed[0] = 1;   // pinned pressure: first vertex in row-major order
+    }
+    std::vector<std::vector<std::pair<int32_t, double>>> rows(nv);
+    for (int k = 0; k < g.ny; ++k)
+        for (int i = 0; i < g.nx; ++i) {
+            if (!g.cell(i, k)) continue;
+            int v00 = vid[(size_t)k * (g.nx + 1) + i], v10 = vid[(size_t)k * (g.nx + 1) + i + 1];
+            int v11 = vid[(size_t)(k + 1) * (g.nx + 1) + i + 1], v01 = vid[(size_t)(k + 1) * (g.nx + 1) + i];
+            int tris[2][3] = {{v00, v10, v11}, {v00, v11, v01}};
+            for (auto& t : tris) {
+                double gl[3][2], area;
+                grad_bary(xy[t[0]].data(), xy[t[1]].data(), xy[t[2]].data(), gl, area);
+                for (int a = 0; a < 3; ++a) {
+                    if (fixed[t[a]]) continue;
+                    for (int b = 0; b < 3; ++b)
+                        rows[t[a]].push_back({t[b], area * (gl[a][0] * gl[b][0] + gl[a][1] * gl[b][1])});
+                }
+            }
+        }
+    for (int v = 0; v < nv; ++v)
+        if (fixed[v]) rows[v] = {{v, 1.0}};
+    L.L = triplets_to_csr(nv, nv, rows);
+    L.dinv.assign(nv, 0.0);
+    for (int v = 0; v < nv; ++v)
+        for (int32_t p = L.L.rowptr[v]; p < L.L.rowptr[v + 1]; ++p)
+            if (L.L.col[p] == v) L.dinv[v] = 1.0 / L.L.val[p];
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- reference tables
+void make_ref_tables(RefTables& t) {
+    std::memset(&t, 0, sizeof(t));
+    // 7-point degree-5 rule (Radon): centroid + two 3-point orbits (a, a, 1-2a)
+    const double s15 = std::sqrt(15.0);
+    double lam[7][3];
+    lam[0][0] = lam[0][1] = lam[0][2] = 1.0 / 3.0;
+    t.w[0] = 9.0 / 40.0;
+    const double aa[2] = {(6.0 - s15) / 21.0, (6.0 + s15) / 21.0};
+    const double ww[2] = {(155.0 - s15) / 1200.0, (155.0 + s15) / 1200.0};
+    int q = 1;
+    for (int o = 0; o < 2; ++o) {
+        double a = aa[o], b = 1.0 - 2.0 * a;
+        double pts[3][3] = {{b, a, a}, {a, b, a}, {a, a, b}};
+        for (auto& p : pts) {
+            lam[q][0] = p[0];
+            lam[q][1] = p[1];
+            lam[q][2] = p[2];
+            t.w[q] = ww[o];
+            ++q;
+        }
+    }
+    // barycentric gradients on the reference triangle (0,0),(1,0),(0,1)
+    const double dl[3][2] = {{-1.0, -1.0}, {1.0, 0.0}, {0.0, 1.0}};
+    const int ed[3][2] = {{0, 1}, {1, 2}, {2, 0}};
+    for (q = 0; q < 7; ++q) {
+        const double* l = lam[q];
+        for (int i = 0; i < 3; ++i) {
+            t.phi[q][i] = l[i] * (2.0 * l[i] - 1.0);
+            for (int d = 0; d < 2; ++d) t.dphi[q][i][d] = (4.0 * l[i] - 1.0) * dl[i][d];
+            t.psi[q][i] = l[i];
+        }
+        for (int e = 0; e < 3; ++e) {
+            int a = ed[e][0], b = ed[e][1];
+            t.phi[q][3 + e] = 4.0 * l[a] * l[b];
+            for (int d = 0; d < 2; ++d) t.dphi[q][3 + e][d] = 4.0 * (l[b] * dl[a][d] + l[a] * dl[b][d]);
+        }
+    }
+    for (q = 0; q < 7; ++q) {
+        double wq = 0.5 * t.w[q];
+        for (int a = 0; a < 6; ++a)
+            for (int b = 0; b < 6; ++b) {
+                t.Mhat[a][b] += wq * t.phi[q][a] * t.phi[q][b];
+                for (int e = 0; e < 2; ++e)
+                    for (int f = 0; f < 2; ++f) t.Khat[a][b][e][f] += wq * t.dphi[q][a][e] * t.dphi[q][b][f];
+                for (int c = 0; c < 6; ++c)
+                    for (int e = 0; e < 2; ++e) t.That[a][b][c][e] += wq * t.phi[q][a] * t.phi[q][b] * t.dphi[q][c][e];
+            }
+        for (int k = 0; k < 3; ++k)
+            for (int a = 0; a < 6; ++a)
+                for (int e = 0; e < 2; ++e) t.Bhat[k][a][e] -= wq * t.psi[q][k] * t.dphi[q][a][e];
+    }
+    for (int a = 0; a < 6; ++a)
+        for (int b = 0; b < 6; ++b)
+            for (int c = 0; c < 6; ++c)
+                for (int e = 0; e < 2; ++e) t.Shat[a][b][c][e] = 0.5 * (t.That[a][b][c][e] - t.That[c][b][a][e]);
+}
+
+// ---------------------------------------------------------------- mesh
+mhd_status build_mesh(const mhd_mesh_desc* d, HostMesh& m, bool full) {
+    if (!d) {
+        set_error("mhd_ens_mesh: null descriptor");
+        return MHD_EINVAL;
+    }
+    if (d->kind != MHD_MESH_UNIT_SQUARE && d->kind != MHD_MESH_STEP_CHANNEL) {
+        set_error("mhd_ens_mesh: unknown mesh kind");
+        return MHD_EINVAL;
+    }
+    if (d->nx < 1 || d->nx > 4096) {
+        set_error("mhd_ens_mesh: nx must be in [1, 4096]");
+        return MHD_EINVAL;
+    }
+    if (d->kind == MHD_MESH_UNIT_SQUARE && d->natural_outflow) {
+        set_error("mhd_ens_mesh: natural outflow is only defined for the step channel");
+        return MHD_EINVAL;
+    }
+    m.desc = *d;
+    Grid g = make_grid(d, 0);
+    m.nx = g.nx;
+    m.ny = g.ny;
+    m.h = g.h;
+    m.x0 = g.x0;
+    m.y0 = g.y0;
+    m.xmax = g.x0 + g.nx * g.h;
+    const int NX = 2 * g.nx + 1, NY = 2 * g.ny + 1;
+    // ---- P2 nodes on the half-step grid
+    std::vector<int32_t> pid((size_t)NX * NY, -1);
+    std::vector<uint8_t> pbnd((size_t)NX * NY, 0);
+    int nP2 = 0;
+    for (int K = 0; K < NY; ++K)
+        for (int I = 0; I < NX; ++I) {
+            int cnt = 0, tot = 0;
+            if ((I & 1) == 0 && (K & 1) == 0) {
+                cnt = g.vertex_cells(I / 2, K / 2);
+                tot = 4;
+            } else if ((I & 1) == 1 && (K & 1) == 0) {
+                int i = (I - 1) / 2, k = K / 2;
+                cnt = (int)g.cell(i, k - 1) + (int)g.cell(i, k);
+                tot = 2;
+            } else if ((I & 1) == 0 && (K & 1) == 1) {
+                int i = I / 2, k = (K - 1) / 2;
+                cnt = (int)g.cell(i - 1, k) + (int)g.cell(i, k);
+                tot = 2;
+            } else {
+                cnt = (int)g.cell((I - 1) / 2, (K - 1) / 2);
+                tot = 1;
+            }
+            if (cnt > 0) {
+                pid[(size_t)K * NX + I] = nP2++;
+                pbnd[(size_t)K * NX + I] = (cnt < tot) ? 1 : 0;
+            }
+        }
+    m.nP2 = nP2;
+    int nP1 = 0;
+    std::vector<int32_t> vid = vertex_ids(g, nP1);
+    m.nP1 = nP1;
+    int n_el = 0;
+    for (int k = 0; k < g.ny; ++k)
+        for (int i = 0; i < g.nx; ++i) n_el += g.cell(i, k) ? 2 : 0;
+    m.n_el = n_el;
+    if (!full) return MHD_OK;
+
+    m.xy.assign((size_t)nP2 * 2, 0.0);
+    m.bnd.assign(nP2, 0);
+    m.dir.assign(nP2, 0);
+    m.p1_of_p2.assign(nP2, -1);
+    for (int K = 0; K < NY; ++K)
+        for (int I = 0; I < NX; ++I) {
+            int id = pid[(size_t)K * NX + I];
+            if (id < 0) continue;
+            double x = g.x0 + I * 0.5 * g.h, y = g.y0 + K * 0.5 * g.h;
+            m.xy[2 * id] = x;
+            m.xy[2 * id + 1] = y;
+            m.bnd[id] = pbnd[(size_t)K * NX + I];
+            bool outflow = d->natural_outflow && std::fabs(x - m.xmax) < 1e-9 * (1 + m.xmax);
+            m.dir[id] = (m.bnd[id] && !outflow) ? 1 : 0;
+            if ((I & 1) == 0 && (K & 1) == 0) m.p1_of_p2[id] = vid[(size_t)(K / 2) * (g.nx + 1) + I / 2];
+        }
+    m.dir_nodes.clear();
+    for (int i = 0; i < nP2; ++i)
+        if (m.dir[i]) m.dir_nodes.push_back(i);
+    // ---- elements
+    m.tri.resize((size_t)n_el * 6);
+    m.tri1.resize((size_t)n_el * 3);
+    auto P = [&](int I, int K) { return pid[(size_t)K * NX + I]; };
+    auto V = [&](int i, int k) { return vid[(size_t)k * (g.nx + 1) + i]; };
+    int e = 0;
+    for (int k = 0; k < g.ny; ++k)
+        for (int i = 0; i < g.nx; ++i) {
+            if (!g.cell(i, k)) continue;
+            int I = 2 * i, K = 2 * k;
+            // lower (v00, v10, v11), upper (v00, v11, v01); locals 3,4,5 = mid(0,1), mid(1,2), mid(2,0)
+            int lo[6] = {P(I, K), P(I + 2, K), P(I + 2, K + 2), P(I + 1, K), P(I + 2, K + 1), P(I + 1, K + 1)};
+            int up[6] = {P(I, K), P(I + 2, K + 2), P(I, K + 2), P(I + 1, K + 1), P(I + 1, K + 2), P(I, K + 1)};
+            int lo1[3] = {V(i, k), V(i + 1, k), V(i + 1, k + 1)};
+            int up1[3] = {V(i, k), V(i + 1, k + 1), V(i, k + 1)};
+            for (int a = 0; a < 6; ++a) m.tri[(size_t)e * 6 + a] = lo[a];
+            for (int a = 0; a < 3; ++a) m.tri1[(size_t)e * 3 + a] = lo1[a];
+            ++e;
+            for (int a = 0; a < 6; ++a) m.tri[(size_t)e * 6 + a] = up[a];
+            for (int a = 0; a < 3; ++a) m.tri1[(size_t)e * 3 + a] = up1[a];
+            ++e;
+        }
+    // ---- patterns
+    {
+        std::vector<std::vector<int32_t>> rA(nP2), rBt(nP2), rB(nP1);
+        for (e = 0; e < n_el; ++e) {
+            const int32_t* t = &m.tri[(size_t)e * 6];
+            const int32_t* t1 = &m.tri1[(size_t)e * 3];
+            for (int a = 0; a < 6; ++a) {
+                for (int b = 0; b < 6; ++b) rA[t[a]].push_back(t[b]);
+                for (int k = 0; k < 3; ++k) {
+                    rBt[t[a]].push_back(t1[k]);
+                    rB[t1[k]].push_back(t[a]);
+                }
+            }
+        }
+        auto finish = [](std::vector<std::vector<int32_t>>& rows, int64_t ncols, HostCSR& c) {
+            c.nrows = (int64_t)rows.size();
+            c.ncols = ncols;
+            c.rowptr.assign(rows.size() + 1, 0);
+            c.col.clear();
+            for (size_t r = 0; r < rows.size(); ++r) {
+                auto& v = rows[r];
+                std::sort(v.begin(), v.end());
+                v.erase(std::unique(v.begin(), v.end()), v.end());
+                c.col.insert(c.col.end(), v.begin(), v.end());
+                c.rowptr[r + 1] = (int32_t)c.col.size();
+                std::vector<int32_t>().swap(v);
+            }
+        };
+        finish(rA, nP2, m.A);
+        finish(rBt, nP1, m.Bt);
+        finish(rB, nP2, m.B);
+    }
+    auto slot = [](const HostCSR& c, int32_t r, int32_t col) {
+        const int32_t* b = c.col.data() + c.rowptr[r];
+        const int32_t* en = c.col.data() + c.rowptr[r + 1];
+        const int32_t* p = std::lower_bound(b, en, col);
+        return (int32_t)(p - c.col.data());
+    };
+    m.slotA.resize((size_t)n_el * 36);
+    std::vector<int32_t> slotB((size_t)n_el * 18), slotBt((size_t)n_el * 18);
+    for (e = 0; e < n_el; ++e) {
+        const int32_t* t = &m.tri[(size_t)e * 6];
+        const int32_t* t1 = &m.tri1[(size_t)e * 3];
+        for (int a = 0; a < 6; ++a)
+            for (int b = 0; b < 6; ++b) m.slotA[(size_t)e * 36 + a * 6 + b] = slot(m.A, t[a], t[b]);
+        for (int k = 0; k < 3; ++k)
+            for (int a = 0; a < 6; ++a) {
+                slotB[(size_t)e * 18 + k * 6 + a] = slot(m.B, t1[k], t[a]);
+                slotBt[(size_t)e * 18 + k * 6 + a] = slot(m.Bt, t[a], t1[k]);
+            }
+    }
+    auto gather = [](const std::vector<int32_t>& slots, int64_t nslots, std::vector<int32_t>& ptr,
+                     std::vector<int32_t>& idx) {
+        ptr.assign(nslots + 1, 0);
+        for (int32_t s : slots) ptr[s + 1]++;
+        for (int64_t i = 0; i < nslots; ++i) ptr[i + 1] += ptr[i];
+        idx.assign(slots.size(), 0);
+        std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+        for (size_t c = 0; c < slots.size(); ++c) idx[fill[slots[c]]++] = (int32_t)c;
+    };
+    gather(m.slotA, m.A.nnz(), m.gA_ptr, m.gA_idx);
+    gather(slotB, m.B.nnz(), m.gB_ptr, m.gB_idx);
+    gather(slotBt, m.Bt.nnz(), m.gBt_ptr, m.gBt_idx);
+    // ---- node -> (element, local) incidence
+    m.inc_ptr.assign(nP2 + 1, 0);
+    for (e = 0; e < n_el; ++e)
+        for (int a = 0; a < 6; ++a) m.inc_ptr[m.tri[(size_t)e * 6 + a] + 1]++;
+    for (int i = 0; i < nP2; ++i) m.inc_ptr[i + 1] += m.inc_ptr[i];
+    m.inc.assign(m.inc_ptr[nP2], 0);
+    {
+        std::vector<int32_t> fill(m.inc_ptr.begin(), m.inc_ptr.end() - 1);
+        for (e = 0; e < n_el; ++e)
+            for (int a = 0; a < 6; ++a) m.inc[fill[m.tri[(size_t)e * 6 + a]]++] = e * 8 + a;
+    }
+    // ---- lumped P1 mass
+    m.mp.assign(nP1, 0.0);
+    for (e = 0; e < n_el; ++e) {
+        const int32_t* t = &m.tri[(size_t)e * 6];
+        double gl[3][2], area;
+        grad_bary(&m.xy[2 * t[0]], &m.xy[2 * t[1]], &m.xy[2 * t[2]], gl, area);
+        for (int k = 0; k < 3; ++k) m.mp[m.tri1[(size_t)e * 3 + k]] += area / 3.0;
+    }
+    // ---- pressure fixing and multigrid hierarchy
+    m.levels.clear();
+    std::vector<std::vector<uint8_t>> fixed;
+    std::vector<std::vector<int32_t>> vids;
+    int level = 0;
+    while (true) {
+        HostLevel L;
+        std::vector<uint8_t> fx;
+        std::vector<int32_t> vi;
+        build_level(d, level, L, fx, vi);
+        m.levels.push_back(std::move(L));
+        fixed.push_back(std::move(fx));
+        vids.push_back(std::move(vi));
+        const HostLevel& cur = m.levels.back();
+        bool can_halve;
+        if (d->kind == MHD_MESH_UNIT_SQUARE)
+            can_halve = (cur.nx % 2 == 0) && cur.nx >= 4;
+        else
+            can_halve = ((d->nx >> level) % 2 == 0);
+        if (cur.n <= 400 || !can_halve) break;
+        ++level;
+    }
+    m.pfix = fixed[0];
+    m.pin = -1;
+    if (!(d->kind == MHD_MESH_STEP_CHANNEL && d->natural_outflow)) m.pin = 0;
+    // interpolation from level l+1 to level l: P1 interpolation on the coarse triangulation
+    for (size_t l = 0; l + 1 < m.levels.size(); ++l) {
+        HostLevel& F = m.levels[l];
+        const HostLevel& C = m.levels[l + 1];
+        std::vector<std::vector<std::pair<int32_t, double>>> rows(F.n);
+        auto cid = [&](int ci, int ck) -> int32_t {
+            if (ci < 0 || ck < 0 || ci > C.nx || ck > C.ny) return -1;
+            return vids[l + 1][(size_t)ck * (C.nx + 1) + ci];
+        };
+        for (int k = 0; k <= F.ny; ++k)
+            for (int i = 0; i <= F.nx; ++i) {
+                int f = vids[l][(size_t)k * (F.nx + 1) + i];
+                if (f < 0 || fixed[l][f]) continue;
+                std::vector<std::pair<int32_t, double>> ent;
+                if (i % 2 == 0 && k % 2 == 0) {
+                    ent.push_back({cid(i / 2, k / 2), 1.0});
+                } else if (i % 2 == 1 && k % 2 == 0) {
+                    ent.push_back({cid((i - 1) / 2, k / 2), 0.5});
+                    ent.push_back({cid((i + 1) / 2, k / 2), 0.5});
+                } else if (i % 2 == 0 && k % 2 == 1) {
+                    ent.push_back({cid(i / 2, (k - 1) / 2), 0.5});
+                    ent.push_back({cid(i / 2, (k + 1) / 2), 0.5});
+                } else {
+                    ent.push_back({cid((i - 1) / 2, (k - 1) / 2), 0.5});
+                    ent.push_back({cid((i + 1) / 2, (k + 1) / 2), 0.5});
+                }
+                for (auto& en : ent)
+                    if (en.first >= 0 && !fixed[l + 1][en.first]) rows[f].push_back(en);
+            }
+        F.P = triplets_to_csr(F.n, C.n, rows);
+        F.R = transpose(F.P);
+    }
+    HostLevel& Lc = m.levels.back();
+    Lc.cinv.assign((size_t)Lc.n * Lc.n, 0.0);
+    for (int r = 0; r < Lc.n; ++r)
+        for (int32_t p = Lc.L.rowptr[r]; p < Lc.L.rowptr[r + 1]; ++p) Lc.cinv[(size_t)r * Lc.n + Lc.L.col[p]] = Lc.L.val[p];
+    if (!invert_dense(Lc.cinv, Lc.n)) {
+        set_error("mhd_ens_mesh: singular coarsest pressure Laplacian");
+        return MHD_EINVAL;
+    }
+    return MHD_OK;
+}
+
+void mesh_counts(const HostMesh& m, mhd_mesh_info* info) {
+    info->n_el = m.n_el;
+    info->nP2 = m.nP2;
+    info->nP1 = m.nP1;
+    info->n_u = 2 * (int64_t)m.nP2;
+    info->n = 2 * (int64_t)m.nP2 + m.nP1;
+    info->nnz_A = m.A.nnz();
+    info->nnz_B = m.B.nnz();
+    info->nnz = 2 * m.A.nnz() + 2 * m.Bt.nnz() + 2 * m.B.nnz() + (m.pin >= 0 ? 1 : 0);
+    int64_t nb = 0;
+    for (auto b : m.bnd) nb += b;
+    info->n_bd = nb;
+    info->n_dir = (int64_t)m.dir_nodes.size();
+    info->pin = m.pin;
+    info->mg_levels = (int32_t)m.levels.size();
+}
+
+}  // namespace mhd

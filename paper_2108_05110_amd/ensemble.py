@@ -1,0 +1,102 @@
+"""Device-resident driver around the C ABI: a mesh handle and a step context
+holding the member states (V, W, Q, R) in GPU memory.  Problem data (initial
+values, Dirichlet data, forcing) comes from a ``workloads`` problem evaluated
+at this mesh's node coordinates and is uploaded once per distinct time level.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+class Mesh:
+    def __init__(self, kind: int, nx: int, natural_outflow: int = 0):
+        self.handle, self.info = L.mhd_ens_mesh(kind, nx, natural_outflow)
+        self.xy, self.dir_nodes = L.mhd_ens_mesh_coords(self.handle, self.info)
+        self.kind, self.nx = kind, nx
+
+    @property
+    def nP2(self):
+        return int(self.info.nP2)
+
+    @property
+    def nP1(self):
+        return int(self.info.nP1)
+
+    @property
+    def n(self):
+        return int(self.info.n)
+
+    def close(self):
+        if self.handle:
+            L.mhd_ens_mesh_free(self.handle)
+            self.handle = None
+
+
+def to_dev(a, device="cuda"):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(device)
+
+
+class Stepper:
+    """Algorithm 1 on the GPU for one ensemble: mhd_ens_step per time step."""
+
+    def __init__(self, mesh: Mesh, problem, J_max=None, opts=None, device="cuda", time_dependent_data=True):
+        self.mesh = mesh
+        self.pb = problem
+        self.J = problem.J
+        self.device = device
+        self.opts = opts if opts is not None else L.solver_opts()
+        desc = L.CtxDesc(L.Coeffs(problem.dt, problem.mu, float(np.mean(problem.nu)),
+                                  float(np.mean(problem.nu_m)), int(problem.convective)),
+                         self.opts, J_max or self.J)
+        self.ctx = L.mhd_ens_ctx_create(mesh.handle, desc)
+        V0, W0 = problem.ic(mesh.xy)
+        self.V = to_dev(V0, device)
+        self.W = to_dev(W0, device)
+        self.Q = torch.zeros((mesh.nP1, self.J), dtype=torch.float64, device=device)
+        self.R = torch.zeros_like(self.Q)
+        self.nu = np.ascontiguousarray(problem.nu, dtype=np.float64)
+        self.nu_m = np.ascontiguousarray(problem.nu_m, dtype=np.float64)
+        self.time_dependent = time_dependent_data
+        self._data_t = None
+        self.f1 = self.f2 = self.gv = self.gw = None
+        self.t = 0.0
+        self.n = 0
+
+    def set_data(self, t_next):
+        if self._data_t is not None and (not self.time_dependent or self._data_t == t_next):
+            return
+        xy = self.mesh.xy
+        F1, F2 = self.pb.forcing(t_next, xy)
+        if np.any(F1) or np.any(F2):
+            self.f1, self.f2 = to_dev(F1, self.device), to_dev(F2, self.device)
+        else:
+            self.f1 = self.f2 = None
+        dxy = xy[self.mesh.dir_nodes]
+        Gv, Gw = self.pb.bc(t_next, dxy)
+        self.gv, self.gw = to_dev(Gv, self.device), to_dev(Gw, self.device)
+        self._data_t = t_next
+
+    def inputs(self):
+        return L.StepInputs(self.nu.ctypes.data_as(C.POINTER(C.c_double)),
+                            self.nu_m.ctypes.data_as(C.POINTER(C.c_double)),
+                            L.ptr(self.f1), L.ptr(self.f2), L.ptr(self.gv), L.ptr(self.gw), self.J)
+
+    def step(self, stats=True, allow_noconv=False):
+        t_next = (self.n + 1) * self.pb.dt
+        self.set_data(t_next)
+        inp = self.inputs()
+        st = L.mhd_ens_step(self.ctx, self.V, self.W, self.Q, self.R, inp, stats=stats,
+                            allow_noconv=allow_noconv)
+        self.n += 1
+        self.t = t_next
+        return st
+
+    def close(self):
+        if self.ctx:
+            L.mhd_ens_ctx_free(self.ctx)
+            self.ctx = None
