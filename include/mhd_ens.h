@@ -221,6 +221,21 @@ typedef struct {
 mhd_status mhd_ens_step(mhd_ctx ctx, double* V, double* W, double* Q, double* R,
                         const mhd_step_inputs* in, mhd_step_stats* st, mhd_stream_t s);
 
+/* (Section 1: the shared matrix A applied to [x_1|...|x_J]) y = S x for an
+ * (n,J) block with the assembled operator of A: the SpMM the Krylov solver
+ * performs once per iteration.  precision MHD_FP64: x, y double; MHD_FP32_IR:
+ * x, y float with the FP32 shadow values.  x and y must not overlap. */
+mhd_status mhd_ens_spmm(mhd_shared A, const void* x, void* y, int J, int precision, mhd_stream_t s);
+
+/* Diagnostics: while enabled, every saddle-point SpMM launch of this library
+ * (inside mhd_ens_solve / mhd_ens_step and mhd_ens_spmm) is bracketed by HIP
+ * events recorded on its stream.  mhd_ens_timer_read synchronises those
+ * events and returns the summed kernel milliseconds and the launch count
+ * since the last enable; nbytes_fp32 / nbytes_fp64 receive the summed
+ * launch sizes (units of n*J) per precision.  Enabling resets the counters. */
+mhd_status mhd_ens_timer_enable(int on);
+mhd_status mhd_ens_timer_read(double* ms, int64_t* launches, double* nJ_fp32, double* nJ_fp64);
+
 /* Last error message of the calling thread ("" if none). */
 const char* mhd_ens_last_error(void);
 

@@ -24,7 +24,7 @@ EXPORTS = (
     "mhd_ens_mesh_counts", "mhd_ens_mesh", "mhd_ens_mesh_coords", "mhd_ens_mesh_free",
     "mhd_ens_shared_create", "mhd_ens_shared_free", "mhd_ens_assemble_shared", "mhd_ens_shared_csr",
     "mhd_ens_assemble_rhs", "mhd_ens_solve", "mhd_ens_ctx_create", "mhd_ens_ctx_free", "mhd_ens_step",
-    "mhd_ens_last_error", "mhd_ens_version",
+    "mhd_ens_spmm", "mhd_ens_timer_enable", "mhd_ens_timer_read", "mhd_ens_last_error", "mhd_ens_version",
 )
 
 
@@ -99,6 +99,10 @@ def lib():
             "mhd_ens_ctx_create": [P, C.POINTER(CtxDesc), C.POINTER(P)],
             "mhd_ens_ctx_free": [P],
             "mhd_ens_step": [P, P, P, P, P, C.POINTER(StepInputs), C.POINTER(StepStats), P],
+            "mhd_ens_spmm": [P, P, P, I, I, P],
+            "mhd_ens_timer_enable": [I],
+            "mhd_ens_timer_read": [C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_double),
+                                   C.POINTER(C.c_double)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -219,6 +223,20 @@ def mhd_ens_step(ctx, V, W, Q, R, inputs, stats=True, stream=None, allow_noconv=
     check("mhd_ens_step", lib().mhd_ens_step(ctx, ptr(V), ptr(W), ptr(Q), ptr(R), C.byref(inputs),
                                              C.byref(st) if st is not None else None, stream_ptr(stream)), allow)
     return st
+
+
+def mhd_ens_spmm(A, x, y, J, precision, stream=None):
+    check("mhd_ens_spmm", lib().mhd_ens_spmm(A, ptr(x), ptr(y), J, precision, stream_ptr(stream)))
+
+
+def mhd_ens_timer_enable(on=True):
+    check("mhd_ens_timer_enable", lib().mhd_ens_timer_enable(1 if on else 0))
+
+
+def mhd_ens_timer_read():
+    ms, n, a, b = C.c_double(), C.c_int64(), C.c_double(), C.c_double()
+    check("mhd_ens_timer_read", lib().mhd_ens_timer_read(C.byref(ms), C.byref(n), C.byref(a), C.byref(b)))
+    return ms.value, n.value, a.value, b.value
 
 
 def solver_opts(precision=MHD_FP64, rtol=None, inner_rtol=None, maxit=2000, restart=30, jacobi_sweeps=2,

@@ -398,6 +398,24 @@ mhd_status mhd_ens_solve(mhd_shared A, const double* rhs, double* x, int J, cons
     return solve_shared(A->d, rhs, x, J, *o, st, as_stream(s));
 }
 
+mhd_status mhd_ens_spmm(mhd_shared A, const void* x, void* y, int J, int precision, mhd_stream_t s) {
+    CHECK_ARG(A && x && y, "mhd_ens_spmm: null argument");
+    CHECK_ARG(x != y, "mhd_ens_spmm: x and y must not overlap");
+    CHECK_ARG(precision == MHD_FP64 || precision == MHD_FP32_IR, "mhd_ens_spmm: bad precision");
+    if (J < 1 || J > A->d.Jmax) {
+        set_error("mhd_ens_spmm: J outside [1, J_max]");
+        return MHD_ESHAPE;
+    }
+    CHECK_ARG(A->d.assembled, "mhd_ens_spmm: matrix not assembled");
+    return spmm_shared(A->d, x, y, J, precision, as_stream(s));
+}
+
+mhd_status mhd_ens_timer_enable(int on) { return timer_enable(on); }
+
+mhd_status mhd_ens_timer_read(double* ms, int64_t* launches, double* nJ32, double* nJ64) {
+    return timer_read(ms, launches, nJ32, nJ64);
+}
+
 mhd_status mhd_ens_ctx_create(mhd_mesh m, const mhd_ctx_desc* d, mhd_ctx* out) {
     CHECK_ARG(out, "mhd_ens_ctx_create: null output handle");
     *out = nullptr;

@@ -134,6 +134,9 @@ hipError_t launch_energy_partial(const DevMesh& m, const double* vbar, double* o
 mhd_status alloc_gmres(DevShared& S, int restart);
 mhd_status solve_shared(DevShared& S, const double* rhs, double* x, int J, const mhd_solver_opts& o,
                         mhd_solve_stats* st, hipStream_t s);
+mhd_status spmm_shared(DevShared& S, const void* x, void* y, int J, int precision, hipStream_t s);
+mhd_status timer_enable(int on);
+mhd_status timer_read(double* ms, int64_t* launches, double* nJ32, double* nJ64);
 mhd_status saddle_residual64(DevShared& S, const double* b, const double* x, double* r, int J, hipStream_t s);
 
 // pressure post-processing: p -= (sum_k m_k p_k) / sum_k m_k per member

@@ -503,6 +503,37 @@ __global__ void k_add_vec(double* __restrict__ a, const double* __restrict__ b, 
     if (i < n) a[i] += b[i];
 }
 
+// ------------------------------------------------------------------ kernel timer
+struct KTimer {
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    double ms = 0.0;
+    int64_t launches = 0;
+    double nJ32 = 0.0, nJ64 = 0.0;
+};
+KTimer g_timer;
+
+hipError_t timer_fold() {
+    for (size_t i = 0; i + 1 < g_timer.used; i += 2) {
+        hipError_t e = hipEventSynchronize(g_timer.pool[i + 1]);
+        if (e != hipSuccess) return e;
+        float t = 0.f;
+        e = hipEventElapsedTime(&t, g_timer.pool[i], g_timer.pool[i + 1]);
+        if (e != hipSuccess) return e;
+        g_timer.ms += t;
+    }
+    g_timer.used = 0;
+    return hipSuccess;
+}
+
+// record the start (before = true) or the end of one timed launch on stream st
+void timer_mark(hipStream_t st, bool before) {
+    if (!g_timer.on) return;
+    if (before && g_timer.used + 2 > g_timer.pool.size()) (void)timer_fold();
+    if (g_timer.used < g_timer.pool.size()) (void)hipEventRecord(g_timer.pool[g_timer.used++], st);
+}
+
 // ------------------------------------------------------------------ host-side operators
 template <typename T>
 struct Ops {
@@ -516,10 +547,16 @@ struct Ops {
     mhd_status saddle(const T* x, T* y) {
         DevMesh& m = *S.mesh;
         int64_t units = (int64_t)m.nP2 + m.nP1;
+        timer_mark(st, true);
         hipLaunchKernelGGL((k_saddle<T, 0>), dim3(grid_for(units, JP)), dim3(kBlock), 0, st, m.A_rowptr, m.A_col,
                            Vals<T>::A(S), m.Bt_rowptr, m.Bt_col, Vals<T>::Bt(m), m.B_rowptr, m.B_col, Vals<T>::B(m),
                            Vals<T>::dp(m), x, (const T*)nullptr, y, m.nP2, m.nP1, J, JP);
         LAUNCH_CHECK();
+        if (g_timer.on) {
+            timer_mark(st, false);
+            g_timer.launches++;
+            (sizeof(T) == 4 ? g_timer.nJ32 : g_timer.nJ64) += (double)J;
+        }
         return MHD_OK;
     }
 
@@ -823,6 +860,51 @@ mhd_status saddle_residual64(DevShared& S, const double* b, const double* x, dou
                        m.A_rowptr, m.A_col, S.valA, m.Bt_rowptr, m.Bt_col, m.valBt, m.B_rowptr, m.B_col, m.valB,
                        m.diagp, x, b, r, m.nP2, m.nP1, J, JP);
     LAUNCH_CHECK();
+    return MHD_OK;
+}
+
+mhd_status spmm_shared(DevShared& S, const void* x, void* y, int J, int precision, hipStream_t st) {
+    if (precision == MHD_FP32_IR) {
+        Ops<float> ops(S, J, st);
+        return ops.saddle((const float*)x, (float*)y);
+    }
+    Ops<double> ops(S, J, st);
+    return ops.saddle((const double*)x, (double*)y);
+}
+
+mhd_status timer_enable(int on) {
+    if (on) {
+        if (g_timer.pool.empty()) {
+            g_timer.pool.resize(8192);
+            for (auto& e : g_timer.pool) MHD_HIP(hipEventCreate(&e));
+        }
+        g_timer.used = 0;
+    } else {
+        hipError_t e = timer_fold();
+        if (e != hipSuccess) {
+            set_error(std::string("timer: ") + hipGetErrorString(e));
+            return MHD_EHIP;
+        }
+    }
+    if (on) {
+        g_timer.ms = 0.0;
+        g_timer.launches = 0;
+        g_timer.nJ32 = g_timer.nJ64 = 0.0;
+    }
+    g_timer.on = on != 0;
+    return MHD_OK;
+}
+
+mhd_status timer_read(double* ms, int64_t* launches, double* nJ32, double* nJ64) {
+    hipError_t e = timer_fold();
+    if (e != hipSuccess) {
+        set_error(std::string("timer: ") + hipGetErrorString(e));
+        return MHD_EHIP;
+    }
+    if (ms) *ms = g_timer.ms;
+    if (launches) *launches = g_timer.launches;
+    if (nJ32) *nJ32 = g_timer.nJ32;
+    if (nJ64) *nJ64 = g_timer.nJ64;
     return MHD_OK;
 }
 
