@@ -172,6 +172,7 @@ typedef struct {
     int restart;
     int jacobi_sweeps;        /* velocity-block smoothing sweeps in the preconditioner */
     int check_every;          /* inner iterations between convergence checks (>= 1)    */
+    int cgs_passes;           /* Gram-Schmidt passes: 1, 2, or 0 = 1 for FP32, 2 for FP64 */
 } mhd_solver_opts;
 
 typedef struct {

@@ -219,7 +219,39 @@ mhd_status check_coeffs(const mhd_coeffs* c) {
     return MHD_OK;
 }
 
+// Recomputes the Schur-approximation hierarchy when (dt, nu_c) change and
+// copies the new values into the existing device arrays (same patterns).
+mhd_status refresh_schur(DevMesh& D, double dt, double nu_c) {
+    HostMesh& h = D.host;
+    if (h.schur_dt == dt && h.schur_nuc == nu_c) return MHD_OK;
+    mhd_status rc = schur_values(h, dt, nu_c);
+    if (rc) return rc;
+    MHD_HIP(hipDeviceSynchronize());
+    for (size_t l = 0; l < h.levels.size(); ++l) {
+        const HostLevel& H = h.levels[l];
+        DevLevel& G = D.levels[l];
+        if ((int64_t)H.L.val.size() != G.L.nnz) {
+            set_error("refresh_schur: pattern size mismatch");
+            return MHD_EINVAL;
+        }
+        std::vector<float> v32(H.L.val.begin(), H.L.val.end());
+        std::vector<float> d32(H.dinv.begin(), H.dinv.end());
+        MHD_HIP(hipMemcpy(G.L.val, H.L.val.data(), sizeof(double) * H.L.val.size(), hipMemcpyHostToDevice));
+        MHD_HIP(hipMemcpy(G.L.val32, v32.data(), sizeof(float) * v32.size(), hipMemcpyHostToDevice));
+        MHD_HIP(hipMemcpy(G.dinv, H.dinv.data(), sizeof(double) * H.dinv.size(), hipMemcpyHostToDevice));
+        MHD_HIP(hipMemcpy(G.dinv32, d32.data(), sizeof(float) * d32.size(), hipMemcpyHostToDevice));
+        if (l + 1 == h.levels.size()) {
+            std::vector<float> c32(H.cinv.begin(), H.cinv.end());
+            MHD_HIP(hipMemcpy(G.cinv, H.cinv.data(), sizeof(double) * H.cinv.size(), hipMemcpyHostToDevice));
+            MHD_HIP(hipMemcpy(G.cinv32, c32.data(), sizeof(float) * c32.size(), hipMemcpyHostToDevice));
+        }
+    }
+    return MHD_OK;
+}
+
 mhd_status assemble_shared_impl(DevMesh& m, const mhd_coeffs& c, const double* z, int J, DevShared& S, hipStream_t s) {
+    mhd_status rc = refresh_schur(m, c.dt, 0.5 * (c.nu_bar + c.num_bar));
+    if (rc) return rc;
     hipError_t e = launch_mean(z, S.zbar, 2 * (int64_t)m.nP2, J, s);
     if (e == hipSuccess) e = launch_eddy_l2(m, z, S.zbar, S.l2, J, s);
     if (e == hipSuccess) e = launch_assemble_A(m, c, S.zbar, S.l2, S.elem, S.valA, S.valA32, S.dinvA, S.dinvA32, s);
@@ -240,6 +272,7 @@ mhd_status check_solver_opts(const mhd_solver_opts* o) {
     CHECK_ARG(o->maxit >= 1, "maxit must be >= 1");
     CHECK_ARG(o->restart >= 1 && o->restart <= kMaxRestart, "restart must be in [1, 40]");
     CHECK_ARG(o->jacobi_sweeps >= 1 && o->jacobi_sweeps <= 16, "jacobi_sweeps must be in [1, 16]");
+    CHECK_ARG(o->cgs_passes >= 0 && o->cgs_passes <= 2, "cgs_passes must be 0, 1 or 2");
     return MHD_OK;
 }
 

@@ -63,10 +63,14 @@ struct HostMesh {
     // P2 node -> (element, local index) incidence, sorted by element
     std::vector<int32_t> inc_ptr, inc;       // inc entry = e*8 + a
     std::vector<double> mp;      // lumped P1 mass (integral of each P1 basis function)
-    std::vector<HostLevel> levels;
+    std::vector<double> diagM, diagK;        // per P2 node
+    HostCSR Bs, Bts;                         // divergence over velocity unknowns (BC rows applied)
+    double schur_dt = -1.0, schur_nuc = -1.0;
+    std::vector<HostLevel> levels;           // pressure Schur-approximation hierarchy
 };
 
 mhd_status build_mesh(const mhd_mesh_desc* d, HostMesh& m, bool full);
+mhd_status schur_values(HostMesh& m, double dt, double nu_c);
 void mesh_counts(const HostMesh& m, mhd_mesh_info* info);
 
 // reference-element tables (host computed, uploaded to constant memory)

@@ -94,6 +94,7 @@ struct GmresWork {
     double* res = nullptr;        // J residual estimates
     double* partial = nullptr;    // reduction partials
     int64_t partial_len = 0;
+    int nblk_cap = 512;           // blocks of the column-reduction kernels for this J_max
     double* host_res = nullptr;   // pinned host copy (J)
     std::vector<void*> mg_x, mg_x2, mg_b, mg_r;   // per level (n_l x Jmax, sized for double)
     void** dptrs = nullptr;       // device array of the basis block pointers

@@ -139,7 +139,9 @@ bool invert_dense(std::vector<double>& a, int n) {
     return true;
 }
 
-// P1 stiffness of a grid level with fixed rows (pin / outflow) as identity rows.
+// Vertex numbering of one level of the nested P1 grids, and its fixed vertex
+// (the pinned pressure, when there is one).  The level operator itself is
+// filled by schur_values().
 void build_level(const mhd_mesh_desc* d, int level, HostLevel& L, std::vector<uint8_t>& fixed,
                  std::vector<int32_t>& vid) {
     Grid g = make_grid(d, level);
@@ -149,47 +151,118 @@ void build_level(const mhd_mesh_desc* d, int level, HostLevel& L, std::vector<ui
     int nv = 0;
     vid = vertex_ids(g, nv);
     L.n = nv;
-    std::vector<std::array<double, 2>> xy(nv);
-    for (int k = 0; k <= g.ny; ++k)
-        for (int i = 0; i <= g.nx; ++i) {
-            int id = vid[(size_t)k * (g.nx + 1) + i];
-            if (id >= 0) xy[id] = {g.x0 + i * g.h, g.y0 + k * g.h};
-        }
     fixed.assign(nv, 0);
-    double xmax = g.x0 + g.nx * g.h;
-    if (d->kind == MHD_MESH_STEP_CHANNEL && d->natural_outflow) {
-        for (int v = 0; v < nv; ++v)
-            if (std::fabs(xy[v][0] - xmax) < 1e-9 * (1 + xmax)) fixed[v] = 1;
-    } else {
+    if (!(d->kind == MHD_MESH_STEP_CHANNEL && d->natural_outflow))
         fixed[0] = 1;   // pinned pressure: first vertex in row-major order
-    }
-    std::vector<std::vector<std::pair<int32_t, double>>> rows(nv);
-    for (int k = 0; k < g.ny; ++k)
-        for (int i = 0; i < g.nx; ++i) {
-            if (!g.cell(i, k)) continue;
-            int v00 = vid[(size_t)k * (g.nx + 1) + i], v10 = vid[(size_t)k * (g.nx + 1) + i + 1];
-            int v11 = vid[(size_t)(k + 1) * (g.nx + 1) + i + 1], v01 = vid[(size_t)(k + 1) * (g.nx + 1) + i];
-            int tris[2][3] = {{v00, v10, v11}, {v00, v11, v01}};
-            for (auto& t : tris) {
-                double gl[3][2], area;
-                grad_bary(xy[t[0]].data(), xy[t[1]].data(), xy[t[2]].data(), gl, area);
-                for (int a = 0; a < 3; ++a) {
-                    if (fixed[t[a]]) continue;
-                    for (int b = 0; b < 3; ++b)
-                        rows[t[a]].push_back({t[b], area * (gl[a][0] * gl[b][0] + gl[a][1] * gl[b][1])});
+}
+
+// C = A diag(w) B (w empty: identity); the pattern is the symbolic product
+// (entries are kept even when their value is zero, so the pattern does not
+// depend on the values).
+HostCSR spgemm(const HostCSR& A, const std::vector<double>& w, const HostCSR& B) {
+    HostCSR C;
+    C.nrows = A.nrows;
+    C.ncols = B.ncols;
+    C.rowptr.assign(A.nrows + 1, 0);
+    std::vector<double> acc(B.ncols, 0.0);
+    std::vector<int32_t> mark(B.ncols, -1), cols;
+    for (int64_t r = 0; r < A.nrows; ++r) {
+        cols.clear();
+        for (int32_t p = A.rowptr[r]; p < A.rowptr[r + 1]; ++p) {
+            int32_t k = A.col[p];
+            double a = A.val[p] * (w.empty() ? 1.0 : w[k]);
+            for (int32_t q = B.rowptr[k]; q < B.rowptr[k + 1]; ++q) {
+                int32_t c = B.col[q];
+                if (mark[c] != (int32_t)r) {
+                    mark[c] = (int32_t)r;
+                    acc[c] = 0.0;
+                    cols.push_back(c);
                 }
+                acc[c] += a * B.val[q];
             }
         }
-    for (int v = 0; v < nv; ++v)
-        if (fixed[v]) rows[v] = {{v, 1.0}};
-    L.L = triplets_to_csr(nv, nv, rows);
-    L.dinv.assign(nv, 0.0);
-    for (int v = 0; v < nv; ++v)
-        for (int32_t p = L.L.rowptr[v]; p < L.L.rowptr[v + 1]; ++p)
-            if (L.L.col[p] == v) L.dinv[v] = 1.0 / L.L.val[p];
+        std::sort(cols.begin(), cols.end());
+        for (int32_t c : cols) {
+            C.col.push_back(c);
+            C.val.push_back(acc[c]);
+        }
+        C.rowptr[r + 1] = (int32_t)C.col.size();
+    }
+    return C;
+}
+
+// identity row and column for a fixed node (the row is replaced by its
+// diagonal entry; column entries of other rows are kept as explicit zeros)
+void fix_node(HostCSR& A, int32_t f) {
+    HostCSR B;
+    B.nrows = A.nrows;
+    B.ncols = A.ncols;
+    B.rowptr.assign(A.nrows + 1, 0);
+    for (int64_t r = 0; r < A.nrows; ++r) {
+        if (r == f) {
+            B.col.push_back(f);
+            B.val.push_back(1.0);
+        } else {
+            for (int32_t p = A.rowptr[r]; p < A.rowptr[r + 1]; ++p) {
+                B.col.push_back(A.col[p]);
+                B.val.push_back(A.col[p] == f ? 0.0 : A.val[p]);
+            }
+        }
+        B.rowptr[r + 1] = (int32_t)B.col.size();
+    }
+    A = std::move(B);
 }
 
 }  // namespace
+
+// Pressure Schur-complement approximation S_hat = B D^{-1} B^T with
+// D = diag(M)/dt + nu_c diag(K) (the diagonal of the velocity block without its
+// convection part, whose skew-symmetric form has a zero diagonal), and its
+// Galerkin multigrid hierarchy S_{l+1} = P_l^T S_l P_l over the nested P1
+// grids.  Values are recomputed when (dt, nu_c) change; patterns never do.
+mhd_status schur_values(HostMesh& m, double dt, double nu_c) {
+    const int nP2 = m.nP2;
+    std::vector<double> dinv_u(2 * (size_t)nP2, 0.0);
+    for (int i = 0; i < nP2; ++i) {
+        double d = m.diagM[i] / dt + nu_c * m.diagK[i];
+        dinv_u[2 * i] = dinv_u[2 * i + 1] = (d > 0) ? 1.0 / d : 0.0;
+    }
+    std::vector<HostLevel>& L = m.levels;
+    HostCSR S0 = spgemm(m.Bs, dinv_u, m.Bts);
+    if (m.pin >= 0) fix_node(S0, m.pin);
+    for (size_t l = 0; l < L.size(); ++l) {
+        HostCSR cur;
+        if (l == 0) {
+            cur = std::move(S0);
+        } else {
+            HostCSR T = spgemm(L[l - 1].L, {}, L[l - 1].P);
+            cur = spgemm(L[l - 1].R, {}, T);
+            if (m.pin >= 0) fix_node(cur, 0);
+        }
+        if (!L[l].L.col.empty() && (L[l].L.col.size() != cur.col.size())) {
+            set_error("schur hierarchy: pattern changed");
+            return MHD_EINVAL;
+        }
+        L[l].L = std::move(cur);
+        L[l].dinv.assign(L[l].n, 0.0);
+        for (int v = 0; v < L[l].n; ++v)
+            for (int32_t p = L[l].L.rowptr[v]; p < L[l].L.rowptr[v + 1]; ++p)
+                if (L[l].L.col[p] == v) L[l].dinv[v] = L[l].L.val[p] != 0.0 ? 1.0 / L[l].L.val[p] : 0.0;
+    }
+    HostLevel& Lc = L.back();
+    Lc.cinv.assign((size_t)Lc.n * Lc.n, 0.0);
+    for (int r = 0; r < Lc.n; ++r)
+        for (int32_t p = Lc.L.rowptr[r]; p < Lc.L.rowptr[r + 1]; ++p) Lc.cinv[(size_t)r * Lc.n + Lc.L.col[p]] = Lc.L.val[p];
+    if (!invert_dense(Lc.cinv, Lc.n)) {
+        // degenerate meshes (a single cell) give a singular approximation: fall
+        // back to its diagonal inverse, which still defines a preconditioner
+        Lc.cinv.assign((size_t)Lc.n * Lc.n, 0.0);
+        for (int r = 0; r < Lc.n; ++r) Lc.cinv[(size_t)r * Lc.n + r] = Lc.dinv[r];
+    }
+    m.schur_dt = dt;
+    m.schur_nuc = nu_c;
+    return MHD_OK;
+}
 
 // ---------------------------------------------------------------- reference tables
 void make_ref_tables(RefTables& t) {
@@ -493,15 +566,57 @@ mhd_status build_mesh(const mhd_mesh_desc* d, HostMesh& m, bool full) {
         F.P = triplets_to_csr(F.n, C.n, rows);
         F.R = transpose(F.P);
     }
-    HostLevel& Lc = m.levels.back();
-    Lc.cinv.assign((size_t)Lc.n * Lc.n, 0.0);
-    for (int r = 0; r < Lc.n; ++r)
-        for (int32_t p = Lc.L.rowptr[r]; p < Lc.L.rowptr[r + 1]; ++p) Lc.cinv[(size_t)r * Lc.n + Lc.L.col[p]] = Lc.L.val[p];
-    if (!invert_dense(Lc.cinv, Lc.n)) {
-        set_error("mhd_ens_mesh: singular coarsest pressure Laplacian");
-        return MHD_EINVAL;
+    // ---- host copies of the divergence operator and of diag(M), diag(K) (for the Schur approximation)
+    {
+        RefTables t;
+        make_ref_tables(t);
+        std::vector<double> eb((size_t)n_el * 36);
+        m.diagM.assign(nP2, 0.0);
+        m.diagK.assign(nP2, 0.0);
+        for (e = 0; e < n_el; ++e) {
+            const int32_t* tr = &m.tri[(size_t)e * 6];
+            const double* p0 = &m.xy[2 * tr[0]];
+            const double* p1 = &m.xy[2 * tr[1]];
+            const double* p2 = &m.xy[2 * tr[2]];
+            double a = p1[0] - p0[0], b = p2[0] - p0[0], c = p1[1] - p0[1], dd = p2[1] - p0[1];
+            double det = a * dd - b * c;
+            double Ji[2][2] = {{dd / det, -b / det}, {-c / det, a / det}};
+            double G[2][2];
+            for (int x = 0; x < 2; ++x)
+                for (int y = 0; y < 2; ++y) G[x][y] = Ji[x][0] * Ji[y][0] + Ji[x][1] * Ji[y][1];
+            for (int aa = 0; aa < 6; ++aa) {
+                m.diagM[tr[aa]] += det * t.Mhat[aa][aa];
+                double k = 0.0;
+                for (int x = 0; x < 2; ++x)
+                    for (int y = 0; y < 2; ++y) k += t.Khat[aa][aa][x][y] * G[x][y];
+                m.diagK[tr[aa]] += det * k;
+            }
+            for (int k = 0; k < 3; ++k)
+                for (int aa = 0; aa < 6; ++aa)
+                    for (int dir = 0; dir < 2; ++dir) {
+                        double v = 0.0;
+                        for (int x = 0; x < 2; ++x) v += t.Bhat[k][aa][x] * Ji[x][dir];
+                        eb[(size_t)e * 36 + (k * 6 + aa) * 2 + dir] = det * v;
+                    }
+        }
+        // scalar CSRs over velocity unknowns 2i+c: Bs (P1 x 2 nP2), Bts (2 nP2 x P1)
+        std::vector<std::vector<std::pair<int32_t, double>>> rb(nP1), rbt(2 * (size_t)nP2);
+        for (int k = 0; k < nP1; ++k) {
+            if (k == m.pin) continue;                    // pinned row of B is zero
+            for (int32_t p = m.B.rowptr[k]; p < m.B.rowptr[k + 1]; ++p) {
+                double v[2] = {0.0, 0.0};
+                for (int32_t q = m.gB_ptr[p]; q < m.gB_ptr[p + 1]; ++q)
+                    for (int dir = 0; dir < 2; ++dir) v[dir] += eb[(size_t)m.gB_idx[q] * 2 + dir];
+                for (int dir = 0; dir < 2; ++dir) {
+                    rb[k].push_back({2 * m.B.col[p] + dir, v[dir]});
+                    if (!m.dir[m.B.col[p]]) rbt[2 * (size_t)m.B.col[p] + dir].push_back({k, v[dir]});
+                }
+            }
+        }
+        m.Bs = triplets_to_csr(nP1, 2 * (int64_t)nP2, rb);
+        m.Bts = triplets_to_csr(2 * (int64_t)nP2, nP1, rbt);
     }
-    return MHD_OK;
+    return schur_values(m, 1.0, 0.0);
 }
 
 void mesh_counts(const HostMesh& m, mhd_mesh_info* info) {

@@ -29,7 +29,7 @@ namespace mhd {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kRedBlocks = 1024;   // blocks of the column-reduction kernels
+constexpr int kRedBlocks = 512;    // blocks of the column-reduction kernels
 
 __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t G) {
     int64_t q = G >> 3, r = G & 7, x = b & 7, s = b >> 3;
@@ -234,110 +234,217 @@ __global__ void __launch_bounds__(kBlock) k_dense(const T* __restrict__ C, const
     }
 }
 
-// z_p = -(1/dt) x_mg - nu_c r_p / m_p ; pinned row: z_p = r_p ; outflow-fixed rows: mass part only
+// z_p = -x_mg (x_mg ~ S_hat^{-1} r_p from the V-cycle); the pinned row is an
+// identity row of S, so there z_p = r_p
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_schur(const T* __restrict__ xmg, const T* __restrict__ rp,
-                                                  const double* __restrict__ mp_inv, const uint8_t* __restrict__ pfix,
-                                                  int pin, T* __restrict__ zp, int nP1, int J, int JP, T inv_dt,
-                                                  T nu_c) {
+__global__ void __launch_bounds__(kBlock) k_schur(const T* __restrict__ xmg, const T* __restrict__ rp, int pin,
+                                                  T* __restrict__ zp, int nP1, int J, int JP) {
     Lanes L = lanes(JP);
     const int64_t k = L.unit;
     if (k >= nP1) return;
-    const T mi = (T)mp_inv[k];
-    const bool fixed = pfix[k] != 0;
     for (int j = L.j0; j < J; j += JP) {
         const int64_t o = k * J + j;
-        T v;
-        if (k == pin)
-            v = rp[o];
-        else if (fixed)
-            v = -nu_c * mi * rp[o];
-        else
-            v = -inv_dt * xmg[o] - nu_c * mi * rp[o];
-        zp[o] = v;
+        zp[o] = (k == pin) ? rp[o] : -xmg[o];
     }
 }
 
 // ------------------------------------------------------------------ column reductions
-// 2-D mapping: threadIdx.x % CW = column lane, threadIdx.x / CW = row group.
-// partial[(blockIdx.x * nb + i) * J + j] = sum over this block's rows of V_i[r,j] * w[r,j]
-template <typename T, int NB>
-__global__ void __launch_bounds__(kBlock) k_dots(const T* const* __restrict__ V, int nb, const T* __restrict__ w,
+// Column (= member) reductions over the rows of (n x J) blocks.  Mapping: each
+// thread owns VEC consecutive members of one row (vector loads); CW threads
+// cover a row's members, RG = 256 / CW rows are processed side by side and the
+// grid strides over the rows.  Per-block partials are stored member-major,
+// partial[q * nblk + block], and summed by k_reduce in a fixed order, so the
+// results do not depend on scheduling.
+template <typename T, int VEC>
+struct VecT;
+template <>
+struct VecT<float, 4> {
+    using type = float4;
+};
+template <>
+struct VecT<float, 2> {
+    using type = float2;
+};
+template <>
+struct VecT<float, 1> {
+    using type = float;
+};
+template <>
+struct VecT<double, 2> {
+    using type = double2;
+};
+template <>
+struct VecT<double, 1> {
+    using type = double;
+};
+
+template <typename T, int VEC>
+__device__ __forceinline__ void vload(T (&v)[VEC], const T* p) {
+    using V = typename VecT<T, VEC>::type;
+    *reinterpret_cast<V*>(v) = *reinterpret_cast<const V*>(p);
+}
+template <typename T, int VEC>
+__device__ __forceinline__ void vstore(T* p, const T (&v)[VEC]) {
+    using V = typename VecT<T, VEC>::type;
+    *reinterpret_cast<V*>(p) = *reinterpret_cast<const V*>(v);
+}
+
+struct ColMap {
+    int tx, ty, RG, jb;
+    bool ok;
+};
+
+__device__ __forceinline__ ColMap colmap(int CW, int VEC, int J) {
+    ColMap c;
+    c.tx = threadIdx.x % CW;
+    c.ty = threadIdx.x / CW;
+    c.RG = kBlock / CW;
+    c.jb = (blockIdx.y * CW + c.tx) * VEC;
+    c.ok = (c.ty < c.RG) && (c.jb < J);
+    return c;
+}
+
+// block-level sum over the RG row groups of one value per thread; thread ty == 0
+// returns the column sum
+__device__ __forceinline__ double block_colsum(double v, const ColMap& c, double* red, int CW) {
+    red[threadIdx.x] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (c.ty == 0)
+        for (int g = 0; g < c.RG; ++g) s += red[g * CW + c.tx];
+    __syncthreads();
+    return s;
+}
+
+// partial[((c0 + i) * J + j) * nblk + block] = sum over rows of V_i[r, j] * w[r, j], i < nb
+template <typename T, int VEC, int NB>
+__global__ void __launch_bounds__(kBlock) k_dots(const T* const* __restrict__ V, int c0, int nb, const T* __restrict__ w,
                                                  int64_t n, int J, int CW, double* __restrict__ partial) {
     __shared__ double red[kBlock];
-    const int tx = threadIdx.x % CW, ty = threadIdx.x / CW, RG = kBlock / CW;
-    const int j = blockIdx.y * CW + tx;
-    double acc[NB];
+    const ColMap c = colmap(CW, VEC, J);
+    double acc[NB][VEC];
 #pragma unroll
-    for (int i = 0; i < NB; ++i) acc[i] = 0.0;
-    if (j < J) {
-        for (int64_t r = (int64_t)blockIdx.x * RG + ty; r < n; r += (int64_t)gridDim.x * RG) {
-            const double wv = (double)w[r * J + j];
+    for (int i = 0; i < NB; ++i)
+#pragma unroll
+        for (int u = 0; u < VEC; ++u) acc[i][u] = 0.0;
+    if (c.ok) {
+        const T* vp[NB];
+#pragma unroll
+        for (int i = 0; i < NB; ++i) vp[i] = (i < nb) ? V[c0 + i] : nullptr;
+        for (int64_t r = (int64_t)blockIdx.x * c.RG + c.ty; r < n; r += (int64_t)gridDim.x * c.RG) {
+            T wv[VEC];
+            vload<T, VEC>(wv, w + r * J + c.jb);
 #pragma unroll
             for (int i = 0; i < NB; ++i)
-                if (i < nb) acc[i] += (double)V[i][r * J + j] * wv;
+                if (i < nb) {
+                    T vv[VEC];
+                    vload<T, VEC>(vv, vp[i] + r * J + c.jb);
+#pragma unroll
+                    for (int u = 0; u < VEC; ++u) acc[i][u] += (double)vv[u] * (double)wv[u];
+                }
         }
     }
-    for (int i = 0; i < nb; ++i) {
-        red[threadIdx.x] = acc[i];
-        __syncthreads();
-        if (ty == 0) {
-            double s = 0.0;
-            for (int g = 0; g < RG; ++g) s += red[g * CW + tx];
-            if (j < J) partial[((int64_t)blockIdx.x * nb + i) * J + j] = s;
+    const int64_t nblk = gridDim.x;
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        if (i < nb) {
+#pragma unroll
+            for (int u = 0; u < VEC; ++u) {
+                double sv = block_colsum(acc[i][u], c, red, CW);
+                if (c.ty == 0 && c.ok) partial[((int64_t)(c0 + i) * J + c.jb + u) * nblk + blockIdx.x] = sv;
+            }
         }
-        __syncthreads();
     }
 }
 
-// w -= sum_i h[i*J + j] V_i ; partial norms of the result
-template <typename T>
+// w -= sum_{i<nb} h[i*J + j] V_i ; partial[j * nblk + block] = sum over rows of w^2
+template <typename T, int VEC>
 __global__ void __launch_bounds__(kBlock) k_update(const T* const* __restrict__ V, int nb, const double* __restrict__ h,
                                                    T* __restrict__ w, int64_t n, int J, int CW,
                                                    double* __restrict__ partial) {
     __shared__ double red[kBlock];
-    const int tx = threadIdx.x % CW, ty = threadIdx.x / CW, RG = kBlock / CW;
-    const int j = blockIdx.y * CW + tx;
-    double acc = 0.0;
-    if (j < J) {
-        for (int64_t r = (int64_t)blockIdx.x * RG + ty; r < n; r += (int64_t)gridDim.x * RG) {
-            T v = w[r * J + j];
-            for (int i = 0; i < nb; ++i) v -= (T)h[i * J + j] * V[i][r * J + j];
-            w[r * J + j] = v;
-            acc += (double)v * (double)v;
+    const ColMap c = colmap(CW, VEC, J);
+    double acc[VEC];
+#pragma unroll
+    for (int u = 0; u < VEC; ++u) acc[u] = 0.0;
+    if (c.ok) {
+        for (int64_t r = (int64_t)blockIdx.x * c.RG + c.ty; r < n; r += (int64_t)gridDim.x * c.RG) {
+            T wv[VEC];
+            vload<T, VEC>(wv, w + r * J + c.jb);
+            for (int i = 0; i < nb; ++i) {
+                T vv[VEC];
+                vload<T, VEC>(vv, V[i] + r * J + c.jb);
+#pragma unroll
+                for (int u = 0; u < VEC; ++u) wv[u] -= (T)h[(int64_t)i * J + c.jb + u] * vv[u];
+            }
+            vstore<T, VEC>(w + r * J + c.jb, wv);
+#pragma unroll
+            for (int u = 0; u < VEC; ++u) acc[u] += (double)wv[u] * (double)wv[u];
         }
     }
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    if (ty == 0) {
-        double s = 0.0;
-        for (int g = 0; g < RG; ++g) s += red[g * CW + tx];
-        if (j < J) partial[(int64_t)blockIdx.x * J + j] = s;
+    const int64_t nblk = gridDim.x;
+#pragma unroll
+    for (int u = 0; u < VEC; ++u) {
+        double sv = block_colsum(acc[u], c, red, CW);
+        if (c.ty == 0 && c.ok) partial[((int64_t)c.jb + u) * nblk + blockIdx.x] = sv;
     }
 }
 
-// u = sum_i y[i*J + j] V_i
-template <typename T>
+// partial[j * nblk + block] = sum over rows of a[r, j]^2 (FP64 blocks)
+template <int VEC>
+__global__ void __launch_bounds__(kBlock) k_colsq(const double* __restrict__ a, int64_t n, int J, int CW,
+                                                  double* __restrict__ partial) {
+    __shared__ double red[kBlock];
+    const ColMap c = colmap(CW, VEC, J);
+    double acc[VEC];
+#pragma unroll
+    for (int u = 0; u < VEC; ++u) acc[u] = 0.0;
+    if (c.ok)
+        for (int64_t r = (int64_t)blockIdx.x * c.RG + c.ty; r < n; r += (int64_t)gridDim.x * c.RG) {
+            double v[VEC];
+            vload<double, VEC>(v, a + r * J + c.jb);
+#pragma unroll
+            for (int u = 0; u < VEC; ++u) acc[u] += v[u] * v[u];
+        }
+    const int64_t nblk = gridDim.x;
+#pragma unroll
+    for (int u = 0; u < VEC; ++u) {
+        double sv = block_colsum(acc[u], c, red, CW);
+        if (c.ty == 0 && c.ok) partial[((int64_t)c.jb + u) * nblk + blockIdx.x] = sv;
+    }
+}
+
+// u = sum_{i<nb} y[i*J + j] V_i
+template <typename T, int VEC>
 __global__ void __launch_bounds__(kBlock) k_combine(const T* const* __restrict__ V, int nb, const double* __restrict__ yv,
                                                     T* __restrict__ u, int64_t n, int J, int CW) {
-    const int tx = threadIdx.x % CW, ty = threadIdx.x / CW, RG = kBlock / CW;
-    const int j = blockIdx.y * CW + tx;
-    if (j >= J) return;
-    for (int64_t r = (int64_t)blockIdx.x * RG + ty; r < n; r += (int64_t)gridDim.x * RG) {
-        T s = 0;
-        for (int i = 0; i < nb; ++i) s += (T)yv[i * J + j] * V[i][r * J + j];
-        u[r * J + j] = s;
+    const ColMap c = colmap(CW, VEC, J);
+    if (!c.ok) return;
+    for (int64_t r = (int64_t)blockIdx.x * c.RG + c.ty; r < n; r += (int64_t)gridDim.x * c.RG) {
+        T s[VEC];
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) s[q] = 0;
+        for (int i = 0; i < nb; ++i) {
+            T vv[VEC];
+            vload<T, VEC>(vv, V[i] + r * J + c.jb);
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) s[q] += (T)yv[(int64_t)i * J + c.jb + q] * vv[q];
+        }
+        vstore<T, VEC>(u + r * J + c.jb, s);
     }
 }
 
-// fixed-order sum of block partials: out[q] = sum_b partial[b * width + q] (sqrt if requested)
-__global__ void k_reduce(const double* __restrict__ partial, int nblk, int64_t width, double* __restrict__ out,
-                         int take_sqrt) {
-    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= width) return;
+// out[q] = sum_b partial[q * nblk + b], one wavefront per output, fixed order
+// (strided lane sums, then a butterfly); optional square root
+__global__ void __launch_bounds__(kBlock) k_reduce(const double* __restrict__ partial, int nblk, int64_t width,
+                                                   double* __restrict__ out, int take_sqrt) {
+    const int lane = threadIdx.x & 63;
+    const int64_t q = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += partial[(int64_t)b * width + q];
-    out[q] = take_sqrt ? sqrt(s) : s;
+    if (q < width)
+        for (int b = lane; b < nblk; b += 64) s += partial[q * nblk + b];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (q < width && lane == 0) out[q] = take_sqrt ? sqrt(s) : s;
 }
 
 // elementwise helpers
@@ -421,22 +528,17 @@ __global__ void k_lsq(const double* __restrict__ H, const double* __restrict__ g
     }
 }
 
-// weighted column sums for the pressure mean: partial[b*J + j] = sum_k w_k p[k,j]
+// weighted column sums for the pressure mean: partial[j * nblk + b] = sum_k w_k p[k,j]
 __global__ void __launch_bounds__(kBlock) k_wsum(const double* __restrict__ p, const double* __restrict__ w, int64_t n,
                                                  int J, int CW, double* __restrict__ partial) {
     __shared__ double red[kBlock];
-    const int tx = threadIdx.x % CW, ty = threadIdx.x / CW, RG = kBlock / CW;
-    const int j = blockIdx.y * CW + tx;
+    const ColMap c = colmap(CW, 1, J);
     double acc = 0.0;
-    if (j < J)
-        for (int64_t r = (int64_t)blockIdx.x * RG + ty; r < n; r += (int64_t)gridDim.x * RG) acc += w[r] * p[r * J + j];
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    if (ty == 0) {
-        double s = 0.0;
-        for (int g = 0; g < RG; ++g) s += red[g * CW + tx];
-        if (j < J) partial[(int64_t)blockIdx.x * J + j] = s;
-    }
+    if (c.ok)
+        for (int64_t r = (int64_t)blockIdx.x * c.RG + c.ty; r < n; r += (int64_t)gridDim.x * c.RG)
+            acc += w[r] * p[r * J + c.jb];
+    double sv = block_colsum(acc, c, red, CW);
+    if (c.ty == 0 && c.ok) partial[(int64_t)c.jb * gridDim.x + blockIdx.x] = sv;
 }
 
 __global__ void __launch_bounds__(kBlock) k_sub_mean(double* __restrict__ p, const double* __restrict__ sums,
@@ -445,26 +547,46 @@ __global__ void __launch_bounds__(kBlock) k_sub_mean(double* __restrict__ p, con
     for (; idx < n * J; idx += (int64_t)gridDim.x * kBlock) p[idx] -= sums[idx % J] * inv_area;
 }
 
+__global__ void k_add_vec(double* __restrict__ a, const double* __restrict__ b, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] += b[i];
+}
+
 inline unsigned ew_grid(int64_t tot) {
     int64_t g = (tot + kBlock - 1) / kBlock;
     return (unsigned)std::min<int64_t>(std::max<int64_t>(g, 1), 8192);
 }
 
+// launch shape of the column-reduction kernels for (n x J) blocks with VEC members per thread
 struct RedShape {
-    int CW;
+    int CW, VEC, nblk;
     dim3 grid;
-    int nblk;
 };
 
-inline RedShape red_shape(int64_t n, int J) {
+inline RedShape red_shape(int64_t n, int J, int vec_max) {
     RedShape s;
-    s.CW = pick_jp(J);
+    s.VEC = 1;
+    for (int v = vec_max; v > 1; v >>= 1)
+        if (J % v == 0) {
+            s.VEC = v;
+            break;
+        }
+    int cols = J / s.VEC;
+    int tiles = 1;
+    if (cols <= kBlock) {
+        s.CW = cols;
+    } else {
+        s.CW = 64;
+        tiles = (cols + 63) / 64;
+    }
     int RG = kBlock / s.CW;
     int64_t need = (n + RG - 1) / RG;
     s.nblk = (int)std::min<int64_t>(kRedBlocks, std::max<int64_t>(need, 1));
-    s.grid = dim3(s.nblk, (J + s.CW - 1) / s.CW);
+    s.grid = dim3(s.nblk, tiles);
     return s;
 }
+
+inline unsigned reduce_grid(int64_t width) { return (unsigned)((width + (kBlock / 64) - 1) / (kBlock / 64)); }
 
 #define LAUNCH_CHECK()                                     \
     do {                                                   \
@@ -474,34 +596,6 @@ inline RedShape red_shape(int64_t n, int J) {
             return MHD_EHIP;                               \
         }                                                  \
     } while (0)
-
-
-// column sums of squares of one block: partial[b*J + j]
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_colsq(const T* __restrict__ a, int64_t n, int J, int CW,
-                                                  double* __restrict__ partial) {
-    __shared__ double red[kBlock];
-    const int tx = threadIdx.x % CW, ty = threadIdx.x / CW, RG = kBlock / CW;
-    const int j = blockIdx.y * CW + tx;
-    double acc = 0.0;
-    if (j < J)
-        for (int64_t r = (int64_t)blockIdx.x * RG + ty; r < n; r += (int64_t)gridDim.x * RG) {
-            const double v = (double)a[r * J + j];
-            acc += v * v;
-        }
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    if (ty == 0) {
-        double s = 0.0;
-        for (int g = 0; g < RG; ++g) s += red[g * CW + tx];
-        if (j < J) partial[(int64_t)blockIdx.x * J + j] = s;
-    }
-}
-
-__global__ void k_add_vec(double* __restrict__ a, const double* __restrict__ b, int64_t n) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) a[i] += b[i];
-}
 
 // ------------------------------------------------------------------ kernel timer
 struct KTimer {
@@ -532,6 +626,24 @@ void timer_mark(hipStream_t st, bool before) {
     if (!g_timer.on) return;
     if (before && g_timer.used + 2 > g_timer.pool.size()) (void)timer_fold();
     if (g_timer.used < g_timer.pool.size()) (void)hipEventRecord(g_timer.pool[g_timer.used++], st);
+}
+
+// runtime VEC -> compile-time dispatch (4 members per thread for FP32, 2 for FP64)
+template <typename T, typename F>
+mhd_status with_vec(int vec, F f) {
+    if constexpr (sizeof(T) == 4) {
+        if (vec == 4) return f(std::integral_constant<int, 4>{});
+    }
+    if (vec == 2) return f(std::integral_constant<int, 2>{});
+    return f(std::integral_constant<int, 1>{});
+}
+
+inline RedShape cap_blocks(RedShape rs, int cap) {
+    if (rs.nblk > cap) {
+        rs.nblk = cap;
+        rs.grid.x = cap;
+    }
+    return rs;
 }
 
 // ------------------------------------------------------------------ host-side operators
@@ -610,10 +722,8 @@ struct Ops {
         mhd_status rc;
         T* xmg = nullptr;
         if ((rc = vcycle(0, vp, &xmg))) return rc;
-        const T inv_dt = (T)(1.0 / S.coeffs.dt);
-        const T nu_c = (T)(0.5 * (S.coeffs.nu_bar + S.coeffs.num_bar));
-        hipLaunchKernelGGL((k_schur<T>), dim3(grid_for(m.nP1, JP)), dim3(kBlock), 0, st, xmg, vp, m.mp_inv, m.pfix,
-                           m.pin, zp, m.nP1, J, JP, inv_dt, nu_c);
+        hipLaunchKernelGGL((k_schur<T>), dim3(grid_for(m.nP1, JP)), dim3(kBlock), 0, st, xmg, vp, m.pin, zp, m.nP1,
+                           J, JP);
         LAUNCH_CHECK();
         const T omega = (T)0.7;
         T* t = (T*)S.gw.tbuf;
@@ -640,19 +750,27 @@ struct Ops {
 
     mhd_status colnorm(const double* a, double* out) {
         int64_t n = S.mesh->n;
-        RedShape rs = red_shape(n, J);
-        hipLaunchKernelGGL((k_colsq<double>), rs.grid, dim3(kBlock), 0, st, a, n, J, rs.CW, S.gw.partial);
-        LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_reduce, dim3((J + 255) / 256), dim3(256), 0, st, S.gw.partial, rs.nblk, (int64_t)J, out,
+        RedShape rs = red_shape(n, J, ((uintptr_t)a % 16 == 0) ? 2 : 1);
+        rs = cap_blocks(rs, S.gw.nblk_cap);
+        mhd_status rc = with_vec<double>(rs.VEC, [&](auto V) -> mhd_status {
+            hipLaunchKernelGGL((k_colsq<decltype(V)::value>), rs.grid, dim3(kBlock), 0, st, a, n, J, rs.CW,
+                               S.gw.partial);
+            LAUNCH_CHECK();
+            return MHD_OK;
+        });
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_reduce, dim3(reduce_grid(J)), dim3(kBlock), 0, st, S.gw.partial, rs.nblk, (int64_t)J, out,
                            1);
         LAUNCH_CHECK();
         return MHD_OK;
     }
 };
 
+inline size_t slot_bytes(int64_t nrows, int Jmax) { return (((size_t)nrows * Jmax * sizeof(double)) + 255) & ~(size_t)255; }
+
 template <typename T>
 inline T* basis_ptr(DevShared& S, int i) {
-    return (T*)((char*)S.gw.basis + (size_t)i * S.gw.nrows * S.Jmax * sizeof(double));
+    return (T*)((char*)S.gw.basis + (size_t)i * slot_bytes(S.gw.nrows, S.Jmax));
 }
 
 mhd_status sync_copy(double* host, const double* dev, int J, hipStream_t st) {
@@ -675,7 +793,8 @@ mhd_status gmres_solve(DevShared& S, const double* b, double* x, int J, const mh
     const int check = std::max(1, o.check_every);
     const int sweeps = std::max(1, o.jacobi_sweeps);
     Ops<T> ops(S, J, st);
-    RedShape rs = red_shape(n, J);
+    RedShape rs = cap_blocks(red_shape(n, J, 16 / (int)sizeof(T)), G.nblk_cap);
+    const int passes = o.cgs_passes > 0 ? o.cgs_passes : (sizeof(T) == 4 ? 1 : 2);
     const T* const* Vd = (const T* const*)G.dptrs;
     double* hres = G.host_res;                 // pinned, 3 J doubles: residuals, beta, bnorm
     double* hbeta = G.host_res + J;
@@ -727,27 +846,38 @@ mhd_status gmres_solve(DevShared& S, const double* b, double* x, int J, const mh
             T* w = basis_ptr<T>(S, k + 1);
             if ((rc = ops.precond(vk, z, sweeps))) return rc;
             if ((rc = ops.saddle(z, w))) return rc;
-            // classical Gram-Schmidt with one re-orthogonalisation pass
-            for (int pass = 0; pass < 2; ++pass) {
+            // classical Gram-Schmidt (optionally with a re-orthogonalisation pass)
+            for (int pass = 0; pass < passes; ++pass) {
                 double* hdst = pass ? hcol2 : G.hcol;
-                for (int c0 = 0; c0 <= k; c0 += 16) {
-                    int nb = std::min(16, k + 1 - c0);
-                    hipLaunchKernelGGL((k_dots<T, 16>), rs.grid, dim3(kBlock), 0, st, Vd + c0, nb, (const T*)w, n, J,
-                                       rs.CW, G.partial);
-                    LAUNCH_CHECK();
-                    hipLaunchKernelGGL(k_reduce, dim3((nb * J + 255) / 256), dim3(256), 0, st, G.partial, rs.nblk,
-                                       (int64_t)nb * J, hdst + (int64_t)c0 * J, 0);
-                    LAUNCH_CHECK();
+                for (int c0 = 0; c0 <= k; c0 += 8) {
+                    int nb = std::min(8, k + 1 - c0);
+                    rc = with_vec<T>(rs.VEC, [&](auto V) -> mhd_status {
+                        hipLaunchKernelGGL((k_dots<T, decltype(V)::value, 8>), rs.grid, dim3(kBlock), 0, st, Vd, c0, nb,
+                                           (const T*)w, n, J, rs.CW, G.partial);
+                        LAUNCH_CHECK();
+                        return MHD_OK;
+                    });
+                    if (rc) return rc;
                 }
-                hipLaunchKernelGGL((k_update<T>), rs.grid, dim3(kBlock), 0, st, Vd, k + 1, (const double*)hdst, w, n, J,
-                                   rs.CW, G.partial);
+                hipLaunchKernelGGL(k_reduce, dim3(reduce_grid((int64_t)(k + 1) * J)), dim3(kBlock), 0, st, G.partial,
+                                   rs.nblk, (int64_t)(k + 1) * J, hdst, 0);
+                LAUNCH_CHECK();
+                rc = with_vec<T>(rs.VEC, [&](auto V) -> mhd_status {
+                    hipLaunchKernelGGL((k_update<T, decltype(V)::value>), rs.grid, dim3(kBlock), 0, st, Vd, k + 1,
+                                       (const double*)hdst, w, n, J, rs.CW, G.partial);
+                    LAUNCH_CHECK();
+                    return MHD_OK;
+                });
+                if (rc) return rc;
+            }
+            hipLaunchKernelGGL(k_reduce, dim3(reduce_grid(J)), dim3(kBlock), 0, st, G.partial, rs.nblk, (int64_t)J, hn,
+                               1);
+            LAUNCH_CHECK();
+            if (passes > 1) {
+                hipLaunchKernelGGL(k_add_vec, dim3(((k + 1) * J + 255) / 256), dim3(256), 0, st, G.hcol,
+                                   (const double*)hcol2, (int64_t)(k + 1) * J);
                 LAUNCH_CHECK();
             }
-            hipLaunchKernelGGL(k_reduce, dim3((J + 255) / 256), dim3(256), 0, st, G.partial, rs.nblk, (int64_t)J, hn, 1);
-            LAUNCH_CHECK();
-            hipLaunchKernelGGL(k_add_vec, dim3(((k + 1) * J + 255) / 256), dim3(256), 0, st, G.hcol,
-                               (const double*)hcol2, (int64_t)(k + 1) * J);
-            LAUNCH_CHECK();
             hipLaunchKernelGGL(k_givens, dim3((J + 63) / 64), dim3(64), 0, st, G.H, G.cs, G.sn, G.g, G.hcol, hn, G.res,
                                k, mres, J);
             LAUNCH_CHECK();
@@ -770,8 +900,13 @@ mhd_status gmres_solve(DevShared& S, const double* b, double* x, int J, const mh
         hipLaunchKernelGGL(k_lsq, dim3((J + 63) / 64), dim3(64), 0, st, G.H, G.g, G.y, kd, mres, J);
         LAUNCH_CHECK();
         T* u = (T*)G.wbuf;
-        hipLaunchKernelGGL((k_combine<T>), rs.grid, dim3(kBlock), 0, st, Vd, kd, (const double*)G.y, u, n, J, rs.CW);
-        LAUNCH_CHECK();
+        rc = with_vec<T>(rs.VEC, [&](auto V) -> mhd_status {
+            hipLaunchKernelGGL((k_combine<T, decltype(V)::value>), rs.grid, dim3(kBlock), 0, st, Vd, kd,
+                               (const double*)G.y, u, n, J, rs.CW);
+            LAUNCH_CHECK();
+            return MHD_OK;
+        });
+        if (rc) return rc;
         if ((rc = ops.precond(u, (T*)G.zbuf, sweeps))) return rc;
         hipLaunchKernelGGL((k_add_to64<T>), dim3(ew_grid(n * J)), dim3(kBlock), 0, st, x, (const T*)G.zbuf, n * J);
         LAUNCH_CHECK();
@@ -794,7 +929,7 @@ mhd_status alloc_gmres(DevShared& S, int restart) {
     G.restart = restart;
     G.nrows = m.n;
     G.Jmax = S.Jmax;
-    const size_t blk = (size_t)m.n * S.Jmax * sizeof(double);
+    const size_t blk = slot_bytes(m.n, S.Jmax);
     auto A = [&](void** p, size_t bytes) -> mhd_status {
         hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 256));
         if (e != hipSuccess) {
@@ -821,7 +956,8 @@ mhd_status alloc_gmres(DevShared& S, int restart) {
     if ((rc = A((void**)&G.bnorm, J8))) return rc;
     if ((rc = A((void**)&G.hcol, J8 * 2 * (kMaxRestart + 1)))) return rc;
     if ((rc = A((void**)&G.res, J8 * 2))) return rc;
-    G.partial_len = (int64_t)kRedBlocks * 16 * S.Jmax;
+    G.nblk_cap = std::min(kRedBlocks, std::max(64, 524288 / S.Jmax));
+    G.partial_len = (int64_t)G.nblk_cap * (restart + 2) * S.Jmax + 1024;
     if ((rc = A((void**)&G.partial, sizeof(double) * G.partial_len))) return rc;
     if ((rc = A((void**)&G.dptrs, sizeof(void*) * (kMaxRestart + 2)))) return rc;
     std::vector<void*> ptrs(restart + 1);
@@ -909,13 +1045,13 @@ mhd_status timer_read(double* ms, int64_t* launches, double* nJ32, double* nJ64)
 }
 
 hipError_t launch_pressure_zero_mean(const DevMesh& m, double* p, int J, double* partial, hipStream_t st) {
-    RedShape rs = red_shape(m.nP1, J);
+    RedShape rs = cap_blocks(red_shape(m.nP1, J, 1), std::min(kRedBlocks, std::max(64, 524288 / J)));
     hipLaunchKernelGGL(k_wsum, rs.grid, dim3(kBlock), 0, st, (const double*)p, (const double*)m.mp, (int64_t)m.nP1, J,
                        rs.CW, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     double* sums = partial + (int64_t)rs.nblk * J;
-    hipLaunchKernelGGL(k_reduce, dim3((J + 255) / 256), dim3(256), 0, st, (const double*)partial, rs.nblk, (int64_t)J,
+    hipLaunchKernelGGL(k_reduce, dim3(reduce_grid(J)), dim3(kBlock), 0, st, (const double*)partial, rs.nblk, (int64_t)J,
                        sums, 0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     double area = 0.0;
