@@ -528,7 +528,7 @@ mhd_status build_mesh(const mhd_mesh_desc* d, HostMesh& m, bool full) {
             can_halve = (cur.nx % 2 == 0) && cur.nx >= 4;
         else
             can_halve = ((d->nx >> level) % 2 == 0);
-        if (cur.n <= 400 || !can_halve) break;
+        if (cur.n <= 100 || !can_halve) break;
         ++level;
     }
     m.pfix = fixed[0];

@@ -49,6 +49,30 @@ __device__ __forceinline__ Lanes lanes(int JP) {
     L.j0 = lane % JP;
     int64_t blk = xcd_block(blockIdx.x, gridDim.x);
     L.unit = (blk * (kBlock / 64) + wave) * rpw + lane / JP;
+    // one unit per wavefront: make the row index provably uniform so that CSR
+    // indices and values are fetched with scalar loads
+    if (JP == 64) L.unit = __builtin_amdgcn_readfirstlane((int)L.unit);
+    return L;
+}
+
+// Fast-path mapping for (n x J) blocks with J a multiple of JT = 32 VEC: one
+// wavefront per P2 node and member tile; lane l covers component c = l / 32
+// and members jt*JT + (l % 32)*VEC ... + VEC-1, so the node's 2 JT values of
+// the tile are read with one VEC-wide load per lane.
+struct NodeLanes {
+    int c, j;
+    int unit;
+};
+
+template <int VEC>
+__device__ __forceinline__ NodeLanes node_lanes() {
+    NodeLanes L;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    L.c = lane >> 5;
+    L.j = blockIdx.y * (32 * VEC) + (lane & 31) * VEC;
+    int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    L.unit = __builtin_amdgcn_readfirstlane((int)(blk * (kBlock / 64) + wave));
     return L;
 }
 
@@ -143,6 +167,145 @@ __global__ void __launch_bounds__(kBlock) k_saddle(const int32_t* __restrict__ A
     }
 }
 
+template <typename T, int VEC>
+struct VecT;
+
+template <typename T, int VEC>
+__device__ __forceinline__ void vload(T (&v)[VEC], const T* p);
+template <typename T, int VEC>
+__device__ __forceinline__ void vstore(T* p, const T (&v)[VEC]);
+
+// Fast saddle-point SpMM (see NodeLanes): y = S x (MODE 0) or y = b - S x (MODE 1)
+template <typename T, int VEC, int MODE>
+__global__ void __launch_bounds__(kBlock) k_saddle_v(const int32_t* __restrict__ Arp, const int32_t* __restrict__ Acol,
+                                                     const T* __restrict__ Aval, const int32_t* __restrict__ Btrp,
+                                                     const int32_t* __restrict__ Btcol, const T* __restrict__ Btval,
+                                                     const int32_t* __restrict__ Brp, const int32_t* __restrict__ Bcol,
+                                                     const T* __restrict__ Bval, const T* __restrict__ dp,
+                                                     const T* __restrict__ x, const T* __restrict__ bvec,
+                                                     T* __restrict__ y, int nP2, int nP1, int J) {
+    const NodeLanes L = node_lanes<VEC>();
+    const int u = L.unit;
+    if (u >= nP2 + nP1) return;
+    const T* xp = x + 2 * (int64_t)nP2 * J;
+    T acc[VEC];
+#pragma unroll
+    for (int q = 0; q < VEC; ++q) acc[q] = 0;
+    if (u < nP2) {
+        const int32_t a0 = Arp[u], a1 = Arp[u + 1], b0 = Btrp[u], b1 = Btrp[u + 1];
+        const T* xc = x + (int64_t)L.c * J + L.j;
+#pragma unroll 4
+        for (int32_t p = a0; p < a1; ++p) {
+            const int64_t k = Acol[p];
+            const T a = Aval[p];
+            T v[VEC];
+            vload<T, VEC>(v, xc + 2 * k * J);
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) acc[q] += a * v[q];
+        }
+        for (int32_t p = b0; p < b1; ++p) {
+            const int64_t m = Btcol[p];
+            const T bt = L.c ? Btval[2 * p + 1] : Btval[2 * p];
+            T v[VEC];
+            vload<T, VEC>(v, xp + m * J + L.j);
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) acc[q] += bt * v[q];
+        }
+        const int64_t o = (2 * (int64_t)u + L.c) * J + L.j;
+        if (MODE == 1) {
+            T bv[VEC];
+            vload<T, VEC>(bv, bvec + o);
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) acc[q] = bv[q] - acc[q];
+        }
+        vstore<T, VEC>(y + o, acc);
+    } else {
+        const int k = u - nP2;
+        const int32_t q0 = Brp[k], q1 = Brp[k + 1];
+        const T* xc = x + (int64_t)L.c * J + L.j;
+#pragma unroll 4
+        for (int32_t q = q0; q < q1; ++q) {
+            const int64_t i = Bcol[q];
+            const T bb = L.c ? Bval[2 * q + 1] : Bval[2 * q];
+            T v[VEC];
+            vload<T, VEC>(v, xc + 2 * i * J);
+#pragma unroll
+            for (int r = 0; r < VEC; ++r) acc[r] += bb * v[r];
+        }
+        // add the two velocity components' contributions (lanes l and l + 32)
+#pragma unroll
+        for (int r = 0; r < VEC; ++r) acc[r] += __shfl_xor(acc[r], 32, 64);
+        if (L.c == 0) {
+            const T d = dp[k];
+            const int64_t o = (2 * (int64_t)nP2 + k) * J + L.j;
+            T v[VEC];
+            vload<T, VEC>(v, xp + (int64_t)k * J + L.j);
+#pragma unroll
+            for (int r = 0; r < VEC; ++r) acc[r] += d * v[r];
+            if (MODE == 1) {
+                T bv[VEC];
+                vload<T, VEC>(bv, bvec + o);
+#pragma unroll
+                for (int r = 0; r < VEC; ++r) acc[r] = bv[r] - acc[r];
+            }
+            vstore<T, VEC>(y + o, acc);
+        }
+    }
+}
+
+// Fast velocity-block Jacobi sweeps (see NodeLanes)
+// FIRST: t = r_u - B^T z_p ; z = w D^{-1} t
+// else:  zo = z + w D^{-1} (t - A z)
+template <typename T, int VEC, bool FIRST>
+__global__ void __launch_bounds__(kBlock) k_velo_v(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                   const T* __restrict__ val, const T* __restrict__ dinvA,
+                                                   const T* __restrict__ in, const T* __restrict__ zp,
+                                                   T* __restrict__ t, const T* __restrict__ z, T* __restrict__ zo,
+                                                   int nP2, int J, T omega) {
+    const NodeLanes L = node_lanes<VEC>();
+    const int i = L.unit;
+    if (i >= nP2) return;
+    const int32_t p0 = rp[i], p1 = rp[i + 1];
+    const T dw = omega * dinvA[i];
+    const int64_t o = (2 * (int64_t)i + L.c) * J + L.j;
+    T acc[VEC];
+    if (FIRST) {
+        vload<T, VEC>(acc, in + o);                       // r_u
+#pragma unroll 4
+        for (int32_t p = p0; p < p1; ++p) {
+            const int64_t m = col[p];
+            const T bt = L.c ? val[2 * p + 1] : val[2 * p];
+            T v[VEC];
+            vload<T, VEC>(v, zp + m * J + L.j);
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) acc[q] -= bt * v[q];
+        }
+        vstore<T, VEC>(t + o, acc);
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) acc[q] *= dw;
+        vstore<T, VEC>(zo + o, acc);
+    } else {
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) acc[q] = 0;
+        const T* zc = z + (int64_t)L.c * J + L.j;
+#pragma unroll 4
+        for (int32_t p = p0; p < p1; ++p) {
+            const int64_t k = col[p];
+            const T a = val[p];
+            T v[VEC];
+            vload<T, VEC>(v, zc + 2 * k * J);
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) acc[q] += a * v[q];
+        }
+        T tv[VEC], zv[VEC];
+        vload<T, VEC>(tv, t + o);
+        vload<T, VEC>(zv, z + o);
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) acc[q] = zv[q] + dw * (tv[q] - acc[q]);
+        vstore<T, VEC>(zo + o, acc);
+    }
+}
+
 // ------------------------------------------------------------------ velocity block Jacobi
 // first sweep: t = r_u - B^T z_p ; z = w D^{-1} t
 template <typename T>
@@ -220,18 +383,21 @@ __global__ void __launch_bounds__(kBlock) k_csr(const int32_t* __restrict__ rp, 
     }
 }
 
-// x = Cinv b on the coarsest level (dense, n <= a few hundred)
+// x = Cinv b on the coarsest level (dense, n <= a few hundred): one block per
+// row and member tile; the 4 wavefronts split the columns, fixed-order sum in LDS
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_dense(const T* __restrict__ C, const T* __restrict__ b, T* __restrict__ x,
-                                                  int n, int J, int JP) {
-    Lanes L = lanes(JP);
-    const int64_t r = L.unit;
-    if (r >= n) return;
-    for (int j = L.j0; j < J; j += JP) {
-        T s = 0;
-        for (int c = 0; c < n; ++c) s += C[r * n + c] * b[(int64_t)c * J + j];
-        x[r * J + j] = s;
-    }
+                                                  int n, int J) {
+    __shared__ T red[kBlock];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r = blockIdx.x;
+    const int j = blockIdx.y * 64 + lane;
+    T s = 0;
+    if (j < J)
+        for (int c = wave; c < n; c += kBlock / 64) s += C[(int64_t)r * n + c] * b[(int64_t)c * J + j];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if (wave == 0 && j < J) x[(int64_t)r * J + j] = red[lane] + red[64 + lane] + red[128 + lane] + red[192 + lane];
 }
 
 // z_p = -x_mg (x_mg ~ S_hat^{-1} r_p from the V-cycle); the pinned row is an
@@ -628,6 +794,15 @@ void timer_mark(hipStream_t st, bool before) {
     if (g_timer.used < g_timer.pool.size()) (void)hipEventRecord(g_timer.pool[g_timer.used++], st);
 }
 
+// vector width of the node-row fast path for J members (0: use the generic kernels)
+inline int fast_vec(int J, int maxvec) {
+    for (int v = maxvec; v >= 1; v >>= 1)
+        if (J % (32 * v) == 0) return v;
+    return 0;
+}
+
+inline dim3 node_grid(int64_t units, int J, int vec) { return dim3((unsigned)((units + 3) / 4), J / (32 * vec)); }
+
 // runtime VEC -> compile-time dispatch (4 members per thread for FP32, 2 for FP64)
 template <typename T, typename F>
 mhd_status with_vec(int vec, F f) {
@@ -660,10 +835,25 @@ struct Ops {
         DevMesh& m = *S.mesh;
         int64_t units = (int64_t)m.nP2 + m.nP1;
         timer_mark(st, true);
-        hipLaunchKernelGGL((k_saddle<T, 0>), dim3(grid_for(units, JP)), dim3(kBlock), 0, st, m.A_rowptr, m.A_col,
-                           Vals<T>::A(S), m.Bt_rowptr, m.Bt_col, Vals<T>::Bt(m), m.B_rowptr, m.B_col, Vals<T>::B(m),
-                           Vals<T>::dp(m), x, (const T*)nullptr, y, m.nP2, m.nP1, J, JP);
-        LAUNCH_CHECK();
+        mhd_status rc = MHD_OK;
+        const bool aligned = (((uintptr_t)x | (uintptr_t)y) % 16) == 0;
+        const int fv = fast_vec(J, aligned ? (sizeof(T) == 4 ? 4 : 2) : 1);
+        if (fv) {
+            rc = with_vec<T>(fv, [&](auto V) -> mhd_status {
+                hipLaunchKernelGGL((k_saddle_v<T, decltype(V)::value, 0>), node_grid(units, J, fv), dim3(kBlock), 0,
+                                   st, m.A_rowptr, m.A_col, Vals<T>::A(S), m.Bt_rowptr, m.Bt_col, Vals<T>::Bt(m),
+                                   m.B_rowptr, m.B_col, Vals<T>::B(m), Vals<T>::dp(m), x, (const T*)nullptr, y, m.nP2,
+                                   m.nP1, J);
+                LAUNCH_CHECK();
+                return MHD_OK;
+            });
+        } else {
+            hipLaunchKernelGGL((k_saddle<T, 0>), dim3(grid_for(units, JP)), dim3(kBlock), 0, st, m.A_rowptr, m.A_col,
+                               Vals<T>::A(S), m.Bt_rowptr, m.Bt_col, Vals<T>::Bt(m), m.B_rowptr, m.B_col,
+                               Vals<T>::B(m), Vals<T>::dp(m), x, (const T*)nullptr, y, m.nP2, m.nP1, J, JP);
+            LAUNCH_CHECK();
+        }
+        if (rc) return rc;
         if (g_timer.on) {
             timer_mark(st, false);
             g_timer.launches++;
@@ -689,8 +879,8 @@ struct Ops {
         T* x = (T*)S.gw.mg_x[l];
         mhd_status rc;
         if (l + 1 == (int)m.levels.size()) {
-            hipLaunchKernelGGL((k_dense<T>), dim3(grid_for(Lv.n, JP)), dim3(kBlock), 0, st, Vals<T>::cinv(Lv), b, x,
-                               Lv.n, J, JP);
+            hipLaunchKernelGGL((k_dense<T>), dim3(Lv.n, (J + 63) / 64), dim3(kBlock), 0, st, Vals<T>::cinv(Lv), b, x,
+                               Lv.n, J);
             LAUNCH_CHECK();
             *out = x;
             return MHD_OK;
@@ -729,14 +919,34 @@ struct Ops {
         T* t = (T*)S.gw.tbuf;
         T* za = z;
         T* zb = (T*)S.gw.z2buf;
-        hipLaunchKernelGGL((k_velo_first<T>), dim3(grid_for(m.nP2, JP)), dim3(kBlock), 0, st, m.Bt_rowptr, m.Bt_col,
-                           Vals<T>::Bt(m), Vals<T>::dA(S), v, zp, t, za, m.nP2, J, JP, omega);
-        LAUNCH_CHECK();
-        for (int s = 1; s < sweeps; ++s) {
-            hipLaunchKernelGGL((k_velo_sweep<T>), dim3(grid_for(m.nP2, JP)), dim3(kBlock), 0, st, m.A_rowptr,
-                               m.A_col, Vals<T>::A(S), Vals<T>::dA(S), t, za, zb, m.nP2, J, JP, omega);
+        const int fv = fast_vec(J, sizeof(T) == 4 ? 4 : 2);
+        if (fv) {
+            rc = with_vec<T>(fv, [&](auto V) -> mhd_status {
+                constexpr int VV = decltype(V)::value;
+                hipLaunchKernelGGL((k_velo_v<T, VV, true>), node_grid(m.nP2, J, fv), dim3(kBlock), 0, st,
+                                   m.Bt_rowptr, m.Bt_col, Vals<T>::Bt(m), Vals<T>::dA(S), v, (const T*)zp, t,
+                                   (const T*)nullptr, za, m.nP2, J, omega);
+                LAUNCH_CHECK();
+                for (int s = 1; s < sweeps; ++s) {
+                    hipLaunchKernelGGL((k_velo_v<T, VV, false>), node_grid(m.nP2, J, fv), dim3(kBlock), 0, st,
+                                       m.A_rowptr, m.A_col, Vals<T>::A(S), Vals<T>::dA(S), (const T*)nullptr,
+                                       (const T*)nullptr, t, (const T*)za, zb, m.nP2, J, omega);
+                    LAUNCH_CHECK();
+                    std::swap(za, zb);
+                }
+                return MHD_OK;
+            });
+            if (rc) return rc;
+        } else {
+            hipLaunchKernelGGL((k_velo_first<T>), dim3(grid_for(m.nP2, JP)), dim3(kBlock), 0, st, m.Bt_rowptr,
+                               m.Bt_col, Vals<T>::Bt(m), Vals<T>::dA(S), v, zp, t, za, m.nP2, J, JP, omega);
             LAUNCH_CHECK();
-            std::swap(za, zb);
+            for (int s = 1; s < sweeps; ++s) {
+                hipLaunchKernelGGL((k_velo_sweep<T>), dim3(grid_for(m.nP2, JP)), dim3(kBlock), 0, st, m.A_rowptr,
+                                   m.A_col, Vals<T>::A(S), Vals<T>::dA(S), t, za, zb, m.nP2, J, JP, omega);
+                LAUNCH_CHECK();
+                std::swap(za, zb);
+            }
         }
         if (za != z) {
             hipError_t e = hipMemcpyAsync(z, za, sizeof(T) * (size_t)2 * m.nP2 * J, hipMemcpyDeviceToDevice, st);
@@ -810,10 +1020,8 @@ mhd_status gmres_solve(DevShared& S, const double* b, double* x, int J, const mh
     const int JPr = pick_jp(J);
     while (true) {
         // FP64 residual r = b - S x and its column norms
-        hipLaunchKernelGGL((k_saddle<double, 1>), dim3(grid_for((int64_t)m.nP2 + m.nP1, JPr)), dim3(kBlock), 0, st,
-                           m.A_rowptr, m.A_col, S.valA, m.Bt_rowptr, m.Bt_col, m.valBt, m.B_rowptr, m.B_col, m.valB,
-                           m.diagp, x, b, G.r64, m.nP2, m.nP1, J, JPr);
-        LAUNCH_CHECK();
+        (void)JPr;
+        if ((rc = saddle_residual64(S, b, x, G.r64, J, st))) return rc;
         if ((rc = ops.colnorm(G.r64, G.beta))) return rc;
         if ((rc = sync_copy(hbeta, G.beta, J, st))) return rc;
         maxrel = 0.0;
@@ -991,10 +1199,23 @@ mhd_status solve_shared(DevShared& S, const double* rhs, double* x, int J, const
 
 mhd_status saddle_residual64(DevShared& S, const double* b, const double* x, double* r, int J, hipStream_t st) {
     DevMesh& m = *S.mesh;
-    int JP = pick_jp(J);
-    hipLaunchKernelGGL((k_saddle<double, 1>), dim3(grid_for((int64_t)m.nP2 + m.nP1, JP)), dim3(kBlock), 0, st,
-                       m.A_rowptr, m.A_col, S.valA, m.Bt_rowptr, m.Bt_col, m.valBt, m.B_rowptr, m.B_col, m.valB,
-                       m.diagp, x, b, r, m.nP2, m.nP1, J, JP);
+    const int64_t units = (int64_t)m.nP2 + m.nP1;
+    const bool aligned = ((uintptr_t)b % 16 == 0) && ((uintptr_t)x % 16 == 0);
+    const int fv = aligned ? fast_vec(J, 2) : (fast_vec(J, 1) ? 1 : 0);
+    if (fv == 2) {
+        hipLaunchKernelGGL((k_saddle_v<double, 2, 1>), node_grid(units, J, 2), dim3(kBlock), 0, st, m.A_rowptr,
+                           m.A_col, S.valA, m.Bt_rowptr, m.Bt_col, m.valBt, m.B_rowptr, m.B_col, m.valB, m.diagp, x, b,
+                           r, m.nP2, m.nP1, J);
+    } else if (fv == 1) {
+        hipLaunchKernelGGL((k_saddle_v<double, 1, 1>), node_grid(units, J, 1), dim3(kBlock), 0, st, m.A_rowptr,
+                           m.A_col, S.valA, m.Bt_rowptr, m.Bt_col, m.valBt, m.B_rowptr, m.B_col, m.valB, m.diagp, x, b,
+                           r, m.nP2, m.nP1, J);
+    } else {
+        int JP = pick_jp(J);
+        hipLaunchKernelGGL((k_saddle<double, 1>), dim3(grid_for(units, JP)), dim3(kBlock), 0, st, m.A_rowptr, m.A_col,
+                           S.valA, m.Bt_rowptr, m.Bt_col, m.valBt, m.B_rowptr, m.B_col, m.valB, m.diagp, x, b, r,
+                           m.nP2, m.nP1, J, JP);
+    }
     LAUNCH_CHECK();
     return MHD_OK;
 }
