@@ -199,6 +199,7 @@ typedef struct {
     mhd_coeffs coeffs;        /* nu_bar/num_bar are recomputed from nu, nu_m each step */
     mhd_solver_opts solver;
     int J_max;
+    int adjoint;              /* 1: also allocate the adjoint-step workspace */
 } mhd_ctx_desc;
 mhd_status mhd_ens_ctx_create(mhd_mesh m, const mhd_ctx_desc* d, mhd_ctx* out);
 mhd_status mhd_ens_ctx_free(mhd_ctx ctx);
@@ -236,6 +237,44 @@ mhd_status mhd_ens_spmm(mhd_shared A, const void* x, void* y, int J, int precisi
  * launch sizes (units of n*J) per precision.  Enabling resets the counters. */
 mhd_status mhd_ens_timer_enable(int on);
 mhd_status mhd_ens_timer_read(double* ms, int64_t* launches, double* nJ_fp32, double* nJ_fp64);
+
+/* ------------------------------------------------------------------------
+ * Discrete adjoint of Algorithm 1 for an ensemble-mean objective.  The
+ * context must have been created with desc.adjoint = 1 and the
+ * skew-symmetric trilinear form.  Adjoint states are (nP2,2,J) FP64 blocks:
+ * lambda_V = dPhi / dV (per member, velocity nodes and components).
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    const double *nu, *nu_m;      /* host (J) member parameters                           */
+    const double* fhat;           /* device (nP2,2) forcing shape f_{1,j} = f_{2,j} = a_j fhat,
+                                     or NULL (no forcing-amplitude gradient)              */
+    int J;
+} mhd_adjoint_inputs;
+
+/* (Section 4.2, E_h) Terminal adjoint of Phi = E_h = (||<v>||^2 + ||<w>||^2)/2
+ * at the state V, W: lambda_V_j = (1/J) M <v>, lambda_W_j = (1/J) M <w>. */
+mhd_status mhd_ens_adjoint_terminal(mhd_ctx ctx, const double* V, const double* W, double* lamV, double* lamW,
+                                    int J, mhd_stream_t s);
+
+/* (Algorithm 1, transposed) One reverse step n+1 -> n: re-assembles the shared
+ * matrices of level n from V_n, W_n, solves S_v^T mu_v = [lamV_np1; 0] and
+ * S_w^T mu_w = [lamW_np1; 0] (same solver and preconditioner on the transposed
+ * operator, J columns), and writes lamV_n, lamW_n including the couplings
+ * through the ensemble means and the eddy-viscosity maximum.  grad (device,
+ * (J,3) row-major: d/dnu_j, d/dnu_m,j, d/da_j) is accumulated, may be NULL.
+ * lamV_n may alias lamV_np1 (and lamW_n lamW_np1).  st (host) may be NULL. */
+mhd_status mhd_ens_adjoint_step(mhd_ctx ctx, const double* V_n, const double* W_n, const double* V_np1,
+                                const double* W_np1, const double* lamV_np1, const double* lamW_np1,
+                                double* lamV_n, double* lamW_n, const mhd_adjoint_inputs* in, double* grad,
+                                mhd_step_stats* st, mhd_stream_t s);
+
+/* (Section 1, v = u + sqrt(s) B, w = u - sqrt(s) B) Gradients w.r.t. initial
+ * mode coefficients: modes (device, (nm,nP2,2)) are the nodal mode fields,
+ * coefficients m < nm scale u, m >= nm scale B.  grad_ic (device (J, 2 nm)) is
+ * overwritten: d/dc_{j,m} = <phi_m, lamV0_j + lamW0_j>, d/dc_{j,nm+m} =
+ * sqrt(s) <phi_m, lamV0_j - lamW0_j>.  nm <= 4. */
+mhd_status mhd_ens_adjoint_ic(mhd_ctx ctx, const double* lamV0, const double* lamW0, const double* modes, int nm,
+                              double s_coupling, double* grad_ic, int J, mhd_stream_t s);
 
 /* Last error message of the calling thread ("" if none). */
 const char* mhd_ens_last_error(void);

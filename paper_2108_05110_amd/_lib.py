@@ -25,6 +25,7 @@ EXPORTS = (
     "mhd_ens_shared_create", "mhd_ens_shared_free", "mhd_ens_assemble_shared", "mhd_ens_shared_csr",
     "mhd_ens_assemble_rhs", "mhd_ens_solve", "mhd_ens_ctx_create", "mhd_ens_ctx_free", "mhd_ens_step",
     "mhd_ens_spmm", "mhd_ens_timer_enable", "mhd_ens_timer_read", "mhd_ens_last_error", "mhd_ens_version",
+    "mhd_ens_adjoint_terminal", "mhd_ens_adjoint_step", "mhd_ens_adjoint_ic",
 )
 
 
@@ -63,7 +64,12 @@ class SolveStats(C.Structure):
 
 
 class CtxDesc(C.Structure):
-    _fields_ = [("coeffs", Coeffs), ("solver", SolverOpts), ("J_max", C.c_int)]
+    _fields_ = [("coeffs", Coeffs), ("solver", SolverOpts), ("J_max", C.c_int), ("adjoint", C.c_int)]
+
+
+class AdjointInputs(C.Structure):
+    _fields_ = [("nu", C.POINTER(C.c_double)), ("nu_m", C.POINTER(C.c_double)), ("fhat", C.c_void_p),
+                ("J", C.c_int)]
 
 
 class StepInputs(C.Structure):
@@ -102,6 +108,10 @@ def lib():
             "mhd_ens_step": [P, P, P, P, P, C.POINTER(StepInputs), C.POINTER(StepStats), P],
             "mhd_ens_spmm": [P, P, P, I, I, P],
             "mhd_ens_timer_enable": [I],
+            "mhd_ens_adjoint_terminal": [P, P, P, P, P, I, P],
+            "mhd_ens_adjoint_step": [P, P, P, P, P, P, P, P, P, C.POINTER(AdjointInputs), P,
+                                     C.POINTER(StepStats), P],
+            "mhd_ens_adjoint_ic": [P, P, P, P, I, C.c_double, P, I, P],
             "mhd_ens_timer_read": [C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                    C.POINTER(C.c_double)],
         }
@@ -238,6 +248,28 @@ def mhd_ens_timer_read():
     ms, n, a, b = C.c_double(), C.c_int64(), C.c_double(), C.c_double()
     check("mhd_ens_timer_read", lib().mhd_ens_timer_read(C.byref(ms), C.byref(n), C.byref(a), C.byref(b)))
     return ms.value, n.value, a.value, b.value
+
+
+def mhd_ens_adjoint_terminal(ctx, V, W, lamV, lamW, J, stream=None):
+    check("mhd_ens_adjoint_terminal",
+          lib().mhd_ens_adjoint_terminal(ctx, ptr(V), ptr(W), ptr(lamV), ptr(lamW), J, stream_ptr(stream)))
+
+
+def mhd_ens_adjoint_step(ctx, V_n, W_n, V_np1, W_np1, lamV_np1, lamW_np1, lamV_n, lamW_n, inputs, grad,
+                         stream=None, allow_noconv=False):
+    st = StepStats()
+    allow = (MHD_OK, MHD_ENOCONV) if allow_noconv else (MHD_OK,)
+    check("mhd_ens_adjoint_step",
+          lib().mhd_ens_adjoint_step(ctx, ptr(V_n), ptr(W_n), ptr(V_np1), ptr(W_np1), ptr(lamV_np1),
+                                     ptr(lamW_np1), ptr(lamV_n), ptr(lamW_n), C.byref(inputs), ptr(grad),
+                                     C.byref(st), stream_ptr(stream)), allow)
+    return st
+
+
+def mhd_ens_adjoint_ic(ctx, lamV0, lamW0, modes, nm, s_coupling, grad_ic, J, stream=None):
+    check("mhd_ens_adjoint_ic",
+          lib().mhd_ens_adjoint_ic(ctx, ptr(lamV0), ptr(lamW0), ptr(modes), nm, s_coupling, ptr(grad_ic), J,
+                                   stream_ptr(stream)))
 
 
 def solver_opts(precision=MHD_FP64, rtol=None, inner_rtol=None, maxit=2000, restart=30, jacobi_sweeps=6,

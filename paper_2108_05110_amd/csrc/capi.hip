@@ -25,6 +25,14 @@ struct mhd_ctx_s {
     double* coef = nullptr;                 // 2 Jmax member coefficients
     double* host_coef = nullptr;            // pinned staging, 2 Jmax
     double* partial = nullptr;              // reductions
+    // adjoint workspace (desc.adjoint)
+    double *Tv = nullptr, *Tv1 = nullptr, *Tw = nullptr, *Tw1 = nullptr;   // (nP2,2,J)
+    double *Kmv = nullptr, *Kmw = nullptr;                                  // (nP2,2,J)
+    double* tmeans = nullptr;                                               // 4 x 2 nP2
+    double *eta_v = nullptr, *eta_w = nullptr;                              // n_el x 7 x 2
+    int32_t *js_v = nullptr, *js_w = nullptr;                               // n_el x 7
+    double* Mf = nullptr;                                                   // 2 nP2
+    double* dots = nullptr;                                                 // 10 J
     std::vector<void*> allocs;
 };
 
@@ -95,6 +103,7 @@ mhd_status build_device_mesh(DevMesh& D) {
     RefTables t;
     make_ref_tables(t);
     upload_ref_tables(t);
+    upload_ref_tables_adjoint(t);
     MHD_HIP(hipGetLastError());
     // element geometry: detJ and the inverse Jacobian of the affine map from the reference triangle
     std::vector<double> geo((size_t)h.n_el * 6, 0.0);
@@ -136,6 +145,8 @@ mhd_status build_device_mesh(DevMesh& D) {
     if ((rc = upload(L, &D.gB_idx, h.gB_idx))) return rc;
     if ((rc = upload(L, &D.gBt_ptr, h.gBt_ptr))) return rc;
     if ((rc = upload(L, &D.gBt_idx, h.gBt_idx))) return rc;
+    if ((rc = upload(L, &D.permA, h.permA))) return rc;
+    if ((rc = upload(L, &D.permBtB, h.permBtB))) return rc;
     if ((rc = upload(L, &D.inc_ptr, h.inc_ptr))) return rc;
     if ((rc = upload(L, &D.inc, h.inc))) return rc;
     if ((rc = dev_alloc(L, &D.valM, D.nnzA))) return rc;
@@ -144,6 +155,10 @@ mhd_status build_device_mesh(DevMesh& D) {
     if ((rc = dev_alloc(L, &D.valB32, 2 * D.nnzB))) return rc;
     if ((rc = dev_alloc(L, &D.valBt, 2 * D.nnzBt))) return rc;
     if ((rc = dev_alloc(L, &D.valBt32, 2 * D.nnzBt))) return rc;
+    if ((rc = dev_alloc(L, &D.valB_T, 2 * D.nnzB))) return rc;
+    if ((rc = dev_alloc(L, &D.valB_T32, 2 * D.nnzB))) return rc;
+    if ((rc = dev_alloc(L, &D.valBt_T, 2 * D.nnzBt))) return rc;
+    if ((rc = dev_alloc(L, &D.valBt_T32, 2 * D.nnzBt))) return rc;
     std::vector<double> dp(h.nP1, 0.0);
     if (h.pin >= 0) dp[h.pin] = 1.0;
     if ((rc = upload(L, &D.diagp, dp))) return rc;
@@ -179,6 +194,7 @@ mhd_status build_device_mesh(DevMesh& D) {
     double* eb = nullptr;
     MHD_HIP(hipMalloc((void**)&eb, sizeof(double) * 108 * std::max(1, h.n_el)));
     hipError_t e = launch_const_assembly(D, eb, 0);
+    if (e == hipSuccess) e = launch_transpose_const(D, 0);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     (void)hipFree(eb);
     if (e != hipSuccess) {
@@ -195,6 +211,8 @@ mhd_status make_shared(DevMesh* m, int J_max, int restart, DevShared& S) {
     mhd_status rc;
     if ((rc = dev_alloc(L, &S.valA, m->nnzA))) return rc;
     if ((rc = dev_alloc(L, &S.valA32, m->nnzA))) return rc;
+    if ((rc = dev_alloc(L, &S.valA_T, m->nnzA))) return rc;
+    if ((rc = dev_alloc(L, &S.valA_T32, m->nnzA))) return rc;
     if ((rc = dev_alloc(L, &S.dinvA, m->nP2))) return rc;
     if ((rc = dev_alloc(L, &S.dinvA32, m->nP2))) return rc;
     if ((rc = dev_alloc(L, &S.zbar, 2 * (size_t)m->nP2))) return rc;
@@ -480,6 +498,23 @@ mhd_status mhd_ens_ctx_create(mhd_mesh m, const mhd_ctx_desc* d, mhd_ctx* out) {
     if ((rc = dev_alloc(c->allocs, &c->partial, (size_t)2048 * d->J_max + 1024))) return fail(rc);
     if (hipHostMalloc((void**)&c->host_coef, sizeof(double) * 2 * d->J_max, hipHostMallocDefault) != hipSuccess)
         return fail(MHD_ENOMEM);
+    if (d->adjoint) {
+        if (d->coeffs.convective != 0) {
+            set_error("mhd_ens_ctx_create: the adjoint supports the skew-symmetric trilinear form only");
+            return fail(MHD_EINVAL);
+        }
+        DevMesh& D = m->d;
+        size_t vb = 2 * (size_t)D.nP2 * d->J_max;
+        for (double** p : {&c->Tv, &c->Tv1, &c->Tw, &c->Tw1, &c->Kmv, &c->Kmw})
+            if ((rc = dev_alloc(c->allocs, p, vb))) return fail(rc);
+        if ((rc = dev_alloc(c->allocs, &c->tmeans, 8 * (size_t)D.nP2))) return fail(rc);
+        if ((rc = dev_alloc(c->allocs, &c->eta_v, 14 * (size_t)D.n_el))) return fail(rc);
+        if ((rc = dev_alloc(c->allocs, &c->eta_w, 14 * (size_t)D.n_el))) return fail(rc);
+        if ((rc = dev_alloc(c->allocs, &c->js_v, 7 * (size_t)D.n_el))) return fail(rc);
+        if ((rc = dev_alloc(c->allocs, &c->js_w, 7 * (size_t)D.n_el))) return fail(rc);
+        if ((rc = dev_alloc(c->allocs, &c->Mf, 2 * (size_t)D.nP2))) return fail(rc);
+        if ((rc = dev_alloc(c->allocs, &c->dots, 10 * (size_t)d->J_max))) return fail(rc);
+    }
     *out = c;
     return MHD_OK;
 }
@@ -584,6 +619,168 @@ mhd_status mhd_ens_step(mhd_ctx ctx, double* V, double* W, double* Q, double* R,
     if (rv == MHD_ENOCONV || rw == MHD_ENOCONV) {
         set_error("mhd_ens_step: a subproblem solve hit maxit");
         return MHD_ENOCONV;
+    }
+    return MHD_OK;
+}
+
+mhd_status mhd_ens_adjoint_terminal(mhd_ctx ctx, const double* V, const double* W, double* lamV, double* lamW,
+                                    int J, mhd_stream_t s) {
+    CHECK_ARG(ctx && V && W && lamV && lamW, "mhd_ens_adjoint_terminal: null argument");
+    if (J < 1 || J > ctx->desc.J_max) {
+        set_error("mhd_ens_adjoint_terminal: J outside [1, J_max]");
+        return MHD_ESHAPE;
+    }
+    DevMesh& D = ctx->mesh->d;
+    hipStream_t st = as_stream(s);
+    double* zb = ctx->Av->d.zbar;
+    hipError_t e = launch_mean(V, zb, 2 * (int64_t)D.nP2, J, st);
+    if (e == hipSuccess) e = launch_energy_adjoint(D, zb, lamV, J, st);
+    if (e == hipSuccess) e = launch_mean(W, zb, 2 * (int64_t)D.nP2, J, st);
+    if (e == hipSuccess) e = launch_energy_adjoint(D, zb, lamW, J, st);
+    if (e != hipSuccess) {
+        set_error(std::string("mhd_ens_adjoint_terminal: ") + hipGetErrorString(e));
+        return MHD_EHIP;
+    }
+    return MHD_OK;
+}
+
+mhd_status mhd_ens_adjoint_step(mhd_ctx ctx, const double* V_n, const double* W_n, const double* V_np1,
+                                const double* W_np1, const double* lamV_np1, const double* lamW_np1,
+                                double* lamV_n, double* lamW_n, const mhd_adjoint_inputs* in, double* grad,
+                                mhd_step_stats* stt, mhd_stream_t s) {
+    CHECK_ARG(ctx && in, "mhd_ens_adjoint_step: null argument");
+    CHECK_ARG(ctx->Tv, "mhd_ens_adjoint_step: context created without the adjoint workspace");
+    CHECK_ARG(V_n && W_n && V_np1 && W_np1 && lamV_np1 && lamW_np1 && lamV_n && lamW_n,
+              "mhd_ens_adjoint_step: null state array");
+    CHECK_ARG(in->nu && in->nu_m, "mhd_ens_adjoint_step: null nu / nu_m");
+    const int J = in->J;
+    if (J < 1 || J > ctx->desc.J_max) {
+        set_error("mhd_ens_adjoint_step: J outside [1, J_max]");
+        return MHD_ESHAPE;
+    }
+    DevMesh& D = ctx->mesh->d;
+    hipStream_t st = as_stream(s);
+    double nub = 0, numb = 0;
+    for (int j = 0; j < J; ++j) {
+        nub += in->nu[j];
+        numb += in->nu_m[j];
+    }
+    nub /= J;
+    numb /= J;
+    MHD_HIP(hipStreamSynchronize(st));   // the pinned staging buffer may still feed an earlier copy
+    for (int j = 0; j < J; ++j) {
+        ctx->host_coef[j] = 0.5 * (in->nu[j] - in->nu_m[j]);
+        ctx->host_coef[J + j] = 0.5 * ((in->nu[j] - nub) + (in->nu_m[j] - numb));
+    }
+    MHD_HIP(hipMemcpyAsync(ctx->coef, ctx->host_coef, sizeof(double) * 2 * J, hipMemcpyHostToDevice, st));
+    mhd_coeffs c = ctx->desc.coeffs;
+    c.nu_bar = nub;
+    c.num_bar = numb;
+    DevShared& Av = ctx->Av->d;
+    DevShared& Aw = ctx->Aw->d;
+    mhd_status rc;
+    if ((rc = assemble_shared_impl(D, c, W_n, J, Av, st))) return rc;    // zbar = <w>
+    if ((rc = assemble_shared_impl(D, c, V_n, J, Aw, st))) return rc;    // zbar = <v>
+    hipError_t e = launch_transpose_A(D, Av, st);
+    if (e == hipSuccess) e = launch_transpose_A(D, Aw, st);
+    if (e != hipSuccess) {
+        set_error(std::string("mhd_ens_adjoint_step transpose: ") + hipGetErrorString(e));
+        return MHD_EHIP;
+    }
+    const size_t vel = sizeof(double) * 2 * (size_t)D.nP2 * J;
+    const size_t prs = sizeof(double) * (size_t)D.nP1 * J;
+    const int64_t poff = 2 * (int64_t)D.nP2 * J;
+    MHD_HIP(hipMemcpyAsync(ctx->bv, lamV_np1, vel, hipMemcpyDeviceToDevice, st));
+    MHD_HIP(hipMemcpyAsync(ctx->bw, lamW_np1, vel, hipMemcpyDeviceToDevice, st));
+    MHD_HIP(hipMemsetAsync(ctx->bv + poff, 0, prs, st));
+    MHD_HIP(hipMemsetAsync(ctx->bw + poff, 0, prs, st));
+    MHD_HIP(hipMemsetAsync(ctx->Xv, 0, vel + prs, st));
+    MHD_HIP(hipMemsetAsync(ctx->Xw, 0, vel + prs, st));
+    mhd_solve_stats sv{}, sw{};
+    Av.transposed = Aw.transposed = true;
+    mhd_status rv = solve_shared(Av, ctx->bv, ctx->Xv, J, ctx->desc.solver, &sv, st);
+    mhd_status rw = (rv == MHD_OK || rv == MHD_ENOCONV) ? solve_shared(Aw, ctx->bw, ctx->Xw, J, ctx->desc.solver, &sw, st)
+                                                        : rv;
+    Av.transposed = Aw.transposed = false;
+    if (rv != MHD_OK && rv != MHD_ENOCONV) return rv;
+    if (rw != MHD_OK && rw != MHD_ENOCONV) return rw;
+    const double* muv = ctx->Xv;
+    const double* muw = ctx->Xw;
+    const int64_t rows = 2 * (int64_t)D.nP2;
+    double* Tvbar = ctx->tmeans;
+    double* Tv1bar = ctx->tmeans + rows;
+    double* Twbar = ctx->tmeans + 2 * rows;
+    double* Tw1bar = ctx->tmeans + 3 * rows;
+    const double eddy_c = 2.0 * c.mu * c.dt;
+    e = launch_adj_T(D, muv, muw, V_n, W_n, V_np1, W_np1, ctx->Tv, ctx->Tv1, ctx->Tw, ctx->Tw1, J, st);
+    if (e == hipSuccess) e = launch_mean(ctx->Tv, Tvbar, rows, J, st);
+    if (e == hipSuccess) e = launch_mean(ctx->Tv1, Tv1bar, rows, J, st);
+    if (e == hipSuccess) e = launch_mean(ctx->Tw, Twbar, rows, J, st);
+    if (e == hipSuccess) e = launch_mean(ctx->Tw1, Tw1bar, rows, J, st);
+    // eddy of S_w (l_v from V_n') against mu_w and W^{n+1}; eddy of S_v (l_w) against mu_v and V^{n+1}
+    if (e == hipSuccess) e = launch_adj_eddy(D, V_n, Aw.zbar, muw, W_np1, ctx->eta_v, ctx->js_v, J, eddy_c, st);
+    if (e == hipSuccess) e = launch_adj_eddy(D, W_n, Av.zbar, muv, V_np1, ctx->eta_w, ctx->js_w, J, eddy_c, st);
+    if (e == hipSuccess)
+        e = launch_adj_lambda(D, ctx->coef, muv, muw, V_n, W_n, Aw.zbar, Av.zbar, ctx->Tv, ctx->Tw, Tvbar, Tv1bar,
+                              Twbar, Tw1bar, ctx->eta_v, ctx->js_v, ctx->eta_w, ctx->js_w, lamV_n, lamW_n, ctx->Kmv,
+                              ctx->Kmw, J, c.dt, st);
+    if (e == hipSuccess && grad) {
+        int nt = 6;
+        const double* X[8] = {ctx->Kmv, ctx->Kmv, ctx->Kmv, ctx->Kmw, ctx->Kmw, ctx->Kmw, muv, muw};
+        const double* Y[8] = {W_n, V_n, V_np1, V_n, W_n, W_np1, ctx->Mf, ctx->Mf};
+        int yv[8] = {0, 0, 0, 0, 0, 0, 1, 1};
+        if (in->fhat) {
+            e = launch_mass_vec_masked(D, in->fhat, ctx->Mf, st);
+            nt = 8;
+        } else {
+            e = hipMemsetAsync(ctx->dots + 6 * J, 0, sizeof(double) * 2 * J, st);
+        }
+        if (e == hipSuccess) e = launch_multidot(X, Y, yv, nt, rows, J, ctx->partial, ctx->dots, st);
+        if (e == hipSuccess) e = launch_adj_grad(ctx->dots, J, grad, st);
+    }
+    if (e != hipSuccess) {
+        set_error(std::string("mhd_ens_adjoint_step: ") + hipGetErrorString(e));
+        return MHD_EHIP;
+    }
+    if (stt) {
+        stt->v = sv;
+        stt->w = sw;
+        stt->energy = 0.0;
+    }
+    if (rv == MHD_ENOCONV || rw == MHD_ENOCONV) {
+        set_error("mhd_ens_adjoint_step: a transposed solve hit maxit");
+        return MHD_ENOCONV;
+    }
+    return MHD_OK;
+}
+
+mhd_status mhd_ens_adjoint_ic(mhd_ctx ctx, const double* lamV0, const double* lamW0, const double* modes, int nm,
+                              double s_coupling, double* grad_ic, int J, mhd_stream_t s) {
+    CHECK_ARG(ctx && lamV0 && lamW0 && modes && grad_ic, "mhd_ens_adjoint_ic: null argument");
+    CHECK_ARG(ctx->dots, "mhd_ens_adjoint_ic: context created without the adjoint workspace");
+    CHECK_ARG(nm >= 1 && nm <= 4, "mhd_ens_adjoint_ic: nm must be in [1, 4]");
+    CHECK_ARG(s_coupling >= 0 && std::isfinite(s_coupling), "mhd_ens_adjoint_ic: bad coupling number");
+    if (J < 1 || J > ctx->desc.J_max) {
+        set_error("mhd_ens_adjoint_ic: J outside [1, J_max]");
+        return MHD_ESHAPE;
+    }
+    DevMesh& D = ctx->mesh->d;
+    hipStream_t st = as_stream(s);
+    const int64_t rows = 2 * (int64_t)D.nP2;
+    const double* X[8];
+    const double* Y[8];
+    int yv[8];
+    for (int m = 0; m < nm; ++m) {
+        X[m] = lamV0;
+        X[nm + m] = lamW0;
+        Y[m] = Y[nm + m] = modes + (int64_t)m * rows;
+        yv[m] = yv[nm + m] = 1;
+    }
+    hipError_t e = launch_multidot(X, Y, yv, 2 * nm, rows, J, ctx->partial, ctx->dots, st);
+    if (e == hipSuccess) e = launch_ic_combine(ctx->dots, nm, J, std::sqrt(s_coupling), grad_ic, st);
+    if (e != hipSuccess) {
+        set_error(std::string("mhd_ens_adjoint_ic: ") + hipGetErrorString(e));
+        return MHD_EHIP;
     }
     return MHD_OK;
 }

@@ -57,6 +57,7 @@ struct HostMesh {
     HostCSR B;                   // P1 x P2
     // element -> CSR slot maps and slot -> element contributions (deterministic gathers)
     std::vector<int32_t> slotA;  // n_el x 36
+    std::vector<int32_t> permA, permBtB;     // transposition maps of the operator slots
     std::vector<int32_t> gA_ptr, gA_idx;     // nnz_A + 1, contributions e*36 + a*6 + b
     std::vector<int32_t> gB_ptr, gB_idx;     // nnz_B + 1, contributions e*18 + k*6 + a
     std::vector<int32_t> gBt_ptr, gBt_idx;   // nnz_Bt + 1, contributions e*18 + k*6 + a

@@ -63,6 +63,11 @@ struct DevMesh {
     float *valB32 = nullptr, *valBt32 = nullptr;
     double* diagp = nullptr;
     float* diagp32 = nullptr;
+    // transposed operator: slot permutations and the constant transposed divergence blocks
+    int32_t* permA = nullptr;                     // nnz_A: slot (i,k) -> slot (k,i)
+    int32_t* permBtB = nullptr;                   // nnz_Bt: B^T slot (i,m) -> B slot (m,i)
+    double *valB_T = nullptr, *valBt_T = nullptr; // B pattern / B^T pattern, 2 values per entry
+    float *valB_T32 = nullptr, *valBt_T32 = nullptr;
     double* mp = nullptr;                         // lumped P1 mass
     double* mp_inv = nullptr;
     uint8_t* pfix = nullptr;                      // nP1: fixed rows of the pressure Laplacian
@@ -105,6 +110,9 @@ struct DevShared {
     int Jmax = 0;
     double* valA = nullptr;       // nnzA
     float* valA32 = nullptr;
+    double* valA_T = nullptr;     // transposed values (adjoint solves)
+    float* valA_T32 = nullptr;
+    bool transposed = false;      // solver uses the transposed operator
     double* dinvA = nullptr;      // nP2 inverse diagonal of A
     float* dinvA32 = nullptr;
     double* zbar = nullptr;       // 2 nP2
@@ -139,6 +147,30 @@ mhd_status spmm_shared(DevShared& S, const void* x, void* y, int J, int precisio
 mhd_status timer_enable(int on);
 mhd_status timer_read(double* ms, int64_t* launches, double* nJ32, double* nJ64);
 mhd_status saddle_residual64(DevShared& S, const double* b, const double* x, double* r, int J, hipStream_t s);
+
+hipError_t launch_reduce_rows(const double* partial, int nblk, int64_t width, double* out, hipStream_t s);
+
+// ---------------------------------------------------------------- adjoint (adjoint.hip)
+void upload_ref_tables_adjoint(const RefTables& t);
+hipError_t launch_transpose_const(DevMesh& m, hipStream_t s);
+hipError_t launch_transpose_A(DevMesh& m, DevShared& S, hipStream_t s);
+hipError_t launch_energy_adjoint(const DevMesh& m, const double* zbar, double* lam, int J, hipStream_t s);
+hipError_t launch_mass_vec_masked(const DevMesh& m, const double* f, double* out, hipStream_t s);
+hipError_t launch_adj_T(const DevMesh& m, const double* muv, const double* muw, const double* V, const double* W,
+                        const double* V1, const double* W1, double* Tv, double* Tv1, double* Tw, double* Tw1, int J,
+                        hipStream_t s);
+hipError_t launch_adj_eddy(const DevMesh& m, const double* Z, const double* zbar, const double* mu, const double* X,
+                           double* eta, int32_t* jstar, int J, double eddy_c, hipStream_t s);
+hipError_t launch_adj_lambda(const DevMesh& m, const double* coef, const double* muv, const double* muw, const double* V,
+                             const double* W, const double* vbar, const double* wbar, const double* Tv,
+                             const double* Tw, const double* Tvbar, const double* Tv1bar, const double* Twbar,
+                             const double* Tw1bar, const double* eta_v, const int32_t* js_v, const double* eta_w,
+                             const int32_t* js_w, double* lamV, double* lamW, double* Kmv, double* Kmw, int J,
+                             double dt, hipStream_t s);
+hipError_t launch_multidot(const double* const* X, const double* const* Y, const int* yvec, int nt, int64_t R, int J,
+                           double* partial, double* out, hipStream_t s);
+hipError_t launch_adj_grad(const double* d, int J, double* grad, hipStream_t s);
+hipError_t launch_ic_combine(const double* d, int nm, int J, double sq, double* grad_ic, hipStream_t s);
 
 // pressure post-processing: p -= (sum_k m_k p_k) / sum_k m_k per member
 hipError_t launch_pressure_zero_mean(const DevMesh& m, double* p, int J, double* partial, hipStream_t s);

@@ -487,6 +487,13 @@ mhd_status build_mesh(const mhd_mesh_desc* d, HostMesh& m, bool full) {
         std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
         for (size_t c = 0; c < slots.size(); ++c) idx[fill[slots[c]]++] = (int32_t)c;
     };
+    // transposition maps: A slot (i,k) -> slot (k,i); B^T slot (i,m) -> B slot (m,i)
+    m.permA.resize(m.A.nnz());
+    for (int i = 0; i < nP2; ++i)
+        for (int32_t p = m.A.rowptr[i]; p < m.A.rowptr[i + 1]; ++p) m.permA[p] = slot(m.A, m.A.col[p], i);
+    m.permBtB.resize(m.Bt.nnz());
+    for (int i = 0; i < nP2; ++i)
+        for (int32_t p = m.Bt.rowptr[i]; p < m.Bt.rowptr[i + 1]; ++p) m.permBtB[p] = slot(m.B, m.Bt.col[p], i);
     gather(m.slotA, m.A.nnz(), m.gA_ptr, m.gA_idx);
     gather(slotB, m.B.nnz(), m.gB_ptr, m.gB_idx);
     gather(slotBt, m.Bt.nnz(), m.gBt_ptr, m.gBt_idx);

@@ -91,10 +91,10 @@ template <typename T>
 struct Vals;
 template <>
 struct Vals<double> {
-    static const double* A(const DevShared& s) { return s.valA; }
+    static const double* A(const DevShared& s) { return s.transposed ? s.valA_T : s.valA; }
     static const double* dA(const DevShared& s) { return s.dinvA; }
-    static const double* B(const DevMesh& m) { return m.valB; }
-    static const double* Bt(const DevMesh& m) { return m.valBt; }
+    static const double* B(const DevShared& s) { return s.transposed ? s.mesh->valB_T : s.mesh->valB; }
+    static const double* Bt(const DevShared& s) { return s.transposed ? s.mesh->valBt_T : s.mesh->valBt; }
     static const double* dp(const DevMesh& m) { return m.diagp; }
     static const double* csr(const DevCSR<double>& c) { return c.val; }
     static const double* dinv(const DevLevel& l) { return l.dinv; }
@@ -102,10 +102,10 @@ struct Vals<double> {
 };
 template <>
 struct Vals<float> {
-    static const float* A(const DevShared& s) { return s.valA32; }
+    static const float* A(const DevShared& s) { return s.transposed ? s.valA_T32 : s.valA32; }
     static const float* dA(const DevShared& s) { return s.dinvA32; }
-    static const float* B(const DevMesh& m) { return m.valB32; }
-    static const float* Bt(const DevMesh& m) { return m.valBt32; }
+    static const float* B(const DevShared& s) { return s.transposed ? s.mesh->valB_T32 : s.mesh->valB32; }
+    static const float* Bt(const DevShared& s) { return s.transposed ? s.mesh->valBt_T32 : s.mesh->valBt32; }
     static const float* dp(const DevMesh& m) { return m.diagp32; }
     static const float* csr(const DevCSR<double>& c) { return c.val32; }
     static const float* dinv(const DevLevel& l) { return l.dinv32; }
@@ -841,16 +841,16 @@ struct Ops {
         if (fv) {
             rc = with_vec<T>(fv, [&](auto V) -> mhd_status {
                 hipLaunchKernelGGL((k_saddle_v<T, decltype(V)::value, 0>), node_grid(units, J, fv), dim3(kBlock), 0,
-                                   st, m.A_rowptr, m.A_col, Vals<T>::A(S), m.Bt_rowptr, m.Bt_col, Vals<T>::Bt(m),
-                                   m.B_rowptr, m.B_col, Vals<T>::B(m), Vals<T>::dp(m), x, (const T*)nullptr, y, m.nP2,
+                                   st, m.A_rowptr, m.A_col, Vals<T>::A(S), m.Bt_rowptr, m.Bt_col, Vals<T>::Bt(S),
+                                   m.B_rowptr, m.B_col, Vals<T>::B(S), Vals<T>::dp(m), x, (const T*)nullptr, y, m.nP2,
                                    m.nP1, J);
                 LAUNCH_CHECK();
                 return MHD_OK;
             });
         } else {
             hipLaunchKernelGGL((k_saddle<T, 0>), dim3(grid_for(units, JP)), dim3(kBlock), 0, st, m.A_rowptr, m.A_col,
-                               Vals<T>::A(S), m.Bt_rowptr, m.Bt_col, Vals<T>::Bt(m), m.B_rowptr, m.B_col,
-                               Vals<T>::B(m), Vals<T>::dp(m), x, (const T*)nullptr, y, m.nP2, m.nP1, J, JP);
+                               Vals<T>::A(S), m.Bt_rowptr, m.Bt_col, Vals<T>::Bt(S), m.B_rowptr, m.B_col,
+                               Vals<T>::B(S), Vals<T>::dp(m), x, (const T*)nullptr, y, m.nP2, m.nP1, J, JP);
             LAUNCH_CHECK();
         }
         if (rc) return rc;
@@ -924,7 +924,7 @@ struct Ops {
             rc = with_vec<T>(fv, [&](auto V) -> mhd_status {
                 constexpr int VV = decltype(V)::value;
                 hipLaunchKernelGGL((k_velo_v<T, VV, true>), node_grid(m.nP2, J, fv), dim3(kBlock), 0, st,
-                                   m.Bt_rowptr, m.Bt_col, Vals<T>::Bt(m), Vals<T>::dA(S), v, (const T*)zp, t,
+                                   m.Bt_rowptr, m.Bt_col, Vals<T>::Bt(S), Vals<T>::dA(S), v, (const T*)zp, t,
                                    (const T*)nullptr, za, m.nP2, J, omega);
                 LAUNCH_CHECK();
                 for (int s = 1; s < sweeps; ++s) {
@@ -939,7 +939,7 @@ struct Ops {
             if (rc) return rc;
         } else {
             hipLaunchKernelGGL((k_velo_first<T>), dim3(grid_for(m.nP2, JP)), dim3(kBlock), 0, st, m.Bt_rowptr,
-                               m.Bt_col, Vals<T>::Bt(m), Vals<T>::dA(S), v, zp, t, za, m.nP2, J, JP, omega);
+                               m.Bt_col, Vals<T>::Bt(S), Vals<T>::dA(S), v, zp, t, za, m.nP2, J, JP, omega);
             LAUNCH_CHECK();
             for (int s = 1; s < sweeps; ++s) {
                 hipLaunchKernelGGL((k_velo_sweep<T>), dim3(grid_for(m.nP2, JP)), dim3(kBlock), 0, st, m.A_rowptr,
@@ -1204,20 +1204,25 @@ mhd_status saddle_residual64(DevShared& S, const double* b, const double* x, dou
     const int fv = aligned ? fast_vec(J, 2) : (fast_vec(J, 1) ? 1 : 0);
     if (fv == 2) {
         hipLaunchKernelGGL((k_saddle_v<double, 2, 1>), node_grid(units, J, 2), dim3(kBlock), 0, st, m.A_rowptr,
-                           m.A_col, S.valA, m.Bt_rowptr, m.Bt_col, m.valBt, m.B_rowptr, m.B_col, m.valB, m.diagp, x, b,
+                           m.A_col, Vals<double>::A(S), m.Bt_rowptr, m.Bt_col, Vals<double>::Bt(S), m.B_rowptr, m.B_col, Vals<double>::B(S), m.diagp, x, b,
                            r, m.nP2, m.nP1, J);
     } else if (fv == 1) {
         hipLaunchKernelGGL((k_saddle_v<double, 1, 1>), node_grid(units, J, 1), dim3(kBlock), 0, st, m.A_rowptr,
-                           m.A_col, S.valA, m.Bt_rowptr, m.Bt_col, m.valBt, m.B_rowptr, m.B_col, m.valB, m.diagp, x, b,
+                           m.A_col, Vals<double>::A(S), m.Bt_rowptr, m.Bt_col, Vals<double>::Bt(S), m.B_rowptr, m.B_col, Vals<double>::B(S), m.diagp, x, b,
                            r, m.nP2, m.nP1, J);
     } else {
         int JP = pick_jp(J);
         hipLaunchKernelGGL((k_saddle<double, 1>), dim3(grid_for(units, JP)), dim3(kBlock), 0, st, m.A_rowptr, m.A_col,
-                           S.valA, m.Bt_rowptr, m.Bt_col, m.valBt, m.B_rowptr, m.B_col, m.valB, m.diagp, x, b, r,
+                           Vals<double>::A(S), m.Bt_rowptr, m.Bt_col, Vals<double>::Bt(S), m.B_rowptr, m.B_col, Vals<double>::B(S), m.diagp, x, b, r,
                            m.nP2, m.nP1, J, JP);
     }
     LAUNCH_CHECK();
     return MHD_OK;
+}
+
+hipError_t launch_reduce_rows(const double* partial, int nblk, int64_t width, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce, dim3(reduce_grid(width)), dim3(kBlock), 0, s, partial, nblk, width, out, 0);
+    return hipGetLastError();
 }
 
 mhd_status spmm_shared(DevShared& S, const void* x, void* y, int J, int precision, hipStream_t st) {

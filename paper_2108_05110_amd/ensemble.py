@@ -44,7 +44,8 @@ def to_dev(a, device="cuda"):
 class Stepper:
     """Algorithm 1 on the GPU for one ensemble: mhd_ens_step per time step."""
 
-    def __init__(self, mesh: Mesh, problem, J_max=None, opts=None, device="cuda", time_dependent_data=True):
+    def __init__(self, mesh: Mesh, problem, J_max=None, opts=None, device="cuda", time_dependent_data=True,
+                 adjoint=False):
         self.mesh = mesh
         self.pb = problem
         self.J = problem.J
@@ -52,7 +53,7 @@ class Stepper:
         self.opts = opts if opts is not None else L.solver_opts()
         desc = L.CtxDesc(L.Coeffs(problem.dt, problem.mu, float(np.mean(problem.nu)),
                                   float(np.mean(problem.nu_m)), int(problem.convective)),
-                         self.opts, J_max or self.J)
+                         self.opts, J_max or self.J, 1 if adjoint else 0)
         self.ctx = L.mhd_ens_ctx_create(mesh.handle, desc)
         V0, W0 = problem.ic(mesh.xy)
         self.V = to_dev(V0, device)
