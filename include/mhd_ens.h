@@ -173,6 +173,11 @@ typedef struct {
     int jacobi_sweeps;        /* velocity-block smoothing sweeps in the preconditioner */
     int check_every;          /* inner iterations between convergence checks (>= 1)    */
     int cgs_passes;           /* Gram-Schmidt passes: 1, 2, or 0 = 1 for FP32, 2 for FP64 */
+    int fixed_cycles;         /* > 0: fixed schedule of fixed_cycles refinement cycles of
+                                 `restart` inner iterations each, with no host
+                                 synchronisation (graph-capturable); rtol, inner_rtol,
+                                 maxit and check_every are then ignored and the stats
+                                 report max_relres = -1, converged = -1              */
 } mhd_solver_opts;
 
 typedef struct {
@@ -200,6 +205,10 @@ typedef struct {
     mhd_solver_opts solver;
     int J_max;
     int adjoint;              /* 1: also allocate the adjoint-step workspace */
+    int graph;                /* 1: capture the step's device work into a HIP graph on the
+                                 first call (per argument set and stream) and replay it
+                                 afterwards; needs solver.fixed_cycles > 0 and a non-null
+                                 stream */
 } mhd_ctx_desc;
 mhd_status mhd_ens_ctx_create(mhd_mesh m, const mhd_ctx_desc* d, mhd_ctx* out);
 mhd_status mhd_ens_ctx_free(mhd_ctx ctx);
@@ -275,6 +284,19 @@ mhd_status mhd_ens_adjoint_step(mhd_ctx ctx, const double* V_n, const double* W_
  * sqrt(s) <phi_m, lamV0_j - lamW0_j>.  nm <= 4. */
 mhd_status mhd_ens_adjoint_ic(mhd_ctx ctx, const double* lamV0, const double* lamW0, const double* modes, int nm,
                               double s_coupling, double* grad_ic, int J, mhd_stream_t s);
+
+/* One launch for several ensembles: the device work of one step of every
+ * context in the group (each with its own mesh, J and fixed solver schedule)
+ * is captured into a single HIP graph with one parallel branch per ensemble
+ * (forked onto the group's own streams) and replayed by every later call with
+ * the same arguments.  Arrays are per context (n of each); in[i] as for
+ * mhd_ens_step.  The stream must be non-null.  Contexts of one group must not
+ * be stepped concurrently elsewhere. */
+typedef struct mhd_group_s* mhd_group;
+mhd_status mhd_ens_group_create(int n, const mhd_ctx* ctxs, mhd_group* out);
+mhd_status mhd_ens_group_step(mhd_group g, double* const* V, double* const* W, double* const* Q, double* const* R,
+                              const mhd_step_inputs* in, mhd_stream_t s);
+mhd_status mhd_ens_group_free(mhd_group g);
 
 /* Last error message of the calling thread ("" if none). */
 const char* mhd_ens_last_error(void);

@@ -26,6 +26,7 @@ EXPORTS = (
     "mhd_ens_assemble_rhs", "mhd_ens_solve", "mhd_ens_ctx_create", "mhd_ens_ctx_free", "mhd_ens_step",
     "mhd_ens_spmm", "mhd_ens_timer_enable", "mhd_ens_timer_read", "mhd_ens_last_error", "mhd_ens_version",
     "mhd_ens_adjoint_terminal", "mhd_ens_adjoint_step", "mhd_ens_adjoint_ic",
+    "mhd_ens_group_create", "mhd_ens_group_step", "mhd_ens_group_free",
 )
 
 
@@ -56,7 +57,7 @@ class CSRView(C.Structure):
 class SolverOpts(C.Structure):
     _fields_ = [("precision", C.c_int), ("rtol", C.c_double), ("inner_rtol", C.c_double), ("maxit", C.c_int),
                 ("restart", C.c_int), ("jacobi_sweeps", C.c_int), ("check_every", C.c_int),
-                ("cgs_passes", C.c_int)]
+                ("cgs_passes", C.c_int), ("fixed_cycles", C.c_int)]
 
 
 class SolveStats(C.Structure):
@@ -64,7 +65,8 @@ class SolveStats(C.Structure):
 
 
 class CtxDesc(C.Structure):
-    _fields_ = [("coeffs", Coeffs), ("solver", SolverOpts), ("J_max", C.c_int), ("adjoint", C.c_int)]
+    _fields_ = [("coeffs", Coeffs), ("solver", SolverOpts), ("J_max", C.c_int), ("adjoint", C.c_int),
+                ("graph", C.c_int)]
 
 
 class AdjointInputs(C.Structure):
@@ -112,6 +114,10 @@ def lib():
             "mhd_ens_adjoint_step": [P, P, P, P, P, P, P, P, P, C.POINTER(AdjointInputs), P,
                                      C.POINTER(StepStats), P],
             "mhd_ens_adjoint_ic": [P, P, P, P, I, C.c_double, P, I, P],
+            "mhd_ens_group_create": [I, C.POINTER(P), C.POINTER(P)],
+            "mhd_ens_group_step": [P, C.POINTER(P), C.POINTER(P), C.POINTER(P), C.POINTER(P),
+                                   C.POINTER(StepInputs), P],
+            "mhd_ens_group_free": [P],
             "mhd_ens_timer_read": [C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                    C.POINTER(C.c_double)],
         }
@@ -272,10 +278,30 @@ def mhd_ens_adjoint_ic(ctx, lamV0, lamW0, modes, nm, s_coupling, grad_ic, J, str
                                    stream_ptr(stream)))
 
 
+def mhd_ens_group_create(ctxs):
+    arr = (C.c_void_p * len(ctxs))(*[c.value if isinstance(c, C.c_void_p) else c for c in ctxs])
+    h = C.c_void_p()
+    check("mhd_ens_group_create", lib().mhd_ens_group_create(len(ctxs), arr, C.byref(h)))
+    return h
+
+
+def mhd_ens_group_step(group, Vs, Ws, Qs, Rs, inputs, stream=None):
+    n = len(Vs)
+    mk = lambda ts: (C.c_void_p * n)(*[t.data_ptr() for t in ts])
+    ins = (StepInputs * n)(*inputs)
+    check("mhd_ens_group_step", lib().mhd_ens_group_step(group, mk(Vs), mk(Ws), mk(Qs), mk(Rs), ins,
+                                                         stream_ptr(stream)))
+
+
+def mhd_ens_group_free(group):
+    check("mhd_ens_group_free", lib().mhd_ens_group_free(group))
+
+
 def solver_opts(precision=MHD_FP64, rtol=None, inner_rtol=None, maxit=2000, restart=30, jacobi_sweeps=6,
-                check_every=1, cgs_passes=0):
+                check_every=1, cgs_passes=0, fixed_cycles=0):
     if rtol is None:
         rtol = 1e-12 if precision == MHD_FP64 else 1e-11
     if inner_rtol is None:
         inner_rtol = 1e-8 if precision == MHD_FP64 else 1e-4
-    return SolverOpts(precision, rtol, inner_rtol, maxit, restart, jacobi_sweeps, check_every, cgs_passes)
+    return SolverOpts(precision, rtol, inner_rtol, maxit, restart, jacobi_sweeps, check_every, cgs_passes,
+                      fixed_cycles)

@@ -16,7 +16,47 @@ struct mhd_mesh_s {
 struct mhd_shared_s {
     mhd::DevShared d;
 };
+namespace mhd {
+struct StepArgs {
+    double *V, *W, *Q, *R;
+    const double *f1, *f2, *gv, *gw;
+    int J;
+    bool operator==(const StepArgs& o) const {
+        return V == o.V && W == o.W && Q == o.Q && R == o.R && f1 == o.f1 && f2 == o.f2 && gv == o.gv &&
+               gw == o.gw && J == o.J;
+    }
+};
+
+struct StepGraph {
+    bool valid = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t stream = nullptr;
+    StepArgs key{};
+    mhd_solve_stats sv{}, sw{};
+    void reset() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+        valid = false;
+    }
+};
+}  // namespace mhd
+
+struct mhd_group_s {
+    std::vector<mhd_ctx> ctxs;
+    std::vector<hipStream_t> streams;
+    std::vector<hipEvent_t> done;
+    hipEvent_t fork = nullptr;
+    mhd::StepGraph graph;
+    std::vector<mhd::StepArgs> keys;
+};
+
 struct mhd_ctx_s {
+    mhd::StepGraph graph;
+    mhd_coeffs graph_coeffs{};
+    std::vector<double> last_coef;          // member coefficients currently on the device
     mhd_mesh mesh = nullptr;
     mhd_shared Av = nullptr, Aw = nullptr;
     mhd_ctx_desc desc{};
@@ -291,6 +331,115 @@ mhd_status check_solver_opts(const mhd_solver_opts* o) {
     CHECK_ARG(o->restart >= 1 && o->restart <= kMaxRestart, "restart must be in [1, 40]");
     CHECK_ARG(o->jacobi_sweeps >= 1 && o->jacobi_sweeps <= 16, "jacobi_sweeps must be in [1, 16]");
     CHECK_ARG(o->cgs_passes >= 0 && o->cgs_passes <= 2, "cgs_passes must be 0, 1 or 2");
+    CHECK_ARG(o->fixed_cycles >= 0 && o->fixed_cycles <= 64, "fixed_cycles must be in [0, 64]");
+    return MHD_OK;
+}
+
+// host part of a step: mean viscosities, member coefficients (uploaded when they
+// change), Schur-hierarchy refresh; no device work is left pending on the
+// pinned staging buffer when it is rewritten
+mhd_status step_prepare(mhd_ctx ctx, const mhd_step_inputs* in, mhd_coeffs& c, hipStream_t st) {
+    CHECK_ARG(in->nu && in->nu_m, "mhd_ens_step: null nu / nu_m");
+    const int J = in->J;
+    if (J < 1 || J > ctx->desc.J_max) {
+        set_error("mhd_ens_step: J outside [1, J_max]");
+        return MHD_ESHAPE;
+    }
+    DevMesh& D = ctx->mesh->d;
+    CHECK_ARG((in->g_v && in->g_w) || D.n_dir == 0, "mhd_ens_step: null Dirichlet data");
+    double nub = 0, numb = 0;
+    for (int j = 0; j < J; ++j) {
+        CHECK_ARG(std::isfinite(in->nu[j]) && std::isfinite(in->nu_m[j]), "mhd_ens_step: non-finite nu");
+        nub += in->nu[j];
+        numb += in->nu_m[j];
+    }
+    nub /= J;
+    numb /= J;
+    std::vector<double> cf(2 * (size_t)J);
+    for (int j = 0; j < J; ++j) {
+        cf[j] = 0.5 * (in->nu[j] - in->nu_m[j]);
+        cf[J + j] = 0.5 * ((in->nu[j] - nub) + (in->nu_m[j] - numb));
+    }
+    if (cf != ctx->last_coef) {
+        MHD_HIP(hipStreamSynchronize(st));
+        std::copy(cf.begin(), cf.end(), ctx->host_coef);
+        MHD_HIP(hipMemcpyAsync(ctx->coef, ctx->host_coef, sizeof(double) * 2 * J, hipMemcpyHostToDevice, st));
+        ctx->last_coef = cf;
+    }
+    c = ctx->desc.coeffs;
+    c.nu_bar = nub;
+    c.num_bar = numb;
+    if (ctx->desc.graph && ctx->graph.valid) {
+        const mhd_coeffs& g = ctx->graph_coeffs;
+        if (g.dt != c.dt || g.nu_bar != c.nu_bar || g.num_bar != c.num_bar || g.mu != c.mu) ctx->graph.reset();
+    }
+    ctx->graph_coeffs = c;
+    return refresh_schur(D, c.dt, 0.5 * (c.nu_bar + c.num_bar));
+}
+
+// device part of a step (a1-a6): capturable into a graph when the solver runs a fixed schedule
+mhd_status step_device(mhd_ctx ctx, const mhd_coeffs& c, const StepArgs& a, hipStream_t stv, mhd_solve_stats* sv,
+                       mhd_solve_stats* sw) {
+    DevMesh& D = ctx->mesh->d;
+    DevShared& Av = ctx->Av->d;
+    DevShared& Aw = ctx->Aw->d;
+    const int J = a.J;
+    mhd_status rc;
+    // v-problem convected by <w>, w-problem by <v>; both from time level n
+    if ((rc = assemble_shared_impl(D, c, a.W, J, Av, stv))) return rc;
+    if ((rc = assemble_shared_impl(D, c, a.V, J, Aw, stv))) return rc;
+    hipError_t e = launch_rhs(D, c, J, a.V, a.W, Av.zbar, ctx->coef, a.f1, a.gv, ctx->bv, stv);
+    if (e == hipSuccess) e = launch_rhs(D, c, J, a.W, a.V, Aw.zbar, ctx->coef, a.f2, a.gw, ctx->bw, stv);
+    if (e != hipSuccess) {
+        set_error(std::string("mhd_ens_step rhs: ") + hipGetErrorString(e));
+        return MHD_EHIP;
+    }
+    const size_t vel = sizeof(double) * 2 * (size_t)D.nP2 * J;
+    const size_t prs = sizeof(double) * (size_t)D.nP1 * J;
+    const int64_t poff = 2 * (int64_t)D.nP2 * J;
+    MHD_HIP(hipMemcpyAsync(ctx->Xv, a.V, vel, hipMemcpyDeviceToDevice, stv));
+    MHD_HIP(hipMemcpyAsync(ctx->Xv + poff, a.Q, prs, hipMemcpyDeviceToDevice, stv));
+    MHD_HIP(hipMemcpyAsync(ctx->Xw, a.W, vel, hipMemcpyDeviceToDevice, stv));
+    MHD_HIP(hipMemcpyAsync(ctx->Xw + poff, a.R, prs, hipMemcpyDeviceToDevice, stv));
+    mhd_status rv = solve_shared(Av, ctx->bv, ctx->Xv, J, ctx->desc.solver, sv, stv);
+    if (rv != MHD_OK && rv != MHD_ENOCONV) return rv;
+    mhd_status rw = solve_shared(Aw, ctx->bw, ctx->Xw, J, ctx->desc.solver, sw, stv);
+    if (rw != MHD_OK && rw != MHD_ENOCONV) return rw;
+    MHD_HIP(hipMemcpyAsync(a.V, ctx->Xv, vel, hipMemcpyDeviceToDevice, stv));
+    MHD_HIP(hipMemcpyAsync(a.Q, ctx->Xv + poff, prs, hipMemcpyDeviceToDevice, stv));
+    MHD_HIP(hipMemcpyAsync(a.W, ctx->Xw, vel, hipMemcpyDeviceToDevice, stv));
+    MHD_HIP(hipMemcpyAsync(a.R, ctx->Xw + poff, prs, hipMemcpyDeviceToDevice, stv));
+    if (D.pin >= 0) {
+        e = launch_pressure_zero_mean(D, a.Q, J, ctx->partial, stv);
+        if (e == hipSuccess) e = launch_pressure_zero_mean(D, a.R, J, ctx->partial, stv);
+        if (e != hipSuccess) {
+            set_error(std::string("pressure normalisation: ") + hipGetErrorString(e));
+            return MHD_EHIP;
+        }
+    }
+    return (rv == MHD_ENOCONV || rw == MHD_ENOCONV) ? MHD_ENOCONV : MHD_OK;
+}
+
+// E = (||<v>||^2 + ||<w>||^2)/2 with the P2 mass matrix (synchronises)
+mhd_status step_energy(mhd_ctx ctx, const StepArgs& a, hipStream_t stv, double* energy) {
+    DevMesh& D = ctx->mesh->d;
+    double* zb = ctx->Av->d.zbar;
+    double E = 0.0;
+    int nblk = (D.nP2 + 255) / 256;
+    std::vector<double> hp(nblk);
+    for (int var = 0; var < 2; ++var) {
+        hipError_t e = launch_mean(var == 0 ? a.V : a.W, zb, 2 * (int64_t)D.nP2, a.J, stv);
+        if (e == hipSuccess) e = launch_energy_partial(D, zb, ctx->partial, stv);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(hp.data(), ctx->partial, sizeof(double) * nblk, hipMemcpyDeviceToHost, stv);
+        if (e == hipSuccess) e = hipStreamSynchronize(stv);
+        if (e != hipSuccess) {
+            set_error(std::string("energy: ") + hipGetErrorString(e));
+            return MHD_EHIP;
+        }
+        for (double v : hp) E += v;
+    }
+    *energy = 0.5 * E;
     return MHD_OK;
 }
 
@@ -475,6 +624,8 @@ mhd_status mhd_ens_ctx_create(mhd_mesh m, const mhd_ctx_desc* d, mhd_ctx* out) {
     if (rc) return rc;
     if ((rc = check_solver_opts(&d->solver))) return rc;
     CHECK_ARG(d->J_max >= 1 && d->J_max <= kMaxJ, "mhd_ens_ctx_create: J_max must be in [1, 4096]");
+    CHECK_ARG(!d->graph || d->solver.fixed_cycles > 0,
+              "mhd_ens_ctx_create: graph mode needs a fixed solver schedule (fixed_cycles > 0)");
     mhd_ctx c = new (std::nothrow) mhd_ctx_s;
     if (!c) return MHD_ENOMEM;
     c->mesh = m;
@@ -521,6 +672,7 @@ mhd_status mhd_ens_ctx_create(mhd_mesh m, const mhd_ctx_desc* d, mhd_ctx* out) {
 
 mhd_status mhd_ens_ctx_free(mhd_ctx c) {
     if (!c) return MHD_OK;
+    c->graph.reset();
     mhd_ens_shared_free(c->Av);
     mhd_ens_shared_free(c->Aw);
     free_list(c->allocs);
@@ -533,93 +685,155 @@ mhd_status mhd_ens_step(mhd_ctx ctx, double* V, double* W, double* Q, double* R,
                         mhd_step_stats* st, mhd_stream_t s) {
     CHECK_ARG(ctx && in, "mhd_ens_step: null argument");
     CHECK_ARG(V && W && Q && R, "mhd_ens_step: null state array");
-    CHECK_ARG(in->nu && in->nu_m, "mhd_ens_step: null nu / nu_m");
-    const int J = in->J;
-    if (J < 1 || J > ctx->desc.J_max) {
-        set_error("mhd_ens_step: J outside [1, J_max]");
-        return MHD_ESHAPE;
-    }
-    DevMesh& D = ctx->mesh->d;
-    CHECK_ARG((in->g_v && in->g_w) || D.n_dir == 0, "mhd_ens_step: null Dirichlet data");
     hipStream_t stv = as_stream(s);
-    // mean viscosities and member coefficients (host, FP64)
-    double nub = 0, numb = 0;
-    for (int j = 0; j < J; ++j) {
-        CHECK_ARG(std::isfinite(in->nu[j]) && std::isfinite(in->nu_m[j]), "mhd_ens_step: non-finite nu");
-        nub += in->nu[j];
-        numb += in->nu_m[j];
-    }
-    nub /= J;
-    numb /= J;
-    for (int j = 0; j < J; ++j) {
-        ctx->host_coef[j] = 0.5 * (in->nu[j] - in->nu_m[j]);
-        ctx->host_coef[J + j] = 0.5 * ((in->nu[j] - nub) + (in->nu_m[j] - numb));
-    }
-    MHD_HIP(hipMemcpyAsync(ctx->coef, ctx->host_coef, sizeof(double) * 2 * J, hipMemcpyHostToDevice, stv));
-    mhd_coeffs c = ctx->desc.coeffs;
-    c.nu_bar = nub;
-    c.num_bar = numb;
-    DevShared& Av = ctx->Av->d;
-    DevShared& Aw = ctx->Aw->d;
-    mhd_status rc;
-    // v-problem convected by <w>, w-problem by <v>; both from time level n
-    if ((rc = assemble_shared_impl(D, c, W, J, Av, stv))) return rc;
-    if ((rc = assemble_shared_impl(D, c, V, J, Aw, stv))) return rc;
-    hipError_t e = launch_rhs(D, c, J, V, W, Av.zbar, ctx->coef, in->f1, in->g_v, ctx->bv, stv);
-    if (e == hipSuccess) e = launch_rhs(D, c, J, W, V, Aw.zbar, ctx->coef, in->f2, in->g_w, ctx->bw, stv);
-    if (e != hipSuccess) {
-        set_error(std::string("mhd_ens_step rhs: ") + hipGetErrorString(e));
-        return MHD_EHIP;
-    }
-    const size_t vel = sizeof(double) * 2 * (size_t)D.nP2 * J;
-    const size_t prs = sizeof(double) * (size_t)D.nP1 * J;
-    const int64_t poff = 2 * (int64_t)D.nP2 * J;
-    MHD_HIP(hipMemcpyAsync(ctx->Xv, V, vel, hipMemcpyDeviceToDevice, stv));
-    MHD_HIP(hipMemcpyAsync(ctx->Xv + poff, Q, prs, hipMemcpyDeviceToDevice, stv));
-    MHD_HIP(hipMemcpyAsync(ctx->Xw, W, vel, hipMemcpyDeviceToDevice, stv));
-    MHD_HIP(hipMemcpyAsync(ctx->Xw + poff, R, prs, hipMemcpyDeviceToDevice, stv));
+    StepArgs a{V, W, Q, R, in->f1, in->f2, in->g_v, in->g_w, in->J};
+    mhd_coeffs c;
+    mhd_status rc = step_prepare(ctx, in, c, stv);
+    if (rc) return rc;
     mhd_solve_stats sv{}, sw{};
-    mhd_status rv = solve_shared(Av, ctx->bv, ctx->Xv, J, ctx->desc.solver, &sv, stv);
-    if (rv != MHD_OK && rv != MHD_ENOCONV) return rv;
-    mhd_status rw = solve_shared(Aw, ctx->bw, ctx->Xw, J, ctx->desc.solver, &sw, stv);
-    if (rw != MHD_OK && rw != MHD_ENOCONV) return rw;
-    MHD_HIP(hipMemcpyAsync(V, ctx->Xv, vel, hipMemcpyDeviceToDevice, stv));
-    MHD_HIP(hipMemcpyAsync(Q, ctx->Xv + poff, prs, hipMemcpyDeviceToDevice, stv));
-    MHD_HIP(hipMemcpyAsync(W, ctx->Xw, vel, hipMemcpyDeviceToDevice, stv));
-    MHD_HIP(hipMemcpyAsync(R, ctx->Xw + poff, prs, hipMemcpyDeviceToDevice, stv));
-    if (D.pin >= 0) {
-        e = launch_pressure_zero_mean(D, Q, J, ctx->partial, stv);
-        if (e == hipSuccess) e = launch_pressure_zero_mean(D, R, J, ctx->partial, stv);
-        if (e != hipSuccess) {
-            set_error(std::string("pressure normalisation: ") + hipGetErrorString(e));
-            return MHD_EHIP;
+    mhd_status rs = MHD_OK;
+    if (ctx->desc.graph) {
+        CHECK_ARG(stv != nullptr, "mhd_ens_step: graph mode needs a non-null stream");
+        if (!ctx->graph.valid || !(ctx->graph.key == a) || ctx->graph.stream != stv) {
+            ctx->graph.reset();
+            MHD_HIP(hipStreamBeginCapture(stv, hipStreamCaptureModeThreadLocal));
+            rs = step_device(ctx, c, a, stv, &sv, &sw);
+            hipGraph_t graph = nullptr;
+            hipError_t e = hipStreamEndCapture(stv, &graph);
+            if (rs != MHD_OK && rs != MHD_ENOCONV) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return rs;
+            }
+            if (e != hipSuccess) {
+                set_error(std::string("mhd_ens_step: graph capture failed: ") + hipGetErrorString(e));
+                return MHD_EHIP;
+            }
+            ctx->graph.graph = graph;
+            MHD_HIP(hipGraphInstantiate(&ctx->graph.exec, graph, nullptr, nullptr, 0));
+            ctx->graph.key = a;
+            ctx->graph.stream = stv;
+            ctx->graph.valid = true;
+            ctx->graph.sv = sv;
+            ctx->graph.sw = sw;
         }
+        MHD_HIP(hipGraphLaunch(ctx->graph.exec, stv));
+        sv = ctx->graph.sv;
+        sw = ctx->graph.sw;
+    } else {
+        rs = step_device(ctx, c, a, stv, &sv, &sw);
+        if (rs != MHD_OK && rs != MHD_ENOCONV) return rs;
     }
     if (st) {
         st->v = sv;
         st->w = sw;
-        // E = (||<v>||^2 + ||<w>||^2)/2 with the P2 mass matrix
-        double E = 0.0;
-        int nblk = (D.nP2 + 255) / 256;
-        std::vector<double> hp(nblk);
-        for (int var = 0; var < 2; ++var) {
-            e = launch_mean(var == 0 ? V : W, Av.zbar, 2 * (int64_t)D.nP2, J, stv);
-            if (e == hipSuccess) e = launch_energy_partial(D, Av.zbar, ctx->partial, stv);
-            if (e == hipSuccess) e = hipMemcpyAsync(hp.data(), ctx->partial, sizeof(double) * nblk,
-                                                    hipMemcpyDeviceToHost, stv);
-            if (e == hipSuccess) e = hipStreamSynchronize(stv);
-            if (e != hipSuccess) {
-                set_error(std::string("energy: ") + hipGetErrorString(e));
-                return MHD_EHIP;
-            }
-            for (double v : hp) E += v;
-        }
-        st->energy = 0.5 * E;
+        if ((rc = step_energy(ctx, a, stv, &st->energy))) return rc;
     }
-    if (rv == MHD_ENOCONV || rw == MHD_ENOCONV) {
+    if (rs == MHD_ENOCONV) {
         set_error("mhd_ens_step: a subproblem solve hit maxit");
         return MHD_ENOCONV;
     }
+    return MHD_OK;
+}
+
+mhd_status mhd_ens_group_create(int n, const mhd_ctx* ctxs, mhd_group* out) {
+    CHECK_ARG(out, "mhd_ens_group_create: null output handle");
+    *out = nullptr;
+    CHECK_ARG(n >= 1 && n <= 64 && ctxs, "mhd_ens_group_create: need 1..64 contexts");
+    for (int i = 0; i < n; ++i) {
+        CHECK_ARG(ctxs[i], "mhd_ens_group_create: null context");
+        CHECK_ARG(ctxs[i]->desc.solver.fixed_cycles > 0,
+                  "mhd_ens_group_create: every context needs a fixed solver schedule (fixed_cycles > 0)");
+    }
+    mhd_group g = new (std::nothrow) mhd_group_s;
+    if (!g) return MHD_ENOMEM;
+    g->ctxs.assign(ctxs, ctxs + n);
+    g->streams.resize(n, nullptr);
+    g->done.resize(n, nullptr);
+    for (int i = 0; i < n; ++i) {
+        if (hipStreamCreateWithFlags(&g->streams[i], hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&g->done[i], hipEventDisableTiming) != hipSuccess) {
+            mhd_ens_group_free(g);
+            set_error("mhd_ens_group_create: stream/event creation failed");
+            return MHD_EHIP;
+        }
+    }
+    if (hipEventCreateWithFlags(&g->fork, hipEventDisableTiming) != hipSuccess) {
+        mhd_ens_group_free(g);
+        set_error("mhd_ens_group_create: event creation failed");
+        return MHD_EHIP;
+    }
+    *out = g;
+    return MHD_OK;
+}
+
+mhd_status mhd_ens_group_free(mhd_group g) {
+    if (!g) return MHD_OK;
+    g->graph.reset();
+    for (auto s : g->streams)
+        if (s) (void)hipStreamDestroy(s);
+    for (auto e : g->done)
+        if (e) (void)hipEventDestroy(e);
+    if (g->fork) (void)hipEventDestroy(g->fork);
+    delete g;
+    return MHD_OK;
+}
+
+mhd_status mhd_ens_group_step(mhd_group g, double* const* V, double* const* W, double* const* Q, double* const* R,
+                              const mhd_step_inputs* in, mhd_stream_t s) {
+    CHECK_ARG(g && V && W && Q && R && in, "mhd_ens_group_step: null argument");
+    hipStream_t st = as_stream(s);
+    CHECK_ARG(st != nullptr, "mhd_ens_group_step: needs a non-null stream (graph capture)");
+    const int n = (int)g->ctxs.size();
+    std::vector<StepArgs> args(n);
+    std::vector<mhd_coeffs> cs(n);
+    for (int i = 0; i < n; ++i) {
+        CHECK_ARG(V[i] && W[i] && Q[i] && R[i], "mhd_ens_group_step: null state array");
+        args[i] = StepArgs{V[i], W[i], Q[i], R[i], in[i].f1, in[i].f2, in[i].g_v, in[i].g_w, in[i].J};
+        mhd_status rc = step_prepare(g->ctxs[i], &in[i], cs[i], st);
+        if (rc) return rc;
+    }
+    // contexts on one mesh share its Schur-approximation hierarchy, so they must share its coefficients
+    for (int i = 0; i < n; ++i)
+        for (int k = i + 1; k < n; ++k)
+            if (g->ctxs[i]->mesh == g->ctxs[k]->mesh &&
+                (cs[i].dt != cs[k].dt || cs[i].nu_bar + cs[i].num_bar != cs[k].nu_bar + cs[k].num_bar)) {
+                set_error("mhd_ens_group_step: contexts on one mesh need equal dt and nu_bar + num_bar");
+                return MHD_EINVAL;
+            }
+    bool same = g->graph.valid && g->graph.stream == st && g->keys.size() == (size_t)n;
+    for (int i = 0; same && i < n; ++i) same = g->keys[i] == args[i];
+    if (!same) {
+        g->graph.reset();
+        MHD_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        mhd_status rs = MHD_OK;
+        hipError_t e = hipEventRecord(g->fork, st);
+        for (int i = 0; i < n && rs == MHD_OK && e == hipSuccess; ++i) {
+            e = hipStreamWaitEvent(g->streams[i], g->fork, 0);
+            if (e != hipSuccess) break;
+            mhd_solve_stats sv, sw;
+            rs = step_device(g->ctxs[i], cs[i], args[i], g->streams[i], &sv, &sw);
+            if (rs == MHD_ENOCONV) rs = MHD_OK;
+            if (rs == MHD_OK) e = hipEventRecord(g->done[i], g->streams[i]);
+            if (rs == MHD_OK && e == hipSuccess) e = hipStreamWaitEvent(st, g->done[i], 0);
+        }
+        hipGraph_t graph = nullptr;
+        hipError_t e2 = hipStreamEndCapture(st, &graph);
+        if (rs != MHD_OK || e != hipSuccess || e2 != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            if (rs == MHD_OK) {
+                set_error(std::string("mhd_ens_group_step: capture failed: ") +
+                          hipGetErrorString(e != hipSuccess ? e : e2));
+                return MHD_EHIP;
+            }
+            return rs;
+        }
+        g->graph.graph = graph;
+        MHD_HIP(hipGraphInstantiate(&g->graph.exec, graph, nullptr, nullptr, 0));
+        g->graph.stream = st;
+        g->graph.valid = true;
+        g->keys = args;
+    }
+    MHD_HIP(hipGraphLaunch(g->graph.exec, st));
     return MHD_OK;
 }
 

@@ -790,6 +790,8 @@ hipError_t timer_fold() {
 // record the start (before = true) or the end of one timed launch on stream st
 void timer_mark(hipStream_t st, bool before) {
     if (!g_timer.on) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return;
     if (before && g_timer.used + 2 > g_timer.pool.size()) (void)timer_fold();
     if (g_timer.used < g_timer.pool.size()) (void)hipEventRecord(g_timer.pool[g_timer.used++], st);
 }
@@ -854,7 +856,8 @@ struct Ops {
             LAUNCH_CHECK();
         }
         if (rc) return rc;
-        if (g_timer.on) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (g_timer.on && hipStreamIsCapturing(st, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone) {
             timer_mark(st, false);
             g_timer.launches++;
             (sizeof(T) == 4 ? g_timer.nJ32 : g_timer.nJ64) += (double)J;
@@ -1012,17 +1015,22 @@ mhd_status gmres_solve(DevShared& S, const double* b, double* x, int J, const mh
     double* hcol2 = G.hcol + (int64_t)(kMaxRestart + 1) * J;
     double* hn = G.res + J;
     mhd_status rc;
-    if ((rc = ops.colnorm(b, G.bnorm))) return rc;
-    if ((rc = sync_copy(hbn, G.bnorm, J, st))) return rc;
+    // fixed schedule: fixed_cycles refinement cycles of mres inner iterations,
+    // no host synchronisation (graph-capturable)
+    const bool fixed = o.fixed_cycles > 0;
+    if (!fixed) {
+        if ((rc = ops.colnorm(b, G.bnorm))) return rc;
+        if ((rc = sync_copy(hbn, G.bnorm, J, st))) return rc;
+    }
     int iters = 0, cycles = 0;
     double maxrel = 0.0;
     bool conv = false;
-    const int JPr = pick_jp(J);
     while (true) {
         // FP64 residual r = b - S x and its column norms
-        (void)JPr;
+        if (fixed && cycles >= o.fixed_cycles) break;
         if ((rc = saddle_residual64(S, b, x, G.r64, J, st))) return rc;
         if ((rc = ops.colnorm(G.r64, G.beta))) return rc;
+        if (!fixed) {
         if ((rc = sync_copy(hbeta, G.beta, J, st))) return rc;
         maxrel = 0.0;
         bool bad = false;
@@ -1041,6 +1049,7 @@ mhd_status gmres_solve(DevShared& S, const double* b, double* x, int J, const mh
             break;
         }
         if (iters >= o.maxit) break;
+        }
         // v0 = r / beta in the inner precision; g = beta e1
         hipLaunchKernelGGL((k_scale_cols<double, T>), dim3(ew_grid(n * J)), dim3(kBlock), 0, st, (const double*)G.r64,
                            G.beta, 1, basis_ptr<T>(S, 0), n, J);
@@ -1048,7 +1057,7 @@ mhd_status gmres_solve(DevShared& S, const double* b, double* x, int J, const mh
         hipLaunchKernelGGL(k_init_g, dim3((J + 255) / 256), dim3(256), 0, st, G.g, G.beta, mres + 1, J);
         LAUNCH_CHECK();
         int kd = 0;
-        for (int k = 0; k < mres && iters < o.maxit; ++k) {
+        for (int k = 0; k < mres && (fixed || iters < o.maxit); ++k) {
             T* vk = basis_ptr<T>(S, k);
             T* z = (T*)G.zbuf;
             T* w = basis_ptr<T>(S, k + 1);
@@ -1094,7 +1103,7 @@ mhd_status gmres_solve(DevShared& S, const double* b, double* x, int J, const mh
             LAUNCH_CHECK();
             ++iters;
             kd = k + 1;
-            if (kd % check == 0 || kd == mres) {
+            if (!fixed && (kd % check == 0 || kd == mres)) {
                 if ((rc = sync_copy(hres, G.res, J, st))) return rc;
                 bool done = true;
                 for (int j = 0; j < J; ++j) {
@@ -1119,6 +1128,10 @@ mhd_status gmres_solve(DevShared& S, const double* b, double* x, int J, const mh
         hipLaunchKernelGGL((k_add_to64<T>), dim3(ew_grid(n * J)), dim3(kBlock), 0, st, x, (const T*)G.zbuf, n * J);
         LAUNCH_CHECK();
         ++cycles;
+    }
+    if (fixed) {
+        if (stt) *stt = {iters, cycles, -1.0, -1};
+        return MHD_OK;
     }
     if (stt) *stt = {iters, cycles, maxrel, conv ? 1 : 0};
     if (!conv) {

@@ -236,3 +236,37 @@ def test_single_step_cavity_128(L):
         say("  err", err)
         assert err <= tol, (prec, err)
     gm.close()
+
+
+def test_step_parity_step_channel_natural_outflow(L):
+    """Step channel [0,30]x[0,10] minus the unit inlet step, h = 1/2, do-nothing
+    outflow (no pressure pin), J = 3, two FP64 steps; pressures compared as is."""
+    from paper_2108_05110_amd.ensemble import Mesh, Stepper
+    say("step channel")
+    m = 2
+    pb = wl.step_channel(J=3, delta=0.1, s=0.01, dt=0.02, nsteps=2)
+    gm = Mesh(L.MHD_MESH_STEP_CHANNEL, m, 1)
+    om_ = om.step_channel(m)
+    ens = scheme.Ensemble(om_, pb)
+    assert ens.pin is None and gm.info.pin == -1
+    h = 1.0 / m
+    pm2 = node_map(gm.xy, om_.xy, h)
+    pm1 = p1_map(gm.xy, om_, h)
+    assert len(gm.dir_nodes) == len(ens.dnodes)
+    stp = Stepper(gm, pb, opts=L.solver_opts(L.MHD_FP64))
+    V, W = pb.ic(om_.xy)
+    for n in range(2):
+        st = stp.step()
+        V, W, Q, R = ens.step(V, W, (n + 1) * pb.dt, shared_lu=True)
+        Vg = np.zeros_like(V)
+        Vg[pm2] = stp.V.cpu().numpy()
+        Wg = np.zeros_like(W)
+        Wg[pm2] = stp.W.cpu().numpy()
+        ev, ew = mass_rel_err(ens, Vg, V), mass_rel_err(ens, Wg, W)
+        say("  step", n + 1, ev, ew, st.v.iters, st.w.iters)
+        assert max(ev, ew) <= 1e-10
+    qg = np.zeros_like(Q)
+    qg[pm1] = stp.Q.cpu().numpy()
+    assert np.abs(qg - Q).max() <= 1e-8 * np.abs(Q).max()
+    stp.close()
+    gm.close()
