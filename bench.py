@@ -92,8 +92,10 @@ def cpu_baseline(N, J, seconds_hint=30.0):
 
 
 class Separate:
-    """J-separate form on the same GPU: shared matrices and right-hand sides as in
-    the ensemble step, then every member solved by its own single-column solve."""
+    """J-separate form on the same GPU: the same shared matrices and right-hand
+    sides as the ensemble step, then every member solved by its own
+    single-column solve with the same solver schedule; the whole step is
+    captured in a graph and replayed, like the ensemble step."""
 
     def __init__(self, L, mesh, stp, opts):
         import torch
@@ -106,31 +108,43 @@ class Separate:
         self.bw = torch.zeros_like(self.bv)
         self.nu = torch.from_numpy(stp.nu).cuda()
         self.nu_m = torch.from_numpy(stp.nu_m).cuda()
-        self.iters = 0
+        self.graph = None
 
-    def step(self):
+    def _body(self):
         import torch
         L, m, s = self.L, self.mesh, self.stp
         J = s.J
-        s.set_data((s.n + 1) * s.pb.dt)
         c = L.Coeffs(s.pb.dt, s.pb.mu, float(s.nu.mean()), float(s.nu_m.mean()), int(s.pb.convective))
         L.mhd_ens_assemble_shared(m.handle, c, s.W, J, self.Av)
         L.mhd_ens_assemble_shared(m.handle, c, s.V, J, self.Aw)
         L.mhd_ens_assemble_rhs(m.handle, c, L.MHD_V_PROBLEM, J, s.V, s.W, self.nu, self.nu_m, s.f1, s.gv, self.bv)
         L.mhd_ens_assemble_rhs(m.handle, c, L.MHD_W_PROBLEM, J, s.W, s.V, self.nu, self.nu_m, s.f2, s.gw, self.bw)
         nvel = 2 * m.nP2
-        newV = torch.empty_like(s.V)
-        newW = torch.empty_like(s.W)
-        for A, b, Z, P, out in ((self.Av, self.bv, s.V, s.Q, newV), (self.Aw, self.bw, s.W, s.R, newW)):
+        for A, b, Z, P in ((self.Av, self.bv, s.V, s.Q), (self.Aw, self.bw, s.W, s.R)):
+            xs = []
             for j in range(J):
                 b1 = b[:, j].contiguous()
                 x1 = torch.cat([Z[:, :, j].reshape(-1), P[:, j]])
-                st, _ = L.mhd_ens_solve(A, b1, x1, 1, self.opts, allow_noconv=True)
-                self.iters += st.iters
-                out[:, :, j] = x1[:nvel].view(m.nP2, 2)
-                P[:, j] = x1[nvel:]
-        s.V.copy_(newV)
-        s.W.copy_(newW)
+                L.mhd_ens_solve(A, b1, x1, 1, self.opts, allow_noconv=True)
+                xs.append(x1)
+            X = torch.stack(xs, 1)
+            Z.copy_(X[:nvel].view(m.nP2, 2, J))
+            P.copy_(X[nvel:])
+
+    def step(self):
+        import torch
+        s = self.stp
+        s.set_data((s.n + 1) * s.pb.dt)
+        if self.opts.fixed_cycles > 0:
+            if self.graph is None:
+                self._body()                     # warm-up outside the capture
+                torch.cuda.synchronize()
+                self.graph = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(self.graph):
+                    self._body()
+            self.graph.replay()
+        else:
+            self._body()
         s.n += 1
 
     def close(self):
@@ -138,77 +152,86 @@ class Separate:
         self.L.mhd_ens_shared_free(self.Aw)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--N", type=int, default=128)
-    ap.add_argument("--J", type=int, default=64)
-    ap.add_argument("--precision", choices=["fp32ir", "fp64"], default="fp32ir")
-    ap.add_argument("--separate-steps", type=int, default=1)
-    ap.add_argument("--no-separate", action="store_true")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "member sharding over several GPUs is a design note, not implemented.", file=sys.stderr)
-        sys.exit(2)
-    rank = int(os.environ.get("RANK", "0"))
-
-    import numpy as np
+def step_accuracy(L, mesh, pb, opts):
+    """Relative L2 difference of one step with `opts` against an FP64 solve to
+    1e-12 from the same state (after a few steps of flow development)."""
     import torch
-    import workloads as wl
-    from paper_2108_05110_amd import _lib as L
-    from paper_2108_05110_amd.ensemble import Mesh, Stepper
+    from paper_2108_05110_amd.ensemble import Stepper
+    a = Stepper(mesh, pb, opts=opts, time_dependent_data=False, graph=opts.fixed_cycles > 0)
+    for _ in range(3):
+        a.step(stats=False)
+    b = Stepper(mesh, pb, opts=L.solver_opts(L.MHD_FP64), time_dependent_data=False)
+    for t_src, t_dst in ((a.V, b.V), (a.W, b.W), (a.Q, b.Q), (a.R, b.R)):
+        t_dst.copy_(t_src)
+    b.n = a.n
+    a.step(stats=False)
+    b.step(stats=False)
+    rel = lambda x, y: float(torch.linalg.norm(x - y) / torch.linalg.norm(y))
+    out = max(rel(a.V, b.V), rel(a.W, b.W))
+    a.close()
+    b.close()
+    return out
 
-    torch.cuda.init()
-    prec = L.MHD_FP32_IR if args.precision == "fp32ir" else L.MHD_FP64
-    opts = L.solver_opts(prec)
-    pb = wl.cavity(J=args.J, s=0.1, dt=0.01)
-    mesh = Mesh(L.MHD_MESH_UNIT_SQUARE, args.N)
-    stp = Stepper(mesh, pb, opts=opts, time_dependent_data=False)
-    for _ in range(args.warmup):
-        stp.step(stats=False)
-    L.mhd_ens_timer_enable(True)
+
+def timed_steps(stp, steps):
+    import torch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    iters = 0
-    for _ in range(args.steps):
-        st = stp.step(stats=True)
-        iters += st.v.iters + st.w.iters
+    for _ in range(steps):
+        stp.step(stats=False)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms, launches, nJ32, nJ64 = L.mhd_ens_timer_read()
-    L.mhd_ens_timer_enable(False)
-    elapsed = t1 - t0
+    return time.perf_counter() - t0
+
+
+def headline(args, L, wl, torch):
+    from paper_2108_05110_amd.ensemble import Mesh, Stepper
+    prec = L.MHD_FP32_IR if args.precision == "fp32ir" else L.MHD_FP64
+    if args.schedule == "fixed":
+        opts = L.solver_opts(prec, restart=args.restart, fixed_cycles=args.cycles, jacobi_sweeps=args.sweeps)
+    else:
+        opts = L.solver_opts(prec, rtol=args.rtol, jacobi_sweeps=args.sweeps)
+    graph = args.schedule == "fixed"
+    pb = wl.cavity(J=args.J, s=0.1, dt=0.01)
+    mesh = Mesh(L.MHD_MESH_UNIT_SQUARE, args.N)
+    # timed region: the graph-captured step (fixed schedule) or the adaptive step
+    stp = Stepper(mesh, pb, opts=opts, time_dependent_data=False, graph=graph)
+    for _ in range(args.warmup):
+        stp.step(stats=False)
+    elapsed = timed_steps(stp, args.steps)
     value = args.J * args.steps / elapsed
+    stp.close()
+    # the same schedule eager, with HIP events around every SpMM launch
+    eag = Stepper(mesh, pb, opts=opts, time_dependent_data=False)
+    eag.step(stats=False)
+    L.mhd_ens_timer_enable(True)
+    e_elapsed = timed_steps(eag, max(2, args.steps // 2))
+    ms, launches, _, _ = L.mhd_ens_timer_read()
+    L.mhd_ens_timer_enable(False)
+    st = eag.step(stats=True)
+    iters = st.v.iters + st.w.iters
+    eag.close()
     word = 4 if prec == L.MHD_FP32_IR else 8
     bpl = spmm_bytes(mesh.info, args.J, word)
     avg_s = (ms / 1e3) / max(launches, 1)
     achieved = bpl / avg_s / 1e9 if launches else None
-    traffic = traffic_from_profiles(args.J, args.N)
-
+    acc = step_accuracy(L, mesh, pb, opts)
     separate = None
     if not args.no_separate:
-        sp = Separate(L, mesh, stp, opts)
-        sp.step()                       # warm-up
+        sstp = Stepper(mesh, pb, opts=opts, time_dependent_data=False)
+        sp = Separate(L, mesh, sstp, opts)
+        sp.step()                       # warm-up (and capture)
         torch.cuda.synchronize()
         s0 = time.perf_counter()
         for _ in range(args.separate_steps):
             sp.step()
         torch.cuda.synchronize()
-        s1 = time.perf_counter()
-        sv = args.J * args.separate_steps / (s1 - s0)
+        sv = args.J * args.separate_steps / (time.perf_counter() - s0)
         separate = {"value": sv, "unit": "member-steps/s", "steps": args.separate_steps,
-                    "form": "same shared matrices, J single-column solves per subproblem",
+                    "form": "same shared matrices and schedule, J single-column solves per subproblem, "
+                            + ("graph-captured" if graph else "eager"),
                     "shared_over_separate": value / sv}
         sp.close()
-
-    cpu = None
-    if rank == 0 and not args.no_cpu_baseline:
-        cpu = cpu_baseline(args.N, args.J)
-
+        sstp.close()
     out = {
         "metric": "member-steps/s at 128^2 P2-P1, J=64 (shared vs J-separate); SpMM HBM GB/s",
         "value": value,
@@ -225,21 +248,163 @@ def main():
         "config": {"workload": f"lid-driven cavity, unit square {args.N}x{args.N} cells, Taylor-Hood P2-P1, "
                                f"J={args.J} members, s=0.1, dt=0.01, Re=1000 (nu, nu_m +-10% uniform)",
                    "n_unknowns": int(mesh.n), "J": args.J,
-                   "precision": "FP32 inner GMRES + FP64 refinement" if prec == L.MHD_FP32_IR else "FP64",
-                   "krylov_iterations_per_step": iters / args.steps},
-        "roofline": {"bound": "hbm", "kernel": "saddle-point SpMM (k_saddle)",
+                   "precision": ("FP32 inner GMRES + FP64 refinement" if prec == L.MHD_FP32_IR else "FP64"),
+                   "schedule": (f"hipGraph step, fixed {args.cycles} refinement cycles x {args.restart} GMRES "
+                                f"iterations, {args.sweeps} Jacobi sweeps" if graph else
+                                f"adaptive, rtol {args.rtol:g}, {args.sweeps} Jacobi sweeps"),
+                   "krylov_iterations_per_step": iters,
+                   "eager_member_steps_per_s": args.J * max(2, args.steps // 2) / e_elapsed,
+                   "step_rel_l2_vs_fp64": acc},
+        "roofline": {"bound": "hbm", "kernel": "saddle-point SpMM (k_saddle_v)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-                     "traffic": traffic, "bytes_per_launch": bpl, "avg_launch_us": avg_s * 1e6,
-                     "launches": launches},
+                     "traffic": traffic_from_profiles(args.J, args.N), "bytes_per_launch": bpl,
+                     "avg_launch_us": avg_s * 1e6, "launches": launches},
         "separate": separate,
-        "cpu_baseline": cpu,
+        "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline(args.N, args.J),
     }
+    mesh.close()
+    return out
+
+
+def adjoint_workload(args, L, wl, torch):
+    """128x128 cavity, J = 32, 50 FP64 steps, gradients of the final ensemble-mean
+    energy w.r.t. (nu, nu_m, forcing amplitude, 8 IC coefficients) of every
+    member, checkpoints every 10 steps; two entries checked by central
+    differences of the GPU forward map."""
+    import numpy as np
+    from oracle.adjoint import modes_and_forcing
+    from paper_2108_05110_amd.autograd import EnsembleEnergy, Rollout
+    from paper_2108_05110_amd.ensemble import Mesh
+    J, N, nsteps = 32, args.N, 50
+    pb = wl.cavity(J=J, s=0.1, dt=0.01, nsteps=nsteps, cfg=3)
+    r = wl.rng(3, 3)
+    a = r.uniform(0.5, 1.5, J)
+    params = torch.tensor(np.column_stack([pb.nu, pb.nu_m, a, pb.ic_coef]), dtype=torch.float64, device="cuda")
+    mesh = Mesh(L.MHD_MESH_UNIT_SQUARE, N)
+    modes, fhat = modes_and_forcing(mesh.xy)
+    ro = Rollout(mesh, pb, modes, fhat, opts=L.solver_opts(L.MHD_FP64), checkpoint_every=10)
+    p = params.clone().requires_grad_(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    phi = EnsembleEnergy.apply(p, ro)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    phi.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    g = p.grad.cpu().numpy()
+    checks = []
+    h = 1e-6
+    for (j, k) in ((0, 0), (5, 2), (9, 4)):
+        pp, pm = params.clone(), params.clone()
+        pp[j, k] += h
+        pm[j, k] -= h
+        fd = (ro.forward(pp, keep_checkpoints=False)[0] - ro.forward(pm, keep_checkpoints=False)[0]) / (2 * h)
+        checks.append({"member": j, "param": k, "adjoint": float(g[j, k]), "central_fd": fd,
+                       "rel_err": abs(g[j, k] - fd) / max(abs(fd), 1e-300)})
+    ro.close()
+    mesh.close()
+    return {"metric": "adjoint gradient wall time (forward + checkpointed reverse)", "value": t2 - t0,
+            "unit": "s", "higher_is_better": False, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"cavity {N}x{N} P2-P1, J={J}, {nsteps} steps dt=0.01, checkpoint every 10, "
+                                   f"objective E_h^M, 11 parameters per member"},
+            "forward_s": t1 - t0, "backward_s": t2 - t1, "phi": float(phi), "fd_checks": checks}
+
+
+def large_workload(args, L, wl, torch):
+    """512x512 cavity with J = 128 plus four 128x128 cavities with J = 16 (distinct
+    seeds, s in {0.01, 0.1, 1, 1}), all advanced by one graph launch per step."""
+    from paper_2108_05110_amd.ensemble import Mesh, Stepper
+    opts = L.solver_opts(L.MHD_FP32_IR, restart=args.restart, fixed_cycles=args.cycles, jacobi_sweeps=args.sweeps)
+    specs = [(512, wl.cavity(J=128, s=0.1, dt=0.01, cfg=4))]
+    for i, sc in enumerate((0.01, 0.1, 1.0, 1.0)):
+        specs.append((128, wl.cavity(J=16, s=sc, dt=0.01, cfg=10 + i)))
+    meshes, steppers = [], []
+    for N, pb in specs:
+        m = Mesh(L.MHD_MESH_UNIT_SQUARE, N)
+        meshes.append(m)
+        s = Stepper(m, pb, opts=opts, time_dependent_data=False)
+        s.set_data(pb.dt)
+        steppers.append(s)
+    grp = L.mhd_ens_group_create([s.ctx for s in steppers])
+    stream = torch.cuda.Stream()
+
+    def go():
+        L.mhd_ens_group_step(grp, [s.V for s in steppers], [s.W for s in steppers], [s.Q for s in steppers],
+                             [s.R for s in steppers], [s.inputs() for s in steppers], stream=stream)
+
+    go()
+    stream.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        go()
+    stream.synchronize()
+    el = time.perf_counter() - t0
+    total_members = sum(s.J for s in steppers)
+    # SpMM of the 512^2 ensemble alone, eager, with HIP events
+    big = Stepper(meshes[0], specs[0][1], opts=opts, time_dependent_data=False)
+    big.step(stats=False)
+    L.mhd_ens_timer_enable(True)
+    timed_steps(big, 1)
+    ms, launches, _, _ = L.mhd_ens_timer_read()
+    L.mhd_ens_timer_enable(False)
+    big.close()
+    bpl = spmm_bytes(meshes[0].info, 128, 4)
+    avg_s = (ms / 1e3) / max(launches, 1)
+    L.mhd_ens_group_free(grp)
+    for s in steppers:
+        s.close()
+    for m in meshes:
+        m.close()
+    ach = bpl / avg_s / 1e9
+    return {"metric": "member-steps/s, one graph launch per step over 5 ensembles", "value": total_members *
+            args.steps / el, "unit": "member-steps/s", "higher_is_better": True, "n_gpus": 1, "dtype": "f32",
+            "data": "synthetic", "steps": args.steps, "ms_per_step": 1e3 * el / args.steps,
+            "config": {"workload": "cavity 512x512 J=128 + 4 x cavity 128x128 J=16, FP32 inner + FP64 refinement, "
+                                   f"fixed {args.cycles}x{args.restart} schedule"},
+            "roofline": {"bound": "hbm", "kernel": "saddle-point SpMM at 512^2, J=128", "achieved": ach,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                         "bytes_per_launch": bpl, "avg_launch_us": avg_s * 1e6, "launches": launches}}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--N", type=int, default=128)
+    ap.add_argument("--J", type=int, default=64)
+    ap.add_argument("--precision", choices=["fp32ir", "fp64"], default="fp32ir")
+    ap.add_argument("--schedule", choices=["fixed", "adaptive"], default="fixed")
+    ap.add_argument("--restart", type=int, default=8)
+    ap.add_argument("--cycles", type=int, default=2)
+    ap.add_argument("--sweeps", type=int, default=6)
+    ap.add_argument("--rtol", type=float, default=1e-10)
+    ap.add_argument("--workload", choices=["cavity", "adjoint", "large"], default="cavity")
+    ap.add_argument("--separate-steps", type=int, default=1)
+    ap.add_argument("--no-separate", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "member sharding over several GPUs is a design note, not implemented.", file=sys.stderr)
+        sys.exit(2)
+    rank = int(os.environ.get("RANK", "0"))
+    import torch
+    import workloads as wl
+    from paper_2108_05110_amd import _lib as L
+    torch.cuda.init()
+    if args.workload == "adjoint":
+        out = adjoint_workload(args, L, wl, torch)
+    elif args.workload == "large":
+        out = large_workload(args, L, wl, torch)
+    else:
+        if rank != 0:
+            args.no_cpu_baseline = True
+        out = headline(args, L, wl, torch)
     if rank == 0:
         print(json.dumps(out), flush=True)
-    stp.close()
-    mesh.close()
-    _ = np
 
 
 if __name__ == "__main__":
