@@ -190,9 +190,10 @@ typedef struct {
 /* (Section 1: A [x_1|...|x_J] = [b_1|...|b_J]) Solves S X = B for the J
  * member columns with the assembled shared matrix: right-preconditioned
  * restarted GMRES with one Arnoldi process per member, one SpMM over all J
- * columns per iteration, block-triangular preconditioner (Jacobi sweeps on
- * A, Cahouet-Chabard Schur approximation with a multigrid V-cycle on the P1
- * pressure Laplacian).  rhs (n,J) FP64 device; x (n,J) FP64 device: initial
+ * columns per iteration, block-triangular preconditioner (damped Jacobi
+ * sweeps on A; Schur complement approximated by B D^-1 B^T, D the diagonal of
+ * M/dt + nu_c K, inverted by a Galerkin multigrid V-cycle on the nested P1
+ * grids).  rhs (n,J) FP64 device; x (n,J) FP64 device: initial
  * guess in, solution out.  st (host) may be NULL; if non-NULL the stream is
  * synchronised.  Returns MHD_ENOCONV (x = best iterate) if maxit is hit. */
 mhd_status mhd_ens_solve(mhd_shared A, const double* rhs, double* x, int J,
@@ -237,6 +238,69 @@ mhd_status mhd_ens_step(mhd_ctx ctx, double* V, double* W, double* Q, double* R,
  * performs once per iteration.  precision MHD_FP64: x, y double; MHD_FP32_IR:
  * x, y float with the FP32 shadow values.  x and y must not overlap. */
 mhd_status mhd_ens_spmm(mhd_shared A, const void* x, void* y, int J, int precision, mhd_stream_t s);
+
+/* Kernel autotuner for the node-row operators.  A solve of a given precision
+ * launches four such operators per Krylov iteration: the saddle-point SpMM,
+ * the first and the following velocity-block Jacobi sweeps of the
+ * preconditioner, and the FP64 residual r = b - S x.  For each one the tuner
+ * times every candidate launch shape on the handle's own workspace.  It keeps
+ * the fastest in a process-wide table keyed by (mesh, J, word size).
+ * mhd_ens_solve and mhd_ens_step tune missing entries on first use; under
+ * graph capture they use the table as it stands (or a default plan).  This
+ * call re-tunes unconditionally.  Candidates:
+ *   gather kernels (each wavefront reads its rows' node values from memory):
+ *     vec   = members per lane per load: 1, 2, 4 for FP32 and 1, 2 for FP64,
+ *             with J a multiple of 32 vec;
+ *     group = units (mesh nodes) per wavefront: 1, 2, 4 with batched gathers,
+ *             or 0 for one unit per wavefront with per-entry CSR loads;
+ *     deep  = 1: pipelined gathers (group 1, 2, 4 or 8): the next row's
+ *             entries load while the current row computes, and all of a
+ *             row's member loads are in flight at once (rows of at most 24
+ *             entries, B^T rows of at most 8);
+ *     deep  = 2: paired rows (group 4 or 8): the two halves of a wavefront
+ *             compute two rows at once with 16-byte member loads (J a
+ *             multiple of 64 for FP32, 32 for FP64; rows of at most 32
+ *             entries); vec is then 16 / word size;
+ *   LDS-staged kernels (J a multiple of 32; each workgroup first copies the
+ *   node values of a square tile of rows, and its halo, into LDS):
+ *     tile  = tile edge in half-steps of the mesh: 8, 12 or 16, where the
+ *             staged values fit the device's LDS per workgroup;
+ *     waves = wavefronts per workgroup: 4 or 8.
+ * Every candidate performs the same arithmetic in the same order, so results
+ * do not depend on the choice.
+ *   out:   host array of cap entries, or NULL; receives every timed candidate
+ *   count: host, or NULL; receives the number of entries written
+ * Synchronises the stream. */
+typedef struct {
+    int32_t op;               /* MHD_TUNE_*                                   */
+    int32_t word;             /* 4 (FP32) or 8 (FP64)                         */
+    int32_t J;
+    int32_t vec;              /* members per lane                             */
+    int32_t group;            /* gather kernels; 0 for LDS-staged entries     */
+    int32_t deep;
+    int32_t tile;             /* LDS-staged kernels; 0 for gather entries     */
+    int32_t waves;
+    float us;                 /* mean launch time in microseconds; -1 if the
+                                 device refused the launch shape              */
+    int32_t chosen;           /* 1 for the plan kept                          */
+} mhd_tune_entry;
+enum { MHD_TUNE_SADDLE = 0, MHD_TUNE_RESIDUAL = 1, MHD_TUNE_JACOBI_FIRST = 2, MHD_TUNE_JACOBI = 3 };
+mhd_status mhd_ens_autotune(mhd_shared A, int J, int precision, mhd_tune_entry* out, int cap, int* count,
+                            mhd_stream_t s);
+
+/* Pins the launch plan of one operator (MHD_TUNE_*) for this handle's mesh, J
+ * and precision (MHD_TUNE_RESIDUAL is always FP64), replacing the tuned one in
+ * the process-wide table, for example to benchmark one shape.
+ *   vec, group, deep: the gather kernels as in mhd_ens_autotune; vec = 0
+ *               selects the generic kernels (any J);
+ *   tile, waves: tile 0, or 8, 12, 16 with waves 4 or 8 for the LDS-staged
+ *               kernels (vec, group are then the fallback used where the
+ *               tiling is not available, e.g. an unaligned block).
+ * Graphs captured earlier keep the kernels they hold.  MHD_EINVAL for a shape
+ * this mesh, J or device does not admit.  Builds the tiling on first use
+ * (synchronous host-to-device copies). */
+mhd_status mhd_ens_set_plan(mhd_shared A, int J, int precision, int op, int vec, int group, int deep, int tile,
+                            int waves);
 
 /* Diagnostics: while enabled, every saddle-point SpMM launch of this library
  * (inside mhd_ens_solve / mhd_ens_step and mhd_ens_spmm) is bracketed by HIP

@@ -27,7 +27,20 @@ EXPORTS = (
     "mhd_ens_spmm", "mhd_ens_timer_enable", "mhd_ens_timer_read", "mhd_ens_last_error", "mhd_ens_version",
     "mhd_ens_adjoint_terminal", "mhd_ens_adjoint_step", "mhd_ens_adjoint_ic",
     "mhd_ens_group_create", "mhd_ens_group_step", "mhd_ens_group_free",
+    "mhd_ens_autotune", "mhd_ens_set_plan",
 )
+
+
+TUNE_SADDLE, TUNE_RESIDUAL, TUNE_JACOBI_FIRST, TUNE_JACOBI = 0, 1, 2, 3
+TUNE_OPS = {TUNE_SADDLE: "saddle", TUNE_RESIDUAL: "residual", TUNE_JACOBI_FIRST: "jacobi_first",
+            TUNE_JACOBI: "jacobi"}
+
+
+class TuneEntry(C.Structure):
+    _fields_ = [("op", C.c_int32), ("word", C.c_int32), ("J", C.c_int32), ("vec", C.c_int32),
+                ("group", C.c_int32), ("deep", C.c_int32), ("tile", C.c_int32), ("waves", C.c_int32),
+                ("us", C.c_float),
+                ("chosen", C.c_int32)]
 
 
 class MeshDesc(C.Structure):
@@ -109,6 +122,8 @@ def lib():
             "mhd_ens_ctx_free": [P],
             "mhd_ens_step": [P, P, P, P, P, C.POINTER(StepInputs), C.POINTER(StepStats), P],
             "mhd_ens_spmm": [P, P, P, I, I, P],
+            "mhd_ens_autotune": [P, I, I, C.POINTER(TuneEntry), I, C.POINTER(I), P],
+            "mhd_ens_set_plan": [P, I, I, I, I, I, I, I, I],
             "mhd_ens_timer_enable": [I],
             "mhd_ens_adjoint_terminal": [P, P, P, P, P, I, P],
             "mhd_ens_adjoint_step": [P, P, P, P, P, P, P, P, P, C.POINTER(AdjointInputs), P,
@@ -244,6 +259,19 @@ def mhd_ens_step(ctx, V, W, Q, R, inputs, stats=True, stream=None, allow_noconv=
 
 def mhd_ens_spmm(A, x, y, J, precision, stream=None):
     check("mhd_ens_spmm", lib().mhd_ens_spmm(A, ptr(x), ptr(y), J, precision, stream_ptr(stream)))
+
+
+def mhd_ens_autotune(A, J, precision, stream=None, cap=256):
+    """Re-tunes the node-row kernels; returns one dict per timed candidate."""
+    out = (TuneEntry * cap)()
+    cnt = C.c_int(0)
+    check("mhd_ens_autotune", lib().mhd_ens_autotune(A, J, precision, out, cap, C.byref(cnt), stream_ptr(stream)))
+    return [dict(op=TUNE_OPS[e.op], word=e.word, J=e.J, vec=e.vec, group=e.group, deep=e.deep, tile=e.tile,
+                 waves=e.waves, us=e.us, chosen=bool(e.chosen)) for e in out[:cnt.value]]
+
+
+def mhd_ens_set_plan(A, J, precision, op, vec, group, deep=0, tile=0, waves=4):
+    check("mhd_ens_set_plan", lib().mhd_ens_set_plan(A, J, precision, op, vec, group, deep, tile, waves))
 
 
 def mhd_ens_timer_enable(on=True):

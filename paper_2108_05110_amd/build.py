@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmhd_ens.so")
-SOURCES = ["mesh.cpp", "assemble.hip", "solve.hip", "adjoint.hip", "capi.hip"]
+SOURCES = ["mesh.cpp", "tiling.cpp", "assemble.hip", "solve.hip", "adjoint.hip", "capi.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed-FP32 instructions are disabled for the device code (the compiler still

@@ -170,6 +170,13 @@ mhd_status build_device_mesh(DevMesh& D) {
     for (size_t i = 0; i < h.dir_nodes.size(); ++i) dir_index[h.dir_nodes[i]] = (int32_t)i;
     if ((rc = upload(L, &D.dir_index, dir_index))) return rc;
     if ((rc = upload(L, &D.dir_nodes, h.dir_nodes))) return rc;
+    D.max_row = 0;
+    for (const HostCSR* c : {&h.A, &h.Bt, &h.B})
+        for (size_t i = 0; i + 1 < c->rowptr.size(); ++i)
+            D.max_row = std::max(D.max_row, (int)(c->rowptr[i + 1] - c->rowptr[i]));
+    D.max_row_bt = 0;
+    for (size_t i = 0; i + 1 < h.Bt.rowptr.size(); ++i)
+        D.max_row_bt = std::max(D.max_row_bt, (int)(h.Bt.rowptr[i + 1] - h.Bt.rowptr[i]));
     if ((rc = upload(L, &D.A_rowptr, h.A.rowptr))) return rc;
     if ((rc = upload(L, &D.A_col, h.A.col))) return rc;
     if ((rc = upload(L, &D.Bt_rowptr, h.Bt.rowptr))) return rc;
@@ -494,7 +501,10 @@ mhd_status mhd_ens_mesh_coords(mhd_mesh m, double* xy_p2, int32_t* dir_nodes) {
 mhd_status mhd_ens_mesh_free(mhd_mesh m) {
     if (!m) return MHD_OK;
     free_list(m->d.allocs);
-    for (auto& l : m->d.levels) (void)l;
+    for (auto*& t : m->d.tiling) {
+        delete t;
+        t = nullptr;
+    }
     delete m;
     return MHD_OK;
 }
@@ -681,6 +691,39 @@ mhd_status mhd_ens_ctx_free(mhd_ctx c) {
     return MHD_OK;
 }
 
+mhd_status mhd_ens_autotune(mhd_shared A, int J, int precision, mhd_tune_entry* out, int cap, int* count,
+                            mhd_stream_t s) {
+    CHECK_ARG(A, "mhd_ens_autotune: null handle");
+    CHECK_ARG(precision == MHD_FP64 || precision == MHD_FP32_IR, "mhd_ens_autotune: bad precision");
+    CHECK_ARG(cap >= 0 && (cap == 0 || out), "mhd_ens_autotune: bad output array");
+    if (J < 1 || J > A->d.Jmax) {
+        set_error("mhd_ens_autotune: J outside [1, J_max]");
+        return MHD_ESHAPE;
+    }
+    hipStream_t st = as_stream(s);
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    MHD_HIP(hipStreamIsCapturing(st, &cs));
+    CHECK_ARG(cs == hipStreamCaptureStatusNone, "mhd_ens_autotune: stream is being captured");
+    std::vector<mhd_tune_entry> rep;
+    mhd_status rc = autotune(A->d, J, precision, st, true, &rep);
+    if (rc) return rc;
+    const int n = std::min<int>(cap, (int)rep.size());
+    for (int i = 0; i < n; ++i) out[i] = rep[i];
+    if (count) *count = n;
+    return MHD_OK;
+}
+
+mhd_status mhd_ens_set_plan(mhd_shared A, int J, int precision, int op, int vec, int group, int deep, int tile,
+                            int waves) {
+    CHECK_ARG(A, "mhd_ens_set_plan: null handle");
+    CHECK_ARG(precision == MHD_FP64 || precision == MHD_FP32_IR, "mhd_ens_set_plan: bad precision");
+    if (J < 1 || J > A->d.Jmax) {
+        set_error("mhd_ens_set_plan: J outside [1, J_max]");
+        return MHD_ESHAPE;
+    }
+    return set_plan(A->d, J, precision, op, vec, group, deep, tile, waves);
+}
+
 mhd_status mhd_ens_step(mhd_ctx ctx, double* V, double* W, double* Q, double* R, const mhd_step_inputs* in,
                         mhd_step_stats* st, mhd_stream_t s) {
     CHECK_ARG(ctx && in, "mhd_ens_step: null argument");
@@ -696,6 +739,8 @@ mhd_status mhd_ens_step(mhd_ctx ctx, double* V, double* W, double* Q, double* R,
         CHECK_ARG(stv != nullptr, "mhd_ens_step: graph mode needs a non-null stream");
         if (!ctx->graph.valid || !(ctx->graph.key == a) || ctx->graph.stream != stv) {
             ctx->graph.reset();
+            // kernel plans are fixed into the graph: tune before capturing
+            if ((rc = autotune(ctx->Av->d, a.J, ctx->desc.solver.precision, stv, false, nullptr))) return rc;
             MHD_HIP(hipStreamBeginCapture(stv, hipStreamCaptureModeThreadLocal));
             rs = step_device(ctx, c, a, stv, &sv, &sw);
             hipGraph_t graph = nullptr;
@@ -804,6 +849,11 @@ mhd_status mhd_ens_group_step(mhd_group g, double* const* V, double* const* W, d
     for (int i = 0; same && i < n; ++i) same = g->keys[i] == args[i];
     if (!same) {
         g->graph.reset();
+        for (int i = 0; i < n; ++i) {
+            mhd_status rc = autotune(g->ctxs[i]->Av->d, args[i].J, g->ctxs[i]->desc.solver.precision, st, false,
+                                     nullptr);
+            if (rc) return rc;
+        }
         MHD_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
         mhd_status rs = MHD_OK;
         hipError_t e = hipEventRecord(g->fork, st);

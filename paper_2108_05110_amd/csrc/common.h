@@ -70,6 +70,25 @@ struct HostMesh {
     std::vector<HostLevel> levels;           // pressure Schur-approximation hierarchy
 };
 
+// Row tiles of the saddle-point operator for the LDS-staged kernels.  The
+// mesh is cut into rectangles of tx x ty half-steps (the P2 node spacing); a
+// tile owns the P2 rows and P1 rows whose nodes lie in its rectangle and
+// stages every node value those rows read.  Empty rectangles are dropped.
+struct HostTiling {
+    int tx = 0, ty = 0;
+    int ntiles = 0;
+    int max_s2 = 0, max_s1 = 0;             // largest staged P2 / P1 node counts
+    int max_r2 = 0, max_r1 = 0;             // largest owned P2 / P1 row counts
+    std::vector<int32_t> r2_ptr, r2;        // tile -> owned P2 rows
+    std::vector<int32_t> r2_self;           // per owned P2 row: local index of its own node
+    std::vector<int32_t> r1_ptr, r1;        // tile -> owned P1 rows
+    std::vector<int32_t> r1_self;           // per owned P1 row: local index of its own node
+    std::vector<int32_t> s2_ptr, s2;        // tile -> staged P2 nodes (ascending)
+    std::vector<int32_t> s1_ptr, s1;        // tile -> staged P1 nodes (ascending)
+    std::vector<int32_t> a_loc, bt_loc, b_loc;   // per CSR entry of A, B^T, B: local column index
+};
+void build_tiling(const HostMesh& m, int tx, int ty, HostTiling& t);
+
 mhd_status build_mesh(const mhd_mesh_desc* d, HostMesh& m, bool full);
 mhd_status schur_values(HostMesh& m, double dt, double nu_c);
 void mesh_counts(const HostMesh& m, mhd_mesh_info* info);

@@ -39,6 +39,17 @@ struct DevLevel {
     float* cinv32 = nullptr;
 };
 
+// Device copy of a HostTiling (row tiles of the LDS-staged kernels)
+struct DevTiling {
+    int tx = 0, ty = 0, ntiles = 0, max_s2 = 0, max_s1 = 0, max_r2 = 0, max_r1 = 0;
+    int32_t *r2_ptr = nullptr, *r2 = nullptr, *r2_self = nullptr;
+    int32_t *r1_ptr = nullptr, *r1 = nullptr, *r1_self = nullptr;
+    int32_t *s2_ptr = nullptr, *s2 = nullptr, *s1_ptr = nullptr, *s1 = nullptr;
+    int32_t *a_loc = nullptr, *bt_loc = nullptr, *b_loc = nullptr;
+};
+constexpr int kTileShapes = 3;          // square tiles of 8, 12 or 16 half-steps
+inline int tile_edge(int id) { return id == 1 ? 8 : id == 2 ? 12 : 16; }
+
 struct DevMesh {
     HostMesh host;
     int nP2 = 0, nP1 = 0, n_el = 0, n_dir = 0, pin = -1;
@@ -54,6 +65,8 @@ struct DevMesh {
     int32_t *Bt_rowptr = nullptr, *Bt_col = nullptr;
     int32_t *B_rowptr = nullptr, *B_col = nullptr;
     int64_t nnzA = 0, nnzBt = 0, nnzB = 0;
+    int max_row = 0;              // longest row of the A, B^T and B patterns
+    int max_row_bt = 0;           // longest row of the B^T pattern
     int32_t *gA_ptr = nullptr, *gA_idx = nullptr;
     int32_t *gB_ptr = nullptr, *gB_idx = nullptr;
     int32_t *gBt_ptr = nullptr, *gBt_idx = nullptr;
@@ -72,6 +85,7 @@ struct DevMesh {
     double* mp_inv = nullptr;
     uint8_t* pfix = nullptr;                      // nP1: fixed rows of the pressure Laplacian
     std::vector<DevLevel> levels;
+    DevTiling* tiling[kTileShapes + 1] = {};   // by shape id 1..kTileShapes, built on demand
     // small scratch for the stand-alone RHS call (member coefficients, means)
     double* scratch_coef = nullptr;               // 2 * kMaxJ
     double* scratch_mean = nullptr;               // 2 nP2
@@ -144,6 +158,9 @@ mhd_status alloc_gmres(DevShared& S, int restart);
 mhd_status solve_shared(DevShared& S, const double* rhs, double* x, int J, const mhd_solver_opts& o,
                         mhd_solve_stats* st, hipStream_t s);
 mhd_status spmm_shared(DevShared& S, const void* x, void* y, int J, int precision, hipStream_t s);
+mhd_status autotune(DevShared& S, int J, int precision, hipStream_t st, bool force,
+                    std::vector<mhd_tune_entry>* report);
+mhd_status set_plan(DevShared& S, int J, int precision, int op, int vec, int group, int deep, int tile, int waves);
 mhd_status timer_enable(int on);
 mhd_status timer_read(double* ms, int64_t* launches, double* nJ32, double* nJ64);
 mhd_status saddle_residual64(DevShared& S, const double* b, const double* x, double* r, int J, hipStream_t s);

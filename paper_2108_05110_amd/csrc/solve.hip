@@ -21,6 +21,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "device.h"
 
@@ -303,6 +306,888 @@ __global__ void __launch_bounds__(kBlock) k_velo_v(const int32_t* __restrict__ r
 #pragma unroll
         for (int q = 0; q < VEC; ++q) acc[q] = zv[q] + dw * (tv[q] - acc[q]);
         vstore<T, VEC>(zo + o, acc);
+    }
+}
+
+// ------------------------------------------------------------------ batched-gather node-row kernels
+// Same lane layout as NodeLanes, but a wavefront handles G consecutive units
+// and gathers a row in batches: lane t first loads the row's t-th column index
+// and value (one coalesced load for the whole row), then the column indices are
+// broadcast with v_readlane so that 4 or 8 member-row loads of x are in flight
+// before the first multiply-add.  Rows are padded to the batch width with a
+// valid column and a zero value; a row may hold at most kMaxRowBatched entries.
+constexpr int kMaxRowBatched = 56;
+
+__device__ __forceinline__ float lane_bcast(float v, int t) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), t));
+}
+__device__ __forceinline__ double lane_bcast(double v, int t) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), t);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), t);
+    return __builtin_bit_cast(double, (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+__device__ __forceinline__ int rl(int v, int i) { return __builtin_amdgcn_readlane(v, i); }
+
+// One row's entries spread over the lanes: lane t < cnt holds entry t.  With
+// PAIR the row has two values per entry (one per velocity component).
+template <typename T, bool PAIR>
+struct RowLanes {
+    int cnt;
+    int col;
+    T v0, v1;
+};
+
+template <typename T, bool PAIR>
+__device__ __forceinline__ RowLanes<T, PAIR> row_lanes(const int32_t* __restrict__ col, const T* __restrict__ val,
+                                                       int32_t p0, int32_t p1, int pad_col) {
+    RowLanes<T, PAIR> R;
+    const int lane = threadIdx.x & 63;
+    R.cnt = p1 - p0;
+    R.col = pad_col;
+    R.v0 = 0;
+    R.v1 = 0;
+    if (lane < R.cnt) {
+        R.col = col[p0 + lane];
+        if (PAIR) {
+            R.v0 = val[2 * (p0 + lane)];
+            R.v1 = val[2 * (p0 + lane) + 1];
+        } else {
+            R.v0 = val[p0 + lane];
+        }
+    }
+    return R;
+}
+
+// acc[q] += sum over entries t in [t0, t0 + NB) of a_t * xb[col_t * cstride + q]
+// (NEG: acc[q] -= ..., with the same fused multiply-adds as a sequential loop)
+template <typename T, int VEC, int NB, bool PAIR, bool NEG>
+__device__ __forceinline__ void gather_batch(const RowLanes<T, PAIR>& R, int t0, int c, const T* __restrict__ xb,
+                                             int64_t cstride, T (&acc)[VEC]) {
+    T v[NB][VEC];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const int64_t k = __builtin_amdgcn_readlane(R.col, t0 + i);
+        vload<T, VEC>(v[i], xb + k * cstride);
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        T a;
+        if (PAIR) {
+            const T a0 = lane_bcast(R.v0, t0 + i), a1 = lane_bcast(R.v1, t0 + i);
+            a = c ? a1 : a0;
+        } else {
+            a = lane_bcast(R.v0, t0 + i);
+        }
+        if (NEG) a = -a;
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) acc[q] += a * v[i][q];
+    }
+}
+
+template <typename T, int VEC, bool PAIR, bool NEG = false>
+__device__ __forceinline__ void gather_row(const RowLanes<T, PAIR>& R, int c, const T* __restrict__ xb, int64_t cstride,
+                                           T (&acc)[VEC]) {
+    int t = 0;
+    for (; t + 8 <= R.cnt; t += 8) gather_batch<T, VEC, 8, PAIR, NEG>(R, t, c, xb, cstride, acc);
+    const int r = R.cnt - t;
+    if (r > 4)
+        gather_batch<T, VEC, 8, PAIR, NEG>(R, t, c, xb, cstride, acc);
+    else if (r > 0)
+        gather_batch<T, VEC, 4, PAIR, NEG>(R, t, c, xb, cstride, acc);
+}
+
+struct GroupLanes {
+    int c, j;
+    int u0;   // first unit of this wavefront (uniform)
+};
+
+template <int VEC, int G>
+__device__ __forceinline__ GroupLanes group_lanes() {
+    GroupLanes L;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    L.c = lane >> 5;
+    L.j = blockIdx.y * (32 * VEC) + (lane & 31) * VEC;
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    L.u0 = __builtin_amdgcn_readfirstlane((int)((blk * (kBlock / 64) + wave) * G));
+    return L;
+}
+
+// y = S x (MODE 0) or y = b - S x (MODE 1), G units per wavefront
+template <typename T, int VEC, int MODE, int G>
+__global__ void __launch_bounds__(kBlock) k_saddle_g(const int32_t* __restrict__ Arp, const int32_t* __restrict__ Acol,
+                                                     const T* __restrict__ Aval, const int32_t* __restrict__ Btrp,
+                                                     const int32_t* __restrict__ Btcol, const T* __restrict__ Btval,
+                                                     const int32_t* __restrict__ Brp, const int32_t* __restrict__ Bcol,
+                                                     const T* __restrict__ Bval, const T* __restrict__ dp,
+                                                     const T* __restrict__ x, const T* __restrict__ bvec,
+                                                     T* __restrict__ y, int nP2, int nP1, int J) {
+    const GroupLanes L = group_lanes<VEC, G>();
+    const T* xp = x + 2 * (int64_t)nP2 * J;
+    const T* xc = x + (int64_t)L.c * J + L.j;
+    for (int g = 0; g < G; ++g) {
+        const int u = L.u0 + g;
+        if (u >= nP2 + nP1) return;
+        T acc[VEC];
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) acc[q] = 0;
+        if (u < nP2) {
+            const RowLanes<T, false> RA = row_lanes<T, false>(Acol, Aval, Arp[u], Arp[u + 1], u);
+            const RowLanes<T, true> RB = row_lanes<T, true>(Btcol, Btval, Btrp[u], Btrp[u + 1], 0);
+            gather_row<T, VEC, false>(RA, L.c, xc, 2 * (int64_t)J, acc);
+            gather_row<T, VEC, true>(RB, L.c, xp + L.j, J, acc);
+            const int64_t o = (2 * (int64_t)u + L.c) * J + L.j;
+            if (MODE == 1) {
+                T bv[VEC];
+                vload<T, VEC>(bv, bvec + o);
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) acc[q] = bv[q] - acc[q];
+            }
+            vstore<T, VEC>(y + o, acc);
+        } else {
+            const int k = u - nP2;
+            const RowLanes<T, true> RB = row_lanes<T, true>(Bcol, Bval, Brp[k], Brp[k + 1], 0);
+            gather_row<T, VEC, true>(RB, L.c, xc, 2 * (int64_t)J, acc);
+            // add the two velocity components' contributions (lanes l and l + 32)
+#pragma unroll
+            for (int r = 0; r < VEC; ++r) acc[r] += __shfl_xor(acc[r], 32, 64);
+            if (L.c == 0) {
+                const T d = dp[k];
+                const int64_t o = (2 * (int64_t)nP2 + k) * J + L.j;
+                T v[VEC];
+                vload<T, VEC>(v, xp + (int64_t)k * J + L.j);
+#pragma unroll
+                for (int r = 0; r < VEC; ++r) acc[r] += d * v[r];
+                if (MODE == 1) {
+                    T bv[VEC];
+                    vload<T, VEC>(bv, bvec + o);
+#pragma unroll
+                    for (int r = 0; r < VEC; ++r) acc[r] = bv[r] - acc[r];
+                }
+                vstore<T, VEC>(y + o, acc);
+            }
+        }
+    }
+}
+
+// Velocity-block Jacobi sweeps, G nodes per wavefront (operations as k_velo_v)
+template <typename T, int VEC, bool FIRST, int G>
+__global__ void __launch_bounds__(kBlock) k_velo_g(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                   const T* __restrict__ val, const T* __restrict__ dinvA,
+                                                   const T* __restrict__ in, const T* __restrict__ zp,
+                                                   T* __restrict__ t, const T* __restrict__ z, T* __restrict__ zo,
+                                                   int nP2, int J, T omega) {
+    const GroupLanes L = group_lanes<VEC, G>();
+    for (int g = 0; g < G; ++g) {
+        const int i = L.u0 + g;
+        if (i >= nP2) return;
+        const T dw = omega * dinvA[i];
+        const int64_t o = (2 * (int64_t)i + L.c) * J + L.j;
+        T acc[VEC];
+        if (FIRST) {
+            const RowLanes<T, true> RB = row_lanes<T, true>(col, val, rp[i], rp[i + 1], 0);
+            vload<T, VEC>(acc, in + o);   // r_u
+            gather_row<T, VEC, true, true>(RB, L.c, zp + L.j, J, acc);
+            vstore<T, VEC>(t + o, acc);
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) acc[q] *= dw;
+            vstore<T, VEC>(zo + o, acc);
+        } else {
+            const RowLanes<T, false> RA = row_lanes<T, false>(col, val, rp[i], rp[i + 1], i);
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) acc[q] = 0;
+            gather_row<T, VEC, false>(RA, L.c, z + (int64_t)L.c * J + L.j, 2 * (int64_t)J, acc);
+            T tv[VEC], zv[VEC];
+            vload<T, VEC>(tv, t + o);
+            vload<T, VEC>(zv, z + o);
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) acc[q] = zv[q] + dw * (tv[q] - acc[q]);
+            vstore<T, VEC>(zo + o, acc);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ pipelined gather kernels
+// Gather kernels with deep memory-level parallelism: a wavefront owns G
+// consecutive units; the CSR bounds of all G rows come in with one load per
+// lane, the next row's column indices and values are loaded while the current
+// row is computed, and all member-row loads of a row (up to kDeepA entries of
+// A or B, kDeepBt of B^T, padded to batches of 8) are in flight before the
+// first multiply-add.  Lane layout as NodeLanes.
+constexpr int kDeepA = 24;
+constexpr int kDeepBt = 8;
+
+template <typename T, bool PAIR>
+__device__ __forceinline__ T entry_value(const RowLanes<T, PAIR>& R, int t, int c) {
+    if (PAIR) {
+        const T a0 = lane_bcast(R.v0, t), a1 = lane_bcast(R.v1, t);
+        return c ? a1 : a0;
+    }
+    return lane_bcast(R.v0, t);
+}
+
+// acc[q] += sum_t a_t xb[col_t cstride + q] over a row of at most NBAT batches
+// of 8 entries: every load is issued before the first multiply-add
+template <typename T, int VEC, int NBAT, bool PAIR, bool NEG>
+__device__ __forceinline__ void deep_row(const RowLanes<T, PAIR>& R, int c, const T* __restrict__ xb, int64_t cstride,
+                                         T (&acc)[VEC]) {
+    const int nb = (R.cnt + 7) >> 3;
+    T v[NBAT][8][VEC];
+#pragma unroll
+    for (int b = 0; b < NBAT; ++b)
+        if (b < nb) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int64_t k = __builtin_amdgcn_readlane(R.col, 8 * b + i);
+                vload<T, VEC>(v[b][i], xb + k * cstride);
+            }
+        }
+#pragma unroll
+    for (int b = 0; b < NBAT; ++b)
+        if (b < nb) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                T a = entry_value<T, PAIR>(R, 8 * b + i, c);
+                if (NEG) a = -a;
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) acc[q] += a * v[b][i][q];
+            }
+        }
+}
+
+template <typename T>
+struct DeepRows {
+    RowLanes<T, false> A;   // A row of a P2 unit
+    RowLanes<T, true> B;    // B^T row of a P2 unit, or B row of a P1 unit
+};
+
+// y = S x (MODE 0) or y = b - S x (MODE 1), G units per wavefront
+template <typename T, int VEC, int MODE, int G>
+__global__ void __launch_bounds__(kBlock) k_saddle_p(const int32_t* __restrict__ Arp, const int32_t* __restrict__ Acol,
+                                                     const T* __restrict__ Aval, const int32_t* __restrict__ Btrp,
+                                                     const int32_t* __restrict__ Btcol, const T* __restrict__ Btval,
+                                                     const int32_t* __restrict__ Brp, const int32_t* __restrict__ Bcol,
+                                                     const T* __restrict__ Bval, const T* __restrict__ dp,
+                                                     const T* __restrict__ x, const T* __restrict__ bvec,
+                                                     T* __restrict__ y, int nP2, int nP1, int J) {
+    const GroupLanes L = group_lanes<VEC, G>();
+    const int n = min(G, nP2 + nP1 - L.u0);
+    if (n <= 0) return;
+    const int lane = threadIdx.x & 63;
+    int m0 = 0, m1 = 0, m2 = 0, m3 = 0;   // CSR bounds of unit u0 + lane
+    if (lane < n) {
+        const int u = L.u0 + lane;
+        if (u < nP2) {
+            m0 = Arp[u];
+            m1 = Arp[u + 1];
+            m2 = Btrp[u];
+            m3 = Btrp[u + 1];
+        } else {
+            m2 = Brp[u - nP2];
+            m3 = Brp[u - nP2 + 1];
+        }
+    }
+    auto load = [&](int g) {
+        DeepRows<T> R;
+        const int u = L.u0 + g;
+        if (u < nP2) {
+            R.A = row_lanes<T, false>(Acol, Aval, rl(m0, g), rl(m1, g), u);
+            R.B = row_lanes<T, true>(Btcol, Btval, rl(m2, g), rl(m3, g), 0);
+        } else {
+            R.A.cnt = 0;
+            R.A.col = 0;
+            R.A.v0 = R.A.v1 = 0;
+            R.B = row_lanes<T, true>(Bcol, Bval, rl(m2, g), rl(m3, g), 0);
+        }
+        return R;
+    };
+    const T* xp = x + 2 * (int64_t)nP2 * J;
+    const T* xc = x + (int64_t)L.c * J + L.j;
+    DeepRows<T> cur = load(0);
+    for (int g = 0; g < n; ++g) {
+        DeepRows<T> nxt = cur;
+        if (g + 1 < n) nxt = load(g + 1);
+        const int u = L.u0 + g;
+        T acc[VEC];
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) acc[q] = 0;
+        if (u < nP2) {
+            deep_row<T, VEC, kDeepA / 8, false, false>(cur.A, L.c, xc, 2 * (int64_t)J, acc);
+            deep_row<T, VEC, kDeepBt / 8, true, false>(cur.B, L.c, xp + L.j, J, acc);
+            const int64_t o = (2 * (int64_t)u + L.c) * J + L.j;
+            if (MODE == 1) {
+                T bv[VEC];
+                vload<T, VEC>(bv, bvec + o);
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) acc[q] = bv[q] - acc[q];
+            }
+            vstore<T, VEC>(y + o, acc);
+        } else {
+            const int k = u - nP2;
+            deep_row<T, VEC, kDeepA / 8, true, false>(cur.B, L.c, xc, 2 * (int64_t)J, acc);
+#pragma unroll
+            for (int r = 0; r < VEC; ++r) acc[r] += __shfl_xor(acc[r], 32, 64);
+            if (L.c == 0) {
+                const T d = dp[k];
+                const int64_t o = (2 * (int64_t)nP2 + k) * J + L.j;
+                T v[VEC];
+                vload<T, VEC>(v, xp + (int64_t)k * J + L.j);
+#pragma unroll
+                for (int r = 0; r < VEC; ++r) acc[r] += d * v[r];
+                if (MODE == 1) {
+                    T bv[VEC];
+                    vload<T, VEC>(bv, bvec + o);
+#pragma unroll
+                    for (int r = 0; r < VEC; ++r) acc[r] = bv[r] - acc[r];
+                }
+                vstore<T, VEC>(y + o, acc);
+            }
+        }
+        cur = nxt;
+    }
+}
+
+// velocity-block Jacobi sweeps, pipelined (operations as k_velo_v)
+template <typename T, int VEC, bool FIRST, int G>
+__global__ void __launch_bounds__(kBlock) k_velo_p(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                   const T* __restrict__ val, const T* __restrict__ dinvA,
+                                                   const T* __restrict__ in, const T* __restrict__ zp,
+                                                   T* __restrict__ t, const T* __restrict__ z, T* __restrict__ zo,
+                                                   int nP2, int J, T omega) {
+    const GroupLanes L = group_lanes<VEC, G>();
+    const int n = min(G, nP2 - L.u0);
+    if (n <= 0) return;
+    const int lane = threadIdx.x & 63;
+    int m0 = 0, m1 = 0;
+    if (lane < n) {
+        m0 = rp[L.u0 + lane];
+        m1 = rp[L.u0 + lane + 1];
+    }
+    auto load = [&](int g) {
+        return row_lanes<T, FIRST>(col, val, rl(m0, g), rl(m1, g), FIRST ? 0 : L.u0 + g);
+    };
+    RowLanes<T, FIRST> cur = load(0);
+    for (int g = 0; g < n; ++g) {
+        RowLanes<T, FIRST> nxt = cur;
+        if (g + 1 < n) nxt = load(g + 1);
+        const int i = L.u0 + g;
+        const T dw = omega * dinvA[i];
+        const int64_t o = (2 * (int64_t)i + L.c) * J + L.j;
+        T acc[VEC];
+        if constexpr (FIRST) {
+            vload<T, VEC>(acc, in + o);   // r_u
+            deep_row<T, VEC, kDeepBt / 8, true, true>(cur, L.c, zp + L.j, J, acc);
+            vstore<T, VEC>(t + o, acc);
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) acc[q] *= dw;
+            vstore<T, VEC>(zo + o, acc);
+        } else {
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) acc[q] = 0;
+            deep_row<T, VEC, kDeepA / 8, false, false>(cur, L.c, z + (int64_t)L.c * J + L.j, 2 * (int64_t)J, acc);
+            T tv[VEC], zv[VEC];
+            vload<T, VEC>(tv, t + o);
+            vload<T, VEC>(zv, z + o);
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) acc[q] = zv[q] + dw * (tv[q] - acc[q]);
+            vstore<T, VEC>(zo + o, acc);
+        }
+        cur = nxt;
+    }
+}
+
+// ------------------------------------------------------------------ paired-row gather kernels
+// Two rows per wavefront at a time: lanes 0-31 compute one row and lanes 32-63
+// another, each half covering both velocity components of MJ = 16 V members
+// with 16-byte loads (V = 16 / sizeof(T) members per lane), so every load
+// instruction fetches two member rows of x.  A wavefront owns G consecutive
+// units of one kind (P2 or P1) and pairs unit g with unit g + G/2.  Within a
+// half, lane h covers component h / 16 and members (h % 16) V ... + V - 1.
+// Entries are consumed in CSR order per row (rows padded with zero values to
+// the longer row of the pair), so the arithmetic matches the other kernels.
+constexpr int kPairRow = 32;   // longest row the paired kernels accept
+
+struct PairLanes {
+    int half, c, j;
+    int u0, uend;   // units [u0, u0 + G) of this wavefront, clipped to uend (uniform)
+};
+
+template <int V, int G>
+__device__ __forceinline__ PairLanes pair_lanes(int nP2, int nP1, int wP2) {
+    PairLanes L;
+    const int lane = threadIdx.x & 63;
+    L.half = lane >> 5;
+    const int h = lane & 31;
+    L.c = h >> 4;
+    L.j = blockIdx.y * (16 * V) + (h & 15) * V;
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int w = __builtin_amdgcn_readfirstlane((int)(blk * (kBlock / 64) + (threadIdx.x >> 6)));
+    if (w < wP2) {
+        L.u0 = w * G;
+        L.uend = nP2;
+    } else {
+        L.u0 = nP2 + (w - wP2) * G;
+        L.uend = nP2 + nP1;
+    }
+    return L;
+}
+
+// lane t + 32 half of a RowLanes-like spread holds entry t of its half's row
+template <typename T, bool PAIR>
+struct HalfRow {
+    int cnt;   // entries of this lane's row
+    int col;
+    T v0, v1;
+};
+
+template <typename T, bool PAIR>
+__device__ __forceinline__ HalfRow<T, PAIR> half_row(const int32_t* __restrict__ col, const T* __restrict__ val,
+                                                     int32_t p0, int32_t p1, int pad_col) {
+    HalfRow<T, PAIR> R;
+    const int h = threadIdx.x & 31;
+    R.cnt = p1 - p0;
+    R.col = pad_col;
+    R.v0 = 0;
+    R.v1 = 0;
+    if (h < R.cnt) {
+        R.col = col[p0 + h];
+        if (PAIR) {
+            R.v0 = val[2 * (p0 + h)];
+            R.v1 = val[2 * (p0 + h) + 1];
+        } else {
+            R.v0 = val[p0 + h];
+        }
+    }
+    return R;
+}
+
+template <typename T>
+__device__ __forceinline__ T half_bcast(T v, int src) {
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, __builtin_amdgcn_ds_bpermute(src << 2, __builtin_bit_cast(int, v)));
+    } else {
+        const long long b = __builtin_bit_cast(long long, v);
+        const int lo = __builtin_amdgcn_ds_bpermute(src << 2, (int)(b & 0xffffffffLL));
+        const int hi = __builtin_amdgcn_ds_bpermute(src << 2, (int)(b >> 32));
+        return __builtin_bit_cast(T, (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+    }
+}
+
+// acc[q] += sum_t a_t xb[col_t cstride + q] for this lane's row; n = entries of
+// the longer row of the pair (uniform), batches of 8 loads in flight
+template <typename T, int V, bool PAIR, bool NEG>
+__device__ __forceinline__ void pair_row(const HalfRow<T, PAIR>& R, int n, int half, int c, const T* __restrict__ xb,
+                                         int64_t cstride, T (&acc)[V]) {
+    const int base = half << 5;
+    for (int t = 0; t < n; t += 8) {
+        T v[8][V];
+        T a[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int src = base + min(t + i, 31);
+            const int64_t k = __builtin_amdgcn_ds_bpermute(src << 2, R.col);
+            vload<T, V>(v[i], xb + k * cstride);
+            if (PAIR) {
+                const T a0 = half_bcast(R.v0, src), a1 = half_bcast(R.v1, src);
+                a[i] = c ? a1 : a0;
+            } else {
+                a[i] = half_bcast(R.v0, src);
+            }
+            if (t + i >= R.cnt) a[i] = 0;
+            if (NEG) a[i] = -a[i];
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+#pragma unroll
+            for (int q = 0; q < V; ++q) acc[q] += a[i] * v[i][q];
+        }
+    }
+}
+
+// y = S x (MODE 0) or y = b - S x (MODE 1)
+template <typename T, int MODE, int G>
+__global__ void __launch_bounds__(kBlock) k_saddle_h(const int32_t* __restrict__ Arp, const int32_t* __restrict__ Acol,
+                                                     const T* __restrict__ Aval, const int32_t* __restrict__ Btrp,
+                                                     const int32_t* __restrict__ Btcol, const T* __restrict__ Btval,
+                                                     const int32_t* __restrict__ Brp, const int32_t* __restrict__ Bcol,
+                                                     const T* __restrict__ Bval, const T* __restrict__ dp,
+                                                     const T* __restrict__ x, const T* __restrict__ bvec,
+                                                     T* __restrict__ y, int nP2, int nP1, int J, int wP2) {
+    constexpr int V = 16 / (int)sizeof(T);
+    const PairLanes L = pair_lanes<V, G>(nP2, nP1, wP2);
+    const T* xp = x + 2 * (int64_t)nP2 * J;
+    const T* xc = x + (int64_t)L.c * J + L.j;
+    for (int s = 0; s < G / 2; ++s) {
+        const int ua = L.u0 + s, ub = L.u0 + s + G / 2;
+        if (ua >= L.uend) return;
+        const bool has_b = ub < L.uend;
+        const int u = (L.half && has_b) ? ub : ua;   // a lone row is computed twice, stored once
+        T acc[V];
+#pragma unroll
+        for (int q = 0; q < V; ++q) acc[q] = 0;
+        if (u < nP2) {
+            const HalfRow<T, false> RA = half_row<T, false>(Acol, Aval, Arp[u], Arp[u + 1], u);
+            const HalfRow<T, true> RB = half_row<T, true>(Btcol, Btval, Btrp[u], Btrp[u + 1], 0);
+            const int na = max(__builtin_amdgcn_readlane(RA.cnt, 0), __builtin_amdgcn_readlane(RA.cnt, 32));
+            const int nb = max(__builtin_amdgcn_readlane(RB.cnt, 0), __builtin_amdgcn_readlane(RB.cnt, 32));
+            pair_row<T, V, false, false>(RA, na, L.half, L.c, xc, 2 * (int64_t)J, acc);
+            pair_row<T, V, true, false>(RB, nb, L.half, L.c, xp + L.j, J, acc);
+            const int64_t o = (2 * (int64_t)u + L.c) * J + L.j;
+            if (MODE == 1) {
+                T bv[V];
+                vload<T, V>(bv, bvec + o);
+#pragma unroll
+                for (int q = 0; q < V; ++q) acc[q] = bv[q] - acc[q];
+            }
+            if (!L.half || has_b) vstore<T, V>(y + o, acc);
+        } else {
+            const int k = u - nP2;
+            const HalfRow<T, true> RB = half_row<T, true>(Bcol, Bval, Brp[k], Brp[k + 1], 0);
+            const int nb = max(__builtin_amdgcn_readlane(RB.cnt, 0), __builtin_amdgcn_readlane(RB.cnt, 32));
+            pair_row<T, V, true, false>(RB, nb, L.half, L.c, xc, 2 * (int64_t)J, acc);
+#pragma unroll
+            for (int r = 0; r < V; ++r) acc[r] += __shfl_xor(acc[r], 16, 64);   // the two components
+            if (L.c == 0 && (!L.half || has_b)) {
+                const T d = dp[k];
+                const int64_t o = (2 * (int64_t)nP2 + k) * J + L.j;
+                T v[V];
+                vload<T, V>(v, xp + (int64_t)k * J + L.j);
+#pragma unroll
+                for (int r = 0; r < V; ++r) acc[r] += d * v[r];
+                if (MODE == 1) {
+                    T bv[V];
+                    vload<T, V>(bv, bvec + o);
+#pragma unroll
+                    for (int r = 0; r < V; ++r) acc[r] = bv[r] - acc[r];
+                }
+                vstore<T, V>(y + o, acc);
+            }
+        }
+    }
+}
+
+// velocity-block Jacobi, paired rows (operations as k_velo_v); units are P2 only
+template <typename T, bool FIRST, int G>
+__global__ void __launch_bounds__(kBlock) k_velo_h(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                   const T* __restrict__ val, const T* __restrict__ dinvA,
+                                                   const T* __restrict__ in, const T* __restrict__ zp,
+                                                   T* __restrict__ t, const T* __restrict__ z, T* __restrict__ zo,
+                                                   int nP2, int J, T omega) {
+    constexpr int V = 16 / (int)sizeof(T);
+    const PairLanes L = pair_lanes<V, G>(nP2, 0, 1 << 30);
+    for (int s = 0; s < G / 2; ++s) {
+        const int ua = L.u0 + s, ub = L.u0 + s + G / 2;
+        if (ua >= L.uend) return;
+        const bool has_b = ub < L.uend;
+        const int i = (L.half && has_b) ? ub : ua;
+        const bool store = !L.half || has_b;
+        const T dw = omega * dinvA[i];
+        const int64_t o = (2 * (int64_t)i + L.c) * J + L.j;
+        T acc[V];
+        const HalfRow<T, FIRST> R = half_row<T, FIRST>(col, val, rp[i], rp[i + 1], FIRST ? 0 : i);
+        const int n = max(__builtin_amdgcn_readlane(R.cnt, 0), __builtin_amdgcn_readlane(R.cnt, 32));
+        if constexpr (FIRST) {
+            vload<T, V>(acc, in + o);   // r_u
+            pair_row<T, V, true, true>(R, n, L.half, L.c, zp + L.j, J, acc);
+            if (store) vstore<T, V>(t + o, acc);
+#pragma unroll
+            for (int q = 0; q < V; ++q) acc[q] *= dw;
+            if (store) vstore<T, V>(zo + o, acc);
+        } else {
+#pragma unroll
+            for (int q = 0; q < V; ++q) acc[q] = 0;
+            pair_row<T, V, false, false>(R, n, L.half, L.c, z + (int64_t)L.c * J + L.j, 2 * (int64_t)J, acc);
+            T tv[V], zv[V];
+            vload<T, V>(tv, t + o);
+            vload<T, V>(zv, z + o);
+#pragma unroll
+            for (int q = 0; q < V; ++q) acc[q] = zv[q] + dw * (tv[q] - acc[q]);
+            if (store) vstore<T, V>(zo + o, acc);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ LDS-staged node-row kernels
+// One workgroup per (row tile, slice of JT = 32 VEC members).  The node values
+// the tile's rows read are first copied into LDS with 16-byte loads
+// ([node][component][JT] for velocities, [node][JT] for pressures).  Each
+// wavefront then computes whole rows from LDS with lane = component * 32 +
+// member group of VEC; a row's column offsets and values are uniform across
+// the wavefront and come in through scalar loads.  Entries are consumed in CSR
+// order, so the arithmetic matches the other kernels.
+constexpr int kTileJ = 32;   // members of a slice per member per lane
+
+struct TileView {
+    const int32_t *r2_ptr, *r2, *r2_self, *r1_ptr, *r1, *r1_self, *s2_ptr, *s2, *s1_ptr, *s1;
+    const int32_t *a_loc, *bt_loc, *b_loc;
+};
+
+// dst[(s * comps + c) * JT + q] = src[nodes[s] * node_stride + c * comp_stride + q], q < JT;
+// 16-byte chunks, kStageU loads in flight per thread before the LDS stores
+constexpr int kStageU = 4;
+template <typename T, int JT>
+__device__ __forceinline__ void stage_nodes(T* dst, const int32_t* __restrict__ nodes, int cnt,
+                                            const T* __restrict__ src, int64_t node_stride, int comps,
+                                            int64_t comp_stride, int nthreads) {
+    constexpr int CH = 16 / (int)sizeof(T);
+    constexpr int NCH = JT / CH;
+    using V = typename VecT<T, CH>::type;
+    const int total = cnt * comps * NCH;
+    auto load = [&](int i) -> V {
+        const int q = i % NCH;
+        const int sc = i / NCH;
+        const int c = sc % comps, s = sc / comps;
+        return *(const V*)(src + (int64_t)nodes[s] * node_stride + c * comp_stride + q * CH);
+    };
+    int i = threadIdx.x;
+    for (; i + (kStageU - 1) * nthreads < total; i += kStageU * nthreads) {
+        V v[kStageU];
+#pragma unroll
+        for (int k = 0; k < kStageU; ++k) v[k] = load(i + k * nthreads);
+#pragma unroll
+        for (int k = 0; k < kStageU; ++k) *(V*)(dst + (int64_t)(i + k * nthreads) * CH) = v[k];
+    }
+    for (; i < total; i += nthreads) *(V*)(dst + (int64_t)i * CH) = load(i);
+}
+
+template <typename T, int VEC>
+__device__ __forceinline__ void lds_load(T (&v)[VEC], const T* p) {
+    if constexpr (VEC == 1) {
+        v[0] = *p;
+    } else {
+        using V = typename VecT<T, VEC>::type;
+        const V w = *(const V*)p;
+        v[0] = w.x;
+        v[1] = w.y;
+    }
+}
+
+// acc[q] += sum over entries p in [p0, p1) of val[p] * base[loc[p] * stride + q]
+template <typename T, int VEC>
+__device__ __forceinline__ void lds_gather(const int32_t* __restrict__ loc, const T* __restrict__ val, int p0,
+                                           int p1, const T* base, int stride, T (&acc)[VEC]) {
+    int p = p0;
+    for (; p + 4 <= p1; p += 4) {
+        T v[4][VEC];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) lds_load<T, VEC>(v[i], base + loc[p + i] * stride);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const T a = val[p + i];
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) acc[q] += a * v[i][q];
+        }
+    }
+    for (; p < p1; ++p) {
+        T v[VEC];
+        lds_load<T, VEC>(v, base + loc[p] * stride);
+        const T a = val[p];
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) acc[q] += a * v[q];
+    }
+}
+
+// two values per entry (one per velocity component): acc0 with val[2p], acc1
+// with val[2p + 1]; NEG subtracts
+template <typename T, int VEC, bool NEG>
+__device__ __forceinline__ void lds_gather2(const int32_t* __restrict__ loc, const T* __restrict__ val, int p0,
+                                            int p1, const T* base, int stride, T (&acc0)[VEC], T (&acc1)[VEC]) {
+    int p = p0;
+    for (; p + 4 <= p1; p += 4) {
+        T v[4][VEC];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) lds_load<T, VEC>(v[i], base + loc[p + i] * stride);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const T a0 = NEG ? -val[2 * (p + i)] : val[2 * (p + i)];
+            const T a1 = NEG ? -val[2 * (p + i) + 1] : val[2 * (p + i) + 1];
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) {
+                acc0[q] += a0 * v[i][q];
+                acc1[q] += a1 * v[i][q];
+            }
+        }
+    }
+    for (; p < p1; ++p) {
+        T v[VEC];
+        lds_load<T, VEC>(v, base + loc[p] * stride);
+        const T a0 = NEG ? -val[2 * p] : val[2 * p];
+        const T a1 = NEG ? -val[2 * p + 1] : val[2 * p + 1];
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) {
+            acc0[q] += a0 * v[q];
+            acc1[q] += a1 * v[q];
+        }
+    }
+}
+
+struct TileLanes {
+    int tile, j0, c, jj, wave;
+};
+
+template <int VEC>
+__device__ __forceinline__ TileLanes tile_lanes(int MT) {
+    TileLanes L;
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    L.tile = (int)(blk / MT);
+    L.j0 = (int)(blk % MT) * kTileJ * VEC;
+    const int lane = threadIdx.x & 63;
+    L.c = lane >> 5;
+    L.jj = (lane & 31) * VEC;
+    L.wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    return L;
+}
+
+// Row metadata of one wavefront's rows: lane i holds the i-th row the
+// wavefront owns (rows base + wave + i NW of the tile), at most 64 rows.
+struct WaveRows {
+    int n;              // rows of this wavefront (uniform)
+    int row, p0, p1, q0, q1;
+};
+
+__device__ __forceinline__ WaveRows wave_rows(const int32_t* __restrict__ rows, int rb, int re, int wave, int NW,
+                                              const int32_t* __restrict__ rp0, const int32_t* __restrict__ rp1) {
+    WaveRows W;
+    const int lane = threadIdx.x & 63;
+    W.n = re - rb > wave ? (re - rb - wave + NW - 1) / NW : 0;
+    W.row = W.p0 = W.p1 = W.q0 = W.q1 = 0;
+    if (lane < W.n) {
+        W.row = rows[rb + wave + lane * NW];
+        W.p0 = rp0[W.row];
+        W.p1 = rp0[W.row + 1];
+        if (rp1) {
+            W.q0 = rp1[W.row];
+            W.q1 = rp1[W.row + 1];
+        }
+    }
+    return W;
+}
+
+
+// y = S x (MODE 0) or y = b - S x (MODE 1)
+template <typename T, int VEC, int MODE, int NW>
+__global__ void __launch_bounds__(NW * 64) k_saddle_lds(TileView tv, const int32_t* __restrict__ Arp,
+                                                        const T* __restrict__ Aval, const int32_t* __restrict__ Btrp,
+                                                        const T* __restrict__ Btval, const int32_t* __restrict__ Brp,
+                                                        const T* __restrict__ Bval, const T* __restrict__ dp,
+                                                        const T* __restrict__ x, const T* __restrict__ bvec,
+                                                        T* __restrict__ y, int nP2, int J, int MT, int max_s2) {
+    constexpr int JT = kTileJ * VEC;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* xs = (T*)smem_raw;
+    T* ps = xs + (int64_t)max_s2 * 2 * JT;
+    const TileLanes L = tile_lanes<VEC>(MT);
+    const WaveRows W2 = wave_rows(tv.r2, tv.r2_ptr[L.tile], tv.r2_ptr[L.tile + 1], L.wave, NW, Arp, Btrp);
+    const WaveRows W1 = wave_rows(tv.r1, tv.r1_ptr[L.tile], tv.r1_ptr[L.tile + 1], L.wave, NW, Brp, nullptr);
+    const int s20 = tv.s2_ptr[L.tile], s10 = tv.s1_ptr[L.tile];
+    const T* xp = x + 2 * (int64_t)nP2 * J;
+    stage_nodes<T, JT>(xs, tv.s2 + s20, tv.s2_ptr[L.tile + 1] - s20, x + L.j0, 2 * (int64_t)J, 2, J, NW * 64);
+    stage_nodes<T, JT>(ps, tv.s1 + s10, tv.s1_ptr[L.tile + 1] - s10, xp + L.j0, J, 1, 0, NW * 64);
+    __syncthreads();
+    const T* xsc = xs + L.c * JT + L.jj;
+    const T* psc = ps + L.jj;
+    for (int i = 0; i < W2.n; ++i) {
+        T acc0[VEC], acc1[VEC];
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) acc0[q] = 0;
+        lds_gather<T, VEC>(tv.a_loc, Aval, rl(W2.p0, i), rl(W2.p1, i), xsc, 2 * JT, acc0);
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) acc1[q] = acc0[q];
+        lds_gather2<T, VEC, false>(tv.bt_loc, Btval, rl(W2.q0, i), rl(W2.q1, i), psc, JT, acc0, acc1);
+        const int64_t o = (2 * (int64_t)rl(W2.row, i) + L.c) * J + L.j0 + L.jj;
+        T out[VEC];
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) out[q] = L.c ? acc1[q] : acc0[q];
+        if (MODE == 1) {
+            T bv[VEC];
+            vload<T, VEC>(bv, bvec + o);
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) out[q] = bv[q] - out[q];
+        }
+        vstore<T, VEC>(y + o, out);
+    }
+    const int r1b = tv.r1_ptr[L.tile] + L.wave;
+    for (int i = 0; i < W1.n; ++i) {
+        const int k = rl(W1.row, i);
+        T acc0[VEC], acc1[VEC], out[VEC];
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) acc0[q] = acc1[q] = 0;
+        lds_gather2<T, VEC, false>(tv.b_loc, Bval, rl(W1.p0, i), rl(W1.p1, i), xsc, 2 * JT, acc0, acc1);
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) {
+            out[q] = L.c ? acc1[q] : acc0[q];
+            out[q] += __shfl_xor(out[q], 32, 64);   // the two velocity components' contributions
+        }
+        if (L.c == 0) {
+            const T d = dp[k];
+            T v[VEC];
+            lds_load<T, VEC>(v, ps + tv.r1_self[r1b + i * NW] * JT + L.jj);
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) out[q] += d * v[q];
+            const int64_t o = (2 * (int64_t)nP2 + k) * J + L.j0 + L.jj;
+            if (MODE == 1) {
+                T bv[VEC];
+                vload<T, VEC>(bv, bvec + o);
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) out[q] = bv[q] - out[q];
+            }
+            vstore<T, VEC>(y + o, out);
+        }
+    }
+}
+
+// velocity-block Jacobi (operations as k_velo_v).  FIRST stages the pressure
+// part z_p, the other sweeps stage z.
+template <typename T, int VEC, bool FIRST, int NW>
+__global__ void __launch_bounds__(NW * 64) k_velo_lds(TileView tv, const int32_t* __restrict__ rp,
+                                                      const T* __restrict__ val, const T* __restrict__ dinvA,
+                                                      const T* __restrict__ in, const T* __restrict__ zp,
+                                                      T* __restrict__ t, const T* __restrict__ z,
+                                                      T* __restrict__ zo, int J, int MT, T omega) {
+    constexpr int JT = kTileJ * VEC;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* xs = (T*)smem_raw;
+    const TileLanes L = tile_lanes<VEC>(MT);
+    const WaveRows W = wave_rows(tv.r2, tv.r2_ptr[L.tile], tv.r2_ptr[L.tile + 1], L.wave, NW, rp, nullptr);
+    if (FIRST) {
+        const int s10 = tv.s1_ptr[L.tile];
+        stage_nodes<T, JT>(xs, tv.s1 + s10, tv.s1_ptr[L.tile + 1] - s10, zp + L.j0, J, 1, 0, NW * 64);
+    } else {
+        const int s20 = tv.s2_ptr[L.tile];
+        stage_nodes<T, JT>(xs, tv.s2 + s20, tv.s2_ptr[L.tile + 1] - s20, z + L.j0, 2 * (int64_t)J, 2, J, NW * 64);
+    }
+    __syncthreads();
+    const int rb = tv.r2_ptr[L.tile] + L.wave;
+    for (int i = 0; i < W.n; ++i) {
+        const int u = rl(W.row, i);
+        const T dw = omega * dinvA[u];
+        const int64_t o = (2 * (int64_t)u + L.c) * J + L.j0 + L.jj;
+        T acc[VEC];
+        if constexpr (FIRST) {
+            T acc1[VEC];
+            vload<T, VEC>(acc, in + o);   // r_u
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) acc1[q] = acc[q];
+            lds_gather2<T, VEC, true>(tv.bt_loc, val, rl(W.p0, i), rl(W.p1, i), xs + L.jj, JT, acc, acc1);
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) acc[q] = L.c ? acc1[q] : acc[q];
+            vstore<T, VEC>(t + o, acc);
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) acc[q] *= dw;
+            vstore<T, VEC>(zo + o, acc);
+        } else {
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) acc[q] = 0;
+            lds_gather<T, VEC>(tv.a_loc, val, rl(W.p0, i), rl(W.p1, i), xs + L.c * JT + L.jj, 2 * JT, acc);
+            T tv_[VEC], zv[VEC];
+            vload<T, VEC>(tv_, t + o);
+            lds_load<T, VEC>(zv, xs + (tv.r2_self[rb + i * NW] * 2 + L.c) * JT + L.jj);
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) acc[q] = zv[q] + dw * (tv_[q] - acc[q]);
+            vstore<T, VEC>(zo + o, acc);
+        }
     }
 }
 
@@ -823,6 +1708,530 @@ inline RedShape cap_blocks(RedShape rs, int cap) {
     return rs;
 }
 
+// ------------------------------------------------------------------ node-row kernel plans (autotuned)
+// A plan picks, for one operator on one (mesh, J, word size), either the
+// LDS-staged kernels (tile: square row tiles of 8, 12 or 16 half-steps; nw
+// wavefronts per workgroup) or the gather kernels with vec members per lane per
+// load (1, 2 or 4) and g units per wavefront (1, 2 or 4 batched gathers; 0 for
+// one unit per wavefront with per-entry CSR loads).  vec == 0 selects the
+// generic kernels (J not a multiple of 32).  Every candidate performs the same
+// floating-point operations in the same order per member, so the choice changes
+// the speed, not the result.
+struct NodePlan {
+    int vec = 0;
+    int g = 0;
+    int tile = 0;   // > 0: LDS-staged kernels on the tiling of this shape id
+    int nw = 4;     // wavefronts per workgroup of the LDS-staged kernels
+    int deep = 0;   // 1: pipelined gather kernels with g units per wavefront;
+                    // 2: paired-row kernels with g units per wavefront
+};
+
+struct PlanRec {
+    NodePlan p;
+    float us = 0.f;
+};
+
+struct PlanKey {
+    int64_t nP2, nP1, nnzA, nnzB;
+    int J, word, op;
+    bool operator<(const PlanKey& o) const {
+        return std::tie(nP2, nP1, nnzA, nnzB, J, word, op) < std::tie(o.nP2, o.nP1, o.nnzA, o.nnzB, o.J, o.word, o.op);
+    }
+};
+
+std::mutex g_plan_mu;
+std::map<PlanKey, PlanRec> g_plans;
+
+PlanKey plan_key(const DevMesh& m, int J, int word, int op) {
+    return PlanKey{m.nP2, m.nP1, m.nnzA, m.nnzB, J, word, op};
+}
+
+inline int word_max_vec(int word) { return word == 4 ? 4 : 2; }
+
+NodePlan default_plan(const DevMesh& m, int J, int word) {
+    NodePlan p;
+    p.vec = fast_vec(J, word_max_vec(word));
+    p.g = (p.vec && m.max_row <= kMaxRowBatched) ? 1 : 0;
+    return p;
+}
+
+NodePlan get_plan(const DevMesh& m, int J, int word, int op) {
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    auto it = g_plans.find(plan_key(m, J, word, op));
+    return it != g_plans.end() ? it->second.p : default_plan(m, J, word);
+}
+
+// vector loads need 16-byte aligned block bases; otherwise one member per lane
+inline NodePlan align_plan(NodePlan p, bool aligned) {
+    if (!aligned) {
+        p.tile = 0;
+        if (p.vec > 1) p.vec = 1;
+    }
+    return p;
+}
+
+// ------------------------------------------------------------------ row tilings (built on demand)
+std::mutex g_tiling_mu;
+
+int max_lds_bytes() {
+    static int lim = -1;
+    if (lim < 0) {
+        int dev = 0, v = 65536;
+        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+            v = 65536;
+        lim = v;
+    }
+    return lim;
+}
+
+// builds and uploads the tiling of shape id on first use (host synchronous: not under capture)
+mhd_status ensure_tiling(DevMesh& m, int id) {
+    if (id < 1 || id > kTileShapes) return MHD_OK;
+    std::lock_guard<std::mutex> lk(g_tiling_mu);
+    if (m.tiling[id]) return MHD_OK;
+    HostTiling h;
+    build_tiling(m.host, tile_edge(id), tile_edge(id), h);
+    auto* d = new (std::nothrow) DevTiling;
+    if (!d) return MHD_ENOMEM;
+    d->tx = h.tx;
+    d->ty = h.ty;
+    d->ntiles = h.ntiles;
+    d->max_s2 = h.max_s2;
+    d->max_s1 = h.max_s1;
+    d->max_r2 = h.max_r2;
+    d->max_r1 = h.max_r1;
+    auto up = [&](int32_t** p, const std::vector<int32_t>& v) -> mhd_status {
+        const size_t bytes = std::max<size_t>(v.size() * sizeof(int32_t), 256);
+        hipError_t e = hipMalloc((void**)p, bytes);
+        if (e == hipSuccess) {
+            m.allocs.push_back(*p);
+            if (!v.empty()) e = hipMemcpy(*p, v.data(), v.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+        }
+        if (e != hipSuccess) {
+            set_error(std::string("tiling upload: ") + hipGetErrorString(e));
+            return MHD_ENOMEM;
+        }
+        return MHD_OK;
+    };
+    mhd_status rc = MHD_OK;
+    if (!rc) rc = up(&d->r2_ptr, h.r2_ptr);
+    if (!rc) rc = up(&d->r2, h.r2);
+    if (!rc) rc = up(&d->r2_self, h.r2_self);
+    if (!rc) rc = up(&d->r1_ptr, h.r1_ptr);
+    if (!rc) rc = up(&d->r1, h.r1);
+    if (!rc) rc = up(&d->r1_self, h.r1_self);
+    if (!rc) rc = up(&d->s2_ptr, h.s2_ptr);
+    if (!rc) rc = up(&d->s2, h.s2);
+    if (!rc) rc = up(&d->s1_ptr, h.s1_ptr);
+    if (!rc) rc = up(&d->s1, h.s1);
+    if (!rc) rc = up(&d->a_loc, h.a_loc);
+    if (!rc) rc = up(&d->bt_loc, h.bt_loc);
+    if (!rc) rc = up(&d->b_loc, h.b_loc);
+    if (rc) {
+        delete d;
+        return rc;
+    }
+    m.tiling[id] = d;
+    return MHD_OK;
+}
+
+inline TileView tile_view(const DevTiling& t) {
+    return TileView{t.r2_ptr, t.r2, t.r2_self, t.r1_ptr, t.r1, t.r1_self, t.s2_ptr, t.s2, t.s1_ptr, t.s1,
+                    t.a_loc, t.bt_loc, t.b_loc};
+}
+
+// dynamic LDS of the staged kernels: SpMM and Jacobi first / later sweeps
+inline size_t lds_bytes(const DevTiling& t, int op, int word, int vec) {
+    const size_t jt = (size_t)kTileJ * vec * word;
+    if (op == MHD_TUNE_JACOBI_FIRST) return (size_t)t.max_s1 * jt;
+    if (op == MHD_TUNE_JACOBI) return (size_t)t.max_s2 * 2 * jt;
+    return ((size_t)t.max_s2 * 2 + t.max_s1) * jt;
+}
+
+// LDS-staged kernels: members per lane the word size admits for J
+inline bool lds_vec_ok(int J, int word, int vec) {
+    return (vec == 1 || (vec == 2 && word == 4)) && J % (kTileJ * vec) == 0;
+}
+
+// each wavefront keeps the metadata of its rows in one register (<= 64 rows)
+inline bool tile_fits(const DevTiling& t, int nw) { return t.max_r2 <= 64 * nw && t.max_r1 <= 64 * nw; }
+
+template <typename K>
+hipError_t allow_lds(K kernel, size_t bytes) {
+    if (bytes <= 65536) return hipSuccess;
+    return hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <typename F>
+mhd_status with_g(int g, F f) {
+    switch (g) {
+        case 1: return f(std::integral_constant<int, 1>{});
+        case 2: return f(std::integral_constant<int, 2>{});
+        case 4: return f(std::integral_constant<int, 4>{});
+        default: return f(std::integral_constant<int, 0>{});
+    }
+}
+
+template <typename F>
+mhd_status with_gd(int g, F f) {
+    switch (g) {
+        case 2: return f(std::integral_constant<int, 2>{});
+        case 4: return f(std::integral_constant<int, 4>{});
+        case 8: return f(std::integral_constant<int, 8>{});
+        default: return f(std::integral_constant<int, 1>{});
+    }
+}
+
+// rows short enough for the pipelined kernels
+inline bool deep_ok(const DevMesh& m) { return m.max_row <= kDeepA && m.max_row_bt <= kDeepBt; }
+
+// paired-row kernels: J a multiple of 16 members per lane-load, short rows
+inline bool pair_ok(const DevMesh& m, int J, int word) { return m.max_row <= kPairRow && J % (256 / word) == 0; }
+
+template <typename F>
+mhd_status with_gp(int g, F f) {
+    return g == 8 ? f(std::integral_constant<int, 8>{}) : f(std::integral_constant<int, 4>{});
+}
+
+inline dim3 group_grid(int64_t units, int J, int vec, int g) {
+    const int64_t per = (int64_t)(kBlock / 64) * g;
+    return dim3((unsigned)((units + per - 1) / per), J / (32 * vec));
+}
+
+// y = S x (MODE 0) or y = b - S x (MODE 1) with plan p
+template <typename T, int MODE>
+mhd_status launch_saddle_plan(NodePlan p, DevShared& S, const T* x, const T* b, T* y, int J, hipStream_t st) {
+    DevMesh& m = *S.mesh;
+    const int64_t units = (int64_t)m.nP2 + m.nP1;
+    if (p.tile > 0 && m.tiling[p.tile] && lds_vec_ok(J, sizeof(T), p.vec) && tile_fits(*m.tiling[p.tile], p.nw)) {
+        const DevTiling& tl = *m.tiling[p.tile];
+        const int MT = J / (kTileJ * p.vec);
+        const size_t lds = lds_bytes(tl, MHD_TUNE_SADDLE, sizeof(T), p.vec);
+        const dim3 grid((unsigned)((int64_t)tl.ntiles * MT));
+        auto go = [&](auto kern, int threads) -> mhd_status {
+            MHD_HIP(allow_lds(kern, lds));
+            hipLaunchKernelGGL(kern, grid, dim3(threads), lds, st, tile_view(tl), m.A_rowptr, Vals<T>::A(S),
+                               m.Bt_rowptr, Vals<T>::Bt(S), m.B_rowptr, Vals<T>::B(S), Vals<T>::dp(m), x, b, y, m.nP2,
+                               J, MT, tl.max_s2);
+            LAUNCH_CHECK();
+            return MHD_OK;
+        };
+        if constexpr (sizeof(T) == 4) {
+            if (p.vec == 2) return p.nw == 8 ? go(k_saddle_lds<T, 2, MODE, 8>, 512) : go(k_saddle_lds<T, 2, MODE, 4>, 256);
+        }
+        return p.nw == 8 ? go(k_saddle_lds<T, 1, MODE, 8>, 512) : go(k_saddle_lds<T, 1, MODE, 4>, 256);
+    }
+    if (p.tile > 0) p = default_plan(m, J, sizeof(T));
+    if (p.deep == 2 && pair_ok(m, J, sizeof(T))) {
+        return with_gp(p.g, [&](auto Gc) -> mhd_status {
+            constexpr int GG = decltype(Gc)::value;
+            const int wP2 = (m.nP2 + GG - 1) / GG, wP1 = (m.nP1 + GG - 1) / GG;
+            const dim3 grid((unsigned)((wP2 + wP1 + 3) / 4), J / (256 / (int)sizeof(T)));
+            hipLaunchKernelGGL((k_saddle_h<T, MODE, GG>), grid, dim3(kBlock), 0, st, m.A_rowptr, m.A_col,
+                               Vals<T>::A(S), m.Bt_rowptr, m.Bt_col, Vals<T>::Bt(S), m.B_rowptr, m.B_col,
+                               Vals<T>::B(S), Vals<T>::dp(m), x, b, y, m.nP2, m.nP1, J, wP2);
+            LAUNCH_CHECK();
+            return MHD_OK;
+        });
+    }
+    if (p.deep == 1 && p.vec && deep_ok(m)) {
+        return with_vec<T>(p.vec, [&](auto V) -> mhd_status {
+            constexpr int VV = decltype(V)::value;
+            return with_gd(p.g, [&](auto Gc) -> mhd_status {
+                constexpr int GG = decltype(Gc)::value;
+                hipLaunchKernelGGL((k_saddle_p<T, VV, MODE, GG>), group_grid(units, J, VV, GG), dim3(kBlock), 0, st,
+                                   m.A_rowptr, m.A_col, Vals<T>::A(S), m.Bt_rowptr, m.Bt_col, Vals<T>::Bt(S),
+                                   m.B_rowptr, m.B_col, Vals<T>::B(S), Vals<T>::dp(m), x, b, y, m.nP2, m.nP1, J);
+                LAUNCH_CHECK();
+                return MHD_OK;
+            });
+        });
+    }
+    if (p.deep) p = default_plan(m, J, sizeof(T));
+    if (p.vec == 0) {
+        const int JP = pick_jp(J);
+        hipLaunchKernelGGL((k_saddle<T, MODE>), dim3(grid_for(units, JP)), dim3(kBlock), 0, st, m.A_rowptr, m.A_col,
+                           Vals<T>::A(S), m.Bt_rowptr, m.Bt_col, Vals<T>::Bt(S), m.B_rowptr, m.B_col, Vals<T>::B(S),
+                           Vals<T>::dp(m), x, b, y, m.nP2, m.nP1, J, JP);
+        LAUNCH_CHECK();
+        return MHD_OK;
+    }
+    return with_vec<T>(p.vec, [&](auto V) -> mhd_status {
+        constexpr int VV = decltype(V)::value;
+        return with_g(p.g, [&](auto Gc) -> mhd_status {
+            constexpr int GG = decltype(Gc)::value;
+            if constexpr (GG == 0) {
+                hipLaunchKernelGGL((k_saddle_v<T, VV, MODE>), node_grid(units, J, VV), dim3(kBlock), 0, st,
+                                   m.A_rowptr, m.A_col, Vals<T>::A(S), m.Bt_rowptr, m.Bt_col, Vals<T>::Bt(S),
+                                   m.B_rowptr, m.B_col, Vals<T>::B(S), Vals<T>::dp(m), x, b, y, m.nP2, m.nP1, J);
+            } else {
+                hipLaunchKernelGGL((k_saddle_g<T, VV, MODE, GG>), group_grid(units, J, VV, GG), dim3(kBlock), 0, st,
+                                   m.A_rowptr, m.A_col, Vals<T>::A(S), m.Bt_rowptr, m.Bt_col, Vals<T>::Bt(S),
+                                   m.B_rowptr, m.B_col, Vals<T>::B(S), Vals<T>::dp(m), x, b, y, m.nP2, m.nP1, J);
+            }
+            LAUNCH_CHECK();
+            return MHD_OK;
+        });
+    });
+}
+
+// velocity-block Jacobi with plan p.  FIRST: t = r_u - B^T z_p, zo = w D^-1 t
+// (in = r_u); else zo = z + w D^-1 (t - A z).
+template <typename T, bool FIRST>
+mhd_status launch_velo_plan(NodePlan p, DevShared& S, const T* in, const T* zp, T* t, const T* z, T* zo, int J,
+                            hipStream_t st, T omega) {
+    DevMesh& m = *S.mesh;
+    const int32_t* rp = FIRST ? m.Bt_rowptr : m.A_rowptr;
+    const int32_t* col = FIRST ? m.Bt_col : m.A_col;
+    const T* val = FIRST ? Vals<T>::Bt(S) : Vals<T>::A(S);
+    if (p.tile > 0 && m.tiling[p.tile] && lds_vec_ok(J, sizeof(T), p.vec) && tile_fits(*m.tiling[p.tile], p.nw)) {
+        const DevTiling& tl = *m.tiling[p.tile];
+        const int MT = J / (kTileJ * p.vec);
+        const size_t lds = lds_bytes(tl, FIRST ? MHD_TUNE_JACOBI_FIRST : MHD_TUNE_JACOBI, sizeof(T), p.vec);
+        const dim3 grid((unsigned)((int64_t)tl.ntiles * MT));
+        auto go = [&](auto kern, int threads) -> mhd_status {
+            MHD_HIP(allow_lds(kern, lds));
+            hipLaunchKernelGGL(kern, grid, dim3(threads), lds, st, tile_view(tl), rp, val, Vals<T>::dA(S), in, zp, t,
+                               z, zo, J, MT, omega);
+            LAUNCH_CHECK();
+            return MHD_OK;
+        };
+        if constexpr (sizeof(T) == 4) {
+            if (p.vec == 2) return p.nw == 8 ? go(k_velo_lds<T, 2, FIRST, 8>, 512) : go(k_velo_lds<T, 2, FIRST, 4>, 256);
+        }
+        return p.nw == 8 ? go(k_velo_lds<T, 1, FIRST, 8>, 512) : go(k_velo_lds<T, 1, FIRST, 4>, 256);
+    }
+    if (p.tile > 0) p = default_plan(m, J, sizeof(T));
+    if (p.deep == 2 && pair_ok(m, J, sizeof(T))) {
+        return with_gp(p.g, [&](auto Gc) -> mhd_status {
+            constexpr int GG = decltype(Gc)::value;
+            const int w = (m.nP2 + GG - 1) / GG;
+            const dim3 grid((unsigned)((w + 3) / 4), J / (256 / (int)sizeof(T)));
+            hipLaunchKernelGGL((k_velo_h<T, FIRST, GG>), grid, dim3(kBlock), 0, st, rp, col, val, Vals<T>::dA(S), in,
+                               zp, t, z, zo, m.nP2, J, omega);
+            LAUNCH_CHECK();
+            return MHD_OK;
+        });
+    }
+    if (p.deep == 1 && p.vec && deep_ok(m)) {
+        return with_vec<T>(p.vec, [&](auto V) -> mhd_status {
+            constexpr int VV = decltype(V)::value;
+            return with_gd(p.g, [&](auto Gc) -> mhd_status {
+                constexpr int GG = decltype(Gc)::value;
+                hipLaunchKernelGGL((k_velo_p<T, VV, FIRST, GG>), group_grid(m.nP2, J, VV, GG), dim3(kBlock), 0, st,
+                                   rp, col, val, Vals<T>::dA(S), in, zp, t, z, zo, m.nP2, J, omega);
+                LAUNCH_CHECK();
+                return MHD_OK;
+            });
+        });
+    }
+    if (p.deep) p = default_plan(m, J, sizeof(T));
+    if (p.vec == 0) {
+        const int JP = pick_jp(J);
+        if (FIRST)
+            hipLaunchKernelGGL((k_velo_first<T>), dim3(grid_for(m.nP2, JP)), dim3(kBlock), 0, st, rp, col, val,
+                               Vals<T>::dA(S), in, zp, t, zo, m.nP2, J, JP, omega);
+        else
+            hipLaunchKernelGGL((k_velo_sweep<T>), dim3(grid_for(m.nP2, JP)), dim3(kBlock), 0, st, rp, col, val,
+                               Vals<T>::dA(S), (const T*)t, z, zo, m.nP2, J, JP, omega);
+        LAUNCH_CHECK();
+        return MHD_OK;
+    }
+    return with_vec<T>(p.vec, [&](auto V) -> mhd_status {
+        constexpr int VV = decltype(V)::value;
+        return with_g(p.g, [&](auto Gc) -> mhd_status {
+            constexpr int GG = decltype(Gc)::value;
+            if constexpr (GG == 0) {
+                hipLaunchKernelGGL((k_velo_v<T, VV, FIRST>), node_grid(m.nP2, J, VV), dim3(kBlock), 0, st, rp, col,
+                                   val, Vals<T>::dA(S), in, zp, t, z, zo, m.nP2, J, omega);
+            } else {
+                hipLaunchKernelGGL((k_velo_g<T, VV, FIRST, GG>), group_grid(m.nP2, J, VV, GG), dim3(kBlock), 0, st,
+                                   rp, col, val, Vals<T>::dA(S), in, zp, t, z, zo, m.nP2, J, omega);
+            }
+            LAUNCH_CHECK();
+            return MHD_OK;
+        });
+    });
+}
+
+// Times every candidate plan of one operator on the handle's workspace buffers
+// (contents irrelevant: zeroed first) and records the fastest.  Synchronises st.
+template <typename T>
+mhd_status tune_op(DevShared& S, int J, int op, hipStream_t st, std::vector<mhd_tune_entry>* rep) {
+    DevMesh& m = *S.mesh;
+    const int word = (int)sizeof(T);
+    std::vector<NodePlan> cands;
+    for (int v = word_max_vec(word); v >= 1; v >>= 1) {
+        if (J % (32 * v)) continue;
+        cands.push_back(NodePlan{v, 0, 0, 4, 0});
+        if (m.max_row <= kMaxRowBatched)
+            for (int g : {1, 2, 4}) cands.push_back(NodePlan{v, g, 0, 4, 0});
+        if (deep_ok(m))
+            for (int g : {1, 2, 4, 8}) cands.push_back(NodePlan{v, g, 0, 4, 1});
+    }
+    if (pair_ok(m, J, word))
+        for (int g : {4, 8}) cands.push_back(NodePlan{16 / word, g, 0, 4, 2});
+    for (int v : {2, 1}) {
+        if (!lds_vec_ok(J, word, v)) continue;
+        for (int id = 1; id <= kTileShapes; ++id) {
+            mhd_status rc = ensure_tiling(m, id);
+            if (rc) return rc;
+            if (lds_bytes(*m.tiling[id], op, word, v) > (size_t)max_lds_bytes()) continue;
+            for (int nw : {4, 8})
+                if (tile_fits(*m.tiling[id], nw)) cands.push_back(NodePlan{v, 0, id, nw, 0});
+        }
+    }
+    PlanRec best;
+    if (!cands.empty()) {
+        T* x = (T*)S.gw.zbuf;
+        T* y = (T*)S.gw.wbuf;
+        T* t = (T*)S.gw.tbuf;
+        T* b = (T*)S.gw.r64;
+        const size_t bytes = sizeof(T) * (size_t)m.n * J;
+        MHD_HIP(hipMemsetAsync(x, 0, bytes, st));
+        MHD_HIP(hipMemsetAsync(t, 0, bytes, st));
+        MHD_HIP(hipMemsetAsync(b, 0, bytes, st));
+        const T* xp = x + 2 * (int64_t)m.nP2 * J;
+        auto run = [&](const NodePlan& p) -> mhd_status {
+            switch (op) {
+                case MHD_TUNE_SADDLE: return launch_saddle_plan<T, 0>(p, S, x, nullptr, y, J, st);
+                case MHD_TUNE_RESIDUAL:
+                    if constexpr (sizeof(T) == 8) return launch_saddle_plan<T, 1>(p, S, x, b, y, J, st);
+                    return MHD_EINVAL;
+                case MHD_TUNE_JACOBI_FIRST: return launch_velo_plan<T, true>(p, S, x, xp, t, nullptr, y, J, st, (T)0.7);
+                default: return launch_velo_plan<T, false>(p, S, nullptr, nullptr, t, x, y, J, st, (T)0.7);
+            }
+        };
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        MHD_HIP(hipEventCreate(&e0));
+        MHD_HIP(hipEventCreate(&e1));
+        mhd_status rc = MHD_OK;
+        best.us = 1e30f;
+        std::vector<float> times(cands.size(), 0.f);
+        constexpr int kReps = 10;
+        for (size_t c = 0; c < cands.size() && rc == MHD_OK; ++c) {
+            if (run(cands[c]) != MHD_OK) {   // warm-up; a shape the device refuses is skipped
+                (void)hipGetLastError();
+                times[c] = -1.f;
+                continue;
+            }
+            if (hipEventRecord(e0, st) != hipSuccess) rc = MHD_EHIP;
+            for (int r = 0; r < kReps && rc == MHD_OK; ++r) rc = run(cands[c]);
+            if (rc == MHD_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+                rc = MHD_EHIP;
+            float ms = 0.f;
+            if (rc == MHD_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = MHD_EHIP;
+            times[c] = 1000.f * ms / kReps;
+            if (rc == MHD_OK && times[c] < best.us) best = PlanRec{cands[c], times[c]};
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (rc) {
+            if (rc == MHD_EHIP) set_error("autotune: HIP event failure");
+            return rc;
+        }
+        if (rep)
+            for (size_t c = 0; c < cands.size(); ++c) {
+                const NodePlan& q = cands[c];
+                const bool same = q.tile == best.p.tile && q.vec == best.p.vec && q.deep == best.p.deep &&
+                                  (q.tile ? q.nw == best.p.nw : q.g == best.p.g);
+                rep->push_back(mhd_tune_entry{op, word, J, q.vec, q.tile ? 0 : q.g, q.deep, q.tile ? tile_edge(q.tile) : 0,
+                                              q.tile ? q.nw : 0, times[c], same ? 1 : 0});
+            }
+    }
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    g_plans[plan_key(m, J, word, op)] = best;
+    return MHD_OK;
+}
+
+bool plan_cached(const DevMesh& m, int J, int word, int op) {
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    return g_plans.count(plan_key(m, J, word, op)) != 0;
+}
+
+}  // namespace
+
+// Tunes the node-row operators a solve of this precision uses (inner SpMM and
+// Jacobi sweeps in the inner word size, FP64 residual).  Without force, only
+// missing plans are tuned.  Does nothing (and returns MHD_OK) while st is being
+// captured: the cached or default plans are used then.
+// Pins the plan of one operator for (mesh, J, word size), replacing the tuned one.
+mhd_status set_plan(DevShared& S, int J, int precision, int op, int vec, int group, int deep, int tile, int waves) {
+    DevMesh& m = *S.mesh;
+    const int word = (precision == MHD_FP32_IR && op != MHD_TUNE_RESIDUAL) ? 4 : 8;
+    if (op < MHD_TUNE_SADDLE || op > MHD_TUNE_JACOBI) {
+        set_error("mhd_ens_set_plan: unknown operator");
+        return MHD_EINVAL;
+    }
+    if (deep == 2) {
+        if (tile || !(group == 4 || group == 8) || !pair_ok(m, J, word)) {
+            set_error("mhd_ens_set_plan: paired rows need group 4 or 8, J a multiple of 256 / word size and rows of "
+                      "<= 32 entries");
+            return MHD_EINVAL;
+        }
+        std::lock_guard<std::mutex> lk(g_plan_mu);
+        g_plans[plan_key(m, J, word, op)] = PlanRec{NodePlan{16 / word, group, 0, 4, 2}, 0.f};
+        return MHD_OK;
+    }
+    if (!(vec == 0 || vec == 1 || vec == 2 || (vec == 4 && word == 4)) || (vec && J % (32 * vec))) {
+        set_error("mhd_ens_set_plan: vec must be 0 or 1, 2 (4 for FP32) with J a multiple of 32 vec");
+        return MHD_EINVAL;
+    }
+    if (deep) {
+        if (!vec || !(group == 1 || group == 2 || group == 4 || group == 8) || !deep_ok(m)) {
+            set_error("mhd_ens_set_plan: pipelined gathers need vec > 0, group 1, 2, 4 or 8 and rows of <= 24 (B^T: "
+                      "8) entries");
+            return MHD_EINVAL;
+        }
+    } else if (!(group == 0 || group == 1 || group == 2 || group == 4) || (group && m.max_row > kMaxRowBatched)) {
+        set_error("mhd_ens_set_plan: group must be 0, 1, 2 or 4 (batched gathers need rows of <= 56 entries)");
+        return MHD_EINVAL;
+    }
+    int id = 0;
+    if (tile) {
+        for (int k = 1; k <= kTileShapes; ++k)
+            if (tile_edge(k) == tile) id = k;
+        if (!id || !(waves == 4 || waves == 8) || !lds_vec_ok(J, word, vec)) {
+            set_error("mhd_ens_set_plan: tile must be 0, 8, 12 or 16 with waves 4 or 8, vec 1 (or 2 for FP32) and J a "
+                      "multiple of 32 vec");
+            return MHD_EINVAL;
+        }
+        mhd_status rc = ensure_tiling(m, id);
+        if (rc) return rc;
+        if (lds_bytes(*m.tiling[id], op, word, vec) > (size_t)max_lds_bytes() || !tile_fits(*m.tiling[id], waves)) {
+            set_error("mhd_ens_set_plan: tile needs more LDS or rows per wavefront than a workgroup may use");
+            return MHD_EINVAL;
+        }
+    }
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    g_plans[plan_key(m, J, word, op)] = PlanRec{NodePlan{vec, (vec && !id) ? group : 0, id, waves, (vec && !id) ? deep : 0}, 0.f};
+    return MHD_OK;
+}
+
+mhd_status autotune(DevShared& S, int J, int precision, hipStream_t st, bool force, std::vector<mhd_tune_entry>* rep) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    MHD_HIP(hipStreamIsCapturing(st, &cs));
+    if (cs != hipStreamCaptureStatusNone) return MHD_OK;
+    DevMesh& m = *S.mesh;
+    const int word = precision == MHD_FP32_IR ? 4 : 8;
+    mhd_status rc;
+    for (int op : {MHD_TUNE_SADDLE, MHD_TUNE_JACOBI_FIRST, MHD_TUNE_JACOBI}) {
+        if (!force && plan_cached(m, J, word, op)) continue;
+        rc = word == 4 ? tune_op<float>(S, J, op, st, rep) : tune_op<double>(S, J, op, st, rep);
+        if (rc) return rc;
+    }
+    if (force || !plan_cached(m, J, 8, MHD_TUNE_RESIDUAL))
+        if ((rc = tune_op<double>(S, J, MHD_TUNE_RESIDUAL, st, rep))) return rc;
+    // plans are shared by meshes of equal size: make sure this mesh holds the tilings they use
+    for (int op : {MHD_TUNE_SADDLE, MHD_TUNE_JACOBI_FIRST, MHD_TUNE_JACOBI, MHD_TUNE_RESIDUAL}) {
+        const NodePlan p = get_plan(m, J, op == MHD_TUNE_RESIDUAL ? 8 : word, op);
+        if (p.tile && (rc = ensure_tiling(*S.mesh, p.tile))) return rc;
+    }
+    return MHD_OK;
+}
+
+namespace {
+
 // ------------------------------------------------------------------ host-side operators
 template <typename T>
 struct Ops {
@@ -831,30 +2240,19 @@ struct Ops {
     hipStream_t st;
     int JP;
 
-    Ops(DevShared& s, int j, hipStream_t stream) : S(s), J(j), st(stream), JP(pick_jp(j)) {}
+    NodePlan p_saddle, p_first, p_sweep;   // autotuned node-row kernels for this (mesh, J, word size)
+
+    Ops(DevShared& s, int j, hipStream_t stream) : S(s), J(j), st(stream), JP(pick_jp(j)) {
+        const int word = (int)sizeof(T);
+        p_saddle = get_plan(*S.mesh, J, word, MHD_TUNE_SADDLE);
+        p_first = get_plan(*S.mesh, J, word, MHD_TUNE_JACOBI_FIRST);
+        p_sweep = get_plan(*S.mesh, J, word, MHD_TUNE_JACOBI);
+    }
 
     mhd_status saddle(const T* x, T* y) {
-        DevMesh& m = *S.mesh;
-        int64_t units = (int64_t)m.nP2 + m.nP1;
         timer_mark(st, true);
-        mhd_status rc = MHD_OK;
         const bool aligned = (((uintptr_t)x | (uintptr_t)y) % 16) == 0;
-        const int fv = fast_vec(J, aligned ? (sizeof(T) == 4 ? 4 : 2) : 1);
-        if (fv) {
-            rc = with_vec<T>(fv, [&](auto V) -> mhd_status {
-                hipLaunchKernelGGL((k_saddle_v<T, decltype(V)::value, 0>), node_grid(units, J, fv), dim3(kBlock), 0,
-                                   st, m.A_rowptr, m.A_col, Vals<T>::A(S), m.Bt_rowptr, m.Bt_col, Vals<T>::Bt(S),
-                                   m.B_rowptr, m.B_col, Vals<T>::B(S), Vals<T>::dp(m), x, (const T*)nullptr, y, m.nP2,
-                                   m.nP1, J);
-                LAUNCH_CHECK();
-                return MHD_OK;
-            });
-        } else {
-            hipLaunchKernelGGL((k_saddle<T, 0>), dim3(grid_for(units, JP)), dim3(kBlock), 0, st, m.A_rowptr, m.A_col,
-                               Vals<T>::A(S), m.Bt_rowptr, m.Bt_col, Vals<T>::Bt(S), m.B_rowptr, m.B_col,
-                               Vals<T>::B(S), Vals<T>::dp(m), x, (const T*)nullptr, y, m.nP2, m.nP1, J, JP);
-            LAUNCH_CHECK();
-        }
+        mhd_status rc = launch_saddle_plan<T, 0>(align_plan(p_saddle, aligned), S, x, nullptr, y, J, st);
         if (rc) return rc;
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
         if (g_timer.on && hipStreamIsCapturing(st, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone) {
@@ -922,34 +2320,14 @@ struct Ops {
         T* t = (T*)S.gw.tbuf;
         T* za = z;
         T* zb = (T*)S.gw.z2buf;
-        const int fv = fast_vec(J, sizeof(T) == 4 ? 4 : 2);
-        if (fv) {
-            rc = with_vec<T>(fv, [&](auto V) -> mhd_status {
-                constexpr int VV = decltype(V)::value;
-                hipLaunchKernelGGL((k_velo_v<T, VV, true>), node_grid(m.nP2, J, fv), dim3(kBlock), 0, st,
-                                   m.Bt_rowptr, m.Bt_col, Vals<T>::Bt(S), Vals<T>::dA(S), v, (const T*)zp, t,
-                                   (const T*)nullptr, za, m.nP2, J, omega);
-                LAUNCH_CHECK();
-                for (int s = 1; s < sweeps; ++s) {
-                    hipLaunchKernelGGL((k_velo_v<T, VV, false>), node_grid(m.nP2, J, fv), dim3(kBlock), 0, st,
-                                       m.A_rowptr, m.A_col, Vals<T>::A(S), Vals<T>::dA(S), (const T*)nullptr,
-                                       (const T*)nullptr, t, (const T*)za, zb, m.nP2, J, omega);
-                    LAUNCH_CHECK();
-                    std::swap(za, zb);
-                }
-                return MHD_OK;
-            });
-            if (rc) return rc;
-        } else {
-            hipLaunchKernelGGL((k_velo_first<T>), dim3(grid_for(m.nP2, JP)), dim3(kBlock), 0, st, m.Bt_rowptr,
-                               m.Bt_col, Vals<T>::Bt(S), Vals<T>::dA(S), v, zp, t, za, m.nP2, J, JP, omega);
-            LAUNCH_CHECK();
-            for (int s = 1; s < sweeps; ++s) {
-                hipLaunchKernelGGL((k_velo_sweep<T>), dim3(grid_for(m.nP2, JP)), dim3(kBlock), 0, st, m.A_rowptr,
-                                   m.A_col, Vals<T>::A(S), Vals<T>::dA(S), t, za, zb, m.nP2, J, JP, omega);
-                LAUNCH_CHECK();
-                std::swap(za, zb);
-            }
+        const bool aligned = (((uintptr_t)v | (uintptr_t)z | (uintptr_t)t | (uintptr_t)zb) % 16) == 0;
+        if ((rc = launch_velo_plan<T, true>(align_plan(p_first, aligned), S, v, zp, t, nullptr, za, J, st, omega)))
+            return rc;
+        for (int s = 1; s < sweeps; ++s) {
+            if ((rc = launch_velo_plan<T, false>(align_plan(p_sweep, aligned), S, nullptr, nullptr, t, za, zb, J, st,
+                                                 omega)))
+                return rc;
+            std::swap(za, zb);
         }
         if (za != z) {
             hipError_t e = hipMemcpyAsync(z, za, sizeof(T) * (size_t)2 * m.nP2 * J, hipMemcpyDeviceToDevice, st);
@@ -1206,31 +2584,16 @@ mhd_status alloc_gmres(DevShared& S, int restart) {
 
 mhd_status solve_shared(DevShared& S, const double* rhs, double* x, int J, const mhd_solver_opts& o,
                         mhd_solve_stats* st, hipStream_t s) {
+    mhd_status rc = autotune(S, J, o.precision, s, false, nullptr);
+    if (rc) return rc;
     if (o.precision == MHD_FP32_IR) return gmres_solve<float>(S, rhs, x, J, o, st, s);
     return gmres_solve<double>(S, rhs, x, J, o, st, s);
 }
 
 mhd_status saddle_residual64(DevShared& S, const double* b, const double* x, double* r, int J, hipStream_t st) {
-    DevMesh& m = *S.mesh;
-    const int64_t units = (int64_t)m.nP2 + m.nP1;
-    const bool aligned = ((uintptr_t)b % 16 == 0) && ((uintptr_t)x % 16 == 0);
-    const int fv = aligned ? fast_vec(J, 2) : (fast_vec(J, 1) ? 1 : 0);
-    if (fv == 2) {
-        hipLaunchKernelGGL((k_saddle_v<double, 2, 1>), node_grid(units, J, 2), dim3(kBlock), 0, st, m.A_rowptr,
-                           m.A_col, Vals<double>::A(S), m.Bt_rowptr, m.Bt_col, Vals<double>::Bt(S), m.B_rowptr, m.B_col, Vals<double>::B(S), m.diagp, x, b,
-                           r, m.nP2, m.nP1, J);
-    } else if (fv == 1) {
-        hipLaunchKernelGGL((k_saddle_v<double, 1, 1>), node_grid(units, J, 1), dim3(kBlock), 0, st, m.A_rowptr,
-                           m.A_col, Vals<double>::A(S), m.Bt_rowptr, m.Bt_col, Vals<double>::Bt(S), m.B_rowptr, m.B_col, Vals<double>::B(S), m.diagp, x, b,
-                           r, m.nP2, m.nP1, J);
-    } else {
-        int JP = pick_jp(J);
-        hipLaunchKernelGGL((k_saddle<double, 1>), dim3(grid_for(units, JP)), dim3(kBlock), 0, st, m.A_rowptr, m.A_col,
-                           Vals<double>::A(S), m.Bt_rowptr, m.Bt_col, Vals<double>::Bt(S), m.B_rowptr, m.B_col, Vals<double>::B(S), m.diagp, x, b, r,
-                           m.nP2, m.nP1, J, JP);
-    }
-    LAUNCH_CHECK();
-    return MHD_OK;
+    const bool aligned = (((uintptr_t)b | (uintptr_t)x | (uintptr_t)r) % 16) == 0;
+    const NodePlan p = align_plan(get_plan(*S.mesh, J, 8, MHD_TUNE_RESIDUAL), aligned);
+    return launch_saddle_plan<double, 1>(p, S, x, b, r, J, st);
 }
 
 hipError_t launch_reduce_rows(const double* partial, int nblk, int64_t width, double* out, hipStream_t s) {

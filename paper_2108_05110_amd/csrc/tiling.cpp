@@ -1,0 +1,93 @@
+// Row tiles of the saddle-point operator for the LDS-staged SpMM and Jacobi
+// kernels (host side).  Rows are grouped by the rectangle of tx x ty
+// half-steps their node lies in; each tile lists the node values its rows read
+// (the union of their column indices), and every CSR entry gets the position
+// of its column in its row's tile list.
+#include <algorithm>
+#include <cmath>
+
+#include "common.h"
+
+namespace mhd {
+
+void build_tiling(const HostMesh& m, int tx, int ty, HostTiling& t) {
+    t = HostTiling{};
+    t.tx = tx;
+    t.ty = ty;
+    const int nP2 = m.nP2, nP1 = m.nP1;
+    // half-step coordinates and rectangle of every P2 node
+    int hxmax = 0, hymax = 0;
+    std::vector<int> hx(nP2), hy(nP2);
+    for (int i = 0; i < nP2; ++i) {
+        hx[i] = (int)std::lround(2.0 * (m.xy[2 * (size_t)i] - m.x0) / m.h);
+        hy[i] = (int)std::lround(2.0 * (m.xy[2 * (size_t)i + 1] - m.y0) / m.h);
+        hxmax = std::max(hxmax, hx[i]);
+        hymax = std::max(hymax, hy[i]);
+    }
+    const int gx = hxmax / tx + 1, gy = hymax / ty + 1;
+    std::vector<int> rect(nP2);
+    for (int i = 0; i < nP2; ++i) rect[i] = (hy[i] / ty) * gx + hx[i] / tx;
+    std::vector<int32_t> p2_of_p1(nP1, -1);
+    for (int i = 0; i < nP2; ++i)
+        if (m.p1_of_p2[i] >= 0) p2_of_p1[m.p1_of_p2[i]] = i;
+    // rows of every rectangle, ascending
+    std::vector<std::vector<int32_t>> rows2((size_t)gx * gy), rows1((size_t)gx * gy);
+    for (int i = 0; i < nP2; ++i) rows2[rect[i]].push_back(i);
+    for (int k = 0; k < nP1; ++k) rows1[rect[p2_of_p1[k]]].push_back(k);
+
+    t.a_loc.assign(m.A.col.size(), 0);
+    t.bt_loc.assign(m.Bt.col.size(), 0);
+    t.b_loc.assign(m.B.col.size(), 0);
+    t.r2_ptr.push_back(0);
+    t.r1_ptr.push_back(0);
+    t.s2_ptr.push_back(0);
+    t.s1_ptr.push_back(0);
+    std::vector<int32_t> loc2(nP2, -1), loc1(nP1, -1);
+    std::vector<int32_t> st2, st1;
+    for (size_t r = 0; r < rows2.size(); ++r) {
+        const auto& R2 = rows2[r];
+        const auto& R1 = rows1[r];
+        if (R2.empty() && R1.empty()) continue;
+        st2.clear();
+        st1.clear();
+        for (int32_t u : R2) {
+            for (int32_t p = m.A.rowptr[u]; p < m.A.rowptr[u + 1]; ++p) st2.push_back(m.A.col[p]);
+            for (int32_t p = m.Bt.rowptr[u]; p < m.Bt.rowptr[u + 1]; ++p) st1.push_back(m.Bt.col[p]);
+            st2.push_back(u);
+        }
+        for (int32_t k : R1) {
+            for (int32_t q = m.B.rowptr[k]; q < m.B.rowptr[k + 1]; ++q) st2.push_back(m.B.col[q]);
+            st1.push_back(k);
+        }
+        std::sort(st2.begin(), st2.end());
+        st2.erase(std::unique(st2.begin(), st2.end()), st2.end());
+        std::sort(st1.begin(), st1.end());
+        st1.erase(std::unique(st1.begin(), st1.end()), st1.end());
+        for (size_t s = 0; s < st2.size(); ++s) loc2[st2[s]] = (int32_t)s;
+        for (size_t s = 0; s < st1.size(); ++s) loc1[st1[s]] = (int32_t)s;
+        for (int32_t u : R2) {
+            for (int32_t p = m.A.rowptr[u]; p < m.A.rowptr[u + 1]; ++p) t.a_loc[p] = loc2[m.A.col[p]];
+            for (int32_t p = m.Bt.rowptr[u]; p < m.Bt.rowptr[u + 1]; ++p) t.bt_loc[p] = loc1[m.Bt.col[p]];
+            t.r2.push_back(u);
+            t.r2_self.push_back(loc2[u]);
+        }
+        for (int32_t k : R1) {
+            for (int32_t q = m.B.rowptr[k]; q < m.B.rowptr[k + 1]; ++q) t.b_loc[q] = loc2[m.B.col[q]];
+            t.r1.push_back(k);
+            t.r1_self.push_back(loc1[k]);
+        }
+        t.s2.insert(t.s2.end(), st2.begin(), st2.end());
+        t.s1.insert(t.s1.end(), st1.begin(), st1.end());
+        t.r2_ptr.push_back((int32_t)t.r2.size());
+        t.r1_ptr.push_back((int32_t)t.r1.size());
+        t.s2_ptr.push_back((int32_t)t.s2.size());
+        t.s1_ptr.push_back((int32_t)t.s1.size());
+        t.max_s2 = std::max(t.max_s2, (int)st2.size());
+        t.max_s1 = std::max(t.max_s1, (int)st1.size());
+        t.max_r2 = std::max(t.max_r2, (int)R2.size());
+        t.max_r1 = std::max(t.max_r1, (int)R1.size());
+        ++t.ntiles;
+    }
+}
+
+}  // namespace mhd
