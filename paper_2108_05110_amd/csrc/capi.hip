@@ -107,6 +107,8 @@ mhd_status upload_csr(std::vector<void*>& list, DevCSR<double>& d, const HostCSR
     d.nrows = h.nrows;
     d.ncols = h.ncols;
     d.nnz = h.nnz();
+    d.max_row = 0;
+    for (size_t i = 0; i + 1 < h.rowptr.size(); ++i) d.max_row = std::max(d.max_row, h.rowptr[i + 1] - h.rowptr[i]);
     mhd_status rc;
     if ((rc = upload(list, &d.rowptr, h.rowptr))) return rc;
     if ((rc = upload(list, &d.col, h.col))) return rc;

@@ -24,6 +24,7 @@ constexpr int kMaxJ = 4096;        // member count limit of one handle
 template <typename T>
 struct DevCSR {
     int64_t nrows = 0, ncols = 0, nnz = 0;
+    int max_row = 0;              // longest row
     int32_t* rowptr = nullptr;
     int32_t* col = nullptr;
     double* val = nullptr;
@@ -116,6 +117,7 @@ struct GmresWork {
     int nblk_cap = 512;           // blocks of the column-reduction kernels for this J_max
     double* host_res = nullptr;   // pinned host copy (J)
     std::vector<void*> mg_x, mg_x2, mg_b, mg_r;   // per level (n_l x Jmax, sized for double)
+    void* dense_part = nullptr;   // partial products of the coarsest dense solve (kDenseKS x n_c x Jmax)
     void** dptrs = nullptr;       // device array of the basis block pointers
 };
 

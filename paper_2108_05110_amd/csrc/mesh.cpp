@@ -36,6 +36,10 @@ struct Grid {
     }
 };
 
+// the pressure hierarchy stops at a level of at most this many vertices, which
+// is solved with its dense inverse (33 x 33 vertices of a unit-square level)
+constexpr int kCoarseMax = 1100;
+
 Grid make_grid(const mhd_mesh_desc* d, int level) {
     Grid g{};
     int s = 1 << level;
@@ -535,7 +539,7 @@ mhd_status build_mesh(const mhd_mesh_desc* d, HostMesh& m, bool full) {
             can_halve = (cur.nx % 2 == 0) && cur.nx >= 4;
         else
             can_halve = ((d->nx >> level) % 2 == 0);
-        if (cur.n <= 100 || !can_halve) break;
+        if (cur.n <= kCoarseMax || !can_halve) break;
         ++level;
     }
     m.pfix = fixed[0];

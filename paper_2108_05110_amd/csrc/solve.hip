@@ -909,6 +909,173 @@ __global__ void __launch_bounds__(kBlock) k_velo_h(const int32_t* __restrict__ r
     }
 }
 
+// ------------------------------------------------------------------ multigrid kernels
+// Packed-row CSR kernel for the pressure multigrid: LPR lanes per row, each
+// lane V = 256 / (LPR sizeof(T)) consecutive members, so one load instruction
+// fetches 64 / LPR member rows of a tile of MJ = 256 / sizeof(T) members.
+// Lane h of a row's group first loads the row's h-th column and value; they
+// are broadcast with ds_bpermute.  Rows of at most LPR entries.
+// MODE 0: y = A x ; 1: y += A x ; 2: y = b - A x ; 3: y = x + w dinv (b - A x) ;
+// 4: y = w dinv b ; 5: the two first Jacobi sweeps from a zero guess,
+// y = x1 + w dinv (b - A x1) with x1 = w dinv b formed on the fly (x unused).
+template <typename T, int MODE, int LPR>
+__global__ void __launch_bounds__(kBlock) k_mg(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                               const T* __restrict__ val, const T* __restrict__ dinv,
+                                               const T* __restrict__ x, const T* __restrict__ b, T* __restrict__ y,
+                                               int n, int J, T omega) {
+    constexpr int V = 256 / (LPR * (int)sizeof(T));
+    constexpr int RPW = 64 / LPR;   // rows per wavefront
+    const int lane = threadIdx.x & 63;
+    const int slot = lane / LPR, h = lane % LPR;
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int r = (int)((blk * (kBlock / 64) + (threadIdx.x >> 6)) * RPW + slot);
+    const int j = blockIdx.y * (LPR * V) + h * V;
+    const bool valid = r < n;
+    int p0 = 0, cnt = 0;
+    if (valid) {
+        p0 = rp[r];
+        cnt = rp[r + 1] - p0;
+    }
+    int c = 0;
+    T a = 0;
+    if (h < cnt) {
+        c = col[p0 + h];
+        a = val[p0 + h];
+    }
+    int nmax = 0;
+#pragma unroll
+    for (int g = 0; g < RPW; ++g) nmax = max(nmax, __builtin_amdgcn_readlane(cnt, g * LPR));
+    T s[V];
+#pragma unroll
+    for (int q = 0; q < V; ++q) s[q] = 0;
+    if (MODE != 4) {
+        for (int t = 0; t < nmax; t += 4) {
+            T v[4][V];
+            T w[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int src = slot * LPR + min(t + i, LPR - 1);
+                const int k = __builtin_amdgcn_ds_bpermute(src << 2, c);
+                w[i] = half_bcast(a, src);
+                if (t + i >= cnt) w[i] = 0;
+                vload<T, V>(v[i], (MODE == 5 ? b : x) + (int64_t)k * J + j);
+                if (MODE == 5) {
+                    const T d = omega * dinv[k];
+#pragma unroll
+                    for (int q = 0; q < V; ++q) v[i][q] = d * v[i][q];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+#pragma unroll
+                for (int q = 0; q < V; ++q) s[q] += w[i] * v[i][q];
+            }
+        }
+    }
+    if (!valid) return;
+    const int64_t o = (int64_t)r * J + j;
+    T out[V];
+    if (MODE == 0) {
+#pragma unroll
+        for (int q = 0; q < V; ++q) out[q] = s[q];
+    } else if (MODE == 1) {
+        vload<T, V>(out, y + o);
+#pragma unroll
+        for (int q = 0; q < V; ++q) out[q] += s[q];
+    } else {
+        T bv[V];
+        vload<T, V>(bv, b + o);
+        const T d = dinv ? dinv[r] : (T)0;
+        if (MODE == 2) {
+#pragma unroll
+            for (int q = 0; q < V; ++q) out[q] = bv[q] - s[q];
+        } else if (MODE == 3) {
+            T xv[V];
+            vload<T, V>(xv, x + o);
+#pragma unroll
+            for (int q = 0; q < V; ++q) out[q] = xv[q] + omega * d * (bv[q] - s[q]);
+        } else if (MODE == 4) {
+#pragma unroll
+            for (int q = 0; q < V; ++q) out[q] = omega * d * bv[q];
+        } else {
+#pragma unroll
+            for (int q = 0; q < V; ++q) out[q] = omega * d * bv[q] + omega * d * (bv[q] - s[q]);
+        }
+    }
+    vstore<T, V>(y + o, out);
+}
+
+// Dense x = C b on the coarsest level (C: n x n row-major, b and x: n x J),
+// split over kDenseKS column ranges: a workgroup computes the partial product
+// of a 64-row x 64-member block over one range (4 x 4 outputs per thread from
+// 16-column slices staged in LDS); k_dense_sum adds the kDenseKS partials in a
+// fixed order.
+constexpr int kDenseKS = 8;
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_dense_part(const T* __restrict__ C, const T* __restrict__ b,
+                                                       T* __restrict__ part, int n, int J) {
+    __shared__ T As[16][64];   // [column][row]
+    __shared__ T Bs[16][64];   // [column][member]
+    const int tid = threadIdx.x;
+    const int ty = tid >> 4, tx = tid & 15;
+    const int r0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
+    const int kc = (n + kDenseKS - 1) / kDenseKS;
+    const int k0 = blockIdx.z * kc, k1 = min(n, k0 + kc);
+    T acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[i][q] = 0;
+    for (int kb = k0; kb < k1; kb += 16) {
+        // stage C[r0 .. r0+63][kb .. kb+15] and b[kb .. kb+15][j0 .. j0+63]
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int idx = tid + e * kBlock;         // 0 .. 1023
+            const int rr = idx >> 4, kk = idx & 15;    // C: row-major reads
+            const int r = r0 + rr, k = kb + kk;
+            As[kk][rr] = (r < n && k < k1) ? C[(int64_t)r * n + k] : (T)0;
+            const int bk = idx >> 6, bj = idx & 63;
+            Bs[bk][bj] = (kb + bk < k1 && j0 + bj < J) ? b[(int64_t)(kb + bk) * J + j0 + bj] : (T)0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+            T av[4], bv[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                av[i] = As[kk][ty * 4 + i];
+                bv[i] = Bs[kk][tx * 4 + i];
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[i][q] += av[i] * bv[q];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r = r0 + ty * 4 + i;
+        if (r >= n) continue;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int j = j0 + tx * 4 + q;
+            if (j < J) part[((int64_t)blockIdx.z * n + r) * J + j] = acc[i][q];
+        }
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_dense_sum(const T* __restrict__ part, T* __restrict__ x, int64_t nJ) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= nJ) return;
+    T s = part[i];
+#pragma unroll
+    for (int k = 1; k < kDenseKS; ++k) s += part[(int64_t)k * nJ + i];
+    x[i] = s;
+}
+
 // ------------------------------------------------------------------ LDS-staged node-row kernels
 // One workgroup per (row tile, slice of JT = 32 VEC members).  The node values
 // the tile's rows read are first copied into LDS with 16-byte loads
@@ -1245,7 +1412,8 @@ __global__ void __launch_bounds__(kBlock) k_velo_sweep(const int32_t* __restrict
 
 // ------------------------------------------------------------------ scalar CSR (multigrid)
 // MODE 0: y = A x ; MODE 1: y += A x ; MODE 2: y = b - A x ;
-// MODE 3: y = x + w dinv (b - A x) ; MODE 4: y = w dinv b (x unused)
+// MODE 3: y = x + w dinv (b - A x) ; MODE 4: y = w dinv b (x unused) ;
+// MODE 5: MODE 4 followed by MODE 3 in one pass (x unused)
 template <typename T, int MODE>
 __global__ void __launch_bounds__(kBlock) k_csr(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                                                 const T* __restrict__ val, const T* __restrict__ dinv,
@@ -1257,7 +1425,12 @@ __global__ void __launch_bounds__(kBlock) k_csr(const int32_t* __restrict__ rp, 
     const int32_t p0 = rp[r], p1 = rp[r + 1];
     for (int j = L.j0; j < J; j += JP) {
         T s = 0;
-        if (MODE != 4)
+        if (MODE == 5)
+            for (int32_t p = p0; p < p1; ++p) {
+                const int64_t k = col[p];
+                s += val[p] * (omega * dinv[k] * b[k * J + j]);
+            }
+        else if (MODE != 4)
             for (int32_t p = p0; p < p1; ++p) s += val[p] * x[(int64_t)col[p] * J + j];
         const int64_t o = r * J + j;
         if (MODE == 0) y[o] = s;
@@ -1265,24 +1438,8 @@ __global__ void __launch_bounds__(kBlock) k_csr(const int32_t* __restrict__ rp, 
         if (MODE == 2) y[o] = b[o] - s;
         if (MODE == 3) y[o] = x[o] + omega * dinv[r] * (b[o] - s);
         if (MODE == 4) y[o] = omega * dinv[r] * b[o];
+        if (MODE == 5) y[o] = omega * dinv[r] * b[o] + omega * dinv[r] * (b[o] - s);
     }
-}
-
-// x = Cinv b on the coarsest level (dense, n <= a few hundred): one block per
-// row and member tile; the 4 wavefronts split the columns, fixed-order sum in LDS
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_dense(const T* __restrict__ C, const T* __restrict__ b, T* __restrict__ x,
-                                                  int n, int J) {
-    __shared__ T red[kBlock];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int r = blockIdx.x;
-    const int j = blockIdx.y * 64 + lane;
-    T s = 0;
-    if (j < J)
-        for (int c = wave; c < n; c += kBlock / 64) s += C[(int64_t)r * n + c] * b[(int64_t)c * J + j];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    if (wave == 0 && j < J) x[(int64_t)r * J + j] = red[lane] + red[64 + lane] + red[128 + lane] + red[192 + lane];
 }
 
 // z_p = -x_mg (x_mg ~ S_hat^{-1} r_p from the V-cycle); the pinned row is an
@@ -2265,8 +2422,19 @@ struct Ops {
 
     template <int MODE>
     mhd_status csr(const DevCSR<double>& c, const T* dinv, const T* x, const T* b, T* y, T omega) {
-        hipLaunchKernelGGL((k_csr<T, MODE>), dim3(grid_for(c.nrows, JP)), dim3(kBlock), 0, st, c.rowptr, c.col,
-                           Vals<T>::csr(c), dinv, x, b, y, c.nrows, J, JP, omega);
+        constexpr int MJ = 256 / (int)sizeof(T);
+        if (J % MJ == 0 && c.max_row <= 16) {
+            const int64_t waves = (c.nrows + 3) / 4;
+            hipLaunchKernelGGL((k_mg<T, MODE, 16>), dim3((unsigned)((waves + 3) / 4), J / MJ), dim3(kBlock), 0, st,
+                               c.rowptr, c.col, Vals<T>::csr(c), dinv, x, b, y, (int)c.nrows, J, omega);
+        } else if (J % MJ == 0 && c.max_row <= 32) {
+            const int64_t waves = (c.nrows + 1) / 2;
+            hipLaunchKernelGGL((k_mg<T, MODE, 32>), dim3((unsigned)((waves + 3) / 4), J / MJ), dim3(kBlock), 0, st,
+                               c.rowptr, c.col, Vals<T>::csr(c), dinv, x, b, y, (int)c.nrows, J, omega);
+        } else {
+            hipLaunchKernelGGL((k_csr<T, MODE>), dim3(grid_for(c.nrows, JP)), dim3(kBlock), 0, st, c.rowptr, c.col,
+                               Vals<T>::csr(c), dinv, x, b, y, c.nrows, J, JP, omega);
+        }
         LAUNCH_CHECK();
         return MHD_OK;
     }
@@ -2280,8 +2448,13 @@ struct Ops {
         T* x = (T*)S.gw.mg_x[l];
         mhd_status rc;
         if (l + 1 == (int)m.levels.size()) {
-            hipLaunchKernelGGL((k_dense<T>), dim3(Lv.n, (J + 63) / 64), dim3(kBlock), 0, st, Vals<T>::cinv(Lv), b, x,
-                               Lv.n, J);
+            T* part = (T*)S.gw.dense_part;
+            hipLaunchKernelGGL((k_dense_part<T>), dim3((Lv.n + 63) / 64, (J + 63) / 64, kDenseKS), dim3(kBlock), 0,
+                               st, Vals<T>::cinv(Lv), b, part, Lv.n, J);
+            LAUNCH_CHECK();
+            const int64_t nJ = (int64_t)Lv.n * J;
+            hipLaunchKernelGGL((k_dense_sum<T>), dim3((unsigned)((nJ + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
+                               (const T*)part, x, nJ);
             LAUNCH_CHECK();
             *out = x;
             return MHD_OK;
@@ -2291,8 +2464,8 @@ struct Ops {
         T* r = (T*)S.gw.mg_r[l];
         T* bc = (T*)S.gw.mg_b[l + 1];
         const T* dinv = Vals<T>::dinv(Lv);
-        if ((rc = csr<4>(Lv.L, dinv, nullptr, b, x, omega))) return rc;   // x  = w D^-1 b
-        if ((rc = csr<3>(Lv.L, dinv, x, b, x2, omega))) return rc;        // x2 = x + w D^-1 (b - L x)
+        // x2 = x + w D^-1 (b - L x) with x = w D^-1 b: two sweeps from a zero guess in one pass
+        if ((rc = csr<5>(Lv.L, dinv, nullptr, b, x2, omega))) return rc;
         if ((rc = csr<2>(Lv.L, dinv, x2, b, r, omega))) return rc;        // r  = b - L x2
         if ((rc = csr<0>(Lv.R, dinv, r, nullptr, bc, omega))) return rc;  // bc = R r
         T* xc = nullptr;
@@ -2562,6 +2735,7 @@ mhd_status alloc_gmres(DevShared& S, int restart) {
     std::vector<void*> ptrs(restart + 1);
     for (int i = 0; i <= restart; ++i) ptrs[i] = (char*)G.basis + (size_t)i * blk;
     MHD_HIP(hipMemcpy(G.dptrs, ptrs.data(), sizeof(void*) * (restart + 1), hipMemcpyHostToDevice));
+    if ((rc = A(&G.dense_part, (size_t)kDenseKS * m.levels.back().n * S.Jmax * sizeof(double)))) return rc;
     for (size_t l = 0; l < m.levels.size(); ++l) {
         size_t lb = (size_t)m.levels[l].n * S.Jmax * sizeof(double);
         void *a, *b, *c, *d;
