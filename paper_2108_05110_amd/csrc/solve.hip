@@ -1010,7 +1010,7 @@ __global__ void __launch_bounds__(kBlock) k_mg(const int32_t* __restrict__ rp, c
 // of a 64-row x 64-member block over one range (4 x 4 outputs per thread from
 // 16-column slices staged in LDS); k_dense_sum adds the kDenseKS partials in a
 // fixed order.
-constexpr int kDenseKS = 8;
+constexpr int kDenseKS = 16;
 
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_dense_part(const T* __restrict__ C, const T* __restrict__ b,
@@ -1027,18 +1027,30 @@ __global__ void __launch_bounds__(kBlock) k_dense_part(const T* __restrict__ C, 
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int q = 0; q < 4; ++q) acc[i][q] = 0;
-    for (int kb = k0; kb < k1; kb += 16) {
-        // stage C[r0 .. r0+63][kb .. kb+15] and b[kb .. kb+15][j0 .. j0+63]
+    // the next 16-column slice is loaded into registers while the current one is used
+    T ca[4], cb[4];
+    auto fetch = [&](int kb) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            const int idx = tid + e * kBlock;         // 0 .. 1023
-            const int rr = idx >> 4, kk = idx & 15;    // C: row-major reads
+            const int idx = tid + e * kBlock;          // 0 .. 1023
+            const int rr = idx >> 4, kk = idx & 15;
             const int r = r0 + rr, k = kb + kk;
-            As[kk][rr] = (r < n && k < k1) ? C[(int64_t)r * n + k] : (T)0;
+            ca[e] = (r < n && k < k1) ? C[(int64_t)r * n + k] : (T)0;
             const int bk = idx >> 6, bj = idx & 63;
-            Bs[bk][bj] = (kb + bk < k1 && j0 + bj < J) ? b[(int64_t)(kb + bk) * J + j0 + bj] : (T)0;
+            cb[e] = (kb + bk < k1 && j0 + bj < J) ? b[(int64_t)(kb + bk) * J + j0 + bj] : (T)0;
+        }
+    };
+    if (k0 < k1) fetch(k0);
+    for (int kb = k0; kb < k1; kb += 16) {
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int idx = tid + e * kBlock;
+            As[idx & 15][idx >> 4] = ca[e];
+            Bs[idx >> 6][idx & 63] = cb[e];
         }
         __syncthreads();
+        if (kb + 16 < k1) fetch(kb + 16);
 #pragma unroll
         for (int kk = 0; kk < 16; ++kk) {
             T av[4], bv[4];
@@ -1052,7 +1064,6 @@ __global__ void __launch_bounds__(kBlock) k_dense_part(const T* __restrict__ C, 
 #pragma unroll
                 for (int q = 0; q < 4; ++q) acc[i][q] += av[i] * bv[q];
         }
-        __syncthreads();
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -2491,8 +2502,9 @@ struct Ops {
         LAUNCH_CHECK();
         const T omega = (T)0.7;
         T* t = (T*)S.gw.tbuf;
-        T* za = z;
-        T* zb = (T*)S.gw.z2buf;
+        // ping-pong between z and z2buf, starting so that the last sweep writes z
+        T* za = (sweeps % 2) ? z : (T*)S.gw.z2buf;
+        T* zb = (sweeps % 2) ? (T*)S.gw.z2buf : z;
         const bool aligned = (((uintptr_t)v | (uintptr_t)z | (uintptr_t)t | (uintptr_t)zb) % 16) == 0;
         if ((rc = launch_velo_plan<T, true>(align_plan(p_first, aligned), S, v, zp, t, nullptr, za, J, st, omega)))
             return rc;
