@@ -63,15 +63,19 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(J, N):
-    """HBM bytes per SpMM launch measured with rocprofv3 counters, if recorded for
-    the current kernel source; else None."""
+def traffic_from_profiles(J, N, plan):
+    """HBM bytes per SpMM launch measured with rocprofv3 counters (FETCH_SIZE +
+    WRITE_SIZE, scaled by the same counters on a copy of known size), if they
+    were recorded for the current kernel source, shape and launch plan; else
+    None."""
     path = os.path.join(ROOT, "profiles", "spmm_traffic_cavity128_J64.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
     if rec.get("source_hash") != source_hash() or rec.get("J") != J or rec.get("N") != N:
+        return None
+    if plan is None or any(rec.get("plan", {}).get(k) != plan.get(k) for k in ("vec", "group", "deep", "tile", "waves")):
         return None
     return rec.get("bytes_per_launch")
 
@@ -324,11 +328,63 @@ def headline(args, L, wl, torch):
                      "kernel": f"saddle-point SpMM ({saddle_kernel_name(plans.get('saddle'))})",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-                     "traffic": traffic_from_profiles(args.J, args.N), "bytes_per_launch": bpl,
+                     "traffic": traffic_from_profiles(args.J, args.N, plans.get("saddle")), "bytes_per_launch": bpl,
                      "avg_launch_us": avg_s * 1e6, "launches": launches},
         "separate": separate,
         "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline(args.N, args.J),
     }
+    mesh.close()
+    return out
+
+
+def spmm_workload(args, L, wl, torch):
+    """The saddle-point SpMM alone at the headline shape with the tuned plan,
+    and a plain device copy of known size beside it (the reference for
+    hardware byte counters): the run profiled for HBM traffic."""
+    from paper_2108_05110_amd.ensemble import Mesh, to_dev
+    prec = L.MHD_FP32_IR if args.precision == "fp32ir" else L.MHD_FP64
+    dt = torch.float32 if prec == L.MHD_FP32_IR else torch.float64
+    mesh = Mesh(L.MHD_MESH_UNIT_SQUARE, args.N)
+    pb = wl.cavity(J=args.J, s=0.1, dt=0.01)
+    V, W = pb.ic(mesh.xy)
+    A = L.mhd_ens_shared_create(mesh.handle, args.J, 8)
+    c = L.Coeffs(pb.dt, pb.mu, float(pb.nu.mean()), float(pb.nu_m.mean()), 0)
+    L.mhd_ens_assemble_shared(mesh.handle, c, to_dev(W), args.J, A)
+    if args.plan:
+        # a pinned plan (under counter collection the tuner's timings are not representative)
+        vec, group, deep, tile, waves = (int(v) for v in args.plan.split(","))
+        L.mhd_ens_set_plan(A, args.J, prec, L.TUNE_SADDLE, vec, group, deep, tile, waves)
+        plans = {"saddle": {"word": 4 if prec == L.MHD_FP32_IR else 8, "vec": vec, "group": group, "deep": deep,
+                            "tile": tile, "waves": waves, "us": None, "candidates": 0}}
+    else:
+        plans = tuned_plans(L, wl, mesh, args.J, prec)
+    x = torch.randn((mesh.n, args.J), device="cuda", dtype=torch.float64).to(dt)
+    y = torch.empty_like(x)
+    copy_bytes = 256 << 20
+    src = torch.ones(copy_bytes // 4, device="cuda", dtype=torch.float32)
+    dst = torch.empty_like(src)
+    for _ in range(args.warmup):
+        L.mhd_ens_spmm(A, x, y, args.J, prec)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        L.mhd_ens_spmm(A, x, y, args.J, prec)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / args.steps
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    L.mhd_ens_shared_free(A)
+    word = 4 if prec == L.MHD_FP32_IR else 8
+    bpl = spmm_bytes(mesh.info, args.J, word)
+    out = {"metric": "saddle-point SpMM algorithmic GB/s", "value": bpl / el / 1e9, "unit": "GB/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": el * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32" if word == 4 else "f64", "data": "synthetic",
+           "config": {"workload": f"saddle-point SpMM, unit square {args.N}x{args.N} P2-P1, J={args.J}",
+                      "bytes_per_launch": bpl, "copy_reference_bytes": copy_bytes,
+                      "kernel": saddle_kernel_name(plans.get("saddle"))},
+           "autotune": plans}
     mesh.close()
     return out
 
@@ -447,10 +503,11 @@ def main():
     ap.add_argument("--cycles", type=int, default=2)
     ap.add_argument("--sweeps", type=int, default=6)
     ap.add_argument("--rtol", type=float, default=1e-10)
-    ap.add_argument("--workload", choices=["cavity", "adjoint", "large"], default="cavity")
+    ap.add_argument("--workload", choices=["cavity", "adjoint", "large", "spmm"], default="cavity")
     ap.add_argument("--separate-steps", type=int, default=1)
     ap.add_argument("--no-separate", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--plan", default="", help="spmm workload: pinned SpMM plan vec,group,deep,tile,waves")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -465,6 +522,8 @@ def main():
         out = adjoint_workload(args, L, wl, torch)
     elif args.workload == "large":
         out = large_workload(args, L, wl, torch)
+    elif args.workload == "spmm":
+        out = spmm_workload(args, L, wl, torch)
     else:
         if rank != 0:
             args.no_cpu_baseline = True

@@ -303,8 +303,9 @@ mhd_status mhd_ens_set_plan(mhd_shared A, int J, int precision, int op, int vec,
                             int waves);
 
 /* Diagnostics: while enabled, every saddle-point SpMM launch of this library
- * (inside mhd_ens_solve / mhd_ens_step and mhd_ens_spmm) is bracketed by HIP
- * events recorded on its stream.  mhd_ens_timer_read synchronises those
+ * (inside mhd_ens_solve / mhd_ens_step and mhd_ens_spmm, outside graph
+ * capture) is timed by a pair of HIP events that its dispatch records at the
+ * kernel's start and end.  mhd_ens_timer_read synchronises those
  * events and returns the summed kernel milliseconds and the launch count
  * since the last enable; nbytes_fp32 / nbytes_fp64 receive the summed
  * launch sizes (units of n*J) per precision.  Enabling resets the counters. */

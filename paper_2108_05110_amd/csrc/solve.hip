@@ -16,6 +16,7 @@
 // Every kernel streams member blocks row-major (member index fastest); rows
 // are spread over the 8 XCDs in contiguous ranges.  Column reductions go
 // through per-block partials and a fixed-order second pass (deterministic).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -1840,13 +1841,21 @@ hipError_t timer_fold() {
     return hipSuccess;
 }
 
-// record the start (before = true) or the end of one timed launch on stream st
-void timer_mark(hipStream_t st, bool before) {
-    if (!g_timer.on) return;
+// While t_ev0 is set, launch_k records the kernel's own start and end into
+// (t_ev0, t_ev1) with the dispatch packet (the SpMM timer of the diagnostics).
+thread_local hipEvent_t t_ev0 = nullptr, t_ev1 = nullptr;
+
+// arms (t_ev0, t_ev1) for the next launch on st when the timer is on and st is
+// not being captured; returns whether it did
+bool timer_begin(hipStream_t st) {
+    if (!g_timer.on) return false;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return;
-    if (before && g_timer.used + 2 > g_timer.pool.size()) (void)timer_fold();
-    if (g_timer.used < g_timer.pool.size()) (void)hipEventRecord(g_timer.pool[g_timer.used++], st);
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return false;
+    if (g_timer.used + 2 > g_timer.pool.size()) (void)timer_fold();
+    if (g_timer.used + 2 > g_timer.pool.size()) return false;
+    t_ev0 = g_timer.pool[g_timer.used++];
+    t_ev1 = g_timer.pool[g_timer.used++];
+    return true;
 }
 
 // vector width of the node-row fast path for J members (0: use the generic kernels)
@@ -2066,6 +2075,15 @@ inline dim3 group_grid(int64_t units, int J, int vec, int g) {
     return dim3((unsigned)((units + per - 1) / per), J / (32 * vec));
 }
 
+
+template <typename K, typename... Args>
+void launch_k(K kernel, dim3 grid, dim3 block, size_t shmem, hipStream_t st, Args... args) {
+    if (t_ev0)
+        hipExtLaunchKernelGGL(kernel, grid, block, (std::uint32_t)shmem, st, t_ev0, t_ev1, 0u, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, shmem, st, args...);
+}
+
 // y = S x (MODE 0) or y = b - S x (MODE 1) with plan p
 template <typename T, int MODE>
 mhd_status launch_saddle_plan(NodePlan p, DevShared& S, const T* x, const T* b, T* y, int J, hipStream_t st) {
@@ -2078,7 +2096,7 @@ mhd_status launch_saddle_plan(NodePlan p, DevShared& S, const T* x, const T* b, 
         const dim3 grid((unsigned)((int64_t)tl.ntiles * MT));
         auto go = [&](auto kern, int threads) -> mhd_status {
             MHD_HIP(allow_lds(kern, lds));
-            hipLaunchKernelGGL(kern, grid, dim3(threads), lds, st, tile_view(tl), m.A_rowptr, Vals<T>::A(S),
+            launch_k(kern, grid, dim3(threads), lds, st, tile_view(tl), m.A_rowptr, Vals<T>::A(S),
                                m.Bt_rowptr, Vals<T>::Bt(S), m.B_rowptr, Vals<T>::B(S), Vals<T>::dp(m), x, b, y, m.nP2,
                                J, MT, tl.max_s2);
             LAUNCH_CHECK();
@@ -2095,7 +2113,7 @@ mhd_status launch_saddle_plan(NodePlan p, DevShared& S, const T* x, const T* b, 
             constexpr int GG = decltype(Gc)::value;
             const int wP2 = (m.nP2 + GG - 1) / GG, wP1 = (m.nP1 + GG - 1) / GG;
             const dim3 grid((unsigned)((wP2 + wP1 + 3) / 4), J / (256 / (int)sizeof(T)));
-            hipLaunchKernelGGL((k_saddle_h<T, MODE, GG>), grid, dim3(kBlock), 0, st, m.A_rowptr, m.A_col,
+            launch_k(k_saddle_h<T, MODE, GG>, grid, dim3(kBlock), 0, st, m.A_rowptr, m.A_col,
                                Vals<T>::A(S), m.Bt_rowptr, m.Bt_col, Vals<T>::Bt(S), m.B_rowptr, m.B_col,
                                Vals<T>::B(S), Vals<T>::dp(m), x, b, y, m.nP2, m.nP1, J, wP2);
             LAUNCH_CHECK();
@@ -2107,7 +2125,7 @@ mhd_status launch_saddle_plan(NodePlan p, DevShared& S, const T* x, const T* b, 
             constexpr int VV = decltype(V)::value;
             return with_gd(p.g, [&](auto Gc) -> mhd_status {
                 constexpr int GG = decltype(Gc)::value;
-                hipLaunchKernelGGL((k_saddle_p<T, VV, MODE, GG>), group_grid(units, J, VV, GG), dim3(kBlock), 0, st,
+                launch_k(k_saddle_p<T, VV, MODE, GG>, group_grid(units, J, VV, GG), dim3(kBlock), 0, st,
                                    m.A_rowptr, m.A_col, Vals<T>::A(S), m.Bt_rowptr, m.Bt_col, Vals<T>::Bt(S),
                                    m.B_rowptr, m.B_col, Vals<T>::B(S), Vals<T>::dp(m), x, b, y, m.nP2, m.nP1, J);
                 LAUNCH_CHECK();
@@ -2118,7 +2136,7 @@ mhd_status launch_saddle_plan(NodePlan p, DevShared& S, const T* x, const T* b, 
     if (p.deep) p = default_plan(m, J, sizeof(T));
     if (p.vec == 0) {
         const int JP = pick_jp(J);
-        hipLaunchKernelGGL((k_saddle<T, MODE>), dim3(grid_for(units, JP)), dim3(kBlock), 0, st, m.A_rowptr, m.A_col,
+        launch_k(k_saddle<T, MODE>, dim3(grid_for(units, JP)), dim3(kBlock), 0, st, m.A_rowptr, m.A_col,
                            Vals<T>::A(S), m.Bt_rowptr, m.Bt_col, Vals<T>::Bt(S), m.B_rowptr, m.B_col, Vals<T>::B(S),
                            Vals<T>::dp(m), x, b, y, m.nP2, m.nP1, J, JP);
         LAUNCH_CHECK();
@@ -2129,11 +2147,11 @@ mhd_status launch_saddle_plan(NodePlan p, DevShared& S, const T* x, const T* b, 
         return with_g(p.g, [&](auto Gc) -> mhd_status {
             constexpr int GG = decltype(Gc)::value;
             if constexpr (GG == 0) {
-                hipLaunchKernelGGL((k_saddle_v<T, VV, MODE>), node_grid(units, J, VV), dim3(kBlock), 0, st,
+                launch_k(k_saddle_v<T, VV, MODE>, node_grid(units, J, VV), dim3(kBlock), 0, st,
                                    m.A_rowptr, m.A_col, Vals<T>::A(S), m.Bt_rowptr, m.Bt_col, Vals<T>::Bt(S),
                                    m.B_rowptr, m.B_col, Vals<T>::B(S), Vals<T>::dp(m), x, b, y, m.nP2, m.nP1, J);
             } else {
-                hipLaunchKernelGGL((k_saddle_g<T, VV, MODE, GG>), group_grid(units, J, VV, GG), dim3(kBlock), 0, st,
+                launch_k(k_saddle_g<T, VV, MODE, GG>, group_grid(units, J, VV, GG), dim3(kBlock), 0, st,
                                    m.A_rowptr, m.A_col, Vals<T>::A(S), m.Bt_rowptr, m.Bt_col, Vals<T>::Bt(S),
                                    m.B_rowptr, m.B_col, Vals<T>::B(S), Vals<T>::dp(m), x, b, y, m.nP2, m.nP1, J);
             }
@@ -2418,13 +2436,12 @@ struct Ops {
     }
 
     mhd_status saddle(const T* x, T* y) {
-        timer_mark(st, true);
+        const bool timed = timer_begin(st);
         const bool aligned = (((uintptr_t)x | (uintptr_t)y) % 16) == 0;
         mhd_status rc = launch_saddle_plan<T, 0>(align_plan(p_saddle, aligned), S, x, nullptr, y, J, st);
+        t_ev0 = t_ev1 = nullptr;
         if (rc) return rc;
-        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-        if (g_timer.on && hipStreamIsCapturing(st, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone) {
-            timer_mark(st, false);
+        if (timed) {
             g_timer.launches++;
             (sizeof(T) == 4 ? g_timer.nJ32 : g_timer.nJ64) += (double)J;
         }
