@@ -265,7 +265,10 @@ mhd_status mhd_ens_spmm(mhd_shared A, const void* x, void* y, int J, int precisi
  *   node values of a square tile of rows, and its halo, into LDS):
  *     tile  = tile edge in half-steps of the mesh: 8, 12 or 16, where the
  *             staged values fit the device's LDS per workgroup;
- *     waves = wavefronts per workgroup: 4 or 8.
+ *     waves = wavefronts per workgroup: 4 or 8;
+ *     deep  = 3: the tile's CSR entries are staged into LDS as well, so a
+ *             row is computed from LDS only (deep = 0: entries by scalar
+ *             loads from memory).
  * Every candidate performs the same arithmetic in the same order, so results
  * do not depend on the choice.
  *   out:   host array of cap entries, or NULL; receives every timed candidate
@@ -294,8 +297,8 @@ mhd_status mhd_ens_autotune(mhd_shared A, int J, int precision, mhd_tune_entry* 
  *   vec, group, deep: the gather kernels as in mhd_ens_autotune; vec = 0
  *               selects the generic kernels (any J);
  *   tile, waves: tile 0, or 8, 12, 16 with waves 4 or 8 for the LDS-staged
- *               kernels (vec, group are then the fallback used where the
- *               tiling is not available, e.g. an unaligned block).
+ *               kernels, with deep 0 or 3 (where the tiling is not usable,
+ *               e.g. an unaligned block, the gather kernels run instead).
  * Graphs captured earlier keep the kernels they hold.  MHD_EINVAL for a shape
  * this mesh, J or device does not admit.  Builds the tiling on first use
  * (synchronous host-to-device copies). */

@@ -86,6 +86,13 @@ struct HostTiling {
     std::vector<int32_t> s2_ptr, s2;        // tile -> staged P2 nodes (ascending)
     std::vector<int32_t> s1_ptr, s1;        // tile -> staged P1 nodes (ascending)
     std::vector<int32_t> a_loc, bt_loc, b_loc;   // per CSR entry of A, B^T, B: local column index
+    // the entries again in tile order (rows as listed in r2 / r1): per entry the
+    // local column index and the position of the entry in the global CSR arrays;
+    // each row is padded to a multiple of 4 entries with (0, -1)
+    std::vector<int32_t> ta_rp, ta_loc, ta_gp;   // over r2 (size |r2| + 1)
+    std::vector<int32_t> tbt_rp, tbt_loc, tbt_gp;
+    std::vector<int32_t> tb_rp, tb_loc, tb_gp;   // over r1
+    int max_ea = 0, max_ebt = 0, max_eb = 0;     // largest per-tile entry counts
 };
 void build_tiling(const HostMesh& m, int tx, int ty, HostTiling& t);
 

@@ -47,6 +47,10 @@ struct DevTiling {
     int32_t *r1_ptr = nullptr, *r1 = nullptr, *r1_self = nullptr;
     int32_t *s2_ptr = nullptr, *s2 = nullptr, *s1_ptr = nullptr, *s1 = nullptr;
     int32_t *a_loc = nullptr, *bt_loc = nullptr, *b_loc = nullptr;
+    int32_t *ta_rp = nullptr, *ta_loc = nullptr, *ta_gp = nullptr;
+    int32_t *tbt_rp = nullptr, *tbt_loc = nullptr, *tbt_gp = nullptr;
+    int32_t *tb_rp = nullptr, *tb_loc = nullptr, *tb_gp = nullptr;
+    int max_ea = 0, max_ebt = 0, max_eb = 0;
 };
 constexpr int kTileShapes = 3;          // square tiles of 8, 12 or 16 half-steps
 inline int tile_edge(int id) { return id == 1 ? 8 : id == 2 ? 12 : 16; }

@@ -706,8 +706,11 @@ __global__ void __launch_bounds__(kBlock) k_velo_p(const int32_t* __restrict__ r
 // instruction fetches two member rows of x.  A wavefront owns G consecutive
 // units of one kind (P2 or P1) and pairs unit g with unit g + G/2.  Within a
 // half, lane h covers component h / 16 and members (h % 16) V ... + V - 1.
-// Entries are consumed in CSR order per row (rows padded with zero values to
-// the longer row of the pair), so the arithmetic matches the other kernels.
+// Lane h of a half first turns the row's h-th entry into a byte offset of the
+// member row it reads; per entry the offset and value are broadcast within the
+// half (ds_bpermute) and the load is a buffer load with that offset.  Rows are
+// padded with zero values to the longer row of the pair; entries are consumed
+// in CSR order, so the arithmetic matches the other kernels.
 constexpr int kPairRow = 32;   // longest row the paired kernels accept
 
 struct PairLanes {
@@ -735,35 +738,6 @@ __device__ __forceinline__ PairLanes pair_lanes(int nP2, int nP1, int wP2) {
     return L;
 }
 
-// lane t + 32 half of a RowLanes-like spread holds entry t of its half's row
-template <typename T, bool PAIR>
-struct HalfRow {
-    int cnt;   // entries of this lane's row
-    int col;
-    T v0, v1;
-};
-
-template <typename T, bool PAIR>
-__device__ __forceinline__ HalfRow<T, PAIR> half_row(const int32_t* __restrict__ col, const T* __restrict__ val,
-                                                     int32_t p0, int32_t p1, int pad_col) {
-    HalfRow<T, PAIR> R;
-    const int h = threadIdx.x & 31;
-    R.cnt = p1 - p0;
-    R.col = pad_col;
-    R.v0 = 0;
-    R.v1 = 0;
-    if (h < R.cnt) {
-        R.col = col[p0 + h];
-        if (PAIR) {
-            R.v0 = val[2 * (p0 + h)];
-            R.v1 = val[2 * (p0 + h) + 1];
-        } else {
-            R.v0 = val[p0 + h];
-        }
-    }
-    return R;
-}
-
 template <typename T>
 __device__ __forceinline__ T half_bcast(T v, int src) {
     if constexpr (sizeof(T) == 4) {
@@ -776,27 +750,83 @@ __device__ __forceinline__ T half_bcast(T v, int src) {
     }
 }
 
-// acc[q] += sum_t a_t xb[col_t cstride + q] for this lane's row; n = entries of
-// the longer row of the pair (uniform), batches of 8 loads in flight
+// ds_bpermute with a byte address (lane * 4)
+template <typename T>
+__device__ __forceinline__ T bperm_addr(T v, int addr) {
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, __builtin_amdgcn_ds_bpermute(addr, __builtin_bit_cast(int, v)));
+    } else {
+        const long long b = __builtin_bit_cast(long long, v);
+        const int lo = __builtin_amdgcn_ds_bpermute(addr, (int)(b & 0xffffffffLL));
+        const int hi = __builtin_amdgcn_ds_bpermute(addr, (int)(b >> 32));
+        return __builtin_bit_cast(T, (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+    }
+}
+
+// lane h of a half holds entry h of its half's row: byte offset of the member
+// row the entry reads (column * row_bytes + base_bytes; entries past the row
+// read the first member row with a zero value) and the value(s)
+template <typename T, bool PAIR>
+struct HalfRow {
+    int cnt;         // entries of this lane's row
+    unsigned off;
+    T v0, v1;
+};
+
+template <typename T, bool PAIR>
+__device__ __forceinline__ HalfRow<T, PAIR> half_row(const int32_t* __restrict__ col, const T* __restrict__ val,
+                                                     int32_t p0, int32_t p1, unsigned row_bytes,
+                                                     unsigned base_bytes) {
+    HalfRow<T, PAIR> R;
+    const int h = threadIdx.x & 31;
+    R.cnt = p1 - p0;
+    R.off = base_bytes;
+    R.v0 = 0;
+    R.v1 = 0;
+    if (h < R.cnt) {
+        R.off = (unsigned)col[p0 + h] * row_bytes + base_bytes;
+        if (PAIR) {
+            R.v0 = val[2 * (p0 + h)];
+            R.v1 = val[2 * (p0 + h) + 1];
+        } else {
+            R.v0 = val[p0 + h];
+        }
+    }
+    return R;
+}
+
+// a buffer resource over `bytes` bytes from p (loads past the end return 0)
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+template <typename T, int V>
+__device__ __forceinline__ void bload(T (&v)[V], __amdgpu_buffer_rsrc_t r, unsigned off) {
+    static_assert(sizeof(T) * V == 16, "16-byte member loads");
+    auto w = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0);
+    __builtin_memcpy(v, &w, 16);
+}
+
+// acc[q] += sum_t a_t x[off_t + lane_off + q] for this lane's row; n = entries
+// of the longer row of the pair (uniform, <= kPairRow), 8 loads in flight
 template <typename T, int V, bool PAIR, bool NEG>
-__device__ __forceinline__ void pair_row(const HalfRow<T, PAIR>& R, int n, int half, int c, const T* __restrict__ xb,
-                                         int64_t cstride, T (&acc)[V]) {
-    const int base = half << 5;
+__device__ __forceinline__ void pair_row(const HalfRow<T, PAIR>& R, int n, int half, int c,
+                                         __amdgpu_buffer_rsrc_t xr, unsigned lane_off, T (&acc)[V]) {
+    const int hb = half << 7;   // byte address of lane 32 half
     for (int t = 0; t < n; t += 8) {
         T v[8][V];
         T a[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
-            const int src = base + min(t + i, 31);
-            const int64_t k = __builtin_amdgcn_ds_bpermute(src << 2, R.col);
-            vload<T, V>(v[i], xb + k * cstride);
+            const int addr = hb + ((t + i) << 2);
+            const unsigned off = (unsigned)__builtin_amdgcn_ds_bpermute(addr, (int)R.off);
+            bload<T, V>(v[i], xr, off + lane_off);
             if (PAIR) {
-                const T a0 = half_bcast(R.v0, src), a1 = half_bcast(R.v1, src);
+                const T a0 = bperm_addr(R.v0, addr), a1 = bperm_addr(R.v1, addr);
                 a[i] = c ? a1 : a0;
             } else {
-                a[i] = half_bcast(R.v0, src);
+                a[i] = bperm_addr(R.v0, addr);
             }
-            if (t + i >= R.cnt) a[i] = 0;
             if (NEG) a[i] = -a[i];
         }
 #pragma unroll
@@ -818,8 +848,11 @@ __global__ void __launch_bounds__(kBlock) k_saddle_h(const int32_t* __restrict__
                                                      T* __restrict__ y, int nP2, int nP1, int J, int wP2) {
     constexpr int V = 16 / (int)sizeof(T);
     const PairLanes L = pair_lanes<V, G>(nP2, nP1, wP2);
-    const T* xp = x + 2 * (int64_t)nP2 * J;
-    const T* xc = x + (int64_t)L.c * J + L.j;
+    const unsigned W = sizeof(T);
+    const __amdgpu_buffer_rsrc_t xr = make_rsrc(x, (unsigned)((2 * (int64_t)nP2 + nP1) * J * W));
+    const unsigned vrow = 2u * J * W;                      // bytes per velocity node (both components)
+    const unsigned pbase = 2u * (unsigned)nP2 * J * W;     // start of the pressure block
+    const unsigned lane_v = ((unsigned)L.c * J + L.j) * W, lane_p = (unsigned)L.j * W;
     for (int s = 0; s < G / 2; ++s) {
         const int ua = L.u0 + s, ub = L.u0 + s + G / 2;
         if (ua >= L.uend) return;
@@ -829,12 +862,12 @@ __global__ void __launch_bounds__(kBlock) k_saddle_h(const int32_t* __restrict__
 #pragma unroll
         for (int q = 0; q < V; ++q) acc[q] = 0;
         if (u < nP2) {
-            const HalfRow<T, false> RA = half_row<T, false>(Acol, Aval, Arp[u], Arp[u + 1], u);
-            const HalfRow<T, true> RB = half_row<T, true>(Btcol, Btval, Btrp[u], Btrp[u + 1], 0);
+            const HalfRow<T, false> RA = half_row<T, false>(Acol, Aval, Arp[u], Arp[u + 1], vrow, 0);
+            const HalfRow<T, true> RB = half_row<T, true>(Btcol, Btval, Btrp[u], Btrp[u + 1], J * W, pbase);
             const int na = max(__builtin_amdgcn_readlane(RA.cnt, 0), __builtin_amdgcn_readlane(RA.cnt, 32));
             const int nb = max(__builtin_amdgcn_readlane(RB.cnt, 0), __builtin_amdgcn_readlane(RB.cnt, 32));
-            pair_row<T, V, false, false>(RA, na, L.half, L.c, xc, 2 * (int64_t)J, acc);
-            pair_row<T, V, true, false>(RB, nb, L.half, L.c, xp + L.j, J, acc);
+            pair_row<T, V, false, false>(RA, na, L.half, L.c, xr, lane_v, acc);
+            pair_row<T, V, true, false>(RB, nb, L.half, L.c, xr, lane_p, acc);
             const int64_t o = (2 * (int64_t)u + L.c) * J + L.j;
             if (MODE == 1) {
                 T bv[V];
@@ -845,16 +878,16 @@ __global__ void __launch_bounds__(kBlock) k_saddle_h(const int32_t* __restrict__
             if (!L.half || has_b) vstore<T, V>(y + o, acc);
         } else {
             const int k = u - nP2;
-            const HalfRow<T, true> RB = half_row<T, true>(Bcol, Bval, Brp[k], Brp[k + 1], 0);
+            const HalfRow<T, true> RB = half_row<T, true>(Bcol, Bval, Brp[k], Brp[k + 1], vrow, 0);
             const int nb = max(__builtin_amdgcn_readlane(RB.cnt, 0), __builtin_amdgcn_readlane(RB.cnt, 32));
-            pair_row<T, V, true, false>(RB, nb, L.half, L.c, xc, 2 * (int64_t)J, acc);
+            pair_row<T, V, true, false>(RB, nb, L.half, L.c, xr, lane_v, acc);
 #pragma unroll
             for (int r = 0; r < V; ++r) acc[r] += __shfl_xor(acc[r], 16, 64);   // the two components
             if (L.c == 0 && (!L.half || has_b)) {
                 const T d = dp[k];
                 const int64_t o = (2 * (int64_t)nP2 + k) * J + L.j;
                 T v[V];
-                vload<T, V>(v, xp + (int64_t)k * J + L.j);
+                vload<T, V>(v, x + (2 * (int64_t)nP2 + k) * J + L.j);
 #pragma unroll
                 for (int r = 0; r < V; ++r) acc[r] += d * v[r];
                 if (MODE == 1) {
@@ -878,6 +911,12 @@ __global__ void __launch_bounds__(kBlock) k_velo_h(const int32_t* __restrict__ r
                                                    int nP2, int J, T omega) {
     constexpr int V = 16 / (int)sizeof(T);
     const PairLanes L = pair_lanes<V, G>(nP2, 0, 1 << 30);
+    const unsigned W = sizeof(T);
+    // FIRST gathers from the pressure block zp (nP1 rows of J), the sweeps from z
+    const __amdgpu_buffer_rsrc_t xr =
+        FIRST ? make_rsrc(zp, 0x7fffffffu) : make_rsrc(z, (unsigned)(2 * (int64_t)nP2 * J * W));
+    const unsigned lane_off = FIRST ? (unsigned)L.j * W : ((unsigned)L.c * J + L.j) * W;
+    const unsigned row_bytes = FIRST ? J * W : 2u * J * W;
     for (int s = 0; s < G / 2; ++s) {
         const int ua = L.u0 + s, ub = L.u0 + s + G / 2;
         if (ua >= L.uend) return;
@@ -887,11 +926,11 @@ __global__ void __launch_bounds__(kBlock) k_velo_h(const int32_t* __restrict__ r
         const T dw = omega * dinvA[i];
         const int64_t o = (2 * (int64_t)i + L.c) * J + L.j;
         T acc[V];
-        const HalfRow<T, FIRST> R = half_row<T, FIRST>(col, val, rp[i], rp[i + 1], FIRST ? 0 : i);
+        const HalfRow<T, FIRST> R = half_row<T, FIRST>(col, val, rp[i], rp[i + 1], row_bytes, 0);
         const int n = max(__builtin_amdgcn_readlane(R.cnt, 0), __builtin_amdgcn_readlane(R.cnt, 32));
         if constexpr (FIRST) {
             vload<T, V>(acc, in + o);   // r_u
-            pair_row<T, V, true, true>(R, n, L.half, L.c, zp + L.j, J, acc);
+            pair_row<T, V, true, true>(R, n, L.half, L.c, xr, lane_off, acc);
             if (store) vstore<T, V>(t + o, acc);
 #pragma unroll
             for (int q = 0; q < V; ++q) acc[q] *= dw;
@@ -899,7 +938,7 @@ __global__ void __launch_bounds__(kBlock) k_velo_h(const int32_t* __restrict__ r
         } else {
 #pragma unroll
             for (int q = 0; q < V; ++q) acc[q] = 0;
-            pair_row<T, V, false, false>(R, n, L.half, L.c, z + (int64_t)L.c * J + L.j, 2 * (int64_t)J, acc);
+            pair_row<T, V, false, false>(R, n, L.half, L.c, xr, lane_off, acc);
             T tv[V], zv[V];
             vload<T, V>(tv, t + o);
             vload<T, V>(zv, z + o);
@@ -1363,6 +1402,262 @@ __global__ void __launch_bounds__(NW * 64) k_velo_lds(TileView tv, const int32_t
             T tv_[VEC], zv[VEC];
             vload<T, VEC>(tv_, t + o);
             lds_load<T, VEC>(zv, xs + (tv.r2_self[rb + i * NW] * 2 + L.c) * JT + L.jj);
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) acc[q] = zv[q] + dw * (tv_[q] - acc[q]);
+            vstore<T, VEC>(zo + o, acc);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ LDS-staged rows with staged entries
+// As the LDS-staged kernels above, but the tile's CSR entries (local column
+// index and value, gathered from the global value arrays in tile order) are
+// staged into LDS beside the node values, so computing a row touches only LDS:
+// the entry index is uniform across the wavefront (an LDS broadcast read), the
+// node values are read per lane.  Entries are consumed in CSR order.
+struct TileEnt {
+    const int32_t *ta_rp, *ta_loc, *ta_gp, *tbt_rp, *tbt_loc, *tbt_gp, *tb_rp, *tb_loc, *tb_gp;
+};
+struct TileDims {
+    int max_s2, max_s1, max_ea, max_ebt, max_eb;
+};
+
+// lane i < n holds the i-th row of this wavefront in tile order: its global row
+// id and its entry bounds relative to the tile's first entry (e0)
+struct WaveTRows {
+    int n, row, p0, p1, q0, q1, self;
+};
+
+__device__ __forceinline__ WaveTRows wave_trows(int rb, int re, int wave, int NW, const int32_t* __restrict__ rows,
+                                                const int32_t* __restrict__ rpa, int ea0,
+                                                const int32_t* __restrict__ rpb, int eb0,
+                                                const int32_t* __restrict__ selfs) {
+    WaveTRows W;
+    const int lane = threadIdx.x & 63;
+    W.n = re - rb > wave ? (re - rb - wave + NW - 1) / NW : 0;
+    W.row = W.p0 = W.p1 = W.q0 = W.q1 = W.self = 0;
+    if (lane < W.n) {
+        const int r = rb + wave + lane * NW;
+        W.row = rows[r];
+        W.p0 = rpa[r] - ea0;
+        W.p1 = rpa[r + 1] - ea0;
+        if (rpb) {
+            W.q0 = rpb[r] - eb0;
+            W.q1 = rpb[r + 1] - eb0;
+        }
+        if (selfs) W.self = selfs[r];
+    }
+    return W;
+}
+
+// copies cnt staged entries: loc[e] = tloc[e0 + e], val[NV e + v] = gval[NV gp[e0 + e] + v]
+template <typename T, int NV>
+__device__ __forceinline__ void stage_entries(int32_t* loc, T* val, const int32_t* __restrict__ tloc,
+                                              const int32_t* __restrict__ tgp, const T* __restrict__ gval, int e0,
+                                              int cnt, int nthreads) {
+    for (int e = threadIdx.x; e < cnt; e += nthreads) {
+        loc[e] = tloc[e0 + e];
+        const int64_t g = tgp[e0 + e];   // -1: padding entry
+#pragma unroll
+        for (int v = 0; v < NV; ++v) val[NV * e + v] = g >= 0 ? gval[NV * g + v] : (T)0;
+    }
+}
+
+// A whole row at once: its padded entries [e0, e0 + n4) (n4 a multiple of 4,
+// at most 4 NG) are read 4 at a time (uniform LDS reads, broadcast to all
+// lanes), then all node values, then the multiply-adds in entry order.
+// acc0 += val . x; with PAIR also acc1 += val' . x (values val[2e], val[2e + 1]).
+template <typename T, int VEC, int NG, bool PAIR, bool NEG>
+__device__ __forceinline__ void lds_row_all(const int32_t* loc, const T* val, int e0, int n4, const T* base,
+                                            int stride, T (&acc0)[VEC], T (&acc1)[VEC]) {
+    int4 l[NG];
+    T a0[NG][4], a1[NG][4];
+    T v[NG][4][VEC];
+#pragma unroll
+    for (int g = 0; g < NG; ++g)
+        if (4 * g < n4) {
+            l[g] = *(const int4*)(loc + e0 + 4 * g);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if (PAIR) {
+                    a0[g][i] = val[2 * (e0 + 4 * g + i)];
+                    a1[g][i] = val[2 * (e0 + 4 * g + i) + 1];
+                } else {
+                    a0[g][i] = val[e0 + 4 * g + i];
+                }
+            }
+        }
+#pragma unroll
+    for (int g = 0; g < NG; ++g)
+        if (4 * g < n4) {
+            lds_load<T, VEC>(v[g][0], base + l[g].x * stride);
+            lds_load<T, VEC>(v[g][1], base + l[g].y * stride);
+            lds_load<T, VEC>(v[g][2], base + l[g].z * stride);
+            lds_load<T, VEC>(v[g][3], base + l[g].w * stride);
+        }
+#pragma unroll
+    for (int g = 0; g < NG; ++g)
+        if (4 * g < n4) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const T p0 = NEG ? -a0[g][i] : a0[g][i];
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) acc0[q] += p0 * v[g][i][q];
+                if (PAIR) {
+                    const T p1 = NEG ? -a1[g][i] : a1[g][i];
+#pragma unroll
+                    for (int q = 0; q < VEC; ++q) acc1[q] += p1 * v[g][i][q];
+                }
+            }
+        }
+}
+
+// y = S x (MODE 0) or y = b - S x (MODE 1)
+template <typename T, int VEC, int MODE, int NW>
+__global__ void __launch_bounds__(NW * 64) k_saddle_t(TileView tv, TileEnt te, TileDims d,
+                                                      const T* __restrict__ Aval, const T* __restrict__ Btval,
+                                                      const T* __restrict__ Bval, const T* __restrict__ dp,
+                                                      const T* __restrict__ x, const T* __restrict__ bvec,
+                                                      T* __restrict__ y, int nP2, int J, int MT) {
+    constexpr int JT = kTileJ * VEC;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* xs = (T*)smem_raw;
+    T* ps = xs + (int64_t)d.max_s2 * 2 * JT;
+    T* av = ps + (int64_t)d.max_s1 * JT;
+    T* btv = av + d.max_ea;
+    T* bv = btv + 2 * d.max_ebt;
+    int32_t* al = (int32_t*)(bv + 2 * d.max_eb);
+    int32_t* btl = al + d.max_ea;
+    int32_t* bl = btl + d.max_ebt;
+    const TileLanes L = tile_lanes<VEC>(MT);
+    const int r2b = tv.r2_ptr[L.tile], r2e = tv.r2_ptr[L.tile + 1];
+    const int r1b = tv.r1_ptr[L.tile], r1e = tv.r1_ptr[L.tile + 1];
+    const int ea0 = te.ta_rp[r2b], ebt0 = te.tbt_rp[r2b], eb0 = te.tb_rp[r1b];
+    const WaveTRows W2 = wave_trows(r2b, r2e, L.wave, NW, tv.r2, te.ta_rp, ea0, te.tbt_rp, ebt0, nullptr);
+    const WaveTRows W1 = wave_trows(r1b, r1e, L.wave, NW, tv.r1, te.tb_rp, eb0, nullptr, 0, tv.r1_self);
+    const int s20 = tv.s2_ptr[L.tile], s10 = tv.s1_ptr[L.tile];
+    const T* xp = x + 2 * (int64_t)nP2 * J;
+    stage_nodes<T, JT>(xs, tv.s2 + s20, tv.s2_ptr[L.tile + 1] - s20, x + L.j0, 2 * (int64_t)J, 2, J, NW * 64);
+    stage_nodes<T, JT>(ps, tv.s1 + s10, tv.s1_ptr[L.tile + 1] - s10, xp + L.j0, J, 1, 0, NW * 64);
+    stage_entries<T, 1>(al, av, te.ta_loc, te.ta_gp, Aval, ea0, te.ta_rp[r2e] - ea0, NW * 64);
+    stage_entries<T, 2>(btl, btv, te.tbt_loc, te.tbt_gp, Btval, ebt0, te.tbt_rp[r2e] - ebt0, NW * 64);
+    stage_entries<T, 2>(bl, bv, te.tb_loc, te.tb_gp, Bval, eb0, te.tb_rp[r1e] - eb0, NW * 64);
+    __syncthreads();
+    const T* xsc = xs + L.c * JT + L.jj;
+    const T* psc = ps + L.jj;
+    for (int i = 0; i < W2.n; ++i) {
+        T acc0[VEC], acc1[VEC], out[VEC];
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) acc0[q] = 0;
+        {
+            const int a0 = rl(W2.p0, i);
+            lds_row_all<T, VEC, kDeepA / 4, false, false>(al, av, a0, rl(W2.p1, i) - a0, xsc, 2 * JT, acc0, acc1);
+        }
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) acc1[q] = acc0[q];
+        {
+            const int b0 = rl(W2.q0, i);
+            lds_row_all<T, VEC, kDeepBt / 4, true, false>(btl, btv, b0, rl(W2.q1, i) - b0, psc, JT, acc0, acc1);
+        }
+        const int64_t o = (2 * (int64_t)rl(W2.row, i) + L.c) * J + L.j0 + L.jj;
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) out[q] = L.c ? acc1[q] : acc0[q];
+        if (MODE == 1) {
+            T b_[VEC];
+            vload<T, VEC>(b_, bvec + o);
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) out[q] = b_[q] - out[q];
+        }
+        vstore<T, VEC>(y + o, out);
+    }
+    for (int i = 0; i < W1.n; ++i) {
+        const int k = rl(W1.row, i);
+        T acc0[VEC], acc1[VEC], out[VEC];
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) acc0[q] = acc1[q] = 0;
+        {
+            const int q0 = rl(W1.p0, i);
+            lds_row_all<T, VEC, kDeepA / 4, true, false>(bl, bv, q0, rl(W1.p1, i) - q0, xsc, 2 * JT, acc0, acc1);
+        }
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) {
+            out[q] = L.c ? acc1[q] : acc0[q];
+            out[q] += __shfl_xor(out[q], 32, 64);   // the two velocity components' contributions
+        }
+        if (L.c == 0) {
+            const T dk = dp[k];
+            T v[VEC];
+            lds_load<T, VEC>(v, ps + rl(W1.self, i) * JT + L.jj);
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) out[q] += dk * v[q];
+            const int64_t o = (2 * (int64_t)nP2 + k) * J + L.j0 + L.jj;
+            if (MODE == 1) {
+                T b_[VEC];
+                vload<T, VEC>(b_, bvec + o);
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) out[q] = b_[q] - out[q];
+            }
+            vstore<T, VEC>(y + o, out);
+        }
+    }
+}
+
+// velocity-block Jacobi (operations as k_velo_v), rows and entries from LDS
+template <typename T, int VEC, bool FIRST, int NW>
+__global__ void __launch_bounds__(NW * 64) k_velo_t(TileView tv, TileEnt te, TileDims d, const T* __restrict__ val,
+                                                    const T* __restrict__ dinvA, const T* __restrict__ in,
+                                                    const T* __restrict__ zp, T* __restrict__ t,
+                                                    const T* __restrict__ z, T* __restrict__ zo, int J, int MT,
+                                                    T omega) {
+    constexpr int JT = kTileJ * VEC;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* xs = (T*)smem_raw;
+    const int nx = FIRST ? d.max_s1 * JT : d.max_s2 * 2 * JT;
+    T* ev = xs + nx;
+    int32_t* el = (int32_t*)(ev + (FIRST ? 2 * d.max_ebt : d.max_ea));
+    const TileLanes L = tile_lanes<VEC>(MT);
+    const int r2b = tv.r2_ptr[L.tile], r2e = tv.r2_ptr[L.tile + 1];
+    const int32_t* rp = FIRST ? te.tbt_rp : te.ta_rp;
+    const int e0 = rp[r2b];
+    const WaveTRows W = wave_trows(r2b, r2e, L.wave, NW, tv.r2, rp, e0, nullptr, 0, FIRST ? nullptr : tv.r2_self);
+    if (FIRST) {
+        const int s10 = tv.s1_ptr[L.tile];
+        stage_nodes<T, JT>(xs, tv.s1 + s10, tv.s1_ptr[L.tile + 1] - s10, zp + L.j0, J, 1, 0, NW * 64);
+        stage_entries<T, 2>(el, ev, te.tbt_loc, te.tbt_gp, val, e0, rp[r2e] - e0, NW * 64);
+    } else {
+        const int s20 = tv.s2_ptr[L.tile];
+        stage_nodes<T, JT>(xs, tv.s2 + s20, tv.s2_ptr[L.tile + 1] - s20, z + L.j0, 2 * (int64_t)J, 2, J, NW * 64);
+        stage_entries<T, 1>(el, ev, te.ta_loc, te.ta_gp, val, e0, rp[r2e] - e0, NW * 64);
+    }
+    __syncthreads();
+    for (int i = 0; i < W.n; ++i) {
+        const int u = rl(W.row, i);
+        const T dw = omega * dinvA[u];
+        const int64_t o = (2 * (int64_t)u + L.c) * J + L.j0 + L.jj;
+        T acc[VEC];
+        if constexpr (FIRST) {
+            T acc1[VEC];
+            vload<T, VEC>(acc, in + o);   // r_u
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) acc1[q] = acc[q];
+            const int e0_ = rl(W.p0, i);
+            lds_row_all<T, VEC, kDeepBt / 4, true, true>(el, ev, e0_, rl(W.p1, i) - e0_, xs + L.jj, JT, acc, acc1);
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) acc[q] = L.c ? acc1[q] : acc[q];
+            vstore<T, VEC>(t + o, acc);
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) acc[q] *= dw;
+            vstore<T, VEC>(zo + o, acc);
+        } else {
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) acc[q] = 0;
+            T unused[VEC];
+            const int e0_ = rl(W.p0, i);
+            lds_row_all<T, VEC, kDeepA / 4, false, false>(el, ev, e0_, rl(W.p1, i) - e0_, xs + L.c * JT + L.jj, 2 * JT,
+                                                          acc, unused);
+            T tv_[VEC], zv[VEC];
+            vload<T, VEC>(tv_, t + o);
+            lds_load<T, VEC>(zv, xs + (rl(W.self, i) * 2 + L.c) * JT + L.jj);
 #pragma unroll
             for (int q = 0; q < VEC; ++q) acc[q] = zv[q] + dw * (tv_[q] - acc[q]);
             vstore<T, VEC>(zo + o, acc);
@@ -2004,6 +2299,18 @@ mhd_status ensure_tiling(DevMesh& m, int id) {
     if (!rc) rc = up(&d->a_loc, h.a_loc);
     if (!rc) rc = up(&d->bt_loc, h.bt_loc);
     if (!rc) rc = up(&d->b_loc, h.b_loc);
+    if (!rc) rc = up(&d->ta_rp, h.ta_rp);
+    if (!rc) rc = up(&d->ta_loc, h.ta_loc);
+    if (!rc) rc = up(&d->ta_gp, h.ta_gp);
+    if (!rc) rc = up(&d->tbt_rp, h.tbt_rp);
+    if (!rc) rc = up(&d->tbt_loc, h.tbt_loc);
+    if (!rc) rc = up(&d->tbt_gp, h.tbt_gp);
+    if (!rc) rc = up(&d->tb_rp, h.tb_rp);
+    if (!rc) rc = up(&d->tb_loc, h.tb_loc);
+    if (!rc) rc = up(&d->tb_gp, h.tb_gp);
+    d->max_ea = h.max_ea;
+    d->max_ebt = h.max_ebt;
+    d->max_eb = h.max_eb;
     if (rc) {
         delete d;
         return rc;
@@ -2024,6 +2331,24 @@ inline size_t lds_bytes(const DevTiling& t, int op, int word, int vec) {
     if (op == MHD_TUNE_JACOBI) return (size_t)t.max_s2 * 2 * jt;
     return ((size_t)t.max_s2 * 2 + t.max_s1) * jt;
 }
+
+// LDS-staged kernels with staged entries (plan deep == 3): node values plus the
+// tile's entries (value and 4-byte local column)
+inline size_t lds_bytes_ent(const DevTiling& t, int op, int word, int vec) {
+    const size_t x = lds_bytes(t, op, word, vec);
+    if (op == MHD_TUNE_JACOBI_FIRST) return x + (size_t)t.max_ebt * (2 * word + 4);
+    if (op == MHD_TUNE_JACOBI) return x + (size_t)t.max_ea * (word + 4);
+    return x + (size_t)t.max_ea * (word + 4) + ((size_t)t.max_ebt + t.max_eb) * (2 * word + 4);
+}
+
+inline size_t plan_lds_bytes(const DevTiling& t, int op, int word, int vec, int deep) {
+    return deep == 3 ? lds_bytes_ent(t, op, word, vec) : lds_bytes(t, op, word, vec);
+}
+
+inline TileEnt tile_ent(const DevTiling& t) {
+    return TileEnt{t.ta_rp, t.ta_loc, t.ta_gp, t.tbt_rp, t.tbt_loc, t.tbt_gp, t.tb_rp, t.tb_loc, t.tb_gp};
+}
+inline TileDims tile_dims(const DevTiling& t) { return TileDims{t.max_s2, t.max_s1, t.max_ea, t.max_ebt, t.max_eb}; }
 
 // LDS-staged kernels: members per lane the word size admits for J
 inline bool lds_vec_ok(int J, int word, int vec) {
@@ -2092,8 +2417,22 @@ mhd_status launch_saddle_plan(NodePlan p, DevShared& S, const T* x, const T* b, 
     if (p.tile > 0 && m.tiling[p.tile] && lds_vec_ok(J, sizeof(T), p.vec) && tile_fits(*m.tiling[p.tile], p.nw)) {
         const DevTiling& tl = *m.tiling[p.tile];
         const int MT = J / (kTileJ * p.vec);
-        const size_t lds = lds_bytes(tl, MHD_TUNE_SADDLE, sizeof(T), p.vec);
+        const size_t lds = plan_lds_bytes(tl, MHD_TUNE_SADDLE, sizeof(T), p.vec, p.deep);
         const dim3 grid((unsigned)((int64_t)tl.ntiles * MT));
+        if (p.deep == 3 && deep_ok(m)) {
+            auto go3 = [&](auto kern, int threads) -> mhd_status {
+                MHD_HIP(allow_lds(kern, lds));
+                launch_k(kern, grid, dim3(threads), lds, st, tile_view(tl), tile_ent(tl), tile_dims(tl), Vals<T>::A(S),
+                         Vals<T>::Bt(S), Vals<T>::B(S), Vals<T>::dp(m), x, b, y, m.nP2, J, MT);
+                LAUNCH_CHECK();
+                return MHD_OK;
+            };
+            if constexpr (sizeof(T) == 4) {
+                if (p.vec == 2)
+                    return p.nw == 8 ? go3(k_saddle_t<T, 2, MODE, 8>, 512) : go3(k_saddle_t<T, 2, MODE, 4>, 256);
+            }
+            return p.nw == 8 ? go3(k_saddle_t<T, 1, MODE, 8>, 512) : go3(k_saddle_t<T, 1, MODE, 4>, 256);
+        }
         auto go = [&](auto kern, int threads) -> mhd_status {
             MHD_HIP(allow_lds(kern, lds));
             launch_k(kern, grid, dim3(threads), lds, st, tile_view(tl), m.A_rowptr, Vals<T>::A(S),
@@ -2173,8 +2512,23 @@ mhd_status launch_velo_plan(NodePlan p, DevShared& S, const T* in, const T* zp, 
     if (p.tile > 0 && m.tiling[p.tile] && lds_vec_ok(J, sizeof(T), p.vec) && tile_fits(*m.tiling[p.tile], p.nw)) {
         const DevTiling& tl = *m.tiling[p.tile];
         const int MT = J / (kTileJ * p.vec);
-        const size_t lds = lds_bytes(tl, FIRST ? MHD_TUNE_JACOBI_FIRST : MHD_TUNE_JACOBI, sizeof(T), p.vec);
+        const size_t lds =
+            plan_lds_bytes(tl, FIRST ? MHD_TUNE_JACOBI_FIRST : MHD_TUNE_JACOBI, sizeof(T), p.vec, p.deep);
         const dim3 grid((unsigned)((int64_t)tl.ntiles * MT));
+        if (p.deep == 3 && deep_ok(m)) {
+            auto go3 = [&](auto kern, int threads) -> mhd_status {
+                MHD_HIP(allow_lds(kern, lds));
+                hipLaunchKernelGGL(kern, grid, dim3(threads), lds, st, tile_view(tl), tile_ent(tl), tile_dims(tl), val,
+                                   Vals<T>::dA(S), in, zp, t, z, zo, J, MT, omega);
+                LAUNCH_CHECK();
+                return MHD_OK;
+            };
+            if constexpr (sizeof(T) == 4) {
+                if (p.vec == 2)
+                    return p.nw == 8 ? go3(k_velo_t<T, 2, FIRST, 8>, 512) : go3(k_velo_t<T, 2, FIRST, 4>, 256);
+            }
+            return p.nw == 8 ? go3(k_velo_t<T, 1, FIRST, 8>, 512) : go3(k_velo_t<T, 1, FIRST, 4>, 256);
+        }
         auto go = [&](auto kern, int threads) -> mhd_status {
             MHD_HIP(allow_lds(kern, lds));
             hipLaunchKernelGGL(kern, grid, dim3(threads), lds, st, tile_view(tl), rp, val, Vals<T>::dA(S), in, zp, t,
@@ -2262,9 +2616,12 @@ mhd_status tune_op(DevShared& S, int J, int op, hipStream_t st, std::vector<mhd_
         for (int id = 1; id <= kTileShapes; ++id) {
             mhd_status rc = ensure_tiling(m, id);
             if (rc) return rc;
-            if (lds_bytes(*m.tiling[id], op, word, v) > (size_t)max_lds_bytes()) continue;
-            for (int nw : {4, 8})
-                if (tile_fits(*m.tiling[id], nw)) cands.push_back(NodePlan{v, 0, id, nw, 0});
+            for (int dp : {0, 3}) {
+                if (dp == 3 && !deep_ok(m)) continue;
+                if (plan_lds_bytes(*m.tiling[id], op, word, v, dp) > (size_t)max_lds_bytes()) continue;
+                for (int nw : {4, 8})
+                    if (tile_fits(*m.tiling[id], nw)) cands.push_back(NodePlan{v, 0, id, nw, dp});
+            }
         }
     }
     PlanRec best;
@@ -2363,12 +2720,21 @@ mhd_status set_plan(DevShared& S, int J, int precision, int op, int vec, int gro
         set_error("mhd_ens_set_plan: vec must be 0 or 1, 2 (4 for FP32) with J a multiple of 32 vec");
         return MHD_EINVAL;
     }
-    if (deep) {
+    if (deep == 3 && !tile) {
+        set_error("mhd_ens_set_plan: staged entries (deep 3) need an LDS tile");
+        return MHD_EINVAL;
+    }
+    if (tile) {
+        // checked below
+    } else if (deep == 1) {
         if (!vec || !(group == 1 || group == 2 || group == 4 || group == 8) || !deep_ok(m)) {
             set_error("mhd_ens_set_plan: pipelined gathers need vec > 0, group 1, 2, 4 or 8 and rows of <= 24 (B^T: "
                       "8) entries");
             return MHD_EINVAL;
         }
+    } else if (deep != 0) {
+        set_error("mhd_ens_set_plan: deep must be 0, 1, 2 or 3");
+        return MHD_EINVAL;
     } else if (!(group == 0 || group == 1 || group == 2 || group == 4) || (group && m.max_row > kMaxRowBatched)) {
         set_error("mhd_ens_set_plan: group must be 0, 1, 2 or 4 (batched gathers need rows of <= 56 entries)");
         return MHD_EINVAL;
@@ -2377,20 +2743,22 @@ mhd_status set_plan(DevShared& S, int J, int precision, int op, int vec, int gro
     if (tile) {
         for (int k = 1; k <= kTileShapes; ++k)
             if (tile_edge(k) == tile) id = k;
-        if (!id || !(waves == 4 || waves == 8) || !lds_vec_ok(J, word, vec)) {
+        if (!id || !(waves == 4 || waves == 8) || !lds_vec_ok(J, word, vec) || !(deep == 0 || deep == 3) ||
+            (deep == 3 && !deep_ok(m))) {
             set_error("mhd_ens_set_plan: tile must be 0, 8, 12 or 16 with waves 4 or 8, vec 1 (or 2 for FP32) and J a "
                       "multiple of 32 vec");
             return MHD_EINVAL;
         }
         mhd_status rc = ensure_tiling(m, id);
         if (rc) return rc;
-        if (lds_bytes(*m.tiling[id], op, word, vec) > (size_t)max_lds_bytes() || !tile_fits(*m.tiling[id], waves)) {
+        if (plan_lds_bytes(*m.tiling[id], op, word, vec, deep) > (size_t)max_lds_bytes() ||
+            !tile_fits(*m.tiling[id], waves)) {
             set_error("mhd_ens_set_plan: tile needs more LDS or rows per wavefront than a workgroup may use");
             return MHD_EINVAL;
         }
     }
     std::lock_guard<std::mutex> lk(g_plan_mu);
-    g_plans[plan_key(m, J, word, op)] = PlanRec{NodePlan{vec, (vec && !id) ? group : 0, id, waves, (vec && !id) ? deep : 0}, 0.f};
+    g_plans[plan_key(m, J, word, op)] = PlanRec{NodePlan{vec, (vec && !id) ? group : 0, id, waves, vec ? deep : 0}, 0.f};
     return MHD_OK;
 }
 

@@ -10,6 +10,17 @@
 
 namespace mhd {
 
+namespace {
+// pads a row of tile-ordered entries to a multiple of 4 with (local column 0,
+// no global entry): the LDS-staged kernels read a row 4 entries at a time
+void pad4(std::vector<int32_t>& loc, std::vector<int32_t>& gp) {
+    while (loc.size() % 4) {
+        loc.push_back(0);
+        gp.push_back(-1);
+    }
+}
+}  // namespace
+
 void build_tiling(const HostMesh& m, int tx, int ty, HostTiling& t) {
     t = HostTiling{};
     t.tx = tx;
@@ -40,6 +51,9 @@ void build_tiling(const HostMesh& m, int tx, int ty, HostTiling& t) {
     t.b_loc.assign(m.B.col.size(), 0);
     t.r2_ptr.push_back(0);
     t.r1_ptr.push_back(0);
+    t.ta_rp.push_back(0);
+    t.tbt_rp.push_back(0);
+    t.tb_rp.push_back(0);
     t.s2_ptr.push_back(0);
     t.s1_ptr.push_back(0);
     std::vector<int32_t> loc2(nP2, -1), loc1(nP1, -1);
@@ -65,17 +79,39 @@ void build_tiling(const HostMesh& m, int tx, int ty, HostTiling& t) {
         st1.erase(std::unique(st1.begin(), st1.end()), st1.end());
         for (size_t s = 0; s < st2.size(); ++s) loc2[st2[s]] = (int32_t)s;
         for (size_t s = 0; s < st1.size(); ++s) loc1[st1[s]] = (int32_t)s;
+        const size_t ea0 = t.ta_loc.size(), ebt0 = t.tbt_loc.size(), eb0 = t.tb_loc.size();
         for (int32_t u : R2) {
-            for (int32_t p = m.A.rowptr[u]; p < m.A.rowptr[u + 1]; ++p) t.a_loc[p] = loc2[m.A.col[p]];
-            for (int32_t p = m.Bt.rowptr[u]; p < m.Bt.rowptr[u + 1]; ++p) t.bt_loc[p] = loc1[m.Bt.col[p]];
+            for (int32_t p = m.A.rowptr[u]; p < m.A.rowptr[u + 1]; ++p) {
+                t.a_loc[p] = loc2[m.A.col[p]];
+                t.ta_loc.push_back(t.a_loc[p]);
+                t.ta_gp.push_back(p);
+            }
+            pad4(t.ta_loc, t.ta_gp);
+            for (int32_t p = m.Bt.rowptr[u]; p < m.Bt.rowptr[u + 1]; ++p) {
+                t.bt_loc[p] = loc1[m.Bt.col[p]];
+                t.tbt_loc.push_back(t.bt_loc[p]);
+                t.tbt_gp.push_back(p);
+            }
+            pad4(t.tbt_loc, t.tbt_gp);
+            t.ta_rp.push_back((int32_t)t.ta_loc.size());
+            t.tbt_rp.push_back((int32_t)t.tbt_loc.size());
             t.r2.push_back(u);
             t.r2_self.push_back(loc2[u]);
         }
         for (int32_t k : R1) {
-            for (int32_t q = m.B.rowptr[k]; q < m.B.rowptr[k + 1]; ++q) t.b_loc[q] = loc2[m.B.col[q]];
+            for (int32_t q = m.B.rowptr[k]; q < m.B.rowptr[k + 1]; ++q) {
+                t.b_loc[q] = loc2[m.B.col[q]];
+                t.tb_loc.push_back(t.b_loc[q]);
+                t.tb_gp.push_back(q);
+            }
+            pad4(t.tb_loc, t.tb_gp);
+            t.tb_rp.push_back((int32_t)t.tb_loc.size());
             t.r1.push_back(k);
             t.r1_self.push_back(loc1[k]);
         }
+        t.max_ea = std::max(t.max_ea, (int)(t.ta_loc.size() - ea0));
+        t.max_ebt = std::max(t.max_ebt, (int)(t.tbt_loc.size() - ebt0));
+        t.max_eb = std::max(t.max_eb, (int)(t.tb_loc.size() - eb0));
         t.s2.insert(t.s2.end(), st2.begin(), st2.end());
         t.s1.insert(t.s1.end(), st1.begin(), st1.end());
         t.r2_ptr.push_back((int32_t)t.r2.size());

@@ -49,7 +49,7 @@ def candidates(J, word):
         out += [(16 // word, g, 2, 0, 4) for g in (4, 8)]
     for v in (2, 1):
         if J % (32 * v) == 0 and (v == 1 or word == 4):
-            out += [(v, 0, 0, t, w) for t in (8, 12, 16) for w in (4, 8)]
+            out += [(v, 0, dp, t, w) for dp in (0, 3) for t in (8, 12, 16) for w in (4, 8)]
     return out
 
 
