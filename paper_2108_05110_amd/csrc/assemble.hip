@@ -371,6 +371,109 @@ __global__ void __launch_bounds__(kBlock) k_rhs(
     }
 }
 
+// Element phase of the batched right-hand sides: group of JP lanes per
+// element, lanes over members.  For each local row a and component d the
+// element's contribution
+//   M_e (self/dt + f) - K_e (cm other + cp self) - C_e(other - <other>) self
+// (C_e the element convection matrix of the trilinear form) is written to
+// out[e][a][d][j]; k_rhs_node adds a node's contributions in element order.
+__global__ void __launch_bounds__(kBlock) k_rhs_elem(const int32_t* __restrict__ tri, const double* __restrict__ geo,
+                                                     const double* __restrict__ self, const double* __restrict__ other,
+                                                     const double* __restrict__ obar, const double* __restrict__ coef,
+                                                     const double* __restrict__ F, double* __restrict__ out, int n_el,
+                                                     int J, int JP, double inv_dt, int convective) {
+    Lanes L = lanes(JP);
+    const int64_t e = L.unit;
+    if (e >= n_el) return;
+    const Geo g = load_geo(geo, e);
+    int t[6];
+#pragma unroll
+    for (int a = 0; a < 6; ++a) t[a] = tri[e * 6 + a];
+    for (int j = L.j0; j < J; j += JP) {
+        const double cm = coef[j], cp = coef[J + j];
+        double s[6][2], ms[6][2], ks[6][2], uh[6][2];
+#pragma unroll
+        for (int b = 0; b < 6; ++b) {
+            double o[2];
+#pragma unroll
+            for (int d = 0; d < 2; ++d) {
+                const int64_t idx = (int64_t)(2 * t[b] + d) * J + j;
+                s[b][d] = self[idx];
+                o[d] = other[idx];
+                ms[b][d] = s[b][d] * inv_dt + (F ? F[idx] : 0.0);
+                ks[b][d] = cm * o[d] + cp * s[b][d];
+            }
+            const double u0 = o[0] - obar[2 * t[b]], u1 = o[1] - obar[2 * t[b] + 1];
+            uh[b][0] = g.det * (g.Ji[0][0] * u0 + g.Ji[0][1] * u1);
+            uh[b][1] = g.det * (g.Ji[1][0] * u0 + g.Ji[1][1] * u1);
+        }
+        const double(*T)[6][6][2] = convective ? c_ref.That : c_ref.Shat;
+#pragma unroll 1
+        for (int a = 0; a < 6; ++a) {
+            double r0 = 0.0, r1 = 0.0;
+#pragma unroll 2
+            for (int b = 0; b < 6; ++b) {
+                const double m = g.det * c_ref.Mhat[a][b];
+                double k = 0.0;
+#pragma unroll
+                for (int p = 0; p < 2; ++p)
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) k += c_ref.Khat[a][b][p][q] * g.G[p][q];
+                k *= g.det;
+                r0 += m * ms[b][0] - k * ks[b][0];
+                r1 += m * ms[b][1] - k * ks[b][1];
+            }
+#pragma unroll 2
+            for (int c = 0; c < 6; ++c) {
+                double cf = 0.0;
+#pragma unroll
+                for (int b = 0; b < 6; ++b) cf += T[a][b][c][0] * uh[b][0] + T[a][b][c][1] * uh[b][1];
+                r0 -= cf * s[c][0];
+                r1 -= cf * s[c][1];
+            }
+            out[((e * 6 + a) * 2) * J + j] = r0;
+            out[((e * 6 + a) * 2 + 1) * J + j] = r1;
+        }
+    }
+}
+
+// Node phase: b_i = sum over the (element, local row) incidences of node i of
+// the element contributions (element order); Dirichlet rows take g_j, the
+// pressure rows are zero.
+__global__ void __launch_bounds__(kBlock) k_rhs_node(const int32_t* __restrict__ inc_ptr, const int32_t* __restrict__ inc,
+                                                     const int32_t* __restrict__ dir_index, const double* __restrict__ part,
+                                                     const double* __restrict__ G, double* __restrict__ b, int nP2,
+                                                     int nP1, int J, int JP) {
+    Lanes L = lanes(JP);
+    const int64_t i = L.unit;
+    if (i >= (int64_t)nP2 + nP1) return;
+    if (i >= nP2) {
+        const int64_t k = i - nP2;
+        for (int j = L.j0; j < J; j += JP) b[(2 * (int64_t)nP2 + k) * J + j] = 0.0;
+        return;
+    }
+    const int di = dir_index[i];
+    if (di >= 0) {
+        for (int j = L.j0; j < J; j += JP) {
+            b[(2 * i) * J + j] = G[(2 * (int64_t)di) * J + j];
+            b[(2 * i + 1) * J + j] = G[(2 * (int64_t)di + 1) * J + j];
+        }
+        return;
+    }
+    const int32_t q0 = inc_ptr[i], q1 = inc_ptr[i + 1];
+    for (int j = L.j0; j < J; j += JP) {
+        double r0 = 0.0, r1 = 0.0;
+        for (int32_t q = q0; q < q1; ++q) {
+            const int32_t ea = inc[q];
+            const int64_t row = (int64_t)(ea >> 3) * 6 + (ea & 7);
+            r0 += part[(row * 2) * J + j];
+            r1 += part[(row * 2 + 1) * J + j];
+        }
+        b[(2 * i) * J + j] = r0;
+        b[(2 * i + 1) * J + j] = r1;
+    }
+}
+
 // per-node partial of vbar^T M vbar (both components); partial per block
 __global__ void __launch_bounds__(kBlock) k_energy(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
                                                    const double* __restrict__ valM, const double* __restrict__ vb,
@@ -451,6 +554,20 @@ hipError_t launch_rhs(const DevMesh& m, const mhd_coeffs& c, int J, const double
     hipLaunchKernelGGL(k_rhs, dim3(grid_for(units, JP)), dim3(kBlock), 0, s, m.A_rowptr, m.A_col, m.valM, m.valK,
                        m.inc_ptr, m.inc, m.tri, m.geo, m.dir_index, self_n, other_n, obar, coef, forcing, bc, rhs,
                        m.nP2, m.nP1, J, JP, 1.0 / c.dt, c.convective);
+    return hipGetLastError();
+}
+
+hipError_t launch_rhs_elem(const DevMesh& m, const mhd_coeffs& c, int J, const double* self_n, const double* other_n,
+                           const double* obar, const double* coef, const double* forcing, const double* bc,
+                           double* part, double* rhs, hipStream_t s) {
+    const int JP = pick_jp(J);
+    hipLaunchKernelGGL(k_rhs_elem, dim3(grid_for(m.n_el, JP)), dim3(kBlock), 0, s, m.tri, m.geo, self_n, other_n, obar,
+                       coef, forcing, part, m.n_el, J, JP, 1.0 / c.dt, c.convective);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t units = (int64_t)m.nP2 + m.nP1;
+    hipLaunchKernelGGL(k_rhs_node, dim3(grid_for(units, JP)), dim3(kBlock), 0, s, m.inc_ptr, m.inc, m.dir_index,
+                       (const double*)part, bc, rhs, m.nP2, m.nP1, J, JP);
     return hipGetLastError();
 }
 

@@ -63,6 +63,7 @@ struct mhd_ctx_s {
     double *bv = nullptr, *bw = nullptr;    // right-hand sides (n x Jmax)
     double *Xv = nullptr, *Xw = nullptr;    // solution blocks [velocity; pressure]
     double* coef = nullptr;                 // 2 Jmax member coefficients
+    double* rhs_part = nullptr;             // element contributions of a right-hand side (n_el x 12 x Jmax)
     double* host_coef = nullptr;            // pinned staging, 2 Jmax
     double* partial = nullptr;              // reductions
     // adjoint workspace (desc.adjoint)
@@ -397,8 +398,9 @@ mhd_status step_device(mhd_ctx ctx, const mhd_coeffs& c, const StepArgs& a, hipS
     // v-problem convected by <w>, w-problem by <v>; both from time level n
     if ((rc = assemble_shared_impl(D, c, a.W, J, Av, stv))) return rc;
     if ((rc = assemble_shared_impl(D, c, a.V, J, Aw, stv))) return rc;
-    hipError_t e = launch_rhs(D, c, J, a.V, a.W, Av.zbar, ctx->coef, a.f1, a.gv, ctx->bv, stv);
-    if (e == hipSuccess) e = launch_rhs(D, c, J, a.W, a.V, Aw.zbar, ctx->coef, a.f2, a.gw, ctx->bw, stv);
+    hipError_t e = launch_rhs_elem(D, c, J, a.V, a.W, Av.zbar, ctx->coef, a.f1, a.gv, ctx->rhs_part, ctx->bv, stv);
+    if (e == hipSuccess)
+        e = launch_rhs_elem(D, c, J, a.W, a.V, Aw.zbar, ctx->coef, a.f2, a.gw, ctx->rhs_part, ctx->bw, stv);
     if (e != hipSuccess) {
         set_error(std::string("mhd_ens_step rhs: ") + hipGetErrorString(e));
         return MHD_EHIP;
@@ -658,6 +660,7 @@ mhd_status mhd_ens_ctx_create(mhd_mesh m, const mhd_ctx_desc* d, mhd_ctx* out) {
     if ((rc = dev_alloc(c->allocs, &c->Xv, blk))) return fail(rc);
     if ((rc = dev_alloc(c->allocs, &c->Xw, blk))) return fail(rc);
     if ((rc = dev_alloc(c->allocs, &c->coef, 2 * (size_t)d->J_max))) return fail(rc);
+    if ((rc = dev_alloc(c->allocs, &c->rhs_part, (size_t)m->d.n_el * 12 * d->J_max))) return fail(rc);
     if ((rc = dev_alloc(c->allocs, &c->partial, (size_t)2048 * d->J_max + 1024))) return fail(rc);
     if (hipHostMalloc((void**)&c->host_coef, sizeof(double) * 2 * d->J_max, hipHostMallocDefault) != hipSuccess)
         return fail(MHD_ENOMEM);

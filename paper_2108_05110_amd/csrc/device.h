@@ -154,6 +154,11 @@ hipError_t launch_assemble_A(const DevMesh& m, const mhd_coeffs& c, const double
                              double* elem, double* valA, float* valA32, double* dinvA, float* dinvA32,
                              hipStream_t s);
 hipError_t launch_member_coefs(const double* nu, const double* nu_m, int J, double* coef, hipStream_t s);
+// right-hand sides in two passes (element contributions into part, n_el x 12 x J,
+// then a per-node sum); same result as launch_rhs up to the order of the sums
+hipError_t launch_rhs_elem(const DevMesh& m, const mhd_coeffs& c, int J, const double* self_n, const double* other_n,
+                           const double* obar, const double* coef, const double* forcing, const double* bc,
+                           double* part, double* rhs, hipStream_t s);
 hipError_t launch_rhs(const DevMesh& m, const mhd_coeffs& c, int J, const double* self_n,
                       const double* other_n, const double* obar, const double* coef, const double* forcing,
                       const double* bc, double* rhs, hipStream_t s);
