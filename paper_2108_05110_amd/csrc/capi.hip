@@ -63,7 +63,10 @@ struct mhd_ctx_s {
     double *bv = nullptr, *bw = nullptr;    // right-hand sides (n x Jmax)
     double *Xv = nullptr, *Xw = nullptr;    // solution blocks [velocity; pressure]
     double* coef = nullptr;                 // 2 Jmax member coefficients
-    double* rhs_part = nullptr;             // element contributions of a right-hand side (n_el x 12 x Jmax)
+    double* rhs_part = nullptr;             // element contributions of the v right-hand side (n_el x 12 x Jmax)
+    double* rhs_part_w = nullptr;           // the same for the w right-hand side
+    hipStream_t side = nullptr;             // second stream: the w-subproblem of a fixed-schedule step
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     double* host_coef = nullptr;            // pinned staging, 2 Jmax
     double* partial = nullptr;              // reductions
     // adjoint workspace (desc.adjoint)
@@ -388,40 +391,59 @@ mhd_status step_prepare(mhd_ctx ctx, const mhd_step_inputs* in, mhd_coeffs& c, h
 }
 
 // device part of a step (a1-a6): capturable into a graph when the solver runs a fixed schedule
-mhd_status step_device(mhd_ctx ctx, const mhd_coeffs& c, const StepArgs& a, hipStream_t stv, mhd_solve_stats* sv,
-                       mhd_solve_stats* sw) {
+// One subproblem of a step on stream st: shared matrix from the other
+// variable, right-hand sides, solve into X (initial guess: the state at n).
+mhd_status subproblem(mhd_ctx ctx, const mhd_coeffs& c, int J, const double* self, const double* other,
+                      const double* pres, const double* f, const double* g, DevShared& A, double* part, double* rhs,
+                      double* X, hipStream_t st, mhd_solve_stats* stats) {
     DevMesh& D = ctx->mesh->d;
-    DevShared& Av = ctx->Av->d;
-    DevShared& Aw = ctx->Aw->d;
-    const int J = a.J;
     mhd_status rc;
-    // v-problem convected by <w>, w-problem by <v>; both from time level n
-    if ((rc = assemble_shared_impl(D, c, a.W, J, Av, stv))) return rc;
-    if ((rc = assemble_shared_impl(D, c, a.V, J, Aw, stv))) return rc;
-    hipError_t e = launch_rhs_elem(D, c, J, a.V, a.W, Av.zbar, ctx->coef, a.f1, a.gv, ctx->rhs_part, ctx->bv, stv);
-    if (e == hipSuccess)
-        e = launch_rhs_elem(D, c, J, a.W, a.V, Aw.zbar, ctx->coef, a.f2, a.gw, ctx->rhs_part, ctx->bw, stv);
+    if ((rc = assemble_shared_impl(D, c, other, J, A, st))) return rc;
+    hipError_t e = launch_rhs_elem(D, c, J, self, other, A.zbar, ctx->coef, f, g, part, rhs, st);
     if (e != hipSuccess) {
         set_error(std::string("mhd_ens_step rhs: ") + hipGetErrorString(e));
         return MHD_EHIP;
     }
     const size_t vel = sizeof(double) * 2 * (size_t)D.nP2 * J;
     const size_t prs = sizeof(double) * (size_t)D.nP1 * J;
-    const int64_t poff = 2 * (int64_t)D.nP2 * J;
-    MHD_HIP(hipMemcpyAsync(ctx->Xv, a.V, vel, hipMemcpyDeviceToDevice, stv));
-    MHD_HIP(hipMemcpyAsync(ctx->Xv + poff, a.Q, prs, hipMemcpyDeviceToDevice, stv));
-    MHD_HIP(hipMemcpyAsync(ctx->Xw, a.W, vel, hipMemcpyDeviceToDevice, stv));
-    MHD_HIP(hipMemcpyAsync(ctx->Xw + poff, a.R, prs, hipMemcpyDeviceToDevice, stv));
-    mhd_status rv = solve_shared(Av, ctx->bv, ctx->Xv, J, ctx->desc.solver, sv, stv);
+    MHD_HIP(hipMemcpyAsync(X, self, vel, hipMemcpyDeviceToDevice, st));
+    MHD_HIP(hipMemcpyAsync(X + 2 * (int64_t)D.nP2 * J, pres, prs, hipMemcpyDeviceToDevice, st));
+    return solve_shared(A, rhs, X, J, ctx->desc.solver, stats, st);
+}
+
+// device part of a step (a1-a6): capturable into a graph when the solver runs
+// a fixed schedule.  Both subproblems read time level n only; with a fixed
+// schedule and `split`, the w-subproblem runs on the context's second stream,
+// forked from and joined back into stv.  The new state is written after both.
+mhd_status step_device(mhd_ctx ctx, const mhd_coeffs& c, const StepArgs& a, hipStream_t stv, mhd_solve_stats* sv,
+                       mhd_solve_stats* sw, bool split) {
+    DevMesh& D = ctx->mesh->d;
+    const int J = a.J;
+    const bool two = split && ctx->side != nullptr;
+    hipStream_t stw = two ? ctx->side : stv;
+    if (two) {
+        MHD_HIP(hipEventRecord(ctx->ev_fork, stv));
+        MHD_HIP(hipStreamWaitEvent(stw, ctx->ev_fork, 0));
+    }
+    // v-problem convected by <w>, w-problem by <v>
+    mhd_status rv = subproblem(ctx, c, J, a.V, a.W, a.Q, a.f1, a.gv, ctx->Av->d, ctx->rhs_part, ctx->bv, ctx->Xv, stv, sv);
     if (rv != MHD_OK && rv != MHD_ENOCONV) return rv;
-    mhd_status rw = solve_shared(Aw, ctx->bw, ctx->Xw, J, ctx->desc.solver, sw, stv);
+    mhd_status rw =
+        subproblem(ctx, c, J, a.W, a.V, a.R, a.f2, a.gw, ctx->Aw->d, ctx->rhs_part_w, ctx->bw, ctx->Xw, stw, sw);
     if (rw != MHD_OK && rw != MHD_ENOCONV) return rw;
+    if (two) {
+        MHD_HIP(hipEventRecord(ctx->ev_join, stw));
+        MHD_HIP(hipStreamWaitEvent(stv, ctx->ev_join, 0));
+    }
+    const size_t vel = sizeof(double) * 2 * (size_t)D.nP2 * J;
+    const size_t prs = sizeof(double) * (size_t)D.nP1 * J;
+    const int64_t poff = 2 * (int64_t)D.nP2 * J;
     MHD_HIP(hipMemcpyAsync(a.V, ctx->Xv, vel, hipMemcpyDeviceToDevice, stv));
     MHD_HIP(hipMemcpyAsync(a.Q, ctx->Xv + poff, prs, hipMemcpyDeviceToDevice, stv));
     MHD_HIP(hipMemcpyAsync(a.W, ctx->Xw, vel, hipMemcpyDeviceToDevice, stv));
     MHD_HIP(hipMemcpyAsync(a.R, ctx->Xw + poff, prs, hipMemcpyDeviceToDevice, stv));
     if (D.pin >= 0) {
-        e = launch_pressure_zero_mean(D, a.Q, J, ctx->partial, stv);
+        hipError_t e = launch_pressure_zero_mean(D, a.Q, J, ctx->partial, stv);
         if (e == hipSuccess) e = launch_pressure_zero_mean(D, a.R, J, ctx->partial, stv);
         if (e != hipSuccess) {
             set_error(std::string("pressure normalisation: ") + hipGetErrorString(e));
@@ -645,6 +667,9 @@ mhd_status mhd_ens_ctx_create(mhd_mesh m, const mhd_ctx_desc* d, mhd_ctx* out) {
     c->mesh = m;
     c->desc = *d;
     auto fail = [&](mhd_status r) {
+        if (c->side) (void)hipStreamDestroy(c->side);
+        if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+        if (c->ev_join) (void)hipEventDestroy(c->ev_join);
         if (c->Av) mhd_ens_shared_free(c->Av);
         if (c->Aw) mhd_ens_shared_free(c->Aw);
         free_list(c->allocs);
@@ -661,6 +686,15 @@ mhd_status mhd_ens_ctx_create(mhd_mesh m, const mhd_ctx_desc* d, mhd_ctx* out) {
     if ((rc = dev_alloc(c->allocs, &c->Xw, blk))) return fail(rc);
     if ((rc = dev_alloc(c->allocs, &c->coef, 2 * (size_t)d->J_max))) return fail(rc);
     if ((rc = dev_alloc(c->allocs, &c->rhs_part, (size_t)m->d.n_el * 12 * d->J_max))) return fail(rc);
+    if ((rc = dev_alloc(c->allocs, &c->rhs_part_w, (size_t)m->d.n_el * 12 * d->J_max))) return fail(rc);
+    if (d->solver.fixed_cycles > 0) {
+        if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+            set_error("mhd_ens_ctx_create: stream/event creation failed");
+            return fail(MHD_EHIP);
+        }
+    }
     if ((rc = dev_alloc(c->allocs, &c->partial, (size_t)2048 * d->J_max + 1024))) return fail(rc);
     if (hipHostMalloc((void**)&c->host_coef, sizeof(double) * 2 * d->J_max, hipHostMallocDefault) != hipSuccess)
         return fail(MHD_ENOMEM);
@@ -688,6 +722,12 @@ mhd_status mhd_ens_ctx_create(mhd_mesh m, const mhd_ctx_desc* d, mhd_ctx* out) {
 mhd_status mhd_ens_ctx_free(mhd_ctx c) {
     if (!c) return MHD_OK;
     c->graph.reset();
+    if (c->side) {
+        (void)hipStreamSynchronize(c->side);
+        (void)hipStreamDestroy(c->side);
+    }
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     mhd_ens_shared_free(c->Av);
     mhd_ens_shared_free(c->Aw);
     free_list(c->allocs);
@@ -747,7 +787,7 @@ mhd_status mhd_ens_step(mhd_ctx ctx, double* V, double* W, double* Q, double* R,
             // kernel plans are fixed into the graph: tune before capturing
             if ((rc = autotune(ctx->Av->d, a.J, ctx->desc.solver.precision, stv, false, nullptr))) return rc;
             MHD_HIP(hipStreamBeginCapture(stv, hipStreamCaptureModeThreadLocal));
-            rs = step_device(ctx, c, a, stv, &sv, &sw);
+            rs = step_device(ctx, c, a, stv, &sv, &sw, true);
             hipGraph_t graph = nullptr;
             hipError_t e = hipStreamEndCapture(stv, &graph);
             if (rs != MHD_OK && rs != MHD_ENOCONV) {
@@ -770,7 +810,7 @@ mhd_status mhd_ens_step(mhd_ctx ctx, double* V, double* W, double* Q, double* R,
         sv = ctx->graph.sv;
         sw = ctx->graph.sw;
     } else {
-        rs = step_device(ctx, c, a, stv, &sv, &sw);
+        rs = step_device(ctx, c, a, stv, &sv, &sw, true);
         if (rs != MHD_OK && rs != MHD_ENOCONV) return rs;
     }
     if (st) {
@@ -866,7 +906,8 @@ mhd_status mhd_ens_group_step(mhd_group g, double* const* V, double* const* W, d
             e = hipStreamWaitEvent(g->streams[i], g->fork, 0);
             if (e != hipSuccess) break;
             mhd_solve_stats sv, sw;
-            rs = step_device(g->ctxs[i], cs[i], args[i], g->streams[i], &sv, &sw);
+            // the ensembles of a group already run on parallel branches: no further split inside a branch
+            rs = step_device(g->ctxs[i], cs[i], args[i], g->streams[i], &sv, &sw, false);
             if (rs == MHD_ENOCONV) rs = MHD_OK;
             if (rs == MHD_OK) e = hipEventRecord(g->done[i], g->streams[i]);
             if (rs == MHD_OK && e == hipSuccess) e = hipStreamWaitEvent(st, g->done[i], 0);
