@@ -91,6 +91,7 @@ struct DevMesh {
     uint8_t* pfix = nullptr;                      // nP1: fixed rows of the pressure Laplacian
     std::vector<DevLevel> levels;
     DevTiling* tiling[kTileShapes + 1] = {};   // by shape id 1..kTileShapes, built on demand
+    int32_t* pair_sched[9] = {};               // paired-row SpMM wave order by units per wavefront (4, 8)
     // small scratch for the stand-alone RHS call (member coefficients, means)
     double* scratch_coef = nullptr;               // 2 * kMaxJ
     double* scratch_mean = nullptr;               // 2 nP2

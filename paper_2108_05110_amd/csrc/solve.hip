@@ -424,13 +424,22 @@ __global__ void __launch_bounds__(kBlock) k_saddle_g(const int32_t* __restrict__
                                                      const int32_t* __restrict__ Brp, const int32_t* __restrict__ Bcol,
                                                      const T* __restrict__ Bval, const T* __restrict__ dp,
                                                      const T* __restrict__ x, const T* __restrict__ bvec,
-                                                     T* __restrict__ y, int nP2, int nP1, int J) {
-    const GroupLanes L = group_lanes<VEC, G>();
+                                                     T* __restrict__ y, int nP2, int nP1, int J,
+                                                     const int32_t* __restrict__ sched) {
+    GroupLanes L = group_lanes<VEC, G>();
+    int uend = nP2 + nP1;
+    if (sched) {   // wave order as in pair_lanes (P1 wavefronts interleaved with the P2 ones)
+        const int w = L.u0 / G;
+        if (w >= (nP2 + G - 1) / G + (nP1 + G - 1) / G) return;
+        const int d = sched[w];
+        L.u0 = d >= 0 ? d : nP2 + (-d - 1);
+        uend = d >= 0 ? nP2 : nP2 + nP1;
+    }
     const T* xp = x + 2 * (int64_t)nP2 * J;
     const T* xc = x + (int64_t)L.c * J + L.j;
     for (int g = 0; g < G; ++g) {
         const int u = L.u0 + g;
-        if (u >= nP2 + nP1) return;
+        if (u >= uend) return;
         T acc[VEC];
 #pragma unroll
         for (int q = 0; q < VEC; ++q) acc[q] = 0;
@@ -718,8 +727,10 @@ struct PairLanes {
     int u0, uend;   // units [u0, u0 + G) of this wavefront, clipped to uend (uniform)
 };
 
+// sched (optional): wave order; entry >= 0 is a wavefront of P2 units starting
+// at that unit, entry < 0 one of P1 units starting at nP2 + (-entry - 1)
 template <int V, int G>
-__device__ __forceinline__ PairLanes pair_lanes(int nP2, int nP1, int wP2) {
+__device__ __forceinline__ PairLanes pair_lanes(int nP2, int nP1, int wP2, const int32_t* __restrict__ sched = nullptr) {
     PairLanes L;
     const int lane = threadIdx.x & 63;
     L.half = lane >> 5;
@@ -728,7 +739,17 @@ __device__ __forceinline__ PairLanes pair_lanes(int nP2, int nP1, int wP2) {
     L.j = blockIdx.y * (16 * V) + (h & 15) * V;
     const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
     const int w = __builtin_amdgcn_readfirstlane((int)(blk * (kBlock / 64) + (threadIdx.x >> 6)));
-    if (w < wP2) {
+    if (sched) {
+        const int nw = (nP2 + G - 1) / G + (nP1 + G - 1) / G;
+        const int d = w < nw ? sched[w] : -(nP1 + 1);   // past the schedule: an empty P1 wavefront
+        if (d >= 0) {
+            L.u0 = d;
+            L.uend = nP2;
+        } else {
+            L.u0 = nP2 + (-d - 1);
+            L.uend = nP2 + nP1;
+        }
+    } else if (w < wP2) {
         L.u0 = w * G;
         L.uend = nP2;
     } else {
@@ -845,9 +866,10 @@ __global__ void __launch_bounds__(kBlock) k_saddle_h(const int32_t* __restrict__
                                                      const int32_t* __restrict__ Brp, const int32_t* __restrict__ Bcol,
                                                      const T* __restrict__ Bval, const T* __restrict__ dp,
                                                      const T* __restrict__ x, const T* __restrict__ bvec,
-                                                     T* __restrict__ y, int nP2, int nP1, int J, int wP2) {
+                                                     T* __restrict__ y, int nP2, int nP1, int J, int wP2,
+                                                     const int32_t* __restrict__ sched) {
     constexpr int V = 16 / (int)sizeof(T);
-    const PairLanes L = pair_lanes<V, G>(nP2, nP1, wP2);
+    const PairLanes L = pair_lanes<V, G>(nP2, nP1, wP2, sched);
     const unsigned W = sizeof(T);
     const __amdgpu_buffer_rsrc_t xr = make_rsrc(x, (unsigned)((2 * (int64_t)nP2 + nP1) * J * W));
     const unsigned vrow = 2u * J * W;                      // bytes per velocity node (both components)
@@ -2319,6 +2341,38 @@ mhd_status ensure_tiling(DevMesh& m, int id) {
     return MHD_OK;
 }
 
+// Wave order of the paired-row and batched SpMM with g units per wavefront: the wavefronts
+// of P2 units and of P1 units sorted by the P2 index of their first node, so
+// that the divergence rows of a region run right after its velocity rows and
+// find the velocity members they gather in L2.  Built once per mesh and g.
+mhd_status ensure_pair_sched(DevMesh& m, int g) {
+    if (g != 1 && g != 2 && g != 4 && g != 8) return MHD_OK;
+    std::lock_guard<std::mutex> lk(g_tiling_mu);
+    if (m.pair_sched[g]) return MHD_OK;
+    const HostMesh& h = m.host;
+    std::vector<int32_t> p2_of_p1(m.nP1, 0);
+    for (int i = 0; i < m.nP2; ++i)
+        if (h.p1_of_p2[i] >= 0) p2_of_p1[h.p1_of_p2[i]] = i;
+    std::vector<std::pair<int64_t, int32_t>> waves;   // (key, entry)
+    for (int u = 0; u < m.nP2; u += g) waves.push_back({2 * (int64_t)u, u});
+    for (int k = 0; k < m.nP1; k += g) waves.push_back({2 * (int64_t)p2_of_p1[k] + 1, -(k + 1)});
+    std::sort(waves.begin(), waves.end());
+    std::vector<int32_t> sched(waves.size());
+    for (size_t i = 0; i < waves.size(); ++i) sched[i] = waves[i].second;
+    int32_t* d = nullptr;
+    hipError_t e = hipMalloc((void**)&d, sched.size() * sizeof(int32_t));
+    if (e == hipSuccess) {
+        m.allocs.push_back(d);
+        e = hipMemcpy(d, sched.data(), sched.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) {
+        set_error(std::string("pair schedule upload: ") + hipGetErrorString(e));
+        return MHD_ENOMEM;
+    }
+    m.pair_sched[g] = d;
+    return MHD_OK;
+}
+
 inline TileView tile_view(const DevTiling& t) {
     return TileView{t.r2_ptr, t.r2, t.r2_self, t.r1_ptr, t.r1, t.r1_self, t.s2_ptr, t.s2, t.s1_ptr, t.s1,
                     t.a_loc, t.bt_loc, t.b_loc};
@@ -2452,9 +2506,9 @@ mhd_status launch_saddle_plan(NodePlan p, DevShared& S, const T* x, const T* b, 
             constexpr int GG = decltype(Gc)::value;
             const int wP2 = (m.nP2 + GG - 1) / GG, wP1 = (m.nP1 + GG - 1) / GG;
             const dim3 grid((unsigned)((wP2 + wP1 + 3) / 4), J / (256 / (int)sizeof(T)));
-            launch_k(k_saddle_h<T, MODE, GG>, grid, dim3(kBlock), 0, st, m.A_rowptr, m.A_col,
-                               Vals<T>::A(S), m.Bt_rowptr, m.Bt_col, Vals<T>::Bt(S), m.B_rowptr, m.B_col,
-                               Vals<T>::B(S), Vals<T>::dp(m), x, b, y, m.nP2, m.nP1, J, wP2);
+            launch_k(k_saddle_h<T, MODE, GG>, grid, dim3(kBlock), 0, st, m.A_rowptr, m.A_col, Vals<T>::A(S),
+                     m.Bt_rowptr, m.Bt_col, Vals<T>::Bt(S), m.B_rowptr, m.B_col, Vals<T>::B(S), Vals<T>::dp(m), x, b,
+                     y, m.nP2, m.nP1, J, wP2, (const int32_t*)m.pair_sched[GG]);
             LAUNCH_CHECK();
             return MHD_OK;
         });
@@ -2490,9 +2544,12 @@ mhd_status launch_saddle_plan(NodePlan p, DevShared& S, const T* x, const T* b, 
                                    m.A_rowptr, m.A_col, Vals<T>::A(S), m.Bt_rowptr, m.Bt_col, Vals<T>::Bt(S),
                                    m.B_rowptr, m.B_col, Vals<T>::B(S), Vals<T>::dp(m), x, b, y, m.nP2, m.nP1, J);
             } else {
-                launch_k(k_saddle_g<T, VV, MODE, GG>, group_grid(units, J, VV, GG), dim3(kBlock), 0, st,
-                                   m.A_rowptr, m.A_col, Vals<T>::A(S), m.Bt_rowptr, m.Bt_col, Vals<T>::Bt(S),
-                                   m.B_rowptr, m.B_col, Vals<T>::B(S), Vals<T>::dp(m), x, b, y, m.nP2, m.nP1, J);
+                const int32_t* sched = m.pair_sched[GG];
+                const int64_t nw = sched ? (m.nP2 + GG - 1) / GG + (m.nP1 + GG - 1) / GG : (units + GG - 1) / GG;
+                const dim3 grid((unsigned)((nw + kBlock / 64 - 1) / (kBlock / 64)), J / (32 * VV));
+                launch_k(k_saddle_g<T, VV, MODE, GG>, grid, dim3(kBlock), 0, st, m.A_rowptr, m.A_col, Vals<T>::A(S),
+                         m.Bt_rowptr, m.Bt_col, Vals<T>::Bt(S), m.B_rowptr, m.B_col, Vals<T>::B(S), Vals<T>::dp(m), x,
+                         b, y, m.nP2, m.nP1, J, sched);
             }
             LAUNCH_CHECK();
             return MHD_OK;
@@ -2605,12 +2662,20 @@ mhd_status tune_op(DevShared& S, int J, int op, hipStream_t st, std::vector<mhd_
         if (J % (32 * v)) continue;
         cands.push_back(NodePlan{v, 0, 0, 4, 0});
         if (m.max_row <= kMaxRowBatched)
-            for (int g : {1, 2, 4}) cands.push_back(NodePlan{v, g, 0, 4, 0});
+            for (int g : {1, 2, 4}) {
+                mhd_status rc = ensure_pair_sched(m, g);
+                if (rc) return rc;
+                cands.push_back(NodePlan{v, g, 0, 4, 0});
+            }
         if (deep_ok(m))
             for (int g : {1, 2, 4, 8}) cands.push_back(NodePlan{v, g, 0, 4, 1});
     }
     if (pair_ok(m, J, word))
-        for (int g : {4, 8}) cands.push_back(NodePlan{16 / word, g, 0, 4, 2});
+        for (int g : {4, 8}) {
+            mhd_status rc = ensure_pair_sched(m, g);
+            if (rc) return rc;
+            cands.push_back(NodePlan{16 / word, g, 0, 4, 2});
+        }
     for (int v : {2, 1}) {
         if (!lds_vec_ok(J, word, v)) continue;
         for (int id = 1; id <= kTileShapes; ++id) {
@@ -2712,6 +2777,8 @@ mhd_status set_plan(DevShared& S, int J, int precision, int op, int vec, int gro
                       "<= 32 entries");
             return MHD_EINVAL;
         }
+        mhd_status rc = ensure_pair_sched(m, group);
+        if (rc) return rc;
         std::lock_guard<std::mutex> lk(g_plan_mu);
         g_plans[plan_key(m, J, word, op)] = PlanRec{NodePlan{16 / word, group, 0, 4, 2}, 0.f};
         return MHD_OK;
@@ -2757,6 +2824,10 @@ mhd_status set_plan(DevShared& S, int J, int precision, int op, int vec, int gro
             return MHD_EINVAL;
         }
     }
+    if (vec && !id && deep == 0 && group) {
+        mhd_status rc = ensure_pair_sched(m, group);
+        if (rc) return rc;
+    }
     std::lock_guard<std::mutex> lk(g_plan_mu);
     g_plans[plan_key(m, J, word, op)] = PlanRec{NodePlan{vec, (vec && !id) ? group : 0, id, waves, vec ? deep : 0}, 0.f};
     return MHD_OK;
@@ -2780,6 +2851,7 @@ mhd_status autotune(DevShared& S, int J, int precision, hipStream_t st, bool for
     for (int op : {MHD_TUNE_SADDLE, MHD_TUNE_JACOBI_FIRST, MHD_TUNE_JACOBI, MHD_TUNE_RESIDUAL}) {
         const NodePlan p = get_plan(m, J, op == MHD_TUNE_RESIDUAL ? 8 : word, op);
         if (p.tile && (rc = ensure_tiling(*S.mesh, p.tile))) return rc;
+        if ((p.deep == 2 || (p.deep == 0 && p.tile == 0)) && (rc = ensure_pair_sched(*S.mesh, p.g))) return rc;
     }
     return MHD_OK;
 }
