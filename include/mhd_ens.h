@@ -210,6 +210,10 @@ typedef struct {
                                  first call (per argument set and stream) and replay it
                                  afterwards; needs solver.fixed_cycles > 0 and a non-null
                                  stream */
+    int serial;               /* 0 (default): with a fixed schedule the w-subproblem runs on
+                                 a second stream of the context, concurrently with the
+                                 v-subproblem (both read time level n only); 1: both on the
+                                 caller's stream, one after the other */
 } mhd_ctx_desc;
 mhd_status mhd_ens_ctx_create(mhd_mesh m, const mhd_ctx_desc* d, mhd_ctx* out);
 mhd_status mhd_ens_ctx_free(mhd_ctx ctx);

@@ -79,7 +79,7 @@ class SolveStats(C.Structure):
 
 class CtxDesc(C.Structure):
     _fields_ = [("coeffs", Coeffs), ("solver", SolverOpts), ("J_max", C.c_int), ("adjoint", C.c_int),
-                ("graph", C.c_int)]
+                ("graph", C.c_int), ("serial", C.c_int)]
 
 
 class AdjointInputs(C.Structure):

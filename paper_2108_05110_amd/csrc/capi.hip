@@ -687,7 +687,7 @@ mhd_status mhd_ens_ctx_create(mhd_mesh m, const mhd_ctx_desc* d, mhd_ctx* out) {
     if ((rc = dev_alloc(c->allocs, &c->coef, 2 * (size_t)d->J_max))) return fail(rc);
     if ((rc = dev_alloc(c->allocs, &c->rhs_part, (size_t)m->d.n_el * 12 * d->J_max))) return fail(rc);
     if ((rc = dev_alloc(c->allocs, &c->rhs_part_w, (size_t)m->d.n_el * 12 * d->J_max))) return fail(rc);
-    if (d->solver.fixed_cycles > 0) {
+    if (d->solver.fixed_cycles > 0 && !d->serial) {
         if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
             hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {

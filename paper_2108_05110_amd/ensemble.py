@@ -45,7 +45,7 @@ class Stepper:
     """Algorithm 1 on the GPU for one ensemble: mhd_ens_step per time step."""
 
     def __init__(self, mesh: Mesh, problem, J_max=None, opts=None, device="cuda", time_dependent_data=True,
-                 adjoint=False, graph=False, stream=None):
+                 adjoint=False, graph=False, stream=None, serial=False):
         self.mesh = mesh
         self.pb = problem
         self.J = problem.J
@@ -53,7 +53,7 @@ class Stepper:
         self.opts = opts if opts is not None else L.solver_opts()
         desc = L.CtxDesc(L.Coeffs(problem.dt, problem.mu, float(np.mean(problem.nu)),
                                   float(np.mean(problem.nu_m)), int(problem.convective)),
-                         self.opts, J_max or self.J, 1 if adjoint else 0, 1 if graph else 0)
+                         self.opts, J_max or self.J, 1 if adjoint else 0, 1 if graph else 0, 1 if serial else 0)
         # graph capture needs a stream other than the legacy null stream (default priority)
         self.stream = stream if stream is not None else (torch.cuda.Stream() if graph else None)
         self.ctx = L.mhd_ens_ctx_create(mesh.handle, desc)
