@@ -466,7 +466,7 @@ def large_workload(args, L, wl, torch):
     el = time.perf_counter() - t0
     total_members = sum(s.J for s in steppers)
     # SpMM of the 512^2 ensemble alone, eager, with HIP events
-    big = Stepper(meshes[0], specs[0][1], opts=opts, time_dependent_data=False)
+    big = Stepper(meshes[0], specs[0][1], opts=opts, time_dependent_data=False, serial=True)
     big.step(stats=False)
     L.mhd_ens_timer_enable(True)
     timed_steps(big, 1)
