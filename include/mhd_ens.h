@@ -178,6 +178,8 @@ typedef struct {
                                  synchronisation (graph-capturable); rtol, inner_rtol,
                                  maxit and check_every are then ignored and the stats
                                  report max_relres = -1, converged = -1              */
+    double jacobi_omega;      /* damping of the velocity-block Jacobi sweeps, in (0, 1.5];
+                                 0 = the default 0.85                                 */
 } mhd_solver_opts;
 
 typedef struct {

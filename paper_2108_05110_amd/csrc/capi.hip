@@ -326,6 +326,7 @@ mhd_status assemble_shared_impl(DevMesh& m, const mhd_coeffs& c, const double* z
     hipError_t e = launch_mean(z, S.zbar, 2 * (int64_t)m.nP2, J, s);
     if (e == hipSuccess) e = launch_eddy_l2(m, z, S.zbar, S.l2, J, s);
     if (e == hipSuccess) e = launch_assemble_A(m, c, S.zbar, S.l2, S.elem, S.valA, S.valA32, S.dinvA, S.dinvA32, s);
+    if (e == hipSuccess) e = scatter_ell_values(S, s);
     if (e != hipSuccess) {
         set_error(std::string("assemble_shared: ") + hipGetErrorString(e));
         return MHD_EHIP;
@@ -345,6 +346,8 @@ mhd_status check_solver_opts(const mhd_solver_opts* o) {
     CHECK_ARG(o->jacobi_sweeps >= 1 && o->jacobi_sweeps <= 16, "jacobi_sweeps must be in [1, 16]");
     CHECK_ARG(o->cgs_passes >= 0 && o->cgs_passes <= 2, "cgs_passes must be 0, 1 or 2");
     CHECK_ARG(o->fixed_cycles >= 0 && o->fixed_cycles <= 64, "fixed_cycles must be in [0, 64]");
+    CHECK_ARG(o->jacobi_omega == 0 || (std::isfinite(o->jacobi_omega) && o->jacobi_omega > 0 && o->jacobi_omega <= 1.5),
+              "jacobi_omega must be 0 (default) or in (0, 1.5]");
     return MHD_OK;
 }
 
@@ -528,6 +531,10 @@ mhd_status mhd_ens_mesh_free(mhd_mesh m) {
     if (!m) return MHD_OK;
     free_list(m->d.allocs);
     for (auto*& t : m->d.tiling) {
+        delete t;
+        t = nullptr;
+    }
+    for (auto*& t : m->d.ell) {
         delete t;
         t = nullptr;
     }

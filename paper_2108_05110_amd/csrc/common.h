@@ -96,6 +96,36 @@ struct HostTiling {
 };
 void build_tiling(const HostMesh& m, int tx, int ty, HostTiling& t);
 
+// Row-per-lane tiles of the saddle-point operator (sliced ELL over LDS-staged
+// node values).  Rectangles of tx x ty half-steps as above; a workgroup stages
+// the values of kEllM members of every node its rows read, then each lane
+// computes one row.  A tile's P2 rows (sorted by entry counts, longest first)
+// and its P1 rows are cut into blocks of 64, one wavefront each; a block's
+// entries are stored column-major (entry k of all 64 lanes together), padded
+// to the longest row of the block with (the first slot of the kind the entries
+// read, CSR position -1).
+constexpr int kEllM = 16;          // members per workgroup
+constexpr int kEllP2Bytes = 144;   // LDS bytes per staged P2 node: 2 x kEllM floats + 16 bytes padding
+constexpr int kEllP1Bytes = 80;    // LDS bytes per staged P1 node: kEllM floats + 16 bytes padding
+struct HostEll {
+    int tx = 0, ty = 0, ntiles = 0;
+    int max_lds = 0;                 // largest staged bytes of a tile
+    int max_lds1 = 0;                // largest staged bytes of a tile's P1 nodes alone
+    int max_lds2 = 0;                // largest staged bytes of a tile's P2 nodes alone
+    int max_blocks = 0;              // largest number of row blocks of a tile
+    int max_blocks2 = 0;             // largest number of P2 row blocks of a tile (they come first)
+    int max_k = 0;                   // longest row
+    std::vector<int32_t> tile;       // 8 per tile: s2 offset, s2 count, s1 offset, s1 count, first block, blocks
+    std::vector<int32_t> s2, s1;     // staged P2 / P1 nodes of every tile (ascending within a tile)
+    std::vector<int32_t> blk;        // 8 per block: kind (0 P2, 1 P1), rows, K1, K2, entries 1, entries 2, row offset
+    std::vector<int32_t> rows;       // 64 per block: row (P2 node or P1 node) or -1
+    std::vector<int32_t> self;       // 64 per block: LDS offset of the row's own node
+    std::vector<int32_t> loc;        // per entry: LDS byte offset of the staged node it reads
+    std::vector<int32_t> gp;         // per entry: position in the CSR value arrays, -1 for padding
+};
+// P2 blocks: entries 1 are A (K1 per lane), entries 2 are B^T (K2); P1 blocks: entries 1 are B.
+void build_ell(const HostMesh& m, int tx, int ty, HostEll& t);
+
 mhd_status build_mesh(const mhd_mesh_desc* d, HostMesh& m, bool full);
 mhd_status schur_values(HostMesh& m, double dt, double nu_c);
 void mesh_counts(const HostMesh& m, mhd_mesh_info* info);

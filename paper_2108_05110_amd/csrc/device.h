@@ -55,6 +55,25 @@ struct DevTiling {
 constexpr int kTileShapes = 3;          // square tiles of 8, 12 or 16 half-steps
 inline int tile_edge(int id) { return id == 1 ? 8 : id == 2 ? 12 : 16; }
 
+// Row-per-lane tiles on the device (layout as HostEll).  Entry values: the B^T
+// and B values are mesh constants (bv0, bv1: first and second value of the
+// entry, 0 for A entries and padding); the A values live with each shared
+// operator (DevShared::ellA) and are scattered there by the assembly through
+// posA (CSR position of an A entry -> its entry index).
+struct DevEll {
+    int tx = 0, ty = 0, ntiles = 0, max_lds = 0, max_lds1 = 0, max_lds2 = 0, max_blocks = 0, max_blocks2 = 0;
+    int max_k = 0;
+    int64_t nent = 0;
+    int32_t *tile = nullptr, *s2 = nullptr, *s1 = nullptr, *blk = nullptr, *rows = nullptr, *self = nullptr;
+    int32_t* loc = nullptr;
+    float *bv0 = nullptr, *bv1 = nullptr;
+    int32_t* posA = nullptr;
+};
+constexpr double kJacobiOmega = 0.85;  // velocity-block Jacobi damping when the options leave it 0
+constexpr int kEllShapes = 3;           // rectangles of 16 x 16, 32 x 8 and 16 x 8 half-steps
+inline int ell_tx(int id) { return id == 2 ? 32 : 16; }
+inline int ell_ty(int id) { return id == 1 ? 16 : 8; }
+
 struct DevMesh {
     HostMesh host;
     int nP2 = 0, nP1 = 0, n_el = 0, n_dir = 0, pin = -1;
@@ -91,6 +110,7 @@ struct DevMesh {
     uint8_t* pfix = nullptr;                      // nP1: fixed rows of the pressure Laplacian
     std::vector<DevLevel> levels;
     DevTiling* tiling[kTileShapes + 1] = {};   // by shape id 1..kTileShapes, built on demand
+    DevEll* ell[kEllShapes + 1] = {};          // row-per-lane tiles by shape id 1..kEllShapes, built on demand
     int32_t* pair_sched[9] = {};               // paired-row SpMM wave order by units per wavefront (4, 8)
     // small scratch for the stand-alone RHS call (member coefficients, means)
     double* scratch_coef = nullptr;               // 2 * kMaxJ
@@ -141,6 +161,8 @@ struct DevShared {
     double* elem = nullptr;       // n_el x 36
     mhd_coeffs coeffs{};
     bool assembled = false;
+    float* ellA[kEllShapes + 1] = {};   // A values in the entry order of the row-per-lane tiles (FP32)
+    bool ell_live[kEllShapes + 1] = {};  // a plan uses the tiling: assemblies refresh ellA
     GmresWork gw;
     std::vector<void*> allocs;
 };
@@ -176,6 +198,8 @@ mhd_status set_plan(DevShared& S, int J, int precision, int op, int vec, int gro
 mhd_status timer_enable(int on);
 mhd_status timer_read(double* ms, int64_t* launches, double* nJ32, double* nJ64);
 mhd_status saddle_residual64(DevShared& S, const double* b, const double* x, double* r, int J, hipStream_t s);
+// copies the FP32 A values into every row-per-lane entry array the operator holds
+hipError_t scatter_ell_values(DevShared& S, hipStream_t s);
 
 hipError_t launch_reduce_rows(const double* partial, int nblk, int64_t width, double* out, hipStream_t s);
 

@@ -971,6 +971,349 @@ __global__ void __launch_bounds__(kBlock) k_velo_h(const int32_t* __restrict__ r
     }
 }
 
+// ------------------------------------------------------------------ row-per-lane tiles (sliced ELL)
+// One workgroup per (tile, slice of kEllM members).  The workgroup first copies
+// the slice of every node value its rows read into LDS (all loads of a thread
+// in flight before its LDS stores), then each wavefront takes one block of 64
+// rows, one row per lane: per entry the lane reads the entry's LDS offset and
+// value (coalesced, the block's entries are stored column-major, prefetched a
+// chunk ahead) and the staged node with 16-byte LDS reads, and accumulates all
+// kEllM members of both components.  Entries are consumed in CSR order with the
+// same operations as the other SpMM kernels, so the results agree bitwise.
+struct EllView {
+    const int32_t *tile, *s2, *s1, *blk, *rows, *self, *loc;
+    const float *av, *bv0, *bv1;
+};
+
+constexpr int kEllChunk = 4;   // entries per prefetch chunk
+
+struct EllMeta {
+    int off[kEllChunk];
+    float a[kEllChunk], b[kEllChunk];
+};
+
+template <bool PAIR>
+__device__ __forceinline__ void ell_meta(EllMeta& M, const EllView& E, const float* __restrict__ v0,
+                                         const float* __restrict__ v1, int e, int k0, int K) {
+#pragma unroll
+    for (int i = 0; i < kEllChunk; ++i) {
+        const int k = k0 + i;
+        M.off[i] = 0;
+        M.a[i] = 0.f;
+        M.b[i] = 0.f;
+        if (k < K) {
+            M.off[i] = E.loc[e + 64 * k];
+            M.a[i] = v0[e + 64 * k];
+            if (PAIR) M.b[i] = v1[e + 64 * k];
+        }
+    }
+}
+
+// Copies the kEllM-member slice (members j0 ...) of n2 velocity nodes (rows 2 node
+// and 2 node + 1 of v2) to LDS slots of kEllP2Bytes from offset 0, and of n1
+// pressure nodes (row node of v1) to slots of kEllP1Bytes from offset dst1.  A
+// P2 node is 8 chunks of 16 bytes (component q / 4, members 4 (q % 4) ...), a P1
+// node 4.  Branch-free so that all loads of a thread are in flight together:
+// chunks past the end reload the first listed node and go to a 16-byte slot past
+// the staged values.
+template <int NT>
+__device__ __forceinline__ void ell_stage(unsigned char* lds, const int32_t* __restrict__ s2, int n2,
+                                          const int32_t* __restrict__ s1, int n1, int dst1,
+                                          const float* __restrict__ v2, const float* __restrict__ v1, int J, int j0) {
+    const int c2 = n2 * 8, tot = c2 + n1 * 4;
+    const int spill = max(n2 * kEllP2Bytes, dst1 + n1 * kEllP1Bytes);
+    for (int base = threadIdx.x; base < tot; base += 8 * NT) {
+        int row[8], dst[8];
+        bool one[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int i = base + k * NT;
+            const bool is2 = i < c2, is1 = !is2 && i < tot;
+            const int j = is2 ? i : (is1 ? i - c2 : 0);   // chunk within its kind
+            const int sl = is1 ? (j >> 2) : (j >> 3);
+            const int node = is1 ? s1[sl] : (n2 ? s2[sl] : s1[0]);
+            one[k] = is1 || !n2;
+            row[k] = one[k] ? node : 2 * node + ((j >> 2) & 1);
+            dst[k] = is2 ? sl * kEllP2Bytes + ((j >> 2) & 1) * (kEllM * 4) + (j & 3) * 16
+                         : (is1 ? dst1 + sl * kEllP1Bytes + (j & 3) * 16 : spill);
+        }
+        float4 v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int i = base + k * NT;
+            const int j = i < c2 ? i : (i < tot ? i - c2 : 0);
+            const float* src = one[k] ? v1 : v2;
+            v[k] = *(const float4*)(src + (int64_t)row[k] * J + j0 + (j & 3) * 4);
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) *(float4*)(lds + dst[k]) = v[k];
+    }
+}
+
+// y = S x, FP32, J a multiple of kEllM; NW wavefronts per workgroup (>= blocks of any tile)
+template <int NW>
+__global__ void __launch_bounds__(NW * 64) k_saddle_e(EllView E, const float* __restrict__ dp,
+                                                      const float* __restrict__ x, float* __restrict__ y, int nP2,
+                                                      int J, int MS) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    constexpr int NT = NW * 64;
+    const int64_t bid = xcd_block(blockIdx.x, gridDim.x);
+    const int tile = (int)(bid / MS);
+    const int j0 = (int)(bid % MS) * kEllM;
+    const int32_t* td = E.tile + 8 * tile;
+    const int s2o = td[0], n2 = td[1], s1o = td[2], n1 = td[3], b0 = td[4], nb = td[5];
+    ell_stage<NT>(smem_raw, E.s2 + s2o, n2, E.s1 + s1o, n1, n2 * kEllP2Bytes, x, x + 2 * (int64_t)nP2 * J, J, j0);
+    __syncthreads();
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    if (wave >= nb) return;
+    const int32_t* bd = E.blk + 8 * (b0 + wave);
+    const int kind = bd[0], K1 = bd[2], K2 = bd[3], e1 = bd[4] + lane, e2 = bd[5] + lane, ro = bd[6];
+    const int row = E.rows[ro + lane];
+    if (kind == 0) {
+        float acc[2][kEllM];
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int m = 0; m < kEllM; ++m) acc[c][m] = 0.f;
+        EllMeta cur, nxt;
+        ell_meta<false>(cur, E, E.av, nullptr, e1, 0, K1);
+        for (int k0 = 0; k0 < K1; k0 += kEllChunk) {
+            if (k0 + kEllChunk < K1)
+                ell_meta<false>(nxt, E, E.av, nullptr, e1, k0 + kEllChunk, K1);
+            else
+                ell_meta<true>(nxt, E, E.bv0, E.bv1, e2, 0, K2);   // the B^T part's first chunk
+#pragma unroll
+            for (int i = 0; i < kEllChunk; ++i) {
+                if (k0 + i >= K1) break;
+                const float4* xs = (const float4*)(smem_raw + cur.off[i]);
+                const float a = cur.a[i];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const float4 w = xs[q];
+                    float* r = &acc[q >> 2][(q & 3) * 4];
+                    r[0] += a * w.x;
+                    r[1] += a * w.y;
+                    r[2] += a * w.z;
+                    r[3] += a * w.w;
+                }
+            }
+            cur = nxt;
+        }
+        if (K1 == 0) ell_meta<true>(cur, E, E.bv0, E.bv1, e2, 0, K2);
+        for (int k0 = 0; k0 < K2; k0 += kEllChunk) {
+            if (k0 + kEllChunk < K2) ell_meta<true>(nxt, E, E.bv0, E.bv1, e2, k0 + kEllChunk, K2);
+#pragma unroll
+            for (int i = 0; i < kEllChunk; ++i) {
+                if (k0 + i >= K2) break;
+                const float4* ps = (const float4*)(smem_raw + cur.off[i]);
+                const float a0 = cur.a[i], a1 = cur.b[i];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const float4 w = ps[q];
+                    acc[0][4 * q + 0] += a0 * w.x;
+                    acc[0][4 * q + 1] += a0 * w.y;
+                    acc[0][4 * q + 2] += a0 * w.z;
+                    acc[0][4 * q + 3] += a0 * w.w;
+                    acc[1][4 * q + 0] += a1 * w.x;
+                    acc[1][4 * q + 1] += a1 * w.y;
+                    acc[1][4 * q + 2] += a1 * w.z;
+                    acc[1][4 * q + 3] += a1 * w.w;
+                }
+            }
+            cur = nxt;
+        }
+        if (row >= 0) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                float4* o = (float4*)(y + (2 * (int64_t)row + c) * J + j0);
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    o[q] = make_float4(acc[c][4 * q], acc[c][4 * q + 1], acc[c][4 * q + 2], acc[c][4 * q + 3]);
+            }
+        }
+    } else {
+        float ax[kEllM], ay[kEllM];
+#pragma unroll
+        for (int m = 0; m < kEllM; ++m) ax[m] = ay[m] = 0.f;
+        EllMeta cur, nxt;
+        ell_meta<true>(cur, E, E.bv0, E.bv1, e1, 0, K1);
+        for (int k0 = 0; k0 < K1; k0 += kEllChunk) {
+            if (k0 + kEllChunk < K1) ell_meta<true>(nxt, E, E.bv0, E.bv1, e1, k0 + kEllChunk, K1);
+#pragma unroll
+            for (int i = 0; i < kEllChunk; ++i) {
+                if (k0 + i >= K1) break;
+                const float4* xs = (const float4*)(smem_raw + cur.off[i]);
+                const float a0 = cur.a[i], a1 = cur.b[i];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const float4 w = xs[q], u = xs[4 + q];
+                    ax[4 * q + 0] += a0 * w.x;
+                    ax[4 * q + 1] += a0 * w.y;
+                    ax[4 * q + 2] += a0 * w.z;
+                    ax[4 * q + 3] += a0 * w.w;
+                    ay[4 * q + 0] += a1 * u.x;
+                    ay[4 * q + 1] += a1 * u.y;
+                    ay[4 * q + 2] += a1 * u.z;
+                    ay[4 * q + 3] += a1 * u.w;
+                }
+            }
+            cur = nxt;
+        }
+        if (row >= 0) {
+            const float d = dp[row];
+            const float4* ps = (const float4*)(smem_raw + E.self[ro + lane]);
+            float4* o = (float4*)(y + (2 * (int64_t)nP2 + row) * J + j0);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float4 w = ps[q];
+                float r[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) r[t] = ax[4 * q + t] + ay[4 * q + t];
+                r[0] += d * w.x;
+                r[1] += d * w.y;
+                r[2] += d * w.z;
+                r[3] += d * w.w;
+                o[q] = make_float4(r[0], r[1], r[2], r[3]);
+            }
+        }
+    }
+}
+
+// Velocity-block Jacobi with row-per-lane tiles (operations as k_velo_h): FIRST
+// stages the pressure slice of z_p and forms t = r_u - B^T z_p, z = w D^-1 t;
+// the other sweeps stage the velocity slice of z and form z + w D^-1 (t - A z).
+// Only the P2 row blocks (the first of a tile) are computed.
+template <bool FIRST, int NW>
+__global__ void __launch_bounds__(NW * 64) k_velo_e(EllView E, const float* __restrict__ dinvA,
+                                                    const float* __restrict__ in, const float* __restrict__ zp,
+                                                    float* __restrict__ t, const float* __restrict__ z,
+                                                    float* __restrict__ zo, int J, int MS, float omega) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    constexpr int NT = NW * 64;
+    const int64_t bid = xcd_block(blockIdx.x, gridDim.x);
+    const int tile = (int)(bid / MS);
+    const int j0 = (int)(bid % MS) * kEllM;
+    const int32_t* td = E.tile + 8 * tile;
+    const int s2o = td[0], n2 = td[1], s1o = td[2], n1 = td[3], b0 = td[4], nb = td[5];
+    if (FIRST)   // P1 slots at 0: entry offsets (past the P2 slots) are shifted back
+        ell_stage<NT>(smem_raw, E.s2 + s2o, 0, E.s1 + s1o, n1, 0, zp, zp, J, j0);
+    else
+        ell_stage<NT>(smem_raw, E.s2 + s2o, n2, E.s1 + s1o, 0, 0, z, z, J, j0);
+    __syncthreads();
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    if (wave >= nb) return;
+    const int32_t* bd = E.blk + 8 * (b0 + wave);
+    if (bd[0] != 0) return;
+    const int K1 = bd[2], K2 = bd[3], e1 = bd[4] + lane, e2 = bd[5] + lane, ro = bd[6];
+    const int row = E.rows[ro + lane];
+    const unsigned char* lds = FIRST ? smem_raw - n2 * kEllP2Bytes : smem_raw;
+    float acc[2][kEllM];
+    const int64_t o = 2 * (int64_t)max(row, 0) * J + j0;
+    if constexpr (FIRST) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const float4* r = (const float4*)(in + o + (int64_t)c * J);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float4 w = row >= 0 ? r[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+                acc[c][4 * q] = w.x;
+                acc[c][4 * q + 1] = w.y;
+                acc[c][4 * q + 2] = w.z;
+                acc[c][4 * q + 3] = w.w;
+            }
+        }
+        EllMeta cur, nxt;
+        ell_meta<true>(cur, E, E.bv0, E.bv1, e2, 0, K2);
+        for (int k0 = 0; k0 < K2; k0 += kEllChunk) {
+            if (k0 + kEllChunk < K2) ell_meta<true>(nxt, E, E.bv0, E.bv1, e2, k0 + kEllChunk, K2);
+#pragma unroll
+            for (int i = 0; i < kEllChunk; ++i) {
+                if (k0 + i >= K2) break;
+                const float4* ps = (const float4*)(lds + cur.off[i]);
+                const float a0 = -cur.a[i], a1 = -cur.b[i];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const float4 w = ps[q];
+                    acc[0][4 * q + 0] += a0 * w.x;
+                    acc[0][4 * q + 1] += a0 * w.y;
+                    acc[0][4 * q + 2] += a0 * w.z;
+                    acc[0][4 * q + 3] += a0 * w.w;
+                    acc[1][4 * q + 0] += a1 * w.x;
+                    acc[1][4 * q + 1] += a1 * w.y;
+                    acc[1][4 * q + 2] += a1 * w.z;
+                    acc[1][4 * q + 3] += a1 * w.w;
+                }
+            }
+            cur = nxt;
+        }
+        if (row >= 0) {
+            const float dw = omega * dinvA[row];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                float4* ot = (float4*)(t + o + (int64_t)c * J);
+                float4* oz = (float4*)(zo + o + (int64_t)c * J);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    ot[q] = make_float4(acc[c][4 * q], acc[c][4 * q + 1], acc[c][4 * q + 2], acc[c][4 * q + 3]);
+                    oz[q] = make_float4(acc[c][4 * q] * dw, acc[c][4 * q + 1] * dw, acc[c][4 * q + 2] * dw,
+                                        acc[c][4 * q + 3] * dw);
+                }
+            }
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int m = 0; m < kEllM; ++m) acc[c][m] = 0.f;
+        EllMeta cur, nxt;
+        ell_meta<false>(cur, E, E.av, nullptr, e1, 0, K1);
+        for (int k0 = 0; k0 < K1; k0 += kEllChunk) {
+            if (k0 + kEllChunk < K1) ell_meta<false>(nxt, E, E.av, nullptr, e1, k0 + kEllChunk, K1);
+#pragma unroll
+            for (int i = 0; i < kEllChunk; ++i) {
+                if (k0 + i >= K1) break;
+                const float4* xs = (const float4*)(lds + cur.off[i]);
+                const float a = cur.a[i];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const float4 w = xs[q];
+                    float* r = &acc[q >> 2][(q & 3) * 4];
+                    r[0] += a * w.x;
+                    r[1] += a * w.y;
+                    r[2] += a * w.z;
+                    r[3] += a * w.w;
+                }
+            }
+            cur = nxt;
+        }
+        if (row >= 0) {
+            const float dw = omega * dinvA[row];
+            const float4* zs = (const float4*)(lds + E.self[ro + lane]);
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const float4* tr = (const float4*)(t + o + (int64_t)c * J);
+                float4* oz = (float4*)(zo + o + (int64_t)c * J);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const float4 tv = tr[q], zv = zs[4 * c + q];
+                    float* a = &acc[c][4 * q];
+                    oz[q] = make_float4(zv.x + dw * (tv.x - a[0]), zv.y + dw * (tv.y - a[1]),
+                                        zv.z + dw * (tv.z - a[2]), zv.w + dw * (tv.w - a[3]));
+                }
+            }
+        }
+    }
+}
+
+// A values into the entry order of a row-per-lane tiling: dst[pos[p]] = src[p]
+__global__ void __launch_bounds__(kBlock) k_ell_scatter(const float* __restrict__ src, const int32_t* __restrict__ pos,
+                                                        float* __restrict__ dst, int64_t n) {
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p < n) dst[pos[p]] = src[p];
+}
+
 // ------------------------------------------------------------------ multigrid kernels
 // Packed-row CSR kernel for the pressure multigrid: LPR lanes per row, each
 // lane V = 256 / (LPR sizeof(T)) consecutive members, so one load instruction
@@ -2341,6 +2684,151 @@ mhd_status ensure_tiling(DevMesh& m, int id) {
     return MHD_OK;
 }
 
+// builds and uploads the row-per-lane tiling of shape id on first use (host
+// synchronous: not under capture); B and B^T values are copied in entry order
+mhd_status ensure_ell(DevMesh& m, int id) {
+    if (id < 1 || id > kEllShapes) return MHD_EINVAL;
+    std::lock_guard<std::mutex> lk(g_tiling_mu);
+    if (m.ell[id]) return MHD_OK;
+    HostEll h;
+    build_ell(m.host, ell_tx(id), ell_ty(id), h);
+    const size_t nent = h.loc.size();
+    std::vector<float> bt32(2 * (size_t)m.nnzBt), b32(2 * (size_t)m.nnzB);
+    MHD_HIP(hipMemcpy(bt32.data(), m.valBt32, sizeof(float) * bt32.size(), hipMemcpyDeviceToHost));
+    MHD_HIP(hipMemcpy(b32.data(), m.valB32, sizeof(float) * b32.size(), hipMemcpyDeviceToHost));
+    std::vector<float> bv0(nent, 0.f), bv1(nent, 0.f);
+    std::vector<int32_t> posA((size_t)m.nnzA, -1);
+    for (size_t b = 0; b < h.blk.size() / 8; ++b) {
+        const int32_t* bd = &h.blk[8 * b];
+        const int kind = bd[0], K1 = bd[2], K2 = bd[3], e1 = bd[4], e2 = bd[5];
+        for (int e = e1; e < e1 + 64 * K1; ++e) {
+            const int g = h.gp[e];
+            if (g < 0) continue;
+            if (kind == 0) {
+                posA[g] = e;
+            } else {
+                bv0[e] = b32[2 * (size_t)g];
+                bv1[e] = b32[2 * (size_t)g + 1];
+            }
+        }
+        for (int e = e2; e < e2 + 64 * K2; ++e) {
+            const int g = h.gp[e];
+            if (g < 0) continue;
+            bv0[e] = bt32[2 * (size_t)g];
+            bv1[e] = bt32[2 * (size_t)g + 1];
+        }
+    }
+    for (int32_t q : posA)
+        if (q < 0) {
+            set_error("row-per-lane tiling: an A entry has no slot");
+            return MHD_EINVAL;
+        }
+    auto* d = new (std::nothrow) DevEll;
+    if (!d) return MHD_ENOMEM;
+    d->tx = h.tx;
+    d->ty = h.ty;
+    d->ntiles = h.ntiles;
+    d->max_lds = h.max_lds;
+    d->max_blocks = h.max_blocks;
+    d->max_blocks2 = h.max_blocks2;
+    d->max_lds1 = h.max_lds1;
+    d->max_lds2 = h.max_lds2;
+    d->max_k = h.max_k;
+    d->nent = (int64_t)nent;
+    auto up = [&](auto** p, const auto& v) -> mhd_status {
+        const size_t bytes = std::max<size_t>(v.size() * sizeof(v[0]), 256);
+        hipError_t e = hipMalloc((void**)p, bytes);
+        if (e == hipSuccess) {
+            m.allocs.push_back(*p);
+            if (!v.empty()) e = hipMemcpy(*p, v.data(), v.size() * sizeof(v[0]), hipMemcpyHostToDevice);
+        }
+        if (e != hipSuccess) {
+            set_error(std::string("row-per-lane tiling upload: ") + hipGetErrorString(e));
+            return MHD_ENOMEM;
+        }
+        return MHD_OK;
+    };
+    mhd_status rc = MHD_OK;
+    if (!rc) rc = up(&d->tile, h.tile);
+    if (!rc) rc = up(&d->s2, h.s2);
+    if (!rc) rc = up(&d->s1, h.s1);
+    if (!rc) rc = up(&d->blk, h.blk);
+    if (!rc) rc = up(&d->rows, h.rows);
+    if (!rc) rc = up(&d->self, h.self);
+    if (!rc) rc = up(&d->loc, h.loc);
+    if (!rc) rc = up(&d->bv0, bv0);
+    if (!rc) rc = up(&d->bv1, bv1);
+    if (!rc) rc = up(&d->posA, posA);
+    if (rc) {
+        delete d;
+        return rc;
+    }
+    m.ell[id] = d;
+    return MHD_OK;
+}
+
+// the operator's A values in the entry order of tiling id (allocated and filled
+// on first use; later assemblies refresh it)
+mhd_status ensure_ell_values(DevShared& S, int id, hipStream_t st) {
+    mhd_status rc = ensure_ell(*S.mesh, id);
+    if (rc) return rc;
+    if (S.ellA[id]) return MHD_OK;
+    const DevEll& t = *S.mesh->ell[id];
+    float* p = nullptr;
+    MHD_HIP(hipMalloc((void**)&p, sizeof(float) * (size_t)std::max<int64_t>(t.nent, 64)));
+    S.allocs.push_back(p);
+    MHD_HIP(hipMemsetAsync(p, 0, sizeof(float) * (size_t)std::max<int64_t>(t.nent, 64), st));   // padding stays 0
+    hipLaunchKernelGGL(k_ell_scatter, dim3((unsigned)((S.mesh->nnzA + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
+                       S.valA32, t.posA, p, S.mesh->nnzA);
+    MHD_HIP(hipGetLastError());
+    MHD_HIP(hipStreamSynchronize(st));
+    S.ellA[id] = p;
+    return MHD_OK;
+}
+
+// as ensure_ell_values, and later assemblies keep the values current
+mhd_status use_ell(DevShared& S, int id, hipStream_t st) {
+    mhd_status rc = ensure_ell_values(S, id, st);
+    if (rc) return rc;
+    if (!S.ell_live[id]) {
+        // values may be stale if assemblies ran while the tiling was unused
+        hipLaunchKernelGGL(k_ell_scatter, dim3((unsigned)((S.mesh->nnzA + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
+                           S.valA32, S.mesh->ell[id]->posA, S.ellA[id], S.mesh->nnzA);
+        MHD_HIP(hipGetLastError());
+        S.ell_live[id] = true;
+    }
+    return MHD_OK;
+}
+
+// shape code of the public interface (tx * 100 + ty) <-> shape id
+inline int ell_code(int id) { return ell_tx(id) * 100 + ell_ty(id); }
+inline int ell_id(int code) {
+    for (int id = 1; id <= kEllShapes; ++id)
+        if (ell_code(id) == code) return id;
+    return 0;
+}
+
+bool ell_usable(const DevShared& S, int id, int J) {
+    if (id < 1 || id > kEllShapes || S.transposed || J % kEllM || !S.ellA[id] || !S.mesh->ell[id]) return false;
+    const DevEll& t = *S.mesh->ell[id];
+    return t.max_blocks <= 8 && t.max_blocks2 <= 8 && t.max_lds + 16 <= max_lds_bytes();
+}
+
+}  // namespace
+
+hipError_t scatter_ell_values(DevShared& S, hipStream_t s) {
+    for (int id = 1; id <= kEllShapes; ++id) {
+        if (!S.ellA[id] || !S.ell_live[id] || !S.mesh->ell[id]) continue;
+        hipLaunchKernelGGL(k_ell_scatter, dim3((unsigned)((S.mesh->nnzA + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                           S.valA32, S.mesh->ell[id]->posA, S.ellA[id], S.mesh->nnzA);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+namespace {
+
 // Wave order of the paired-row and batched SpMM with g units per wavefront: the wavefronts
 // of P2 units and of P1 units sorted by the P2 index of their first node, so
 // that the divergence rows of a region run right after its velocity rows and
@@ -2468,6 +2956,27 @@ template <typename T, int MODE>
 mhd_status launch_saddle_plan(NodePlan p, DevShared& S, const T* x, const T* b, T* y, int J, hipStream_t st) {
     DevMesh& m = *S.mesh;
     const int64_t units = (int64_t)m.nP2 + m.nP1;
+    if (p.deep == 6) {
+        if constexpr (sizeof(T) == 4 && MODE == 0) {
+            if (ell_usable(S, p.tile, J)) {
+                const DevEll& t = *m.ell[p.tile];
+                const int MS = J / kEllM;
+                const EllView E{t.tile, t.s2, t.s1, t.blk, t.rows, t.self, t.loc, S.ellA[p.tile], t.bv0, t.bv1};
+                const dim3 grid((unsigned)((int64_t)t.ntiles * MS));
+                const size_t lds = (size_t)t.max_lds + 16;   // + the slot of the staging overrun
+                auto go = [&](auto kern, int threads) -> mhd_status {
+                    MHD_HIP(allow_lds(kern, lds));
+                    launch_k(kern, grid, dim3(threads), lds, st, E, Vals<float>::dp(m), x, y, m.nP2, J, MS);
+                    LAUNCH_CHECK();
+                    return MHD_OK;
+                };
+                if (t.max_blocks <= 2) return go(k_saddle_e<2>, 128);
+                if (t.max_blocks <= 4) return go(k_saddle_e<4>, 256);
+                return go(k_saddle_e<8>, 512);
+            }
+        }
+        p = default_plan(m, J, sizeof(T));
+    }
     if (p.tile > 0 && m.tiling[p.tile] && lds_vec_ok(J, sizeof(T), p.vec) && tile_fits(*m.tiling[p.tile], p.nw)) {
         const DevTiling& tl = *m.tiling[p.tile];
         const int MT = J / (kTileJ * p.vec);
@@ -2562,6 +3071,27 @@ mhd_status launch_saddle_plan(NodePlan p, DevShared& S, const T* x, const T* b, 
 template <typename T, bool FIRST>
 mhd_status launch_velo_plan(NodePlan p, DevShared& S, const T* in, const T* zp, T* t, const T* z, T* zo, int J,
                             hipStream_t st, T omega) {
+    if (p.deep == 6) {
+        if constexpr (sizeof(T) == 4) {
+            if (ell_usable(S, p.tile, J)) {
+                const DevEll& tl = *S.mesh->ell[p.tile];
+                const int MS = J / kEllM;
+                const EllView E{tl.tile, tl.s2, tl.s1, tl.blk, tl.rows, tl.self, tl.loc, S.ellA[p.tile], tl.bv0, tl.bv1};
+                const dim3 grid((unsigned)((int64_t)tl.ntiles * MS));
+                const size_t lds = (size_t)(FIRST ? tl.max_lds1 : tl.max_lds2) + 16;
+                auto go = [&](auto kern, int threads) -> mhd_status {
+                    MHD_HIP(allow_lds(kern, lds));
+                    launch_k(kern, grid, dim3(threads), lds, st, E, Vals<float>::dA(S), in, zp, t, z, zo, J, MS, omega);
+                    LAUNCH_CHECK();
+                    return MHD_OK;
+                };
+                if (tl.max_blocks2 <= 2) return go(k_velo_e<FIRST, 2>, 128);
+                if (tl.max_blocks2 <= 4) return go(k_velo_e<FIRST, 4>, 256);
+                return go(k_velo_e<FIRST, 8>, 512);
+            }
+        }
+        p = default_plan(*S.mesh, J, sizeof(T));
+    }
     DevMesh& m = *S.mesh;
     const int32_t* rp = FIRST ? m.Bt_rowptr : m.A_rowptr;
     const int32_t* col = FIRST ? m.Bt_col : m.A_col;
@@ -2689,6 +3219,12 @@ mhd_status tune_op(DevShared& S, int J, int op, hipStream_t st, std::vector<mhd_
             }
         }
     }
+    if (word == 4 && op != MHD_TUNE_RESIDUAL && J % kEllM == 0 && !S.transposed)
+        for (int id = 1; id <= kEllShapes; ++id) {
+            mhd_status rc = ensure_ell_values(S, id, st);
+            if (rc) return rc;
+            if (ell_usable(S, id, J)) cands.push_back(NodePlan{4, 0, id, 0, 6});
+        }
     PlanRec best;
     if (!cands.empty()) {
         T* x = (T*)S.gw.zbuf;
@@ -2743,7 +3279,8 @@ mhd_status tune_op(DevShared& S, int J, int op, hipStream_t st, std::vector<mhd_
                 const NodePlan& q = cands[c];
                 const bool same = q.tile == best.p.tile && q.vec == best.p.vec && q.deep == best.p.deep &&
                                   (q.tile ? q.nw == best.p.nw : q.g == best.p.g);
-                rep->push_back(mhd_tune_entry{op, word, J, q.vec, q.tile ? 0 : q.g, q.deep, q.tile ? tile_edge(q.tile) : 0,
+                rep->push_back(mhd_tune_entry{op, word, J, q.vec, q.tile ? 0 : q.g, q.deep,
+                                              q.tile ? (q.deep == 6 ? ell_code(q.tile) : tile_edge(q.tile)) : 0,
                                               q.tile ? q.nw : 0, times[c], same ? 1 : 0});
             }
     }
@@ -2770,6 +3307,24 @@ mhd_status set_plan(DevShared& S, int J, int precision, int op, int vec, int gro
     if (op < MHD_TUNE_SADDLE || op > MHD_TUNE_JACOBI) {
         set_error("mhd_ens_set_plan: unknown operator");
         return MHD_EINVAL;
+    }
+    if (deep == 6) {
+        const int id = ell_id(tile);
+        if (word != 4 || op == MHD_TUNE_RESIDUAL || J % kEllM || !id) {
+            set_error("mhd_ens_set_plan: row-per-lane tiles (deep 6) are an FP32 plan (SpMM and Jacobi sweeps) with "
+                      "tile 1616, 3208 or 1608 and J a multiple of 16");
+            return MHD_EINVAL;
+        }
+        mhd_status rc = use_ell(S, id, nullptr);
+        if (rc) return rc;
+        MHD_HIP(hipStreamSynchronize(nullptr));
+        if (!ell_usable(S, id, J)) {
+            set_error("mhd_ens_set_plan: tile needs more LDS or row blocks than a workgroup may use");
+            return MHD_EINVAL;
+        }
+        std::lock_guard<std::mutex> lk(g_plan_mu);
+        g_plans[plan_key(m, J, word, op)] = PlanRec{NodePlan{4, 0, id, 0, 6}, 0.f};
+        return MHD_OK;
     }
     if (deep == 2) {
         if (tile || !(group == 4 || group == 8) || !pair_ok(m, J, word)) {
@@ -2800,7 +3355,7 @@ mhd_status set_plan(DevShared& S, int J, int precision, int op, int vec, int gro
             return MHD_EINVAL;
         }
     } else if (deep != 0) {
-        set_error("mhd_ens_set_plan: deep must be 0, 1, 2 or 3");
+        set_error("mhd_ens_set_plan: deep must be 0, 1, 2, 3 or 6");
         return MHD_EINVAL;
     } else if (!(group == 0 || group == 1 || group == 2 || group == 4) || (group && m.max_row > kMaxRowBatched)) {
         set_error("mhd_ens_set_plan: group must be 0, 1, 2 or 4 (batched gathers need rows of <= 56 entries)");
@@ -2850,7 +3405,11 @@ mhd_status autotune(DevShared& S, int J, int precision, hipStream_t st, bool for
     // plans are shared by meshes of equal size: make sure this mesh holds the tilings they use
     for (int op : {MHD_TUNE_SADDLE, MHD_TUNE_JACOBI_FIRST, MHD_TUNE_JACOBI, MHD_TUNE_RESIDUAL}) {
         const NodePlan p = get_plan(m, J, op == MHD_TUNE_RESIDUAL ? 8 : word, op);
-        if (p.tile && (rc = ensure_tiling(*S.mesh, p.tile))) return rc;
+        if (p.deep == 6) {
+            if ((rc = use_ell(S, p.tile, st))) return rc;
+        } else if (p.tile && (rc = ensure_tiling(*S.mesh, p.tile))) {
+            return rc;
+        }
         if ((p.deep == 2 || (p.deep == 0 && p.tile == 0)) && (rc = ensure_pair_sched(*S.mesh, p.g))) return rc;
     }
     return MHD_OK;
@@ -2946,7 +3505,7 @@ struct Ops {
     }
 
     // z = P^{-1} v (block upper-triangular preconditioner)
-    mhd_status precond(const T* v, T* z, int sweeps) {
+    mhd_status precond(const T* v, T* z, int sweeps, double omega_d) {
         DevMesh& m = *S.mesh;
         const int64_t off = 2 * (int64_t)m.nP2 * J;
         const T* vp = v + off;
@@ -2957,7 +3516,7 @@ struct Ops {
         hipLaunchKernelGGL((k_schur<T>), dim3(grid_for(m.nP1, JP)), dim3(kBlock), 0, st, xmg, vp, m.pin, zp, m.nP1,
                            J, JP);
         LAUNCH_CHECK();
-        const T omega = (T)0.7;
+        const T omega = (T)omega_d;
         T* t = (T*)S.gw.tbuf;
         // ping-pong between z and z2buf, starting so that the last sweep writes z
         T* za = (sweeps % 2) ? z : (T*)S.gw.z2buf;
@@ -3025,6 +3584,7 @@ mhd_status gmres_solve(DevShared& S, const double* b, double* x, int J, const mh
     const int mres = std::max(1, std::min(o.restart > 0 ? o.restart : G.restart, G.restart));
     const int check = std::max(1, o.check_every);
     const int sweeps = std::max(1, o.jacobi_sweeps);
+    const double omega = o.jacobi_omega > 0 ? o.jacobi_omega : kJacobiOmega;
     Ops<T> ops(S, J, st);
     RedShape rs = cap_blocks(red_shape(n, J, 16 / (int)sizeof(T)), G.nblk_cap);
     const int passes = o.cgs_passes > 0 ? o.cgs_passes : (sizeof(T) == 4 ? 1 : 2);
@@ -3081,7 +3641,7 @@ mhd_status gmres_solve(DevShared& S, const double* b, double* x, int J, const mh
             T* vk = basis_ptr<T>(S, k);
             T* z = (T*)G.zbuf;
             T* w = basis_ptr<T>(S, k + 1);
-            if ((rc = ops.precond(vk, z, sweeps))) return rc;
+            if ((rc = ops.precond(vk, z, sweeps, omega))) return rc;
             if ((rc = ops.saddle(z, w))) return rc;
             // classical Gram-Schmidt (optionally with a re-orthogonalisation pass)
             for (int pass = 0; pass < passes; ++pass) {
@@ -3144,7 +3704,7 @@ mhd_status gmres_solve(DevShared& S, const double* b, double* x, int J, const mh
             return MHD_OK;
         });
         if (rc) return rc;
-        if ((rc = ops.precond(u, (T*)G.zbuf, sweeps))) return rc;
+        if ((rc = ops.precond(u, (T*)G.zbuf, sweeps, omega))) return rc;
         hipLaunchKernelGGL((k_add_to64<T>), dim3(ew_grid(n * J)), dim3(kBlock), 0, st, x, (const T*)G.zbuf, n * J);
         LAUNCH_CHECK();
         ++cycles;

@@ -1,10 +1,11 @@
 // Row tiles of the saddle-point operator for the LDS-staged SpMM and Jacobi
-// kernels (host side).  Rows are grouped by the rectangle of tx x ty
+// kernels (host side): CSR-order tiles and row-per-lane (sliced ELL) tiles.  Rows are grouped by the rectangle of tx x ty
 // half-steps their node lies in; each tile lists the node values its rows read
 // (the union of their column indices), and every CSR entry gets the position
 // of its column in its row's tile list.
 #include <algorithm>
 #include <cmath>
+#include <tuple>
 
 #include "common.h"
 
@@ -122,6 +123,116 @@ void build_tiling(const HostMesh& m, int tx, int ty, HostTiling& t) {
         t.max_s1 = std::max(t.max_s1, (int)st1.size());
         t.max_r2 = std::max(t.max_r2, (int)R2.size());
         t.max_r1 = std::max(t.max_r1, (int)R1.size());
+        ++t.ntiles;
+    }
+}
+
+void build_ell(const HostMesh& m, int tx, int ty, HostEll& t) {
+    t = HostEll{};
+    t.tx = tx;
+    t.ty = ty;
+    const int nP2 = m.nP2, nP1 = m.nP1;
+    int hxmax = 0;
+    std::vector<int> hx(nP2), hy(nP2);
+    for (int i = 0; i < nP2; ++i) {
+        hx[i] = (int)std::lround(2.0 * (m.xy[2 * (size_t)i] - m.x0) / m.h);
+        hy[i] = (int)std::lround(2.0 * (m.xy[2 * (size_t)i + 1] - m.y0) / m.h);
+        hxmax = std::max(hxmax, hx[i]);
+    }
+    const int gx = hxmax / tx + 1;
+    int nrect = 0;
+    std::vector<int> rect(nP2);
+    for (int i = 0; i < nP2; ++i) {
+        rect[i] = (hy[i] / ty) * gx + hx[i] / tx;
+        nrect = std::max(nrect, rect[i] + 1);
+    }
+    std::vector<int32_t> p2_of_p1(nP1, -1);
+    for (int i = 0; i < nP2; ++i)
+        if (m.p1_of_p2[i] >= 0) p2_of_p1[m.p1_of_p2[i]] = i;
+    std::vector<std::vector<int32_t>> rows2(nrect), rows1(nrect);
+    for (int i = 0; i < nP2; ++i) rows2[rect[i]].push_back(i);
+    for (int k = 0; k < nP1; ++k) rows1[rect[p2_of_p1[k]]].push_back(k);
+    auto len = [](const HostCSR& c, int r) { return c.rowptr[r + 1] - c.rowptr[r]; };
+    std::vector<int32_t> off2(nP2, -1), off1(nP1, -1);
+    std::vector<int32_t> st2, st1;
+    for (int r = 0; r < nrect; ++r) {
+        std::vector<int32_t> R2 = rows2[r], R1 = rows1[r];
+        if (R2.empty() && R1.empty()) continue;
+        st2.clear();
+        st1.clear();
+        for (int32_t u : R2) {
+            for (int32_t p = m.A.rowptr[u]; p < m.A.rowptr[u + 1]; ++p) st2.push_back(m.A.col[p]);
+            for (int32_t p = m.Bt.rowptr[u]; p < m.Bt.rowptr[u + 1]; ++p) st1.push_back(m.Bt.col[p]);
+        }
+        for (int32_t k : R1) {
+            for (int32_t q = m.B.rowptr[k]; q < m.B.rowptr[k + 1]; ++q) st2.push_back(m.B.col[q]);
+            st1.push_back(k);
+        }
+        // staged P2 nodes by (line, parity of the position along the line, position): the
+        // same-kind nodes a lane's neighbours read lie 2 half-steps apart and so get
+        // consecutive slots, whose padded LDS rows start in different banks
+        auto key = [&](int32_t u) { return std::make_tuple(hy[u], hx[u] & 1, hx[u]); };
+        std::sort(st2.begin(), st2.end());
+        st2.erase(std::unique(st2.begin(), st2.end()), st2.end());
+        std::sort(st2.begin(), st2.end(), [&](int32_t a, int32_t b) { return key(a) < key(b); });
+        std::sort(st1.begin(), st1.end());
+        st1.erase(std::unique(st1.begin(), st1.end()), st1.end());
+        const int p1base = (int)st2.size() * kEllP2Bytes;
+        for (size_t s = 0; s < st2.size(); ++s) off2[st2[s]] = (int32_t)s * kEllP2Bytes;
+        for (size_t s = 0; s < st1.size(); ++s) off1[st1[s]] = p1base + (int32_t)s * kEllP1Bytes;
+        t.max_lds = std::max(t.max_lds, p1base + (int)st1.size() * kEllP1Bytes);
+        t.max_lds1 = std::max(t.max_lds1, (int)st1.size() * kEllP1Bytes);
+        t.max_lds2 = std::max(t.max_lds2, p1base);
+        t.max_blocks2 = std::max(t.max_blocks2, (int)((R2.size() + 63) / 64));
+        // longest rows first, so that the rows of a block have similar lengths
+        std::stable_sort(R2.begin(), R2.end(), [&](int32_t a, int32_t b) {
+            const int la = len(m.A, a), lb = len(m.A, b);
+            if (la != lb) return la > lb;
+            const int ba = len(m.Bt, a), bb = len(m.Bt, b);
+            return ba != bb ? ba > bb : key(a) < key(b);
+        });
+        std::stable_sort(R1.begin(), R1.end(), [&](int32_t a, int32_t b) { return len(m.B, a) > len(m.B, b); });
+        const int first = (int)(t.blk.size() / 8);
+        auto add_blocks = [&](const std::vector<int32_t>& R, int kind) {
+            for (size_t b0 = 0; b0 < R.size(); b0 += 64) {
+                const int nr = (int)std::min<size_t>(64, R.size() - b0);
+                const HostCSR& c1 = kind == 0 ? m.A : m.B;
+                int K1 = 0, K2 = 0;
+                for (int l = 0; l < nr; ++l) {
+                    K1 = std::max(K1, len(c1, R[b0 + l]));
+                    if (kind == 0) K2 = std::max(K2, len(m.Bt, R[b0 + l]));
+                }
+                t.max_k = std::max(t.max_k, std::max(K1, K2));
+                const int e1 = (int)t.loc.size(), e2 = e1 + 64 * K1, ro = (int)t.rows.size();
+                t.blk.insert(t.blk.end(), {kind, nr, K1, K2, e1, e2, ro, 0});
+                t.loc.resize((size_t)e2, 0);                      // padding reads the first P2 slot
+                t.loc.resize((size_t)e2 + 64 * K2, p1base);       // ... or the first P1 slot
+                t.gp.resize((size_t)e2 + 64 * K2, -1);
+                for (int l = 0; l < 64; ++l) {
+                    const int32_t row = l < nr ? R[b0 + l] : -1;
+                    t.rows.push_back(row);
+                    t.self.push_back(row < 0 ? 0 : kind == 1 ? off1[row] : off2[row]);
+                    if (row < 0) continue;
+                    for (int32_t p = c1.rowptr[row], k = 0; p < c1.rowptr[row + 1]; ++p, ++k) {
+                        t.loc[(size_t)e1 + 64 * k + l] = off2[c1.col[p]];
+                        t.gp[(size_t)e1 + 64 * k + l] = p;
+                    }
+                    if (kind == 0)
+                        for (int32_t p = m.Bt.rowptr[row], k = 0; p < m.Bt.rowptr[row + 1]; ++p, ++k) {
+                            t.loc[(size_t)e2 + 64 * k + l] = off1[m.Bt.col[p]];
+                            t.gp[(size_t)e2 + 64 * k + l] = p;
+                        }
+                }
+            }
+        };
+        add_blocks(R2, 0);
+        add_blocks(R1, 1);
+        const int nblk = (int)(t.blk.size() / 8) - first;
+        t.max_blocks = std::max(t.max_blocks, nblk);
+        t.tile.insert(t.tile.end(), {(int32_t)t.s2.size(), (int32_t)st2.size(), (int32_t)t.s1.size(),
+                                     (int32_t)st1.size(), first, nblk, 0, 0});
+        t.s2.insert(t.s2.end(), st2.begin(), st2.end());
+        t.s1.insert(t.s1.end(), st1.begin(), st1.end());
         ++t.ntiles;
     }
 }

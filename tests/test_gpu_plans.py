@@ -53,6 +53,13 @@ def candidates(J, word):
     return out
 
 
+def ell_candidates(J, word):
+    """Row-per-lane tiles (FP32 SpMM only): tile code tx * 100 + ty."""
+    if word != 4 or J % 16:
+        return []
+    return [(4, 0, 6, code, 0) for code in (1616, 3208, 1608)]
+
+
 def set_plan(L, A, J, precision, op, plan):
     """False if the device cannot hold this LDS tile."""
     try:
@@ -87,7 +94,7 @@ def test_every_spmm_plan(L, precision, J):
     ref = S @ x.double().cpu().numpy()
     tol = 2e-6 if word == 4 else 1e-14
     planned = {}
-    for plan in candidates(J, word):
+    for plan in candidates(J, word) + ell_candidates(J, word):
         if not set_plan(L, A, J, precision, L.TUNE_SADDLE, plan):
             say("  plan", plan, "does not fit in LDS")
             continue
@@ -118,14 +125,19 @@ def test_every_solver_plan_same_solution(L, precision):
     rng = np.random.default_rng(3)
     b = torch.from_numpy(rng.standard_normal((gm.n, J))).cuda()
     results = {}
-    for plan in candidates(J, word):
+    for plan in candidates(J, word) + ell_candidates(J, word):
         if plan[0] == 0:
             continue
-        ok = all([set_plan(L, A, J, precision, op, plan)
-                  for op in (L.TUNE_SADDLE, L.TUNE_JACOBI_FIRST, L.TUNE_JACOBI)])
-        # FP64 residual: LDS tiles take vec 1, paired rows need J a multiple of 32
-        resid = (1,) + plan[1:] if plan[3] else (min(plan[0], 2),) + plan[1:]
-        ok = set_plan(L, A, J, precision, L.TUNE_RESIDUAL, resid) and ok
+        if plan[2] == 6:   # FP32 plans: the FP64 residual keeps a gather plan
+            ok = all([set_plan(L, A, J, precision, op, plan)
+                      for op in (L.TUNE_SADDLE, L.TUNE_JACOBI_FIRST, L.TUNE_JACOBI)])
+            ok = set_plan(L, A, J, precision, L.TUNE_RESIDUAL, (1, 1, 0, 0, 4)) and ok
+        else:
+            ok = all([set_plan(L, A, J, precision, op, plan)
+                      for op in (L.TUNE_SADDLE, L.TUNE_JACOBI_FIRST, L.TUNE_JACOBI)])
+            # FP64 residual: LDS tiles take vec 1, paired rows need J a multiple of 32
+            resid = (1,) + plan[1:] if plan[3] else (min(plan[0], 2),) + plan[1:]
+            ok = set_plan(L, A, J, precision, L.TUNE_RESIDUAL, resid) and ok
         if not ok:
             say("  plan", plan, "does not fit in LDS")
             continue
@@ -158,5 +170,30 @@ def test_autotune_report(L):
         say(key, [(e["vec"], e["group"], e["deep"], e["tile"], e["waves"], round(e["us"], 2)) for e in es])
     # a J with no vector shape tunes nothing and solves with the generic kernels
     assert L.mhd_ens_autotune(A, 5, 1) == []
+    L.mhd_ens_shared_free(A)
+    gm.close()
+
+
+def test_row_tile_values_follow_assembly(L):
+    """The row-per-lane SpMM keeps its own copy of the A values in tile order:
+    a new assembly of the same handle must reach it."""
+    from paper_2108_05110_amd.ensemble import to_dev
+    J = 32
+    pb, gm, A, V, W = shared(L, J, seed=4)
+    assert set_plan(L, A, J, 1, L.TUNE_SADDLE, (4, 0, 6, 1608, 0))
+    x = torch.from_numpy(np.random.default_rng(5).standard_normal((gm.n, J))).to("cuda", torch.float32)
+    for step in range(2):
+        if step:
+            W2 = W + 0.3 * np.random.default_rng(6).standard_normal(W.shape)
+            c = L.Coeffs(pb.dt, pb.mu, float(pb.nu.mean()), float(pb.nu_m.mean()), 0)
+            L.mhd_ens_assemble_shared(gm.handle, c, to_dev(W2), J, A)
+        S = csr_from_view(torch, L.mhd_ens_shared_csr(A))
+        y = torch.full((gm.n, J), float("nan"), dtype=torch.float32, device="cuda")
+        L.mhd_ens_spmm(A, x, y, J, 1)
+        torch.cuda.synchronize()
+        ref = S @ x.double().cpu().numpy()
+        err = np.abs(y.double().cpu().numpy() - ref).max() / np.abs(ref).max()
+        say("  assembly", step, "err", err)
+        assert err <= 2e-6
     L.mhd_ens_shared_free(A)
     gm.close()
