@@ -232,8 +232,10 @@ def tuned_plans(L, wl, mesh, J, prec):
 def saddle_kernel_name(plan):
     if plan is None:
         return "k_saddle"
+    if plan["deep"] == 6:
+        return "k_saddle_e"
     if plan["tile"]:
-        return "k_saddle_lds"
+        return "k_saddle_t" if plan["deep"] == 3 else "k_saddle_lds"
     if plan["deep"]:
         return KERNEL_NAMES[plan["deep"]]
     return "k_saddle_g" if plan["group"] else "k_saddle_v"

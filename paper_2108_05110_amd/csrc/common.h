@@ -98,17 +98,16 @@ void build_tiling(const HostMesh& m, int tx, int ty, HostTiling& t);
 
 // Row-per-lane tiles of the saddle-point operator (sliced ELL over LDS-staged
 // node values).  Rectangles of tx x ty half-steps as above; a workgroup stages
-// the values of kEllM members of every node its rows read, then each lane
+// the values of M members of every node its rows read, then each lane
 // computes one row.  A tile's P2 rows (sorted by entry counts, longest first)
 // and its P1 rows are cut into blocks of 64, one wavefront each; a block's
 // entries are stored column-major (entry k of all 64 lanes together), padded
 // to the longest row of the block with (the first slot of the kind the entries
 // read, CSR position -1).
-constexpr int kEllM = 16;          // members per workgroup
-constexpr int kEllP2Bytes = 144;   // LDS bytes per staged P2 node: 2 x kEllM floats + 16 bytes padding
-constexpr int kEllP1Bytes = 80;    // LDS bytes per staged P1 node: kEllM floats + 16 bytes padding
+constexpr int ell_p2_bytes(int M) { return 8 * M + 16; }   // LDS bytes per staged P2 node: 2 x M floats + 16 padding
+constexpr int ell_p1_bytes(int M) { return 4 * M + 16; }   // LDS bytes per staged P1 node: M floats + 16 padding
 struct HostEll {
-    int tx = 0, ty = 0, ntiles = 0;
+    int tx = 0, ty = 0, m = 0, ntiles = 0;
     int max_lds = 0;                 // largest staged bytes of a tile
     int max_lds1 = 0;                // largest staged bytes of a tile's P1 nodes alone
     int max_lds2 = 0;                // largest staged bytes of a tile's P2 nodes alone
@@ -124,7 +123,7 @@ struct HostEll {
     std::vector<int32_t> gp;         // per entry: position in the CSR value arrays, -1 for padding
 };
 // P2 blocks: entries 1 are A (K1 per lane), entries 2 are B^T (K2); P1 blocks: entries 1 are B.
-void build_ell(const HostMesh& m, int tx, int ty, HostEll& t);
+void build_ell(const HostMesh& m, int tx, int ty, int M, HostEll& t);
 
 mhd_status build_mesh(const mhd_mesh_desc* d, HostMesh& m, bool full);
 mhd_status schur_values(HostMesh& m, double dt, double nu_c);

@@ -55,25 +55,28 @@ struct DevTiling {
 constexpr int kTileShapes = 3;          // square tiles of 8, 12 or 16 half-steps
 inline int tile_edge(int id) { return id == 1 ? 8 : id == 2 ? 12 : 16; }
 
-// Row-per-lane tiles on the device (layout as HostEll).  Entry values: the B^T
-// and B values are mesh constants (bv0, bv1: first and second value of the
-// entry, 0 for A entries and padding); the A values live with each shared
-// operator (DevShared::ellA) and are scattered there by the assembly through
-// posA (CSR position of an A entry -> its entry index).
+// Row-per-lane tiles on the device (layout as HostEll).  Entries are packed
+// with their LDS offset: B^T and B entries (mesh constants) as (offset, first
+// value, second value, 0) in bm; A entries as (offset, value) in an array of
+// each shared operator (DevShared::ellA), copied from am0 (values 0) and given
+// its values by the assembly through posA (CSR position of an A entry -> its
+// entry index).
 struct DevEll {
-    int tx = 0, ty = 0, ntiles = 0, max_lds = 0, max_lds1 = 0, max_lds2 = 0, max_blocks = 0, max_blocks2 = 0;
+    int tx = 0, ty = 0, m = 0, ntiles = 0, max_lds = 0, max_lds1 = 0, max_lds2 = 0, max_blocks = 0, max_blocks2 = 0;
     int max_k = 0;
     int64_t nent = 0;
     int32_t *tile = nullptr, *s2 = nullptr, *s1 = nullptr, *blk = nullptr, *rows = nullptr, *self = nullptr;
-    int32_t* loc = nullptr;
-    float *bv0 = nullptr, *bv1 = nullptr;
+    int4* bm = nullptr;
+    int2* am0 = nullptr;
     int32_t* posA = nullptr;
 };
+// shapes 1-3: rectangles of 16 x 16, 32 x 8 and 16 x 8 half-steps with 16
+// members per workgroup; 4-6: the same with 8 members
+constexpr int kEllShapes = 6;
+inline int ell_tx(int id) { return (id - 1) % 3 == 1 ? 32 : 16; }
+inline int ell_ty(int id) { return (id - 1) % 3 == 0 ? 16 : 8; }
+inline int ell_m(int id) { return id > 3 ? 8 : 16; }
 constexpr double kJacobiOmega = 0.85;  // velocity-block Jacobi damping when the options leave it 0
-constexpr int kEllShapes = 3;           // rectangles of 16 x 16, 32 x 8 and 16 x 8 half-steps
-inline int ell_tx(int id) { return id == 2 ? 32 : 16; }
-inline int ell_ty(int id) { return id == 1 ? 16 : 8; }
-
 struct DevMesh {
     HostMesh host;
     int nP2 = 0, nP1 = 0, n_el = 0, n_dir = 0, pin = -1;
@@ -161,7 +164,7 @@ struct DevShared {
     double* elem = nullptr;       // n_el x 36
     mhd_coeffs coeffs{};
     bool assembled = false;
-    float* ellA[kEllShapes + 1] = {};   // A values in the entry order of the row-per-lane tiles (FP32)
+    int2* ellA[kEllShapes + 1] = {};    // packed A entries of the row-per-lane tiles (FP32 values)
     bool ell_live[kEllShapes + 1] = {};  // a plan uses the tiling: assemblies refresh ellA
     GmresWork gw;
     std::vector<void*> allocs;

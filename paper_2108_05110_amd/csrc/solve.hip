@@ -972,17 +972,18 @@ __global__ void __launch_bounds__(kBlock) k_velo_h(const int32_t* __restrict__ r
 }
 
 // ------------------------------------------------------------------ row-per-lane tiles (sliced ELL)
-// One workgroup per (tile, slice of kEllM members).  The workgroup first copies
-// the slice of every node value its rows read into LDS (all loads of a thread
-// in flight before its LDS stores), then each wavefront takes one block of 64
-// rows, one row per lane: per entry the lane reads the entry's LDS offset and
-// value (coalesced, the block's entries are stored column-major, prefetched a
+// One workgroup per (tile, slice of M members).  The workgroup first copies the
+// slice of every node value its rows read into LDS (all loads of a thread in
+// flight before its LDS stores), then each wavefront takes one block of 64 rows,
+// one row per lane: per entry the lane loads the entry's packed LDS offset and
+// value(s) (coalesced: a block's entries are stored column-major; prefetched a
 // chunk ahead) and the staged node with 16-byte LDS reads, and accumulates all
-// kEllM members of both components.  Entries are consumed in CSR order with the
-// same operations as the other SpMM kernels, so the results agree bitwise.
+// M members of both components.  Entries are consumed in CSR order with the
+// same operations as the other SpMM and Jacobi kernels, so results agree bitwise.
 struct EllView {
-    const int32_t *tile, *s2, *s1, *blk, *rows, *self, *loc;
-    const float *av, *bv0, *bv1;
+    const int32_t *tile, *s2, *s1, *blk, *rows, *self;
+    const int2* am;   // A entries: (LDS offset, value bits)
+    const int4* bm;   // B^T / B entries: (LDS offset, first value bits, second value bits, 0)
 };
 
 constexpr int kEllChunk = 4;   // entries per prefetch chunk
@@ -992,9 +993,9 @@ struct EllMeta {
     float a[kEllChunk], b[kEllChunk];
 };
 
+// entries k0 ... k0 + kEllChunk - 1 (< K) of a lane whose entry k sits at e + 64 k
 template <bool PAIR>
-__device__ __forceinline__ void ell_meta(EllMeta& M, const EllView& E, const float* __restrict__ v0,
-                                         const float* __restrict__ v1, int e, int k0, int K) {
+__device__ __forceinline__ void ell_meta(EllMeta& M, const EllView& E, int e, int k0, int K) {
 #pragma unroll
     for (int i = 0; i < kEllChunk; ++i) {
         const int k = k0 + i;
@@ -1002,26 +1003,36 @@ __device__ __forceinline__ void ell_meta(EllMeta& M, const EllView& E, const flo
         M.a[i] = 0.f;
         M.b[i] = 0.f;
         if (k < K) {
-            M.off[i] = E.loc[e + 64 * k];
-            M.a[i] = v0[e + 64 * k];
-            if (PAIR) M.b[i] = v1[e + 64 * k];
+            if (PAIR) {
+                const int4 q = E.bm[e + 64 * k];
+                M.off[i] = q.x;
+                M.a[i] = __int_as_float(q.y);
+                M.b[i] = __int_as_float(q.z);
+            } else {
+                const int2 q = E.am[e + 64 * k];
+                M.off[i] = q.x;
+                M.a[i] = __int_as_float(q.y);
+            }
         }
     }
 }
 
-// Copies the kEllM-member slice (members j0 ...) of n2 velocity nodes (rows 2 node
-// and 2 node + 1 of v2) to LDS slots of kEllP2Bytes from offset 0, and of n1
-// pressure nodes (row node of v1) to slots of kEllP1Bytes from offset dst1.  A
-// P2 node is 8 chunks of 16 bytes (component q / 4, members 4 (q % 4) ...), a P1
-// node 4.  Branch-free so that all loads of a thread are in flight together:
-// chunks past the end reload the first listed node and go to a 16-byte slot past
-// the staged values.
-template <int NT>
+// Copies the M-member slice (members j0 ...) of n2 velocity nodes (rows 2 node
+// and 2 node + 1 of v2) to LDS slots of ell_p2_bytes(M) from offset 0, and of
+// n1 pressure nodes (row node of v1) to slots of ell_p1_bytes(M) from offset
+// dst1.  A P2 node is 2 M / 4 chunks of 16 bytes (component, 4 members), a P1
+// node M / 4.  Branch-free so that all loads of a thread are in flight
+// together: chunks past the end reload the first listed node and go to a
+// 16-byte slot past the staged values.
+template <int M, int NT>
 __device__ __forceinline__ void ell_stage(unsigned char* lds, const int32_t* __restrict__ s2, int n2,
                                           const int32_t* __restrict__ s1, int n1, int dst1,
                                           const float* __restrict__ v2, const float* __restrict__ v1, int J, int j0) {
-    const int c2 = n2 * 8, tot = c2 + n1 * 4;
-    const int spill = max(n2 * kEllP2Bytes, dst1 + n1 * kEllP1Bytes);
+    constexpr int Q = M / 4;                 // chunks per component
+    constexpr int LQ = Q == 4 ? 2 : 1;       // log2 Q
+    constexpr int S2 = ell_p2_bytes(M), S1 = ell_p1_bytes(M);
+    const int c2 = n2 * 2 * Q, tot = c2 + n1 * Q;
+    const int spill = max(n2 * S2, dst1 + n1 * S1);
     for (int base = threadIdx.x; base < tot; base += 8 * NT) {
         int row[8], dst[8];
         bool one[8];
@@ -1030,12 +1041,12 @@ __device__ __forceinline__ void ell_stage(unsigned char* lds, const int32_t* __r
             const int i = base + k * NT;
             const bool is2 = i < c2, is1 = !is2 && i < tot;
             const int j = is2 ? i : (is1 ? i - c2 : 0);   // chunk within its kind
-            const int sl = is1 ? (j >> 2) : (j >> 3);
+            const int sl = is1 ? (j >> LQ) : (j >> (LQ + 1));
             const int node = is1 ? s1[sl] : (n2 ? s2[sl] : s1[0]);
             one[k] = is1 || !n2;
-            row[k] = one[k] ? node : 2 * node + ((j >> 2) & 1);
-            dst[k] = is2 ? sl * kEllP2Bytes + ((j >> 2) & 1) * (kEllM * 4) + (j & 3) * 16
-                         : (is1 ? dst1 + sl * kEllP1Bytes + (j & 3) * 16 : spill);
+            row[k] = one[k] ? node : 2 * node + ((j >> LQ) & 1);
+            dst[k] = is2 ? sl * S2 + ((j >> LQ) & 1) * (M * 4) + (j & (Q - 1)) * 16
+                         : (is1 ? dst1 + sl * S1 + (j & (Q - 1)) * 16 : spill);
         }
         float4 v[8];
 #pragma unroll
@@ -1043,15 +1054,72 @@ __device__ __forceinline__ void ell_stage(unsigned char* lds, const int32_t* __r
             const int i = base + k * NT;
             const int j = i < c2 ? i : (i < tot ? i - c2 : 0);
             const float* src = one[k] ? v1 : v2;
-            v[k] = *(const float4*)(src + (int64_t)row[k] * J + j0 + (j & 3) * 4);
+            v[k] = *(const float4*)(src + (int64_t)row[k] * J + j0 + (j & (Q - 1)) * 4);
         }
 #pragma unroll
         for (int k = 0; k < 8; ++k) *(float4*)(lds + dst[k]) = v[k];
     }
 }
 
-// y = S x, FP32, J a multiple of kEllM; NW wavefronts per workgroup (>= blocks of any tile)
-template <int NW>
+// acc[c][m] += a * x[c][m] over entries of a lane (A entries: velocity node, both components)
+template <int M>
+__device__ __forceinline__ void ell_rows_a(float (&acc)[2][M], const EllView& E, const unsigned char* lds, int e,
+                                           int K) {
+    EllMeta cur, nxt;
+    ell_meta<false>(cur, E, e, 0, K);
+    for (int k0 = 0; k0 < K; k0 += kEllChunk) {
+        if (k0 + kEllChunk < K) ell_meta<false>(nxt, E, e, k0 + kEllChunk, K);
+#pragma unroll
+        for (int i = 0; i < kEllChunk; ++i) {
+            if (k0 + i >= K) break;
+            const float4* xs = (const float4*)(lds + cur.off[i]);
+            const float a = cur.a[i];
+#pragma unroll
+            for (int q = 0; q < M / 2; ++q) {
+                const float4 w = xs[q];
+                float* r = &acc[q / (M / 4)][(q % (M / 4)) * 4];
+                r[0] += a * w.x;
+                r[1] += a * w.y;
+                r[2] += a * w.z;
+                r[3] += a * w.w;
+            }
+        }
+        cur = nxt;
+    }
+}
+
+// acc[0][m] += s a0 p[m], acc[1][m] += s a1 p[m] over B^T entries (pressure node), s = -1 if NEG
+template <int M, bool NEG>
+__device__ __forceinline__ void ell_rows_bt(float (&acc)[2][M], const EllView& E, const unsigned char* lds, int e,
+                                            int K) {
+    EllMeta cur, nxt;
+    ell_meta<true>(cur, E, e, 0, K);
+    for (int k0 = 0; k0 < K; k0 += kEllChunk) {
+        if (k0 + kEllChunk < K) ell_meta<true>(nxt, E, e, k0 + kEllChunk, K);
+#pragma unroll
+        for (int i = 0; i < kEllChunk; ++i) {
+            if (k0 + i >= K) break;
+            const float4* ps = (const float4*)(lds + cur.off[i]);
+            const float a0 = NEG ? -cur.a[i] : cur.a[i], a1 = NEG ? -cur.b[i] : cur.b[i];
+#pragma unroll
+            for (int q = 0; q < M / 4; ++q) {
+                const float4 w = ps[q];
+                acc[0][4 * q + 0] += a0 * w.x;
+                acc[0][4 * q + 1] += a0 * w.y;
+                acc[0][4 * q + 2] += a0 * w.z;
+                acc[0][4 * q + 3] += a0 * w.w;
+                acc[1][4 * q + 0] += a1 * w.x;
+                acc[1][4 * q + 1] += a1 * w.y;
+                acc[1][4 * q + 2] += a1 * w.z;
+                acc[1][4 * q + 3] += a1 * w.w;
+            }
+        }
+        cur = nxt;
+    }
+}
+
+// y = S x, FP32, J a multiple of M; NW wavefronts per workgroup (>= blocks of any tile)
+template <int M, int NW>
 __global__ void __launch_bounds__(NW * 64) k_saddle_e(EllView E, const float* __restrict__ dp,
                                                       const float* __restrict__ x, float* __restrict__ y, int nP2,
                                                       int J, int MS) {
@@ -1059,10 +1127,11 @@ __global__ void __launch_bounds__(NW * 64) k_saddle_e(EllView E, const float* __
     constexpr int NT = NW * 64;
     const int64_t bid = xcd_block(blockIdx.x, gridDim.x);
     const int tile = (int)(bid / MS);
-    const int j0 = (int)(bid % MS) * kEllM;
+    const int j0 = (int)(bid % MS) * M;
     const int32_t* td = E.tile + 8 * tile;
     const int s2o = td[0], n2 = td[1], s1o = td[2], n1 = td[3], b0 = td[4], nb = td[5];
-    ell_stage<NT>(smem_raw, E.s2 + s2o, n2, E.s1 + s1o, n1, n2 * kEllP2Bytes, x, x + 2 * (int64_t)nP2 * J, J, j0);
+    ell_stage<M, NT>(smem_raw, E.s2 + s2o, n2, E.s1 + s1o, n1, n2 * ell_p2_bytes(M), x,
+                     x + 2 * (int64_t)nP2 * J, J, j0);
     __syncthreads();
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
@@ -1070,92 +1139,45 @@ __global__ void __launch_bounds__(NW * 64) k_saddle_e(EllView E, const float* __
     const int32_t* bd = E.blk + 8 * (b0 + wave);
     const int kind = bd[0], K1 = bd[2], K2 = bd[3], e1 = bd[4] + lane, e2 = bd[5] + lane, ro = bd[6];
     const int row = E.rows[ro + lane];
+    float acc[2][M];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int m = 0; m < M; ++m) acc[c][m] = 0.f;
     if (kind == 0) {
-        float acc[2][kEllM];
-#pragma unroll
-        for (int c = 0; c < 2; ++c)
-#pragma unroll
-            for (int m = 0; m < kEllM; ++m) acc[c][m] = 0.f;
-        EllMeta cur, nxt;
-        ell_meta<false>(cur, E, E.av, nullptr, e1, 0, K1);
-        for (int k0 = 0; k0 < K1; k0 += kEllChunk) {
-            if (k0 + kEllChunk < K1)
-                ell_meta<false>(nxt, E, E.av, nullptr, e1, k0 + kEllChunk, K1);
-            else
-                ell_meta<true>(nxt, E, E.bv0, E.bv1, e2, 0, K2);   // the B^T part's first chunk
-#pragma unroll
-            for (int i = 0; i < kEllChunk; ++i) {
-                if (k0 + i >= K1) break;
-                const float4* xs = (const float4*)(smem_raw + cur.off[i]);
-                const float a = cur.a[i];
-#pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    const float4 w = xs[q];
-                    float* r = &acc[q >> 2][(q & 3) * 4];
-                    r[0] += a * w.x;
-                    r[1] += a * w.y;
-                    r[2] += a * w.z;
-                    r[3] += a * w.w;
-                }
-            }
-            cur = nxt;
-        }
-        if (K1 == 0) ell_meta<true>(cur, E, E.bv0, E.bv1, e2, 0, K2);
-        for (int k0 = 0; k0 < K2; k0 += kEllChunk) {
-            if (k0 + kEllChunk < K2) ell_meta<true>(nxt, E, E.bv0, E.bv1, e2, k0 + kEllChunk, K2);
-#pragma unroll
-            for (int i = 0; i < kEllChunk; ++i) {
-                if (k0 + i >= K2) break;
-                const float4* ps = (const float4*)(smem_raw + cur.off[i]);
-                const float a0 = cur.a[i], a1 = cur.b[i];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const float4 w = ps[q];
-                    acc[0][4 * q + 0] += a0 * w.x;
-                    acc[0][4 * q + 1] += a0 * w.y;
-                    acc[0][4 * q + 2] += a0 * w.z;
-                    acc[0][4 * q + 3] += a0 * w.w;
-                    acc[1][4 * q + 0] += a1 * w.x;
-                    acc[1][4 * q + 1] += a1 * w.y;
-                    acc[1][4 * q + 2] += a1 * w.z;
-                    acc[1][4 * q + 3] += a1 * w.w;
-                }
-            }
-            cur = nxt;
-        }
+        ell_rows_a<M>(acc, E, smem_raw, e1, K1);
+        ell_rows_bt<M, false>(acc, E, smem_raw, e2, K2);
         if (row >= 0) {
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
                 float4* o = (float4*)(y + (2 * (int64_t)row + c) * J + j0);
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
+                for (int q = 0; q < M / 4; ++q)
                     o[q] = make_float4(acc[c][4 * q], acc[c][4 * q + 1], acc[c][4 * q + 2], acc[c][4 * q + 3]);
             }
         }
     } else {
-        float ax[kEllM], ay[kEllM];
-#pragma unroll
-        for (int m = 0; m < kEllM; ++m) ax[m] = ay[m] = 0.f;
+        // B rows: acc[0] = sum b_x x_0, acc[1] = sum b_y x_1 over the velocity nodes
         EllMeta cur, nxt;
-        ell_meta<true>(cur, E, E.bv0, E.bv1, e1, 0, K1);
+        ell_meta<true>(cur, E, e1, 0, K1);
         for (int k0 = 0; k0 < K1; k0 += kEllChunk) {
-            if (k0 + kEllChunk < K1) ell_meta<true>(nxt, E, E.bv0, E.bv1, e1, k0 + kEllChunk, K1);
+            if (k0 + kEllChunk < K1) ell_meta<true>(nxt, E, e1, k0 + kEllChunk, K1);
 #pragma unroll
             for (int i = 0; i < kEllChunk; ++i) {
                 if (k0 + i >= K1) break;
                 const float4* xs = (const float4*)(smem_raw + cur.off[i]);
                 const float a0 = cur.a[i], a1 = cur.b[i];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const float4 w = xs[q], u = xs[4 + q];
-                    ax[4 * q + 0] += a0 * w.x;
-                    ax[4 * q + 1] += a0 * w.y;
-                    ax[4 * q + 2] += a0 * w.z;
-                    ax[4 * q + 3] += a0 * w.w;
-                    ay[4 * q + 0] += a1 * u.x;
-                    ay[4 * q + 1] += a1 * u.y;
-                    ay[4 * q + 2] += a1 * u.z;
-                    ay[4 * q + 3] += a1 * u.w;
+                for (int q = 0; q < M / 4; ++q) {
+                    const float4 w = xs[q], u = xs[M / 4 + q];
+                    acc[0][4 * q + 0] += a0 * w.x;
+                    acc[0][4 * q + 1] += a0 * w.y;
+                    acc[0][4 * q + 2] += a0 * w.z;
+                    acc[0][4 * q + 3] += a0 * w.w;
+                    acc[1][4 * q + 0] += a1 * u.x;
+                    acc[1][4 * q + 1] += a1 * u.y;
+                    acc[1][4 * q + 2] += a1 * u.z;
+                    acc[1][4 * q + 3] += a1 * u.w;
                 }
             }
             cur = nxt;
@@ -1165,11 +1187,11 @@ __global__ void __launch_bounds__(NW * 64) k_saddle_e(EllView E, const float* __
             const float4* ps = (const float4*)(smem_raw + E.self[ro + lane]);
             float4* o = (float4*)(y + (2 * (int64_t)nP2 + row) * J + j0);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
+            for (int q = 0; q < M / 4; ++q) {
                 const float4 w = ps[q];
                 float r[4];
 #pragma unroll
-                for (int t = 0; t < 4; ++t) r[t] = ax[4 * q + t] + ay[4 * q + t];
+                for (int t = 0; t < 4; ++t) r[t] = acc[0][4 * q + t] + acc[1][4 * q + t];
                 r[0] += d * w.x;
                 r[1] += d * w.y;
                 r[2] += d * w.z;
@@ -1184,7 +1206,7 @@ __global__ void __launch_bounds__(NW * 64) k_saddle_e(EllView E, const float* __
 // stages the pressure slice of z_p and forms t = r_u - B^T z_p, z = w D^-1 t;
 // the other sweeps stage the velocity slice of z and form z + w D^-1 (t - A z).
 // Only the P2 row blocks (the first of a tile) are computed.
-template <bool FIRST, int NW>
+template <int M, bool FIRST, int NW>
 __global__ void __launch_bounds__(NW * 64) k_velo_e(EllView E, const float* __restrict__ dinvA,
                                                     const float* __restrict__ in, const float* __restrict__ zp,
                                                     float* __restrict__ t, const float* __restrict__ z,
@@ -1193,13 +1215,13 @@ __global__ void __launch_bounds__(NW * 64) k_velo_e(EllView E, const float* __re
     constexpr int NT = NW * 64;
     const int64_t bid = xcd_block(blockIdx.x, gridDim.x);
     const int tile = (int)(bid / MS);
-    const int j0 = (int)(bid % MS) * kEllM;
+    const int j0 = (int)(bid % MS) * M;
     const int32_t* td = E.tile + 8 * tile;
     const int s2o = td[0], n2 = td[1], s1o = td[2], n1 = td[3], b0 = td[4], nb = td[5];
-    if (FIRST)   // P1 slots at 0: entry offsets (past the P2 slots) are shifted back
-        ell_stage<NT>(smem_raw, E.s2 + s2o, 0, E.s1 + s1o, n1, 0, zp, zp, J, j0);
+    if (FIRST)   // P1 slots from 0: entry offsets (past the P2 slots) are shifted back
+        ell_stage<M, NT>(smem_raw, E.s2 + s2o, 0, E.s1 + s1o, n1, 0, zp, zp, J, j0);
     else
-        ell_stage<NT>(smem_raw, E.s2 + s2o, n2, E.s1 + s1o, 0, 0, z, z, J, j0);
+        ell_stage<M, NT>(smem_raw, E.s2 + s2o, n2, E.s1 + s1o, 0, 0, z, z, J, j0);
     __syncthreads();
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
@@ -1208,15 +1230,15 @@ __global__ void __launch_bounds__(NW * 64) k_velo_e(EllView E, const float* __re
     if (bd[0] != 0) return;
     const int K1 = bd[2], K2 = bd[3], e1 = bd[4] + lane, e2 = bd[5] + lane, ro = bd[6];
     const int row = E.rows[ro + lane];
-    const unsigned char* lds = FIRST ? smem_raw - n2 * kEllP2Bytes : smem_raw;
-    float acc[2][kEllM];
+    const unsigned char* lds = FIRST ? smem_raw - n2 * ell_p2_bytes(M) : smem_raw;
+    float acc[2][M];
     const int64_t o = 2 * (int64_t)max(row, 0) * J + j0;
     if constexpr (FIRST) {
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
             const float4* r = (const float4*)(in + o + (int64_t)c * J);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
+            for (int q = 0; q < M / 4; ++q) {
                 const float4 w = row >= 0 ? r[q] : make_float4(0.f, 0.f, 0.f, 0.f);
                 acc[c][4 * q] = w.x;
                 acc[c][4 * q + 1] = w.y;
@@ -1224,30 +1246,7 @@ __global__ void __launch_bounds__(NW * 64) k_velo_e(EllView E, const float* __re
                 acc[c][4 * q + 3] = w.w;
             }
         }
-        EllMeta cur, nxt;
-        ell_meta<true>(cur, E, E.bv0, E.bv1, e2, 0, K2);
-        for (int k0 = 0; k0 < K2; k0 += kEllChunk) {
-            if (k0 + kEllChunk < K2) ell_meta<true>(nxt, E, E.bv0, E.bv1, e2, k0 + kEllChunk, K2);
-#pragma unroll
-            for (int i = 0; i < kEllChunk; ++i) {
-                if (k0 + i >= K2) break;
-                const float4* ps = (const float4*)(lds + cur.off[i]);
-                const float a0 = -cur.a[i], a1 = -cur.b[i];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const float4 w = ps[q];
-                    acc[0][4 * q + 0] += a0 * w.x;
-                    acc[0][4 * q + 1] += a0 * w.y;
-                    acc[0][4 * q + 2] += a0 * w.z;
-                    acc[0][4 * q + 3] += a0 * w.w;
-                    acc[1][4 * q + 0] += a1 * w.x;
-                    acc[1][4 * q + 1] += a1 * w.y;
-                    acc[1][4 * q + 2] += a1 * w.z;
-                    acc[1][4 * q + 3] += a1 * w.w;
-                }
-            }
-            cur = nxt;
-        }
+        ell_rows_bt<M, true>(acc, E, lds, e2, K2);
         if (row >= 0) {
             const float dw = omega * dinvA[row];
 #pragma unroll
@@ -1255,7 +1254,7 @@ __global__ void __launch_bounds__(NW * 64) k_velo_e(EllView E, const float* __re
                 float4* ot = (float4*)(t + o + (int64_t)c * J);
                 float4* oz = (float4*)(zo + o + (int64_t)c * J);
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
+                for (int q = 0; q < M / 4; ++q) {
                     ot[q] = make_float4(acc[c][4 * q], acc[c][4 * q + 1], acc[c][4 * q + 2], acc[c][4 * q + 3]);
                     oz[q] = make_float4(acc[c][4 * q] * dw, acc[c][4 * q + 1] * dw, acc[c][4 * q + 2] * dw,
                                         acc[c][4 * q + 3] * dw);
@@ -1266,28 +1265,8 @@ __global__ void __launch_bounds__(NW * 64) k_velo_e(EllView E, const float* __re
 #pragma unroll
         for (int c = 0; c < 2; ++c)
 #pragma unroll
-            for (int m = 0; m < kEllM; ++m) acc[c][m] = 0.f;
-        EllMeta cur, nxt;
-        ell_meta<false>(cur, E, E.av, nullptr, e1, 0, K1);
-        for (int k0 = 0; k0 < K1; k0 += kEllChunk) {
-            if (k0 + kEllChunk < K1) ell_meta<false>(nxt, E, E.av, nullptr, e1, k0 + kEllChunk, K1);
-#pragma unroll
-            for (int i = 0; i < kEllChunk; ++i) {
-                if (k0 + i >= K1) break;
-                const float4* xs = (const float4*)(lds + cur.off[i]);
-                const float a = cur.a[i];
-#pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    const float4 w = xs[q];
-                    float* r = &acc[q >> 2][(q & 3) * 4];
-                    r[0] += a * w.x;
-                    r[1] += a * w.y;
-                    r[2] += a * w.z;
-                    r[3] += a * w.w;
-                }
-            }
-            cur = nxt;
-        }
+            for (int m = 0; m < M; ++m) acc[c][m] = 0.f;
+        ell_rows_a<M>(acc, E, lds, e1, K1);
         if (row >= 0) {
             const float dw = omega * dinvA[row];
             const float4* zs = (const float4*)(lds + E.self[ro + lane]);
@@ -1296,8 +1275,8 @@ __global__ void __launch_bounds__(NW * 64) k_velo_e(EllView E, const float* __re
                 const float4* tr = (const float4*)(t + o + (int64_t)c * J);
                 float4* oz = (float4*)(zo + o + (int64_t)c * J);
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const float4 tv = tr[q], zv = zs[4 * c + q];
+                for (int q = 0; q < M / 4; ++q) {
+                    const float4 tv = tr[q], zv = zs[(M / 4) * c + q];
                     float* a = &acc[c][4 * q];
                     oz[q] = make_float4(zv.x + dw * (tv.x - a[0]), zv.y + dw * (tv.y - a[1]),
                                         zv.z + dw * (tv.z - a[2]), zv.w + dw * (tv.w - a[3]));
@@ -1307,11 +1286,11 @@ __global__ void __launch_bounds__(NW * 64) k_velo_e(EllView E, const float* __re
     }
 }
 
-// A values into the entry order of a row-per-lane tiling: dst[pos[p]] = src[p]
+// A values into the packed entries of a row-per-lane tiling: am[pos[p]].y = bits of src[p]
 __global__ void __launch_bounds__(kBlock) k_ell_scatter(const float* __restrict__ src, const int32_t* __restrict__ pos,
-                                                        float* __restrict__ dst, int64_t n) {
+                                                        int2* __restrict__ am, int64_t n) {
     const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (p < n) dst[pos[p]] = src[p];
+    if (p < n) am[pos[p]].y = __float_as_int(src[p]);
 }
 
 // ------------------------------------------------------------------ multigrid kernels
@@ -2685,19 +2664,29 @@ mhd_status ensure_tiling(DevMesh& m, int id) {
 }
 
 // builds and uploads the row-per-lane tiling of shape id on first use (host
-// synchronous: not under capture); B and B^T values are copied in entry order
+// synchronous: not under capture); B and B^T entries are packed with their values
 mhd_status ensure_ell(DevMesh& m, int id) {
     if (id < 1 || id > kEllShapes) return MHD_EINVAL;
     std::lock_guard<std::mutex> lk(g_tiling_mu);
     if (m.ell[id]) return MHD_OK;
     HostEll h;
-    build_ell(m.host, ell_tx(id), ell_ty(id), h);
+    build_ell(m.host, ell_tx(id), ell_ty(id), ell_m(id), h);
     const size_t nent = h.loc.size();
     std::vector<float> bt32(2 * (size_t)m.nnzBt), b32(2 * (size_t)m.nnzB);
     MHD_HIP(hipMemcpy(bt32.data(), m.valBt32, sizeof(float) * bt32.size(), hipMemcpyDeviceToHost));
     MHD_HIP(hipMemcpy(b32.data(), m.valB32, sizeof(float) * b32.size(), hipMemcpyDeviceToHost));
-    std::vector<float> bv0(nent, 0.f), bv1(nent, 0.f);
+    auto bits = [](float f) {
+        int32_t b;
+        std::memcpy(&b, &f, 4);
+        return b;
+    };
+    std::vector<int4> bm(nent);
+    std::vector<int2> am(nent);
     std::vector<int32_t> posA((size_t)m.nnzA, -1);
+    for (size_t e = 0; e < nent; ++e) {
+        bm[e] = make_int4(h.loc[e], 0, 0, 0);
+        am[e] = make_int2(h.loc[e], 0);
+    }
     for (size_t b = 0; b < h.blk.size() / 8; ++b) {
         const int32_t* bd = &h.blk[8 * b];
         const int kind = bd[0], K1 = bd[2], K2 = bd[3], e1 = bd[4], e2 = bd[5];
@@ -2707,15 +2696,15 @@ mhd_status ensure_ell(DevMesh& m, int id) {
             if (kind == 0) {
                 posA[g] = e;
             } else {
-                bv0[e] = b32[2 * (size_t)g];
-                bv1[e] = b32[2 * (size_t)g + 1];
+                bm[e].y = bits(b32[2 * (size_t)g]);
+                bm[e].z = bits(b32[2 * (size_t)g + 1]);
             }
         }
         for (int e = e2; e < e2 + 64 * K2; ++e) {
             const int g = h.gp[e];
             if (g < 0) continue;
-            bv0[e] = bt32[2 * (size_t)g];
-            bv1[e] = bt32[2 * (size_t)g + 1];
+            bm[e].y = bits(bt32[2 * (size_t)g]);
+            bm[e].z = bits(bt32[2 * (size_t)g + 1]);
         }
     }
     for (int32_t q : posA)
@@ -2727,12 +2716,13 @@ mhd_status ensure_ell(DevMesh& m, int id) {
     if (!d) return MHD_ENOMEM;
     d->tx = h.tx;
     d->ty = h.ty;
+    d->m = h.m;
     d->ntiles = h.ntiles;
     d->max_lds = h.max_lds;
-    d->max_blocks = h.max_blocks;
-    d->max_blocks2 = h.max_blocks2;
     d->max_lds1 = h.max_lds1;
     d->max_lds2 = h.max_lds2;
+    d->max_blocks = h.max_blocks;
+    d->max_blocks2 = h.max_blocks2;
     d->max_k = h.max_k;
     d->nent = (int64_t)nent;
     auto up = [&](auto** p, const auto& v) -> mhd_status {
@@ -2755,9 +2745,8 @@ mhd_status ensure_ell(DevMesh& m, int id) {
     if (!rc) rc = up(&d->blk, h.blk);
     if (!rc) rc = up(&d->rows, h.rows);
     if (!rc) rc = up(&d->self, h.self);
-    if (!rc) rc = up(&d->loc, h.loc);
-    if (!rc) rc = up(&d->bv0, bv0);
-    if (!rc) rc = up(&d->bv1, bv1);
+    if (!rc) rc = up(&d->bm, bm);
+    if (!rc) rc = up(&d->am0, am);
     if (!rc) rc = up(&d->posA, posA);
     if (rc) {
         delete d;
@@ -2767,17 +2756,18 @@ mhd_status ensure_ell(DevMesh& m, int id) {
     return MHD_OK;
 }
 
-// the operator's A values in the entry order of tiling id (allocated and filled
-// on first use; later assemblies refresh it)
+// the operator's packed A entries for tiling id (allocated and filled on first
+// use; later assemblies refresh them while a plan uses the tiling)
 mhd_status ensure_ell_values(DevShared& S, int id, hipStream_t st) {
     mhd_status rc = ensure_ell(*S.mesh, id);
     if (rc) return rc;
     if (S.ellA[id]) return MHD_OK;
     const DevEll& t = *S.mesh->ell[id];
-    float* p = nullptr;
-    MHD_HIP(hipMalloc((void**)&p, sizeof(float) * (size_t)std::max<int64_t>(t.nent, 64)));
+    int2* p = nullptr;
+    const size_t bytes = sizeof(int2) * (size_t)std::max<int64_t>(t.nent, 64);
+    MHD_HIP(hipMalloc((void**)&p, bytes));
     S.allocs.push_back(p);
-    MHD_HIP(hipMemsetAsync(p, 0, sizeof(float) * (size_t)std::max<int64_t>(t.nent, 64), st));   // padding stays 0
+    MHD_HIP(hipMemcpyAsync(p, t.am0, sizeof(int2) * (size_t)t.nent, hipMemcpyDeviceToDevice, st));
     hipLaunchKernelGGL(k_ell_scatter, dim3((unsigned)((S.mesh->nnzA + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
                        S.valA32, t.posA, p, S.mesh->nnzA);
     MHD_HIP(hipGetLastError());
@@ -2800,8 +2790,8 @@ mhd_status use_ell(DevShared& S, int id, hipStream_t st) {
     return MHD_OK;
 }
 
-// shape code of the public interface (tx * 100 + ty) <-> shape id
-inline int ell_code(int id) { return ell_tx(id) * 100 + ell_ty(id); }
+// shape code of the public interface: tx * 100 + ty, plus 10000 for 8 members per workgroup
+inline int ell_code(int id) { return ell_tx(id) * 100 + ell_ty(id) + (ell_m(id) == 8 ? 10000 : 0); }
 inline int ell_id(int code) {
     for (int id = 1; id <= kEllShapes; ++id)
         if (ell_code(id) == code) return id;
@@ -2809,7 +2799,7 @@ inline int ell_id(int code) {
 }
 
 bool ell_usable(const DevShared& S, int id, int J) {
-    if (id < 1 || id > kEllShapes || S.transposed || J % kEllM || !S.ellA[id] || !S.mesh->ell[id]) return false;
+    if (id < 1 || id > kEllShapes || S.transposed || J % ell_m(id) || !S.ellA[id] || !S.mesh->ell[id]) return false;
     const DevEll& t = *S.mesh->ell[id];
     return t.max_blocks <= 8 && t.max_blocks2 <= 8 && t.max_lds + 16 <= max_lds_bytes();
 }
@@ -2960,8 +2950,8 @@ mhd_status launch_saddle_plan(NodePlan p, DevShared& S, const T* x, const T* b, 
         if constexpr (sizeof(T) == 4 && MODE == 0) {
             if (ell_usable(S, p.tile, J)) {
                 const DevEll& t = *m.ell[p.tile];
-                const int MS = J / kEllM;
-                const EllView E{t.tile, t.s2, t.s1, t.blk, t.rows, t.self, t.loc, S.ellA[p.tile], t.bv0, t.bv1};
+                const int MS = J / t.m;
+                const EllView E{t.tile, t.s2, t.s1, t.blk, t.rows, t.self, S.ellA[p.tile], t.bm};
                 const dim3 grid((unsigned)((int64_t)t.ntiles * MS));
                 const size_t lds = (size_t)t.max_lds + 16;   // + the slot of the staging overrun
                 auto go = [&](auto kern, int threads) -> mhd_status {
@@ -2970,9 +2960,13 @@ mhd_status launch_saddle_plan(NodePlan p, DevShared& S, const T* x, const T* b, 
                     LAUNCH_CHECK();
                     return MHD_OK;
                 };
-                if (t.max_blocks <= 2) return go(k_saddle_e<2>, 128);
-                if (t.max_blocks <= 4) return go(k_saddle_e<4>, 256);
-                return go(k_saddle_e<8>, 512);
+                auto by_waves = [&](auto Mc) -> mhd_status {
+                    constexpr int MM = decltype(Mc)::value;
+                    if (t.max_blocks <= 2) return go(k_saddle_e<MM, 2>, 128);
+                    if (t.max_blocks <= 4) return go(k_saddle_e<MM, 4>, 256);
+                    return go(k_saddle_e<MM, 8>, 512);
+                };
+                return t.m == 8 ? by_waves(std::integral_constant<int, 8>{}) : by_waves(std::integral_constant<int, 16>{});
             }
         }
         p = default_plan(m, J, sizeof(T));
@@ -3075,8 +3069,8 @@ mhd_status launch_velo_plan(NodePlan p, DevShared& S, const T* in, const T* zp, 
         if constexpr (sizeof(T) == 4) {
             if (ell_usable(S, p.tile, J)) {
                 const DevEll& tl = *S.mesh->ell[p.tile];
-                const int MS = J / kEllM;
-                const EllView E{tl.tile, tl.s2, tl.s1, tl.blk, tl.rows, tl.self, tl.loc, S.ellA[p.tile], tl.bv0, tl.bv1};
+                const int MS = J / tl.m;
+                const EllView E{tl.tile, tl.s2, tl.s1, tl.blk, tl.rows, tl.self, S.ellA[p.tile], tl.bm};
                 const dim3 grid((unsigned)((int64_t)tl.ntiles * MS));
                 const size_t lds = (size_t)(FIRST ? tl.max_lds1 : tl.max_lds2) + 16;
                 auto go = [&](auto kern, int threads) -> mhd_status {
@@ -3085,9 +3079,13 @@ mhd_status launch_velo_plan(NodePlan p, DevShared& S, const T* in, const T* zp, 
                     LAUNCH_CHECK();
                     return MHD_OK;
                 };
-                if (tl.max_blocks2 <= 2) return go(k_velo_e<FIRST, 2>, 128);
-                if (tl.max_blocks2 <= 4) return go(k_velo_e<FIRST, 4>, 256);
-                return go(k_velo_e<FIRST, 8>, 512);
+                auto by_waves = [&](auto Mc) -> mhd_status {
+                    constexpr int MM = decltype(Mc)::value;
+                    if (tl.max_blocks2 <= 2) return go(k_velo_e<MM, FIRST, 2>, 128);
+                    if (tl.max_blocks2 <= 4) return go(k_velo_e<MM, FIRST, 4>, 256);
+                    return go(k_velo_e<MM, FIRST, 8>, 512);
+                };
+                return tl.m == 8 ? by_waves(std::integral_constant<int, 8>{}) : by_waves(std::integral_constant<int, 16>{});
             }
         }
         p = default_plan(*S.mesh, J, sizeof(T));
@@ -3219,7 +3217,7 @@ mhd_status tune_op(DevShared& S, int J, int op, hipStream_t st, std::vector<mhd_
             }
         }
     }
-    if (word == 4 && op != MHD_TUNE_RESIDUAL && J % kEllM == 0 && !S.transposed)
+    if (word == 4 && op != MHD_TUNE_RESIDUAL && J % 8 == 0 && !S.transposed)
         for (int id = 1; id <= kEllShapes; ++id) {
             mhd_status rc = ensure_ell_values(S, id, st);
             if (rc) return rc;
@@ -3310,9 +3308,10 @@ mhd_status set_plan(DevShared& S, int J, int precision, int op, int vec, int gro
     }
     if (deep == 6) {
         const int id = ell_id(tile);
-        if (word != 4 || op == MHD_TUNE_RESIDUAL || J % kEllM || !id) {
+        if (word != 4 || op == MHD_TUNE_RESIDUAL || !id || J % ell_m(id)) {
             set_error("mhd_ens_set_plan: row-per-lane tiles (deep 6) are an FP32 plan (SpMM and Jacobi sweeps) with "
-                      "tile 1616, 3208 or 1608 and J a multiple of 16");
+                      "tile 1616, 3208 or 1608 (16 members per workgroup, J a multiple of 16) or 11616, 13208 or "
+                      "11608 (8 members, J a multiple of 8)");
             return MHD_EINVAL;
         }
         mhd_status rc = use_ell(S, id, nullptr);

@@ -127,10 +127,12 @@ void build_tiling(const HostMesh& m, int tx, int ty, HostTiling& t) {
     }
 }
 
-void build_ell(const HostMesh& m, int tx, int ty, HostEll& t) {
+void build_ell(const HostMesh& m, int tx, int ty, int M, HostEll& t) {
     t = HostEll{};
     t.tx = tx;
     t.ty = ty;
+    t.m = M;
+    const int P2B = ell_p2_bytes(M), P1B = ell_p1_bytes(M);
     const int nP2 = m.nP2, nP1 = m.nP1;
     int hxmax = 0;
     std::vector<int> hx(nP2), hy(nP2);
@@ -177,11 +179,11 @@ void build_ell(const HostMesh& m, int tx, int ty, HostEll& t) {
         std::sort(st2.begin(), st2.end(), [&](int32_t a, int32_t b) { return key(a) < key(b); });
         std::sort(st1.begin(), st1.end());
         st1.erase(std::unique(st1.begin(), st1.end()), st1.end());
-        const int p1base = (int)st2.size() * kEllP2Bytes;
-        for (size_t s = 0; s < st2.size(); ++s) off2[st2[s]] = (int32_t)s * kEllP2Bytes;
-        for (size_t s = 0; s < st1.size(); ++s) off1[st1[s]] = p1base + (int32_t)s * kEllP1Bytes;
-        t.max_lds = std::max(t.max_lds, p1base + (int)st1.size() * kEllP1Bytes);
-        t.max_lds1 = std::max(t.max_lds1, (int)st1.size() * kEllP1Bytes);
+        const int p1base = (int)st2.size() * P2B;
+        for (size_t s = 0; s < st2.size(); ++s) off2[st2[s]] = (int32_t)s * P2B;
+        for (size_t s = 0; s < st1.size(); ++s) off1[st1[s]] = p1base + (int32_t)s * P1B;
+        t.max_lds = std::max(t.max_lds, p1base + (int)st1.size() * P1B);
+        t.max_lds1 = std::max(t.max_lds1, (int)st1.size() * P1B);
         t.max_lds2 = std::max(t.max_lds2, p1base);
         t.max_blocks2 = std::max(t.max_blocks2, (int)((R2.size() + 63) / 64));
         // longest rows first, so that the rows of a block have similar lengths

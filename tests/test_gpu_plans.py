@@ -54,10 +54,11 @@ def candidates(J, word):
 
 
 def ell_candidates(J, word):
-    """Row-per-lane tiles (FP32 SpMM only): tile code tx * 100 + ty."""
-    if word != 4 or J % 16:
+    """Row-per-lane tiles (FP32): tile code tx * 100 + ty (+ 10000: 8 members per workgroup)."""
+    if word != 4 or J % 8:
         return []
-    return [(4, 0, 6, code, 0) for code in (1616, 3208, 1608)]
+    codes = (11616, 13208, 11608) + ((1616, 3208, 1608) if J % 16 == 0 else ())
+    return [(4, 0, 6, code, 0) for code in codes]
 
 
 def set_plan(L, A, J, precision, op, plan):
