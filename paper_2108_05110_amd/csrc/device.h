@@ -147,6 +147,8 @@ struct GmresWork {
     std::vector<void*> mg_x, mg_x2, mg_b, mg_r;   // per level (n_l x Jmax, sized for double)
     void* dense_part = nullptr;   // partial products of the coarsest dense solve (kDenseKS x n_c x Jmax)
     void** dptrs = nullptr;       // device array of the basis block pointers
+    void* zbasis = nullptr;       // restart FP32 blocks: the preconditioned basis vectors of FP32 solves
+    void** zptrs = nullptr;       // device array of their pointers
 };
 
 struct DevShared {

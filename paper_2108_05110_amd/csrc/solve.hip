@@ -3588,6 +3588,12 @@ mhd_status gmres_solve(DevShared& S, const double* b, double* x, int J, const mh
     RedShape rs = cap_blocks(red_shape(n, J, 16 / (int)sizeof(T)), G.nblk_cap);
     const int passes = o.cgs_passes > 0 ? o.cgs_passes : (sizeof(T) == 4 ? 1 : 2);
     const T* const* Vd = (const T* const*)G.dptrs;
+    // FP32 solves keep z_k = P^-1 v_k (flexible form), saving one preconditioner
+    // application per refinement cycle; FP64 solves recompute P^-1 (V y)
+    const bool keepz = sizeof(T) == 4 && G.zbasis != nullptr;
+    const T* const* Zd = (const T* const*)G.zptrs;
+    const size_t zblk = (((size_t)n * S.Jmax * sizeof(float)) + 255) & ~(size_t)255;
+    auto zslot = [&](int k) { return (T*)((char*)G.zbasis + (size_t)k * zblk); };
     double* hres = G.host_res;                 // pinned, 3 J doubles: residuals, beta, bnorm
     double* hbeta = G.host_res + J;
     double* hbn = G.host_res + 2 * J;
@@ -3638,7 +3644,7 @@ mhd_status gmres_solve(DevShared& S, const double* b, double* x, int J, const mh
         int kd = 0;
         for (int k = 0; k < mres && (fixed || iters < o.maxit); ++k) {
             T* vk = basis_ptr<T>(S, k);
-            T* z = (T*)G.zbuf;
+            T* z = keepz ? zslot(k) : (T*)G.zbuf;
             T* w = basis_ptr<T>(S, k + 1);
             if ((rc = ops.precond(vk, z, sweeps, omega))) return rc;
             if ((rc = ops.saddle(z, w))) return rc;
@@ -3692,19 +3698,23 @@ mhd_status gmres_solve(DevShared& S, const double* b, double* x, int J, const mh
                 if (done) break;
             }
         }
-        // x += P^{-1} (V y)
+        // x += P^{-1} (V y), or with the preconditioned vectors kept, x += Z y (Z = P^-1 V)
         hipLaunchKernelGGL(k_lsq, dim3((J + 63) / 64), dim3(64), 0, st, G.H, G.g, G.y, kd, mres, J);
         LAUNCH_CHECK();
         T* u = (T*)G.wbuf;
         rc = with_vec<T>(rs.VEC, [&](auto V) -> mhd_status {
-            hipLaunchKernelGGL((k_combine<T, decltype(V)::value>), rs.grid, dim3(kBlock), 0, st, Vd, kd,
+            hipLaunchKernelGGL((k_combine<T, decltype(V)::value>), rs.grid, dim3(kBlock), 0, st, keepz ? Zd : Vd, kd,
                                (const double*)G.y, u, n, J, rs.CW);
             LAUNCH_CHECK();
             return MHD_OK;
         });
         if (rc) return rc;
-        if ((rc = ops.precond(u, (T*)G.zbuf, sweeps, omega))) return rc;
-        hipLaunchKernelGGL((k_add_to64<T>), dim3(ew_grid(n * J)), dim3(kBlock), 0, st, x, (const T*)G.zbuf, n * J);
+        const T* dx = u;
+        if (!keepz) {
+            if ((rc = ops.precond(u, (T*)G.zbuf, sweeps, omega))) return rc;
+            dx = (const T*)G.zbuf;
+        }
+        hipLaunchKernelGGL((k_add_to64<T>), dim3(ew_grid(n * J)), dim3(kBlock), 0, st, x, dx, n * J);
         LAUNCH_CHECK();
         ++cycles;
     }
@@ -3763,6 +3773,13 @@ mhd_status alloc_gmres(DevShared& S, int restart) {
     std::vector<void*> ptrs(restart + 1);
     for (int i = 0; i <= restart; ++i) ptrs[i] = (char*)G.basis + (size_t)i * blk;
     MHD_HIP(hipMemcpy(G.dptrs, ptrs.data(), sizeof(void*) * (restart + 1), hipMemcpyHostToDevice));
+    // FP32 solves keep M^-1 v_k of every inner iteration (slots of n x Jmax floats)
+    const size_t zblk = (((size_t)m.n * S.Jmax * sizeof(float)) + 255) & ~(size_t)255;
+    if ((rc = A(&G.zbasis, zblk * restart))) return rc;
+    if ((rc = A((void**)&G.zptrs, sizeof(void*) * (kMaxRestart + 1)))) return rc;
+    std::vector<void*> zp(restart);
+    for (int i = 0; i < restart; ++i) zp[i] = (char*)G.zbasis + (size_t)i * zblk;
+    MHD_HIP(hipMemcpy(G.zptrs, zp.data(), sizeof(void*) * restart, hipMemcpyHostToDevice));
     if ((rc = A(&G.dense_part, (size_t)kDenseKS * m.levels.back().n * S.Jmax * sizeof(double)))) return rc;
     for (size_t l = 0; l < m.levels.size(); ++l) {
         size_t lb = (size_t)m.levels[l].n * S.Jmax * sizeof(double);
