@@ -2190,16 +2190,25 @@ __global__ void __launch_bounds__(kBlock) k_dots(const T* const* __restrict__ V,
         const T* vp[NB];
 #pragma unroll
         for (int i = 0; i < NB; ++i) vp[i] = (i < nb) ? V[c0 + i] : nullptr;
-        for (int64_t r = (int64_t)blockIdx.x * c.RG + c.ty; r < n; r += (int64_t)gridDim.x * c.RG) {
-            T wv[VEC];
+        // two rows per iteration (r and r + stride) for more loads in flight
+        const int64_t stride = (int64_t)gridDim.x * c.RG;
+        for (int64_t r = (int64_t)blockIdx.x * c.RG + c.ty; r < n; r += 2 * stride) {
+            const int64_t r2 = r + stride < n ? r + stride : r;
+            const double g2 = r + stride < n ? 1.0 : 0.0;
+            T wv[VEC], wv2[VEC];
             vload<T, VEC>(wv, w + r * J + c.jb);
+            vload<T, VEC>(wv2, w + r2 * J + c.jb);
 #pragma unroll
             for (int i = 0; i < NB; ++i)
                 if (i < nb) {
-                    T vv[VEC];
+                    T vv[VEC], vv2[VEC];
                     vload<T, VEC>(vv, vp[i] + r * J + c.jb);
+                    vload<T, VEC>(vv2, vp[i] + r2 * J + c.jb);
 #pragma unroll
-                    for (int u = 0; u < VEC; ++u) acc[i][u] += (double)vv[u] * (double)wv[u];
+                    for (int u = 0; u < VEC; ++u) {
+                        acc[i][u] += (double)vv[u] * (double)wv[u];
+                        acc[i][u] += g2 * ((double)vv2[u] * (double)wv2[u]);
+                    }
                 }
         }
     }
@@ -2227,18 +2236,33 @@ __global__ void __launch_bounds__(kBlock) k_update(const T* const* __restrict__ 
 #pragma unroll
     for (int u = 0; u < VEC; ++u) acc[u] = 0.0;
     if (c.ok) {
-        for (int64_t r = (int64_t)blockIdx.x * c.RG + c.ty; r < n; r += (int64_t)gridDim.x * c.RG) {
-            T wv[VEC];
+        // two rows per iteration (r and r + stride; the second only if it exists)
+        const int64_t stride = (int64_t)gridDim.x * c.RG;
+        for (int64_t r = (int64_t)blockIdx.x * c.RG + c.ty; r < n; r += 2 * stride) {
+            const bool two = r + stride < n;
+            const int64_t r2 = two ? r + stride : r;
+            T wv[VEC], wv2[VEC];
             vload<T, VEC>(wv, w + r * J + c.jb);
+            vload<T, VEC>(wv2, w + r2 * J + c.jb);
             for (int i = 0; i < nb; ++i) {
-                T vv[VEC];
+                T vv[VEC], vv2[VEC];
                 vload<T, VEC>(vv, V[i] + r * J + c.jb);
+                vload<T, VEC>(vv2, V[i] + r2 * J + c.jb);
 #pragma unroll
-                for (int u = 0; u < VEC; ++u) wv[u] -= (T)h[(int64_t)i * J + c.jb + u] * vv[u];
+                for (int u = 0; u < VEC; ++u) {
+                    const T hh = (T)h[(int64_t)i * J + c.jb + u];
+                    wv[u] -= hh * vv[u];
+                    wv2[u] -= hh * vv2[u];
+                }
             }
             vstore<T, VEC>(w + r * J + c.jb, wv);
 #pragma unroll
             for (int u = 0; u < VEC; ++u) acc[u] += (double)wv[u] * (double)wv[u];
+            if (two) {
+                vstore<T, VEC>(w + r2 * J + c.jb, wv2);
+#pragma unroll
+                for (int u = 0; u < VEC; ++u) acc[u] += (double)wv2[u] * (double)wv2[u];
+            }
         }
     }
     const int64_t nblk = gridDim.x;
@@ -2279,17 +2303,26 @@ __global__ void __launch_bounds__(kBlock) k_combine(const T* const* __restrict__
                                                     T* __restrict__ u, int64_t n, int J, int CW) {
     const ColMap c = colmap(CW, VEC, J);
     if (!c.ok) return;
-    for (int64_t r = (int64_t)blockIdx.x * c.RG + c.ty; r < n; r += (int64_t)gridDim.x * c.RG) {
-        T s[VEC];
+    const int64_t stride = (int64_t)gridDim.x * c.RG;
+    for (int64_t r = (int64_t)blockIdx.x * c.RG + c.ty; r < n; r += 2 * stride) {
+        const bool two = r + stride < n;
+        const int64_t r2 = two ? r + stride : r;
+        T s[VEC], s2[VEC];
 #pragma unroll
-        for (int q = 0; q < VEC; ++q) s[q] = 0;
+        for (int q = 0; q < VEC; ++q) s[q] = s2[q] = 0;
         for (int i = 0; i < nb; ++i) {
-            T vv[VEC];
+            T vv[VEC], vv2[VEC];
             vload<T, VEC>(vv, V[i] + r * J + c.jb);
+            vload<T, VEC>(vv2, V[i] + r2 * J + c.jb);
 #pragma unroll
-            for (int q = 0; q < VEC; ++q) s[q] += (T)yv[(int64_t)i * J + c.jb + q] * vv[q];
+            for (int q = 0; q < VEC; ++q) {
+                const T yy = (T)yv[(int64_t)i * J + c.jb + q];
+                s[q] += yy * vv[q];
+                s2[q] += yy * vv2[q];
+            }
         }
         vstore<T, VEC>(u + r * J + c.jb, s);
+        if (two) vstore<T, VEC>(u + r2 * J + c.jb, s2);
     }
 }
 
@@ -2322,6 +2355,29 @@ __global__ void __launch_bounds__(kBlock) k_scale_cols(const TI* __restrict__ a,
         else
             r = v * f;
         out[idx] = (TO)r;
+    }
+}
+
+// as k_scale_cols with VEC consecutive members per thread (J a multiple of VEC):
+// out[r, j] = a[r, j] / s[j] (invert; 0 where s[j] <= 0) or a[r, j] s[j]
+template <typename TI, typename TO, int VEC>
+__global__ void __launch_bounds__(kBlock) k_scale_cols_v(const TI* __restrict__ a, const double* __restrict__ s,
+                                                         int invert, TO* __restrict__ out, int64_t n, int J, int CW) {
+    const ColMap c = colmap(CW, VEC, J);
+    if (!c.ok) return;
+    double f[VEC];
+#pragma unroll
+    for (int u = 0; u < VEC; ++u) f[u] = s[c.jb + u];
+    for (int64_t r = (int64_t)blockIdx.x * c.RG + c.ty; r < n; r += (int64_t)gridDim.x * c.RG) {
+        TI v[VEC];
+        TO o[VEC];
+        vload<TI, VEC>(v, a + r * J + c.jb);
+#pragma unroll
+        for (int u = 0; u < VEC; ++u) {
+            const double x = (double)v[u];
+            o[u] = (TO)(invert ? (f[u] > 0.0 ? x / f[u] : 0.0) : x * f[u]);
+        }
+        vstore<TO, VEC>(out + r * J + c.jb, o);
     }
 }
 
@@ -3574,6 +3630,23 @@ mhd_status sync_copy(double* host, const double* dev, int J, hipStream_t st) {
     return MHD_OK;
 }
 
+// out = a / s (per column) with 16-byte loads where the shape allows, else elementwise
+template <typename TI, typename TO>
+mhd_status launch_scale_cols(const TI* a, const double* s, TO* out, int64_t n, int J, hipStream_t st) {
+    constexpr int V = 16 / (int)sizeof(TI);
+    const RedShape rs = red_shape(n, J, V);
+    if (rs.VEC == V && ((uintptr_t)a | (uintptr_t)out) % 16 == 0) {
+        const int RG = kBlock / rs.CW;
+        const unsigned nb = (unsigned)std::min<int64_t>(8192, (n + RG - 1) / RG);
+        hipLaunchKernelGGL((k_scale_cols_v<TI, TO, V>), dim3(nb, rs.grid.y), dim3(kBlock), 0, st, a, s, 1, out, n, J,
+                           rs.CW);
+    } else {
+        hipLaunchKernelGGL((k_scale_cols<TI, TO>), dim3(ew_grid(n * J)), dim3(kBlock), 0, st, a, s, 1, out, n, J);
+    }
+    LAUNCH_CHECK();
+    return MHD_OK;
+}
+
 template <typename T>
 mhd_status gmres_solve(DevShared& S, const double* b, double* x, int J, const mhd_solver_opts& o,
                        mhd_solve_stats* stt, hipStream_t st) {
@@ -3636,9 +3709,7 @@ mhd_status gmres_solve(DevShared& S, const double* b, double* x, int J, const mh
         if (iters >= o.maxit) break;
         }
         // v0 = r / beta in the inner precision; g = beta e1
-        hipLaunchKernelGGL((k_scale_cols<double, T>), dim3(ew_grid(n * J)), dim3(kBlock), 0, st, (const double*)G.r64,
-                           G.beta, 1, basis_ptr<T>(S, 0), n, J);
-        LAUNCH_CHECK();
+        if ((rc = launch_scale_cols<double, T>(G.r64, G.beta, basis_ptr<T>(S, 0), n, J, st))) return rc;
         hipLaunchKernelGGL(k_init_g, dim3((J + 255) / 256), dim3(256), 0, st, G.g, G.beta, mres + 1, J);
         LAUNCH_CHECK();
         int kd = 0;
@@ -3683,9 +3754,7 @@ mhd_status gmres_solve(DevShared& S, const double* b, double* x, int J, const mh
             hipLaunchKernelGGL(k_givens, dim3((J + 63) / 64), dim3(64), 0, st, G.H, G.cs, G.sn, G.g, G.hcol, hn, G.res,
                                k, mres, J);
             LAUNCH_CHECK();
-            hipLaunchKernelGGL((k_scale_cols<T, T>), dim3(ew_grid(n * J)), dim3(kBlock), 0, st, (const T*)w, hn, 1, w,
-                               n, J);
-            LAUNCH_CHECK();
+            if ((rc = launch_scale_cols<T, T>(w, hn, w, n, J, st))) return rc;
             ++iters;
             kd = k + 1;
             if (!fixed && (kd % check == 0 || kd == mres)) {
