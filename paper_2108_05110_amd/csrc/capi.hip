@@ -791,8 +791,10 @@ mhd_status mhd_ens_step(mhd_ctx ctx, double* V, double* W, double* Q, double* R,
         CHECK_ARG(stv != nullptr, "mhd_ens_step: graph mode needs a non-null stream");
         if (!ctx->graph.valid || !(ctx->graph.key == a) || ctx->graph.stream != stv) {
             ctx->graph.reset();
-            // kernel plans are fixed into the graph: tune before capturing
+            // kernel plans are fixed into the graph: tune before capturing (the second
+            // handle only takes the per-operator data of the plans tuned on the first)
             if ((rc = autotune(ctx->Av->d, a.J, ctx->desc.solver.precision, stv, false, nullptr))) return rc;
+            if ((rc = autotune(ctx->Aw->d, a.J, ctx->desc.solver.precision, stv, false, nullptr))) return rc;
             MHD_HIP(hipStreamBeginCapture(stv, hipStreamCaptureModeThreadLocal));
             rs = step_device(ctx, c, a, stv, &sv, &sw, true);
             hipGraph_t graph = nullptr;
@@ -904,6 +906,8 @@ mhd_status mhd_ens_group_step(mhd_group g, double* const* V, double* const* W, d
         for (int i = 0; i < n; ++i) {
             mhd_status rc = autotune(g->ctxs[i]->Av->d, args[i].J, g->ctxs[i]->desc.solver.precision, st, false,
                                      nullptr);
+            if (rc) return rc;
+            rc = autotune(g->ctxs[i]->Aw->d, args[i].J, g->ctxs[i]->desc.solver.precision, st, false, nullptr);
             if (rc) return rc;
         }
         MHD_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
