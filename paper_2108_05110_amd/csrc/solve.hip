@@ -2175,9 +2175,10 @@ __device__ __forceinline__ double block_colsum(double v, const ColMap& c, double
     return s;
 }
 
-// partial[((c0 + i) * J + j) * nblk + block] = sum over rows of V_i[r, j] * w[r, j], i < nb
+// partial[((c0 + i) * J + j) * nblk + block] = sum over rows of V_i[r, j] * w[r, j], i < NB.
+// NB is the exact count, so all loads of an iteration are issued before the products.
 template <typename T, int VEC, int NB>
-__global__ void __launch_bounds__(kBlock) k_dots(const T* const* __restrict__ V, int c0, int nb, const T* __restrict__ w,
+__global__ void __launch_bounds__(kBlock) k_dots(const T* const* __restrict__ V, int c0, const T* __restrict__ w,
                                                  int64_t n, int J, int CW, double* __restrict__ partial) {
     __shared__ double red[kBlock];
     const ColMap c = colmap(CW, VEC, J);
@@ -2189,45 +2190,46 @@ __global__ void __launch_bounds__(kBlock) k_dots(const T* const* __restrict__ V,
     if (c.ok) {
         const T* vp[NB];
 #pragma unroll
-        for (int i = 0; i < NB; ++i) vp[i] = (i < nb) ? V[c0 + i] : nullptr;
+        for (int i = 0; i < NB; ++i) vp[i] = V[c0 + i];
         // two rows per iteration (r and r + stride) for more loads in flight
         const int64_t stride = (int64_t)gridDim.x * c.RG;
         for (int64_t r = (int64_t)blockIdx.x * c.RG + c.ty; r < n; r += 2 * stride) {
             const int64_t r2 = r + stride < n ? r + stride : r;
             const double g2 = r + stride < n ? 1.0 : 0.0;
-            T wv[VEC], wv2[VEC];
+            T wv[VEC], wv2[VEC], vv[NB][VEC], vv2[NB][VEC];
             vload<T, VEC>(wv, w + r * J + c.jb);
             vload<T, VEC>(wv2, w + r2 * J + c.jb);
 #pragma unroll
-            for (int i = 0; i < NB; ++i)
-                if (i < nb) {
-                    T vv[VEC], vv2[VEC];
-                    vload<T, VEC>(vv, vp[i] + r * J + c.jb);
-                    vload<T, VEC>(vv2, vp[i] + r2 * J + c.jb);
+            for (int i = 0; i < NB; ++i) {
+                vload<T, VEC>(vv[i], vp[i] + r * J + c.jb);
+                vload<T, VEC>(vv2[i], vp[i] + r2 * J + c.jb);
+            }
 #pragma unroll
-                    for (int u = 0; u < VEC; ++u) {
-                        acc[i][u] += (double)vv[u] * (double)wv[u];
-                        acc[i][u] += g2 * ((double)vv2[u] * (double)wv2[u]);
-                    }
+            for (int i = 0; i < NB; ++i)
+#pragma unroll
+                for (int u = 0; u < VEC; ++u) {
+                    acc[i][u] += (double)vv[i][u] * (double)wv[u];
+                    acc[i][u] += g2 * ((double)vv2[i][u] * (double)wv2[u]);
                 }
         }
     }
     const int64_t nblk = gridDim.x;
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
-        if (i < nb) {
 #pragma unroll
-            for (int u = 0; u < VEC; ++u) {
-                double sv = block_colsum(acc[i][u], c, red, CW);
-                if (c.ty == 0 && c.ok) partial[((int64_t)(c0 + i) * J + c.jb + u) * nblk + blockIdx.x] = sv;
-            }
+        for (int u = 0; u < VEC; ++u) {
+            double sv = block_colsum(acc[i][u], c, red, CW);
+            if (c.ty == 0 && c.ok) partial[((int64_t)(c0 + i) * J + c.jb + u) * nblk + blockIdx.x] = sv;
         }
     }
 }
 
-// w -= sum_{i<nb} h[i*J + j] V_i ; partial[j * nblk + block] = sum over rows of w^2
-template <typename T, int VEC>
-__global__ void __launch_bounds__(kBlock) k_update(const T* const* __restrict__ V, int nb, const double* __restrict__ h,
+// w -= sum_{i<NB} h[(c0 + i) J + j] V_{c0 + i}; with LAST also partial[j * nblk +
+// block] = sum over rows of w^2.  NB is the exact count (all loads of an
+// iteration issued before the arithmetic); longer updates run in chunks, which
+// perform the same operations in the same order.
+template <typename T, int VEC, int NB, bool LAST>
+__global__ void __launch_bounds__(kBlock) k_update(const T* const* __restrict__ V, int c0, const double* __restrict__ h,
                                                    T* __restrict__ w, int64_t n, int J, int CW,
                                                    double* __restrict__ partial) {
     __shared__ double red[kBlock];
@@ -2236,40 +2238,52 @@ __global__ void __launch_bounds__(kBlock) k_update(const T* const* __restrict__ 
 #pragma unroll
     for (int u = 0; u < VEC; ++u) acc[u] = 0.0;
     if (c.ok) {
+        T hh[NB][VEC];
+        const T* vp[NB];
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            vp[i] = V[c0 + i];
+#pragma unroll
+            for (int u = 0; u < VEC; ++u) hh[i][u] = (T)h[(int64_t)(c0 + i) * J + c.jb + u];
+        }
         // two rows per iteration (r and r + stride; the second only if it exists)
         const int64_t stride = (int64_t)gridDim.x * c.RG;
         for (int64_t r = (int64_t)blockIdx.x * c.RG + c.ty; r < n; r += 2 * stride) {
             const bool two = r + stride < n;
             const int64_t r2 = two ? r + stride : r;
-            T wv[VEC], wv2[VEC];
+            T wv[VEC], wv2[VEC], vv[NB][VEC], vv2[NB][VEC];
             vload<T, VEC>(wv, w + r * J + c.jb);
             vload<T, VEC>(wv2, w + r2 * J + c.jb);
-            for (int i = 0; i < nb; ++i) {
-                T vv[VEC], vv2[VEC];
-                vload<T, VEC>(vv, V[i] + r * J + c.jb);
-                vload<T, VEC>(vv2, V[i] + r2 * J + c.jb);
+#pragma unroll
+            for (int i = 0; i < NB; ++i) {
+                vload<T, VEC>(vv[i], vp[i] + r * J + c.jb);
+                vload<T, VEC>(vv2[i], vp[i] + r2 * J + c.jb);
+            }
+#pragma unroll
+            for (int i = 0; i < NB; ++i)
 #pragma unroll
                 for (int u = 0; u < VEC; ++u) {
-                    const T hh = (T)h[(int64_t)i * J + c.jb + u];
-                    wv[u] -= hh * vv[u];
-                    wv2[u] -= hh * vv2[u];
+                    wv[u] -= hh[i][u] * vv[i][u];
+                    wv2[u] -= hh[i][u] * vv2[i][u];
                 }
-            }
             vstore<T, VEC>(w + r * J + c.jb, wv);
+            if (two) vstore<T, VEC>(w + r2 * J + c.jb, wv2);
+            if (LAST) {
 #pragma unroll
-            for (int u = 0; u < VEC; ++u) acc[u] += (double)wv[u] * (double)wv[u];
-            if (two) {
-                vstore<T, VEC>(w + r2 * J + c.jb, wv2);
-#pragma unroll
-                for (int u = 0; u < VEC; ++u) acc[u] += (double)wv2[u] * (double)wv2[u];
+                for (int u = 0; u < VEC; ++u) {
+                    acc[u] += (double)wv[u] * (double)wv[u];
+                    if (two) acc[u] += (double)wv2[u] * (double)wv2[u];
+                }
             }
         }
     }
-    const int64_t nblk = gridDim.x;
+    if (LAST) {
+        const int64_t nblk = gridDim.x;
 #pragma unroll
-    for (int u = 0; u < VEC; ++u) {
-        double sv = block_colsum(acc[u], c, red, CW);
-        if (c.ty == 0 && c.ok) partial[((int64_t)c.jb + u) * nblk + blockIdx.x] = sv;
+        for (int u = 0; u < VEC; ++u) {
+            double sv = block_colsum(acc[u], c, red, CW);
+            if (c.ty == 0 && c.ok) partial[((int64_t)c.jb + u) * nblk + blockIdx.x] = sv;
+        }
     }
 }
 
@@ -2297,30 +2311,45 @@ __global__ void __launch_bounds__(kBlock) k_colsq(const double* __restrict__ a, 
     }
 }
 
-// u = sum_{i<nb} y[i*J + j] V_i
-template <typename T, int VEC>
-__global__ void __launch_bounds__(kBlock) k_combine(const T* const* __restrict__ V, int nb, const double* __restrict__ yv,
+// u = sum_{i<NB} y[(c0 + i) J + j] V_{c0 + i}, added to u unless FIRST (chunks of an
+// NB-exact combination, as k_update)
+template <typename T, int VEC, int NB, bool FIRST>
+__global__ void __launch_bounds__(kBlock) k_combine(const T* const* __restrict__ V, int c0, const double* __restrict__ yv,
                                                     T* __restrict__ u, int64_t n, int J, int CW) {
     const ColMap c = colmap(CW, VEC, J);
     if (!c.ok) return;
+    T yy[NB][VEC];
+    const T* vp[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        vp[i] = V[c0 + i];
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) yy[i][q] = (T)yv[(int64_t)(c0 + i) * J + c.jb + q];
+    }
     const int64_t stride = (int64_t)gridDim.x * c.RG;
     for (int64_t r = (int64_t)blockIdx.x * c.RG + c.ty; r < n; r += 2 * stride) {
         const bool two = r + stride < n;
         const int64_t r2 = two ? r + stride : r;
-        T s[VEC], s2[VEC];
+        T s[VEC], s2[VEC], vv[NB][VEC], vv2[NB][VEC];
+        if (FIRST) {
 #pragma unroll
-        for (int q = 0; q < VEC; ++q) s[q] = s2[q] = 0;
-        for (int i = 0; i < nb; ++i) {
-            T vv[VEC], vv2[VEC];
-            vload<T, VEC>(vv, V[i] + r * J + c.jb);
-            vload<T, VEC>(vv2, V[i] + r2 * J + c.jb);
+            for (int q = 0; q < VEC; ++q) s[q] = s2[q] = 0;
+        } else {
+            vload<T, VEC>(s, u + r * J + c.jb);
+            vload<T, VEC>(s2, u + r2 * J + c.jb);
+        }
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            vload<T, VEC>(vv[i], vp[i] + r * J + c.jb);
+            vload<T, VEC>(vv2[i], vp[i] + r2 * J + c.jb);
+        }
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
 #pragma unroll
             for (int q = 0; q < VEC; ++q) {
-                const T yy = (T)yv[(int64_t)i * J + c.jb + q];
-                s[q] += yy * vv[q];
-                s2[q] += yy * vv2[q];
+                s[q] += yy[i][q] * vv[i][q];
+                s2[q] += yy[i][q] * vv2[i][q];
             }
-        }
         vstore<T, VEC>(u + r * J + c.jb, s);
         if (two) vstore<T, VEC>(u + r2 * J + c.jb, s2);
     }
@@ -3630,6 +3659,21 @@ mhd_status sync_copy(double* host, const double* dev, int J, hipStream_t st) {
     return MHD_OK;
 }
 
+// f(integral_constant<int, nb>) for nb = 1 ... 8
+template <typename F>
+mhd_status with_nb(int nb, F f) {
+    switch (nb) {
+        case 1: return f(std::integral_constant<int, 1>{});
+        case 2: return f(std::integral_constant<int, 2>{});
+        case 3: return f(std::integral_constant<int, 3>{});
+        case 4: return f(std::integral_constant<int, 4>{});
+        case 5: return f(std::integral_constant<int, 5>{});
+        case 6: return f(std::integral_constant<int, 6>{});
+        case 7: return f(std::integral_constant<int, 7>{});
+        default: return f(std::integral_constant<int, 8>{});
+    }
+}
+
 // out = a / s (per column) with 16-byte loads where the shape allows, else elementwise
 template <typename TI, typename TO>
 mhd_status launch_scale_cols(const TI* a, const double* s, TO* out, int64_t n, int J, hipStream_t st) {
@@ -3723,25 +3767,38 @@ mhd_status gmres_solve(DevShared& S, const double* b, double* x, int J, const mh
             for (int pass = 0; pass < passes; ++pass) {
                 double* hdst = pass ? hcol2 : G.hcol;
                 for (int c0 = 0; c0 <= k; c0 += 8) {
-                    int nb = std::min(8, k + 1 - c0);
+                    const int nb = std::min(8, k + 1 - c0);
                     rc = with_vec<T>(rs.VEC, [&](auto V) -> mhd_status {
-                        hipLaunchKernelGGL((k_dots<T, decltype(V)::value, 8>), rs.grid, dim3(kBlock), 0, st, Vd, c0, nb,
-                                           (const T*)w, n, J, rs.CW, G.partial);
-                        LAUNCH_CHECK();
-                        return MHD_OK;
+                        return with_nb(nb, [&](auto NBc) -> mhd_status {
+                            hipLaunchKernelGGL((k_dots<T, decltype(V)::value, decltype(NBc)::value>), rs.grid,
+                                               dim3(kBlock), 0, st, Vd, c0, (const T*)w, n, J, rs.CW, G.partial);
+                            LAUNCH_CHECK();
+                            return MHD_OK;
+                        });
                     });
                     if (rc) return rc;
                 }
                 hipLaunchKernelGGL(k_reduce, dim3(reduce_grid((int64_t)(k + 1) * J)), dim3(kBlock), 0, st, G.partial,
                                    rs.nblk, (int64_t)(k + 1) * J, hdst, 0);
                 LAUNCH_CHECK();
-                rc = with_vec<T>(rs.VEC, [&](auto V) -> mhd_status {
-                    hipLaunchKernelGGL((k_update<T, decltype(V)::value>), rs.grid, dim3(kBlock), 0, st, Vd, k + 1,
-                                       (const double*)hdst, w, n, J, rs.CW, G.partial);
-                    LAUNCH_CHECK();
-                    return MHD_OK;
-                });
-                if (rc) return rc;
+                for (int c0 = 0; c0 <= k; c0 += 8) {
+                    const int nb = std::min(8, k + 1 - c0);
+                    const bool last = c0 + nb == k + 1;
+                    rc = with_vec<T>(rs.VEC, [&](auto V) -> mhd_status {
+                        return with_nb(nb, [&](auto NBc) -> mhd_status {
+                            constexpr int VV = decltype(V)::value, NN = decltype(NBc)::value;
+                            if (last)
+                                hipLaunchKernelGGL((k_update<T, VV, NN, true>), rs.grid, dim3(kBlock), 0, st, Vd, c0,
+                                                   (const double*)hdst, w, n, J, rs.CW, G.partial);
+                            else
+                                hipLaunchKernelGGL((k_update<T, VV, NN, false>), rs.grid, dim3(kBlock), 0, st, Vd, c0,
+                                                   (const double*)hdst, w, n, J, rs.CW, G.partial);
+                            LAUNCH_CHECK();
+                            return MHD_OK;
+                        });
+                    });
+                    if (rc) return rc;
+                }
             }
             hipLaunchKernelGGL(k_reduce, dim3(reduce_grid(J)), dim3(kBlock), 0, st, G.partial, rs.nblk, (int64_t)J, hn,
                                1);
@@ -3771,13 +3828,23 @@ mhd_status gmres_solve(DevShared& S, const double* b, double* x, int J, const mh
         hipLaunchKernelGGL(k_lsq, dim3((J + 63) / 64), dim3(64), 0, st, G.H, G.g, G.y, kd, mres, J);
         LAUNCH_CHECK();
         T* u = (T*)G.wbuf;
-        rc = with_vec<T>(rs.VEC, [&](auto V) -> mhd_status {
-            hipLaunchKernelGGL((k_combine<T, decltype(V)::value>), rs.grid, dim3(kBlock), 0, st, keepz ? Zd : Vd, kd,
-                               (const double*)G.y, u, n, J, rs.CW);
-            LAUNCH_CHECK();
-            return MHD_OK;
-        });
-        if (rc) return rc;
+        for (int c0 = 0; c0 < kd; c0 += 8) {
+            const int nb = std::min(8, kd - c0);
+            rc = with_vec<T>(rs.VEC, [&](auto V) -> mhd_status {
+                return with_nb(nb, [&](auto NBc) -> mhd_status {
+                    constexpr int VV = decltype(V)::value, NN = decltype(NBc)::value;
+                    if (c0 == 0)
+                        hipLaunchKernelGGL((k_combine<T, VV, NN, true>), rs.grid, dim3(kBlock), 0, st, keepz ? Zd : Vd,
+                                           c0, (const double*)G.y, u, n, J, rs.CW);
+                    else
+                        hipLaunchKernelGGL((k_combine<T, VV, NN, false>), rs.grid, dim3(kBlock), 0, st, keepz ? Zd : Vd,
+                                           c0, (const double*)G.y, u, n, J, rs.CW);
+                    LAUNCH_CHECK();
+                    return MHD_OK;
+                });
+            });
+            if (rc) return rc;
+        }
         const T* dx = u;
         if (!keepz) {
             if ((rc = ops.precond(u, (T*)G.zbuf, sweeps, omega))) return rc;
