@@ -72,12 +72,13 @@ def traffic_from_profiles(J, N, plan):
     if not os.path.exists(path):
         return None
     with open(path) as f:
-        rec = json.load(f)
-    if rec.get("source_hash") != source_hash() or rec.get("J") != J or rec.get("N") != N:
+        prof = json.load(f)
+    if prof.get("source_hash") != source_hash() or prof.get("J") != J or prof.get("N") != N or plan is None:
         return None
-    if plan is None or any(rec.get("plan", {}).get(k) != plan.get(k) for k in ("vec", "group", "deep", "tile", "waves")):
-        return None
-    return rec.get("bytes_per_launch")
+    for rec in prof.get("records", []):   # one record per profiled launch plan
+        if all(rec.get("plan", {}).get(k) == plan.get(k) for k in ("vec", "group", "deep", "tile", "waves")):
+            return rec.get("bytes_per_launch")
+    return None
 
 
 def cpu_baseline(N, J, seconds_hint=30.0):
@@ -263,6 +264,15 @@ def headline(args, L, wl, torch):
     pb = wl.cavity(J=args.J, s=0.1, dt=0.01)
     mesh = Mesh(L.MHD_MESH_UNIT_SQUARE, args.N)
     plans = tuned_plans(L, wl, mesh, args.J, prec)
+    if args.plan:
+        # study option: pin the SpMM plan after tuning (the table is process-wide)
+        from paper_2108_05110_amd.ensemble import to_dev
+        vec, group, deep, tile, waves = (int(v) for v in args.plan.split(","))
+        A = L.mhd_ens_shared_create(mesh.handle, args.J, 8)
+        L.mhd_ens_set_plan(A, args.J, prec, L.TUNE_SADDLE, vec, group, deep, tile, waves)
+        L.mhd_ens_shared_free(A)
+        plans["saddle"] = {"word": 4 if prec == L.MHD_FP32_IR else 8, "vec": vec, "group": group, "deep": deep,
+                           "tile": tile, "waves": waves, "us": None, "candidates": 0}
     # timed region: the graph-captured step (fixed schedule) or the adaptive step
     stp = Stepper(mesh, pb, opts=opts, time_dependent_data=False, graph=graph)
     for _ in range(args.warmup):
@@ -513,7 +523,8 @@ def main():
     ap.add_argument("--separate-steps", type=int, default=1)
     ap.add_argument("--no-separate", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--plan", default="", help="spmm workload: pinned SpMM plan vec,group,deep,tile,waves")
+    ap.add_argument("--plan", default="", help="pinned SpMM plan vec,group,deep,tile,waves (spmm workload; study "
+                    "option for the step)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "

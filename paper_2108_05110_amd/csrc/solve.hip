@@ -1301,12 +1301,14 @@ __global__ void __launch_bounds__(kBlock) k_ell_scatter(const float* __restrict_
 // are broadcast with ds_bpermute.  Rows of at most LPR entries.
 // MODE 0: y = A x ; 1: y += A x ; 2: y = b - A x ; 3: y = x + w dinv (b - A x) ;
 // 4: y = w dinv b ; 5: the two first Jacobi sweeps from a zero guess,
-// y = x1 + w dinv (b - A x1) with x1 = w dinv b formed on the fly (x unused).
+// y = x1 + w dinv (b - A x1) with x1 = w dinv b formed on the fly (x unused);
+// 6: the last sweep of MODE 3 written as the Schur part of the preconditioner,
+// y = -(x + w dinv (b - A x)), and y = b on row pin (an identity row).
 template <typename T, int MODE, int LPR>
 __global__ void __launch_bounds__(kBlock) k_mg(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                                                const T* __restrict__ val, const T* __restrict__ dinv,
                                                const T* __restrict__ x, const T* __restrict__ b, T* __restrict__ y,
-                                               int n, int J, T omega) {
+                                               int n, int J, T omega, int pin) {
     constexpr int V = 256 / (LPR * (int)sizeof(T));
     constexpr int RPW = 64 / LPR;   // rows per wavefront
     const int lane = threadIdx.x & 63;
@@ -1373,11 +1375,15 @@ __global__ void __launch_bounds__(kBlock) k_mg(const int32_t* __restrict__ rp, c
         if (MODE == 2) {
 #pragma unroll
             for (int q = 0; q < V; ++q) out[q] = bv[q] - s[q];
-        } else if (MODE == 3) {
+        } else if (MODE == 3 || MODE == 6) {
             T xv[V];
             vload<T, V>(xv, x + o);
 #pragma unroll
             for (int q = 0; q < V; ++q) out[q] = xv[q] + omega * d * (bv[q] - s[q]);
+            if (MODE == 6) {
+#pragma unroll
+                for (int q = 0; q < V; ++q) out[q] = r == pin ? bv[q] : -out[q];
+            }
         } else if (MODE == 4) {
 #pragma unroll
             for (int q = 0; q < V; ++q) out[q] = omega * d * bv[q];
@@ -3531,17 +3537,22 @@ struct Ops {
         return MHD_OK;
     }
 
+    // the packed-row kernels apply (J a multiple of 256 bytes of members, rows of <= 32 entries)
+    bool packed(const DevCSR<double>& c) const { return J % (256 / (int)sizeof(T)) == 0 && c.max_row <= 32; }
+
     template <int MODE>
-    mhd_status csr(const DevCSR<double>& c, const T* dinv, const T* x, const T* b, T* y, T omega) {
+    mhd_status csr(const DevCSR<double>& c, const T* dinv, const T* x, const T* b, T* y, T omega, int pin = -1) {
         constexpr int MJ = 256 / (int)sizeof(T);
         if (J % MJ == 0 && c.max_row <= 16) {
             const int64_t waves = (c.nrows + 3) / 4;
             hipLaunchKernelGGL((k_mg<T, MODE, 16>), dim3((unsigned)((waves + 3) / 4), J / MJ), dim3(kBlock), 0, st,
-                               c.rowptr, c.col, Vals<T>::csr(c), dinv, x, b, y, (int)c.nrows, J, omega);
+                               c.rowptr, c.col, Vals<T>::csr(c), dinv, x, b, y, (int)c.nrows, J, omega, pin);
         } else if (J % MJ == 0 && c.max_row <= 32) {
             const int64_t waves = (c.nrows + 1) / 2;
             hipLaunchKernelGGL((k_mg<T, MODE, 32>), dim3((unsigned)((waves + 3) / 4), J / MJ), dim3(kBlock), 0, st,
-                               c.rowptr, c.col, Vals<T>::csr(c), dinv, x, b, y, (int)c.nrows, J, omega);
+                               c.rowptr, c.col, Vals<T>::csr(c), dinv, x, b, y, (int)c.nrows, J, omega, pin);
+        } else if constexpr (MODE == 6) {
+            return MHD_EINVAL;   // callers check packed() first
         } else {
             hipLaunchKernelGGL((k_csr<T, MODE>), dim3(grid_for(c.nrows, JP)), dim3(kBlock), 0, st, c.rowptr, c.col,
                                Vals<T>::csr(c), dinv, x, b, y, c.nrows, J, JP, omega);
@@ -3553,7 +3564,7 @@ struct Ops {
     // One V(2,2)-cycle with damped Jacobi smoothing on level l for L_l x = b.
     // Uses the level's buffers x, x2, r and the next level's b and x.  Returns
     // the buffer holding the result in *out.
-    mhd_status vcycle(int l, const T* b, T** out) {
+    mhd_status vcycle(int l, const T* b, T** out, T* schur = nullptr, int pin = -1) {
         DevMesh& m = *S.mesh;
         const DevLevel& Lv = m.levels[l];
         T* x = (T*)S.gw.mg_x[l];
@@ -3583,6 +3594,11 @@ struct Ops {
         if ((rc = vcycle(l + 1, bc, &xc))) return rc;
         if ((rc = csr<1>(Lv.P, dinv, xc, nullptr, x2, omega))) return rc; // x2 += P xc
         if ((rc = csr<3>(Lv.L, dinv, x2, b, x, omega))) return rc;        // post-smoothing
+        if (schur) {   // the last sweep writes the Schur part z_p directly
+            if ((rc = csr<6>(Lv.L, dinv, x, b, schur, omega, pin))) return rc;
+            *out = schur;
+            return MHD_OK;
+        }
         if ((rc = csr<3>(Lv.L, dinv, x, b, x2, omega))) return rc;
         *out = x2;
         return MHD_OK;
@@ -3596,10 +3612,14 @@ struct Ops {
         T* zp = z + off;
         mhd_status rc;
         T* xmg = nullptr;
-        if ((rc = vcycle(0, vp, &xmg))) return rc;
-        hipLaunchKernelGGL((k_schur<T>), dim3(grid_for(m.nP1, JP)), dim3(kBlock), 0, st, xmg, vp, m.pin, zp, m.nP1,
-                           J, JP);
-        LAUNCH_CHECK();
+        if (m.levels.size() > 1 && packed(m.levels[0].L)) {
+            if ((rc = vcycle(0, vp, &xmg, zp, m.pin))) return rc;   // z_p written by the last smoothing sweep
+        } else {
+            if ((rc = vcycle(0, vp, &xmg))) return rc;
+            hipLaunchKernelGGL((k_schur<T>), dim3(grid_for(m.nP1, JP)), dim3(kBlock), 0, st, xmg, vp, m.pin, zp,
+                               m.nP1, J, JP);
+            LAUNCH_CHECK();
+        }
         const T omega = (T)omega_d;
         T* t = (T*)S.gw.tbuf;
         // ping-pong between z and z2buf, starting so that the last sweep writes z
