@@ -274,9 +274,20 @@ mhd_status mhd_ens_spmm(mhd_shared A, const void* x, void* y, int J, int precisi
  *     waves = wavefronts per workgroup: 4 or 8;
  *     deep  = 3: the tile's CSR entries are staged into LDS as well, so a
  *             row is computed from LDS only (deep = 0: entries by scalar
- *             loads from memory).
+ *             loads from memory);
+ *   row-per-lane tiles (FP32 SpMM and Jacobi sweeps, not the FP64 residual):
+ *     deep  = 6: each workgroup stages the values of M members of every node
+ *             a rectangle of rows reads, then every lane computes one row,
+ *             reading its entries as packed (LDS offset, value) records;
+ *     tile  = tx * 100 + ty, the rectangle in half-steps (1616, 3208 or
+ *             1608) with M = 16 members per workgroup (J a multiple of 16),
+ *             or the same plus 10000 (11616, 13208, 11608) with M = 8 (J a
+ *             multiple of 8); vec is reported as 4, group and waves as 0.
  * Every candidate performs the same arithmetic in the same order, so results
- * do not depend on the choice.
+ * do not depend on the choice.  Tuning a handle builds the tilings and packed
+ * entry arrays of every candidate on first use (device memory held until the
+ * mesh or handle is freed); assemblies refresh the A values of the row-per-lane
+ * tilings a plan uses.
  *   out:   host array of cap entries, or NULL; receives every timed candidate
  *   count: host, or NULL; receives the number of entries written
  * Synchronises the stream. */
@@ -304,7 +315,9 @@ mhd_status mhd_ens_autotune(mhd_shared A, int J, int precision, mhd_tune_entry* 
  *               selects the generic kernels (any J);
  *   tile, waves: tile 0, or 8, 12, 16 with waves 4 or 8 for the LDS-staged
  *               kernels, with deep 0 or 3 (where the tiling is not usable,
- *               e.g. an unaligned block, the gather kernels run instead).
+ *               e.g. an unaligned block, the gather kernels run instead);
+ *               with deep 6 a row-per-lane tile code as in mhd_ens_autotune
+ *               (FP32 SpMM and Jacobi operators only; waves ignored).
  * Graphs captured earlier keep the kernels they hold.  MHD_EINVAL for a shape
  * this mesh, J or device does not admit.  Builds the tiling on first use
  * (synchronous host-to-device copies). */
