@@ -956,7 +956,7 @@ __global__ void __launch_bounds__(kBlock) k_velo_h(const int32_t* __restrict__ r
             if (store) vstore<T, V>(t + o, acc);
 #pragma unroll
             for (int q = 0; q < V; ++q) acc[q] *= dw;
-            if (store) vstore<T, V>(zo + o, acc);
+            if (store && zo) vstore<T, V>(zo + o, acc);   // no zo: the next kernel forms w D^-1 t itself
         } else {
 #pragma unroll
             for (int q = 0; q < V; ++q) acc[q] = 0;
@@ -968,6 +968,85 @@ __global__ void __launch_bounds__(kBlock) k_velo_h(const int32_t* __restrict__ r
             for (int q = 0; q < V; ++q) acc[q] = zv[q] + dw * (tv[q] - acc[q]);
             if (store) vstore<T, V>(zo + o, acc);
         }
+    }
+}
+
+// a * b rounded on its own: the product carries no contraction flag, so it is
+// never fused into a neighbouring add
+template <typename T>
+__device__ __forceinline__ T mul_rn(T a, T b) {
+#pragma clang fp contract(off)
+    return a * b;
+}
+
+// acc[q] += sum_t a_t (x[off_t + lane_off + q] s_t) with a per-entry scale s_t
+// (held in R.v1 by the entry's lane), the operations of forming the scaled
+// vector first and then the product
+template <typename T, int V>
+__device__ __forceinline__ void pair_row_scaled(const HalfRow<T, false>& R, int n, int half,
+                                                __amdgpu_buffer_rsrc_t xr, unsigned lane_off, T (&acc)[V]) {
+    const int hb = half << 7;
+    for (int t = 0; t < n; t += 8) {
+        T v[8][V];
+        T a[8], sc[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int addr = hb + ((t + i) << 2);
+            const unsigned off = (unsigned)__builtin_amdgcn_ds_bpermute(addr, (int)R.off);
+            bload<T, V>(v[i], xr, off + lane_off);
+            a[i] = bperm_addr(R.v0, addr);
+            sc[i] = bperm_addr(R.v1, addr);
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+#pragma unroll
+            for (int q = 0; q < V; ++q) {
+                const T zq = mul_rn(v[i][q], sc[i]);
+                acc[q] += a[i] * zq;
+            }
+        }
+    }
+}
+
+// The second velocity Jacobi sweep straight from t, paired rows: with
+// z1 = w D^-1 t formed on the fly for the row and its neighbours,
+// zo = z1 + w D^-1 (t - A z1), the same operations as the first sweep's z1
+// store followed by k_velo_h (so the first sweep need not store z1).
+template <typename T, int G>
+__global__ void __launch_bounds__(kBlock) k_velo_h2(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                    const T* __restrict__ val, const T* __restrict__ dinvA,
+                                                    const T* __restrict__ t, T* __restrict__ zo, int nP2, int J,
+                                                    T omega) {
+    constexpr int V = 16 / (int)sizeof(T);
+    const PairLanes L = pair_lanes<V, G>(nP2, 0, 1 << 30);
+    const unsigned W = sizeof(T);
+    const __amdgpu_buffer_rsrc_t tr = make_rsrc(t, (unsigned)(2 * (int64_t)nP2 * J * W));
+    const unsigned lane_off = ((unsigned)L.c * J + L.j) * W;
+    for (int s = 0; s < G / 2; ++s) {
+        const int ua = L.u0 + s, ub = L.u0 + s + G / 2;
+        if (ua >= L.uend) return;
+        const bool has_b = ub < L.uend;
+        const int i = (L.half && has_b) ? ub : ua;
+        const bool store = !L.half || has_b;
+        const T dw = omega * dinvA[i];
+        const int64_t o = (2 * (int64_t)i + L.c) * J + L.j;
+        HalfRow<T, false> R = half_row<T, false>(col, val, rp[i], rp[i + 1], 2u * J * W, 0);
+        {   // the entry's scale w D^-1 of its column, in the unused second value
+            const int h = threadIdx.x & 31;
+            R.v1 = h < R.cnt ? omega * dinvA[col[rp[i] + h]] : (T)0;
+        }
+        const int n = max(__builtin_amdgcn_readlane(R.cnt, 0), __builtin_amdgcn_readlane(R.cnt, 32));
+        T acc[V], tv[V];
+        vload<T, V>(tv, t + o);
+#pragma unroll
+        for (int q = 0; q < V; ++q) acc[q] = 0;
+        pair_row_scaled<T, V>(R, n, L.half, tr, lane_off, acc);
+#pragma unroll
+        for (int q = 0; q < V; ++q) {
+            const T zv = mul_rn(tv[q], dw);
+            acc[q] = zv + dw * (tv[q] - acc[q]);
+        }
+        if (store) vstore<T, V>(zo + o, acc);
     }
 }
 
@@ -3626,11 +3705,30 @@ struct Ops {
         T* za = (sweeps % 2) ? z : (T*)S.gw.z2buf;
         T* zb = (sweeps % 2) ? (T*)S.gw.z2buf : z;
         const bool aligned = (((uintptr_t)v | (uintptr_t)z | (uintptr_t)t | (uintptr_t)zb) % 16) == 0;
-        if ((rc = launch_velo_plan<T, true>(align_plan(p_first, aligned), S, v, zp, t, nullptr, za, J, st, omega)))
+        const NodePlan pf = align_plan(p_first, aligned), ps = align_plan(p_sweep, aligned);
+        int s = 1;
+        if (sweeps >= 2 && pf.deep == 2 && ps.deep == 2 && pair_ok(m, J, sizeof(T))) {
+            // first sweep stores t only; the second forms z1 = w D^-1 t on the fly
+            if ((rc = launch_velo_plan<T, true>(pf, S, v, zp, t, nullptr, nullptr, J, st, omega))) return rc;
+            T* z2 = ((sweeps - 2) % 2 == 0) ? z : (T*)S.gw.z2buf;   // so that the last sweep writes z
+            rc = with_gp(ps.g, [&](auto Gc) -> mhd_status {
+                constexpr int GG = decltype(Gc)::value;
+                const int w = (m.nP2 + GG - 1) / GG;
+                hipLaunchKernelGGL((k_velo_h2<T, GG>), dim3((unsigned)((w + 3) / 4), J / (256 / (int)sizeof(T))),
+                                   dim3(kBlock), 0, st, m.A_rowptr, m.A_col, Vals<T>::A(S), Vals<T>::dA(S),
+                                   (const T*)t, z2, m.nP2, J, omega);
+                LAUNCH_CHECK();
+                return MHD_OK;
+            });
+            if (rc) return rc;
+            za = z2;
+            zb = (z2 == z) ? (T*)S.gw.z2buf : z;
+            s = 2;
+        } else if ((rc = launch_velo_plan<T, true>(pf, S, v, zp, t, nullptr, za, J, st, omega))) {
             return rc;
-        for (int s = 1; s < sweeps; ++s) {
-            if ((rc = launch_velo_plan<T, false>(align_plan(p_sweep, aligned), S, nullptr, nullptr, t, za, zb, J, st,
-                                                 omega)))
+        }
+        for (; s < sweeps; ++s) {
+            if ((rc = launch_velo_plan<T, false>(ps, S, nullptr, nullptr, t, za, zb, J, st, omega)))
                 return rc;
             std::swap(za, zb);
         }
