@@ -2233,6 +2233,27 @@ __device__ __forceinline__ void vstore(T* p, const T (&v)[VEC]) {
     *reinterpret_cast<V*>(p) = *reinterpret_cast<const V*>(v);
 }
 
+// vload through a global-address-space pointer: for block pointers read from a
+// pointer array, which the compiler would otherwise load as flat accesses
+// Compiler-only ordering point (emits no code) for a software-pipelined row
+// loop: the registers of the row about to be used are marked as produced here,
+// so the work on them cannot move above the next row's loads issued before this
+// point, and those loads cannot move below it (memory clobber).
+template <typename T, int VEC>
+__device__ __forceinline__ void settle(T (&v)[VEC]) {
+#pragma unroll
+    for (int u = 0; u < VEC; ++u) asm volatile("" : "+v"(v[u])::"memory");
+}
+
+template <typename T, int VEC>
+__device__ __forceinline__ void gload(T (&v)[VEC], const T* p) {
+    using GV = T __attribute__((ext_vector_type(VEC)));
+    using GP = const GV __attribute__((address_space(1)))*;
+    const GV x = *(GP)(p);
+#pragma unroll
+    for (int u = 0; u < VEC; ++u) v[u] = x[u];
+}
+
 struct ColMap {
     int tx, ty, RG, jb;
     bool ok;
@@ -2260,53 +2281,98 @@ __device__ __forceinline__ double block_colsum(double v, const ColMap& c, double
     return s;
 }
 
+// Column sums of NV values per thread at once: value q of thread (tx, ty) is
+// summed over the RG row groups in row-group order (as block_colsum) and
+// out(q, tx, sum) is called once for every q and every tx < CW whose columns
+// exist. Up to kColsumBatch values share one pass through LDS (red holds
+// kColsumBatch * kBlock doubles), and the sums of a pass are spread over the
+// whole block instead of the threads of row group 0.
+constexpr int kColsumBatch = 8;
+
+template <int NV, int VEC, typename Out>
+__device__ __forceinline__ void block_colsums(const double (&v)[NV], const ColMap& c, double* red, int CW, int J,
+                                              Out out) {
+    constexpr int K = NV < kColsumBatch ? NV : kColsumBatch;
+#pragma unroll
+    for (int q0 = 0; q0 < NV; q0 += K) {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if (q0 + k < NV) red[k * kBlock + threadIdx.x] = v[q0 + k];
+        __syncthreads();
+        for (int o = threadIdx.x; o < K * CW; o += kBlock) {
+            const int k = o / CW, tx = o - k * CW;
+            if (q0 + k < NV && ((int)blockIdx.y * CW + tx) * VEC < J) {
+                double sum = 0.0;
+                for (int g = 0; g < c.RG; ++g) sum += red[k * kBlock + g * CW + tx];
+                out(q0 + k, tx, sum);
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // partial[((c0 + i) * J + j) * nblk + block] = sum over rows of V_i[r, j] * w[r, j], i < NB.
 // NB is the exact count, so all loads of an iteration are issued before the products.
 template <typename T, int VEC, int NB>
 __global__ void __launch_bounds__(kBlock) k_dots(const T* const* __restrict__ V, int c0, const T* __restrict__ w,
                                                  int64_t n, int J, int CW, double* __restrict__ partial) {
-    __shared__ double red[kBlock];
+    __shared__ double red[kColsumBatch * kBlock];
     const ColMap c = colmap(CW, VEC, J);
-    double acc[NB][VEC];
+    double acc[NB * VEC];
 #pragma unroll
-    for (int i = 0; i < NB; ++i)
-#pragma unroll
-        for (int u = 0; u < VEC; ++u) acc[i][u] = 0.0;
-    if (c.ok) {
+    for (int q = 0; q < NB * VEC; ++q) acc[q] = 0.0;
+    if (c.ok && n > 0) {
         const T* vp[NB];
 #pragma unroll
         for (int i = 0; i < NB; ++i) vp[i] = V[c0 + i];
-        // two rows per iteration (r and r + stride) for more loads in flight
+        // Two register sets in turn: the next row's loads are issued before the
+        // current row's products. The trip count is the block's (uniform), rows
+        // past the end are re-reads of row n - 1 that add nothing.
         const int64_t stride = (int64_t)gridDim.x * c.RG;
-        for (int64_t r = (int64_t)blockIdx.x * c.RG + c.ty; r < n; r += 2 * stride) {
-            const int64_t r2 = r + stride < n ? r + stride : r;
-            const double g2 = r + stride < n ? 1.0 : 0.0;
-            T wv[VEC], wv2[VEC], vv[NB][VEC], vv2[NB][VEC];
-            vload<T, VEC>(wv, w + r * J + c.jb);
-            vload<T, VEC>(wv2, w + r2 * J + c.jb);
+        const int64_t r0 = (int64_t)blockIdx.x * c.RG;
+        const int64_t trips = r0 < n ? (n - r0 + stride - 1) / stride : 0;
+        int64_t r = r0 + c.ty;
+        T wa[VEC], va[NB][VEC], wb[VEC], vb[NB][VEC];
+        auto load = [&](int64_t rr, T (&w_)[VEC], T (&v_)[NB][VEC]) {
+            const int64_t o = (rr < n ? rr : n - 1) * J + c.jb;
+            gload<T, VEC>(w_, w + o);
 #pragma unroll
-            for (int i = 0; i < NB; ++i) {
-                vload<T, VEC>(vv[i], vp[i] + r * J + c.jb);
-                vload<T, VEC>(vv2[i], vp[i] + r2 * J + c.jb);
-            }
+            for (int i = 0; i < NB; ++i) gload<T, VEC>(v_[i], vp[i] + o);
+        };
+        auto hold = [&](T (&w_)[VEC], T (&v_)[NB][VEC]) {
+            settle<T, VEC>(w_);
+#pragma unroll
+            for (int i = 0; i < NB; ++i) settle<T, VEC>(v_[i]);
+        };
+        auto add = [&](int64_t rr, const T (&w_)[VEC], const T (&v_)[NB][VEC]) {
+            const bool live = rr < n;
+            T wz[VEC];
+#pragma unroll
+            for (int u = 0; u < VEC; ++u) wz[u] = live ? w_[u] : T(0);
 #pragma unroll
             for (int i = 0; i < NB; ++i)
 #pragma unroll
-                for (int u = 0; u < VEC; ++u) {
-                    acc[i][u] += (double)vv[i][u] * (double)wv[u];
-                    acc[i][u] += g2 * ((double)vv2[i][u] * (double)wv2[u]);
-                }
+                for (int u = 0; u < VEC; ++u) acc[i * VEC + u] += (double)v_[i][u] * (double)wz[u];
+        };
+        if (trips > 0) load(r, wa, va);
+        for (int64_t k = 0; k < trips; k += 2) {
+            load(r + stride, wb, vb);
+            hold(wa, va);
+            add(r, wa, va);
+            r += stride;
+            load(r + stride, wa, va);
+            hold(wb, vb);
+            add(r, wb, vb);
+            r += stride;
         }
     }
     const int64_t nblk = gridDim.x;
-#pragma unroll
-    for (int i = 0; i < NB; ++i) {
-#pragma unroll
-        for (int u = 0; u < VEC; ++u) {
-            double sv = block_colsum(acc[i][u], c, red, CW);
-            if (c.ty == 0 && c.ok) partial[((int64_t)(c0 + i) * J + c.jb + u) * nblk + blockIdx.x] = sv;
-        }
-    }
+    block_colsums<NB * VEC, VEC>(acc, c, red, CW, J,
+                                 [&](int q, int tx, double sum) {
+                                     const int i = q / VEC, u = q - i * VEC;
+                                     const int64_t j = ((int64_t)blockIdx.y * CW + tx) * VEC + u;
+                                     partial[((int64_t)(c0 + i) * J + j) * nblk + blockIdx.x] = sum;
+                                 });
 }
 
 // w -= sum_{i<NB} h[(c0 + i) J + j] V_{c0 + i}; with LAST also partial[j * nblk +
@@ -2317,7 +2383,7 @@ template <typename T, int VEC, int NB, bool LAST>
 __global__ void __launch_bounds__(kBlock) k_update(const T* const* __restrict__ V, int c0, const double* __restrict__ h,
                                                    T* __restrict__ w, int64_t n, int J, int CW,
                                                    double* __restrict__ partial) {
-    __shared__ double red[kBlock];
+    __shared__ double red[kColsumBatch * kBlock];
     const ColMap c = colmap(CW, VEC, J);
     double acc[VEC];
 #pragma unroll
@@ -2331,44 +2397,57 @@ __global__ void __launch_bounds__(kBlock) k_update(const T* const* __restrict__ 
 #pragma unroll
             for (int u = 0; u < VEC; ++u) hh[i][u] = (T)h[(int64_t)(c0 + i) * J + c.jb + u];
         }
-        // two rows per iteration (r and r + stride; the second only if it exists)
+        // Two register sets in turn: the next row's loads are issued before the
+        // current row is updated. The trip count is the block's (uniform), rows
+        // past the end are re-reads of row n - 1 that store and add nothing.
         const int64_t stride = (int64_t)gridDim.x * c.RG;
-        for (int64_t r = (int64_t)blockIdx.x * c.RG + c.ty; r < n; r += 2 * stride) {
-            const bool two = r + stride < n;
-            const int64_t r2 = two ? r + stride : r;
-            T wv[VEC], wv2[VEC], vv[NB][VEC], vv2[NB][VEC];
-            vload<T, VEC>(wv, w + r * J + c.jb);
-            vload<T, VEC>(wv2, w + r2 * J + c.jb);
+        const int64_t r0 = (int64_t)blockIdx.x * c.RG;
+        const int64_t trips = r0 < n ? (n - r0 + stride - 1) / stride : 0;
+        int64_t r = r0 + c.ty;
+        T wa[VEC], va[NB][VEC], wb[VEC], vb[NB][VEC];
+        auto load = [&](int64_t rr, T (&w_)[VEC], T (&v_)[NB][VEC]) {
+            const int64_t o = (rr < n ? rr : n - 1) * J + c.jb;
+            gload<T, VEC>(w_, w + o);
 #pragma unroll
-            for (int i = 0; i < NB; ++i) {
-                vload<T, VEC>(vv[i], vp[i] + r * J + c.jb);
-                vload<T, VEC>(vv2[i], vp[i] + r2 * J + c.jb);
-            }
+            for (int i = 0; i < NB; ++i) gload<T, VEC>(v_[i], vp[i] + o);
+        };
+        auto hold = [&](T (&w_)[VEC], T (&v_)[NB][VEC]) {
+            settle<T, VEC>(w_);
+#pragma unroll
+            for (int i = 0; i < NB; ++i) settle<T, VEC>(v_[i]);
+        };
+        auto update = [&](int64_t rr, T (&w_)[VEC], const T (&v_)[NB][VEC]) {
+            const bool live = rr < n;
 #pragma unroll
             for (int i = 0; i < NB; ++i)
 #pragma unroll
-                for (int u = 0; u < VEC; ++u) {
-                    wv[u] -= hh[i][u] * vv[i][u];
-                    wv2[u] -= hh[i][u] * vv2[i][u];
-                }
-            vstore<T, VEC>(w + r * J + c.jb, wv);
-            if (two) vstore<T, VEC>(w + r2 * J + c.jb, wv2);
+                for (int u = 0; u < VEC; ++u) w_[u] -= hh[i][u] * v_[i][u];
+            if (live) vstore<T, VEC>(w + rr * J + c.jb, w_);
             if (LAST) {
 #pragma unroll
                 for (int u = 0; u < VEC; ++u) {
-                    acc[u] += (double)wv[u] * (double)wv[u];
-                    if (two) acc[u] += (double)wv2[u] * (double)wv2[u];
+                    const T wl = live ? w_[u] : T(0);
+                    acc[u] += (double)wl * (double)wl;
                 }
             }
+        };
+        if (trips > 0) load(r, wa, va);
+        for (int64_t k = 0; k < trips; k += 2) {
+            load(r + stride, wb, vb);
+            hold(wa, va);
+            update(r, wa, va);
+            r += stride;
+            load(r + stride, wa, va);
+            hold(wb, vb);
+            update(r, wb, vb);
+            r += stride;
         }
     }
     if (LAST) {
         const int64_t nblk = gridDim.x;
-#pragma unroll
-        for (int u = 0; u < VEC; ++u) {
-            double sv = block_colsum(acc[u], c, red, CW);
-            if (c.ty == 0 && c.ok) partial[((int64_t)c.jb + u) * nblk + blockIdx.x] = sv;
-        }
+        block_colsums<VEC, VEC>(acc, c, red, CW, J, [&](int u, int tx, double sum) {
+            partial[(((int64_t)blockIdx.y * CW + tx) * VEC + u) * nblk + blockIdx.x] = sum;
+        });
     }
 }
 
@@ -2376,7 +2455,7 @@ __global__ void __launch_bounds__(kBlock) k_update(const T* const* __restrict__ 
 template <int VEC>
 __global__ void __launch_bounds__(kBlock) k_colsq(const double* __restrict__ a, int64_t n, int J, int CW,
                                                   double* __restrict__ partial) {
-    __shared__ double red[kBlock];
+    __shared__ double red[kColsumBatch * kBlock];
     const ColMap c = colmap(CW, VEC, J);
     double acc[VEC];
 #pragma unroll
@@ -2389,11 +2468,9 @@ __global__ void __launch_bounds__(kBlock) k_colsq(const double* __restrict__ a, 
             for (int u = 0; u < VEC; ++u) acc[u] += v[u] * v[u];
         }
     const int64_t nblk = gridDim.x;
-#pragma unroll
-    for (int u = 0; u < VEC; ++u) {
-        double sv = block_colsum(acc[u], c, red, CW);
-        if (c.ty == 0 && c.ok) partial[((int64_t)c.jb + u) * nblk + blockIdx.x] = sv;
-    }
+    block_colsums<VEC, VEC>(acc, c, red, CW, J, [&](int u, int tx, double sum) {
+        partial[(((int64_t)blockIdx.y * CW + tx) * VEC + u) * nblk + blockIdx.x] = sum;
+    });
 }
 
 // u = sum_{i<NB} y[(c0 + i) J + j] V_{c0 + i}, added to u unless FIRST (chunks of an
@@ -2411,32 +2488,47 @@ __global__ void __launch_bounds__(kBlock) k_combine(const T* const* __restrict__
 #pragma unroll
         for (int q = 0; q < VEC; ++q) yy[i][q] = (T)yv[(int64_t)(c0 + i) * J + c.jb + q];
     }
+    // Two register sets in turn: the next row's loads are issued before the
+    // current row is combined. The trip count is the block's (uniform), rows past
+    // the end are re-reads of row n - 1 that store nothing.
     const int64_t stride = (int64_t)gridDim.x * c.RG;
-    for (int64_t r = (int64_t)blockIdx.x * c.RG + c.ty; r < n; r += 2 * stride) {
-        const bool two = r + stride < n;
-        const int64_t r2 = two ? r + stride : r;
-        T s[VEC], s2[VEC], vv[NB][VEC], vv2[NB][VEC];
+    const int64_t r0 = (int64_t)blockIdx.x * c.RG;
+    const int64_t trips = r0 < n ? (n - r0 + stride - 1) / stride : 0;
+    int64_t r = r0 + c.ty;
+    T sa[VEC], va[NB][VEC], sb[VEC], vb[NB][VEC];
+    auto load = [&](int64_t rr, T (&s_)[VEC], T (&v_)[NB][VEC]) {
+        const int64_t o = (rr < n ? rr : n - 1) * J + c.jb;
         if (FIRST) {
 #pragma unroll
-            for (int q = 0; q < VEC; ++q) s[q] = s2[q] = 0;
+            for (int q = 0; q < VEC; ++q) s_[q] = 0;
         } else {
-            vload<T, VEC>(s, u + r * J + c.jb);
-            vload<T, VEC>(s2, u + r2 * J + c.jb);
+            gload<T, VEC>(s_, u + o);
         }
 #pragma unroll
-        for (int i = 0; i < NB; ++i) {
-            vload<T, VEC>(vv[i], vp[i] + r * J + c.jb);
-            vload<T, VEC>(vv2[i], vp[i] + r2 * J + c.jb);
-        }
+        for (int i = 0; i < NB; ++i) gload<T, VEC>(v_[i], vp[i] + o);
+    };
+    auto hold = [&](T (&s_)[VEC], T (&v_)[NB][VEC]) {
+        settle<T, VEC>(s_);
+#pragma unroll
+        for (int i = 0; i < NB; ++i) settle<T, VEC>(v_[i]);
+    };
+    auto combine = [&](int64_t rr, T (&s_)[VEC], const T (&v_)[NB][VEC]) {
 #pragma unroll
         for (int i = 0; i < NB; ++i)
 #pragma unroll
-            for (int q = 0; q < VEC; ++q) {
-                s[q] += yy[i][q] * vv[i][q];
-                s2[q] += yy[i][q] * vv2[i][q];
-            }
-        vstore<T, VEC>(u + r * J + c.jb, s);
-        if (two) vstore<T, VEC>(u + r2 * J + c.jb, s2);
+            for (int q = 0; q < VEC; ++q) s_[q] += yy[i][q] * v_[i][q];
+        if (rr < n) vstore<T, VEC>(u + rr * J + c.jb, s_);
+    };
+    if (trips > 0) load(r, sa, va);
+    for (int64_t k = 0; k < trips; k += 2) {
+        load(r + stride, sb, vb);
+        hold(sa, va);
+        combine(r, sa, va);
+        r += stride;
+        load(r + stride, sa, va);
+        hold(sb, vb);
+        combine(r, sb, vb);
+        r += stride;
     }
 }
 
