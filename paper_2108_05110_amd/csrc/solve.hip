@@ -1140,12 +1140,12 @@ __device__ __forceinline__ void ell_stage(unsigned char* lds, const int32_t* __r
     }
 }
 
-// acc[c][m] += a * x[c][m] over entries of a lane (A entries: velocity node, both components)
+// acc[c][m] += a * x[c][m] over entries of a lane (A entries: velocity node, both
+// components); first holds the lane's first chunk, loaded by the caller
 template <int M>
 __device__ __forceinline__ void ell_rows_a(float (&acc)[2][M], const EllView& E, const unsigned char* lds, int e,
-                                           int K) {
-    EllMeta cur, nxt;
-    ell_meta<false>(cur, E, e, 0, K);
+                                           int K, const EllMeta& first) {
+    EllMeta cur = first, nxt;
     for (int k0 = 0; k0 < K; k0 += kEllChunk) {
         if (k0 + kEllChunk < K) ell_meta<false>(nxt, E, e, k0 + kEllChunk, K);
 #pragma unroll
@@ -1165,6 +1165,14 @@ __device__ __forceinline__ void ell_rows_a(float (&acc)[2][M], const EllView& E,
         }
         cur = nxt;
     }
+}
+
+template <int M>
+__device__ __forceinline__ void ell_rows_a(float (&acc)[2][M], const EllView& E, const unsigned char* lds, int e,
+                                           int K) {
+    EllMeta first;
+    ell_meta<false>(first, E, e, 0, K);
+    ell_rows_a<M>(acc, E, lds, e, K, first);
 }
 
 // acc[0][m] += s a0 p[m], acc[1][m] += s a1 p[m] over B^T entries (pressure node), s = -1 if NEG
@@ -1209,14 +1217,23 @@ __global__ void __launch_bounds__(NW * 64) k_saddle_e(EllView E, const float* __
     const int j0 = (int)(bid % MS) * M;
     const int32_t* td = E.tile + 8 * tile;
     const int s2o = td[0], n2 = td[1], s1o = td[2], n1 = td[3], b0 = td[4], nb = td[5];
+    // the first chunk of a lane's entries is requested before the staging, so
+    // that its latency overlaps the staging's
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const int32_t* bd = E.blk + 8 * (b0 + (wave < nb ? wave : 0));
+    const int kind = bd[0], K1 = bd[2], K2 = bd[3], e1 = bd[4] + lane, e2 = bd[5] + lane, ro = bd[6];
+    EllMeta first;
+    if (wave < nb) {
+        if (kind == 0)
+            ell_meta<false>(first, E, e1, 0, K1);
+        else
+            ell_meta<true>(first, E, e1, 0, K1);
+    }
     ell_stage<M, NT>(smem_raw, E.s2 + s2o, n2, E.s1 + s1o, n1, n2 * ell_p2_bytes(M), x,
                      x + 2 * (int64_t)nP2 * J, J, j0);
     __syncthreads();
-    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int lane = threadIdx.x & 63;
     if (wave >= nb) return;
-    const int32_t* bd = E.blk + 8 * (b0 + wave);
-    const int kind = bd[0], K1 = bd[2], K2 = bd[3], e1 = bd[4] + lane, e2 = bd[5] + lane, ro = bd[6];
     const int row = E.rows[ro + lane];
     float acc[2][M];
 #pragma unroll
@@ -1224,7 +1241,7 @@ __global__ void __launch_bounds__(NW * 64) k_saddle_e(EllView E, const float* __
 #pragma unroll
         for (int m = 0; m < M; ++m) acc[c][m] = 0.f;
     if (kind == 0) {
-        ell_rows_a<M>(acc, E, smem_raw, e1, K1);
+        ell_rows_a<M>(acc, E, smem_raw, e1, K1, first);
         ell_rows_bt<M, false>(acc, E, smem_raw, e2, K2);
         if (row >= 0) {
 #pragma unroll
@@ -1237,8 +1254,7 @@ __global__ void __launch_bounds__(NW * 64) k_saddle_e(EllView E, const float* __
         }
     } else {
         // B rows: acc[0] = sum b_x x_0, acc[1] = sum b_y x_1 over the velocity nodes
-        EllMeta cur, nxt;
-        ell_meta<true>(cur, E, e1, 0, K1);
+        EllMeta cur = first, nxt;
         for (int k0 = 0; k0 < K1; k0 += kEllChunk) {
             if (k0 + kEllChunk < K1) ell_meta<true>(nxt, E, e1, k0 + kEllChunk, K1);
 #pragma unroll
@@ -3226,6 +3242,7 @@ mhd_status launch_saddle_plan(NodePlan p, DevShared& S, const T* x, const T* b, 
                     constexpr int MM = decltype(Mc)::value;
                     if (t.max_blocks <= 2) return go(k_saddle_e<MM, 2>, 128);
                     if (t.max_blocks <= 4) return go(k_saddle_e<MM, 4>, 256);
+                    if (t.max_blocks <= 5) return go(k_saddle_e<MM, 5>, 320);
                     return go(k_saddle_e<MM, 8>, 512);
                 };
                 return t.m == 8 ? by_waves(std::integral_constant<int, 8>{}) : by_waves(std::integral_constant<int, 16>{});
