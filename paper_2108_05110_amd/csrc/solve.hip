@@ -828,34 +828,43 @@ __device__ __forceinline__ void bload(T (&v)[V], __amdgpu_buffer_rsrc_t r, unsig
     __builtin_memcpy(v, &w, 16);
 }
 
+// acc[q] += sum_t a_t x[off_t + lane_off + q] over entries t0 ... t0 + B - 1
+// (B loads in flight)
+template <typename T, int V, bool PAIR, bool NEG, int B>
+__device__ __forceinline__ void pair_batch(const HalfRow<T, PAIR>& R, int t0, int hb, int c,
+                                           __amdgpu_buffer_rsrc_t xr, unsigned lane_off, T (&acc)[V]) {
+    T v[B][V];
+    T a[B];
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+        const int addr = hb + ((t0 + i) << 2);
+        const unsigned off = (unsigned)__builtin_amdgcn_ds_bpermute(addr, (int)R.off);
+        bload<T, V>(v[i], xr, off + lane_off);
+        if (PAIR) {
+            const T a0 = bperm_addr(R.v0, addr), a1 = bperm_addr(R.v1, addr);
+            a[i] = c ? a1 : a0;
+        } else {
+            a[i] = bperm_addr(R.v0, addr);
+        }
+        if (NEG) a[i] = -a[i];
+    }
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+#pragma unroll
+        for (int q = 0; q < V; ++q) acc[q] += a[i] * v[i][q];
+    }
+}
+
 // acc[q] += sum_t a_t x[off_t + lane_off + q] for this lane's row; n = entries
-// of the longer row of the pair (uniform, <= kPairRow), 8 loads in flight
+// of the longer row of the pair (uniform, <= kPairRow), in entry order: batches
+// of 8 loads, the rest in batches of 4 (entries past the row add zero)
 template <typename T, int V, bool PAIR, bool NEG>
 __device__ __forceinline__ void pair_row(const HalfRow<T, PAIR>& R, int n, int half, int c,
                                          __amdgpu_buffer_rsrc_t xr, unsigned lane_off, T (&acc)[V]) {
     const int hb = half << 7;   // byte address of lane 32 half
-    for (int t = 0; t < n; t += 8) {
-        T v[8][V];
-        T a[8];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int addr = hb + ((t + i) << 2);
-            const unsigned off = (unsigned)__builtin_amdgcn_ds_bpermute(addr, (int)R.off);
-            bload<T, V>(v[i], xr, off + lane_off);
-            if (PAIR) {
-                const T a0 = bperm_addr(R.v0, addr), a1 = bperm_addr(R.v1, addr);
-                a[i] = c ? a1 : a0;
-            } else {
-                a[i] = bperm_addr(R.v0, addr);
-            }
-            if (NEG) a[i] = -a[i];
-        }
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-#pragma unroll
-            for (int q = 0; q < V; ++q) acc[q] += a[i] * v[i][q];
-        }
-    }
+    int t = 0;
+    for (; t + 8 <= n; t += 8) pair_batch<T, V, PAIR, NEG, 8>(R, t, hb, c, xr, lane_off, acc);
+    for (; t < n; t += 4) pair_batch<T, V, PAIR, NEG, 4>(R, t, hb, c, xr, lane_off, acc);
 }
 
 // y = S x (MODE 0) or y = b - S x (MODE 1)
@@ -986,26 +995,30 @@ template <typename T, int V>
 __device__ __forceinline__ void pair_row_scaled(const HalfRow<T, false>& R, int n, int half,
                                                 __amdgpu_buffer_rsrc_t xr, unsigned lane_off, T (&acc)[V]) {
     const int hb = half << 7;
-    for (int t = 0; t < n; t += 8) {
-        T v[8][V];
-        T a[8], sc[8];
+    auto batch = [&](auto nb, int t0) {
+        constexpr int B = decltype(nb)::value;
+        T v[B][V];
+        T a[B], sc[B];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int addr = hb + ((t + i) << 2);
+        for (int i = 0; i < B; ++i) {
+            const int addr = hb + ((t0 + i) << 2);
             const unsigned off = (unsigned)__builtin_amdgcn_ds_bpermute(addr, (int)R.off);
             bload<T, V>(v[i], xr, off + lane_off);
             a[i] = bperm_addr(R.v0, addr);
             sc[i] = bperm_addr(R.v1, addr);
         }
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
+        for (int i = 0; i < B; ++i) {
 #pragma unroll
             for (int q = 0; q < V; ++q) {
                 const T zq = mul_rn(v[i][q], sc[i]);
                 acc[q] += a[i] * zq;
             }
         }
-    }
+    };
+    int t = 0;
+    for (; t + 8 <= n; t += 8) batch(std::integral_constant<int, 8>{}, t);
+    for (; t < n; t += 4) batch(std::integral_constant<int, 4>{}, t);
 }
 
 // The second velocity Jacobi sweep straight from t, paired rows: with
