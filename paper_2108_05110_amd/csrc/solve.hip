@@ -855,16 +855,36 @@ __device__ __forceinline__ void pair_batch(const HalfRow<T, PAIR>& R, int t0, in
     }
 }
 
+// Runs batch(std::integral_constant<int, B>, t0) over entries 0 ... n - 1 in
+// order: batches of 8 loads, then the remainder r < 8 as 8 (r = 7), 4 + 2 or
+// 4 + 1 (r = 6, 5), 4 (r = 3, 4), 2 or 1; entries past the row add zero
+template <typename F>
+__device__ __forceinline__ void pair_batches(int n, F&& batch) {
+    int t = 0;
+    for (; t + 8 <= n; t += 8) batch(std::integral_constant<int, 8>{}, t);
+    int r = n - t;
+    if (r == 7) {
+        batch(std::integral_constant<int, 8>{}, t);
+        return;
+    }
+    if (r >= 3) {
+        batch(std::integral_constant<int, 4>{}, t);
+        t += 4;
+        r -= 4;
+    }
+    if (r == 2) batch(std::integral_constant<int, 2>{}, t);
+    if (r == 1) batch(std::integral_constant<int, 1>{}, t);
+}
+
 // acc[q] += sum_t a_t x[off_t + lane_off + q] for this lane's row; n = entries
-// of the longer row of the pair (uniform, <= kPairRow), in entry order: batches
-// of 8 loads, the rest in batches of 4 (entries past the row add zero)
+// of the longer row of the pair (uniform, <= kPairRow), in entry order
 template <typename T, int V, bool PAIR, bool NEG>
 __device__ __forceinline__ void pair_row(const HalfRow<T, PAIR>& R, int n, int half, int c,
                                          __amdgpu_buffer_rsrc_t xr, unsigned lane_off, T (&acc)[V]) {
     const int hb = half << 7;   // byte address of lane 32 half
-    int t = 0;
-    for (; t + 8 <= n; t += 8) pair_batch<T, V, PAIR, NEG, 8>(R, t, hb, c, xr, lane_off, acc);
-    for (; t < n; t += 4) pair_batch<T, V, PAIR, NEG, 4>(R, t, hb, c, xr, lane_off, acc);
+    pair_batches(n, [&](auto nb, int t0) {
+        pair_batch<T, V, PAIR, NEG, decltype(nb)::value>(R, t0, hb, c, xr, lane_off, acc);
+    });
 }
 
 // y = S x (MODE 0) or y = b - S x (MODE 1)
@@ -1016,9 +1036,7 @@ __device__ __forceinline__ void pair_row_scaled(const HalfRow<T, false>& R, int 
             }
         }
     };
-    int t = 0;
-    for (; t + 8 <= n; t += 8) batch(std::integral_constant<int, 8>{}, t);
-    for (; t < n; t += 4) batch(std::integral_constant<int, 4>{}, t);
+    pair_batches(n, batch);
 }
 
 // The second velocity Jacobi sweep straight from t, paired rows: with
