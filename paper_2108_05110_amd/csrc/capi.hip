@@ -122,6 +122,15 @@ mhd_status upload_csr(std::vector<void*>& list, DevCSR<double>& d, const HostCSR
     return MHD_OK;
 }
 
+// FP32 copy of a coarsest level's dense inverse with rows of ld floats, zero
+// past column and row n (the matrix-core coarse solve reads 16 x 16 blocks)
+std::vector<float> padded_inverse32(const HostLevel& H, int ld) {
+    std::vector<float> c((size_t)ld * ld, 0.f);
+    for (int r = 0; r < H.n; ++r)
+        for (int k = 0; k < H.n; ++k) c[(size_t)r * ld + k] = (float)H.cinv[(size_t)r * H.n + k];
+    return c;
+}
+
 void free_list(std::vector<void*>& list) {
     for (void* p : list) (void)hipFree(p);
     list.clear();
@@ -239,8 +248,8 @@ mhd_status build_device_mesh(DevMesh& D) {
             if ((rc = upload_csr(L, G.R, H.R))) return rc;
         } else {
             if ((rc = upload(L, &G.cinv, H.cinv))) return rc;
-            std::vector<float> c32(H.cinv.begin(), H.cinv.end());
-            if ((rc = upload(L, &G.cinv32, c32))) return rc;
+            G.ld32 = (H.n + 15) / 16 * 16;
+            if ((rc = upload(L, &G.cinv32, padded_inverse32(H, G.ld32)))) return rc;
         }
     }
     // constant matrices (mass, stiffness, divergence) assembled on the device
@@ -312,7 +321,7 @@ mhd_status refresh_schur(DevMesh& D, double dt, double nu_c) {
         MHD_HIP(hipMemcpy(G.dinv, H.dinv.data(), sizeof(double) * H.dinv.size(), hipMemcpyHostToDevice));
         MHD_HIP(hipMemcpy(G.dinv32, d32.data(), sizeof(float) * d32.size(), hipMemcpyHostToDevice));
         if (l + 1 == h.levels.size()) {
-            std::vector<float> c32(H.cinv.begin(), H.cinv.end());
+            const std::vector<float> c32 = padded_inverse32(H, G.ld32);
             MHD_HIP(hipMemcpy(G.cinv, H.cinv.data(), sizeof(double) * H.cinv.size(), hipMemcpyHostToDevice));
             MHD_HIP(hipMemcpy(G.cinv32, c32.data(), sizeof(float) * c32.size(), hipMemcpyHostToDevice));
         }

@@ -36,8 +36,9 @@ struct DevLevel {
     DevCSR<double> L, P, R;
     double* dinv = nullptr;
     float* dinv32 = nullptr;
-    double* cinv = nullptr;       // coarsest only
-    float* cinv32 = nullptr;
+    double* cinv = nullptr;       // coarsest only, n x n
+    float* cinv32 = nullptr;      // coarsest only, ld32 x ld32 with zeros past n
+    int ld32 = 0;                 // n rounded up to a multiple of 16
 };
 
 // Device copy of a HostTiling (row tiles of the LDS-staged kernels)

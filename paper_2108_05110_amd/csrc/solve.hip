@@ -25,6 +25,7 @@
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <type_traits>
 
 #include "device.h"
 
@@ -103,6 +104,7 @@ struct Vals<double> {
     static const double* csr(const DevCSR<double>& c) { return c.val; }
     static const double* dinv(const DevLevel& l) { return l.dinv; }
     static const double* cinv(const DevLevel& l) { return l.cinv; }
+    static int cinv_ld(const DevLevel& l) { return l.n; }
 };
 template <>
 struct Vals<float> {
@@ -114,6 +116,7 @@ struct Vals<float> {
     static const float* csr(const DevCSR<double>& c) { return c.val32; }
     static const float* dinv(const DevLevel& l) { return l.dinv32; }
     static const float* cinv(const DevLevel& l) { return l.cinv32; }
+    static int cinv_ld(const DevLevel& l) { return l.ld32; }
 };
 
 // ------------------------------------------------------------------ saddle-point SpMM
@@ -1521,7 +1524,7 @@ __global__ void __launch_bounds__(kBlock) k_mg(const int32_t* __restrict__ rp, c
     vstore<T, V>(y + o, out);
 }
 
-// Dense x = C b on the coarsest level (C: n x n row-major, b and x: n x J),
+// Dense x = C b on the coarsest level (C: n x n row-major with row length ld, b and x: n x J),
 // split over kDenseKS column ranges: a workgroup computes the partial product
 // of a 64-row x 64-member block over one range (4 x 4 outputs per thread from
 // 16-column slices staged in LDS); k_dense_sum adds the kDenseKS partials in a
@@ -1530,7 +1533,7 @@ constexpr int kDenseKS = 16;
 
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_dense_part(const T* __restrict__ C, const T* __restrict__ b,
-                                                       T* __restrict__ part, int n, int J) {
+                                                       T* __restrict__ part, int n, int ld, int J) {
     __shared__ T As[16][64];   // [column][row]
     __shared__ T Bs[16][64];   // [column][member]
     const int tid = threadIdx.x;
@@ -1551,7 +1554,7 @@ __global__ void __launch_bounds__(kBlock) k_dense_part(const T* __restrict__ C, 
             const int idx = tid + e * kBlock;          // 0 .. 1023
             const int rr = idx >> 4, kk = idx & 15;
             const int r = r0 + rr, k = kb + kk;
-            ca[e] = (r < n && k < k1) ? C[(int64_t)r * n + k] : (T)0;
+            ca[e] = (r < n && k < k1) ? C[(int64_t)r * ld + k] : (T)0;
             const int bk = idx >> 6, bj = idx & 63;
             cb[e] = (kb + bk < k1 && j0 + bj < J) ? b[(int64_t)(kb + bk) * J + j0 + bj] : (T)0;
         }
@@ -1601,6 +1604,62 @@ __global__ void __launch_bounds__(kBlock) k_dense_sum(const T* __restrict__ part
 #pragma unroll
     for (int k = 1; k < kDenseKS; ++k) s += part[(int64_t)k * nJ + i];
     x[i] = s;
+}
+
+// The same product in FP32 on the matrix cores (J a multiple of 16, C zero-padded
+// to ld x ld, ld a multiple of 16).  A workgroup of kDenseWaves wavefronts owns a
+// 16-row x 16-member block of x; wavefront w takes an equal share of the
+// 16-column blocks of C, loads kDenseBlocks of them (a row's 16 columns as four
+// 16-byte loads across the lane groups, and the matching 16 rows of b) before
+// its v_mfma_f32_16x16x4f32 steps, and the partial blocks are added in wavefront
+// order through LDS.  Column k = 16 q + 4 g + s enters step s of block q in lane
+// group g, for both operands.
+constexpr int kDenseWaves = 16, kDenseBlocks = 5;
+typedef float floatx4_t __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(kDenseWaves * 64) k_dense_mf(const float* __restrict__ C, const float* __restrict__ b,
+                                                              float* __restrict__ x, int n, int ld, int J) {
+    __shared__ float red[kDenseWaves][16][17];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int r0 = blockIdx.x * 16, j0 = blockIdx.y * 16;
+    const int nkb = ld / 16, per = (nkb + kDenseWaves - 1) / kDenseWaves;
+    const int kb0 = min(nkb, w * per), kb1 = min(nkb, kb0 + per);
+    const int g = lane >> 4, c = lane & 15;
+    const float* arow = C + (int64_t)(r0 + c) * ld + 4 * g;
+    floatx4_t d = {0.f, 0.f, 0.f, 0.f};
+    for (int q0 = kb0; q0 < kb1; q0 += kDenseBlocks) {
+        float4 a[kDenseBlocks];
+        float bv[kDenseBlocks][4];
+#pragma unroll
+        for (int q = 0; q < kDenseBlocks; ++q) {
+            const int kb = q0 + q < kb1 ? q0 + q : kb0;   // past the share: a reload left unused
+            a[q] = *(const float4*)(arow + 16 * kb);
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int k = 16 * kb + 4 * g + s;
+                bv[q][s] = k < n ? b[(int64_t)k * J + j0 + c] : 0.f;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kDenseBlocks; ++q) {
+            if (q0 + q < kb1) {
+                d = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q].x, bv[q][0], d, 0, 0, 0);
+                d = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q].y, bv[q][1], d, 0, 0, 0);
+                d = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q].z, bv[q][2], d, 0, 0, 0);
+                d = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q].w, bv[q][3], d, 0, 0, 0);
+            }
+        }
+    }
+    // lane (g, c) holds rows 4 g ... 4 g + 3 of column c of the block
+#pragma unroll
+    for (int i = 0; i < 4; ++i) red[w][4 * g + i][c] = d[i];
+    __syncthreads();
+    if (threadIdx.x < 256) {
+        const int row = threadIdx.x >> 4, col = threadIdx.x & 15;
+        float sum = red[0][row][col];
+        for (int q = 1; q < kDenseWaves; ++q) sum += red[q][row][col];
+        if (r0 + row < n) x[(int64_t)(r0 + row) * J + j0 + col] = sum;
+    }
 }
 
 // ------------------------------------------------------------------ LDS-staged node-row kernels
@@ -3789,9 +3848,18 @@ struct Ops {
         T* x = (T*)S.gw.mg_x[l];
         mhd_status rc;
         if (l + 1 == (int)m.levels.size()) {
+            if constexpr (std::is_same<T, float>::value) {
+                if (J % 16 == 0) {
+                    hipLaunchKernelGGL(k_dense_mf, dim3((Lv.n + 15) / 16, J / 16), dim3(kDenseWaves * 64), 0, st,
+                                       Lv.cinv32, b, x, Lv.n, Lv.ld32, J);
+                    LAUNCH_CHECK();
+                    *out = x;
+                    return MHD_OK;
+                }
+            }
             T* part = (T*)S.gw.dense_part;
             hipLaunchKernelGGL((k_dense_part<T>), dim3((Lv.n + 63) / 64, (J + 63) / 64, kDenseKS), dim3(kBlock), 0,
-                               st, Vals<T>::cinv(Lv), b, part, Lv.n, J);
+                               st, Vals<T>::cinv(Lv), b, part, Lv.n, Vals<T>::cinv_ld(Lv), J);
             LAUNCH_CHECK();
             const int64_t nJ = (int64_t)Lv.n * J;
             hipLaunchKernelGGL((k_dense_sum<T>), dim3((unsigned)((nJ + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,

@@ -121,10 +121,11 @@ def test_rhs_parity(L, J, which):
     gm.close()
 
 
-@pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 1e-9)])
-def test_solve_parity(L, precision, tol):
-    say("solve", precision)
-    N, J = 8, 4
+# J = 16 (FP32 inner solves) takes the matrix-core coarse-grid solve, J = 4 the vector one
+@pytest.mark.parametrize("precision,tol,J", [(0, 1e-10, 4), (1, 1e-9, 4), (1, 1e-9, 16)])
+def test_solve_parity(L, precision, tol, J):
+    say("solve", precision, J)
+    N = 8
     pb = wl.cavity(J=J, s=0.3, dt=0.01, nu_mean=0.001, num_mean=0.001, ic_amp=0.05)
     gm, om_, ens, pm2, pm1, perm = setup_pair(L, N, pb)
     V, W = random_state(pb, om_.xy, 3)
