@@ -60,9 +60,11 @@ __device__ __forceinline__ double group_max(double v, int JP) {
     return v;
 }
 
-inline int pick_jp(int J) {
+// lanes per unit (row or element): the power of two >= J, at most cap (16: a
+// wavefront takes four or more units and a lane several members)
+inline int pick_jp(int J, int cap = 16) {
     int p = 1;
-    while (p < J && p < 64) p <<= 1;
+    while (p < J && p < cap) p <<= 1;
     return p;
 }
 
@@ -566,8 +568,9 @@ hipError_t launch_rhs_elem(const DevMesh& m, const mhd_coeffs& c, int J, const d
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t units = (int64_t)m.nP2 + m.nP1;
-    hipLaunchKernelGGL(k_rhs_node, dim3(grid_for(units, JP)), dim3(kBlock), 0, s, m.inc_ptr, m.inc, m.dir_index,
-                       (const double*)part, bc, rhs, m.nP2, m.nP1, J, JP);
+    const int JN = pick_jp(J, 64);   // the node gather keeps one member per lane
+    hipLaunchKernelGGL(k_rhs_node, dim3(grid_for(units, JN)), dim3(kBlock), 0, s, m.inc_ptr, m.inc, m.dir_index,
+                       (const double*)part, bc, rhs, m.nP2, m.nP1, J, JN);
     return hipGetLastError();
 }
 
