@@ -2707,15 +2707,14 @@ __global__ void k_init_g(double* __restrict__ g, const double* __restrict__ beta
     g[j] = beta[j];
 }
 
-// Givens step k for every member (FP64): rotate column k of H, new rotation, update g.
-__global__ void k_givens(double* __restrict__ H, double* __restrict__ cs, double* __restrict__ sn,
-                         double* __restrict__ g, const double* __restrict__ hcol, const double* __restrict__ hn,
-                         double* __restrict__ res, int k, int m, int J) {
-    int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= J) return;
+// Givens step k for member j (FP64): rotate column k of H (hcol, with hn the new
+// subdiagonal entry), new rotation, update g and the residual estimate
+__device__ __forceinline__ void givens_step(double* __restrict__ H, double* __restrict__ cs, double* __restrict__ sn,
+                                            double* __restrict__ g, const double* __restrict__ hcol, double hnj,
+                                            double* __restrict__ res, int k, int m, int J, int j) {
     double h[kMaxRestart + 1];
     for (int i = 0; i <= k; ++i) h[i] = hcol[i * J + j];
-    h[k + 1] = hn[j];
+    h[k + 1] = hnj;
     for (int i = 0; i < k; ++i) {
         double c = cs[i * J + j], s = sn[i * J + j];
         double t = c * h[i] + s * h[i + 1];
@@ -2741,6 +2740,35 @@ __global__ void k_givens(double* __restrict__ H, double* __restrict__ cs, double
     g[(k + 1) * J + j] = -s * gk;
     g[k * J + j] = c * gk;
     res[j] = fabs(g[(k + 1) * J + j]);
+}
+
+// Givens step k for every member
+__global__ void k_givens(double* __restrict__ H, double* __restrict__ cs, double* __restrict__ sn,
+                         double* __restrict__ g, const double* __restrict__ hcol, const double* __restrict__ hn,
+                         double* __restrict__ res, int k, int m, int J) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= J) return;
+    givens_step(H, cs, sn, g, hcol, hn[j], res, k, m, J, j);
+}
+
+// hn[j] = sqrt(sum_b partial[j * nblk + b]) as k_reduce (one wavefront per
+// member, same order), then the Givens step k of member j as k_givens
+__global__ void __launch_bounds__(kBlock) k_norm_givens(const double* __restrict__ partial, int nblk,
+                                                        double* __restrict__ hn, double* __restrict__ H,
+                                                        double* __restrict__ cs, double* __restrict__ sn,
+                                                        double* __restrict__ g, const double* __restrict__ hcol,
+                                                        double* __restrict__ res, int k, int m, int J) {
+    const int lane = threadIdx.x & 63;
+    const int j = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    double s = 0.0;
+    if (j < J)
+        for (int b = lane; b < nblk; b += 64) s += partial[(int64_t)j * nblk + b];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (j < J && lane == 0) {
+        const double hnj = sqrt(s);
+        hn[j] = hnj;
+        givens_step(H, cs, sn, g, hcol, hnj, res, k, m, J, j);
+    }
 }
 
 // back substitution H(0:kd,0:kd) y = g(0:kd) per member
@@ -4126,17 +4154,21 @@ mhd_status gmres_solve(DevShared& S, const double* b, double* x, int J, const mh
                     if (rc) return rc;
                 }
             }
-            hipLaunchKernelGGL(k_reduce, dim3(reduce_grid(J)), dim3(kBlock), 0, st, G.partial, rs.nblk, (int64_t)J, hn,
-                               1);
-            LAUNCH_CHECK();
             if (passes > 1) {
+                hipLaunchKernelGGL(k_reduce, dim3(reduce_grid(J)), dim3(kBlock), 0, st, G.partial, rs.nblk,
+                                   (int64_t)J, hn, 1);
+                LAUNCH_CHECK();
                 hipLaunchKernelGGL(k_add_vec, dim3(((k + 1) * J + 255) / 256), dim3(256), 0, st, G.hcol,
                                    (const double*)hcol2, (int64_t)(k + 1) * J);
                 LAUNCH_CHECK();
+                hipLaunchKernelGGL(k_givens, dim3((J + 63) / 64), dim3(64), 0, st, G.H, G.cs, G.sn, G.g, G.hcol, hn,
+                                   G.res, k, mres, J);
+                LAUNCH_CHECK();
+            } else {
+                hipLaunchKernelGGL(k_norm_givens, dim3(reduce_grid(J)), dim3(kBlock), 0, st, (const double*)G.partial,
+                                   rs.nblk, hn, G.H, G.cs, G.sn, G.g, (const double*)G.hcol, G.res, k, mres, J);
+                LAUNCH_CHECK();
             }
-            hipLaunchKernelGGL(k_givens, dim3((J + 63) / 64), dim3(64), 0, st, G.H, G.cs, G.sn, G.g, G.hcol, hn, G.res,
-                               k, mres, J);
-            LAUNCH_CHECK();
             if ((rc = launch_scale_cols<T, T>(w, hn, w, n, J, st))) return rc;
             ++iters;
             kd = k + 1;
