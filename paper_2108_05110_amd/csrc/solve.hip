@@ -2482,13 +2482,13 @@ __global__ void __launch_bounds__(kBlock) k_dots(const T* const* __restrict__ V,
 }
 
 // w -= sum_{i<NB} h[(c0 + i) J + j] V_{c0 + i}; with LAST also partial[j * nblk +
-// block] = sum over rows of w^2.  NB is the exact count (all loads of an
+// block] = sum over rows of w^2 (store = 0: the norm only, w left as it was).  NB is the exact count (all loads of an
 // iteration issued before the arithmetic); longer updates run in chunks, which
 // perform the same operations in the same order.
 template <typename T, int VEC, int NB, bool LAST>
 __global__ void __launch_bounds__(kBlock) k_update(const T* const* __restrict__ V, int c0, const double* __restrict__ h,
                                                    T* __restrict__ w, int64_t n, int J, int CW,
-                                                   double* __restrict__ partial) {
+                                                   double* __restrict__ partial, int store = 1) {
     __shared__ double red[kColsumBatch * kBlock];
     const ColMap c = colmap(CW, VEC, J);
     double acc[VEC];
@@ -2528,7 +2528,7 @@ __global__ void __launch_bounds__(kBlock) k_update(const T* const* __restrict__ 
             for (int i = 0; i < NB; ++i)
 #pragma unroll
                 for (int u = 0; u < VEC; ++u) w_[u] -= hh[i][u] * v_[i][u];
-            if (live) vstore<T, VEC>(w + rr * J + c.jb, w_);
+            if (live && store) vstore<T, VEC>(w + rr * J + c.jb, w_);
             if (LAST) {
 #pragma unroll
                 for (int u = 0; u < VEC; ++u) {
@@ -4141,9 +4141,11 @@ mhd_status gmres_solve(DevShared& S, const double* b, double* x, int J, const mh
                     rc = with_vec<T>(rs.VEC, [&](auto V) -> mhd_status {
                         return with_nb(nb, [&](auto NBc) -> mhd_status {
                             constexpr int VV = decltype(V)::value, NN = decltype(NBc)::value;
+                            // the last vector of a cycle is only needed for its norm
+                            const int store = (k + 1 < mres || pass + 1 < passes) ? 1 : 0;
                             if (last)
                                 hipLaunchKernelGGL((k_update<T, VV, NN, true>), rs.grid, dim3(kBlock), 0, st, Vd, c0,
-                                                   (const double*)hdst, w, n, J, rs.CW, G.partial);
+                                                   (const double*)hdst, w, n, J, rs.CW, G.partial, store);
                             else
                                 hipLaunchKernelGGL((k_update<T, VV, NN, false>), rs.grid, dim3(kBlock), 0, st, Vd, c0,
                                                    (const double*)hdst, w, n, J, rs.CW, G.partial);
@@ -4169,7 +4171,9 @@ mhd_status gmres_solve(DevShared& S, const double* b, double* x, int J, const mh
                                    rs.nblk, hn, G.H, G.cs, G.sn, G.g, (const double*)G.hcol, G.res, k, mres, J);
                 LAUNCH_CHECK();
             }
-            if ((rc = launch_scale_cols<T, T>(w, hn, w, n, J, st))) return rc;
+            // v_{k+1} = w / h_{k+1,k}; the last vector of a cycle is never used
+            if (k + 1 < mres)
+                if ((rc = launch_scale_cols<T, T>(w, hn, w, n, J, st))) return rc;
             ++iters;
             kd = k + 1;
             if (!fixed && (kd % check == 0 || kd == mres)) {
