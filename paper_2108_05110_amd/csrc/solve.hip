@@ -2580,10 +2580,12 @@ __global__ void __launch_bounds__(kBlock) k_colsq(const double* __restrict__ a, 
 }
 
 // u = sum_{i<NB} y[(c0 + i) J + j] V_{c0 + i}, added to u unless FIRST (chunks of an
-// NB-exact combination, as k_update)
+// NB-exact combination, as k_update); with x64 the result is added to the FP64
+// x instead of being stored (the last chunk of x += Z y)
 template <typename T, int VEC, int NB, bool FIRST>
 __global__ void __launch_bounds__(kBlock) k_combine(const T* const* __restrict__ V, int c0, const double* __restrict__ yv,
-                                                    T* __restrict__ u, int64_t n, int J, int CW) {
+                                                    T* __restrict__ u, int64_t n, int J, int CW,
+                                                    double* __restrict__ x64 = nullptr) {
     const ColMap c = colmap(CW, VEC, J);
     if (!c.ok) return;
     T yy[NB][VEC];
@@ -2623,7 +2625,22 @@ __global__ void __launch_bounds__(kBlock) k_combine(const T* const* __restrict__
         for (int i = 0; i < NB; ++i)
 #pragma unroll
             for (int q = 0; q < VEC; ++q) s_[q] += yy[i][q] * v_[i][q];
-        if (rr < n) vstore<T, VEC>(u + rr * J + c.jb, s_);
+        if (rr >= n) return;
+        if (!x64) {
+            vstore<T, VEC>(u + rr * J + c.jb, s_);
+        } else if constexpr (VEC % 2 == 0) {   // x += u in FP64 instead of storing u (as k_add_to64)
+#pragma unroll
+            for (int q = 0; q < VEC; q += 2) {
+                double2* xp = (double2*)(x64 + rr * J + c.jb + q);
+                double2 xv = *xp;
+                xv.x += (double)s_[q];
+                xv.y += (double)s_[q + 1];
+                *xp = xv;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) x64[rr * J + c.jb + q] += (double)s_[q];
+        }
     };
     if (trips > 0) load(r, sa, va);
     for (int64_t k = 0; k < trips; k += 2) {
@@ -4190,30 +4207,34 @@ mhd_status gmres_solve(DevShared& S, const double* b, double* x, int J, const mh
         hipLaunchKernelGGL(k_lsq, dim3((J + 63) / 64), dim3(64), 0, st, G.H, G.g, G.y, kd, mres, J);
         LAUNCH_CHECK();
         T* u = (T*)G.wbuf;
+        // with Z kept the last chunk adds its result to x directly (16-byte aligned x)
+        const bool fuse_x = keepz && ((uintptr_t)x % 16) == 0;
         for (int c0 = 0; c0 < kd; c0 += 8) {
             const int nb = std::min(8, kd - c0);
+            double* x64 = (fuse_x && c0 + nb == kd) ? x : nullptr;
             rc = with_vec<T>(rs.VEC, [&](auto V) -> mhd_status {
                 return with_nb(nb, [&](auto NBc) -> mhd_status {
                     constexpr int VV = decltype(V)::value, NN = decltype(NBc)::value;
                     if (c0 == 0)
                         hipLaunchKernelGGL((k_combine<T, VV, NN, true>), rs.grid, dim3(kBlock), 0, st, keepz ? Zd : Vd,
-                                           c0, (const double*)G.y, u, n, J, rs.CW);
+                                           c0, (const double*)G.y, u, n, J, rs.CW, x64);
                     else
                         hipLaunchKernelGGL((k_combine<T, VV, NN, false>), rs.grid, dim3(kBlock), 0, st, keepz ? Zd : Vd,
-                                           c0, (const double*)G.y, u, n, J, rs.CW);
+                                           c0, (const double*)G.y, u, n, J, rs.CW, x64);
                     LAUNCH_CHECK();
                     return MHD_OK;
                 });
             });
             if (rc) return rc;
         }
-        const T* dx = u;
         if (!keepz) {
             if ((rc = ops.precond(u, (T*)G.zbuf, sweeps, omega))) return rc;
-            dx = (const T*)G.zbuf;
+            hipLaunchKernelGGL((k_add_to64<T>), dim3(ew_grid(n * J)), dim3(kBlock), 0, st, x, (const T*)G.zbuf, n * J);
+            LAUNCH_CHECK();
+        } else if (!fuse_x && kd > 0) {
+            hipLaunchKernelGGL((k_add_to64<T>), dim3(ew_grid(n * J)), dim3(kBlock), 0, st, x, (const T*)u, n * J);
+            LAUNCH_CHECK();
         }
-        hipLaunchKernelGGL((k_add_to64<T>), dim3(ew_grid(n * J)), dim3(kBlock), 0, st, x, dx, n * J);
-        LAUNCH_CHECK();
         ++cycles;
     }
     if (fixed) {
