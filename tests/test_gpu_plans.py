@@ -155,6 +155,29 @@ def test_every_solver_plan_same_solution(L, precision):
     gm.close()
 
 
+def test_unaligned_solution_vector(L):
+    """x at an 8-byte offset (not 16-byte aligned): the FP64 residual takes one
+    member per lane and the FP32 inner solve adds its correction to x in a pass
+    of its own instead of inside the last basis combination; the iterates are
+    the same as with an aligned x."""
+    J = 64
+    pb, gm, A, V, W = shared(L, J, seed=4)
+    rng = np.random.default_rng(5)
+    b = torch.from_numpy(rng.standard_normal((gm.n, J))).cuda()
+    x0 = torch.zeros((gm.n, J), dtype=torch.float64, device="cuda")
+    st0, _ = L.mhd_ens_solve(A, b, x0, J, L.solver_opts(1, rtol=1e-10))
+    big = torch.zeros(gm.n * J + 2, dtype=torch.float64, device="cuda")
+    x1 = big[1:1 + gm.n * J].view(gm.n, J)
+    assert x1.data_ptr() % 16 == 8
+    st1, _ = L.mhd_ens_solve(A, b, x1, J, L.solver_opts(1, rtol=1e-10))
+    say("  aligned iters", st0.iters, "cycles", st0.cycles, "unaligned iters", st1.iters, "cycles", st1.cycles)
+    assert st0.converged == 1 and st1.converged == 1
+    assert (st1.iters, st1.cycles) == (st0.iters, st0.cycles)
+    assert torch.equal(x1, x0)
+    L.mhd_ens_shared_free(A)
+    gm.close()
+
+
 def test_autotune_report(L):
     J = 64
     pb, gm, A, _, _ = shared(L, J)
