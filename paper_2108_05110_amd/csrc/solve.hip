@@ -2339,8 +2339,6 @@ __device__ __forceinline__ void vstore(T* p, const T (&v)[VEC]) {
     *reinterpret_cast<V*>(p) = *reinterpret_cast<const V*>(v);
 }
 
-// vload through a global-address-space pointer: for block pointers read from a
-// pointer array, which the compiler would otherwise load as flat accesses
 // Compiler-only ordering point (emits no code) for a software-pipelined row
 // loop: the registers of the row about to be used are marked as produced here,
 // so the work on them cannot move above the next row's loads issued before this
@@ -2351,6 +2349,8 @@ __device__ __forceinline__ void settle(T (&v)[VEC]) {
     for (int u = 0; u < VEC; ++u) asm volatile("" : "+v"(v[u])::"memory");
 }
 
+// vload through a global-address-space pointer: for block pointers read from a
+// pointer array, which the compiler would otherwise load as flat accesses
 template <typename T, int VEC>
 __device__ __forceinline__ void gload(T (&v)[VEC], const T* p) {
     using GV = T __attribute__((ext_vector_type(VEC)));
