@@ -172,7 +172,12 @@ typedef struct {
     int restart;
     int jacobi_sweeps;        /* velocity-block smoothing sweeps in the preconditioner */
     int check_every;          /* inner iterations between convergence checks (>= 1)    */
-    int cgs_passes;           /* Gram-Schmidt passes: 1, 2, or 0 = 1 for FP32, 2 for FP64 */
+    int cgs_passes;           /* classical Gram-Schmidt passes: 1, 2, or 0 = 1 for FP32,
+                                 2 for FP64.  One pass takes the new vector's norm
+                                 from the dot products (|w|^2 - |h|^2) and stores it
+                                 normalised in the same update; two passes
+                                 re-orthogonalise and norm the vector directly
+                                 (more accurate, about 2x the Gram-Schmidt traffic) */
     int fixed_cycles;         /* > 0: fixed schedule of fixed_cycles refinement cycles of
                                  `restart` inner iterations each, with no host
                                  synchronisation (graph-capturable); rtol, inner_rtol,

@@ -2417,16 +2417,18 @@ __device__ __forceinline__ void block_colsums(const double (&v)[NV], const ColMa
     }
 }
 
-// partial[((c0 + i) * J + j) * nblk + block] = sum over rows of V_i[r, j] * w[r, j], i < NB.
-// NB is the exact count, so all loads of an iteration are issued before the products.
-template <typename T, int VEC, int NB>
+// partial[((c0 + i) * J + j) * nblk + block] = sum over rows of V_i[r, j] * w[r, j], i < NB;
+// with WW also sum over rows of w[r, j]^2 at i = NB.  NB is the exact count, so
+// all loads of an iteration are issued before the products.
+template <typename T, int VEC, int NB, bool WW = false>
 __global__ void __launch_bounds__(kBlock) k_dots(const T* const* __restrict__ V, int c0, const T* __restrict__ w,
                                                  int64_t n, int J, int CW, double* __restrict__ partial) {
     __shared__ double red[kColsumBatch * kBlock];
+    constexpr int NA = (NB + (WW ? 1 : 0)) * VEC;
     const ColMap c = colmap(CW, VEC, J);
-    double acc[NB * VEC];
+    double acc[NA];
 #pragma unroll
-    for (int q = 0; q < NB * VEC; ++q) acc[q] = 0.0;
+    for (int q = 0; q < NA; ++q) acc[q] = 0.0;
     if (c.ok && n > 0) {
         const T* vp[NB];
 #pragma unroll
@@ -2459,6 +2461,10 @@ __global__ void __launch_bounds__(kBlock) k_dots(const T* const* __restrict__ V,
             for (int i = 0; i < NB; ++i)
 #pragma unroll
                 for (int u = 0; u < VEC; ++u) acc[i * VEC + u] += (double)v_[i][u] * (double)wz[u];
+            if (WW) {
+#pragma unroll
+                for (int u = 0; u < VEC; ++u) acc[NB * VEC + u] += (double)wz[u] * (double)wz[u];
+            }
         };
         if (trips > 0) load(r, wa, va);
         for (int64_t k = 0; k < trips; k += 2) {
@@ -2473,7 +2479,7 @@ __global__ void __launch_bounds__(kBlock) k_dots(const T* const* __restrict__ V,
         }
     }
     const int64_t nblk = gridDim.x;
-    block_colsums<NB * VEC, VEC>(acc, c, red, CW, J,
+    block_colsums<NA, VEC>(acc, c, red, CW, J,
                                  [&](int q, int tx, double sum) {
                                      const int i = q / VEC, u = q - i * VEC;
                                      const int64_t j = ((int64_t)blockIdx.y * CW + tx) * VEC + u;
@@ -2482,13 +2488,15 @@ __global__ void __launch_bounds__(kBlock) k_dots(const T* const* __restrict__ V,
 }
 
 // w -= sum_{i<NB} h[(c0 + i) J + j] V_{c0 + i}; with LAST also partial[j * nblk +
-// block] = sum over rows of w^2 (store = 0: the norm only, w left as it was).  NB is the exact count (all loads of an
+// block] = sum over rows of w^2 (store = 0: the norm only, w left as it was);
+// with scale the result is stored divided by scale[j] (0 where scale[j] is 0).  NB is the exact count (all loads of an
 // iteration issued before the arithmetic); longer updates run in chunks, which
 // perform the same operations in the same order.
 template <typename T, int VEC, int NB, bool LAST>
 __global__ void __launch_bounds__(kBlock) k_update(const T* const* __restrict__ V, int c0, const double* __restrict__ h,
                                                    T* __restrict__ w, int64_t n, int J, int CW,
-                                                   double* __restrict__ partial, int store = 1) {
+                                                   double* __restrict__ partial, int store = 1,
+                                                   const double* __restrict__ scale = nullptr) {
     __shared__ double red[kColsumBatch * kBlock];
     const ColMap c = colmap(CW, VEC, J);
     double acc[VEC];
@@ -2503,6 +2511,9 @@ __global__ void __launch_bounds__(kBlock) k_update(const T* const* __restrict__ 
 #pragma unroll
             for (int u = 0; u < VEC; ++u) hh[i][u] = (T)h[(int64_t)(c0 + i) * J + c.jb + u];
         }
+        double f[VEC];
+#pragma unroll
+        for (int u = 0; u < VEC; ++u) f[u] = scale ? scale[c.jb + u] : 1.0;
         // Two register sets in turn: the next row's loads are issued before the
         // current row is updated. The trip count is the block's (uniform), rows
         // past the end are re-reads of row n - 1 that store and add nothing.
@@ -2528,7 +2539,16 @@ __global__ void __launch_bounds__(kBlock) k_update(const T* const* __restrict__ 
             for (int i = 0; i < NB; ++i)
 #pragma unroll
                 for (int u = 0; u < VEC; ++u) w_[u] -= hh[i][u] * v_[i][u];
-            if (live && store) vstore<T, VEC>(w + rr * J + c.jb, w_);
+            if (live && store) {
+                if (scale) {   // as k_scale_cols_v with invert
+                    T o[VEC];
+#pragma unroll
+                    for (int u = 0; u < VEC; ++u) o[u] = (T)(f[u] > 0.0 ? (double)w_[u] / f[u] : 0.0);
+                    vstore<T, VEC>(w + rr * J + c.jb, o);
+                } else {
+                    vstore<T, VEC>(w + rr * J + c.jb, w_);
+                }
+            }
             if (LAST) {
 #pragma unroll
                 for (int u = 0; u < VEC; ++u) {
@@ -2768,24 +2788,23 @@ __global__ void k_givens(double* __restrict__ H, double* __restrict__ cs, double
     givens_step(H, cs, sn, g, hcol, hn[j], res, k, m, J, j);
 }
 
-// hn[j] = sqrt(sum_b partial[j * nblk + b]) as k_reduce (one wavefront per
-// member, same order), then the Givens step k of member j as k_givens
-__global__ void __launch_bounds__(kBlock) k_norm_givens(const double* __restrict__ partial, int nblk,
-                                                        double* __restrict__ hn, double* __restrict__ H,
-                                                        double* __restrict__ cs, double* __restrict__ sn,
-                                                        double* __restrict__ g, const double* __restrict__ hcol,
-                                                        double* __restrict__ res, int k, int m, int J) {
-    const int lane = threadIdx.x & 63;
-    const int j = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+// One Gram-Schmidt pass with the norm from the dot products: hn[j] =
+// sqrt(|w|^2 - sum_i h_i^2) (0 if not positive), |w|^2 held in hcol row k + 1,
+// then the Givens step k of member j as k_givens
+__global__ void k_pyth_givens(const double* __restrict__ hcol, double* __restrict__ hn, double* __restrict__ H,
+                              double* __restrict__ cs, double* __restrict__ sn, double* __restrict__ g,
+                              double* __restrict__ res, int k, int m, int J) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= J) return;
     double s = 0.0;
-    if (j < J)
-        for (int b = lane; b < nblk; b += 64) s += partial[(int64_t)j * nblk + b];
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-    if (j < J && lane == 0) {
-        const double hnj = sqrt(s);
-        hn[j] = hnj;
-        givens_step(H, cs, sn, g, hcol, hnj, res, k, m, J, j);
+    for (int i = 0; i <= k; ++i) {
+        const double h = hcol[i * J + j];
+        s += h * h;
     }
+    const double d = hcol[(k + 1) * J + j] - s;
+    const double hnj = d > 0.0 ? sqrt(d) : 0.0;
+    hn[j] = hnj;
+    givens_step(H, cs, sn, g, hcol, hnj, res, k, m, J, j);
 }
 
 // back substitution H(0:kd,0:kd) y = g(0:kd) per member
@@ -4134,7 +4153,51 @@ mhd_status gmres_solve(DevShared& S, const double* b, double* x, int J, const mh
             T* w = basis_ptr<T>(S, k + 1);
             if ((rc = ops.precond(vk, z, sweeps, omega))) return rc;
             if ((rc = ops.saddle(z, w))) return rc;
-            // classical Gram-Schmidt (optionally with a re-orthogonalisation pass)
+            if (passes == 1) {
+                // one classical Gram-Schmidt pass: |w|^2 comes with the dot products,
+                // h_{k+1,k} = sqrt(|w|^2 - |h|^2) (V orthonormal), and the update
+                // stores v_{k+1} = (w - V h) / h_{k+1,k} directly; the last vector of
+                // a cycle is never used, so its update is skipped
+                for (int c0 = 0; c0 <= k; c0 += 8) {
+                    const int nb = std::min(8, k + 1 - c0);
+                    const bool last = c0 + nb == k + 1;
+                    rc = with_vec<T>(rs.VEC, [&](auto V) -> mhd_status {
+                        return with_nb(nb, [&](auto NBc) -> mhd_status {
+                            constexpr int VV = decltype(V)::value, NN = decltype(NBc)::value;
+                            if (last)
+                                hipLaunchKernelGGL((k_dots<T, VV, NN, true>), rs.grid, dim3(kBlock), 0, st, Vd, c0,
+                                                   (const T*)w, n, J, rs.CW, G.partial);
+                            else
+                                hipLaunchKernelGGL((k_dots<T, VV, NN, false>), rs.grid, dim3(kBlock), 0, st, Vd, c0,
+                                                   (const T*)w, n, J, rs.CW, G.partial);
+                            LAUNCH_CHECK();
+                            return MHD_OK;
+                        });
+                    });
+                    if (rc) return rc;
+                }
+                hipLaunchKernelGGL(k_reduce, dim3(reduce_grid((int64_t)(k + 2) * J)), dim3(kBlock), 0, st, G.partial,
+                                   rs.nblk, (int64_t)(k + 2) * J, G.hcol, 0);
+                LAUNCH_CHECK();
+                hipLaunchKernelGGL(k_pyth_givens, dim3((J + 63) / 64), dim3(64), 0, st, (const double*)G.hcol, hn, G.H,
+                                   G.cs, G.sn, G.g, G.res, k, mres, J);
+                LAUNCH_CHECK();
+                for (int c0 = 0; c0 <= k && k + 1 < mres; c0 += 8) {
+                    const int nb = std::min(8, k + 1 - c0);
+                    const double* sc = c0 + nb == k + 1 ? (const double*)hn : nullptr;
+                    rc = with_vec<T>(rs.VEC, [&](auto V) -> mhd_status {
+                        return with_nb(nb, [&](auto NBc) -> mhd_status {
+                            constexpr int VV = decltype(V)::value, NN = decltype(NBc)::value;
+                            hipLaunchKernelGGL((k_update<T, VV, NN, false>), rs.grid, dim3(kBlock), 0, st, Vd, c0,
+                                               (const double*)G.hcol, w, n, J, rs.CW, G.partial, 1, sc);
+                            LAUNCH_CHECK();
+                            return MHD_OK;
+                        });
+                    });
+                    if (rc) return rc;
+                }
+            } else {
+            // classical Gram-Schmidt with a re-orthogonalisation pass
             for (int pass = 0; pass < passes; ++pass) {
                 double* hdst = pass ? hcol2 : G.hcol;
                 for (int c0 = 0; c0 <= k; c0 += 8) {
@@ -4173,24 +4236,19 @@ mhd_status gmres_solve(DevShared& S, const double* b, double* x, int J, const mh
                     if (rc) return rc;
                 }
             }
-            if (passes > 1) {
-                hipLaunchKernelGGL(k_reduce, dim3(reduce_grid(J)), dim3(kBlock), 0, st, G.partial, rs.nblk,
-                                   (int64_t)J, hn, 1);
-                LAUNCH_CHECK();
-                hipLaunchKernelGGL(k_add_vec, dim3(((k + 1) * J + 255) / 256), dim3(256), 0, st, G.hcol,
-                                   (const double*)hcol2, (int64_t)(k + 1) * J);
-                LAUNCH_CHECK();
-                hipLaunchKernelGGL(k_givens, dim3((J + 63) / 64), dim3(64), 0, st, G.H, G.cs, G.sn, G.g, G.hcol, hn,
-                                   G.res, k, mres, J);
-                LAUNCH_CHECK();
-            } else {
-                hipLaunchKernelGGL(k_norm_givens, dim3(reduce_grid(J)), dim3(kBlock), 0, st, (const double*)G.partial,
-                                   rs.nblk, hn, G.H, G.cs, G.sn, G.g, (const double*)G.hcol, G.res, k, mres, J);
-                LAUNCH_CHECK();
-            }
+            hipLaunchKernelGGL(k_reduce, dim3(reduce_grid(J)), dim3(kBlock), 0, st, G.partial, rs.nblk, (int64_t)J, hn,
+                               1);
+            LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_add_vec, dim3(((k + 1) * J + 255) / 256), dim3(256), 0, st, G.hcol,
+                               (const double*)hcol2, (int64_t)(k + 1) * J);
+            LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_givens, dim3((J + 63) / 64), dim3(64), 0, st, G.H, G.cs, G.sn, G.g, G.hcol, hn,
+                               G.res, k, mres, J);
+            LAUNCH_CHECK();
             // v_{k+1} = w / h_{k+1,k}; the last vector of a cycle is never used
             if (k + 1 < mres)
                 if ((rc = launch_scale_cols<T, T>(w, hn, w, n, J, st))) return rc;
+            }
             ++iters;
             kd = k + 1;
             if (!fixed && (kd % check == 0 || kd == mres)) {
