@@ -2744,13 +2744,14 @@ __global__ void k_init_g(double* __restrict__ g, const double* __restrict__ beta
     g[j] = beta[j];
 }
 
-// Givens step k for member j (FP64): rotate column k of H (hcol, with hn the new
-// subdiagonal entry), new rotation, update g and the residual estimate
+// Givens step k for member j (FP64): rotate column k of H (hv[i * hs], i <= k,
+// with hnj the new subdiagonal entry), new rotation, update g and the residual
+// estimate
 __device__ __forceinline__ void givens_step(double* __restrict__ H, double* __restrict__ cs, double* __restrict__ sn,
-                                            double* __restrict__ g, const double* __restrict__ hcol, double hnj,
+                                            double* __restrict__ g, const double* hv, int hs, double hnj,
                                             double* __restrict__ res, int k, int m, int J, int j) {
     double h[kMaxRestart + 1];
-    for (int i = 0; i <= k; ++i) h[i] = hcol[i * J + j];
+    for (int i = 0; i <= k; ++i) h[i] = hv[i * hs];
     h[k + 1] = hnj;
     for (int i = 0; i < k; ++i) {
         double c = cs[i * J + j], s = sn[i * J + j];
@@ -2785,26 +2786,39 @@ __global__ void k_givens(double* __restrict__ H, double* __restrict__ cs, double
                          double* __restrict__ res, int k, int m, int J) {
     int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= J) return;
-    givens_step(H, cs, sn, g, hcol, hn[j], res, k, m, J, j);
+    givens_step(H, cs, sn, g, hcol + j, J, hn[j], res, k, m, J, j);
 }
 
-// One Gram-Schmidt pass with the norm from the dot products: hn[j] =
-// sqrt(|w|^2 - sum_i h_i^2) (0 if not positive), |w|^2 held in hcol row k + 1,
-// then the Givens step k of member j as k_givens
-__global__ void k_pyth_givens(const double* __restrict__ hcol, double* __restrict__ hn, double* __restrict__ H,
-                              double* __restrict__ cs, double* __restrict__ sn, double* __restrict__ g,
-                              double* __restrict__ res, int k, int m, int J) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= J) return;
-    double s = 0.0;
-    for (int i = 0; i <= k; ++i) {
-        const double h = hcol[i * J + j];
-        s += h * h;
+// One Gram-Schmidt pass with the norm from the dot products, one workgroup per
+// member j: hcol[i J + j] = sum_b partial[(i J + j) nblk + b] for i <= k + 1 (per
+// value the order of k_reduce: strided lane sums, then a butterfly), where rows
+// i <= k are h = V^T w and row k + 1 is |w|^2; then hn[j] = sqrt(|w|^2 - sum_i
+// h_i^2) (0 if not positive) and the Givens step k of member j as k_givens
+__global__ void __launch_bounds__(kBlock) k_reduce_pyth_givens(const double* __restrict__ partial, int nblk,
+                                                               double* __restrict__ hcol, double* __restrict__ hn,
+                                                               double* __restrict__ H, double* __restrict__ cs,
+                                                               double* __restrict__ sn, double* __restrict__ g,
+                                                               double* __restrict__ res, int k, int m, int J) {
+    __shared__ double hs[kMaxRestart + 2];
+    const int j = blockIdx.x;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int i = wave; i <= k + 1; i += kBlock / 64) {
+        double sum = 0.0;
+        for (int bk = lane; bk < nblk; bk += 64) sum += partial[((int64_t)i * J + j) * nblk + bk];
+        for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
+        if (lane == 0) {
+            hs[i] = sum;
+            hcol[i * J + j] = sum;
+        }
     }
-    const double d = hcol[(k + 1) * J + j] - s;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double s2 = 0.0;
+    for (int i = 0; i <= k; ++i) s2 += hs[i] * hs[i];
+    const double d = hs[k + 1] - s2;
     const double hnj = d > 0.0 ? sqrt(d) : 0.0;
     hn[j] = hnj;
-    givens_step(H, cs, sn, g, hcol, hnj, res, k, m, J, j);
+    givens_step(H, cs, sn, g, hs, 1, hnj, res, k, m, J, j);
 }
 
 // back substitution H(0:kd,0:kd) y = g(0:kd) per member
@@ -4176,11 +4190,8 @@ mhd_status gmres_solve(DevShared& S, const double* b, double* x, int J, const mh
                     });
                     if (rc) return rc;
                 }
-                hipLaunchKernelGGL(k_reduce, dim3(reduce_grid((int64_t)(k + 2) * J)), dim3(kBlock), 0, st, G.partial,
-                                   rs.nblk, (int64_t)(k + 2) * J, G.hcol, 0);
-                LAUNCH_CHECK();
-                hipLaunchKernelGGL(k_pyth_givens, dim3((J + 63) / 64), dim3(64), 0, st, (const double*)G.hcol, hn, G.H,
-                                   G.cs, G.sn, G.g, G.res, k, mres, J);
+                hipLaunchKernelGGL(k_reduce_pyth_givens, dim3(J), dim3(kBlock), 0, st, (const double*)G.partial,
+                                   rs.nblk, G.hcol, hn, G.H, G.cs, G.sn, G.g, G.res, k, mres, J);
                 LAUNCH_CHECK();
                 for (int c0 = 0; c0 <= k && k + 1 < mres; c0 += 8) {
                     const int nb = std::min(8, k + 1 - c0);
