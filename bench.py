@@ -100,7 +100,6 @@ def cpu_baseline(N, J, seconds_hint=30.0):
     b = ens.rhs(V[:, :, :1], W[:, :, :1], F1[:, :, :1], G[:, :, :1])
     ens.solve_members(Sv, b, members=[0])
     dt = time.perf_counter() - t0
-    _ = np
     return {"value": 0.5 / dt, "unit": "member-steps/s", "cores": 1, "kind": "oracle",
             "sample": f"v-subproblem of 1 member, step 1, {N}x{N} cavity with J={J} members in the "
                       f"ensemble statistics (= 0.5 member-step), per-member SuperLU, "
@@ -409,7 +408,7 @@ def adjoint_workload(args, L, wl, torch):
     member, checkpoints every 10 steps; two entries checked by central
     differences of the GPU forward map."""
     import numpy as np
-    from oracle.adjoint import modes_and_forcing
+    from workloads import modes_and_forcing
     from paper_2108_05110_amd.autograd import EnsembleEnergy, Rollout
     from paper_2108_05110_amd.ensemble import Mesh
     J, N, nsteps = 32, args.N, 50

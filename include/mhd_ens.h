@@ -329,6 +329,13 @@ mhd_status mhd_ens_autotune(mhd_shared A, int J, int precision, mhd_tune_entry* 
 mhd_status mhd_ens_set_plan(mhd_shared A, int J, int precision, int op, int vec, int group, int deep, int tile,
                             int waves);
 
+/* The launch plan one operator (MHD_TUNE_*) currently runs with for this
+ * handle's mesh, J and precision, in the autotuner's report form: the tuned or
+ * pinned table entry (chosen = 1, us = its tuned time or 0 if pinned) or the
+ * default plan used when the table has none (chosen = 0, us = -1).  Host only:
+ * no device work, no synchronisation.  out: host, one entry. */
+mhd_status mhd_ens_get_plan(mhd_shared A, int J, int precision, int op, mhd_tune_entry* out);
+
 /* Diagnostics: while enabled, every saddle-point SpMM launch of this library
  * (inside mhd_ens_solve / mhd_ens_step and mhd_ens_spmm, outside graph
  * capture) is timed by a pair of HIP events that its dispatch records at the

@@ -22,7 +22,6 @@ every forward state.
 from __future__ import annotations
 
 import numpy as np
-import scipy.sparse as sp
 from scipy.sparse.linalg import splu
 
 from .fem import vec2
@@ -221,15 +220,3 @@ def central_fd(adj, nu, num, a, coef, nsteps, which, j, h=1e-6):
             args[3][j, which[1]] += delta
         return adj.forward(*args, nsteps)[1]
     return (run(h) - run(-h)) / (2 * h)
-
-
-def modes_and_forcing(xy):
-    """The four initial modes of the parameter study and the forcing shape
-    fhat = curl(sin^2(pi x) sin^2(pi y)) (problem data of ``workloads``)."""
-    import workloads as wl
-    modes = [wl.mode_field(k, l, xy) for (k, l) in wl.MODES]
-    return modes, wl.mode_field(1, 1, xy)
-
-
-def _unused():
-    return sp

@@ -92,25 +92,27 @@ class Ensemble:
         return self.saddle(self.velocity_block(zbar, self.eddy_l2(zf)))
 
     # --------------------------------------------------- right-hand sides
-    def rhs(self, Zself, Zother, F, G):
-        """Per-member right-hand sides (n, J) of the subproblem for Zself."""
+    def rhs(self, Zself, Zother, F, G, members=None):
+        """Per-member right-hand sides (n, J) of the subproblem for Zself; with
+        `members`, only those columns (in that order), the ensemble mean still
+        taken over every member of Zother."""
         pb = self.pb
         mesh = self.mesh
-        J = Zself.shape[2]
+        cols = range(Zself.shape[2]) if members is None else list(members)
         nub, numb = pb.nu.mean(), pb.nu_m.mean()
         cminus = 0.5 * (pb.nu - pb.nu_m)
         cplus = 0.5 * ((pb.nu - nub) + (pb.nu_m - numb))
         _, of = self.mean_fluct(Zother)
-        b = np.zeros((mesh.n, J))
+        b = np.zeros((mesh.n, len(cols)))
         nu2 = 2 * mesh.nP2
-        for j in range(J):
+        for i, j in enumerate(cols):
             zs = Zself[:, :, j].ravel()
             zo = Zother[:, :, j].ravel()
             Nj = vec2(self.el.convection(of[:, :, j], skew=self.skew))
-            b[:nu2, j] = (self.M2 @ (zs / pb.dt + F[:, :, j].ravel()) - Nj @ zs
+            b[:nu2, i] = (self.M2 @ (zs / pb.dt + F[:, :, j].ravel()) - Nj @ zs
                           - cminus[j] * (self.K2 @ zo) - cplus[j] * (self.K2 @ zs))
-            b[2 * self.dnodes, j] = G[self.dnodes, 0, j]
-            b[2 * self.dnodes + 1, j] = G[self.dnodes, 1, j]
+            b[2 * self.dnodes, i] = G[self.dnodes, 0, j]
+            b[2 * self.dnodes + 1, i] = G[self.dnodes, 1, j]
         if self.pin is not None:
             b[nu2 + self.pin, :] = 0.0
         return b
@@ -144,10 +146,10 @@ class Ensemble:
         Gv, Gw = self.pb.bc(t_next, xy)
         Sv = self.shared_matrix(W)
         Sw = self.shared_matrix(V)
-        bv = self.rhs(V, W, F1, Gv)
-        bw = self.rhs(W, V, F2, Gw)
-        xv = self.solve_members(Sv, bv, shared_lu, members)
-        xw = self.solve_members(Sw, bw, shared_lu, members)
+        bv = self.rhs(V, W, F1, Gv, members)
+        bw = self.rhs(W, V, F2, Gw, members)
+        xv = self.solve_members(Sv, bv, shared_lu)
+        xw = self.solve_members(Sw, bw, shared_lu)
         V1, Q = self.split(xv)
         W1, R = self.split(xw)
         return V1, W1, Q, R

@@ -27,7 +27,7 @@ EXPORTS = (
     "mhd_ens_spmm", "mhd_ens_timer_enable", "mhd_ens_timer_read", "mhd_ens_last_error", "mhd_ens_version",
     "mhd_ens_adjoint_terminal", "mhd_ens_adjoint_step", "mhd_ens_adjoint_ic",
     "mhd_ens_group_create", "mhd_ens_group_step", "mhd_ens_group_free",
-    "mhd_ens_autotune", "mhd_ens_set_plan",
+    "mhd_ens_autotune", "mhd_ens_set_plan", "mhd_ens_get_plan",
 )
 
 
@@ -106,7 +106,7 @@ def lib():
         if not os.path.exists(LIBPATH):
             raise RuntimeError(f"{LIBPATH} is missing: build it with python -m paper_2108_05110_amd.build")
         L = C.CDLL(LIBPATH)
-        P, I, D = C.c_void_p, C.c_int, C.c_double
+        P, I = C.c_void_p, C.c_int
         sig = {
             "mhd_ens_mesh_counts": [C.POINTER(MeshDesc), C.POINTER(MeshInfo)],
             "mhd_ens_mesh": [C.POINTER(MeshDesc), C.POINTER(P), C.POINTER(MeshInfo)],
@@ -124,6 +124,7 @@ def lib():
             "mhd_ens_spmm": [P, P, P, I, I, P],
             "mhd_ens_autotune": [P, I, I, C.POINTER(TuneEntry), I, C.POINTER(I), P],
             "mhd_ens_set_plan": [P, I, I, I, I, I, I, I, I],
+            "mhd_ens_get_plan": [P, I, I, I, C.POINTER(TuneEntry)],
             "mhd_ens_timer_enable": [I],
             "mhd_ens_adjoint_terminal": [P, P, P, P, P, I, P],
             "mhd_ens_adjoint_step": [P, P, P, P, P, P, P, P, P, C.POINTER(AdjointInputs), P,
@@ -144,7 +145,6 @@ def lib():
         L.mhd_ens_last_error.argtypes = []
         L.mhd_ens_version.restype = C.c_char_p
         L.mhd_ens_version.argtypes = []
-        _ = D
         _lib = L
     return _lib
 
@@ -272,6 +272,18 @@ def mhd_ens_autotune(A, J, precision, stream=None, cap=256):
 
 def mhd_ens_set_plan(A, J, precision, op, vec, group, deep=0, tile=0, waves=4):
     check("mhd_ens_set_plan", lib().mhd_ens_set_plan(A, J, precision, op, vec, group, deep, tile, waves))
+
+
+def mhd_ens_get_plan(A, J, precision, op):
+    e = TuneEntry()
+    check("mhd_ens_get_plan", lib().mhd_ens_get_plan(A, J, precision, op, C.byref(e)))
+    return dict(op=TUNE_OPS[e.op], word=e.word, J=e.J, vec=e.vec, group=e.group, deep=e.deep, tile=e.tile,
+                waves=e.waves, us=e.us, chosen=bool(e.chosen))
+
+
+def mhd_ens_plan(A, J, precision):
+    """The plans of all four node-row operators, keyed by operator name."""
+    return {TUNE_OPS[op]: mhd_ens_get_plan(A, J, precision, op) for op in TUNE_OPS}
 
 
 def mhd_ens_timer_enable(on=True):

@@ -51,6 +51,7 @@ struct mhd_group_s {
     hipEvent_t fork = nullptr;
     mhd::StepGraph graph;
     std::vector<mhd::StepArgs> keys;
+    std::vector<mhd_coeffs> coeffs;   // per context: dt, mu and mean viscosities baked into the graph
 };
 
 struct mhd_ctx_s {
@@ -785,6 +786,16 @@ mhd_status mhd_ens_set_plan(mhd_shared A, int J, int precision, int op, int vec,
     return set_plan(A->d, J, precision, op, vec, group, deep, tile, waves);
 }
 
+mhd_status mhd_ens_get_plan(mhd_shared A, int J, int precision, int op, mhd_tune_entry* out) {
+    CHECK_ARG(A && out, "mhd_ens_get_plan: null argument");
+    CHECK_ARG(precision == MHD_FP64 || precision == MHD_FP32_IR, "mhd_ens_get_plan: bad precision");
+    if (J < 1 || J > A->d.Jmax) {
+        set_error("mhd_ens_get_plan: J outside [1, J_max]");
+        return MHD_ESHAPE;
+    }
+    return query_plan(A->d, J, precision, op, out);
+}
+
 mhd_status mhd_ens_step(mhd_ctx ctx, double* V, double* W, double* Q, double* R, const mhd_step_inputs* in,
                         mhd_step_stats* st, mhd_stream_t s) {
     CHECK_ARG(ctx && in, "mhd_ens_step: null argument");
@@ -908,8 +919,11 @@ mhd_status mhd_ens_group_step(mhd_group g, double* const* V, double* const* W, d
                 set_error("mhd_ens_group_step: contexts on one mesh need equal dt and nu_bar + num_bar");
                 return MHD_EINVAL;
             }
-    bool same = g->graph.valid && g->graph.stream == st && g->keys.size() == (size_t)n;
-    for (int i = 0; same && i < n; ++i) same = g->keys[i] == args[i];
+    // the mean viscosities, dt and mu enter the captured kernels by value: a change re-captures
+    bool same = g->graph.valid && g->graph.stream == st && g->keys.size() == (size_t)n && g->coeffs.size() == (size_t)n;
+    for (int i = 0; same && i < n; ++i)
+        same = g->keys[i] == args[i] && g->coeffs[i].dt == cs[i].dt && g->coeffs[i].mu == cs[i].mu &&
+               g->coeffs[i].nu_bar == cs[i].nu_bar && g->coeffs[i].num_bar == cs[i].num_bar;
     if (!same) {
         g->graph.reset();
         for (int i = 0; i < n; ++i) {
@@ -948,6 +962,7 @@ mhd_status mhd_ens_group_step(mhd_group g, double* const* V, double* const* W, d
         g->graph.stream = st;
         g->graph.valid = true;
         g->keys = args;
+        g->coeffs = cs;
     }
     MHD_HIP(hipGraphLaunch(g->graph.exec, st));
     return MHD_OK;

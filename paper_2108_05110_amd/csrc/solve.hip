@@ -6,10 +6,11 @@
 // Method: right-preconditioned restarted GMRES with one Arnoldi process per
 // member (per-member Hessenberg matrices and Givens rotations in FP64), one
 // SpMM over all J columns per iteration.  Preconditioner (block upper
-// triangular): z_p = S_hat^{-1} r_p with the Cahouet-Chabard approximation
-// S_hat^{-1} = -(1/dt) L_p^{-1} - nu_c M_p^{-1} (L_p: P1 Laplacian, one
-// geometric multigrid V-cycle with damped Jacobi smoothing; M_p lumped P1
-// mass), then z_u = damped Jacobi sweeps on A for r_u - B^T z_p.  The outer
+// triangular): z_p = -S_hat^{-1} r_p with S_hat = B D^{-1} B^T, D the diagonal
+// of M/dt + nu_c K (the velocity block without convection), inverted
+// approximately by one V(2,2)-cycle with damped Jacobi smoothing on a Galerkin
+// hierarchy over the nested P1 vertex grids (dense inverse on the coarsest
+// level), then z_u = damped Jacobi sweeps on A for r_u - B^T z_p.  The outer
 // loop is FP64 iterative refinement: r = b - S x in FP64, a GMRES cycle in
 // the inner precision (FP32 or FP64) on r, x += d.
 //
@@ -3740,6 +3741,32 @@ bool plan_cached(const DevMesh& m, int J, int word, int op) {
 }
 
 }  // namespace
+
+// The plan one operator runs with for (mesh, J, word size): the table entry
+// (chosen = 1) or the default plan (chosen = 0), in the autotuner's report form.
+mhd_status query_plan(DevShared& S, int J, int precision, int op, mhd_tune_entry* out) {
+    DevMesh& m = *S.mesh;
+    if (op < MHD_TUNE_SADDLE || op > MHD_TUNE_JACOBI) {
+        set_error("mhd_ens_get_plan: unknown operator");
+        return MHD_EINVAL;
+    }
+    const int word = (op == MHD_TUNE_RESIDUAL || precision == MHD_FP64) ? 8 : 4;
+    PlanRec r{default_plan(m, J, word), -1.f};
+    bool tuned = false;
+    {
+        std::lock_guard<std::mutex> lk(g_plan_mu);
+        auto it = g_plans.find(plan_key(m, J, word, op));
+        if (it != g_plans.end()) {
+            r = it->second;
+            tuned = true;
+        }
+    }
+    const NodePlan& q = r.p;
+    *out = mhd_tune_entry{op, word, J, q.vec, q.tile ? 0 : q.g, q.deep,
+                          q.tile ? (q.deep == 6 ? ell_code(q.tile) : tile_edge(q.tile)) : 0, q.tile ? q.nw : 0, r.us,
+                          tuned ? 1 : 0};
+    return MHD_OK;
+}
 
 // Tunes the node-row operators a solve of this precision uses (inner SpMM and
 // Jacobi sweeps in the inner word size, FP64 residual).  Without force, only

@@ -107,3 +107,15 @@ class Stepper:
         if self.ctx:
             L.mhd_ens_ctx_free(self.ctx)
             self.ctx = None
+
+
+# Fixed solver schedule of the graph-captured step at the 128x128, J = 64
+# cavity: 2 FP64 refinement cycles of 6 FP32 GMRES iterations, 5 velocity
+# Jacobi sweeps with the library's default damping.
+FIXED_SCHEDULE = dict(restart=6, fixed_cycles=2, jacobi_sweeps=5)
+
+
+def fixed_schedule_opts(precision=L.MHD_FP32_IR, **over):
+    kw = dict(FIXED_SCHEDULE)
+    kw.update(over)
+    return L.solver_opts(precision, **kw)

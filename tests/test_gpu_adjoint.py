@@ -7,7 +7,8 @@ import pytest
 
 import workloads as wl
 from oracle import mesh as om
-from oracle.adjoint import EnsembleAdjoint, modes_and_forcing
+from oracle.adjoint import EnsembleAdjoint
+from workloads import modes_and_forcing
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")

@@ -319,6 +319,32 @@ def test_stability_inequality_and_energy_decay():
 
 
 # ------------------------------------------------------------ structural reductions
+def test_energy_closed_form():
+    """E_h = 1/2 (||<v_h>||^2 + ||<w_h>||^2) (Section 4.2) on member fields whose
+    mean is known in closed form: v_j = c_j (x, y^2), w_j = d_j (1, -2) with
+    mean(c) = 3, mean(d) = -1, so ||<v>||^2 = 9 (1/3 + 1/5) and ||<w>||^2 = 5
+    on the unit square (P2 interpolation and the P2 mass matrix are exact for
+    these fields); on the step channel the constant field measures the area
+    30 * 10 - 1.  A dropped 1/2, a mean of member norms instead of the norm of
+    the mean, a single velocity component or a swapped variable all fail."""
+    c = np.array([1.0, 2.0, 6.0])
+    d = np.array([0.0, 1.0, -4.0])
+    pb = wl.cavity(J=3, s=0.1, dt=0.01)
+    m = om.unit_square(6)
+    ens = scheme.Ensemble(m, pb)
+    x, y = m.xy[:, 0], m.xy[:, 1]
+    V = np.stack([x, y * y], axis=1)[:, :, None] * c[None, None, :]
+    W = np.array([1.0, -2.0])[None, :, None] * d[None, None, :] * np.ones((m.nP2, 1, 1))
+    assert abs(ens.energy(V, W) - 0.5 * (9.0 * (1.0 / 3.0 + 1.0 / 5.0) + 5.0)) < 1e-13
+    assert abs(ens.energy(W, V) - ens.energy(V, W)) < 1e-13
+    assert abs(ens.energy(V, 0 * W) - 0.5 * 9.0 * 8.0 / 15.0) < 1e-13
+    pc = wl.step_channel(J=2, delta=0.1, s=0.01, dt=0.02, nsteps=1)
+    mc = om.step_channel(1)
+    ec = scheme.Ensemble(mc, pc)
+    Vc = np.array([1.0, -2.0])[None, :, None] * np.array([0.5, 1.5])[None, None, :] * np.ones((mc.nP2, 1, 1))
+    assert abs(ec.energy(Vc, 0 * Vc) - 0.5 * 5.0 * 299.0) < 1e-9
+
+
 def test_J1_reduces_to_plain_scheme():
     pb = wl.manufactured(J=1, eps=0.0, dt=0.01, nsteps=4)
     ms = om.unit_square(6)

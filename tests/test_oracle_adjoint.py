@@ -6,7 +6,8 @@ import pytest
 
 import workloads as wl
 from oracle import mesh as om
-from oracle.adjoint import EnsembleAdjoint, central_fd, modes_and_forcing
+from oracle.adjoint import EnsembleAdjoint, central_fd
+from workloads import modes_and_forcing
 
 
 def make(N=4, J=3, s=0.3, dt=0.05, seed=11):

@@ -60,6 +60,13 @@ def mode_field(k: int, l: int, xy: np.ndarray) -> np.ndarray:
     return np.stack([ux, uy], axis=1)
 
 
+def modes_and_forcing(xy: np.ndarray):
+    """The four initial modes of the parameter study (nodal fields at xy) and
+    the forcing shape fhat = curl(sin^2(pi x) sin^2(pi y))."""
+    modes = [mode_field(k, l, xy) for (k, l) in MODES]
+    return modes, mode_field(1, 1, xy)
+
+
 def _on(val, target, tol=1e-12):
     return np.abs(val - target) < tol
 
