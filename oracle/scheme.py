@@ -119,14 +119,17 @@ class Ensemble:
 
     # --------------------------------------------------- solves
     @staticmethod
-    def solve_members(S, b, shared_lu=False, members=None):
-        """Each member's system solved by its own sparse LU (or one shared LU)."""
+    def solve_members(S, b, shared_lu=False, members=None, ordering="COLAMD"):
+        """Each member's system solved by its own sparse LU (or one shared LU).
+        `ordering` is SuperLU's fill-reducing column ordering (it changes the
+        rounding of the direct solve, not what is solved); MMD_AT_PLUS_A keeps
+        the fill of the larger saddle-point systems manageable."""
         Sc = S.tocsc()
         cols = range(b.shape[1]) if members is None else members
         x = np.zeros((b.shape[0], len(cols)))
-        lu = splu(Sc) if shared_lu else None
+        lu = splu(Sc, permc_spec=ordering) if shared_lu else None
         for i, j in enumerate(cols):
-            f = lu if shared_lu else splu(Sc)
+            f = lu if shared_lu else splu(Sc, permc_spec=ordering)
             x[:, i] = f.solve(b[:, j])
         return x
 
@@ -139,8 +142,9 @@ class Ensemble:
             p = p - (self.mP1 @ p) / self.mP1.sum()
         return Z, p
 
-    def step(self, V, W, t_next, shared_lu=False, members=None):
-        """Algorithm 1, one step: returns V^{n+1}, W^{n+1}, q^{n+1}, r^{n+1} (zero mean when pinned)."""
+    def step(self, V, W, t_next, shared_lu=False, members=None, ordering="COLAMD", log=None):
+        """Algorithm 1, one step: returns V^{n+1}, W^{n+1}, q^{n+1}, r^{n+1} (zero mean when pinned).
+        `log`, if given, is called with a short message before each subproblem's solve."""
         xy = self.mesh.xy
         F1, F2 = self.pb.forcing(t_next, xy)
         Gv, Gw = self.pb.bc(t_next, xy)
@@ -148,8 +152,12 @@ class Ensemble:
         Sw = self.shared_matrix(V)
         bv = self.rhs(V, W, F1, Gv, members)
         bw = self.rhs(W, V, F2, Gw, members)
-        xv = self.solve_members(Sv, bv, shared_lu)
-        xw = self.solve_members(Sw, bw, shared_lu)
+        if log:
+            log("oracle: v-subproblem solve")
+        xv = self.solve_members(Sv, bv, shared_lu, ordering=ordering)
+        if log:
+            log("oracle: w-subproblem solve")
+        xw = self.solve_members(Sw, bw, shared_lu, ordering=ordering)
         V1, Q = self.split(xv)
         W1, R = self.split(xw)
         return V1, W1, Q, R
