@@ -31,6 +31,7 @@ import scipy.sparse as sp
 from scipy.sparse.linalg import splu
 
 from .fem import Element, vec2
+from .mesh import nested_dissection
 
 
 class Ensemble:
@@ -118,19 +119,30 @@ class Ensemble:
         return b
 
     # --------------------------------------------------- solves
-    @staticmethod
-    def solve_members(S, b, shared_lu=False, members=None, ordering="COLAMD"):
+    def solve_members(self, S, b, shared_lu=False, members=None, ordering="COLAMD"):
         """Each member's system solved by its own sparse LU (or one shared LU).
-        `ordering` is SuperLU's fill-reducing column ordering (it changes the
-        rounding of the direct solve, not what is solved); MMD_AT_PLUS_A keeps
-        the fill of the larger saddle-point systems manageable."""
-        Sc = S.tocsc()
+        `ordering` is SuperLU's fill-reducing column ordering, or "ND" for the
+        mesh's nested-dissection order applied symmetrically before a factorisation
+        that prefers diagonal pivots.  It changes the rounding of the direct
+        solve, not what is solved; ND keeps the fill of the larger saddle-point
+        systems small."""
         cols = range(b.shape[1]) if members is None else members
+        if ordering == "ND":
+            p = nested_dissection(self.mesh)
+            Sc = S.tocsr()[p][:, p].tocsc()
+            kw = dict(permc_spec="NATURAL", diag_pivot_thresh=0.01, options=dict(SymmetricMode=True))
+        else:
+            p = None
+            Sc = S.tocsc()
+            kw = dict(permc_spec=ordering)
         x = np.zeros((b.shape[0], len(cols)))
-        lu = splu(Sc, permc_spec=ordering) if shared_lu else None
+        lu = splu(Sc, **kw) if shared_lu else None
         for i, j in enumerate(cols):
-            f = lu if shared_lu else splu(Sc, permc_spec=ordering)
-            x[:, i] = f.solve(b[:, j])
+            f = lu if shared_lu else splu(Sc, **kw)
+            if p is None:
+                x[:, i] = f.solve(b[:, j])
+            else:
+                x[p, i] = f.solve(b[p, j])
         return x
 
     def split(self, x):

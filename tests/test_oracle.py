@@ -401,6 +401,40 @@ def test_shared_lu_equals_per_member_lu():
         assert np.abs(x - y).max() < 1e-13
 
 
+@pytest.mark.parametrize("kind", ["square", "channel"])
+def test_nested_dissection_order(kind):
+    """The nested-dissection order is a permutation whose separators split the
+    matrix graph (no entry couples the two halves of a dissection), and a
+    solve in that order matches the default SuperLU ordering to rounding, with
+    a do-nothing outflow (channel) and with the pressure pin (square)."""
+    if kind == "square":
+        pb = wl.cavity(J=2, s=0.1, dt=0.01, nsteps=1, nu_mean=0.01, num_mean=0.01, ic_amp=0.1)
+        ms = om.unit_square(8)
+    else:
+        pb = wl.step_channel(J=2, delta=1e-2, s=0.01, dt=0.02)
+        ms = om.step_channel(2)
+    ens = scheme.Ensemble(ms, pb)
+    p = om.nested_dissection(ms, leaf=16)
+    assert np.array_equal(np.sort(p), np.arange(ms.n))
+    V, W = pb.ic(ms.xy)
+    S = ens.shared_matrix(W).tocsr()
+    # first split: the unknowns strictly either side of the first cut never couple
+    nV = ms.nV
+    xy = np.concatenate([np.repeat(ms.xy, 2, axis=0), ms.xy[:nV]])
+    ax = int(np.argmax(xy.max(0) - xy.min(0)))
+    sep = p[-np.count_nonzero(np.isclose(xy[:, ax], xy[p[-1], ax])):]
+    cut = xy[sep[0], ax]
+    assert np.allclose(xy[sep, ax], cut)
+    side = np.sign(np.round(xy[:, ax] - cut, 9))
+    r, c = S.nonzero()
+    assert not np.any(side[r] * side[c] < 0)
+    assert np.any(side < 0) and np.any(side > 0)
+    a = ens.step(V, W, pb.dt, shared_lu=True, ordering="ND")
+    b = ens.step(V, W, pb.dt, shared_lu=True)
+    for x, y in zip(a, b):
+        assert np.abs(x - y).max() <= 1e-11 * max(1.0, np.abs(y).max())
+
+
 def test_member_subset_solve():
     pb = wl.cavity(J=4, s=0.1, dt=0.01, nsteps=1, nu_mean=0.01, num_mean=0.01, ic_amp=0.1)
     ms = om.unit_square(5)
