@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "device.h"
@@ -489,6 +490,67 @@ mhd_status step_energy(mhd_ctx ctx, const StepArgs& a, hipStream_t stv, double* 
     return MHD_OK;
 }
 
+// Right-hand sides of one subproblem (a3): member coefficients c-, c+ and the
+// ensemble mean of the other variable into the given device scratch, then the
+// node kernel.
+mhd_status check_rhs_args(const char* who, mhd_mesh m, const mhd_coeffs* c, int which, int J, const double* self_n,
+                          const double* other_n, const double* nu, const double* nu_m, const double* bc_vals,
+                          const double* rhs) {
+    if (!m) {
+        set_error(std::string(who) + ": null mesh");
+        return MHD_EINVAL;
+    }
+    mhd_status rc = check_coeffs(c);
+    if (rc) return rc;
+    if (!(which == MHD_V_PROBLEM || which == MHD_W_PROBLEM)) {
+        set_error(std::string(who) + ": which must be V or W");
+        return MHD_EINVAL;
+    }
+    if (J < 1 || J > kMaxJ) {
+        set_error(std::string(who) + ": J must be in [1, 4096]");
+        return MHD_EINVAL;
+    }
+    if (!(self_n && other_n && nu && nu_m && rhs)) {
+        set_error(std::string(who) + ": null array");
+        return MHD_EINVAL;
+    }
+    if (!bc_vals && m->d.n_dir != 0) {
+        set_error(std::string(who) + ": null bc_vals with Dirichlet nodes");
+        return MHD_EINVAL;
+    }
+    return MHD_OK;
+}
+
+mhd_status assemble_rhs_impl(const char* who, DevMesh& D, const mhd_coeffs& c, int J, const double* self_n,
+                             const double* other_n, const double* nu, const double* nu_m, const double* forcing,
+                             const double* bc_vals, double* rhs, double* coef, double* mean, hipStream_t st) {
+    hipError_t e = launch_member_coefs(nu, nu_m, J, coef, st);
+    if (e == hipSuccess) e = launch_mean(other_n, mean, 2 * (int64_t)D.nP2, J, st);
+    if (e == hipSuccess) e = launch_rhs(D, c, J, self_n, other_n, mean, coef, forcing, bc_vals, rhs, st);
+    if (e != hipSuccess) {
+        set_error(std::string(who) + ": " + hipGetErrorString(e));
+        return MHD_EHIP;
+    }
+    return MHD_OK;
+}
+
+// A C++ exception (host allocation failure inside a container, for example)
+// must not cross the C ABI: every entry point turns it into a status.
+mhd_status exception_status() {
+    try {
+        throw;
+    } catch (const std::bad_alloc&) {
+        set_error("host allocation failed");
+        return MHD_ENOMEM;
+    } catch (const std::exception& ex) {
+        set_error(std::string("internal error: ") + ex.what());
+        return MHD_EINVAL;
+    } catch (...) {
+        set_error("internal error");
+        return MHD_EINVAL;
+    }
+}
+
 }  // namespace
 }  // namespace mhd
 
@@ -500,16 +562,18 @@ const char* mhd_ens_last_error(void) { return g_last_error.c_str(); }
 
 const char* mhd_ens_version(void) { return "mhd_ens 0.1 (gfx950)"; }
 
-mhd_status mhd_ens_mesh_counts(const mhd_mesh_desc* d, mhd_mesh_info* info) {
+mhd_status mhd_ens_mesh_counts(const mhd_mesh_desc* d, mhd_mesh_info* info) try {
     CHECK_ARG(info, "mhd_ens_mesh_counts: null info");
     HostMesh m;
     mhd_status rc = build_mesh(d, m, true);
     if (rc) return rc;
     mesh_counts(m, info);
     return MHD_OK;
+} catch (...) {
+    return exception_status();
 }
 
-mhd_status mhd_ens_mesh(const mhd_mesh_desc* d, mhd_mesh* out, mhd_mesh_info* info) {
+mhd_status mhd_ens_mesh(const mhd_mesh_desc* d, mhd_mesh* out, mhd_mesh_info* info) try {
     CHECK_ARG(out, "mhd_ens_mesh: null output handle");
     *out = nullptr;
     mhd_mesh m = new (std::nothrow) mhd_mesh_s;
@@ -527,17 +591,21 @@ mhd_status mhd_ens_mesh(const mhd_mesh_desc* d, mhd_mesh* out, mhd_mesh_info* in
     if (info) mesh_counts(m->d.host, info);
     *out = m;
     return MHD_OK;
+} catch (...) {
+    return exception_status();
 }
 
-mhd_status mhd_ens_mesh_coords(mhd_mesh m, double* xy_p2, int32_t* dir_nodes) {
+mhd_status mhd_ens_mesh_coords(mhd_mesh m, double* xy_p2, int32_t* dir_nodes) try {
     CHECK_ARG(m, "mhd_ens_mesh_coords: null mesh");
     if (xy_p2) std::memcpy(xy_p2, m->d.host.xy.data(), sizeof(double) * m->d.host.xy.size());
     if (dir_nodes)
         std::memcpy(dir_nodes, m->d.host.dir_nodes.data(), sizeof(int32_t) * m->d.host.dir_nodes.size());
     return MHD_OK;
+} catch (...) {
+    return exception_status();
 }
 
-mhd_status mhd_ens_mesh_free(mhd_mesh m) {
+mhd_status mhd_ens_mesh_free(mhd_mesh m) try {
     if (!m) return MHD_OK;
     free_list(m->d.allocs);
     for (auto*& t : m->d.tiling) {
@@ -550,9 +618,11 @@ mhd_status mhd_ens_mesh_free(mhd_mesh m) {
     }
     delete m;
     return MHD_OK;
+} catch (...) {
+    return exception_status();
 }
 
-mhd_status mhd_ens_shared_create(mhd_mesh m, int J_max, int restart, mhd_shared* out) {
+mhd_status mhd_ens_shared_create(mhd_mesh m, int J_max, int restart, mhd_shared* out) try {
     CHECK_ARG(out, "mhd_ens_shared_create: null output handle");
     *out = nullptr;
     CHECK_ARG(m, "mhd_ens_shared_create: null mesh");
@@ -568,17 +638,21 @@ mhd_status mhd_ens_shared_create(mhd_mesh m, int J_max, int restart, mhd_shared*
     }
     *out = A;
     return MHD_OK;
+} catch (...) {
+    return exception_status();
 }
 
-mhd_status mhd_ens_shared_free(mhd_shared A) {
+mhd_status mhd_ens_shared_free(mhd_shared A) try {
     if (!A) return MHD_OK;
     free_shared(A->d);
     delete A;
     return MHD_OK;
+} catch (...) {
+    return exception_status();
 }
 
 mhd_status mhd_ens_assemble_shared(mhd_mesh m, const mhd_coeffs* c, const double* z_other, int J, mhd_shared A,
-                                   mhd_stream_t s) {
+                                   mhd_stream_t s) try {
     CHECK_ARG(m && A, "mhd_ens_assemble_shared: null handle");
     CHECK_ARG(A->d.mesh == &m->d, "mhd_ens_assemble_shared: shared handle belongs to another mesh");
     CHECK_ARG(z_other, "mhd_ens_assemble_shared: null z_other");
@@ -589,9 +663,11 @@ mhd_status mhd_ens_assemble_shared(mhd_mesh m, const mhd_coeffs* c, const double
         return MHD_ESHAPE;
     }
     return assemble_shared_impl(m->d, *c, z_other, J, A->d, as_stream(s));
+} catch (...) {
+    return exception_status();
 }
 
-mhd_status mhd_ens_shared_csr(mhd_shared A, mhd_csr_view* v) {
+mhd_status mhd_ens_shared_csr(mhd_shared A, mhd_csr_view* v) try {
     CHECK_ARG(A && v, "mhd_ens_shared_csr: null argument");
     DevMesh& m = *A->d.mesh;
     v->rowptr_A = m.A_rowptr;
@@ -611,33 +687,24 @@ mhd_status mhd_ens_shared_csr(mhd_shared A, mhd_csr_view* v) {
     v->nnz_Bt = m.nnzBt;
     v->nnz_B = m.nnzB;
     return MHD_OK;
+} catch (...) {
+    return exception_status();
 }
 
 mhd_status mhd_ens_assemble_rhs(mhd_mesh m, const mhd_coeffs* c, int which, int J, const double* self_n,
                                 const double* other_n, const double* nu, const double* nu_m, const double* forcing,
-                                const double* bc_vals, double* rhs, mhd_stream_t s) {
-    CHECK_ARG(m, "mhd_ens_assemble_rhs: null mesh");
-    mhd_status rc = check_coeffs(c);
+                                const double* bc_vals, double* rhs, mhd_stream_t s) try {
+    mhd_status rc = check_rhs_args("mhd_ens_assemble_rhs", m, c, which, J, self_n, other_n, nu, nu_m, bc_vals, rhs);
     if (rc) return rc;
-    CHECK_ARG(which == MHD_V_PROBLEM || which == MHD_W_PROBLEM, "mhd_ens_assemble_rhs: which must be V or W");
-    CHECK_ARG(J >= 1 && J <= kMaxJ, "mhd_ens_assemble_rhs: J must be in [1, 4096]");
-    CHECK_ARG(self_n && other_n && nu && nu_m && rhs, "mhd_ens_assemble_rhs: null array");
-    CHECK_ARG(bc_vals || m->d.n_dir == 0, "mhd_ens_assemble_rhs: null bc_vals with Dirichlet nodes");
-    hipStream_t st = as_stream(s);
     DevMesh& D = m->d;
-    hipError_t e = launch_member_coefs(nu, nu_m, J, D.scratch_coef, st);
-    if (e == hipSuccess) e = launch_mean(other_n, D.scratch_mean, 2 * (int64_t)D.nP2, J, st);
-    if (e == hipSuccess)
-        e = launch_rhs(D, *c, J, self_n, other_n, D.scratch_mean, D.scratch_coef, forcing, bc_vals, rhs, st);
-    if (e != hipSuccess) {
-        set_error(std::string("mhd_ens_assemble_rhs: ") + hipGetErrorString(e));
-        return MHD_EHIP;
-    }
-    return MHD_OK;
+    return assemble_rhs_impl("mhd_ens_assemble_rhs", D, *c, J, self_n, other_n, nu, nu_m, forcing, bc_vals, rhs,
+                             D.scratch_coef, D.scratch_mean, as_stream(s));
+} catch (...) {
+    return exception_status();
 }
 
 mhd_status mhd_ens_solve(mhd_shared A, const double* rhs, double* x, int J, const mhd_solver_opts* o,
-                         mhd_solve_stats* st, mhd_stream_t s) {
+                         mhd_solve_stats* st, mhd_stream_t s) try {
     CHECK_ARG(A, "mhd_ens_solve: null handle");
     CHECK_ARG(rhs && x, "mhd_ens_solve: null array");
     mhd_status rc = check_solver_opts(o);
@@ -649,9 +716,11 @@ mhd_status mhd_ens_solve(mhd_shared A, const double* rhs, double* x, int J, cons
     CHECK_ARG(o->restart <= A->d.gw.restart, "mhd_ens_solve: restart larger than the handle's");
     CHECK_ARG(A->d.assembled, "mhd_ens_solve: matrix not assembled");
     return solve_shared(A->d, rhs, x, J, *o, st, as_stream(s));
+} catch (...) {
+    return exception_status();
 }
 
-mhd_status mhd_ens_spmm(mhd_shared A, const void* x, void* y, int J, int precision, mhd_stream_t s) {
+mhd_status mhd_ens_spmm(mhd_shared A, const void* x, void* y, int J, int precision, mhd_stream_t s) try {
     CHECK_ARG(A && x && y, "mhd_ens_spmm: null argument");
     CHECK_ARG(x != y, "mhd_ens_spmm: x and y must not overlap");
     CHECK_ARG(precision == MHD_FP64 || precision == MHD_FP32_IR, "mhd_ens_spmm: bad precision");
@@ -661,15 +730,19 @@ mhd_status mhd_ens_spmm(mhd_shared A, const void* x, void* y, int J, int precisi
     }
     CHECK_ARG(A->d.assembled, "mhd_ens_spmm: matrix not assembled");
     return spmm_shared(A->d, x, y, J, precision, as_stream(s));
+} catch (...) {
+    return exception_status();
 }
 
 mhd_status mhd_ens_timer_enable(int on) { return timer_enable(on); }
 
-mhd_status mhd_ens_timer_read(double* ms, int64_t* launches, double* nJ32, double* nJ64) {
+mhd_status mhd_ens_timer_read(double* ms, int64_t* launches, double* nJ32, double* nJ64) try {
     return timer_read(ms, launches, nJ32, nJ64);
+} catch (...) {
+    return exception_status();
 }
 
-mhd_status mhd_ens_ctx_create(mhd_mesh m, const mhd_ctx_desc* d, mhd_ctx* out) {
+mhd_status mhd_ens_ctx_create(mhd_mesh m, const mhd_ctx_desc* d, mhd_ctx* out) try {
     CHECK_ARG(out, "mhd_ens_ctx_create: null output handle");
     *out = nullptr;
     CHECK_ARG(m && d, "mhd_ens_ctx_create: null argument");
@@ -734,9 +807,11 @@ mhd_status mhd_ens_ctx_create(mhd_mesh m, const mhd_ctx_desc* d, mhd_ctx* out) {
     }
     *out = c;
     return MHD_OK;
+} catch (...) {
+    return exception_status();
 }
 
-mhd_status mhd_ens_ctx_free(mhd_ctx c) {
+mhd_status mhd_ens_ctx_free(mhd_ctx c) try {
     if (!c) return MHD_OK;
     c->graph.reset();
     if (c->side) {
@@ -751,10 +826,12 @@ mhd_status mhd_ens_ctx_free(mhd_ctx c) {
     if (c->host_coef) (void)hipHostFree(c->host_coef);
     delete c;
     return MHD_OK;
+} catch (...) {
+    return exception_status();
 }
 
 mhd_status mhd_ens_autotune(mhd_shared A, int J, int precision, mhd_tune_entry* out, int cap, int* count,
-                            mhd_stream_t s) {
+                            mhd_stream_t s) try {
     CHECK_ARG(A, "mhd_ens_autotune: null handle");
     CHECK_ARG(precision == MHD_FP64 || precision == MHD_FP32_IR, "mhd_ens_autotune: bad precision");
     CHECK_ARG(cap >= 0 && (cap == 0 || out), "mhd_ens_autotune: bad output array");
@@ -773,10 +850,12 @@ mhd_status mhd_ens_autotune(mhd_shared A, int J, int precision, mhd_tune_entry* 
     for (int i = 0; i < n; ++i) out[i] = rep[i];
     if (count) *count = n;
     return MHD_OK;
+} catch (...) {
+    return exception_status();
 }
 
 mhd_status mhd_ens_set_plan(mhd_shared A, int J, int precision, int op, int vec, int group, int deep, int tile,
-                            int waves) {
+                            int waves) try {
     CHECK_ARG(A, "mhd_ens_set_plan: null handle");
     CHECK_ARG(precision == MHD_FP64 || precision == MHD_FP32_IR, "mhd_ens_set_plan: bad precision");
     if (J < 1 || J > A->d.Jmax) {
@@ -784,9 +863,11 @@ mhd_status mhd_ens_set_plan(mhd_shared A, int J, int precision, int op, int vec,
         return MHD_ESHAPE;
     }
     return set_plan(A->d, J, precision, op, vec, group, deep, tile, waves);
+} catch (...) {
+    return exception_status();
 }
 
-mhd_status mhd_ens_get_plan(mhd_shared A, int J, int precision, int op, mhd_tune_entry* out) {
+mhd_status mhd_ens_get_plan(mhd_shared A, int J, int precision, int op, mhd_tune_entry* out) try {
     CHECK_ARG(A && out, "mhd_ens_get_plan: null argument");
     CHECK_ARG(precision == MHD_FP64 || precision == MHD_FP32_IR, "mhd_ens_get_plan: bad precision");
     if (J < 1 || J > A->d.Jmax) {
@@ -794,10 +875,12 @@ mhd_status mhd_ens_get_plan(mhd_shared A, int J, int precision, int op, mhd_tune
         return MHD_ESHAPE;
     }
     return query_plan(A->d, J, precision, op, out);
+} catch (...) {
+    return exception_status();
 }
 
 mhd_status mhd_ens_step(mhd_ctx ctx, double* V, double* W, double* Q, double* R, const mhd_step_inputs* in,
-                        mhd_step_stats* st, mhd_stream_t s) {
+                        mhd_step_stats* st, mhd_stream_t s) try {
     CHECK_ARG(ctx && in, "mhd_ens_step: null argument");
     CHECK_ARG(V && W && Q && R, "mhd_ens_step: null state array");
     hipStream_t stv = as_stream(s);
@@ -852,9 +935,11 @@ mhd_status mhd_ens_step(mhd_ctx ctx, double* V, double* W, double* Q, double* R,
         return MHD_ENOCONV;
     }
     return MHD_OK;
+} catch (...) {
+    return exception_status();
 }
 
-mhd_status mhd_ens_group_create(int n, const mhd_ctx* ctxs, mhd_group* out) {
+mhd_status mhd_ens_group_create(int n, const mhd_ctx* ctxs, mhd_group* out) try {
     CHECK_ARG(out, "mhd_ens_group_create: null output handle");
     *out = nullptr;
     CHECK_ARG(n >= 1 && n <= 64 && ctxs, "mhd_ens_group_create: need 1..64 contexts");
@@ -883,9 +968,11 @@ mhd_status mhd_ens_group_create(int n, const mhd_ctx* ctxs, mhd_group* out) {
     }
     *out = g;
     return MHD_OK;
+} catch (...) {
+    return exception_status();
 }
 
-mhd_status mhd_ens_group_free(mhd_group g) {
+mhd_status mhd_ens_group_free(mhd_group g) try {
     if (!g) return MHD_OK;
     g->graph.reset();
     for (auto s : g->streams)
@@ -895,10 +982,12 @@ mhd_status mhd_ens_group_free(mhd_group g) {
     if (g->fork) (void)hipEventDestroy(g->fork);
     delete g;
     return MHD_OK;
+} catch (...) {
+    return exception_status();
 }
 
 mhd_status mhd_ens_group_step(mhd_group g, double* const* V, double* const* W, double* const* Q, double* const* R,
-                              const mhd_step_inputs* in, mhd_stream_t s) {
+                              const mhd_step_inputs* in, mhd_stream_t s) try {
     CHECK_ARG(g && V && W && Q && R && in, "mhd_ens_group_step: null argument");
     hipStream_t st = as_stream(s);
     CHECK_ARG(st != nullptr, "mhd_ens_group_step: needs a non-null stream (graph capture)");
@@ -966,10 +1055,12 @@ mhd_status mhd_ens_group_step(mhd_group g, double* const* V, double* const* W, d
     }
     MHD_HIP(hipGraphLaunch(g->graph.exec, st));
     return MHD_OK;
+} catch (...) {
+    return exception_status();
 }
 
 mhd_status mhd_ens_adjoint_terminal(mhd_ctx ctx, const double* V, const double* W, double* lamV, double* lamW,
-                                    int J, mhd_stream_t s) {
+                                    int J, mhd_stream_t s) try {
     CHECK_ARG(ctx && V && W && lamV && lamW, "mhd_ens_adjoint_terminal: null argument");
     if (J < 1 || J > ctx->desc.J_max) {
         set_error("mhd_ens_adjoint_terminal: J outside [1, J_max]");
@@ -987,12 +1078,14 @@ mhd_status mhd_ens_adjoint_terminal(mhd_ctx ctx, const double* V, const double* 
         return MHD_EHIP;
     }
     return MHD_OK;
+} catch (...) {
+    return exception_status();
 }
 
 mhd_status mhd_ens_adjoint_step(mhd_ctx ctx, const double* V_n, const double* W_n, const double* V_np1,
                                 const double* W_np1, const double* lamV_np1, const double* lamW_np1,
                                 double* lamV_n, double* lamW_n, const mhd_adjoint_inputs* in, double* grad,
-                                mhd_step_stats* stt, mhd_stream_t s) {
+                                mhd_step_stats* stt, mhd_stream_t s) try {
     CHECK_ARG(ctx && in, "mhd_ens_adjoint_step: null argument");
     CHECK_ARG(ctx->Tv, "mhd_ens_adjoint_step: context created without the adjoint workspace");
     CHECK_ARG(V_n && W_n && V_np1 && W_np1 && lamV_np1 && lamW_np1 && lamV_n && lamW_n,
@@ -1097,10 +1190,12 @@ mhd_status mhd_ens_adjoint_step(mhd_ctx ctx, const double* V_n, const double* W_
         return MHD_ENOCONV;
     }
     return MHD_OK;
+} catch (...) {
+    return exception_status();
 }
 
 mhd_status mhd_ens_adjoint_ic(mhd_ctx ctx, const double* lamV0, const double* lamW0, const double* modes, int nm,
-                              double s_coupling, double* grad_ic, int J, mhd_stream_t s) {
+                              double s_coupling, double* grad_ic, int J, mhd_stream_t s) try {
     CHECK_ARG(ctx && lamV0 && lamW0 && modes && grad_ic, "mhd_ens_adjoint_ic: null argument");
     CHECK_ARG(ctx->dots, "mhd_ens_adjoint_ic: context created without the adjoint workspace");
     CHECK_ARG(nm >= 1 && nm <= 4, "mhd_ens_adjoint_ic: nm must be in [1, 4]");
@@ -1128,6 +1223,8 @@ mhd_status mhd_ens_adjoint_ic(mhd_ctx ctx, const double* lamV0, const double* la
         return MHD_EHIP;
     }
     return MHD_OK;
+} catch (...) {
+    return exception_status();
 }
 
 }  // extern "C"

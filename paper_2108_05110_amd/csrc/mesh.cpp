@@ -39,6 +39,8 @@ struct Grid {
 // the pressure hierarchy stops at a level of at most this many vertices, which
 // is solved with its dense inverse (33 x 33 vertices of a unit-square level)
 constexpr int kCoarseMax = 1100;
+// largest coarsest level whose dense inverse is built (host Gauss-Jordan, about 20 s at 3000)
+constexpr int kCoarseDenseMax = 3000;
 
 Grid make_grid(const mhd_mesh_desc* d, int level) {
     Grid g{};
@@ -541,6 +543,12 @@ mhd_status build_mesh(const mhd_mesh_desc* d, HostMesh& m, bool full) {
             can_halve = ((d->nx >> level) % 2 == 0);
         if (cur.n <= kCoarseMax || !can_halve) break;
         ++level;
+    }
+    if (m.levels.back().n > kCoarseDenseMax) {
+        set_error("mhd_ens_mesh: the pressure multigrid cannot coarsen this mesh to a level of at most " +
+                  std::to_string(kCoarseDenseMax) + " vertices for its dense coarse solve (coarsest level: " +
+                  std::to_string(m.levels.back().n) + " vertices); nx needs more factors of two");
+        return MHD_EINVAL;
     }
     m.pfix = fixed[0];
     m.pin = -1;
