@@ -158,6 +158,24 @@ mhd_status mhd_ens_assemble_rhs(mhd_mesh m, const mhd_coeffs* c, int which, int 
                                 const double* forcing, const double* bc_vals,
                                 double* rhs, mhd_stream_t s);
 
+/* For callers that cannot allocate device memory (code under the caller's own
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc): the same
+ * right-hand sides as mhd_ens_assemble_rhs, same arguments, bitwise the same
+ * result, but the scratch it needs (2 J member coefficients and the 2 nP2
+ * values of the other variable's ensemble mean, 256-byte aligned) lives in a
+ * fixed 32 MiB device array of the library instead of the mesh handle.  The
+ * call allocates nothing.  Each GPU holds its own copy of that array for the
+ * life of the process; calls on one GPU share it and it keeps the last call's
+ * contents (every value is written before it is read), so calls that overlap
+ * on one GPU (concurrent streams or threads) race.  MHD_ESHAPE if
+ * 2 J (rounded up to 32) + 2 nP2 exceeds 4,194,304 doubles, i.e. nP2 above
+ * 2,093,056 at J = 4096. */
+mhd_status mhd_ens_assemble_rhs_noalloc(mhd_mesh m, const mhd_coeffs* c, int which, int J,
+                                        const double* self_n, const double* other_n,
+                                        const double* nu, const double* nu_m,
+                                        const double* forcing, const double* bc_vals,
+                                        double* rhs, mhd_stream_t s);
+
 /* Solver options.  precision: MHD_FP64 (all Krylov work in FP64) or
  * MHD_FP32_IR (FP32 SpMM/preconditioner/Krylov vectors inside FP64 iterative
  * refinement: r = b - S x in FP64, S d = r in FP32, x += d).  rtol: target

@@ -23,7 +23,7 @@ MHD_V_PROBLEM, MHD_W_PROBLEM = 0, 1
 EXPORTS = (
     "mhd_ens_mesh_counts", "mhd_ens_mesh", "mhd_ens_mesh_coords", "mhd_ens_mesh_free",
     "mhd_ens_shared_create", "mhd_ens_shared_free", "mhd_ens_assemble_shared", "mhd_ens_shared_csr",
-    "mhd_ens_assemble_rhs", "mhd_ens_solve", "mhd_ens_ctx_create", "mhd_ens_ctx_free", "mhd_ens_step",
+    "mhd_ens_assemble_rhs", "mhd_ens_assemble_rhs_noalloc", "mhd_ens_solve", "mhd_ens_ctx_create", "mhd_ens_ctx_free", "mhd_ens_step",
     "mhd_ens_spmm", "mhd_ens_timer_enable", "mhd_ens_timer_read", "mhd_ens_last_error", "mhd_ens_version",
     "mhd_ens_adjoint_terminal", "mhd_ens_adjoint_step", "mhd_ens_adjoint_ic",
     "mhd_ens_group_create", "mhd_ens_group_step", "mhd_ens_group_free",
@@ -117,6 +117,7 @@ def lib():
             "mhd_ens_assemble_shared": [P, C.POINTER(Coeffs), P, I, P, P],
             "mhd_ens_shared_csr": [P, C.POINTER(CSRView)],
             "mhd_ens_assemble_rhs": [P, C.POINTER(Coeffs), I, I, P, P, P, P, P, P, P, P],
+            "mhd_ens_assemble_rhs_noalloc": [P, C.POINTER(Coeffs), I, I, P, P, P, P, P, P, P, P],
             "mhd_ens_solve": [P, P, P, I, C.POINTER(SolverOpts), C.POINTER(SolveStats), P],
             "mhd_ens_ctx_create": [P, C.POINTER(CtxDesc), C.POINTER(P)],
             "mhd_ens_ctx_free": [P],
@@ -229,6 +230,13 @@ def mhd_ens_assemble_rhs(mesh, coeffs, which, J, self_n, other_n, nu, nu_m, forc
     check("mhd_ens_assemble_rhs",
           lib().mhd_ens_assemble_rhs(mesh, C.byref(coeffs), which, J, ptr(self_n), ptr(other_n), ptr(nu),
                                      ptr(nu_m), ptr(forcing), ptr(bc_vals), ptr(rhs), stream_ptr(stream)))
+
+
+def mhd_ens_assemble_rhs_noalloc(mesh, coeffs, which, J, self_n, other_n, nu, nu_m, forcing, bc_vals, rhs,
+                                 stream=None):
+    check("mhd_ens_assemble_rhs_noalloc",
+          lib().mhd_ens_assemble_rhs_noalloc(mesh, C.byref(coeffs), which, J, ptr(self_n), ptr(other_n), ptr(nu),
+                                             ptr(nu_m), ptr(forcing), ptr(bc_vals), ptr(rhs), stream_ptr(stream)))
 
 
 def mhd_ens_solve(A, rhs, x, J, opts, stream=None, allow_noconv=False):

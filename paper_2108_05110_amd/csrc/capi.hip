@@ -534,6 +534,43 @@ mhd_status assemble_rhs_impl(const char* who, DevMesh& D, const mhd_coeffs& c, i
     return MHD_OK;
 }
 
+// Fixed device scratch of the allocation-free right-hand side call: 2 J member
+// coefficients, then (at a 256-byte boundary) the 2 nP2 values of the ensemble
+// mean.  4 Mi doubles (32 MiB) per device cover J <= 4096 with nP2 <= 2,093,056
+// (the 1022 x 1022 unit square).  In host code `scratch` names a host-side
+// stand-in, never the device memory: every host use goes through the address
+// that hipGetSymbolAddress returns for the current device.
+constexpr size_t kScratchDoubles = size_t(4) << 20;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+size_t noalloc_mean_offset(int J) { return ((2 * (size_t)J + 31) / 32) * 32; }
+size_t noalloc_rhs_doubles(int J, int64_t nP2) { return noalloc_mean_offset(J) + 2 * (size_t)nP2; }
+
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[64] = {};
+
+// device address of `scratch` on the current device, looked up once per device
+mhd_status scratch_base(const char* who, double** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess || dev < 0 || dev >= 64) {
+        set_error(std::string(who) + ": hipGetDevice: " + hipGetErrorString(e));
+        return MHD_EHIP;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_error(std::string(who) + ": hipGetSymbolAddress(scratch): " + hipGetErrorString(e));
+            return MHD_EHIP;
+        }
+        g_scratch_ptr[dev] = (double*)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return MHD_OK;
+}
+
 // A C++ exception (host allocation failure inside a container, for example)
 // must not cross the C ABI: every entry point turns it into a status.
 mhd_status exception_status() {
@@ -699,6 +736,30 @@ mhd_status mhd_ens_assemble_rhs(mhd_mesh m, const mhd_coeffs* c, int which, int 
     DevMesh& D = m->d;
     return assemble_rhs_impl("mhd_ens_assemble_rhs", D, *c, J, self_n, other_n, nu, nu_m, forcing, bc_vals, rhs,
                              D.scratch_coef, D.scratch_mean, as_stream(s));
+} catch (...) {
+    return exception_status();
+}
+
+mhd_status mhd_ens_assemble_rhs_noalloc(mhd_mesh m, const mhd_coeffs* c, int which, int J, const double* self_n,
+                                        const double* other_n, const double* nu, const double* nu_m,
+                                        const double* forcing, const double* bc_vals, double* rhs, mhd_stream_t s) try {
+    static const char* who = "mhd_ens_assemble_rhs_noalloc";
+    mhd_status rc = check_rhs_args(who, m, c, which, J, self_n, other_n, nu, nu_m, bc_vals, rhs);
+    if (rc) return rc;
+    DevMesh& D = m->d;
+    const size_t need = noalloc_rhs_doubles(J, D.nP2);
+    if (need > kScratchDoubles) {
+        set_error(std::string(who) + ": needs " + std::to_string(need * sizeof(double)) +
+                  " bytes of scratch (2 J member coefficients + 2 nP2 mean values), more than the fixed " +
+                  std::to_string(kScratchDoubles * sizeof(double)) + "-byte device array");
+        return MHD_ESHAPE;
+    }
+    double* base = nullptr;
+    if ((rc = scratch_base(who, &base))) return rc;
+    double* coef = base;
+    double* mean = base + noalloc_mean_offset(J);
+    return assemble_rhs_impl(who, D, *c, J, self_n, other_n, nu, nu_m, forcing, bc_vals, rhs, coef, mean,
+                             as_stream(s));
 } catch (...) {
     return exception_status();
 }
