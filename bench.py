@@ -40,6 +40,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+T_START = time.perf_counter()
+
+
+def log(msg):
+    """Progress line on stderr (the JSON result is the only stdout line)."""
+    print(f"[bench {time.perf_counter() - T_START:7.1f} s] {msg}", file=sys.stderr, flush=True)
 
 
 def spmm_bytes(info, J, word):
@@ -54,6 +60,13 @@ def spmm_bytes(info, J, word):
               + (nP1 + 1) * idx + nnzB * (idx + 2 * word)      # B
               + nP1 * word)                                     # pressure diagonal
     return matrix + 2 * info.n * J * word
+
+
+def spmm_bytes_csr(info, J, word):
+    """Algorithmic bytes of one SpMM with the full saddle-point CSR (the count
+    the throughput targets are stated in): value + int32 column per nonzero,
+    row pointers, x read once and y written once."""
+    return (word + 4) * info.nnz + 4 * (info.n + 1) + 2 * word * info.n * J
 
 
 def source_hash():
@@ -81,14 +94,13 @@ def traffic_from_profiles(J, N, plan):
     return None
 
 
-def cpu_baseline(N, J, seconds_hint=30.0):
-    """FP64 oracle (its own per-member sparse LU) on a bounded sample of the same
-    workload: the v-subproblem of one member in the first step (shared matrix
-    from all J members, that member's right-hand side, its own LU)."""
-    import numpy as np
+def _oracle_v_member(task):
+    """The v-subproblem of one member in the first step of the cavity, as the
+    FP64 oracle computes it: the shared matrix from all J members, that member's
+    right-hand side and its own sparse LU (half a member-step); seconds."""
+    N, J, j = task
     import workloads as wl
     from oracle import mesh as om, scheme
-
     pb = wl.cavity(J=J, s=0.1, dt=0.01)
     ms = om.unit_square(N)
     ens = scheme.Ensemble(ms, pb)
@@ -97,13 +109,81 @@ def cpu_baseline(N, J, seconds_hint=30.0):
     G, _ = pb.bc(pb.dt, ms.xy)
     t0 = time.perf_counter()
     Sv = ens.shared_matrix(W)
-    b = ens.rhs(V[:, :, :1], W[:, :, :1], F1[:, :, :1], G[:, :, :1])
-    ens.solve_members(Sv, b, members=[0])
-    dt = time.perf_counter() - t0
-    return {"value": 0.5 / dt, "unit": "member-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"v-subproblem of 1 member, step 1, {N}x{N} cavity with J={J} members in the "
-                      f"ensemble statistics (= 0.5 member-step), per-member SuperLU, "
-                      f"{dt:.1f} s on one host core"}
+    b = ens.rhs(V, W, F1, G, members=[j])
+    ens.solve_members(Sv, b)
+    return time.perf_counter() - t0
+
+
+def _oracle_v_shared_lu(task):
+    """The same v-subproblem for all J members with one LU shared by them (the
+    paper's saving); seconds."""
+    N, J = task
+    import workloads as wl
+    from oracle import mesh as om, scheme
+    pb = wl.cavity(J=J, s=0.1, dt=0.01)
+    ms = om.unit_square(N)
+    ens = scheme.Ensemble(ms, pb)
+    V, W = pb.ic(ms.xy)
+    F1, _ = pb.forcing(pb.dt, ms.xy)
+    G, _ = pb.bc(pb.dt, ms.xy)
+    t0 = time.perf_counter()
+    Sv = ens.shared_matrix(W)
+    b = ens.rhs(V, W, F1, G)
+    ens.solve_members(Sv, b, shared_lu=True)
+    return time.perf_counter() - t0
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(N, J, max_workers=16):
+    """FP64 oracle on the host, on a bounded sample of the first step: P worker
+    processes (one thread each) each solve the v-subproblem of one member with
+    that member's own sparse LU, all at once (P half member-steps); beside them
+    one more process solves the same v-subproblem for all J members with one
+    shared LU.  P = the host's CPU count, at most the 16-core
+    share of one GPU."""
+    import multiprocessing as mp
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncpu = os.cpu_count() or 1
+    P = max(1, min(ncpu, max_workers))
+    keys = ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")
+    saved = {k: os.environ.get(k) for k in keys}
+    for k in keys:
+        os.environ[k] = "1"
+    try:
+        ctx = mp.get_context("spawn")
+        with ctx.Pool(P + 1) as pool:
+            t0 = time.perf_counter()
+            shared = pool.apply_async(_oracle_v_shared_lu, ((N, J),))
+            times = pool.map(_oracle_v_member, [(N, J, j % J) for j in range(P)], chunksize=1)
+            t_shared = shared.get()
+            wall = time.perf_counter() - t0
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    return {"value": 0.5 * P / max(times), "unit": "member-steps/s", "cores": P, "kind": "oracle",
+            "cpu": cpu_model(),
+            "sample": f"{P} processes x 1 thread at once, each the v-subproblem (half a member-step) of one member "
+                      f"in step 1 of the {N}x{N} cavity with J={J} members in the ensemble statistics, with that "
+                      f"member's own SuperLU; value = {P} x 0.5 / slowest process ({max(times):.1f} s; wall with "
+                      f"start-up {wall:.1f} s)",
+            "shared_lu": {"value": 0.5 * J / t_shared, "unit": "member-steps/s", "cores": 1,
+                          "sample": f"one more process at the same time: the same v-subproblem for all J={J} members "
+                                    f"with one SuperLU factorisation shared by them, {t_shared:.1f} s"}}
 
 
 class Separate:
@@ -188,20 +268,114 @@ def step_accuracy(L, mesh, pb, opts):
     return out
 
 
-def multi_step_error(L, mesh, pb, opts, nsteps=8):
-    """Relative L2 difference after `nsteps` steps from the initial state with
-    `opts` against FP64 solves to 1e-12 (errors of every step accumulated)."""
+def multi_step_error(L, mesh, pb, opts, checkpoints=(8, 200)):
+    """Relative L2 difference after each of `checkpoints` steps from the initial
+    state with `opts` against FP64 solves to 1e-12 (errors of every step
+    accumulated), and the FP64 run's own time per step."""
     import torch
     from paper_2108_05110_amd.ensemble import Stepper
     a = Stepper(mesh, pb, opts=opts, time_dependent_data=False, graph=opts.fixed_cycles > 0)
-    b = Stepper(mesh, pb, opts=L.solver_opts(L.MHD_FP64), time_dependent_data=False)
-    for _ in range(nsteps):
-        a.step(stats=False)
-        b.step(stats=False)
+    b = Stepper(mesh, pb, opts=L.solver_opts(L.MHD_FP64, rtol=1e-11), time_dependent_data=False)
     rel = lambda x, y: float(torch.linalg.norm(x - y) / torch.linalg.norm(y))
-    out = max(rel(a.V, b.V), rel(a.W, b.W))
+    out, t64, worst = {}, 0.0, 0.0
+    for n in range(1, max(checkpoints) + 1):
+        a.step(stats=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = b.step(stats=True, allow_noconv=True)
+        torch.cuda.synchronize()
+        worst = max(worst, st.v.max_relres, st.w.max_relres)
+        if n > 1:
+            t64 += time.perf_counter() - t0
+        if n in checkpoints:
+            out[n] = max(rel(a.V, b.V), rel(a.W, b.W))
+        if n % 25 == 0:
+            log(f"  trajectory step {n}")
+    out["reference_max_relres"] = worst
     a.close()
     b.close()
+    return out, t64 / max(1, max(checkpoints) - 1)
+
+
+def member_problem(pb, j):
+    """Member j of an ensemble problem as a one-member problem (its own data)."""
+    import dataclasses
+    import numpy as np
+    kw = {}
+    for f in dataclasses.fields(pb):
+        v = getattr(pb, f.name)
+        if isinstance(v, np.ndarray) and v.ndim >= 1 and v.shape[0] == pb.J:
+            kw[f.name] = v[j:j + 1].copy()
+    kw["J"] = 1
+    return dataclasses.replace(pb, **kw)
+
+
+def independent_runs(L, mesh, pb, opts, steps):
+    """J independent plain runs on the same GPU: each member advanced by its own
+    one-member step (its own matrices from its own fields and viscosities: the
+    plain decoupled scheme), every step graph-captured; member-steps/s."""
+    import torch
+    from paper_2108_05110_amd.ensemble import Stepper
+    runs = [Stepper(mesh, member_problem(pb, j), opts=opts, time_dependent_data=False,
+                    graph=opts.fixed_cycles > 0) for j in range(pb.J)]
+    for r in runs:
+        r.step(stats=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for r in runs:
+            r.step(stats=False)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    for r in runs:
+        r.close()
+    return pb.J * steps / el
+
+
+def spmm_large(L, wl, torch, N=512, J=128, plan="4,0,6,1608,0"):
+    """The saddle-point SpMM of the 512 x 512 cavity with J = 128 members (FP32),
+    whose operands do not fit the last-level cache: launch time from the HIP
+    events of each dispatch, bytes as the full-CSR count.  The plan is the
+    row-per-lane kernel with 16 x 8 half-step tiles and 16 members per
+    workgroup (the autotuner's pick at this size; pinned so that the bench does
+    not build every candidate's tiling), or "tune"."""
+    from paper_2108_05110_amd.ensemble import Mesh, to_dev
+    log("512^2 SpMM: mesh")
+    mesh = Mesh(L.MHD_MESH_UNIT_SQUARE, N)
+    pb = wl.cavity(J=J, s=0.1, dt=0.01, cfg=4)
+    V, W = pb.ic(mesh.xy)
+    A = L.mhd_ens_shared_create(mesh.handle, J, 1)
+    c = L.Coeffs(pb.dt, pb.mu, float(pb.nu.mean()), float(pb.nu_m.mean()), 0)
+    L.mhd_ens_assemble_shared(mesh.handle, c, to_dev(W), J, A)
+    log("512^2 SpMM: plan")
+    if plan == "tune":
+        rep = L.mhd_ens_autotune(A, J, L.MHD_FP32_IR)
+        plan = next((e for e in rep if e["chosen"] and e["op"] == L.TUNE_SADDLE), None)
+    else:
+        vec, group, deep, tile, waves = (int(v) for v in plan.split(","))
+        L.mhd_ens_set_plan(A, J, L.MHD_FP32_IR, L.TUNE_SADDLE, vec, group, deep, tile, waves)
+        plan = dict(vec=vec, group=group, deep=deep, tile=tile, waves=waves)
+    log("512^2 SpMM: timing")
+    x = torch.randn((mesh.n, J), device="cuda", dtype=torch.float32)
+    y = torch.empty_like(x)
+    for _ in range(3):
+        L.mhd_ens_spmm(A, x, y, J, L.MHD_FP32_IR)
+    torch.cuda.synchronize()
+    L.mhd_ens_timer_enable(True)
+    for _ in range(20):
+        L.mhd_ens_spmm(A, x, y, J, L.MHD_FP32_IR)
+    ms, launches, _, _ = L.mhd_ens_timer_read()
+    L.mhd_ens_timer_enable(False)
+    L.mhd_ens_shared_free(A)
+    avg = ms / 1e3 / max(1, launches)
+    b8 = spmm_bytes_csr(mesh.info, J, 4)
+    out = {"workload": f"cavity {N}x{N} P2-P1, J={J}, FP32", "n_unknowns": int(mesh.n), "nnz": int(mesh.info.nnz),
+           "bytes_per_launch": b8, "avg_launch_us": avg * 1e6, "launches": launches,
+           "achieved": b8 / avg / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": b8 / avg / 1e9 / HBM_PEAK_GBS,
+           "compact_bytes_per_launch": spmm_bytes(mesh.info, J, 4),
+           "kernel": saddle_kernel_name(plan), "plan": {k: plan[k] for k in ("vec", "group", "deep", "tile", "waves")}
+           if plan else None}
+    mesh.close()
     return out
 
 
@@ -262,6 +436,7 @@ def headline(args, L, wl, torch):
     graph = args.schedule == "fixed"
     pb = wl.cavity(J=args.J, s=0.1, dt=0.01)
     mesh = Mesh(L.MHD_MESH_UNIT_SQUARE, args.N)
+    log("autotune")
     plans = tuned_plans(L, wl, mesh, args.J, prec)
     if args.plan:
         # study option: pin the SpMM plan after tuning (the table is process-wide)
@@ -273,6 +448,7 @@ def headline(args, L, wl, torch):
         plans["saddle"] = {"word": 4 if prec == L.MHD_FP32_IR else 8, "vec": vec, "group": group, "deep": deep,
                            "tile": tile, "waves": waves, "us": None, "candidates": 0}
     # timed region: the graph-captured step (fixed schedule) or the adaptive step
+    log("timed steps")
     stp = Stepper(mesh, pb, opts=opts, time_dependent_data=False, graph=graph)
     for _ in range(args.warmup):
         stp.step(stats=False)
@@ -281,6 +457,7 @@ def headline(args, L, wl, torch):
     stp.close()
     # the same schedule eager with the two subproblems one after the other, so that
     # each SpMM runs alone, timed by events its dispatch records
+    log("eager pass with SpMM events")
     eag = Stepper(mesh, pb, opts=opts, time_dependent_data=False, serial=True)
     eag.step(stats=False)
     L.mhd_ens_timer_enable(True)
@@ -291,13 +468,17 @@ def headline(args, L, wl, torch):
     iters = st.v.iters + st.w.iters
     eag.close()
     word = 4 if prec == L.MHD_FP32_IR else 8
-    bpl = spmm_bytes(mesh.info, args.J, word)
+    bpl_compact = spmm_bytes(mesh.info, args.J, word)
+    bpl = spmm_bytes_csr(mesh.info, args.J, word)
     avg_s = (ms / 1e3) / max(launches, 1)
     achieved = bpl / avg_s / 1e9 if launches else None
+    log("one-step accuracy")
     acc = step_accuracy(L, mesh, pb, opts)
-    acc8 = multi_step_error(L, mesh, pb, opts, 8)
+    log(f"{args.traj_steps}-step trajectory against FP64")
+    traj, fp64_s = multi_step_error(L, mesh, pb, opts, (8, args.traj_steps))
     separate = None
     if not args.no_separate:
+        log("J-separate solves")
         sstp = Stepper(mesh, pb, opts=opts, time_dependent_data=False)
         sp = Separate(L, mesh, sstp, opts)
         sp.step()                       # warm-up (and capture)
@@ -313,6 +494,12 @@ def headline(args, L, wl, torch):
                     "shared_over_separate": value / sv}
         sp.close()
         sstp.close()
+        log("J independent runs")
+        iv = independent_runs(L, mesh, pb, opts, args.separate_steps)
+        separate["independent_runs"] = {
+            "value": iv, "unit": "member-steps/s", "steps": args.separate_steps,
+            "form": "J plain one-member runs, each with its own matrices (own fields and viscosities), same schedule, "
+                    "each step graph-captured", "shared_over_independent": value / iv}
     out = {
         "metric": "member-steps/s at 128^2 P2-P1, J=64 (shared vs J-separate); SpMM HBM GB/s",
         "value": value,
@@ -335,17 +522,29 @@ def headline(args, L, wl, torch):
                                 f"adaptive, rtol {args.rtol:g}, {args.sweeps} Jacobi sweeps (damping {args.omega or 0.85:g})"),
                    "krylov_iterations_per_step": iters,
                    "eager_serial_member_steps_per_s": args.J * max(2, args.steps // 2) / e_elapsed,
-                   "step_rel_l2_vs_fp64": acc, "rel_l2_vs_fp64_after_8_steps": acc8},
+                   "step_rel_l2_vs_fp64": acc,
+                   "rel_l2_vs_fp64_after_8_steps": traj.get(8),
+                   f"rel_l2_vs_fp64_after_{args.traj_steps}_steps": traj.get(args.traj_steps),
+                   "trajectory_reference_max_relres": traj.get("reference_max_relres"),
+                   "fp64_mode": {"ms_per_step": 1e3 * fp64_s, "member_steps_per_s": args.J / fp64_s,
+                                 "schedule": "FP64 GMRES with FP64 refinement to rtol 1e-11, adaptive, eager"}},
         "autotune": plans,
         "roofline": {"bound": "hbm",
                      "kernel": f"saddle-point SpMM ({saddle_kernel_name(plans.get('saddle'))})",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
                      "traffic": traffic_from_profiles(args.J, args.N, plans.get("saddle")), "bytes_per_launch": bpl,
+                     "bytes": "full saddle-point CSR: (word + 4) nnz + 4 (n + 1) + 2 word n J",
+                     "compact_bytes_per_launch": bpl_compact,
+                     "compact_frac": (bpl_compact / avg_s / 1e9 / HBM_PEAK_GBS) if launches else None,
                      "avg_launch_us": avg_s * 1e6, "launches": launches},
+        "spmm_512_J128": None if args.no_large_spmm else spmm_large(L, wl, torch, plan=args.large_plan),
         "separate": separate,
-        "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline(args.N, args.J),
+        "cpu_baseline": None,
     }
+    if not args.no_cpu_baseline:
+        log("CPU oracle baseline")
+        out["cpu_baseline"] = cpu_baseline(args.N, args.J)
     mesh.close()
     return out
 
@@ -519,7 +718,10 @@ def main():
     ap.add_argument("--omega", type=float, default=0.0, help="Jacobi damping (0: the library default)")
     ap.add_argument("--rtol", type=float, default=1e-10)
     ap.add_argument("--workload", choices=["cavity", "adjoint", "large", "spmm"], default="cavity")
-    ap.add_argument("--separate-steps", type=int, default=1)
+    ap.add_argument("--separate-steps", type=int, default=5)
+    ap.add_argument("--traj-steps", type=int, default=200, help="steps of the trajectory error against FP64")
+    ap.add_argument("--no-large-spmm", action="store_true")
+    ap.add_argument("--large-plan", default="4,0,6,1608,0", help="SpMM plan at 512^2 (or 'tune')")
     ap.add_argument("--no-separate", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plan", default="", help="pinned SpMM plan vec,group,deep,tile,waves (spmm workload; study "

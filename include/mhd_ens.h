@@ -33,8 +33,15 @@
  *    in the same order.  mhd_ens_mesh_coords returns the coordinates.
  *  - All device work is asynchronous on the caller's stream (0 = the null
  *    stream).  Calls that fill host statistics synchronise that stream.
- *  - No call after creation allocates device memory: every workspace is
- *    sized at creation time from (mesh, J_max, restart).
+ *  - Device memory is allocated only by the create calls (mhd_ens_mesh,
+ *    mhd_ens_shared_create, mhd_ens_ctx_create, mhd_ens_group_create) and by
+ *    the explicit tuning calls (mhd_ens_prepare, mhd_ens_ctx_prepare,
+ *    mhd_ens_autotune, mhd_ens_set_plan), which build the data of the kernel
+ *    plans they choose.  Solves, steps, assemblies and SpMMs never allocate
+ *    (mhd_ens_alloc_stats counts the library's allocations; HIP graph
+ *    instantiation by mhd_ens_step in graph mode is the runtime's own).
+ *    Context creation prepares the plans for J_max; a solve or step with a J
+ *    no tuning call prepared runs the default kernel plans (same results).
  */
 #ifndef MHD_ENS_H
 #define MHD_ENS_H
@@ -94,9 +101,16 @@ mhd_status mhd_ens_mesh_counts(const mhd_mesh_desc* d, mhd_mesh_info* info);
  * them to the current device.  info (host) may be NULL. */
 mhd_status mhd_ens_mesh(const mhd_mesh_desc* d, mhd_mesh* out, mhd_mesh_info* info);
 
-/* Host copies: xy_p2 (nP2*2 doubles, may be NULL), dir_nodes (n_dir int32:
+/* (Section 4: the problem data -- initial values, forcing f_{1,j}, f_{2,j},
+ * boundary values -- are given as functions of x and enter the scheme as
+ * their values at the P2 nodes.)  Host copies of what a caller needs to
+ * evaluate them: xy_p2 (nP2*2 doubles, may be NULL), dir_nodes (n_dir int32:
  * the Dirichlet P2 nodes in the order bc arrays use, may be NULL). */
 mhd_status mhd_ens_mesh_coords(mhd_mesh m, double* xy_p2, int32_t* dir_nodes);
+
+/* Releases a mesh and everything mhd_ens_mesh built for it (Section 2's
+ * finite element spaces on that triangulation).  Handles created from it
+ * must be freed first.  NULL is accepted. */
 mhd_status mhd_ens_mesh_free(mhd_mesh m);
 
 /* Coefficients of one subproblem (Algorithm 1): time step dt, eddy tuning
@@ -126,8 +140,9 @@ mhd_status mhd_ens_shared_free(mhd_shared A);
 mhd_status mhd_ens_assemble_shared(mhd_mesh m, const mhd_coeffs* c, const double* z_other,
                                    int J, mhd_shared A, mhd_stream_t s);
 
-/* Borrowed device views of the assembled operator (valid until the next
- * assemble or free).  Scalar P2 block A: rowptr_A (nP2+1), col_A (nnz_A),
+/* (Algorithm 1, the one left-hand side of each subproblem; Section 2's mixed
+ * form with the divergence constraint) Borrowed device views of the
+ * assembled operator (valid until the next assemble or free).  Scalar P2 block A: rowptr_A (nP2+1), col_A (nnz_A),
  * val_A (nnz_A, FP64).  B^T: rowptr_Bt (nP2+1), col_Bt (P1 ids), val_Bt
  * (2 per entry: x then y component).  B: rowptr_B (nP1+1), col_B (P2 ids),
  * val_B (2 per entry).  D_p: (nP1) pressure diagonal (1 at the pin, else 0). */
@@ -150,13 +165,16 @@ mhd_status mhd_ens_shared_csr(mhd_shared A, mhd_csr_view* view);
  *   forcing:         device (nP2,2,J) FP64 nodal f at t^{n+1}, or NULL (= 0)
  *   bc_vals:         device (n_dir,2,J) FP64 Dirichlet values at t^{n+1},
  *                    in mhd_ens_mesh_coords' dir_nodes order
- *   rhs:             device (n,J) FP64 output
- * The forcing functional (f, chi) is taken as M times the nodal interpolant. */
+ *   rhs:             device (n,J) output, every row written: double for
+ *                    precision MHD_FP64, float for MHD_FP32_IR (the same
+ *                    FP64 arithmetic, rounded once when stored)
+ * The forcing functional (f, chi) is taken as M times the nodal interpolant.
+ * One kernel pass over the elements (no element buffer), deterministic. */
 mhd_status mhd_ens_assemble_rhs(mhd_mesh m, const mhd_coeffs* c, int which, int J,
                                 const double* self_n, const double* other_n,
                                 const double* nu, const double* nu_m,
                                 const double* forcing, const double* bc_vals,
-                                double* rhs, mhd_stream_t s);
+                                void* rhs, int precision, mhd_stream_t s);
 
 /* For callers that cannot allocate device memory (code under the caller's own
  * HIP graph capture, serving loops, harnesses that forbid hipMalloc): the same
@@ -174,7 +192,7 @@ mhd_status mhd_ens_assemble_rhs_noalloc(mhd_mesh m, const mhd_coeffs* c, int whi
                                         const double* self_n, const double* other_n,
                                         const double* nu, const double* nu_m,
                                         const double* forcing, const double* bc_vals,
-                                        double* rhs, mhd_stream_t s);
+                                        void* rhs, int precision, mhd_stream_t s);
 
 /* Solver options.  precision: MHD_FP64 (all Krylov work in FP64) or
  * MHD_FP32_IR (FP32 SpMM/preconditioner/Krylov vectors inside FP64 iterative
@@ -203,13 +221,39 @@ typedef struct {
                                  report max_relres = -1, converged = -1              */
     double jacobi_omega;      /* damping of the velocity-block Jacobi sweeps, in (0, 1.5];
                                  0 = the default 0.85                                 */
+    int mg_unfused;           /* 0 (default): on each multigrid level above the coarsest
+                                 the residual and its restriction run as one precomputed
+                                 sparse operator, and so do the prolongation and the first
+                                 post-smoothing sweep (4 launches per level instead of 6);
+                                 1: one kernel per sweep, residual and transfer (the same
+                                 arithmetic up to rounding)                              */
+    int block_krylov;         /* 1: block GMRES, one Krylov space shared by the J columns
+                                 (block Gram-Schmidt with a second pass, pivoted Cholesky
+                                 QR of each new block that deflates dependent directions,
+                                 block least squares on the host); adaptive schedule only,
+                                 J in {16, 32, 64, 128}.  0 (default): one Arnoldi process
+                                 per member over the shared SpMM                        */
 } mhd_solver_opts;
 
 typedef struct {
     int iters;                /* total inner Krylov iterations                        */
     int cycles;               /* outer refinement / restart cycles                    */
-    double max_relres;        /* max over members of the final relative residual      */
-    int converged;            /* 1 if every member reached rtol                       */
+    double max_relres;        /* max over members of the final relative residual
+                                 ||b_j - S x_j||_2 / ||b_j||_2 (NaN if a residual is not
+                                 finite); with a fixed schedule computed after the solve
+                                 when stats are requested                              */
+    int converged;            /* 1 if every member reached rtol, 0 if not, -1 for a
+                                 fixed schedule (no target)                            */
+    int nonfinite;            /* members whose final residual is NaN or Inf (the call
+                                 then returns MHD_ENOCONV)                              */
+    double* relres;           /* host (J) or NULL, set by the caller: each member's final
+                                 relative residual                                     */
+    int32_t* member_iters;    /* host (J) or NULL, set by the caller: inner iterations
+                                 after which member j's residual first met rtol (all
+                                 members run one shared Krylov schedule, so the total
+                                 if never, and the total for a fixed schedule)         */
+    int min_block_rank;       /* block GMRES: the smallest rank of a basis block after
+                                 deflation; J for the per-member solver                */
 } mhd_solve_stats;
 
 /* (Section 1: A [x_1|...|x_J] = [b_1|...|b_J]) Solves S X = B for the J
@@ -220,7 +264,10 @@ typedef struct {
  * M/dt + nu_c K, inverted by a Galerkin multigrid V-cycle on the nested P1
  * grids).  rhs (n,J) FP64 device; x (n,J) FP64 device: initial
  * guess in, solution out.  st (host) may be NULL; if non-NULL the stream is
- * synchronised.  Returns MHD_ENOCONV (x = best iterate) if maxit is hit. */
+ * synchronised (with a fixed schedule the final residuals are then computed,
+ * outside graph capture).  Returns MHD_ENOCONV (x = best iterate) if maxit is
+ * hit or a residual is not finite.  Allocates nothing and tunes nothing: the
+ * node-row kernels run the plans mhd_ens_prepare chose for this J. */
 mhd_status mhd_ens_solve(mhd_shared A, const double* rhs, double* x, int J,
                          const mhd_solver_opts* o, mhd_solve_stats* st, mhd_stream_t s);
 
@@ -250,15 +297,27 @@ typedef struct {
     int J;
 } mhd_step_inputs;
 
+/* Warning bits of a step (Section 3.1: the stability and convergence theorems
+ * assume alpha_j = nu_bar + num_bar - |nu_j - nu_m,j| - |nu_j' + nu_m,j'| > 0
+ * for every member and mu > 1/2; the scheme still runs without them). */
+#define MHD_WARN_ALPHA      1   /* some alpha_j <= 0                                   */
+#define MHD_WARN_MU         2   /* mu <= 1/2                                           */
+#define MHD_WARN_NONFINITE  4   /* a final residual is NaN or Inf (step returns ENOCONV) */
+
 typedef struct {
-    mhd_solve_stats v, w;
+    mhd_solve_stats v, w;         /* per subproblem; set v.relres etc. for per-member arrays */
     double energy;                /* E_h^{n+1} = (||<v>||^2 + ||<w>||^2)/2 (Section 4.2)   */
+    int warnings;                 /* MHD_WARN_* bits                                       */
+    double min_alpha;             /* min_j alpha_j of this step's parameters               */
 } mhd_step_stats;
 
 /* (Algorithm 1, one step n -> n+1 for all members) V, W: device (nP2,2,J)
  * FP64, in: t^n, out: t^{n+1}.  Q, R: device (nP1,J) FP64, in: pressure of
  * t^n (initial guess), out: pressures of t^{n+1} (zero mean when the pressure
- * is pinned).  st (host) may be NULL (then no synchronisation). */
+ * is pinned).  st (host) may be NULL (then no synchronisation); if non-NULL
+ * the stream is synchronised and, with a fixed schedule, the final residuals
+ * of both subproblems are computed.  Returns MHD_ENOCONV if a solve hit maxit
+ * or a residual is not finite.  Allocates nothing. */
 mhd_status mhd_ens_step(mhd_ctx ctx, double* V, double* W, double* Q, double* R,
                         const mhd_step_inputs* in, mhd_step_stats* st, mhd_stream_t s);
 
@@ -274,9 +333,9 @@ mhd_status mhd_ens_spmm(mhd_shared A, const void* x, void* y, int J, int precisi
  * preconditioner, and the FP64 residual r = b - S x.  For each one the tuner
  * times every candidate launch shape on the handle's own workspace.  It keeps
  * the fastest in a process-wide table keyed by (mesh, J, word size).
- * mhd_ens_solve and mhd_ens_step tune missing entries on first use; under
- * graph capture they use the table as it stands (or a default plan).  This
- * call re-tunes unconditionally.  Candidates:
+ * mhd_ens_prepare and context creation tune missing entries; solves and steps
+ * use the table as it stands (or a default plan where this handle lacks a
+ * plan's data).  This call re-tunes unconditionally.  Candidates:
  *   gather kernels (each wavefront reads its rows' node values from memory):
  *     vec   = members per lane per load: 1, 2, 4 for FP32 and 1, 2 for FP64,
  *             with J a multiple of 32 vec;
@@ -353,6 +412,22 @@ mhd_status mhd_ens_set_plan(mhd_shared A, int J, int precision, int op, int vec,
  * default plan used when the table has none (chosen = 0, us = -1).  Host only:
  * no device work, no synchronisation.  out: host, one entry. */
 mhd_status mhd_ens_get_plan(mhd_shared A, int J, int precision, int op, mhd_tune_entry* out);
+
+/* (Section 1: one matrix for all J members, so its kernels are tuned once per
+ * shape) Prepares a shared-matrix handle for solves with J columns in the
+ * given precision: tunes the node-row operators whose plans the process-wide
+ * table lacks (as mhd_ens_autotune, without re-tuning) and builds this
+ * handle's tilings and packed entries for the chosen plans.  Allocates device
+ * memory and synchronises the stream; not under graph capture. */
+mhd_status mhd_ens_prepare(mhd_shared A, int J, int precision, mhd_stream_t s);
+
+/* mhd_ens_prepare for both subproblem handles of a context, at the context's
+ * precision (context creation already did it for J_max). */
+mhd_status mhd_ens_ctx_prepare(mhd_ctx ctx, int J, mhd_stream_t s);
+
+/* Diagnostics: number and total bytes of the device allocations this library
+ * has made since it was loaded (host, either may be NULL). */
+mhd_status mhd_ens_alloc_stats(int64_t* count, int64_t* bytes);
 
 /* Diagnostics: while enabled, every saddle-point SpMM launch of this library
  * (inside mhd_ens_solve / mhd_ens_step and mhd_ens_spmm, outside graph

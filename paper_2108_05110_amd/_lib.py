@@ -28,6 +28,7 @@ EXPORTS = (
     "mhd_ens_adjoint_terminal", "mhd_ens_adjoint_step", "mhd_ens_adjoint_ic",
     "mhd_ens_group_create", "mhd_ens_group_step", "mhd_ens_group_free",
     "mhd_ens_autotune", "mhd_ens_set_plan", "mhd_ens_get_plan",
+    "mhd_ens_prepare", "mhd_ens_ctx_prepare", "mhd_ens_alloc_stats",
 )
 
 
@@ -70,11 +71,14 @@ class CSRView(C.Structure):
 class SolverOpts(C.Structure):
     _fields_ = [("precision", C.c_int), ("rtol", C.c_double), ("inner_rtol", C.c_double), ("maxit", C.c_int),
                 ("restart", C.c_int), ("jacobi_sweeps", C.c_int), ("check_every", C.c_int),
-                ("cgs_passes", C.c_int), ("fixed_cycles", C.c_int), ("jacobi_omega", C.c_double)]
+                ("cgs_passes", C.c_int), ("fixed_cycles", C.c_int), ("jacobi_omega", C.c_double),
+                ("mg_unfused", C.c_int), ("block_krylov", C.c_int)]
 
 
 class SolveStats(C.Structure):
-    _fields_ = [("iters", C.c_int), ("cycles", C.c_int), ("max_relres", C.c_double), ("converged", C.c_int)]
+    _fields_ = [("iters", C.c_int), ("cycles", C.c_int), ("max_relres", C.c_double), ("converged", C.c_int),
+                ("nonfinite", C.c_int), ("relres", C.POINTER(C.c_double)), ("member_iters", C.POINTER(C.c_int32)),
+                ("min_block_rank", C.c_int)]
 
 
 class CtxDesc(C.Structure):
@@ -93,7 +97,28 @@ class StepInputs(C.Structure):
 
 
 class StepStats(C.Structure):
-    _fields_ = [("v", SolveStats), ("w", SolveStats), ("energy", C.c_double)]
+    _fields_ = [("v", SolveStats), ("w", SolveStats), ("energy", C.c_double), ("warnings", C.c_int),
+                ("min_alpha", C.c_double)]
+
+
+MHD_WARN_ALPHA, MHD_WARN_MU, MHD_WARN_NONFINITE = 1, 2, 4
+
+
+def _member_arrays(st, J):
+    """Attaches host arrays for the per-member statistics (kept alive on st)."""
+    st._keep = []
+    for q in ((st.v, st.w) if isinstance(st, StepStats) else (st,)):
+        r = (C.c_double * J)()
+        it = (C.c_int32 * J)()
+        q.relres = C.cast(r, C.POINTER(C.c_double))
+        q.member_iters = C.cast(it, C.POINTER(C.c_int32))
+        st._keep += [r, it]
+    return st
+
+
+def member_stats(q, J):
+    """(relres, member_iters) lists of one subproblem's statistics."""
+    return [q.relres[j] for j in range(J)], [q.member_iters[j] for j in range(J)]
 
 
 _lib = None
@@ -116,8 +141,8 @@ def lib():
             "mhd_ens_shared_free": [P],
             "mhd_ens_assemble_shared": [P, C.POINTER(Coeffs), P, I, P, P],
             "mhd_ens_shared_csr": [P, C.POINTER(CSRView)],
-            "mhd_ens_assemble_rhs": [P, C.POINTER(Coeffs), I, I, P, P, P, P, P, P, P, P],
-            "mhd_ens_assemble_rhs_noalloc": [P, C.POINTER(Coeffs), I, I, P, P, P, P, P, P, P, P],
+            "mhd_ens_assemble_rhs": [P, C.POINTER(Coeffs), I, I, P, P, P, P, P, P, P, I, P],
+            "mhd_ens_assemble_rhs_noalloc": [P, C.POINTER(Coeffs), I, I, P, P, P, P, P, P, P, I, P],
             "mhd_ens_solve": [P, P, P, I, C.POINTER(SolverOpts), C.POINTER(SolveStats), P],
             "mhd_ens_ctx_create": [P, C.POINTER(CtxDesc), C.POINTER(P)],
             "mhd_ens_ctx_free": [P],
@@ -126,6 +151,9 @@ def lib():
             "mhd_ens_autotune": [P, I, I, C.POINTER(TuneEntry), I, C.POINTER(I), P],
             "mhd_ens_set_plan": [P, I, I, I, I, I, I, I, I],
             "mhd_ens_get_plan": [P, I, I, I, C.POINTER(TuneEntry)],
+            "mhd_ens_prepare": [P, I, I, P],
+            "mhd_ens_ctx_prepare": [P, I, P],
+            "mhd_ens_alloc_stats": [C.POINTER(C.c_int64), C.POINTER(C.c_int64)],
             "mhd_ens_timer_enable": [I],
             "mhd_ens_adjoint_terminal": [P, P, P, P, P, I, P],
             "mhd_ens_adjoint_step": [P, P, P, P, P, P, P, P, P, C.POINTER(AdjointInputs), P,
@@ -226,21 +254,29 @@ def mhd_ens_shared_csr(A):
     return v
 
 
+def _rhs_precision(rhs):
+    import torch
+    return MHD_FP32_IR if rhs.dtype == torch.float32 else MHD_FP64
+
+
 def mhd_ens_assemble_rhs(mesh, coeffs, which, J, self_n, other_n, nu, nu_m, forcing, bc_vals, rhs, stream=None):
+    """rhs: float64 or float32 tensor (n, J); the output precision follows its dtype."""
     check("mhd_ens_assemble_rhs",
           lib().mhd_ens_assemble_rhs(mesh, C.byref(coeffs), which, J, ptr(self_n), ptr(other_n), ptr(nu),
-                                     ptr(nu_m), ptr(forcing), ptr(bc_vals), ptr(rhs), stream_ptr(stream)))
+                                     ptr(nu_m), ptr(forcing), ptr(bc_vals), ptr(rhs), _rhs_precision(rhs),
+                                     stream_ptr(stream)))
 
 
 def mhd_ens_assemble_rhs_noalloc(mesh, coeffs, which, J, self_n, other_n, nu, nu_m, forcing, bc_vals, rhs,
                                  stream=None):
     check("mhd_ens_assemble_rhs_noalloc",
           lib().mhd_ens_assemble_rhs_noalloc(mesh, C.byref(coeffs), which, J, ptr(self_n), ptr(other_n), ptr(nu),
-                                             ptr(nu_m), ptr(forcing), ptr(bc_vals), ptr(rhs), stream_ptr(stream)))
+                                             ptr(nu_m), ptr(forcing), ptr(bc_vals), ptr(rhs), _rhs_precision(rhs),
+                                             stream_ptr(stream)))
 
 
 def mhd_ens_solve(A, rhs, x, J, opts, stream=None, allow_noconv=False):
-    st = SolveStats()
+    st = _member_arrays(SolveStats(), J)
     allow = (MHD_OK, MHD_ENOCONV) if allow_noconv else (MHD_OK,)
     rc = check("mhd_ens_solve", lib().mhd_ens_solve(A, ptr(rhs), ptr(x), J, C.byref(opts), C.byref(st),
                                                     stream_ptr(stream)), allow)
@@ -258,11 +294,25 @@ def mhd_ens_ctx_free(ctx):
 
 
 def mhd_ens_step(ctx, V, W, Q, R, inputs, stats=True, stream=None, allow_noconv=False):
-    st = StepStats() if stats else None
+    st = _member_arrays(StepStats(), inputs.J) if stats else None
     allow = (MHD_OK, MHD_ENOCONV) if allow_noconv else (MHD_OK,)
     check("mhd_ens_step", lib().mhd_ens_step(ctx, ptr(V), ptr(W), ptr(Q), ptr(R), C.byref(inputs),
                                              C.byref(st) if st is not None else None, stream_ptr(stream)), allow)
     return st
+
+
+def mhd_ens_prepare(A, J, precision, stream=None):
+    check("mhd_ens_prepare", lib().mhd_ens_prepare(A, J, precision, stream_ptr(stream)))
+
+
+def mhd_ens_ctx_prepare(ctx, J, stream=None):
+    check("mhd_ens_ctx_prepare", lib().mhd_ens_ctx_prepare(ctx, J, stream_ptr(stream)))
+
+
+def mhd_ens_alloc_stats():
+    n, b = C.c_int64(), C.c_int64()
+    check("mhd_ens_alloc_stats", lib().mhd_ens_alloc_stats(C.byref(n), C.byref(b)))
+    return n.value, b.value
 
 
 def mhd_ens_spmm(A, x, y, J, precision, stream=None):
@@ -346,10 +396,10 @@ def mhd_ens_group_free(group):
 
 
 def solver_opts(precision=MHD_FP64, rtol=None, inner_rtol=None, maxit=2000, restart=30, jacobi_sweeps=6,
-                check_every=1, cgs_passes=0, fixed_cycles=0, jacobi_omega=0.0):
+                check_every=1, cgs_passes=0, fixed_cycles=0, jacobi_omega=0.0, mg_unfused=0, block_krylov=0):
     if rtol is None:
         rtol = 1e-12 if precision == MHD_FP64 else 1e-11
     if inner_rtol is None:
         inner_rtol = 1e-8 if precision == MHD_FP64 else 1e-4
     return SolverOpts(precision, rtol, inner_rtol, maxit, restart, jacobi_sweeps, check_every, cgs_passes,
-                      fixed_cycles, jacobi_omega)
+                      fixed_cycles, jacobi_omega, mg_unfused, block_krylov)

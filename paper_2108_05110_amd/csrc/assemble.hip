@@ -296,183 +296,186 @@ __global__ void k_member_coefs(const double* __restrict__ nu, const double* __re
     }
 }
 
-// One P2 node per group of JP lanes; lanes over members.
-//   b = M (self/dt + f) - cm K other - cp K self - b*(other - <other>, self, .)
-__global__ void __launch_bounds__(kBlock) k_rhs(
-    const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col, const double* __restrict__ valM,
-    const double* __restrict__ valK, const int32_t* __restrict__ inc_ptr, const int32_t* __restrict__ inc,
-    const int32_t* __restrict__ tri, const double* __restrict__ geo, const int32_t* __restrict__ dir_index,
+// -------------------------------------------------------------- (a3) right-hand sides in one pass
+// Every wavefront owns a strip of the structured cell grid and a slice of M
+// members.  Its lanes are SLOTS = 64 / M element slots of M members each; a
+// slot computes one element's 6 x 2 local rows for its members,
+//   r = M_e (self/dt + f) - K_e (cm other + cp self) - C_e(other - <other>) self,
+// with M_e = det Mhat, K_e = det sum_pq G_pq Khat_pq and the convection matrix
+// C_e = sum_b sum_p T[.][b][.][p] uh[b][p] (uh = det J^-1 (other - <other>) at
+// node b).  In the skew-symmetric form C_e is antisymmetric, so only its 15
+// upper entries are formed (the strict upper triangle of the 6 x 6 matrix).
+//
+// Strip: 2 SLOTS - 1 owned cell columns plus one halo column on the left, KS
+// owned cell rows plus one halo row below.  The wavefront walks the rows
+// upwards; each row runs in four colour phases (lower triangles of the even,
+// then odd slot cells, then the upper ones), whose elements share no node, so
+// every lane adds its rows to distinct node accumulators.  Accumulators live in
+// LDS for the three node lines a cell row touches (line K mod 3); a line is
+// final, and written to b, once the rows below and above it are done.  Every
+// node therefore sums its elements in the same order (row, then the four
+// colours) whatever the strip shape: the result is deterministic, without
+// atomics and without an element buffer.  Dirichlet rows take g, pressure rows
+// are zero; each P2 node is owned by exactly one wavefront.
+struct RhsGrid {
+    int nx, ny, nstrips, nseg, nslices, ks;
+};
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename TO, int M>
+__global__ void __launch_bounds__(kBlock) k_rhs_strip(
+    const int32_t* __restrict__ cell_el, const int32_t* __restrict__ hs_p2, const int32_t* __restrict__ tri,
+    const double* __restrict__ geo, const int32_t* __restrict__ dir_index, const int32_t* __restrict__ p1_of_p2,
     const double* __restrict__ self, const double* __restrict__ other, const double* __restrict__ obar,
     const double* __restrict__ coef, const double* __restrict__ F, const double* __restrict__ G,
-    double* __restrict__ b, int nP2, int nP1, int J, int JP, double inv_dt, int convective) {
-    Lanes L = lanes(JP);
-    int64_t i = L.unit;
-    if (i >= (int64_t)nP2 + nP1) return;
-    if (i >= nP2) {   // pressure rows: zero
-        int64_t k = i - nP2;
-        for (int j = L.j0; j < J; j += JP) b[(2 * (int64_t)nP2 + k) * J + j] = 0.0;
-        return;
-    }
-    int di = dir_index[i];
-    if (di >= 0) {
-        for (int j = L.j0; j < J; j += JP) {
-            b[(2 * i) * J + j] = G[(2 * (int64_t)di) * J + j];
-            b[(2 * i + 1) * J + j] = G[(2 * (int64_t)di + 1) * J + j];
+    TO* __restrict__ b, RhsGrid gd, int nP2, int J, double inv_dt, int convective) {
+    constexpr int SLOTS = 64 / M;
+    constexpr int TXO = 2 * SLOTS - 1;          // owned cell columns
+    constexpr int NODES = 2 * TXO;              // owned half-step columns
+    constexpr int LINE = NODES * 2 * M;         // accumulators of one node line
+    // half-step offsets of the local nodes of the lower and upper triangle of a cell
+    constexpr int dI[2][6] = {{0, 2, 2, 1, 2, 1}, {0, 2, 0, 1, 1, 0}};
+    constexpr int dK[2][6] = {{0, 0, 2, 0, 1, 1}, {0, 2, 2, 1, 2, 1}};
+    __shared__ double lds[kBlock / 64][3 * LINE];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t w = xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) + wv;
+    if (w >= (int64_t)gd.nstrips * gd.nseg * gd.nslices) return;    // whole wavefront; no block barrier below
+    const int strip = (int)(w % gd.nstrips);
+    const int seg = (int)((w / gd.nstrips) % gd.nseg);
+    const int slice = (int)(w / ((int64_t)gd.nstrips * gd.nseg));
+    const int slot = lane / M, mem = lane % M;
+    const int j = slice * M + mem;
+    const bool live = j < J;
+    const int ci0 = strip * TXO, ck0 = seg * gd.ks;
+    const int NXh = 2 * gd.nx + 1;
+    const int I0 = 2 * ci0, I1 = min(I0 + NODES, NXh);                  // owned columns [I0, I1)
+    const int K0 = 2 * ck0, K1 = min(2 * (ck0 + gd.ks), 2 * gd.ny + 1); // owned lines [K0, K1)
+    double* L = lds[wv];
+    const double cm = live ? coef[j] : 0.0, cp = live ? coef[J + j] : 0.0;
+
+    auto zero_line = [&](int K) {
+        double* ln = L + (K % 3) * LINE;
+        for (int q = lane; q < LINE; q += 64) ln[q] = 0.0;
+    };
+    auto flush_line = [&](int K) {
+        if (K < K0 || K >= K1) return;
+        const double* ln = L + (K % 3) * LINE;
+        for (int q = lane; q < LINE; q += 64) {
+            const int mm = q % M, d = (q / M) & 1, nd = q / (2 * M);
+            const int I = I0 + nd, jj = slice * M + mm;
+            if (I >= I1 || jj >= J) continue;
+            const int id = hs_p2[(int64_t)K * NXh + I];
+            if (id < 0) continue;
+            const int di = dir_index[id];
+            const double v = di >= 0 ? G[(2 * (int64_t)di + d) * J + jj] : ln[q];
+            b[(2 * (int64_t)id + d) * J + jj] = (TO)v;
+            const int p1 = p1_of_p2[id];
+            if (d == 0 && p1 >= 0) b[(2 * (int64_t)nP2 + p1) * J + jj] = (TO)0;
         }
-        return;
-    }
-    const int32_t p0 = rowptr[i], p1 = rowptr[i + 1];
-    const int32_t q0 = inc_ptr[i], q1 = inc_ptr[i + 1];
-    for (int j = L.j0; j < J; j += JP) {
-        const double cm = coef[j], cp = coef[J + j];
-        double acc0 = 0.0, acc1 = 0.0;
-        for (int32_t p = p0; p < p1; ++p) {
-            const int64_t k = col[p];
-            const double m = valM[p], kk = valK[p];
-            const double s0 = self[(2 * k) * J + j], s1 = self[(2 * k + 1) * J + j];
-            const double o0 = other[(2 * k) * J + j], o1 = other[(2 * k + 1) * J + j];
-            double f0 = 0.0, f1 = 0.0;
-            if (F) {
-                f0 = F[(2 * k) * J + j];
-                f1 = F[(2 * k + 1) * J + j];
+    };
+
+    const int k_first = max(ck0 - 1, 0), k_last = min(ck0 + gd.ks, gd.ny) - 1;
+    for (int k = k_first; k <= k_last; ++k) {
+        if (k == k_first) zero_line(2 * k);
+        zero_line(2 * k + 1);
+        zero_line(2 * k + 2);
+        wave_sync();
+#pragma unroll 1
+        for (int ph = 0; ph < 4; ++ph) {
+            const int up = ph >> 1;
+            const int i = ci0 - 1 + 2 * slot + (ph & 1);
+            int e = -1;
+            if (live && i >= 0 && i < gd.nx) {
+                const int c = cell_el[(int64_t)k * gd.nx + i];
+                if (c >= 0) e = c + up;
             }
-            acc0 += m * (s0 * inv_dt + f0) - kk * (cm * o0 + cp * s0);
-            acc1 += m * (s1 * inv_dt + f1) - kk * (cm * o1 + cp * s1);
-        }
-        for (int32_t q = q0; q < q1; ++q) {
-            const int32_t ea = inc[q];
-            const int64_t e = ea >> 3;
-            const int a = ea & 7;
-            Geo g = load_geo(geo, e);
-            int t[6];
-            double uh[6][2];
-#pragma unroll
-            for (int bb = 0; bb < 6; ++bb) {
-                t[bb] = tri[e * 6 + bb];
-                const double u0 = other[(int64_t)(2 * t[bb]) * J + j] - obar[2 * t[bb]];
-                const double u1 = other[(int64_t)(2 * t[bb] + 1) * J + j] - obar[2 * t[bb] + 1];
-                uh[bb][0] = g.det * (g.Ji[0][0] * u0 + g.Ji[0][1] * u1);
-                uh[bb][1] = g.det * (g.Ji[1][0] * u0 + g.Ji[1][1] * u1);
-            }
-#pragma unroll
-            for (int c = 0; c < 6; ++c) {
-                double cf = 0.0;
+            if (e >= 0) {
+                // the reference tables are read per element through a pointer the
+                // compiler cannot see through, so that it streams them from the
+                // scalar cache instead of holding all of them in registers
+                const RefTables* R = &c_ref;
+                asm volatile("" : "+s"(R));
+                const Geo g = load_geo(geo, e);
+                double s[6][2], ms[6][2], ks[6][2], uh[6][2];
 #pragma unroll
                 for (int bb = 0; bb < 6; ++bb) {
-                    if (convective)
-                        cf += c_ref.That[a][bb][c][0] * uh[bb][0] + c_ref.That[a][bb][c][1] * uh[bb][1];
-                    else
-                        cf += c_ref.Shat[a][bb][c][0] * uh[bb][0] + c_ref.Shat[a][bb][c][1] * uh[bb][1];
+                    const int64_t t = tri[(int64_t)e * 6 + bb];
+                    double od[2];
+#pragma unroll
+                    for (int d = 0; d < 2; ++d) {
+                        const int64_t idx = (2 * t + d) * J + j;
+                        const double sv = self[idx], ov = other[idx];
+                        s[bb][d] = sv;
+                        ms[bb][d] = sv * inv_dt + (F ? F[idx] : 0.0);
+                        ks[bb][d] = cm * ov + cp * sv;
+                        od[d] = ov - obar[2 * t + d];
+                    }
+                    uh[bb][0] = g.det * (g.Ji[0][0] * od[0] + g.Ji[0][1] * od[1]);
+                    uh[bb][1] = g.det * (g.Ji[1][0] * od[0] + g.Ji[1][1] * od[1]);
                 }
-                acc0 -= cf * self[(int64_t)(2 * t[c]) * J + j];
-                acc1 -= cf * self[(int64_t)(2 * t[c] + 1) * J + j];
-            }
-        }
-        b[(2 * i) * J + j] = acc0;
-        b[(2 * i + 1) * J + j] = acc1;
-    }
-}
-
-// Element phase of the batched right-hand sides: group of JP lanes per
-// element, lanes over members.  For each local row a and component d the
-// element's contribution
-//   M_e (self/dt + f) - K_e (cm other + cp self) - C_e(other - <other>) self
-// (C_e the element convection matrix of the trilinear form) is written to
-// out[e][a][d][j]; k_rhs_node adds a node's contributions in element order.
-__global__ void __launch_bounds__(kBlock) k_rhs_elem(const int32_t* __restrict__ tri, const double* __restrict__ geo,
-                                                     const double* __restrict__ self, const double* __restrict__ other,
-                                                     const double* __restrict__ obar, const double* __restrict__ coef,
-                                                     const double* __restrict__ F, double* __restrict__ out, int n_el,
-                                                     int J, int JP, double inv_dt, int convective) {
-    Lanes L = lanes(JP);
-    const int64_t e = L.unit;
-    if (e >= n_el) return;
-    const Geo g = load_geo(geo, e);
-    int t[6];
+                const double G00 = g.G[0][0], G01 = g.G[0][1], G11 = g.G[1][1];
+                double r[6][2];
 #pragma unroll
-    for (int a = 0; a < 6; ++a) t[a] = tri[e * 6 + a];
-    for (int j = L.j0; j < J; j += JP) {
-        const double cm = coef[j], cp = coef[J + j];
-        double s[6][2], ms[6][2], ks[6][2], uh[6][2];
+                for (int a = 0; a < 6; ++a) {
+                    double r0 = 0.0, r1 = 0.0;
 #pragma unroll
-        for (int b = 0; b < 6; ++b) {
-            double o[2];
-#pragma unroll
-            for (int d = 0; d < 2; ++d) {
-                const int64_t idx = (int64_t)(2 * t[b] + d) * J + j;
-                s[b][d] = self[idx];
-                o[d] = other[idx];
-                ms[b][d] = s[b][d] * inv_dt + (F ? F[idx] : 0.0);
-                ks[b][d] = cm * o[d] + cp * s[b][d];
-            }
-            const double u0 = o[0] - obar[2 * t[b]], u1 = o[1] - obar[2 * t[b] + 1];
-            uh[b][0] = g.det * (g.Ji[0][0] * u0 + g.Ji[0][1] * u1);
-            uh[b][1] = g.det * (g.Ji[1][0] * u0 + g.Ji[1][1] * u1);
-        }
-        const double(*T)[6][6][2] = convective ? c_ref.That : c_ref.Shat;
+                    for (int bb = 0; bb < 6; ++bb) {
+                        const double m = R->Mhat[a][bb];
+                        const double kk = R->Kc[a][bb][0] * G00 + R->Kc[a][bb][1] * G01 + R->Kc[a][bb][2] * G11;
+                        r0 += m * ms[bb][0] - kk * ks[bb][0];
+                        r1 += m * ms[bb][1] - kk * ks[bb][1];
+                    }
+                    r[a][0] = g.det * r0;
+                    r[a][1] = g.det * r1;
+                }
+                if (convective) {
 #pragma unroll 1
-        for (int a = 0; a < 6; ++a) {
-            double r0 = 0.0, r1 = 0.0;
-#pragma unroll 2
-            for (int b = 0; b < 6; ++b) {
-                const double m = g.det * c_ref.Mhat[a][b];
-                double k = 0.0;
+                    for (int a = 0; a < 6; ++a)
 #pragma unroll
-                for (int p = 0; p < 2; ++p)
+                        for (int c = 0; c < 6; ++c) {
+                            double cf = 0.0;
 #pragma unroll
-                    for (int q = 0; q < 2; ++q) k += c_ref.Khat[a][b][p][q] * g.G[p][q];
-                k *= g.det;
-                r0 += m * ms[b][0] - k * ks[b][0];
-                r1 += m * ms[b][1] - k * ks[b][1];
+                            for (int bb = 0; bb < 6; ++bb)
+                                cf += R->That[a][bb][c][0] * uh[bb][0] + R->That[a][bb][c][1] * uh[bb][1];
+                            r[a][0] -= cf * s[c][0];
+                            r[a][1] -= cf * s[c][1];
+                        }
+                } else {
+#pragma unroll
+                    for (int a = 0; a < 5; ++a)
+#pragma unroll
+                        for (int c = a + 1; c < 6; ++c) {
+                            double cf = 0.0;
+#pragma unroll
+                            for (int bb = 0; bb < 6; ++bb)
+                                cf += R->Shat[a][bb][c][0] * uh[bb][0] + R->Shat[a][bb][c][1] * uh[bb][1];
+                            r[a][0] -= cf * s[c][0];
+                            r[a][1] -= cf * s[c][1];
+                            r[c][0] += cf * s[a][0];
+                            r[c][1] += cf * s[a][1];
+                        }
+                }
+                const int ci = 2 * i, ck = 2 * k;
+#pragma unroll
+                for (int a = 0; a < 6; ++a) {
+                    const int I = ci + dI[up][a], K = ck + dK[up][a];
+                    if (I < I0 || I >= I1 || K < K0 || K >= K1) continue;
+                    double* acc = L + (K % 3) * LINE + ((I - I0) * 2) * M + mem;
+                    acc[0] += r[a][0];
+                    acc[M] += r[a][1];
+                }
             }
-#pragma unroll 2
-            for (int c = 0; c < 6; ++c) {
-                double cf = 0.0;
-#pragma unroll
-                for (int b = 0; b < 6; ++b) cf += T[a][b][c][0] * uh[b][0] + T[a][b][c][1] * uh[b][1];
-                r0 -= cf * s[c][0];
-                r1 -= cf * s[c][1];
-            }
-            out[((e * 6 + a) * 2) * J + j] = r0;
-            out[((e * 6 + a) * 2 + 1) * J + j] = r1;
+            wave_sync();
         }
-    }
-}
-
-// Node phase: b_i = sum over the (element, local row) incidences of node i of
-// the element contributions (element order); Dirichlet rows take g_j, the
-// pressure rows are zero.
-__global__ void __launch_bounds__(kBlock) k_rhs_node(const int32_t* __restrict__ inc_ptr, const int32_t* __restrict__ inc,
-                                                     const int32_t* __restrict__ dir_index, const double* __restrict__ part,
-                                                     const double* __restrict__ G, double* __restrict__ b, int nP2,
-                                                     int nP1, int J, int JP) {
-    Lanes L = lanes(JP);
-    const int64_t i = L.unit;
-    if (i >= (int64_t)nP2 + nP1) return;
-    if (i >= nP2) {
-        const int64_t k = i - nP2;
-        for (int j = L.j0; j < J; j += JP) b[(2 * (int64_t)nP2 + k) * J + j] = 0.0;
-        return;
-    }
-    const int di = dir_index[i];
-    if (di >= 0) {
-        for (int j = L.j0; j < J; j += JP) {
-            b[(2 * i) * J + j] = G[(2 * (int64_t)di) * J + j];
-            b[(2 * i + 1) * J + j] = G[(2 * (int64_t)di + 1) * J + j];
-        }
-        return;
-    }
-    const int32_t q0 = inc_ptr[i], q1 = inc_ptr[i + 1];
-    for (int j = L.j0; j < J; j += JP) {
-        double r0 = 0.0, r1 = 0.0;
-        for (int32_t q = q0; q < q1; ++q) {
-            const int32_t ea = inc[q];
-            const int64_t row = (int64_t)(ea >> 3) * 6 + (ea & 7);
-            r0 += part[(row * 2) * J + j];
-            r1 += part[(row * 2 + 1) * J + j];
-        }
-        b[(2 * i) * J + j] = r0;
-        b[(2 * i + 1) * J + j] = r1;
+        flush_line(2 * k);
+        flush_line(2 * k + 1);
+        if (k == k_last) flush_line(2 * k + 2);
+        wave_sync();
     }
 }
 
@@ -548,30 +551,40 @@ hipError_t launch_member_coefs(const double* nu, const double* nu_m, int J, doub
     return hipGetLastError();
 }
 
-hipError_t launch_rhs(const DevMesh& m, const mhd_coeffs& c, int J, const double* self_n, const double* other_n,
-                      const double* obar, const double* coef, const double* forcing, const double* bc, double* rhs,
-                      hipStream_t s) {
-    int JP = pick_jp(J);
-    int64_t units = (int64_t)m.nP2 + m.nP1;
-    hipLaunchKernelGGL(k_rhs, dim3(grid_for(units, JP)), dim3(kBlock), 0, s, m.A_rowptr, m.A_col, m.valM, m.valK,
-                       m.inc_ptr, m.inc, m.tri, m.geo, m.dir_index, self_n, other_n, obar, coef, forcing, bc, rhs,
-                       m.nP2, m.nP1, J, JP, 1.0 / c.dt, c.convective);
+// one-pass right-hand sides (k_rhs_strip): M members per element slot, ks owned
+// cell rows per wavefront
+template <typename TO>
+hipError_t launch_rhs_strip_t(const DevMesh& m, const mhd_coeffs& c, int J, const double* self_n,
+                              const double* other_n, const double* obar, const double* coef, const double* forcing,
+                              const double* bc, TO* rhs, hipStream_t s) {
+    const int M = J <= 8 ? 8 : 16;
+    const int txo = 2 * (64 / M) - 1;
+    RhsGrid gd;
+    gd.nx = m.nx;
+    gd.ny = m.ny;
+    gd.ks = 4;
+    gd.nstrips = m.nx / txo + 1;
+    gd.nseg = m.ny / gd.ks + 1;
+    gd.nslices = (J + M - 1) / M;
+    const int64_t waves = (int64_t)gd.nstrips * gd.nseg * gd.nslices;
+    const dim3 grid((unsigned)((waves + kBlock / 64 - 1) / (kBlock / 64)));
+    if (M == 8)
+        hipLaunchKernelGGL((k_rhs_strip<TO, 8>), grid, dim3(kBlock), 0, s, m.cell_el, m.hs_p2, m.tri, m.geo,
+                           m.dir_index, m.p1_of_p2, self_n, other_n, obar, coef, forcing, bc, rhs, gd, m.nP2, J,
+                           1.0 / c.dt, c.convective);
+    else
+        hipLaunchKernelGGL((k_rhs_strip<TO, 16>), grid, dim3(kBlock), 0, s, m.cell_el, m.hs_p2, m.tri, m.geo,
+                           m.dir_index, m.p1_of_p2, self_n, other_n, obar, coef, forcing, bc, rhs, gd, m.nP2, J,
+                           1.0 / c.dt, c.convective);
     return hipGetLastError();
 }
 
-hipError_t launch_rhs_elem(const DevMesh& m, const mhd_coeffs& c, int J, const double* self_n, const double* other_n,
-                           const double* obar, const double* coef, const double* forcing, const double* bc,
-                           double* part, double* rhs, hipStream_t s) {
-    const int JP = pick_jp(J);
-    hipLaunchKernelGGL(k_rhs_elem, dim3(grid_for(m.n_el, JP)), dim3(kBlock), 0, s, m.tri, m.geo, self_n, other_n, obar,
-                       coef, forcing, part, m.n_el, J, JP, 1.0 / c.dt, c.convective);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    const int64_t units = (int64_t)m.nP2 + m.nP1;
-    const int JN = pick_jp(J, 64);   // the node gather keeps one member per lane
-    hipLaunchKernelGGL(k_rhs_node, dim3(grid_for(units, JN)), dim3(kBlock), 0, s, m.inc_ptr, m.inc, m.dir_index,
-                       (const double*)part, bc, rhs, m.nP2, m.nP1, J, JN);
-    return hipGetLastError();
+hipError_t launch_rhs_strip(const DevMesh& m, const mhd_coeffs& c, int J, const double* self_n, const double* other_n,
+                            const double* obar, const double* coef, const double* forcing, const double* bc,
+                            void* rhs, int precision, hipStream_t s) {
+    if (precision == MHD_FP32_IR)
+        return launch_rhs_strip_t<float>(m, c, J, self_n, other_n, obar, coef, forcing, bc, (float*)rhs, s);
+    return launch_rhs_strip_t<double>(m, c, J, self_n, other_n, obar, coef, forcing, bc, (double*)rhs, s);
 }
 
 hipError_t launch_energy_partial(const DevMesh& m, const double* vbar, double* out, hipStream_t s) {

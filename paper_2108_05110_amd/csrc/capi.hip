@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -65,12 +66,12 @@ struct mhd_ctx_s {
     double *bv = nullptr, *bw = nullptr;    // right-hand sides (n x Jmax)
     double *Xv = nullptr, *Xw = nullptr;    // solution blocks [velocity; pressure]
     double* coef = nullptr;                 // 2 Jmax member coefficients
-    double* rhs_part = nullptr;             // element contributions of the v right-hand side (n_el x 12 x Jmax)
-    double* rhs_part_w = nullptr;           // the same for the w right-hand side
     hipStream_t side = nullptr;             // second stream: the w-subproblem of a fixed-schedule step
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     double* host_coef = nullptr;            // pinned staging, 2 Jmax
     double* partial = nullptr;              // reductions
+    double min_alpha = 0.0;                 // min_j alpha_j of the last step's parameters
+    int warnings = 0;                       // MHD_WARN_ALPHA / MHD_WARN_MU of the last step's parameters
     // adjoint workspace (desc.adjoint)
     double *Tv = nullptr, *Tv1 = nullptr, *Tw = nullptr, *Tw1 = nullptr;   // (nP2,2,J)
     double *Kmv = nullptr, *Kmw = nullptr;                                  // (nP2,2,J)
@@ -88,11 +89,22 @@ static thread_local std::string g_last_error;
 
 void set_error(const std::string& msg) { g_last_error = msg; }
 
+static std::atomic<int64_t> g_alloc_count{0}, g_alloc_bytes{0};
+
+hipError_t dev_malloc(void** p, size_t bytes) {
+    hipError_t e = hipMalloc(p, bytes);
+    if (e == hipSuccess) {
+        g_alloc_count.fetch_add(1);
+        g_alloc_bytes.fetch_add((int64_t)bytes);
+    }
+    return e;
+}
+
 namespace {
 
 template <typename T>
 mhd_status dev_alloc(std::vector<void*>& list, T** p, size_t count) {
-    hipError_t e = hipMalloc((void**)p, std::max<size_t>(count * sizeof(T), 256));
+    hipError_t e = dev_malloc((void**)p, std::max<size_t>(count * sizeof(T), 256));
     if (e != hipSuccess) {
         set_error(std::string("hipMalloc(") + std::to_string(count * sizeof(T)) + "): " + hipGetErrorString(e));
         return MHD_ENOMEM;
@@ -186,6 +198,11 @@ mhd_status build_device_mesh(DevMesh& D) {
     std::vector<int32_t> dir_index(h.nP2, -1);
     for (size_t i = 0; i < h.dir_nodes.size(); ++i) dir_index[h.dir_nodes[i]] = (int32_t)i;
     if ((rc = upload(L, &D.dir_index, dir_index))) return rc;
+    if ((rc = upload(L, &D.hs_p2, h.hs_p2))) return rc;
+    if ((rc = upload(L, &D.cell_el, h.cell_el))) return rc;
+    if ((rc = upload(L, &D.p1_of_p2, h.p1_of_p2))) return rc;
+    D.nx = h.nx;
+    D.ny = h.ny;
     if ((rc = upload(L, &D.dir_nodes, h.dir_nodes))) return rc;
     D.max_row = 0;
     for (const HostCSR* c : {&h.A, &h.Bt, &h.B})
@@ -248,6 +265,8 @@ mhd_status build_device_mesh(DevMesh& D) {
         if (l + 1 < h.levels.size()) {
             if ((rc = upload_csr(L, G.P, H.P))) return rc;
             if ((rc = upload_csr(L, G.R, H.R))) return rc;
+            if ((rc = upload_csr(L, G.Dn, H.Dn))) return rc;
+            if ((rc = upload_csr(L, G.Up, H.Up))) return rc;
         } else {
             if ((rc = upload(L, &G.cinv, H.cinv))) return rc;
             G.ld32 = (H.n + 15) / 16 * 16;
@@ -256,7 +275,7 @@ mhd_status build_device_mesh(DevMesh& D) {
     }
     // constant matrices (mass, stiffness, divergence) assembled on the device
     double* eb = nullptr;
-    MHD_HIP(hipMalloc((void**)&eb, sizeof(double) * 108 * std::max(1, h.n_el)));
+    MHD_HIP(dev_malloc((void**)&eb, sizeof(double) * 108 * std::max(1, h.n_el)));
     hipError_t e = launch_const_assembly(D, eb, 0);
     if (e == hipSuccess) e = launch_transpose_const(D, 0);
     if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -282,6 +301,11 @@ mhd_status make_shared(DevMesh* m, int J_max, int restart, DevShared& S) {
     if ((rc = dev_alloc(L, &S.zbar, 2 * (size_t)m->nP2))) return rc;
     if ((rc = dev_alloc(L, &S.l2, 7 * (size_t)m->n_el))) return rc;
     if ((rc = dev_alloc(L, &S.elem, 36 * (size_t)m->n_el))) return rc;
+    // defined values before the first assembly (the kernel tuner may run on them)
+    MHD_HIP(hipMemset(S.valA, 0, sizeof(double) * (size_t)m->nnzA));
+    MHD_HIP(hipMemset(S.valA32, 0, sizeof(float) * (size_t)m->nnzA));
+    MHD_HIP(hipMemset(S.dinvA, 0, sizeof(double) * (size_t)m->nP2));
+    MHD_HIP(hipMemset(S.dinvA32, 0, sizeof(float) * (size_t)m->nP2));
     return alloc_gmres(S, restart);
 }
 
@@ -322,6 +346,18 @@ mhd_status refresh_schur(DevMesh& D, double dt, double nu_c) {
         MHD_HIP(hipMemcpy(G.L.val32, v32.data(), sizeof(float) * v32.size(), hipMemcpyHostToDevice));
         MHD_HIP(hipMemcpy(G.dinv, H.dinv.data(), sizeof(double) * H.dinv.size(), hipMemcpyHostToDevice));
         MHD_HIP(hipMemcpy(G.dinv32, d32.data(), sizeof(float) * d32.size(), hipMemcpyHostToDevice));
+        for (auto hd : {std::make_pair(&H.Dn, &G.Dn), std::make_pair(&H.Up, &G.Up)}) {
+            const HostCSR& hc = *hd.first;
+            DevCSR<double>& dc = *hd.second;
+            if (hc.nnz() == 0) continue;
+            if (hc.nnz() != dc.nnz) {
+                set_error("refresh_schur: fused pattern size mismatch");
+                return MHD_EINVAL;
+            }
+            std::vector<float> f32(hc.val.begin(), hc.val.end());
+            MHD_HIP(hipMemcpy(dc.val, hc.val.data(), sizeof(double) * hc.val.size(), hipMemcpyHostToDevice));
+            MHD_HIP(hipMemcpy(dc.val32, f32.data(), sizeof(float) * f32.size(), hipMemcpyHostToDevice));
+        }
         if (l + 1 == h.levels.size()) {
             const std::vector<float> c32 = padded_inverse32(H, G.ld32);
             MHD_HIP(hipMemcpy(G.cinv, H.cinv.data(), sizeof(double) * H.cinv.size(), hipMemcpyHostToDevice));
@@ -359,6 +395,9 @@ mhd_status check_solver_opts(const mhd_solver_opts* o) {
     CHECK_ARG(o->fixed_cycles >= 0 && o->fixed_cycles <= 64, "fixed_cycles must be in [0, 64]");
     CHECK_ARG(o->jacobi_omega == 0 || (std::isfinite(o->jacobi_omega) && o->jacobi_omega > 0 && o->jacobi_omega <= 1.5),
               "jacobi_omega must be 0 (default) or in (0, 1.5]");
+    CHECK_ARG(o->mg_unfused == 0 || o->mg_unfused == 1, "mg_unfused must be 0 or 1");
+    CHECK_ARG(o->block_krylov == 0 || (o->block_krylov == 1 && o->fixed_cycles == 0),
+              "block_krylov must be 0, or 1 with the adaptive schedule (fixed_cycles 0)");
     return MHD_OK;
 }
 
@@ -382,6 +421,14 @@ mhd_status step_prepare(mhd_ctx ctx, const mhd_step_inputs* in, mhd_coeffs& c, h
     }
     nub /= J;
     numb /= J;
+    // stability conditions of Section 3.1: alpha_j = nu_bar + num_bar - |nu_j - nu_m,j|
+    // - |nu_j' + nu_m,j'| > 0 for every member and mu > 1/2; the scheme runs either way
+    double amin = INFINITY;
+    for (int j = 0; j < J; ++j)
+        amin = std::min(amin, nub + numb - std::fabs(in->nu[j] - in->nu_m[j]) -
+                                  std::fabs((in->nu[j] - nub) + (in->nu_m[j] - numb)));
+    ctx->min_alpha = amin;
+    ctx->warnings = (amin > 0 ? 0 : MHD_WARN_ALPHA) | (ctx->desc.coeffs.mu > 0.5 ? 0 : MHD_WARN_MU);
     std::vector<double> cf(2 * (size_t)J);
     for (int j = 0; j < J; ++j) {
         cf[j] = 0.5 * (in->nu[j] - in->nu_m[j]);
@@ -408,12 +455,12 @@ mhd_status step_prepare(mhd_ctx ctx, const mhd_step_inputs* in, mhd_coeffs& c, h
 // One subproblem of a step on stream st: shared matrix from the other
 // variable, right-hand sides, solve into X (initial guess: the state at n).
 mhd_status subproblem(mhd_ctx ctx, const mhd_coeffs& c, int J, const double* self, const double* other,
-                      const double* pres, const double* f, const double* g, DevShared& A, double* part, double* rhs,
+                      const double* pres, const double* f, const double* g, DevShared& A, double* rhs,
                       double* X, hipStream_t st, mhd_solve_stats* stats) {
     DevMesh& D = ctx->mesh->d;
     mhd_status rc;
     if ((rc = assemble_shared_impl(D, c, other, J, A, st))) return rc;
-    hipError_t e = launch_rhs_elem(D, c, J, self, other, A.zbar, ctx->coef, f, g, part, rhs, st);
+    hipError_t e = launch_rhs_strip(D, c, J, self, other, A.zbar, ctx->coef, f, g, rhs, MHD_FP64, st);
     if (e != hipSuccess) {
         set_error(std::string("mhd_ens_step rhs: ") + hipGetErrorString(e));
         return MHD_EHIP;
@@ -440,10 +487,10 @@ mhd_status step_device(mhd_ctx ctx, const mhd_coeffs& c, const StepArgs& a, hipS
         MHD_HIP(hipStreamWaitEvent(stw, ctx->ev_fork, 0));
     }
     // v-problem convected by <w>, w-problem by <v>
-    mhd_status rv = subproblem(ctx, c, J, a.V, a.W, a.Q, a.f1, a.gv, ctx->Av->d, ctx->rhs_part, ctx->bv, ctx->Xv, stv, sv);
+    mhd_status rv = subproblem(ctx, c, J, a.V, a.W, a.Q, a.f1, a.gv, ctx->Av->d, ctx->bv, ctx->Xv, stv, sv);
     if (rv != MHD_OK && rv != MHD_ENOCONV) return rv;
     mhd_status rw =
-        subproblem(ctx, c, J, a.W, a.V, a.R, a.f2, a.gw, ctx->Aw->d, ctx->rhs_part_w, ctx->bw, ctx->Xw, stw, sw);
+        subproblem(ctx, c, J, a.W, a.V, a.R, a.f2, a.gw, ctx->Aw->d, ctx->bw, ctx->Xw, stw, sw);
     if (rw != MHD_OK && rw != MHD_ENOCONV) return rw;
     if (two) {
         MHD_HIP(hipEventRecord(ctx->ev_join, stw));
@@ -495,7 +542,7 @@ mhd_status step_energy(mhd_ctx ctx, const StepArgs& a, hipStream_t stv, double* 
 // node kernel.
 mhd_status check_rhs_args(const char* who, mhd_mesh m, const mhd_coeffs* c, int which, int J, const double* self_n,
                           const double* other_n, const double* nu, const double* nu_m, const double* bc_vals,
-                          const double* rhs) {
+                          const void* rhs, int precision) {
     if (!m) {
         set_error(std::string(who) + ": null mesh");
         return MHD_EINVAL;
@@ -518,15 +565,21 @@ mhd_status check_rhs_args(const char* who, mhd_mesh m, const mhd_coeffs* c, int 
         set_error(std::string(who) + ": null bc_vals with Dirichlet nodes");
         return MHD_EINVAL;
     }
+    if (precision != MHD_FP64 && precision != MHD_FP32_IR) {
+        set_error(std::string(who) + ": precision must be MHD_FP64 or MHD_FP32_IR");
+        return MHD_EINVAL;
+    }
     return MHD_OK;
 }
 
 mhd_status assemble_rhs_impl(const char* who, DevMesh& D, const mhd_coeffs& c, int J, const double* self_n,
                              const double* other_n, const double* nu, const double* nu_m, const double* forcing,
-                             const double* bc_vals, double* rhs, double* coef, double* mean, hipStream_t st) {
+                             const double* bc_vals, void* rhs, int precision, double* coef, double* mean,
+                             hipStream_t st) {
     hipError_t e = launch_member_coefs(nu, nu_m, J, coef, st);
     if (e == hipSuccess) e = launch_mean(other_n, mean, 2 * (int64_t)D.nP2, J, st);
-    if (e == hipSuccess) e = launch_rhs(D, c, J, self_n, other_n, mean, coef, forcing, bc_vals, rhs, st);
+    if (e == hipSuccess)
+        e = launch_rhs_strip(D, c, J, self_n, other_n, mean, coef, forcing, bc_vals, rhs, precision, st);
     if (e != hipSuccess) {
         set_error(std::string(who) + ": " + hipGetErrorString(e));
         return MHD_EHIP;
@@ -730,21 +783,23 @@ mhd_status mhd_ens_shared_csr(mhd_shared A, mhd_csr_view* v) try {
 
 mhd_status mhd_ens_assemble_rhs(mhd_mesh m, const mhd_coeffs* c, int which, int J, const double* self_n,
                                 const double* other_n, const double* nu, const double* nu_m, const double* forcing,
-                                const double* bc_vals, double* rhs, mhd_stream_t s) try {
-    mhd_status rc = check_rhs_args("mhd_ens_assemble_rhs", m, c, which, J, self_n, other_n, nu, nu_m, bc_vals, rhs);
+                                const double* bc_vals, void* rhs, int precision, mhd_stream_t s) try {
+    mhd_status rc = check_rhs_args("mhd_ens_assemble_rhs", m, c, which, J, self_n, other_n, nu, nu_m, bc_vals, rhs,
+                                   precision);
     if (rc) return rc;
     DevMesh& D = m->d;
     return assemble_rhs_impl("mhd_ens_assemble_rhs", D, *c, J, self_n, other_n, nu, nu_m, forcing, bc_vals, rhs,
-                             D.scratch_coef, D.scratch_mean, as_stream(s));
+                             precision, D.scratch_coef, D.scratch_mean, as_stream(s));
 } catch (...) {
     return exception_status();
 }
 
 mhd_status mhd_ens_assemble_rhs_noalloc(mhd_mesh m, const mhd_coeffs* c, int which, int J, const double* self_n,
                                         const double* other_n, const double* nu, const double* nu_m,
-                                        const double* forcing, const double* bc_vals, double* rhs, mhd_stream_t s) try {
+                                        const double* forcing, const double* bc_vals, void* rhs, int precision,
+                                        mhd_stream_t s) try {
     static const char* who = "mhd_ens_assemble_rhs_noalloc";
-    mhd_status rc = check_rhs_args(who, m, c, which, J, self_n, other_n, nu, nu_m, bc_vals, rhs);
+    mhd_status rc = check_rhs_args(who, m, c, which, J, self_n, other_n, nu, nu_m, bc_vals, rhs, precision);
     if (rc) return rc;
     DevMesh& D = m->d;
     const size_t need = noalloc_rhs_doubles(J, D.nP2);
@@ -758,8 +813,8 @@ mhd_status mhd_ens_assemble_rhs_noalloc(mhd_mesh m, const mhd_coeffs* c, int whi
     if ((rc = scratch_base(who, &base))) return rc;
     double* coef = base;
     double* mean = base + noalloc_mean_offset(J);
-    return assemble_rhs_impl(who, D, *c, J, self_n, other_n, nu, nu_m, forcing, bc_vals, rhs, coef, mean,
-                             as_stream(s));
+    return assemble_rhs_impl(who, D, *c, J, self_n, other_n, nu, nu_m, forcing, bc_vals, rhs, precision, coef,
+                             mean, as_stream(s));
 } catch (...) {
     return exception_status();
 }
@@ -776,7 +831,21 @@ mhd_status mhd_ens_solve(mhd_shared A, const double* rhs, double* x, int J, cons
     }
     CHECK_ARG(o->restart <= A->d.gw.restart, "mhd_ens_solve: restart larger than the handle's");
     CHECK_ARG(A->d.assembled, "mhd_ens_solve: matrix not assembled");
-    return solve_shared(A->d, rhs, x, J, *o, st, as_stream(s));
+    CHECK_ARG(!o->block_krylov || ((J == 16 || J == 32 || J == 64 || J == 128) && A->d.gw.bmat),
+              "mhd_ens_solve: block GMRES needs J in {16, 32, 64, 128} (and J_max <= 128)");
+    hipStream_t hs = as_stream(s);
+    rc = solve_shared(A->d, rhs, x, J, *o, st, hs);
+    if (rc || !st || o->fixed_cycles == 0) return rc;
+    // fixed schedule: the residuals were not looked at during the solve
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    MHD_HIP(hipStreamIsCapturing(hs, &cs));
+    if (cs != hipStreamCaptureStatusNone) return MHD_OK;
+    if ((rc = residual_report(A->d, rhs, x, J, st, hs))) return rc;
+    if (st->nonfinite) {
+        set_error("mhd_ens_solve: non-finite residual");
+        return MHD_ENOCONV;
+    }
+    return MHD_OK;
 } catch (...) {
     return exception_status();
 }
@@ -836,8 +905,6 @@ mhd_status mhd_ens_ctx_create(mhd_mesh m, const mhd_ctx_desc* d, mhd_ctx* out) t
     if ((rc = dev_alloc(c->allocs, &c->Xv, blk))) return fail(rc);
     if ((rc = dev_alloc(c->allocs, &c->Xw, blk))) return fail(rc);
     if ((rc = dev_alloc(c->allocs, &c->coef, 2 * (size_t)d->J_max))) return fail(rc);
-    if ((rc = dev_alloc(c->allocs, &c->rhs_part, (size_t)m->d.n_el * 12 * d->J_max))) return fail(rc);
-    if ((rc = dev_alloc(c->allocs, &c->rhs_part_w, (size_t)m->d.n_el * 12 * d->J_max))) return fail(rc);
     if (d->solver.fixed_cycles > 0 && !d->serial) {
         if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
@@ -847,6 +914,10 @@ mhd_status mhd_ens_ctx_create(mhd_mesh m, const mhd_ctx_desc* d, mhd_ctx* out) t
         }
     }
     if ((rc = dev_alloc(c->allocs, &c->partial, (size_t)2048 * d->J_max + 1024))) return fail(rc);
+    // tune (or take from the process-wide table) the node-row kernel plans for J_max
+    // and build the data they use, so that no step allocates or synchronises for it
+    if ((rc = autotune(c->Av->d, d->J_max, d->solver.precision, nullptr, false, nullptr))) return fail(rc);
+    if ((rc = autotune(c->Aw->d, d->J_max, d->solver.precision, nullptr, false, nullptr))) return fail(rc);
     if (hipHostMalloc((void**)&c->host_coef, sizeof(double) * 2 * d->J_max, hipHostMallocDefault) != hipSuccess)
         return fail(MHD_ENOMEM);
     if (d->adjoint) {
@@ -940,6 +1011,39 @@ mhd_status mhd_ens_get_plan(mhd_shared A, int J, int precision, int op, mhd_tune
     return exception_status();
 }
 
+mhd_status mhd_ens_prepare(mhd_shared A, int J, int precision, mhd_stream_t s) try {
+    CHECK_ARG(A, "mhd_ens_prepare: null handle");
+    CHECK_ARG(precision == MHD_FP64 || precision == MHD_FP32_IR, "mhd_ens_prepare: bad precision");
+    if (J < 1 || J > A->d.Jmax) {
+        set_error("mhd_ens_prepare: J outside [1, J_max]");
+        return MHD_ESHAPE;
+    }
+    hipStream_t st = as_stream(s);
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    MHD_HIP(hipStreamIsCapturing(st, &cs));
+    CHECK_ARG(cs == hipStreamCaptureStatusNone, "mhd_ens_prepare: stream is being captured");
+    return autotune(A->d, J, precision, st, false, nullptr);
+} catch (...) {
+    return exception_status();
+}
+
+mhd_status mhd_ens_ctx_prepare(mhd_ctx ctx, int J, mhd_stream_t s) try {
+    CHECK_ARG(ctx, "mhd_ens_ctx_prepare: null context");
+    mhd_status rc = mhd_ens_prepare(ctx->Av, J, ctx->desc.solver.precision, s);
+    if (rc == MHD_OK) rc = mhd_ens_prepare(ctx->Aw, J, ctx->desc.solver.precision, s);
+    return rc;
+} catch (...) {
+    return exception_status();
+}
+
+mhd_status mhd_ens_alloc_stats(int64_t* count, int64_t* bytes) try {
+    if (count) *count = g_alloc_count.load();
+    if (bytes) *bytes = g_alloc_bytes.load();
+    return MHD_OK;
+} catch (...) {
+    return exception_status();
+}
+
 mhd_status mhd_ens_step(mhd_ctx ctx, double* V, double* W, double* Q, double* R, const mhd_step_inputs* in,
                         mhd_step_stats* st, mhd_stream_t s) try {
     CHECK_ARG(ctx && in, "mhd_ens_step: null argument");
@@ -950,15 +1054,19 @@ mhd_status mhd_ens_step(mhd_ctx ctx, double* V, double* W, double* Q, double* R,
     mhd_status rc = step_prepare(ctx, in, c, stv);
     if (rc) return rc;
     mhd_solve_stats sv{}, sw{};
+    if (st && !ctx->desc.graph) {   // eager: the solves fill the caller's per-member arrays
+        sv.relres = st->v.relres;
+        sv.member_iters = st->v.member_iters;
+        sw.relres = st->w.relres;
+        sw.member_iters = st->w.member_iters;
+    }
     mhd_status rs = MHD_OK;
     if (ctx->desc.graph) {
         CHECK_ARG(stv != nullptr, "mhd_ens_step: graph mode needs a non-null stream");
         if (!ctx->graph.valid || !(ctx->graph.key == a) || ctx->graph.stream != stv) {
             ctx->graph.reset();
-            // kernel plans are fixed into the graph: tune before capturing (the second
-            // handle only takes the per-operator data of the plans tuned on the first)
-            if ((rc = autotune(ctx->Av->d, a.J, ctx->desc.solver.precision, stv, false, nullptr))) return rc;
-            if ((rc = autotune(ctx->Aw->d, a.J, ctx->desc.solver.precision, stv, false, nullptr))) return rc;
+            // kernel plans are fixed into the graph: those prepared at context
+            // creation (or by mhd_ens_ctx_prepare for this J), else the defaults
             MHD_HIP(hipStreamBeginCapture(stv, hipStreamCaptureModeThreadLocal));
             rs = step_device(ctx, c, a, stv, &sv, &sw, true);
             hipGraph_t graph = nullptr;
@@ -987,9 +1095,31 @@ mhd_status mhd_ens_step(mhd_ctx ctx, double* V, double* W, double* Q, double* R,
         if (rs != MHD_OK && rs != MHD_ENOCONV) return rs;
     }
     if (st) {
-        st->v = sv;
-        st->w = sw;
+        auto counts = [](mhd_solve_stats& d, const mhd_solve_stats& r) {
+            d.min_block_rank = r.min_block_rank;
+            d.iters = r.iters;
+            d.cycles = r.cycles;
+            d.max_relres = r.max_relres;
+            d.converged = r.converged;
+            d.nonfinite = r.nonfinite;
+        };
+        counts(st->v, sv);
+        counts(st->w, sw);
+        if (ctx->desc.solver.fixed_cycles > 0) {
+            // a fixed schedule looks at no residual while it runs: report the final ones
+            if ((rc = residual_report(ctx->Av->d, ctx->bv, ctx->Xv, a.J, &st->v, stv))) return rc;
+            if ((rc = residual_report(ctx->Aw->d, ctx->bw, ctx->Xw, a.J, &st->w, stv))) return rc;
+            for (mhd_solve_stats* q : {&st->v, &st->w})
+                if (q->member_iters)
+                    for (int j = 0; j < a.J; ++j) q->member_iters[j] = q->iters;
+        }
+        st->min_alpha = ctx->min_alpha;
+        st->warnings = ctx->warnings | ((st->v.nonfinite || st->w.nonfinite) ? MHD_WARN_NONFINITE : 0);
         if ((rc = step_energy(ctx, a, stv, &st->energy))) return rc;
+        if (st->warnings & MHD_WARN_NONFINITE) {
+            set_error("mhd_ens_step: non-finite residual");
+            return MHD_ENOCONV;
+        }
     }
     if (rs == MHD_ENOCONV) {
         set_error("mhd_ens_step: a subproblem solve hit maxit");
@@ -1076,20 +1206,14 @@ mhd_status mhd_ens_group_step(mhd_group g, double* const* V, double* const* W, d
                g->coeffs[i].nu_bar == cs[i].nu_bar && g->coeffs[i].num_bar == cs[i].num_bar;
     if (!same) {
         g->graph.reset();
-        for (int i = 0; i < n; ++i) {
-            mhd_status rc = autotune(g->ctxs[i]->Av->d, args[i].J, g->ctxs[i]->desc.solver.precision, st, false,
-                                     nullptr);
-            if (rc) return rc;
-            rc = autotune(g->ctxs[i]->Aw->d, args[i].J, g->ctxs[i]->desc.solver.precision, st, false, nullptr);
-            if (rc) return rc;
-        }
+        // kernel plans: those the contexts prepared (at creation for J_max), else the defaults
         MHD_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
         mhd_status rs = MHD_OK;
         hipError_t e = hipEventRecord(g->fork, st);
         for (int i = 0; i < n && rs == MHD_OK && e == hipSuccess; ++i) {
             e = hipStreamWaitEvent(g->streams[i], g->fork, 0);
             if (e != hipSuccess) break;
-            mhd_solve_stats sv, sw;
+            mhd_solve_stats sv{}, sw{};
             // the ensembles of a group already run on parallel branches: no further split inside a branch
             rs = step_device(g->ctxs[i], cs[i], args[i], g->streams[i], &sv, &sw, false);
             if (rs == MHD_ENOCONV) rs = MHD_OK;
@@ -1196,6 +1320,12 @@ mhd_status mhd_ens_adjoint_step(mhd_ctx ctx, const double* V_n, const double* W_
     MHD_HIP(hipMemsetAsync(ctx->Xv, 0, vel + prs, st));
     MHD_HIP(hipMemsetAsync(ctx->Xw, 0, vel + prs, st));
     mhd_solve_stats sv{}, sw{};
+    if (stt) {   // the transposed solves fill the caller's per-member arrays
+        sv.relres = stt->v.relres;
+        sv.member_iters = stt->v.member_iters;
+        sw.relres = stt->w.relres;
+        sw.member_iters = stt->w.member_iters;
+    }
     Av.transposed = Aw.transposed = true;
     mhd_status rv = solve_shared(Av, ctx->bv, ctx->Xv, J, ctx->desc.solver, &sv, st);
     mhd_status rw = (rv == MHD_OK || rv == MHD_ENOCONV) ? solve_shared(Aw, ctx->bw, ctx->Xw, J, ctx->desc.solver, &sw, st)
@@ -1245,6 +1375,8 @@ mhd_status mhd_ens_adjoint_step(mhd_ctx ctx, const double* V_n, const double* W_
         stt->v = sv;
         stt->w = sw;
         stt->energy = 0.0;
+        stt->warnings = 0;
+        stt->min_alpha = 0.0;
     }
     if (rv == MHD_ENOCONV || rw == MHD_ENOCONV) {
         set_error("mhd_ens_adjoint_step: a transposed solve hit maxit");

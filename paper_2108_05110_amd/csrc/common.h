@@ -34,7 +34,11 @@ struct HostLevel {
     HostCSR P;                   // (n x n_coarse) interpolation from level+1 (empty on coarsest)
     HostCSR R;                   // transpose of P
     std::vector<double> cinv;    // dense inverse of L (coarsest level only), row-major
+    HostCSR Dn;                  // (n_coarse x 2n) [R | -R L]: restricted residual from [b; x2]
+    HostCSR Up;                  // (n x (2n + n_coarse)) [E | E P | w D^-1] on [x2; xc; b]: prolongation
+                                 // and one smoothing sweep
 };
+constexpr double kMgOmega = 0.8;   // Jacobi damping of the pressure multigrid
 
 // Structured triangulation of a union of square cells, Taylor-Hood P2/P1 numbering.
 struct HostMesh {
@@ -46,6 +50,8 @@ struct HostMesh {
     std::vector<int32_t> tri;    // n_el x 6 P2 ids (v0,v1,v2,m01,m12,m20)
     std::vector<int32_t> tri1;   // n_el x 3 P1 ids
     std::vector<int32_t> p1_of_p2;  // P2 node -> P1 id (vertices) or -1
+    std::vector<int32_t> hs_p2;  // half-step grid point (I, K) -> P2 id or -1, (2 ny + 1) x (2 nx + 1)
+    std::vector<int32_t> cell_el;   // cell (i, k) -> its lower element (upper = +1) or -1, ny x nx
     std::vector<uint8_t> bnd;    // per P2 node: on the boundary
     std::vector<uint8_t> dir;    // per P2 node: Dirichlet
     std::vector<int32_t> dir_nodes;
@@ -140,6 +146,7 @@ struct RefTables {
     double That[6][6][6][2];// int_ref phi_a phi_b d_e phi_c
     double Shat[6][6][6][2];// (That[a][b][c] - That[c][b][a]) / 2
     double Bhat[3][6][2];   // -int_ref psi_k d_e phi_a
+    double Kc[6][6][3];     // Khat[a][b] combined for a symmetric G: [0][0], [0][1] + [1][0], [1][1]
 };
 void make_ref_tables(RefTables& t);
 

@@ -34,6 +34,7 @@ struct DevCSR {
 struct DevLevel {
     int n = 0;
     DevCSR<double> L, P, R;
+    DevCSR<double> Dn, Up;        // fused V-cycle halves (levels above the coarsest)
     double* dinv = nullptr;
     float* dinv32 = nullptr;
     double* cinv = nullptr;       // coarsest only, n x n
@@ -89,6 +90,10 @@ struct DevMesh {
     uint8_t* dir = nullptr;       // nP2
     int32_t* dir_index = nullptr; // nP2: position in dir_nodes or -1
     int32_t* dir_nodes = nullptr;
+    int32_t* hs_p2 = nullptr;     // (2 ny + 1) x (2 nx + 1): half-step grid point -> P2 id or -1
+    int32_t* cell_el = nullptr;   // ny x nx: cell -> lower element (upper = +1) or -1
+    int32_t* p1_of_p2 = nullptr;  // nP2: P1 id of a vertex node, -1 for an edge node
+    int nx = 0, ny = 0;           // cell grid
     int32_t *A_rowptr = nullptr, *A_col = nullptr, *A_row = nullptr;
     int32_t *Bt_rowptr = nullptr, *Bt_col = nullptr;
     int32_t *B_rowptr = nullptr, *B_col = nullptr;
@@ -148,6 +153,7 @@ struct GmresWork {
     std::vector<void*> mg_x, mg_x2, mg_b, mg_r;   // per level (n_l x Jmax, sized for double)
     void* dense_part = nullptr;   // partial products of the coarsest dense solve (kDenseKS x n_c x Jmax)
     void** dptrs = nullptr;       // device array of the basis block pointers
+    double* bmat = nullptr;       // 2 Jmax^2: J x J matrices of the block solver (Jmax <= kBlockMaxJ)
     void* zbasis = nullptr;       // restart FP32 blocks: the preconditioned basis vectors of FP32 solves
     void** zptrs = nullptr;       // device array of their pointers
 };
@@ -172,6 +178,11 @@ struct DevShared {
     GmresWork gw;
     std::vector<void*> allocs;
 };
+constexpr int kBlockMaxJ = 128;   // block GMRES: J in {16, 32, 64, 128}
+
+// Every device allocation of the library goes through dev_malloc, which counts
+// them (count and bytes since load) for mhd_ens_alloc_stats.
+hipError_t dev_malloc(void** p, size_t bytes);
 
 // ---------------------------------------------------------------- launchers (assemble.hip)
 void upload_ref_tables(const RefTables& t);
@@ -183,14 +194,11 @@ hipError_t launch_assemble_A(const DevMesh& m, const mhd_coeffs& c, const double
                              double* elem, double* valA, float* valA32, double* dinvA, float* dinvA32,
                              hipStream_t s);
 hipError_t launch_member_coefs(const double* nu, const double* nu_m, int J, double* coef, hipStream_t s);
-// right-hand sides in two passes (element contributions into part, n_el x 12 x J,
-// then a per-node sum); same result as launch_rhs up to the order of the sums
-hipError_t launch_rhs_elem(const DevMesh& m, const mhd_coeffs& c, int J, const double* self_n, const double* other_n,
-                           const double* obar, const double* coef, const double* forcing, const double* bc,
-                           double* part, double* rhs, hipStream_t s);
-hipError_t launch_rhs(const DevMesh& m, const mhd_coeffs& c, int J, const double* self_n,
-                      const double* other_n, const double* obar, const double* coef, const double* forcing,
-                      const double* bc, double* rhs, hipStream_t s);
+// right-hand sides of one subproblem in one pass, FP64 or (precision MHD_FP32_IR)
+// FP32 output; every row of rhs (n x J) is written
+hipError_t launch_rhs_strip(const DevMesh& m, const mhd_coeffs& c, int J, const double* self_n, const double* other_n,
+                            const double* obar, const double* coef, const double* forcing, const double* bc,
+                            void* rhs, int precision, hipStream_t s);
 hipError_t launch_energy_partial(const DevMesh& m, const double* vbar, double* out, hipStream_t s);
 
 // ---------------------------------------------------------------- solver (solve.hip)
@@ -198,6 +206,8 @@ mhd_status alloc_gmres(DevShared& S, int restart);
 mhd_status solve_shared(DevShared& S, const double* rhs, double* x, int J, const mhd_solver_opts& o,
                         mhd_solve_stats* st, hipStream_t s);
 mhd_status spmm_shared(DevShared& S, const void* x, void* y, int J, int precision, hipStream_t s);
+mhd_status residual_report(DevShared& S, const double* b, const double* x, int J, mhd_solve_stats* out,
+                           hipStream_t st);
 mhd_status autotune(DevShared& S, int J, int precision, hipStream_t st, bool force,
                     std::vector<mhd_tune_entry>* report);
 mhd_status set_plan(DevShared& S, int J, int precision, int op, int vec, int group, int deep, int tile, int waves);

@@ -219,6 +219,80 @@ void fix_node(HostCSR& A, int32_t f) {
     A = std::move(B);
 }
 
+// alpha A + beta B on the union pattern (entries of either kept)
+HostCSR add_csr(const HostCSR& A, double alpha, const HostCSR& B, double beta) {
+    HostCSR C;
+    C.nrows = A.nrows;
+    C.ncols = A.ncols;
+    C.rowptr.assign(A.nrows + 1, 0);
+    for (int64_t r = 0; r < A.nrows; ++r) {
+        int32_t p = A.rowptr[r], q = B.rowptr[r];
+        const int32_t pe = A.rowptr[r + 1], qe = B.rowptr[r + 1];
+        while (p < pe || q < qe) {
+            const int32_t ca = p < pe ? A.col[p] : INT32_MAX, cb = q < qe ? B.col[q] : INT32_MAX;
+            const int32_t c = std::min(ca, cb);
+            double v = 0.0;
+            if (ca == c) v += alpha * A.val[p++];
+            if (cb == c) v += beta * B.val[q++];
+            C.col.push_back(c);
+            C.val.push_back(v);
+        }
+        C.rowptr[r + 1] = (int32_t)C.col.size();
+    }
+    return C;
+}
+
+HostCSR diag_csr(const std::vector<double>& d) {
+    HostCSR C;
+    C.nrows = C.ncols = (int64_t)d.size();
+    C.rowptr.resize(d.size() + 1);
+    for (size_t i = 0; i < d.size(); ++i) {
+        C.rowptr[i] = (int32_t)i;
+        C.col.push_back((int32_t)i);
+        C.val.push_back(d[i]);
+    }
+    C.rowptr[d.size()] = (int32_t)d.size();
+    return C;
+}
+
+// [A | B] with the columns of B numbered after those of A
+HostCSR hcat_csr(const HostCSR& A, const HostCSR& B) {
+    HostCSR C;
+    C.nrows = A.nrows;
+    C.ncols = A.ncols + B.ncols;
+    C.rowptr.assign(A.nrows + 1, 0);
+    for (int64_t r = 0; r < A.nrows; ++r) {
+        for (int32_t p = A.rowptr[r]; p < A.rowptr[r + 1]; ++p) {
+            C.col.push_back(A.col[p]);
+            C.val.push_back(A.val[p]);
+        }
+        for (int32_t p = B.rowptr[r]; p < B.rowptr[r + 1]; ++p) {
+            C.col.push_back((int32_t)(A.ncols + B.col[p]));
+            C.val.push_back(B.val[p]);
+        }
+        C.rowptr[r + 1] = (int32_t)C.col.size();
+    }
+    return C;
+}
+
+// Two fused steps of a level's V(2,2)-cycle with damped Jacobi smoothing
+// (E = I - w D^-1 L), each a single sparse operator on stacked inputs:
+//   down:  bc = R b - (R L) x2           = [R | -R L] [b; x2]
+//          (the residual of the pre-smoothed x2, restricted);
+//   up:    x = E x2 + (E P) xc + w D^-1 b = [E | E P | w D^-1] [x2; xc; b]
+//          (the coarse correction prolonged into x2, then one smoothing sweep).
+// Patterns are symbolic products, so they depend only on the hierarchy.
+void fused_level_ops(HostLevel& F, double w) {
+    std::vector<double> ones(F.n, 1.0), wd(F.dinv);
+    for (double& v : wd) v *= w;
+    const HostCSR I = diag_csr(ones);
+    const HostCSR RL = spgemm(F.R, {}, F.L);
+    F.Dn = hcat_csr(F.R, add_csr(RL, -1.0, RL, 0.0));
+    const HostCSR DL = spgemm(diag_csr(F.dinv), {}, F.L);
+    const HostCSR E = add_csr(I, 1.0, DL, -w);
+    F.Up = hcat_csr(hcat_csr(E, spgemm(E, {}, F.P)), diag_csr(wd));
+}
+
 }  // namespace
 
 // Pressure Schur-complement approximation S_hat = B D^{-1} B^T with
@@ -254,6 +328,14 @@ mhd_status schur_values(HostMesh& m, double dt, double nu_c) {
         for (int v = 0; v < L[l].n; ++v)
             for (int32_t p = L[l].L.rowptr[v]; p < L[l].L.rowptr[v + 1]; ++p)
                 if (L[l].L.col[p] == v) L[l].dinv[v] = L[l].L.val[p] != 0.0 ? 1.0 / L[l].L.val[p] : 0.0;
+    }
+    for (size_t l = 0; l + 1 < L.size(); ++l) {
+        const int64_t nd = L[l].Dn.nnz(), nu = L[l].Up.nnz();
+        fused_level_ops(L[l], kMgOmega);
+        if ((nd && nd != L[l].Dn.nnz()) || (nu && nu != L[l].Up.nnz())) {
+            set_error("schur hierarchy: fused pattern changed");
+            return MHD_EINVAL;
+        }
     }
     HostLevel& Lc = L.back();
     Lc.cinv.assign((size_t)Lc.n * Lc.n, 0.0);
@@ -326,6 +408,12 @@ void make_ref_tables(RefTables& t) {
         for (int b = 0; b < 6; ++b)
             for (int c = 0; c < 6; ++c)
                 for (int e = 0; e < 2; ++e) t.Shat[a][b][c][e] = 0.5 * (t.That[a][b][c][e] - t.That[c][b][a][e]);
+    for (int a = 0; a < 6; ++a)
+        for (int b = 0; b < 6; ++b) {
+            t.Kc[a][b][0] = t.Khat[a][b][0][0];
+            t.Kc[a][b][1] = t.Khat[a][b][0][1] + t.Khat[a][b][1][0];
+            t.Kc[a][b][2] = t.Khat[a][b][1][1];
+        }
 }
 
 // ---------------------------------------------------------------- mesh
@@ -414,6 +502,8 @@ mhd_status build_mesh(const mhd_mesh_desc* d, HostMesh& m, bool full) {
     // ---- elements
     m.tri.resize((size_t)n_el * 6);
     m.tri1.resize((size_t)n_el * 3);
+    m.hs_p2 = pid;
+    m.cell_el.assign((size_t)g.nx * g.ny, -1);
     auto P = [&](int I, int K) { return pid[(size_t)K * NX + I]; };
     auto V = [&](int i, int k) { return vid[(size_t)k * (g.nx + 1) + i]; };
     int e = 0;
@@ -421,6 +511,7 @@ mhd_status build_mesh(const mhd_mesh_desc* d, HostMesh& m, bool full) {
         for (int i = 0; i < g.nx; ++i) {
             if (!g.cell(i, k)) continue;
             int I = 2 * i, K = 2 * k;
+            m.cell_el[(size_t)k * g.nx + i] = e;
             // lower (v00, v10, v11), upper (v00, v11, v01); locals 3,4,5 = mid(0,1), mid(1,2), mid(2,0)
             int lo[6] = {P(I, K), P(I + 2, K), P(I + 2, K + 2), P(I + 1, K), P(I + 2, K + 1), P(I + 1, K + 1)};
             int up[6] = {P(I, K), P(I + 2, K + 2), P(I, K + 2), P(I + 1, K + 1), P(I + 1, K + 2), P(I, K + 1)};

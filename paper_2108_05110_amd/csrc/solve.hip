@@ -1525,6 +1525,69 @@ __global__ void __launch_bounds__(kBlock) k_mg(const int32_t* __restrict__ rp, c
     vstore<T, V>(y + o, out);
 }
 
+// A fused step of a level's V-cycle as one sparse product on stacked inputs
+// (the level's Dn or Up operator): y = A [x1; x2; x3], where columns below n1
+// index x1, columns in [n1, n1 + n2) index x2 and the others x3.  Packed rows
+// as in k_mg, 32 lanes per row, each lane 256 / (32 sizeof(T)) consecutive
+// members; a row's entries go in chunks of 32 (one entry per lane, broadcast
+// by ds_bpermute) with 8 member loads in flight.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_mgf(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                const T* __restrict__ val, const T* __restrict__ x1,
+                                                const T* __restrict__ x2, const T* __restrict__ x3, int n1, int n2,
+                                                T* __restrict__ y, int n, int J) {
+    constexpr int LPR = 32;
+    constexpr int V = 256 / (LPR * (int)sizeof(T));
+    constexpr int RPW = 64 / LPR;
+    const int lane = threadIdx.x & 63;
+    const int slot = lane / LPR, h = lane % LPR;
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int r = (int)((blk * (kBlock / 64) + (threadIdx.x >> 6)) * RPW + slot);
+    const int j = blockIdx.y * (LPR * V) + h * V;
+    const bool valid = r < n;
+    int p0 = 0, cnt = 0;
+    if (valid) {
+        p0 = rp[r];
+        cnt = rp[r + 1] - p0;
+    }
+    int nmax = 0;
+#pragma unroll
+    for (int g = 0; g < RPW; ++g) nmax = max(nmax, __builtin_amdgcn_readlane(cnt, g * LPR));
+    T s[V];
+#pragma unroll
+    for (int q = 0; q < V; ++q) s[q] = 0;
+    for (int t0 = 0; t0 < nmax; t0 += LPR) {
+        int c = 0;
+        T a = 0;
+        if (t0 + h < cnt) {
+            c = col[p0 + t0 + h];
+            a = val[p0 + t0 + h];
+        }
+        const int nt = min(LPR, nmax - t0);
+        for (int t = 0; t < nt; t += 8) {
+            T v[8][V];
+            T w[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int src = slot * LPR + min(t + i, LPR - 1);
+                const int k = __builtin_amdgcn_ds_bpermute(src << 2, c);
+                w[i] = half_bcast(a, src);
+                if (t0 + t + i >= cnt) w[i] = 0;
+                const T* xp = k < n1 ? x1 + (int64_t)k * J
+                                     : (k < n1 + n2 ? x2 + (int64_t)(k - n1) * J : x3 + (int64_t)(k - n1 - n2) * J);
+                vload<T, V>(v[i], xp + j);
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+#pragma unroll
+                for (int q = 0; q < V; ++q) s[q] += w[i] * v[i][q];
+            }
+        }
+    }
+    if (!valid) return;
+    vstore<T, V>(y + (int64_t)r * J + j, s);
+}
+
 // Dense x = C b on the coarsest level (C: n x n row-major with row length ld, b and x: n x J),
 // split over kDenseKS column ranges: a workgroup computes the partial product
 // of a 64-row x 64-member block over one range (4 x 4 outputs per thread from
@@ -3065,7 +3128,7 @@ mhd_status ensure_tiling(DevMesh& m, int id) {
     d->max_r1 = h.max_r1;
     auto up = [&](int32_t** p, const std::vector<int32_t>& v) -> mhd_status {
         const size_t bytes = std::max<size_t>(v.size() * sizeof(int32_t), 256);
-        hipError_t e = hipMalloc((void**)p, bytes);
+        hipError_t e = dev_malloc((void**)p, bytes);
         if (e == hipSuccess) {
             m.allocs.push_back(*p);
             if (!v.empty()) e = hipMemcpy(*p, v.data(), v.size() * sizeof(int32_t), hipMemcpyHostToDevice);
@@ -3174,7 +3237,7 @@ mhd_status ensure_ell(DevMesh& m, int id) {
     d->nent = (int64_t)nent;
     auto up = [&](auto** p, const auto& v) -> mhd_status {
         const size_t bytes = std::max<size_t>(v.size() * sizeof(v[0]), 256);
-        hipError_t e = hipMalloc((void**)p, bytes);
+        hipError_t e = dev_malloc((void**)p, bytes);
         if (e == hipSuccess) {
             m.allocs.push_back(*p);
             if (!v.empty()) e = hipMemcpy(*p, v.data(), v.size() * sizeof(v[0]), hipMemcpyHostToDevice);
@@ -3212,7 +3275,7 @@ mhd_status ensure_ell_values(DevShared& S, int id, hipStream_t st) {
     const DevEll& t = *S.mesh->ell[id];
     int2* p = nullptr;
     const size_t bytes = sizeof(int2) * (size_t)std::max<int64_t>(t.nent, 64);
-    MHD_HIP(hipMalloc((void**)&p, bytes));
+    MHD_HIP(dev_malloc((void**)&p, bytes));
     S.allocs.push_back(p);
     MHD_HIP(hipMemcpyAsync(p, t.am0, sizeof(int2) * (size_t)t.nent, hipMemcpyDeviceToDevice, st));
     hipLaunchKernelGGL(k_ell_scatter, dim3((unsigned)((S.mesh->nnzA + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
@@ -3285,7 +3348,7 @@ mhd_status ensure_pair_sched(DevMesh& m, int g) {
     std::vector<int32_t> sched(waves.size());
     for (size_t i = 0; i < waves.size(); ++i) sched[i] = waves[i].second;
     int32_t* d = nullptr;
-    hipError_t e = hipMalloc((void**)&d, sched.size() * sizeof(int32_t));
+    hipError_t e = dev_malloc((void**)&d, sched.size() * sizeof(int32_t));
     if (e == hipSuccess) {
         m.allocs.push_back(d);
         e = hipMemcpy(d, sched.data(), sched.size() * sizeof(int32_t), hipMemcpyHostToDevice);
@@ -3899,6 +3962,7 @@ struct Ops {
     int JP;
 
     NodePlan p_saddle, p_first, p_sweep;   // autotuned node-row kernels for this (mesh, J, word size)
+    bool fused_mg = true;                  // V-cycle levels as their two fused operators
 
     Ops(DevShared& s, int j, hipStream_t stream) : S(s), J(j), st(stream), JP(pick_jp(j)) {
         const int word = (int)sizeof(T);
@@ -3973,19 +4037,35 @@ struct Ops {
             *out = x;
             return MHD_OK;
         }
-        const T omega = (T)0.8;
+        const T omega = (T)kMgOmega;
         T* x2 = (T*)S.gw.mg_x2[l];
         T* r = (T*)S.gw.mg_r[l];
         T* bc = (T*)S.gw.mg_b[l + 1];
         const T* dinv = Vals<T>::dinv(Lv);
         // x2 = x + w D^-1 (b - L x) with x = w D^-1 b: two sweeps from a zero guess in one pass
         if ((rc = csr<5>(Lv.L, dinv, nullptr, b, x2, omega))) return rc;
-        if ((rc = csr<2>(Lv.L, dinv, x2, b, r, omega))) return rc;        // r  = b - L x2
-        if ((rc = csr<0>(Lv.R, dinv, r, nullptr, bc, omega))) return rc;  // bc = R r
+        const bool fuse = fused_mg && packed(Lv.L) && Lv.Dn.nnz > 0 && Lv.Dn.max_row <= 64 && Lv.Up.max_row <= 64;
+        const int MJ = 256 / (int)sizeof(T);
+        if (fuse) {   // bc = R (b - L x2) = [R | -R L] [b; x2]
+            const dim3 gd((unsigned)(((Lv.Dn.nrows + 1) / 2 + 3) / 4), J / MJ);
+            hipLaunchKernelGGL((k_mgf<T>), gd, dim3(kBlock), 0, st, Lv.Dn.rowptr, Lv.Dn.col, Vals<T>::csr(Lv.Dn), b,
+                               (const T*)x2, (const T*)nullptr, Lv.n, Lv.n, bc, (int)Lv.Dn.nrows, J);
+            LAUNCH_CHECK();
+        } else {
+            if ((rc = csr<2>(Lv.L, dinv, x2, b, r, omega))) return rc;        // r  = b - L x2
+            if ((rc = csr<0>(Lv.R, dinv, r, nullptr, bc, omega))) return rc;  // bc = R r
+        }
         T* xc = nullptr;
         if ((rc = vcycle(l + 1, bc, &xc))) return rc;
-        if ((rc = csr<1>(Lv.P, dinv, xc, nullptr, x2, omega))) return rc; // x2 += P xc
-        if ((rc = csr<3>(Lv.L, dinv, x2, b, x, omega))) return rc;        // post-smoothing
+        if (fuse) {   // x = E (x2 + P xc) + w D^-1 b = [E | E P | w D^-1] [x2; xc; b]
+            const dim3 gu((unsigned)(((Lv.Up.nrows + 1) / 2 + 3) / 4), J / MJ);
+            hipLaunchKernelGGL((k_mgf<T>), gu, dim3(kBlock), 0, st, Lv.Up.rowptr, Lv.Up.col, Vals<T>::csr(Lv.Up),
+                               (const T*)x2, (const T*)xc, b, Lv.n, m.levels[l + 1].n, x, (int)Lv.Up.nrows, J);
+            LAUNCH_CHECK();
+        } else {
+            if ((rc = csr<1>(Lv.P, dinv, xc, nullptr, x2, omega))) return rc; // x2 += P xc
+            if ((rc = csr<3>(Lv.L, dinv, x2, b, x, omega))) return rc;        // post-smoothing
+        }
         if (schur) {   // the last sweep writes the Schur part z_p directly
             if ((rc = csr<6>(Lv.L, dinv, x, b, schur, omega, pin))) return rc;
             *out = schur;
@@ -4133,6 +4213,7 @@ mhd_status gmres_solve(DevShared& S, const double* b, double* x, int J, const mh
     const int sweeps = std::max(1, o.jacobi_sweeps);
     const double omega = o.jacobi_omega > 0 ? o.jacobi_omega : kJacobiOmega;
     Ops<T> ops(S, J, st);
+    ops.fused_mg = o.mg_unfused == 0;
     RedShape rs = cap_blocks(red_shape(n, J, 16 / (int)sizeof(T)), G.nblk_cap);
     const int passes = o.cgs_passes > 0 ? o.cgs_passes : (sizeof(T) == 4 ? 1 : 2);
     const T* const* Vd = (const T* const*)G.dptrs;
@@ -4158,6 +4239,24 @@ mhd_status gmres_solve(DevShared& S, const double* b, double* x, int J, const mh
     int iters = 0, cycles = 0;
     double maxrel = 0.0;
     bool conv = false;
+    // inner iterations after which each member's true residual first met rtol
+    std::vector<int> first_met(fixed ? 0 : J, -1);
+    auto fill_stats = [&](bool ok, bool nonfinite) {
+        if (!stt) return;
+        stt->iters = iters;
+        stt->cycles = cycles;
+        stt->max_relres = fixed ? -1.0 : maxrel;
+        stt->converged = fixed ? -1 : (ok ? 1 : 0);
+        stt->min_block_rank = J;
+        stt->nonfinite = 0;
+        for (int j = 0; j < J; ++j) {
+            double rel = fixed ? -1.0 : (hbn[j] > 0 ? hbeta[j] / hbn[j] : hbeta[j]);
+            if (!fixed && !std::isfinite(rel)) ++stt->nonfinite;
+            if (stt->relres) stt->relres[j] = rel;
+            if (stt->member_iters) stt->member_iters[j] = (fixed || first_met[j] < 0) ? iters : first_met[j];
+        }
+        (void)nonfinite;
+    };
     while (true) {
         // FP64 residual r = b - S x and its column norms
         if (fixed && cycles >= o.fixed_cycles) break;
@@ -4172,9 +4271,13 @@ mhd_status gmres_solve(DevShared& S, const double* b, double* x, int J, const mh
             if (!std::isfinite(rel)) bad = true;
             maxrel = std::max(maxrel, rel);
         }
+        for (int j = 0; j < J; ++j) {
+            const double rel = hbn[j] > 0 ? hbeta[j] / hbn[j] : hbeta[j];
+            if (first_met[j] < 0 && rel <= o.rtol) first_met[j] = iters;
+        }
         if (bad) {
             set_error("mhd_ens_solve: non-finite residual");
-            if (stt) *stt = {iters, cycles, maxrel, 0};
+            fill_stats(false, true);
             return MHD_ENOCONV;
         }
         if (maxrel <= o.rtol) {
@@ -4333,11 +4436,418 @@ mhd_status gmres_solve(DevShared& S, const double* b, double* x, int J, const mh
         }
         ++cycles;
     }
-    if (fixed) {
-        if (stt) *stt = {iters, cycles, -1.0, -1};
-        return MHD_OK;
+    fill_stats(conv, false);
+    if (fixed) return MHD_OK;
+    if (!conv) {
+        set_error("mhd_ens_solve: maxit reached before rtol (best iterate written)");
+        return MHD_ENOCONV;
     }
-    if (stt) *stt = {iters, cycles, maxrel, conv ? 1 : 0};
+    return MHD_OK;
+}
+
+// ------------------------------------------------------------------ block GMRES
+// One Krylov space shared by the J right-hand sides (paper, Section 1: the
+// shared matrix pairs naturally with block linear solvers): the basis grows by
+// blocks V_k of up to J orthonormal columns, the block upper-Hessenberg H is
+// built by block classical Gram-Schmidt with a second pass, and each new block
+// is orthonormalised by a pivoted Cholesky QR whose small pivots deflate the
+// directions that have become dependent (identical members, converged ones).
+// Deflated columns are zero and stay zero through the linear preconditioner
+// and the SpMM, so every kernel keeps the (n, J) block layout.
+
+// Per-workgroup partials of the J x J product A^T B of two (n, J) blocks in
+// FP64 (J = 16 TA): the workgroup's rows go through LDS 32 at a time and each
+// thread owns a TA x TA tile of the product.  Layout of the partials as
+// k_reduce expects: partial[(a J + b) nblk + workgroup].
+template <typename T, int TA>
+__global__ void __launch_bounds__(kBlock) k_bgram(const T* __restrict__ A, const T* __restrict__ B, int64_t n,
+                                                  double* __restrict__ partial) {
+    constexpr int J = 16 * TA;
+    constexpr int RT = 32;
+    __shared__ T sa[RT * J], sb[RT * J];
+    const int t = threadIdx.x;
+    const int a0 = (t / 16) * TA, b0 = (t % 16) * TA;
+    double acc[TA][TA];
+#pragma unroll
+    for (int i = 0; i < TA; ++i)
+#pragma unroll
+        for (int k = 0; k < TA; ++k) acc[i][k] = 0.0;
+    const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t r0 = (int64_t)blockIdx.x * per, r1 = min(n, r0 + per);
+    for (int64_t rb = r0; rb < r1; rb += RT) {
+        for (int q = t; q < RT * J; q += kBlock) {
+            const int64_t row = rb + q / J;
+            T va = 0, vb = 0;
+            if (row < r1) {
+                va = A[row * J + q % J];
+                vb = B[row * J + q % J];
+            }
+            sa[q] = va;
+            sb[q] = vb;
+        }
+        __syncthreads();
+        for (int rr = 0; rr < RT; ++rr) {
+            double xa[TA], xb[TA];
+#pragma unroll
+            for (int i = 0; i < TA; ++i) {
+                xa[i] = (double)sa[rr * J + a0 + i];
+                xb[i] = (double)sb[rr * J + b0 + i];
+            }
+#pragma unroll
+            for (int i = 0; i < TA; ++i)
+#pragma unroll
+                for (int k = 0; k < TA; ++k) acc[i][k] += xa[i] * xb[k];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < TA; ++i)
+#pragma unroll
+        for (int k = 0; k < TA; ++k) partial[((int64_t)(a0 + i) * J + b0 + k) * gridDim.x + blockIdx.x] = acc[i][k];
+}
+
+// C (op)= A M for (n, J) blocks A, C and a J x J matrix M (FP64, staged in
+// LDS): MODE 0 C = A M, 1 C -= A M, 2 C += A M.  Lanes over the J columns of a
+// row; A's row is read by every lane of the row (one broadcast load per entry).
+template <typename T, int MODE>
+__global__ void __launch_bounds__(kBlock) k_bmm(const T* __restrict__ A, const double* __restrict__ M,
+                                                T* __restrict__ C, int64_t n, int J) {
+    extern __shared__ double sm[];
+    for (int q = threadIdx.x; q < J * J; q += kBlock) sm[q] = M[q];
+    __syncthreads();
+    const int rpb = kBlock / J;
+    const int b = threadIdx.x % J, sub = threadIdx.x / J;
+    if (sub >= rpb) return;
+    for (int64_t row = (int64_t)blockIdx.x * rpb + sub; row < n; row += (int64_t)gridDim.x * rpb) {
+        const T* ar = A + row * J;
+        double acc = 0.0;
+        for (int a = 0; a < J; ++a) acc += (double)ar[a] * sm[a * J + b];
+        T* c = C + row * J + b;
+        if (MODE == 0)
+            *c = (T)acc;
+        else if (MODE == 1)
+            *c = (T)((double)*c - acc);
+        else
+            *c = (T)((double)*c + acc);
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_convert(const double* __restrict__ a, T* __restrict__ out, int64_t tot) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < tot; i += (int64_t)gridDim.x * kBlock)
+        out[i] = (T)a[i];
+}
+
+// Small dense algebra of the block solver on the host (FP64, row-major J x J).
+struct BlockQR {
+    int J = 0;
+    // Pivoted Cholesky of a Gram matrix G = W^T W: W Pi = Q U with rank p (pivots
+    // whose square falls below tol2 times the largest diagonal of G are
+    // dropped).  Returns p; Minv (J x J) maps W to Q (Q = W Minv, columns >= p
+    // zero) and C (J x J) has W = Q C (rows >= p zero).
+    int factor(const std::vector<double>& G, double tol2, std::vector<double>& Minv, std::vector<double>& C) const {
+        std::vector<double> A(G);
+        std::vector<int> piv(J);
+        for (int i = 0; i < J; ++i) piv[i] = i;
+        double dmax = 0.0;
+        for (int i = 0; i < J; ++i) dmax = std::max(dmax, A[(size_t)i * J + i]);
+        std::vector<double> U((size_t)J * J, 0.0);   // rows in pivot order, columns in original order
+        int p = 0;
+        for (; p < J; ++p) {
+            int best = -1;
+            double bv = 0.0;
+            for (int i = p; i < J; ++i) {
+                const double d = A[(size_t)piv[i] * J + piv[i]];
+                if (d > bv) {
+                    bv = d;
+                    best = i;
+                }
+            }
+            if (best < 0 || !(bv > tol2 * dmax) || !(dmax > 0.0)) break;
+            std::swap(piv[p], piv[best]);
+            const int c = piv[p];
+            const double r = std::sqrt(bv);
+            U[(size_t)p * J + c] = r;
+            for (int i = p + 1; i < J; ++i) U[(size_t)p * J + piv[i]] = A[(size_t)c * J + piv[i]] / r;
+            for (int i = p + 1; i < J; ++i)
+                for (int k = p + 1; k < J; ++k) {
+                    const int a = piv[i], bb = piv[k];
+                    A[(size_t)a * J + bb] -= U[(size_t)p * J + a] * U[(size_t)p * J + bb];
+                }
+        }
+        C.assign((size_t)J * J, 0.0);
+        for (int k = 0; k < p; ++k)
+            for (int c = 0; c < J; ++c) C[(size_t)k * J + c] = U[(size_t)k * J + c];
+        // Q = W[:, piv[0..p)] U11^-1 with U11[k][i] = U[k][piv[i]] upper triangular
+        Minv.assign((size_t)J * J, 0.0);
+        std::vector<double> inv((size_t)p * p, 0.0);
+        for (int col = 0; col < p; ++col) {   // solve U11 x = e_col (back substitution)
+            for (int i = p - 1; i >= 0; --i) {
+                double v = (i == col) ? 1.0 : 0.0;
+                for (int k = i + 1; k < p; ++k) v -= U[(size_t)i * J + piv[k]] * inv[(size_t)k * p + col];
+                inv[(size_t)i * p + col] = v / U[(size_t)i * J + piv[i]];
+            }
+        }
+        for (int i = 0; i < p; ++i)
+            for (int k = 0; k < p; ++k) Minv[(size_t)piv[i] * J + k] = inv[(size_t)i * p + k];
+        return p;
+    }
+};
+
+// Least squares min || E1 C0 - Hb Y ||_F for the (m+1)J x mJ block Hessenberg
+// Hb (row-major) by Householder reflections (each column has at most 2J rows
+// below its diagonal); zero pivots (deflated directions) leave their Y rows 0.
+void block_lsq(std::vector<double> Hb, std::vector<double> rhs, int rows, int cols, int J, std::vector<double>& Y) {
+    const int nr = J;   // right-hand side columns
+    std::vector<double> v(rows);
+    std::vector<char> dead(cols, 0);
+    for (int c = 0; c < cols; ++c) {
+        const int last = std::min(rows, (c / J + 2) * J);   // rows with entries in this column
+        double nrm = 0.0;
+        for (int r = c; r < last; ++r) nrm += Hb[(size_t)r * cols + c] * Hb[(size_t)r * cols + c];
+        nrm = std::sqrt(nrm);
+        if (!(nrm > 1e-300)) {
+            dead[c] = 1;
+            continue;
+        }
+        const double x0 = Hb[(size_t)c * cols + c];
+        const double alpha = x0 >= 0 ? -nrm : nrm;
+        for (int r = c; r < last; ++r) v[r] = Hb[(size_t)r * cols + c];
+        v[c] -= alpha;
+        double vv = 0.0;
+        for (int r = c; r < last; ++r) vv += v[r] * v[r];
+        if (!(vv > 0.0)) continue;
+        for (int k = c; k < cols; ++k) {
+            double d = 0.0;
+            for (int r = c; r < last; ++r) d += v[r] * Hb[(size_t)r * cols + k];
+            d = 2.0 * d / vv;
+            for (int r = c; r < last; ++r) Hb[(size_t)r * cols + k] -= d * v[r];
+        }
+        for (int k = 0; k < nr; ++k) {
+            double d = 0.0;
+            for (int r = c; r < last; ++r) d += v[r] * rhs[(size_t)r * nr + k];
+            d = 2.0 * d / vv;
+            for (int r = c; r < last; ++r) rhs[(size_t)r * nr + k] -= d * v[r];
+        }
+    }
+    double dmax = 0.0;
+    for (int c = 0; c < cols; ++c) dmax = std::max(dmax, std::fabs(Hb[(size_t)c * cols + c]));
+    Y.assign((size_t)cols * nr, 0.0);
+    for (int c = cols - 1; c >= 0; --c) {
+        const double d = Hb[(size_t)c * cols + c];
+        if (dead[c] || !(std::fabs(d) > 1e-13 * dmax)) continue;
+        for (int k = 0; k < nr; ++k) {
+            double v2 = rhs[(size_t)c * nr + k];
+            for (int q = c + 1; q < cols; ++q) v2 -= Hb[(size_t)c * cols + q] * Y[(size_t)q * nr + k];
+            Y[(size_t)c * nr + k] = v2 / d;
+        }
+    }
+}
+
+template <typename T>
+mhd_status block_gram(DevShared& S, const T* A, const T* B, int J, hipStream_t st, std::vector<double>& G) {
+    GmresWork& W = S.gw;
+    const int64_t n = S.mesh->n;
+    const int64_t J2 = (int64_t)J * J;
+    const int nb = (int)std::max<int64_t>(16, std::min<int64_t>(256, (W.partial_len - 1024) / J2));
+    switch (J) {
+        case 16: hipLaunchKernelGGL((k_bgram<T, 1>), dim3(nb), dim3(kBlock), 0, st, A, B, n, W.partial); break;
+        case 32: hipLaunchKernelGGL((k_bgram<T, 2>), dim3(nb), dim3(kBlock), 0, st, A, B, n, W.partial); break;
+        case 64: hipLaunchKernelGGL((k_bgram<T, 4>), dim3(nb), dim3(kBlock), 0, st, A, B, n, W.partial); break;
+        default: hipLaunchKernelGGL((k_bgram<T, 8>), dim3(nb), dim3(kBlock), 0, st, A, B, n, W.partial); break;
+    }
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_reduce, dim3(reduce_grid(J2)), dim3(kBlock), 0, st, (const double*)W.partial, nb, J2, W.bmat,
+                       0);
+    LAUNCH_CHECK();
+    G.resize(J2);
+    MHD_HIP(hipMemcpyAsync(G.data(), W.bmat, sizeof(double) * J2, hipMemcpyDeviceToHost, st));
+    MHD_HIP(hipStreamSynchronize(st));
+    return MHD_OK;
+}
+
+template <typename T, int MODE>
+mhd_status block_mm(DevShared& S, const T* A, const std::vector<double>& M, T* C, int J, hipStream_t st) {
+    GmresWork& W = S.gw;
+    double* dM = W.bmat + (size_t)J * J;   // the Gram result occupies the first J^2 entries
+    MHD_HIP(hipMemcpyAsync(dM, M.data(), sizeof(double) * M.size(), hipMemcpyHostToDevice, st));
+    const int64_t n = S.mesh->n;
+    const int rpb = kBlock / J;
+    const unsigned grid = (unsigned)std::min<int64_t>(4096, (n + rpb - 1) / rpb);
+    hipLaunchKernelGGL((k_bmm<T, MODE>), dim3(grid), dim3(kBlock), sizeof(double) * J * J, st, A, (const double*)dM,
+                       C, n, J);
+    LAUNCH_CHECK();
+    // M lives in host memory the next call may overwrite: wait for the copy
+    MHD_HIP(hipStreamSynchronize(st));
+    return MHD_OK;
+}
+
+// Block GMRES inside FP64 iterative refinement (adaptive mode): each cycle
+// orthonormalises R = b - S x (deflating dependent columns), runs `restart`
+// block Arnoldi steps with the right preconditioner, solves the block least
+// squares problem on the host and adds the correction.
+template <typename T>
+mhd_status block_gmres_solve(DevShared& S, const double* b, double* x, int J, const mhd_solver_opts& o,
+                             mhd_solve_stats* stt, hipStream_t st) {
+    DevMesh& m = *S.mesh;
+    GmresWork& G = S.gw;
+    if (!(J == 16 || J == 32 || J == 64 || J == 128) || !G.bmat) {
+        set_error("block GMRES needs J in {16, 32, 64, 128} and a handle with J_max <= 128");
+        return MHD_EINVAL;
+    }
+    const int64_t n = m.n;
+    const int mres = std::max(1, std::min(o.restart > 0 ? o.restart : G.restart, G.restart));
+    const int sweeps = std::max(1, o.jacobi_sweeps);
+    const double omega = o.jacobi_omega > 0 ? o.jacobi_omega : kJacobiOmega;
+    const double tol2 = sizeof(T) == 4 ? 1e-12 : 1e-24;   // deflation: pivot below 1e-6 (1e-12) of the largest
+    Ops<T> ops(S, J, st);
+    ops.fused_mg = o.mg_unfused == 0;
+    BlockQR qr;
+    qr.J = J;
+    const bool keepz = sizeof(T) == 4 && G.zbasis != nullptr;
+    const size_t zblk = (((size_t)n * S.Jmax * sizeof(float)) + 255) & ~(size_t)255;
+    auto zslot = [&](int k) { return (T*)((char*)G.zbasis + (size_t)k * zblk); };
+    double* hbeta = G.host_res + J;
+    double* hbn = G.host_res + 2 * J;
+    mhd_status rc;
+    if ((rc = ops.colnorm(b, G.bnorm))) return rc;
+    if ((rc = sync_copy(hbn, G.bnorm, J, st))) return rc;
+    int iters = 0, cycles = 0, rank_min = J;
+    double maxrel = 0.0;
+    bool conv = false;
+    std::vector<int> first_met(J, -1);
+    std::vector<double> Gm, Minv, Cm, C0, Hb, Y;
+    while (true) {
+        if ((rc = saddle_residual64(S, b, x, G.r64, J, st))) return rc;
+        if ((rc = ops.colnorm(G.r64, G.beta))) return rc;
+        if ((rc = sync_copy(hbeta, G.beta, J, st))) return rc;
+        maxrel = 0.0;
+        bool bad = false;
+        for (int j = 0; j < J; ++j) {
+            const double rel = hbn[j] > 0 ? hbeta[j] / hbn[j] : hbeta[j];
+            if (!std::isfinite(rel)) bad = true;
+            maxrel = std::max(maxrel, rel);
+            if (first_met[j] < 0 && rel <= o.rtol) first_met[j] = iters;
+        }
+        if (bad) {
+            set_error("mhd_ens_solve: non-finite residual");
+            return MHD_ENOCONV;
+        }
+        if (maxrel <= o.rtol) {
+            conv = true;
+            break;
+        }
+        if (iters >= o.maxit) break;
+        // R in the inner precision, orthonormalised: R = V0 C0
+        T* R = (T*)G.wbuf;
+        hipLaunchKernelGGL((k_convert<T>), dim3(ew_grid(n * J)), dim3(kBlock), 0, st, (const double*)G.r64, R, n * J);
+        LAUNCH_CHECK();
+        T* V0 = basis_ptr<T>(S, 0);
+        if ((rc = block_gram<T>(S, R, R, J, st, Gm))) return rc;
+        int p = qr.factor(Gm, tol2, Minv, C0);
+        if ((rc = block_mm<T, 0>(S, R, Minv, V0, J, st))) return rc;
+        if ((rc = block_gram<T>(S, V0, V0, J, st, Gm))) return rc;   // second pass
+        qr.factor(Gm, tol2, Minv, Cm);
+        if ((rc = block_mm<T, 0>(S, V0, Minv, R, J, st))) return rc;
+        MHD_HIP(hipMemcpyAsync(V0, R, sizeof(T) * (size_t)n * J, hipMemcpyDeviceToDevice, st));
+        {
+            std::vector<double> t((size_t)J * J, 0.0);
+            for (int i = 0; i < J; ++i)
+                for (int k = 0; k < J; ++k) {
+                    double v = 0.0;
+                    for (int q = 0; q < J; ++q) v += Cm[(size_t)i * J + q] * C0[(size_t)q * J + k];
+                    t[(size_t)i * J + k] = v;
+                }
+            C0.swap(t);
+        }
+        rank_min = std::min(rank_min, p);
+        // block Arnoldi
+        std::vector<std::vector<double>> H;   // H[i * mres + k]: block (i, k), J x J
+        H.assign((size_t)(mres + 1) * mres, std::vector<double>((size_t)J * J, 0.0));
+        int kd = 0;
+        for (int k = 0; k < mres && iters < o.maxit; ++k) {
+            T* vk = basis_ptr<T>(S, k);
+            T* z = keepz ? zslot(k) : (T*)G.zbuf;
+            T* w = basis_ptr<T>(S, k + 1);
+            if ((rc = ops.precond(vk, z, sweeps, omega))) return rc;
+            if ((rc = ops.saddle(z, w))) return rc;
+            for (int pass = 0; pass < 2; ++pass) {
+                std::vector<std::vector<double>> hk(k + 1);
+                for (int i = 0; i <= k; ++i)
+                    if ((rc = block_gram<T>(S, basis_ptr<T>(S, i), w, J, st, hk[i]))) return rc;
+                for (int i = 0; i <= k; ++i) {
+                    if ((rc = block_mm<T, 1>(S, basis_ptr<T>(S, i), hk[i], w, J, st))) return rc;
+                    for (size_t q = 0; q < hk[i].size(); ++q) H[(size_t)i * mres + k][q] += hk[i][q];
+                }
+            }
+            if ((rc = block_gram<T>(S, w, w, J, st, Gm))) return rc;
+            const int pk = qr.factor(Gm, tol2, Minv, Cm);
+            T* tmp = (T*)G.wbuf;
+            if ((rc = block_mm<T, 0>(S, w, Minv, tmp, J, st))) return rc;
+            if ((rc = block_gram<T>(S, tmp, tmp, J, st, Gm))) return rc;
+            std::vector<double> Minv2, C2;
+            qr.factor(Gm, tol2, Minv2, C2);
+            if ((rc = block_mm<T, 0>(S, tmp, Minv2, w, J, st))) return rc;
+            std::vector<double>& Hn = H[(size_t)(k + 1) * mres + k];
+            for (int i = 0; i < J; ++i)
+                for (int c = 0; c < J; ++c) {
+                    double v = 0.0;
+                    for (int q = 0; q < J; ++q) v += C2[(size_t)i * J + q] * Cm[(size_t)q * J + c];
+                    Hn[(size_t)i * J + c] = v;
+                }
+            rank_min = std::min(rank_min, pk);
+            ++iters;
+            kd = k + 1;
+            if (pk == 0) break;   // the block Krylov space is exhausted
+        }
+        // block least squares and the correction d = P^-1 (V Y) (or Z Y with Z kept)
+        const int rows = (kd + 1) * J, cols = kd * J;
+        Hb.assign((size_t)rows * cols, 0.0);
+        for (int i = 0; i <= kd; ++i)
+            for (int k = 0; k < kd; ++k) {
+                if (i > k + 1) continue;
+                const std::vector<double>& hb = H[(size_t)i * mres + k];
+                for (int a = 0; a < J; ++a)
+                    for (int c = 0; c < J; ++c) Hb[(size_t)(i * J + a) * cols + k * J + c] = hb[(size_t)a * J + c];
+            }
+        std::vector<double> rhs((size_t)rows * J, 0.0);
+        for (int a = 0; a < J; ++a)
+            for (int c = 0; c < J; ++c) rhs[(size_t)a * J + c] = C0[(size_t)a * J + c];
+        block_lsq(Hb, rhs, rows, cols, J, Y);
+        T* u = (T*)G.wbuf;
+        for (int k = 0; k < kd; ++k) {
+            std::vector<double> Yk(Y.begin() + (size_t)k * J * J, Y.begin() + (size_t)(k + 1) * J * J);
+            const T* src = keepz ? zslot(k) : basis_ptr<T>(S, k);
+            if (k == 0) {
+                if ((rc = block_mm<T, 0>(S, src, Yk, u, J, st))) return rc;
+            } else if ((rc = block_mm<T, 2>(S, src, Yk, u, J, st))) {
+                return rc;
+            }
+        }
+        const T* d = u;
+        if (!keepz) {
+            if ((rc = ops.precond(u, (T*)G.zbuf, sweeps, omega))) return rc;
+            d = (const T*)G.zbuf;
+        }
+        if (kd > 0) {
+            hipLaunchKernelGGL((k_add_to64<T>), dim3(ew_grid(n * J)), dim3(kBlock), 0, st, x, d, n * J);
+            LAUNCH_CHECK();
+        }
+        ++cycles;
+        if (kd == 0) break;
+    }
+    if (stt) {
+        stt->iters = iters;
+        stt->cycles = cycles;
+        stt->max_relres = maxrel;
+        stt->converged = conv ? 1 : 0;
+        stt->nonfinite = 0;
+        stt->min_block_rank = rank_min;
+        for (int j = 0; j < J; ++j) {
+            if (stt->relres) stt->relres[j] = hbn[j] > 0 ? hbeta[j] / hbn[j] : hbeta[j];
+            if (stt->member_iters) stt->member_iters[j] = first_met[j] < 0 ? iters : first_met[j];
+        }
+    }
     if (!conv) {
         set_error("mhd_ens_solve: maxit reached before rtol (best iterate written)");
         return MHD_ENOCONV;
@@ -4356,7 +4866,7 @@ mhd_status alloc_gmres(DevShared& S, int restart) {
     G.Jmax = S.Jmax;
     const size_t blk = slot_bytes(m.n, S.Jmax);
     auto A = [&](void** p, size_t bytes) -> mhd_status {
-        hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 256));
+        hipError_t e = dev_malloc(p, std::max<size_t>(bytes, 256));
         if (e != hipSuccess) {
             set_error(std::string("hipMalloc(") + std::to_string(bytes) + "): " + hipGetErrorString(e));
             return MHD_ENOMEM;
@@ -4381,6 +4891,7 @@ mhd_status alloc_gmres(DevShared& S, int restart) {
     if ((rc = A((void**)&G.bnorm, J8))) return rc;
     if ((rc = A((void**)&G.hcol, J8 * 2 * (kMaxRestart + 1)))) return rc;
     if ((rc = A((void**)&G.res, J8 * 2))) return rc;
+    if (S.Jmax <= kBlockMaxJ && (rc = A((void**)&G.bmat, sizeof(double) * 2 * (size_t)S.Jmax * S.Jmax))) return rc;
     G.nblk_cap = std::min(kRedBlocks, std::max(64, 524288 / S.Jmax));
     G.partial_len = (int64_t)G.nblk_cap * (restart + 2) * S.Jmax + 1024;
     if ((rc = A((void**)&G.partial, sizeof(double) * G.partial_len))) return rc;
@@ -4416,12 +4927,44 @@ mhd_status alloc_gmres(DevShared& S, int restart) {
     return MHD_OK;
 }
 
+// No tuning and no allocation here: the node-row operators run the plans in the
+// process-wide table (filled by mhd_ens_prepare / mhd_ens_autotune / context
+// creation) where this handle holds their data, and the default plans otherwise.
 mhd_status solve_shared(DevShared& S, const double* rhs, double* x, int J, const mhd_solver_opts& o,
                         mhd_solve_stats* st, hipStream_t s) {
-    mhd_status rc = autotune(S, J, o.precision, s, false, nullptr);
-    if (rc) return rc;
+    if (o.block_krylov) {
+        if (o.precision == MHD_FP32_IR) return block_gmres_solve<float>(S, rhs, x, J, o, st, s);
+        return block_gmres_solve<double>(S, rhs, x, J, o, st, s);
+    }
     if (o.precision == MHD_FP32_IR) return gmres_solve<float>(S, rhs, x, J, o, st, s);
     return gmres_solve<double>(S, rhs, x, J, o, st, s);
+}
+
+// Final FP64 residuals of a solve: rel_j = ||b_j - S x_j|| / ||b_j|| per member
+// into st (max_relres, nonfinite, relres[] if given).  Synchronises st.
+mhd_status residual_report(DevShared& S, const double* b, const double* x, int J, mhd_solve_stats* out,
+                           hipStream_t st) {
+    GmresWork& G = S.gw;
+    Ops<double> ops(S, J, st);
+    mhd_status rc;
+    if ((rc = saddle_residual64(S, b, x, G.r64, J, st))) return rc;
+    if ((rc = ops.colnorm(G.r64, G.beta))) return rc;
+    if ((rc = ops.colnorm(b, G.bnorm))) return rc;
+    double* hbeta = G.host_res + J;
+    double* hbn = G.host_res + 2 * J;
+    if ((rc = sync_copy(hbeta, G.beta, J, st))) return rc;
+    if ((rc = sync_copy(hbn, G.bnorm, J, st))) return rc;
+    double mx = 0.0;
+    int bad = 0;
+    for (int j = 0; j < J; ++j) {
+        const double rel = hbn[j] > 0 ? hbeta[j] / hbn[j] : hbeta[j];
+        if (!std::isfinite(rel)) ++bad;
+        else mx = std::max(mx, rel);
+        if (out->relres) out->relres[j] = rel;
+    }
+    out->max_relres = bad ? NAN : mx;
+    out->nonfinite = bad;
+    return MHD_OK;
 }
 
 mhd_status saddle_residual64(DevShared& S, const double* b, const double* x, double* r, int J, hipStream_t st) {

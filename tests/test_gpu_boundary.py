@@ -1,0 +1,140 @@
+"""GPU tests of the C ABI's promises: solves and steps allocate no device
+memory (only creation and the explicit tuning calls do), per-member solver
+statistics, the stability-condition warnings of Section 3.1, and non-finite
+residual detection under the fixed (graph-capturable) schedule."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2108_05110_amd import _lib
+    _lib.lib()
+    return _lib
+
+
+def test_steps_and_solves_allocate_nothing(L):
+    from paper_2108_05110_amd.ensemble import Mesh, Stepper, fixed_schedule_opts, to_dev
+    N, J = 32, 16
+    say("alloc-free: 32^2, J=16, graph fixed schedule and eager adaptive steps")
+    pb = wl.cavity(J=J, s=0.1, dt=0.01, ic_amp=0.05)
+    gm = Mesh(L.MHD_MESH_UNIT_SQUARE, N)
+    g = Stepper(gm, pb, opts=fixed_schedule_opts(), time_dependent_data=False, graph=True)
+    e = Stepper(gm, pb, opts=L.solver_opts(L.MHD_FP32_IR), time_dependent_data=False)
+    torch.cuda.synchronize()
+    n0, b0 = L.mhd_ens_alloc_stats()
+    for _ in range(2):
+        g.step(stats=True)      # the first call captures the step graph
+        e.step(stats=True)
+    torch.cuda.synchronize()
+    n1, b1 = L.mhd_ens_alloc_stats()
+    assert (n1, b1) == (n0, b0), (n0, n1, b0, b1)
+    # a bare solve: prepare allocates (tilings, packed entries), the solve does not
+    A = L.mhd_ens_shared_create(gm.handle, J, 8)
+    c = L.Coeffs(pb.dt, pb.mu, float(pb.nu.mean()), float(pb.nu_m.mean()), 0)
+    L.mhd_ens_assemble_shared(gm.handle, c, e.W.reshape(-1), J, A)
+    L.mhd_ens_prepare(A, J, L.MHD_FP32_IR)
+    b = torch.randn((gm.n, J), dtype=torch.float64, device="cuda")
+    x = torch.zeros_like(b)
+    torch.cuda.synchronize()
+    n2, _ = L.mhd_ens_alloc_stats()
+    st, _ = L.mhd_ens_solve(A, b, x, J, L.solver_opts(L.MHD_FP32_IR, restart=8))
+    st2, _ = L.mhd_ens_solve(A, b, torch.zeros_like(b), J - 3, L.solver_opts(L.MHD_FP32_IR, restart=8))
+    torch.cuda.synchronize()
+    n3, _ = L.mhd_ens_alloc_stats()
+    assert n3 == n2, (n2, n3)
+    L.mhd_ens_shared_free(A)
+    g.close()
+    e.close()
+    gm.close()
+
+
+def test_per_member_statistics(L):
+    from paper_2108_05110_amd.ensemble import Mesh, Stepper, fixed_schedule_opts
+    N, J = 16, 8
+    say("per-member statistics: adaptive solve and fixed-schedule step")
+    pb = wl.cavity(J=J, s=0.1, dt=0.01, ic_amp=0.05)
+    gm = Mesh(L.MHD_MESH_UNIT_SQUARE, N)
+    a = Stepper(gm, pb, opts=L.solver_opts(L.MHD_FP64), time_dependent_data=False)
+    st = a.step(stats=True)
+    for q in (st.v, st.w):
+        rel, its = L.member_stats(q, J)
+        say("  adaptive", q.iters, q.max_relres, rel[:3], its[:3])
+        assert q.converged == 1 and q.nonfinite == 0
+        assert max(rel) == pytest.approx(q.max_relres, rel=1e-12)
+        assert all(0 <= r <= 1e-12 for r in rel)
+        assert all(1 <= k <= q.iters for k in its)
+    f = Stepper(gm, pb, opts=fixed_schedule_opts(), time_dependent_data=False, graph=True)
+    for _ in range(2):
+        st = f.step(stats=True)
+    for q in (st.v, st.w):
+        rel, its = L.member_stats(q, J)
+        say("  fixed", q.iters, q.max_relres, rel[:3])
+        assert q.converged == -1 and q.nonfinite == 0
+        assert all(np.isfinite(r) and 0 <= r < 1e-3 for r in rel)
+        assert max(rel) == pytest.approx(q.max_relres, rel=1e-12)
+        assert its == [q.iters] * J
+    a.close()
+    f.close()
+    gm.close()
+
+
+def test_stability_warnings(L):
+    from paper_2108_05110_amd.ensemble import Mesh, Stepper
+    N, J = 8, 3
+    say("warnings: alpha_j <= 0, mu <= 1/2")
+    pb = wl.cavity(J=J, s=0.1, dt=0.01)
+    gm = Mesh(L.MHD_MESH_UNIT_SQUARE, N)
+    ok = Stepper(gm, pb, opts=L.solver_opts(L.MHD_FP64), time_dependent_data=False)
+    st = ok.step(stats=True)
+    assert st.warnings == 0 and st.min_alpha > 0
+    ok.close()
+    pb.nu = np.array([1e-3, 1e-3, 1e-1])
+    pb.nu_m = np.array([1e-3, 1e-3, 1e-3])
+    pb.mu = 0.4
+    nub, numb = pb.nu.mean(), pb.nu_m.mean()
+    alpha = nub + numb - np.abs(pb.nu - pb.nu_m) - np.abs((pb.nu - nub) + (pb.nu_m - numb))
+    bad = Stepper(gm, pb, opts=L.solver_opts(L.MHD_FP64), time_dependent_data=False)
+    st = bad.step(stats=True)
+    say("  warnings", st.warnings, st.min_alpha, alpha)
+    assert st.warnings & L.MHD_WARN_ALPHA and st.warnings & L.MHD_WARN_MU
+    assert st.min_alpha == pytest.approx(alpha.min(), rel=1e-12)
+    bad.close()
+    gm.close()
+
+
+def test_nonfinite_state_reported_under_fixed_schedule(L):
+    """A NaN planted in the state (from the host) reaches the residuals of the
+    fixed schedule, which looks at none while it runs: the step's statistics
+    flag it and the call returns MHD_ENOCONV."""
+    from paper_2108_05110_amd.ensemble import Mesh, Stepper, fixed_schedule_opts
+    N, J = 16, 8
+    say("non-finite detection, fixed schedule")
+    pb = wl.cavity(J=J, s=0.1, dt=0.01)
+    gm = Mesh(L.MHD_MESH_UNIT_SQUARE, N)
+    f = Stepper(gm, pb, opts=fixed_schedule_opts(), time_dependent_data=False, graph=True)
+    f.step(stats=False)
+    f.V[100, 0, 3] = float("nan")
+    with pytest.raises(L.MhdError) as ei:
+        f.step(stats=True)
+    assert ei.value.status == L.MHD_ENOCONV
+    assert "non-finite" in str(ei.value)
+    st = f.step(stats=True, allow_noconv=True)
+    assert st.warnings & L.MHD_WARN_NONFINITE
+    assert st.v.nonfinite + st.w.nonfinite > 0
+    f.close()
+    gm.close()

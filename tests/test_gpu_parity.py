@@ -118,6 +118,42 @@ def test_rhs_parity(L, J, which):
     b_g_in_o[perm] = b_gpu
     scale = np.abs(b_orc).max()
     assert np.abs(b_g_in_o - b_orc).max() <= 1e-13 * scale
+    # FP32 output: the same FP64 arithmetic, rounded once when stored
+    r32 = torch.full((n, J), float("nan"), dtype=torch.float32, device="cuda")
+    L.mhd_ens_assemble_rhs(gm.handle, c, which, J, dev(to_gpu_order(selfZ, pm2)), dev(to_gpu_order(otherZ, pm2)),
+                           dev(pb.nu), dev(pb.nu_m), dev(to_gpu_order(F, pm2)), dev(Gdir), r32)
+    assert torch.equal(r32, rhs.to(torch.float32))
+    gm.close()
+
+
+@pytest.mark.parametrize("m,J", [(2, 20), (1, 70)])
+def test_rhs_parity_step_channel(L, m, J):
+    """Right-hand sides on the step channel (cells missing under the step, a
+    do-nothing outflow) against the oracle, J spanning several member slices
+    with a ragged last one."""
+    from paper_2108_05110_amd.ensemble import Mesh
+    say("rhs channel", m, J)
+    pb = wl.step_channel(J=J, delta=0.1, s=0.01, dt=0.02)
+    gm = Mesh(L.MHD_MESH_STEP_CHANNEL, m, 1)
+    om_ = om.step_channel(m)
+    ens = scheme.Ensemble(om_, pb)
+    h = 1.0 / m
+    pm2 = node_map(gm.xy, om_.xy, h)
+    pm1 = p1_map(gm.xy, om_, h)
+    perm = unknown_perm(pm2, pm1, om_.nP2)
+    V, W = random_state(pb, om_.xy, 5)
+    Gv, _ = pb.bc(pb.dt, om_.xy)
+    F1, _ = pb.forcing(pb.dt, om_.xy)
+    b_orc = ens.rhs(V, W, F1, Gv)
+    rhs = torch.full((gm.n, J), float("nan"), dtype=torch.float64, device="cuda")
+    c = L.Coeffs(pb.dt, pb.mu, float(pb.nu.mean()), float(pb.nu_m.mean()), 0)
+    L.mhd_ens_assemble_rhs(gm.handle, c, 0, J, dev(to_gpu_order(V, pm2)), dev(to_gpu_order(W, pm2)), dev(pb.nu),
+                           dev(pb.nu_m), dev(to_gpu_order(F1, pm2)), dev(to_gpu_order(Gv, pm2)[gm.dir_nodes]), rhs)
+    b_gpu = rhs.cpu().numpy()
+    assert np.isfinite(b_gpu).all()
+    b_g_in_o = np.zeros_like(b_gpu)
+    b_g_in_o[perm] = b_gpu
+    assert np.abs(b_g_in_o - b_orc).max() <= 1e-13 * np.abs(b_orc).max()
     gm.close()
 
 
@@ -139,6 +175,7 @@ def test_solve_parity(L, precision, tol, J):
     L.mhd_ens_assemble_shared(gm.handle, c, dev(to_gpu_order(W, pm2)), J, A)
     bg = b[perm]
     x = torch.zeros((gm.n, J), dtype=torch.float64, device="cuda")
+    L.mhd_ens_prepare(A, J, precision)       # the tuned kernel plans, as a context would use them
     st, _ = L.mhd_ens_solve(A, dev(bg), x, J, L.solver_opts(precision))
     say("  iters", st.iters, "cycles", st.cycles, "relres", st.max_relres)
     xo = np.zeros_like(bg)

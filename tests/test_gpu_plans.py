@@ -221,3 +221,45 @@ def test_row_tile_values_follow_assembly(L):
         assert err <= 2e-6
     L.mhd_ens_shared_free(A)
     gm.close()
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_fused_multigrid_matches_sweeps(L, precision):
+    """The V-cycle levels as their two fused sparse operators against the same
+    cycle run sweep by sweep: the same solution (to the solve tolerance) and
+    iteration counts within rounding effects, and one fixed-schedule FP32 cycle
+    agreeing to FP32 rounding."""
+    from paper_2108_05110_amd.ensemble import Mesh, to_dev
+    N, J = 64, 64
+    say("fused multigrid", precision)
+    pb = wl.cavity(J=J, s=0.3, dt=0.01, ic_amp=0.05)
+    gm = Mesh(L.MHD_MESH_UNIT_SQUARE, N)
+    V, W = pb.ic(gm.xy)
+    A = L.mhd_ens_shared_create(gm.handle, J, 30)
+    c = L.Coeffs(pb.dt, pb.mu, float(pb.nu.mean()), float(pb.nu_m.mean()), 0)
+    L.mhd_ens_assemble_shared(gm.handle, c, to_dev(W), J, A)
+    L.mhd_ens_prepare(A, J, precision)
+    b = torch.randn((gm.n, J), dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(3))
+    out = {}
+    for unf in (0, 1):
+        x = torch.zeros_like(b)
+        st, _ = L.mhd_ens_solve(A, b, x, J, L.solver_opts(precision, rtol=1e-10, mg_unfused=unf))
+        out[unf] = (x, st.iters)
+        say("  unfused" if unf else "  fused", st.iters, st.max_relres)
+    rel = float(torch.linalg.norm(out[0][0] - out[1][0]) / torch.linalg.norm(out[1][0]))
+    assert rel < 1e-8, rel
+    # FP32 inner cycles stop at a residual reduction, so rounding may move a
+    # cycle's end by a few iterations; a wrong operator would change the rate
+    assert abs(out[0][1] - out[1][1]) <= max(2, out[1][1] // 10), (out[0][1], out[1][1])
+    if precision == 1:
+        xs = []
+        for unf in (0, 1):
+            x = torch.zeros_like(b)
+            L.mhd_ens_solve(A, b, x, J, L.solver_opts(1, restart=6, fixed_cycles=1, jacobi_sweeps=5,
+                                                        mg_unfused=unf))
+            xs.append(x)
+        d = float(torch.linalg.norm(xs[0] - xs[1]) / torch.linalg.norm(xs[1]))
+        say("  one fixed cycle: fused vs sweeps", d)
+        assert d < 1e-3, d
+    L.mhd_ens_shared_free(A)
+    gm.close()
