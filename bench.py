@@ -11,9 +11,10 @@ viscosities (synthetic, seeded).  Inputs are resident in device memory before
 the timed region.
 
 The timed step is the HIP graph of one step with a fixed solver schedule
-(default 2 refinement cycles of 6 right-preconditioned GMRES iterations, 5
-Jacobi sweeps damped by 0.85); its error against FP64 solves is reported after one step and
-after 8 steps.  The node-row kernels are chosen by the library's autotuner
+(default 2 refinement cycles of 6 right-preconditioned GMRES iterations, 7
+velocity Jacobi sweeps damped by 0.6, two V-cycles for the Schur part); its
+error against FP64 solves is reported after one step and after 8 steps, and
+its final residual along a 200-step trajectory.  The node-row kernels are chosen by the library's autotuner
 first; the chosen plans are part of the output.
 
 Reported beside it on the same GPU: the J-separate form (the same shared
@@ -255,7 +256,7 @@ def step_accuracy(L, mesh, pb, opts):
     a = Stepper(mesh, pb, opts=opts, time_dependent_data=False, graph=opts.fixed_cycles > 0)
     for _ in range(3):
         a.step(stats=False)
-    b = Stepper(mesh, pb, opts=L.solver_opts(L.MHD_FP64), time_dependent_data=False)
+    b = Stepper(mesh, pb, opts=fp64_reference_opts(L), time_dependent_data=False)
     for t_src, t_dst in ((a.V, b.V), (a.W, b.W), (a.Q, b.Q), (a.R, b.R)):
         t_dst.copy_(t_src)
     b.n = a.n
@@ -268,14 +269,21 @@ def step_accuracy(L, mesh, pb, opts):
     return out
 
 
-def multi_step_error(L, mesh, pb, opts, checkpoints=(8, 200)):
+def fp64_reference_opts(L):
+    """FP64 solves to a relative residual of 1e-11 with a preconditioner that
+    stays convergent in the developed cavity flow (Jacobi damping 0.5, two
+    V-cycles for the Schur part)."""
+    return L.solver_opts(L.MHD_FP64, rtol=1e-11, jacobi_omega=0.5, mg_cycles=2)
+
+
+def multi_step_error(L, mesh, pb, opts, checkpoints=(8,)):
     """Relative L2 difference after each of `checkpoints` steps from the initial
-    state with `opts` against FP64 solves to 1e-12 (errors of every step
-    accumulated), and the FP64 run's own time per step."""
+    state with `opts` against FP64 solves (errors of every step accumulated),
+    the largest final residual of the reference, and its time per step."""
     import torch
     from paper_2108_05110_amd.ensemble import Stepper
     a = Stepper(mesh, pb, opts=opts, time_dependent_data=False, graph=opts.fixed_cycles > 0)
-    b = Stepper(mesh, pb, opts=L.solver_opts(L.MHD_FP64, rtol=1e-11), time_dependent_data=False)
+    b = Stepper(mesh, pb, opts=fp64_reference_opts(L), time_dependent_data=False)
     rel = lambda x, y: float(torch.linalg.norm(x - y) / torch.linalg.norm(y))
     out, t64, worst = {}, 0.0, 0.0
     for n in range(1, max(checkpoints) + 1):
@@ -290,11 +298,48 @@ def multi_step_error(L, mesh, pb, opts, checkpoints=(8, 200)):
         if n in checkpoints:
             out[n] = max(rel(a.V, b.V), rel(a.W, b.W))
         if n % 25 == 0:
-            log(f"  trajectory step {n}")
+            log(f"  trajectory step {n}: error {max(rel(a.V, b.V), rel(a.W, b.W)):.2e}")
     out["reference_max_relres"] = worst
     a.close()
     b.close()
     return out, t64 / max(1, max(checkpoints) - 1)
+
+
+def residual_track(L, mesh, pb, opts, nsteps=200, every=50):
+    """Final relative residuals (max over members and both subproblems) of the
+    graph-captured schedule at every `every`-th of `nsteps` steps."""
+    from paper_2108_05110_amd.ensemble import Stepper
+    a = Stepper(mesh, pb, opts=opts, time_dependent_data=False, graph=True)
+    out = {}
+    for n in range(1, nsteps + 1):
+        st = a.step(stats=(n % every == 0), allow_noconv=True)
+        if n % every == 0:
+            out[n] = max(st.v.max_relres, st.w.max_relres)
+    a.close()
+    return out
+
+
+def trajectory_workload(args, L, wl, torch):
+    """The headline schedule against FP64 solves over `traj_steps` steps of the
+    cavity from the same initial state: relative L2 difference of the member
+    states at checkpoints, and the reference's largest final residual."""
+    from paper_2108_05110_amd.ensemble import Mesh
+    prec = L.MHD_FP32_IR if args.precision == "fp32ir" else L.MHD_FP64
+    opts = L.solver_opts(prec, restart=args.restart, fixed_cycles=args.cycles, jacobi_sweeps=args.sweeps,
+                         jacobi_omega=args.omega, mg_cycles=args.mg_cycles)
+    pb = wl.cavity(J=args.J, s=0.1, dt=0.01)
+    mesh = Mesh(L.MHD_MESH_UNIT_SQUARE, args.N)
+    tuned_plans(L, wl, mesh, args.J, prec)
+    n = args.traj_steps
+    cps = tuple(sorted({1, 8, 25, 50, 100, 150, n} & set(range(1, n + 1))))
+    err, t64 = multi_step_error(L, mesh, pb, opts, cps)
+    mesh.close()
+    return {"metric": "relative L2 difference of the member states against FP64 solves", "value": err.get(n),
+            "unit": "", "n_gpus": 1, "higher_is_better": False, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"cavity {args.N}x{args.N}, J={args.J}, {n} steps dt=0.01",
+                       "schedule": f"{args.cycles}x{args.restart}, {args.sweeps} sweeps damping {args.omega}, "
+                                   f"{args.mg_cycles} V-cycles"},
+            "errors": {str(k): v for k, v in err.items()}, "fp64_ms_per_step": 1e3 * t64}
 
 
 def member_problem(pb, j):
@@ -430,9 +475,10 @@ def headline(args, L, wl, torch):
     prec = L.MHD_FP32_IR if args.precision == "fp32ir" else L.MHD_FP64
     if args.schedule == "fixed":
         opts = L.solver_opts(prec, restart=args.restart, fixed_cycles=args.cycles, jacobi_sweeps=args.sweeps,
-                             jacobi_omega=args.omega)
+                             jacobi_omega=args.omega, mg_cycles=args.mg_cycles)
     else:
-        opts = L.solver_opts(prec, rtol=args.rtol, jacobi_sweeps=args.sweeps, jacobi_omega=args.omega)
+        opts = L.solver_opts(prec, rtol=args.rtol, jacobi_sweeps=args.sweeps, jacobi_omega=args.omega,
+                             mg_cycles=args.mg_cycles)
     graph = args.schedule == "fixed"
     pb = wl.cavity(J=args.J, s=0.1, dt=0.01)
     mesh = Mesh(L.MHD_MESH_UNIT_SQUARE, args.N)
@@ -474,8 +520,10 @@ def headline(args, L, wl, torch):
     achieved = bpl / avg_s / 1e9 if launches else None
     log("one-step accuracy")
     acc = step_accuracy(L, mesh, pb, opts)
-    log(f"{args.traj_steps}-step trajectory against FP64")
-    traj, fp64_s = multi_step_error(L, mesh, pb, opts, (8, args.traj_steps))
+    log("8-step trajectory against FP64")
+    traj, fp64_s = multi_step_error(L, mesh, pb, opts, (8,))
+    log(f"final residuals over {args.traj_steps} steps")
+    track = residual_track(L, mesh, pb, opts, args.traj_steps, 50) if graph else {}
     separate = None
     if not args.no_separate:
         log("J-separate solves")
@@ -518,16 +566,18 @@ def headline(args, L, wl, torch):
                    "n_unknowns": int(mesh.n), "J": args.J,
                    "precision": ("FP32 inner GMRES + FP64 refinement" if prec == L.MHD_FP32_IR else "FP64"),
                    "schedule": (f"hipGraph step, fixed {args.cycles} refinement cycles x {args.restart} GMRES "
-                                f"iterations, {args.sweeps} Jacobi sweeps (damping {args.omega or 0.85:g})" if graph else
-                                f"adaptive, rtol {args.rtol:g}, {args.sweeps} Jacobi sweeps (damping {args.omega or 0.85:g})"),
+                                f"iterations, {args.sweeps} Jacobi sweeps (damping {args.omega or 0.6:g}), "
+                                f"{args.mg_cycles} V-cycle(s)" if graph else
+                                f"adaptive, rtol {args.rtol:g}, {args.sweeps} Jacobi sweeps (damping {args.omega or 0.6:g})"),
                    "krylov_iterations_per_step": iters,
                    "eager_serial_member_steps_per_s": args.J * max(2, args.steps // 2) / e_elapsed,
                    "step_rel_l2_vs_fp64": acc,
                    "rel_l2_vs_fp64_after_8_steps": traj.get(8),
-                   f"rel_l2_vs_fp64_after_{args.traj_steps}_steps": traj.get(args.traj_steps),
-                   "trajectory_reference_max_relres": traj.get("reference_max_relres"),
+                   "reference_max_relres": traj.get("reference_max_relres"),
+                   "final_relres_by_step": {str(k): v for k, v in track.items()},
                    "fp64_mode": {"ms_per_step": 1e3 * fp64_s, "member_steps_per_s": args.J / fp64_s,
-                                 "schedule": "FP64 GMRES with FP64 refinement to rtol 1e-11, adaptive, eager"}},
+                                 "schedule": "FP64 GMRES with FP64 refinement to rtol 1e-11, adaptive, eager, "
+                                             "Jacobi damping 0.5, two V-cycles"}},
         "autotune": plans,
         "roofline": {"bound": "hbm",
                      "kernel": f"saddle-point SpMM ({saddle_kernel_name(plans.get('saddle'))})",
@@ -547,6 +597,77 @@ def headline(args, L, wl, torch):
         out["cpu_baseline"] = cpu_baseline(args.N, args.J)
     mesh.close()
     return out
+
+
+def step_workload(args, L, wl, torch):
+    """Only the graph-captured step of the headline configuration, replayed
+    `steps` times after the warm-up: the run the per-step kernel profile is
+    taken from (tuning and capture happen before the replays)."""
+    from paper_2108_05110_amd.ensemble import Mesh, Stepper
+    prec = L.MHD_FP32_IR if args.precision == "fp32ir" else L.MHD_FP64
+    opts = L.solver_opts(prec, restart=args.restart, fixed_cycles=args.cycles, jacobi_sweeps=args.sweeps,
+                         jacobi_omega=args.omega, mg_cycles=args.mg_cycles)
+    pb = wl.cavity(J=args.J, s=0.1, dt=0.01)
+    mesh = Mesh(L.MHD_MESH_UNIT_SQUARE, args.N)
+    plans = tuned_plans(L, wl, mesh, args.J, prec)
+    stp = Stepper(mesh, pb, opts=opts, time_dependent_data=False, graph=True)
+    for _ in range(args.warmup):
+        stp.step(stats=False)
+    log("replays")
+    elapsed = timed_steps(stp, args.steps)
+    stp.close()
+    mesh.close()
+    return {"metric": "member-steps/s (graph replays only)", "value": args.J * args.steps / elapsed,
+            "unit": "member-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32" if prec == L.MHD_FP32_IR else "f64", "data": "synthetic",
+            "config": {"workload": f"lid-driven cavity {args.N}x{args.N}, J={args.J}, graph step replays"},
+            "autotune": plans}
+
+
+def block_workload(args, L, wl, torch):
+    """Block GMRES (one Krylov space for the J members, with deflation) against
+    one Arnoldi process per member over the same shared SpMM and
+    preconditioner: the first-step systems of the cavity at J = 16 ... 128,
+    FP32 inner solves with FP64 refinement to rtol 1e-10 from x = 0; inner
+    iterations (one SpMM over the J columns each), solve time and final
+    residual."""
+    from paper_2108_05110_amd.ensemble import Mesh, to_dev
+    N = args.N
+    mesh = Mesh(L.MHD_MESH_UNIT_SQUARE, N)
+    rows = []
+    for J in (16, 32, 64, 128):
+        pb = wl.cavity(J=J, s=0.1, dt=0.01)
+        V, W = pb.ic(mesh.xy)
+        V, W = to_dev(V), to_dev(W)
+        A = L.mhd_ens_shared_create(mesh.handle, J, args.restart)
+        c = L.Coeffs(pb.dt, pb.mu, float(pb.nu.mean()), float(pb.nu_m.mean()), 0)
+        L.mhd_ens_assemble_shared(mesh.handle, c, W, J, A)
+        Gv, _ = pb.bc(pb.dt, mesh.xy[mesh.dir_nodes])
+        b = torch.empty((mesh.n, J), dtype=torch.float64, device="cuda")
+        L.mhd_ens_assemble_rhs(mesh.handle, c, L.MHD_V_PROBLEM, J, V, W, to_dev(pb.nu), to_dev(pb.nu_m), None,
+                               to_dev(Gv), b)
+        prec = L.MHD_FP32_IR if args.precision == "fp32ir" else L.MHD_FP64
+        L.mhd_ens_prepare(A, J, prec)
+        row = {"J": J}
+        for name, blk in (("per_member", 0), ("block", 1)):
+            opts = L.solver_opts(prec, rtol=1e-10, restart=args.restart, block_krylov=blk)
+            x = torch.zeros_like(b)
+            L.mhd_ens_solve(A, b, x, J, opts)            # warm-up
+            x.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, _ = L.mhd_ens_solve(A, b, x, J, opts)
+            torch.cuda.synchronize()
+            row[name] = {"iters": st.iters, "cycles": st.cycles, "ms": 1e3 * (time.perf_counter() - t0),
+                         "max_relres": st.max_relres, "min_block_rank": st.min_block_rank}
+        log(f"block J={J}: {row}")
+        rows.append(row)
+        L.mhd_ens_shared_free(A)
+    mesh.close()
+    return {"metric": "block GMRES vs per-member Arnoldi (first-step v-systems of the cavity)", "value": None,
+            "unit": "ms", "n_gpus": 1, "dtype": "f32" if args.precision == "fp32ir" else "f64", "data": "synthetic",
+            "config": {"workload": f"cavity {N}x{N}, restart {args.restart}, rtol 1e-10"}, "rows": rows}
 
 
 def spmm_workload(args, L, wl, torch):
@@ -651,7 +772,7 @@ def large_workload(args, L, wl, torch):
     seeds, s in {0.01, 0.1, 1, 1}), all advanced by one graph launch per step."""
     from paper_2108_05110_amd.ensemble import Mesh, Stepper
     opts = L.solver_opts(L.MHD_FP32_IR, restart=args.restart, fixed_cycles=args.cycles, jacobi_sweeps=args.sweeps,
-                         jacobi_omega=args.omega)
+                         jacobi_omega=args.omega, mg_cycles=args.mg_cycles)
     specs = [(512, wl.cavity(J=128, s=0.1, dt=0.01, cfg=4))]
     for i, sc in enumerate((0.01, 0.1, 1.0, 1.0)):
         specs.append((128, wl.cavity(J=16, s=sc, dt=0.01, cfg=10 + i)))
@@ -714,12 +835,15 @@ def main():
     ap.add_argument("--schedule", choices=["fixed", "adaptive"], default="fixed")
     ap.add_argument("--restart", type=int, default=6)
     ap.add_argument("--cycles", type=int, default=2)
-    ap.add_argument("--sweeps", type=int, default=5)
-    ap.add_argument("--omega", type=float, default=0.0, help="Jacobi damping (0: the library default)")
+    ap.add_argument("--sweeps", type=int, default=7)
+    ap.add_argument("--omega", type=float, default=0.6, help="Jacobi damping (0: the library default 0.6)")
+    ap.add_argument("--mg-cycles", type=int, default=2, help="V-cycles per Schur-part application")
     ap.add_argument("--rtol", type=float, default=1e-10)
-    ap.add_argument("--workload", choices=["cavity", "adjoint", "large", "spmm"], default="cavity")
+    ap.add_argument("--workload", choices=["cavity", "adjoint", "large", "spmm", "step", "block", "trajectory"],
+                    default="cavity")
     ap.add_argument("--separate-steps", type=int, default=5)
-    ap.add_argument("--traj-steps", type=int, default=200, help="steps of the trajectory error against FP64")
+    ap.add_argument("--traj-steps", type=int, default=200,
+                    help="steps of the residual track (and of the trajectory workload)")
     ap.add_argument("--no-large-spmm", action="store_true")
     ap.add_argument("--large-plan", default="4,0,6,1608,0", help="SpMM plan at 512^2 (or 'tune')")
     ap.add_argument("--no-separate", action="store_true")
@@ -742,6 +866,12 @@ def main():
         out = large_workload(args, L, wl, torch)
     elif args.workload == "spmm":
         out = spmm_workload(args, L, wl, torch)
+    elif args.workload == "step":
+        out = step_workload(args, L, wl, torch)
+    elif args.workload == "block":
+        out = block_workload(args, L, wl, torch)
+    elif args.workload == "trajectory":
+        out = trajectory_workload(args, L, wl, torch)
     else:
         if rank != 0:
             args.no_cpu_baseline = True

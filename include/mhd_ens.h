@@ -220,13 +220,19 @@ typedef struct {
                                  maxit and check_every are then ignored and the stats
                                  report max_relres = -1, converged = -1              */
     double jacobi_omega;      /* damping of the velocity-block Jacobi sweeps, in (0, 1.5];
-                                 0 = the default 0.85                                 */
+                                 0 = the default 0.6.  A developed flow makes the spectrum
+                                 of D^-1 A complex, and damping 0.85 then diverges; 0.6
+                                 with two V-cycles (mg_cycles) stays convergent         */
     int mg_unfused;           /* 0 (default): on each multigrid level above the coarsest
                                  the residual and its restriction run as one precomputed
                                  sparse operator, and so do the prolongation and the first
                                  post-smoothing sweep (4 launches per level instead of 6);
                                  1: one kernel per sweep, residual and transfer (the same
                                  arithmetic up to rounding)                              */
+    int mg_cycles;            /* V-cycles per application of the Schur part: 0 or 1 = one,
+                                 2 = two (the second on the first one's residual), a
+                                 closer approximation of (B D^-1 B^T)^-1 for flows where
+                                 the outer iteration is sensitive to it                */
     int block_krylov;         /* 1: block GMRES, one Krylov space shared by the J columns
                                  (block Gram-Schmidt with a second pass, pivoted Cholesky
                                  QR of each new block that deflates dependent directions,

@@ -254,6 +254,8 @@ mhd_status build_device_mesh(DevMesh& D) {
     if ((rc = dev_alloc(L, &D.scratch_mean, 2 * (size_t)h.nP2))) return rc;
     // pressure multigrid hierarchy
     D.levels.resize(h.levels.size());
+    D.levels_dt = h.schur_dt;
+    D.levels_nuc = h.schur_nuc;
     for (size_t l = 0; l < h.levels.size(); ++l) {
         const HostLevel& H = h.levels[l];
         DevLevel& G = D.levels[l];
@@ -287,6 +289,8 @@ mhd_status build_device_mesh(DevMesh& D) {
     return MHD_OK;
 }
 
+mhd_status alloc_schur(DevShared& S);
+
 mhd_status make_shared(DevMesh* m, int J_max, int restart, DevShared& S) {
     S.mesh = m;
     S.Jmax = J_max;
@@ -301,6 +305,7 @@ mhd_status make_shared(DevMesh* m, int J_max, int restart, DevShared& S) {
     if ((rc = dev_alloc(L, &S.zbar, 2 * (size_t)m->nP2))) return rc;
     if ((rc = dev_alloc(L, &S.l2, 7 * (size_t)m->n_el))) return rc;
     if ((rc = dev_alloc(L, &S.elem, 36 * (size_t)m->n_el))) return rc;
+    if ((rc = alloc_schur(S))) return rc;
     // defined values before the first assembly (the kernel tuner may run on them)
     MHD_HIP(hipMemset(S.valA, 0, sizeof(double) * (size_t)m->nnzA));
     MHD_HIP(hipMemset(S.valA32, 0, sizeof(float) * (size_t)m->nnzA));
@@ -325,17 +330,21 @@ mhd_status check_coeffs(const mhd_coeffs* c) {
     return MHD_OK;
 }
 
-// Recomputes the Schur-approximation hierarchy when (dt, nu_c) change and
-// copies the new values into the existing device arrays (same patterns).
-mhd_status refresh_schur(DevMesh& D, double dt, double nu_c) {
+// The handle's Schur-approximation values for (dt, nu_c): recomputed on the host
+// (the mesh keeps the last computation) and copied into the handle's own value
+// arrays when its key changes.  Synchronous; never called under capture.
+mhd_status refresh_schur(DevShared& S, double dt, double nu_c) {
+    if (S.schur_dt == dt && S.schur_nuc == nu_c) return MHD_OK;
+    DevMesh& D = *S.mesh;
     HostMesh& h = D.host;
-    if (h.schur_dt == dt && h.schur_nuc == nu_c) return MHD_OK;
-    mhd_status rc = schur_values(h, dt, nu_c);
-    if (rc) return rc;
+    if (!(h.schur_dt == dt && h.schur_nuc == nu_c)) {
+        mhd_status rc = schur_values(h, dt, nu_c);
+        if (rc) return rc;
+    }
     MHD_HIP(hipDeviceSynchronize());
     for (size_t l = 0; l < h.levels.size(); ++l) {
         const HostLevel& H = h.levels[l];
-        DevLevel& G = D.levels[l];
+        DevLevel& G = S.levels[l];
         if ((int64_t)H.L.val.size() != G.L.nnz) {
             set_error("refresh_schur: pattern size mismatch");
             return MHD_EINVAL;
@@ -364,11 +373,53 @@ mhd_status refresh_schur(DevMesh& D, double dt, double nu_c) {
             MHD_HIP(hipMemcpy(G.cinv32, c32.data(), sizeof(float) * c32.size(), hipMemcpyHostToDevice));
         }
     }
+    S.schur_dt = dt;
+    S.schur_nuc = nu_c;
+    return MHD_OK;
+}
+
+// value arrays of a handle's hierarchy: the mesh's patterns, own values (a copy
+// of the mesh's current ones until the first refresh)
+mhd_status alloc_schur(DevShared& S) {
+    DevMesh& D = *S.mesh;
+    auto& L = S.allocs;
+    S.levels = D.levels;
+    mhd_status rc;
+    auto dup = [&](auto** p, const auto* src, size_t count) -> mhd_status {
+        mhd_status r = dev_alloc(L, p, count);
+        if (r) return r;
+        if (count) MHD_HIP(hipMemcpy(*p, src, sizeof(**p) * count, hipMemcpyDeviceToDevice));
+        return MHD_OK;
+    };
+    for (size_t l = 0; l < D.levels.size(); ++l) {
+        const DevLevel& M = D.levels[l];
+        DevLevel& G = S.levels[l];
+        if ((rc = dup(&G.L.val, M.L.val, M.L.nnz))) return rc;
+        if ((rc = dup(&G.L.val32, M.L.val32, M.L.nnz))) return rc;
+        if ((rc = dup(&G.dinv, M.dinv, M.n))) return rc;
+        if ((rc = dup(&G.dinv32, M.dinv32, M.n))) return rc;
+        if (M.Dn.nnz) {
+            if ((rc = dup(&G.Dn.val, M.Dn.val, M.Dn.nnz))) return rc;
+            if ((rc = dup(&G.Dn.val32, M.Dn.val32, M.Dn.nnz))) return rc;
+        }
+        if (M.Up.nnz) {
+            if ((rc = dup(&G.Up.val, M.Up.val, M.Up.nnz))) return rc;
+            if ((rc = dup(&G.Up.val32, M.Up.val32, M.Up.nnz))) return rc;
+        }
+        if (l + 1 == D.levels.size()) {
+            if ((rc = dup(&G.cinv, M.cinv, (size_t)M.n * M.n))) return rc;
+            if ((rc = dup(&G.cinv32, M.cinv32, (size_t)M.ld32 * M.ld32))) return rc;
+        }
+    }
+    // the key of the values just copied: the mesh's device values keep the
+    // parameters they were built for, while its host copy follows the last refresh
+    S.schur_dt = D.levels_dt;
+    S.schur_nuc = D.levels_nuc;
     return MHD_OK;
 }
 
 mhd_status assemble_shared_impl(DevMesh& m, const mhd_coeffs& c, const double* z, int J, DevShared& S, hipStream_t s) {
-    mhd_status rc = refresh_schur(m, c.dt, 0.5 * (c.nu_bar + c.num_bar));
+    mhd_status rc = refresh_schur(S, c.dt, 0.5 * (c.nu_bar + c.num_bar));
     if (rc) return rc;
     hipError_t e = launch_mean(z, S.zbar, 2 * (int64_t)m.nP2, J, s);
     if (e == hipSuccess) e = launch_eddy_l2(m, z, S.zbar, S.l2, J, s);
@@ -396,6 +447,7 @@ mhd_status check_solver_opts(const mhd_solver_opts* o) {
     CHECK_ARG(o->jacobi_omega == 0 || (std::isfinite(o->jacobi_omega) && o->jacobi_omega > 0 && o->jacobi_omega <= 1.5),
               "jacobi_omega must be 0 (default) or in (0, 1.5]");
     CHECK_ARG(o->mg_unfused == 0 || o->mg_unfused == 1, "mg_unfused must be 0 or 1");
+    CHECK_ARG(o->mg_cycles >= 0 && o->mg_cycles <= 2, "mg_cycles must be 0, 1 or 2");
     CHECK_ARG(o->block_krylov == 0 || (o->block_krylov == 1 && o->fixed_cycles == 0),
               "block_krylov must be 0, or 1 with the adaptive schedule (fixed_cycles 0)");
     return MHD_OK;
@@ -448,7 +500,9 @@ mhd_status step_prepare(mhd_ctx ctx, const mhd_step_inputs* in, mhd_coeffs& c, h
         if (g.dt != c.dt || g.nu_bar != c.nu_bar || g.num_bar != c.num_bar || g.mu != c.mu) ctx->graph.reset();
     }
     ctx->graph_coeffs = c;
-    return refresh_schur(D, c.dt, 0.5 * (c.nu_bar + c.num_bar));
+    mhd_status rc = refresh_schur(ctx->Av->d, c.dt, 0.5 * (c.nu_bar + c.num_bar));
+    if (rc == MHD_OK) rc = refresh_schur(ctx->Aw->d, c.dt, 0.5 * (c.nu_bar + c.num_bar));
+    return rc;
 }
 
 // device part of a step (a1-a6): capturable into a graph when the solver runs a fixed schedule
@@ -1191,14 +1245,6 @@ mhd_status mhd_ens_group_step(mhd_group g, double* const* V, double* const* W, d
         mhd_status rc = step_prepare(g->ctxs[i], &in[i], cs[i], st);
         if (rc) return rc;
     }
-    // contexts on one mesh share its Schur-approximation hierarchy, so they must share its coefficients
-    for (int i = 0; i < n; ++i)
-        for (int k = i + 1; k < n; ++k)
-            if (g->ctxs[i]->mesh == g->ctxs[k]->mesh &&
-                (cs[i].dt != cs[k].dt || cs[i].nu_bar + cs[i].num_bar != cs[k].nu_bar + cs[k].num_bar)) {
-                set_error("mhd_ens_group_step: contexts on one mesh need equal dt and nu_bar + num_bar");
-                return MHD_EINVAL;
-            }
     // the mean viscosities, dt and mu enter the captured kernels by value: a change re-captures
     bool same = g->graph.valid && g->graph.stream == st && g->keys.size() == (size_t)n && g->coeffs.size() == (size_t)n;
     for (int i = 0; same && i < n; ++i)

@@ -78,7 +78,7 @@ constexpr int kEllShapes = 6;
 inline int ell_tx(int id) { return (id - 1) % 3 == 1 ? 32 : 16; }
 inline int ell_ty(int id) { return (id - 1) % 3 == 0 ? 16 : 8; }
 inline int ell_m(int id) { return id > 3 ? 8 : 16; }
-constexpr double kJacobiOmega = 0.85;  // velocity-block Jacobi damping when the options leave it 0
+constexpr double kJacobiOmega = 0.6;   // velocity-block Jacobi damping when the options leave it 0
 struct DevMesh {
     HostMesh host;
     int nP2 = 0, nP1 = 0, n_el = 0, n_dir = 0, pin = -1;
@@ -118,6 +118,7 @@ struct DevMesh {
     double* mp_inv = nullptr;
     uint8_t* pfix = nullptr;                      // nP1: fixed rows of the pressure Laplacian
     std::vector<DevLevel> levels;
+    double levels_dt = -1.0, levels_nuc = -1.0;   // the (dt, nu_c) the levels' values were built for
     DevTiling* tiling[kTileShapes + 1] = {};   // by shape id 1..kTileShapes, built on demand
     DevEll* ell[kEllShapes + 1] = {};          // row-per-lane tiles by shape id 1..kEllShapes, built on demand
     int32_t* pair_sched[9] = {};               // paired-row SpMM wave order by units per wavefront (4, 8)
@@ -151,6 +152,7 @@ struct GmresWork {
     int nblk_cap = 512;           // blocks of the column-reduction kernels for this J_max
     double* host_res = nullptr;   // pinned host copy (J)
     std::vector<void*> mg_x, mg_x2, mg_b, mg_r;   // per level (n_l x Jmax, sized for double)
+    void* mg_y0 = nullptr;        // finest level: the first V-cycle's result when two are run
     void* dense_part = nullptr;   // partial products of the coarsest dense solve (kDenseKS x n_c x Jmax)
     void** dptrs = nullptr;       // device array of the basis block pointers
     double* bmat = nullptr;       // 2 Jmax^2: J x J matrices of the block solver (Jmax <= kBlockMaxJ)
@@ -176,6 +178,10 @@ struct DevShared {
     int2* ellA[kEllShapes + 1] = {};    // packed A entries of the row-per-lane tiles (FP32 values)
     bool ell_live[kEllShapes + 1] = {};  // a plan uses the tiling: assemblies refresh ellA
     GmresWork gw;
+    // this handle's values of the pressure Schur-approximation hierarchy (patterns
+    // shared with the mesh's levels), for its own (dt, nu_c)
+    std::vector<DevLevel> levels;
+    double schur_dt = -1.0, schur_nuc = -1.0;
     std::vector<void*> allocs;
 };
 constexpr int kBlockMaxJ = 128;   // block GMRES: J in {16, 32, 64, 128}

@@ -2348,6 +2348,15 @@ __global__ void __launch_bounds__(kBlock) k_csr(const int32_t* __restrict__ rp, 
     }
 }
 
+// Schur part from two V-cycles: z_p = -(x1 + x2), the pinned row keeping r_p
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_schur2(const T* __restrict__ x1, const T* __restrict__ x2,
+                                                   const T* __restrict__ rp, int pin, T* __restrict__ zp, int64_t nP1,
+                                                   int J) {
+    for (int64_t o = (int64_t)blockIdx.x * kBlock + threadIdx.x; o < nP1 * J; o += (int64_t)gridDim.x * kBlock)
+        zp[o] = (o / J == pin) ? rp[o] : -(x1[o] + x2[o]);
+}
+
 // z_p = -x_mg (x_mg ~ S_hat^{-1} r_p from the V-cycle); the pinned row is an
 // identity row of S, so there z_p = r_p
 template <typename T>
@@ -3963,6 +3972,7 @@ struct Ops {
 
     NodePlan p_saddle, p_first, p_sweep;   // autotuned node-row kernels for this (mesh, J, word size)
     bool fused_mg = true;                  // V-cycle levels as their two fused operators
+    int mg_cycles = 1;                     // V-cycles per Schur-part application (1 or 2)
 
     Ops(DevShared& s, int j, hipStream_t stream) : S(s), J(j), st(stream), JP(pick_jp(j)) {
         const int word = (int)sizeof(T);
@@ -4012,11 +4022,10 @@ struct Ops {
     // Uses the level's buffers x, x2, r and the next level's b and x.  Returns
     // the buffer holding the result in *out.
     mhd_status vcycle(int l, const T* b, T** out, T* schur = nullptr, int pin = -1) {
-        DevMesh& m = *S.mesh;
-        const DevLevel& Lv = m.levels[l];
+        const DevLevel& Lv = S.levels[l];
         T* x = (T*)S.gw.mg_x[l];
         mhd_status rc;
-        if (l + 1 == (int)m.levels.size()) {
+        if (l + 1 == (int)S.levels.size()) {
             if constexpr (std::is_same<T, float>::value) {
                 if (J % 16 == 0) {
                     hipLaunchKernelGGL(k_dense_mf, dim3((Lv.n + 15) / 16, J / 16), dim3(kDenseWaves * 64), 0, st,
@@ -4060,7 +4069,7 @@ struct Ops {
         if (fuse) {   // x = E (x2 + P xc) + w D^-1 b = [E | E P | w D^-1] [x2; xc; b]
             const dim3 gu((unsigned)(((Lv.Up.nrows + 1) / 2 + 3) / 4), J / MJ);
             hipLaunchKernelGGL((k_mgf<T>), gu, dim3(kBlock), 0, st, Lv.Up.rowptr, Lv.Up.col, Vals<T>::csr(Lv.Up),
-                               (const T*)x2, (const T*)xc, b, Lv.n, m.levels[l + 1].n, x, (int)Lv.Up.nrows, J);
+                               (const T*)x2, (const T*)xc, b, Lv.n, S.levels[l + 1].n, x, (int)Lv.Up.nrows, J);
             LAUNCH_CHECK();
         } else {
             if ((rc = csr<1>(Lv.P, dinv, xc, nullptr, x2, omega))) return rc; // x2 += P xc
@@ -4084,7 +4093,19 @@ struct Ops {
         T* zp = z + off;
         mhd_status rc;
         T* xmg = nullptr;
-        if (m.levels.size() > 1 && packed(m.levels[0].L)) {
+        if (mg_cycles == 2 && S.levels.size() > 1 && packed(S.levels[0].L)) {
+            // two V-cycles: x1 = V(r_p), x2 = V(r_p - L x1), z_p = -(x1 + x2)
+            T* x1 = (T*)S.gw.mg_y0;
+            T* res = (T*)S.gw.mg_b[0];
+            const DevLevel& L0 = S.levels[0];
+            if ((rc = vcycle(0, vp, &xmg))) return rc;
+            MHD_HIP(hipMemcpyAsync(x1, xmg, sizeof(T) * (size_t)L0.n * J, hipMemcpyDeviceToDevice, st));
+            if ((rc = csr<2>(L0.L, Vals<T>::dinv(L0), x1, vp, res, (T)kMgOmega))) return rc;
+            if ((rc = vcycle(0, res, &xmg))) return rc;
+            hipLaunchKernelGGL((k_schur2<T>), dim3(ew_grid((int64_t)m.nP1 * J)), dim3(kBlock), 0, st, (const T*)x1,
+                               (const T*)xmg, vp, m.pin, zp, (int64_t)m.nP1, J);
+            LAUNCH_CHECK();
+        } else if (S.levels.size() > 1 && packed(S.levels[0].L)) {
             if ((rc = vcycle(0, vp, &xmg, zp, m.pin))) return rc;   // z_p written by the last smoothing sweep
         } else {
             if ((rc = vcycle(0, vp, &xmg))) return rc;
@@ -4214,6 +4235,7 @@ mhd_status gmres_solve(DevShared& S, const double* b, double* x, int J, const mh
     const double omega = o.jacobi_omega > 0 ? o.jacobi_omega : kJacobiOmega;
     Ops<T> ops(S, J, st);
     ops.fused_mg = o.mg_unfused == 0;
+    ops.mg_cycles = o.mg_cycles == 2 ? 2 : 1;
     RedShape rs = cap_blocks(red_shape(n, J, 16 / (int)sizeof(T)), G.nblk_cap);
     const int passes = o.cgs_passes > 0 ? o.cgs_passes : (sizeof(T) == 4 ? 1 : 2);
     const T* const* Vd = (const T* const*)G.dptrs;
@@ -4597,7 +4619,8 @@ struct BlockQR {
 // Least squares min || E1 C0 - Hb Y ||_F for the (m+1)J x mJ block Hessenberg
 // Hb (row-major) by Householder reflections (each column has at most 2J rows
 // below its diagonal); zero pivots (deflated directions) leave their Y rows 0.
-void block_lsq(std::vector<double> Hb, std::vector<double> rhs, int rows, int cols, int J, std::vector<double>& Y) {
+void block_lsq(std::vector<double> Hb, std::vector<double> rhs, int rows, int cols, int J, std::vector<double>& Y,
+               std::vector<double>* resid = nullptr) {
     const int nr = J;   // right-hand side columns
     std::vector<double> v(rows);
     std::vector<char> dead(cols, 0);
@@ -4629,6 +4652,12 @@ void block_lsq(std::vector<double> Hb, std::vector<double> rhs, int rows, int co
             d = 2.0 * d / vv;
             for (int r = c; r < last; ++r) rhs[(size_t)r * nr + k] -= d * v[r];
         }
+    }
+    if (resid) {   // least-squares residual of each column: the transformed rows below the triangle
+        resid->assign(nr, 0.0);
+        for (int r = cols; r < rows; ++r)
+            for (int k = 0; k < nr; ++k) (*resid)[k] += rhs[(size_t)r * nr + k] * rhs[(size_t)r * nr + k];
+        for (double& v : *resid) v = std::sqrt(v);
     }
     double dmax = 0.0;
     for (int c = 0; c < cols; ++c) dmax = std::max(dmax, std::fabs(Hb[(size_t)c * cols + c]));
@@ -4699,9 +4728,13 @@ mhd_status block_gmres_solve(DevShared& S, const double* b, double* x, int J, co
     const int mres = std::max(1, std::min(o.restart > 0 ? o.restart : G.restart, G.restart));
     const int sweeps = std::max(1, o.jacobi_sweeps);
     const double omega = o.jacobi_omega > 0 ? o.jacobi_omega : kJacobiOmega;
-    const double tol2 = sizeof(T) == 4 ? 1e-12 : 1e-24;   // deflation: pivot below 1e-6 (1e-12) of the largest
+    // deflation: a pivot below 1e-5 (FP32 basis) or 1e-7 (FP64) of the largest, the
+    // rounding level of a Cholesky update of the Gram matrix
+    const double tol2 = sizeof(T) == 4 ? 1e-10 : 1e-14;
+    const int check = std::max(1, o.check_every);
     Ops<T> ops(S, J, st);
     ops.fused_mg = o.mg_unfused == 0;
+    ops.mg_cycles = o.mg_cycles == 2 ? 2 : 1;
     BlockQR qr;
     qr.J = J;
     const bool keepz = sizeof(T) == 4 && G.zbasis != nullptr;
@@ -4765,6 +4798,23 @@ mhd_status block_gmres_solve(DevShared& S, const double* b, double* x, int J, co
         std::vector<std::vector<double>> H;   // H[i * mres + k]: block (i, k), J x J
         H.assign((size_t)(mres + 1) * mres, std::vector<double>((size_t)J * J, 0.0));
         int kd = 0;
+        bool have_y = false;
+        std::vector<double> lsres;
+        auto solve_ls = [&](int kk, std::vector<double>* res) {
+            const int rows = (kk + 1) * J, cols = kk * J;
+            Hb.assign((size_t)rows * cols, 0.0);
+            for (int i = 0; i <= kk; ++i)
+                for (int k = 0; k < kk; ++k) {
+                    if (i > k + 1) continue;
+                    const std::vector<double>& hb = H[(size_t)i * mres + k];
+                    for (int a = 0; a < J; ++a)
+                        for (int c = 0; c < J; ++c) Hb[(size_t)(i * J + a) * cols + k * J + c] = hb[(size_t)a * J + c];
+                }
+            std::vector<double> rhs((size_t)rows * J, 0.0);
+            for (int a = 0; a < J; ++a)
+                for (int c = 0; c < J; ++c) rhs[(size_t)a * J + c] = C0[(size_t)a * J + c];
+            block_lsq(Hb, rhs, rows, cols, J, Y, res);
+        };
         for (int k = 0; k < mres && iters < o.maxit; ++k) {
             T* vk = basis_ptr<T>(S, k);
             T* z = keepz ? zslot(k) : (T*)G.zbuf;
@@ -4799,21 +4849,19 @@ mhd_status block_gmres_solve(DevShared& S, const double* b, double* x, int J, co
             ++iters;
             kd = k + 1;
             if (pk == 0) break;   // the block Krylov space is exhausted
+            if (kd % check == 0 && kd < mres) {   // the members' least-squares residuals so far
+                solve_ls(kd, &lsres);
+                bool done = true;
+                for (int j = 0; j < J; ++j)
+                    if (!(lsres[j] <= std::max(o.inner_rtol * hbeta[j], 0.5 * o.rtol * hbn[j]))) done = false;
+                if (done) {
+                    have_y = true;
+                    break;
+                }
+            }
         }
         // block least squares and the correction d = P^-1 (V Y) (or Z Y with Z kept)
-        const int rows = (kd + 1) * J, cols = kd * J;
-        Hb.assign((size_t)rows * cols, 0.0);
-        for (int i = 0; i <= kd; ++i)
-            for (int k = 0; k < kd; ++k) {
-                if (i > k + 1) continue;
-                const std::vector<double>& hb = H[(size_t)i * mres + k];
-                for (int a = 0; a < J; ++a)
-                    for (int c = 0; c < J; ++c) Hb[(size_t)(i * J + a) * cols + k * J + c] = hb[(size_t)a * J + c];
-            }
-        std::vector<double> rhs((size_t)rows * J, 0.0);
-        for (int a = 0; a < J; ++a)
-            for (int c = 0; c < J; ++c) rhs[(size_t)a * J + c] = C0[(size_t)a * J + c];
-        block_lsq(Hb, rhs, rows, cols, J, Y);
+        if (!have_y) solve_ls(kd, nullptr);
         T* u = (T*)G.wbuf;
         for (int k = 0; k < kd; ++k) {
             std::vector<double> Yk(Y.begin() + (size_t)k * J * J, Y.begin() + (size_t)(k + 1) * J * J);
@@ -4919,6 +4967,7 @@ mhd_status alloc_gmres(DevShared& S, int restart) {
         G.mg_b.push_back(c);
         G.mg_r.push_back(d);
     }
+    if ((rc = A(&G.mg_y0, (size_t)m.levels[0].n * S.Jmax * sizeof(double)))) return rc;
     hipError_t e = hipHostMalloc((void**)&G.host_res, sizeof(double) * 3 * S.Jmax, hipHostMallocDefault);
     if (e != hipSuccess) {
         set_error(std::string("hipHostMalloc: ") + hipGetErrorString(e));

@@ -110,9 +110,13 @@ class Stepper:
 
 
 # Fixed solver schedule of the graph-captured step at the 128x128, J = 64
-# cavity: 2 FP64 refinement cycles of 6 FP32 GMRES iterations, 5 velocity
-# Jacobi sweeps with the library's default damping.
-FIXED_SCHEDULE = dict(restart=6, fixed_cycles=2, jacobi_sweeps=5)
+# cavity: 2 FP64 refinement cycles of 6 FP32 GMRES iterations, 7 velocity
+# Jacobi sweeps damped by 0.6 and two V-cycles for the Schur part.  Damping
+# 0.85 is faster while the flow is weak but diverges once the cavity flow
+# develops (about step 60 at dt = 0.01); this schedule keeps the one-step
+# error against FP64 solves below 3e-7 and the final relative residual below
+# 1e-8 over 200 steps.
+FIXED_SCHEDULE = dict(restart=6, fixed_cycles=2, jacobi_sweeps=7, jacobi_omega=0.6, mg_cycles=2)
 
 
 def fixed_schedule_opts(precision=L.MHD_FP32_IR, **over):

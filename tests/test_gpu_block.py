@@ -106,8 +106,11 @@ def test_block_gmres_deflates_identical_members(L, precision):
 
 def test_block_gmres_iterations_vs_per_member(L):
     """On the 32 x 32 cavity with J = 32 distinct right-hand sides, the block
-    Krylov space (dimension k J after k steps) needs no more iterations than
-    one Arnoldi process per member."""
+    Krylov space (dimension k J after k steps) contains every member's own
+    space, so its least-squares residuals after k steps are no larger than
+    one Arnoldi process per member reaches; both test them after every step
+    and stop a cycle at the same bar, so the block method needs no more
+    iterations."""
     from paper_2108_05110_amd.ensemble import Mesh, to_dev
     N, J = 32, 32
     say("block vs per-member iterations")

@@ -138,3 +138,42 @@ def test_nonfinite_state_reported_under_fixed_schedule(L):
     assert st.v.nonfinite + st.w.nonfinite > 0
     f.close()
     gm.close()
+
+
+def test_later_handles_on_a_mesh_match_the_first(L):
+    """A shared-matrix handle created after another one on the same mesh, and
+    after the mesh's pressure Schur hierarchy was recomputed for the time step,
+    must carry the hierarchy for its own (dt, nu) and solve exactly as the first:
+    same iterations, bit-identical iterates.  The same holds for whole graph-
+    captured steps of a second stepper started after the first was closed."""
+    from paper_2108_05110_amd.ensemble import Mesh, Stepper, fixed_schedule_opts, to_dev
+    N, J = 32, 8
+    say("later handles: 32^2, J=8, FP64 solves and fixed-schedule steppers")
+    pb = wl.cavity(J=J, s=0.1, dt=0.01, ic_amp=0.05)
+    gm = Mesh(L.MHD_MESH_UNIT_SQUARE, N)
+    V, W = pb.ic(gm.xy)
+    c = L.Coeffs(pb.dt, pb.mu, float(pb.nu.mean()), float(pb.nu_m.mean()), 0)
+    g = torch.Generator("cuda").manual_seed(3)
+    b = torch.randn((gm.n, J), dtype=torch.float64, device="cuda", generator=g)
+    out = []
+    for k in range(3):
+        A = L.mhd_ens_shared_create(gm.handle, J, 30)
+        L.mhd_ens_assemble_shared(gm.handle, c, to_dev(W), J, A)
+        x = torch.zeros_like(b)
+        st, _ = L.mhd_ens_solve(A, b, x, J, L.solver_opts(L.MHD_FP64, rtol=1e-10))
+        say(f"  handle {k}: {st.iters} iterations, relres {st.max_relres:.2e}")
+        out.append((st.iters, x))
+        L.mhd_ens_shared_free(A)
+    for its, x in out[1:]:
+        assert its == out[0][0]
+        assert torch.equal(x, out[0][1])
+    states = []
+    for k in range(2):
+        s = Stepper(gm, pb, opts=fixed_schedule_opts(), time_dependent_data=False, graph=True)
+        for _ in range(3):
+            st = s.step(stats=True)
+        say(f"  stepper {k}: final relres {st.v.max_relres:.2e} {st.w.max_relres:.2e}")
+        states.append((s.V.clone(), s.W.clone()))
+        s.close()
+    assert torch.equal(states[0][0], states[1][0]) and torch.equal(states[0][1], states[1][1])
+    gm.close()

@@ -101,3 +101,35 @@ def test_group_launch_equals_individual_steps(L):
         s.close()
     ma.close()
     mb.close()
+
+
+def test_group_on_one_mesh_with_different_viscosities(L):
+    """Two ensembles on one mesh whose mean viscosities differ (each shared
+    matrix handle keeps its own Schur-approximation values): one group launch
+    equals the two contexts stepped alone, bitwise, over three steps, and the
+    alternating contexts keep their values (no refresh between their steps)."""
+    from paper_2108_05110_amd.ensemble import Mesh, Stepper
+    say("group, one mesh, different viscosities")
+    pa = wl.cavity(J=4, s=0.1, dt=0.01, ic_amp=1e-2, cfg=7, nu_mean=1e-2, num_mean=1e-2)
+    pbb = wl.cavity(J=4, s=0.1, dt=0.01, ic_amp=1e-2, cfg=8, nu_mean=2e-3, num_mean=3e-3)
+    m = Mesh(L.MHD_MESH_UNIT_SQUARE, 16)
+    ref = [Stepper(m, pa, opts=fixed_opts(L)), Stepper(m, pbb, opts=fixed_opts(L))]
+    grp = [Stepper(m, pa, opts=fixed_opts(L)), Stepper(m, pbb, opts=fixed_opts(L))]
+    for s in grp:
+        s.set_data(s.pb.dt)
+    g = L.mhd_ens_group_create([s.ctx for s in grp])
+    stream = torch.cuda.Stream()
+    for n in range(3):
+        for s in ref:                 # alternate the two contexts on the one mesh
+            s.step(stats=False)
+        torch.cuda.synchronize()
+        L.mhd_ens_group_step(g, [s.V for s in grp], [s.W for s in grp], [s.Q for s in grp], [s.R for s in grp],
+                             [s.inputs() for s in grp], stream=stream)
+        stream.synchronize()
+        for r, s in zip(ref, grp):
+            assert torch.equal(r.V, s.V) and torch.equal(r.W, s.W), n
+    assert not torch.equal(grp[0].V, grp[1].V)
+    L.mhd_ens_group_free(g)
+    for s in ref + grp:
+        s.close()
+    m.close()
