@@ -71,8 +71,16 @@ def spmm_bytes_csr(info, J, word):
 
 
 def source_hash():
+    """Hash of the code that decides the SpMM's memory traffic: the row-per-lane
+    (sliced-ELL) kernels of solve.hip and the host code that lays out their
+    tiles.  A change anywhere else leaves recorded counter values valid."""
     h = hashlib.sha256()
     with open(os.path.join(ROOT, "paper_2108_05110_amd", "csrc", "solve.hip"), "rb") as f:
+        src = f.read()
+    begin = src.index(b"// ------------------------------------------------------------------ row-per-lane tiles")
+    end = src.index(b"// ------------------------------------------------------------------", begin + 10)
+    h.update(src[begin:end])
+    with open(os.path.join(ROOT, "paper_2108_05110_amd", "csrc", "tiling.cpp"), "rb") as f:
         h.update(f.read())
     return h.hexdigest()[:16]
 
@@ -82,7 +90,7 @@ def traffic_from_profiles(J, N, plan):
     WRITE_SIZE, scaled by the same counters on a copy of known size), if they
     were recorded for the current kernel source, shape and launch plan; else
     None."""
-    path = os.path.join(ROOT, "profiles", "spmm_traffic_cavity128_J64.json")
+    path = os.path.join(ROOT, "profiles", f"spmm_traffic_cavity{N}_J{J}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -418,6 +426,7 @@ def spmm_large(L, wl, torch, N=512, J=128, plan="4,0,6,1608,0"):
            "bytes_per_launch": b8, "avg_launch_us": avg * 1e6, "launches": launches,
            "achieved": b8 / avg / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": b8 / avg / 1e9 / HBM_PEAK_GBS,
            "compact_bytes_per_launch": spmm_bytes(mesh.info, J, 4),
+           "traffic": traffic_from_profiles(J, N, plan),
            "kernel": saddle_kernel_name(plan), "plan": {k: plan[k] for k in ("vec", "group", "deep", "tile", "waves")}
            if plan else None}
     mesh.close()
@@ -458,6 +467,40 @@ def saddle_kernel_name(plan):
     if plan["deep"]:
         return KERNEL_NAMES[plan["deep"]]
     return "k_saddle_g" if plan["group"] else "k_saddle_v"
+
+
+def rhs_timing(L, wl, torch, mesh, J, reps=20):
+    """One subproblem's batched right-hand sides (mhd_ens_assemble_rhs) at the
+    headline shape, FP64 and FP32 output, timed with events around `reps`
+    launches on the current stream.  Algorithmic bytes: the member states of
+    both variables read once (FP64), the ensemble mean and boundary values,
+    the right-hand sides written once; the cavity has no body force."""
+    import numpy as np
+    pb = wl.cavity(J=J, s=0.1, dt=0.01)
+    V, W = pb.ic(mesh.xy)
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), device="cuda")
+    Vd, Wd, nu, num = dev(V), dev(W), dev(pb.nu), dev(pb.nu_m)
+    Gv, _ = pb.bc(pb.dt, mesh.xy[mesh.dir_nodes])
+    g = dev(Gv)
+    c = L.Coeffs(pb.dt, pb.mu, float(pb.nu.mean()), float(pb.nu_m.mean()), 0)
+    out = {}
+    nP2, n, ndir = V.shape[0], int(mesh.n), len(mesh.dir_nodes)
+    for name, dt in (("fp64", torch.float64), ("fp32", torch.float32)):
+        rhs = torch.empty((n, J), dtype=dt, device="cuda")
+        for _ in range(3):
+            L.mhd_ens_assemble_rhs(mesh.handle, c, L.MHD_V_PROBLEM, J, Vd, Wd, nu, num, None, g, rhs)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            L.mhd_ens_assemble_rhs(mesh.handle, c, L.MHD_V_PROBLEM, J, Vd, Wd, nu, num, None, g, rhs)
+        e1.record()
+        torch.cuda.synchronize()
+        us = 1e3 * e0.elapsed_time(e1) / reps
+        word = 8 if dt == torch.float64 else 4
+        b = 8 * (2 * 2 * nP2 * J + 2 * nP2 + 2 * ndir * J) + word * n * J
+        out[name] = {"us": us, "bytes": b, "GB_s": b / us / 1e3, "frac_hbm": b / us / 1e3 / HBM_PEAK_GBS}
+    out["kernel"] = "k_rhs_strip"
+    return out
 
 
 def timed_steps(stp, steps):
@@ -518,6 +561,8 @@ def headline(args, L, wl, torch):
     bpl = spmm_bytes_csr(mesh.info, args.J, word)
     avg_s = (ms / 1e3) / max(launches, 1)
     achieved = bpl / avg_s / 1e9 if launches else None
+    log("right-hand side timing")
+    rhs_us = rhs_timing(L, wl, torch, mesh, args.J)
     log("one-step accuracy")
     acc = step_accuracy(L, mesh, pb, opts)
     log("8-step trajectory against FP64")
@@ -588,6 +633,7 @@ def headline(args, L, wl, torch):
                      "compact_bytes_per_launch": bpl_compact,
                      "compact_frac": (bpl_compact / avg_s / 1e9 / HBM_PEAK_GBS) if launches else None,
                      "avg_launch_us": avg_s * 1e6, "launches": launches},
+        "rhs": rhs_us,
         "spmm_512_J128": None if args.no_large_spmm else spmm_large(L, wl, torch, plan=args.large_plan),
         "separate": separate,
         "cpu_baseline": None,
@@ -613,6 +659,8 @@ def step_workload(args, L, wl, torch):
     stp = Stepper(mesh, pb, opts=opts, time_dependent_data=False, graph=True)
     for _ in range(args.warmup):
         stp.step(stats=False)
+    torch.cuda.synchronize()
+    time.sleep(0.25)   # an idle gap that separates the replays from tuning and capture in a kernel trace
     log("replays")
     elapsed = timed_steps(stp, args.steps)
     stp.close()
@@ -709,13 +757,14 @@ def spmm_workload(args, L, wl, torch):
     torch.cuda.synchronize()
     L.mhd_ens_shared_free(A)
     word = 4 if prec == L.MHD_FP32_IR else 8
-    bpl = spmm_bytes(mesh.info, args.J, word)
+    bpl = spmm_bytes_csr(mesh.info, args.J, word)
     out = {"metric": "saddle-point SpMM algorithmic GB/s", "value": bpl / el / 1e9, "unit": "GB/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": el * 1e3,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f32" if word == 4 else "f64", "data": "synthetic",
            "config": {"workload": f"saddle-point SpMM, unit square {args.N}x{args.N} P2-P1, J={args.J}",
-                      "bytes_per_launch": bpl, "copy_reference_bytes": copy_bytes,
+                      "bytes_per_launch": bpl, "compact_bytes_per_launch": spmm_bytes(mesh.info, args.J, word),
+                      "copy_reference_bytes": copy_bytes,
                       "kernel": saddle_kernel_name(plans.get("saddle"))},
            "autotune": plans}
     mesh.close()

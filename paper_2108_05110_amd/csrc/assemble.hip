@@ -328,7 +328,7 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 template <typename TO, int M>
-__global__ void __launch_bounds__(kBlock) k_rhs_strip(
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 3))) k_rhs_strip(
     const int32_t* __restrict__ cell_el, const int32_t* __restrict__ hs_p2, const int32_t* __restrict__ tri,
     const double* __restrict__ geo, const int32_t* __restrict__ dir_index, const int32_t* __restrict__ p1_of_p2,
     const double* __restrict__ self, const double* __restrict__ other, const double* __restrict__ obar,
@@ -338,10 +338,15 @@ __global__ void __launch_bounds__(kBlock) k_rhs_strip(
     constexpr int TXO = 2 * SLOTS - 1;          // owned cell columns
     constexpr int NODES = 2 * TXO;              // owned half-step columns
     constexpr int LINE = NODES * 2 * M;         // accumulators of one node line
-    // half-step offsets of the local nodes of the lower and upper triangle of a cell
-    constexpr int dI[2][6] = {{0, 2, 2, 1, 2, 1}, {0, 2, 0, 1, 1, 0}};
-    constexpr int dK[2][6] = {{0, 0, 2, 0, 1, 1}, {0, 2, 2, 1, 2, 1}};
+    // half-step offsets of the local nodes of the lower (0) and upper (1)
+    // triangle of a cell, one 4-bit field per node (a register operand, not a table
+    // in memory): lower (0,0) (2,0) (2,2) (1,0) (2,1) (1,1), upper (0,0) (2,2)
+    // (0,2) (1,1) (1,2) (0,1) as (I, K)
+    constexpr unsigned kDI[2] = {0x121220u, 0x011020u};
+    constexpr unsigned kDK[2] = {0x110200u, 0x121220u};
     __shared__ double lds[kBlock / 64][3 * LINE];
+    __shared__ int topo[kBlock / 64][SLOTS][4][7];   // per phase: the 6 nodes, then the element (-1: none)
+    __shared__ int meta[kBlock / 64][3][NODES][3];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t w = xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) + wv;
     if (w >= (int64_t)gd.nstrips * gd.nseg * gd.nslices) return;    // whole wavefront; no block barrier below
@@ -362,19 +367,38 @@ __global__ void __launch_bounds__(kBlock) k_rhs_strip(
         double* ln = L + (K % 3) * LINE;
         for (int q = lane; q < LINE; q += 64) ln[q] = 0.0;
     };
-    auto flush_line = [&](int K) {
+    // node, Dirichlet index and P1 index of the owned nodes of lines 2k .. 2k+2
+    // (k the current cell row), fetched once per row
+    auto fetch_meta = [&](int k) {
+        for (int q = lane; q < 3 * NODES; q += 64) {
+            const int l = q / NODES, nd = q % NODES;
+            const int I = I0 + nd, K = 2 * k + l;
+            int id = -1, di = -1, p1 = -1;
+            if (I < I1 && K >= K0 && K < K1) {
+                id = hs_p2[(int64_t)K * NXh + I];
+                if (id >= 0) {
+                    di = dir_index[id];
+                    p1 = p1_of_p2[id];
+                }
+            }
+            meta[wv][l][nd][0] = id;
+            meta[wv][l][nd][1] = di;
+            meta[wv][l][nd][2] = p1;
+        }
+    };
+    auto flush_line = [&](int K, int k) {
         if (K < K0 || K >= K1) return;
         const double* ln = L + (K % 3) * LINE;
+        const int l = K - 2 * k;
         for (int q = lane; q < LINE; q += 64) {
             const int mm = q % M, d = (q / M) & 1, nd = q / (2 * M);
-            const int I = I0 + nd, jj = slice * M + mm;
-            if (I >= I1 || jj >= J) continue;
-            const int id = hs_p2[(int64_t)K * NXh + I];
-            if (id < 0) continue;
-            const int di = dir_index[id];
+            const int jj = slice * M + mm;
+            const int id = meta[wv][l][nd][0];
+            if (id < 0 || jj >= J) continue;
+            const int di = meta[wv][l][nd][1];
             const double v = di >= 0 ? G[(2 * (int64_t)di + d) * J + jj] : ln[q];
             b[(2 * (int64_t)id + d) * J + jj] = (TO)v;
-            const int p1 = p1_of_p2[id];
+            const int p1 = meta[wv][l][nd][2];
             if (d == 0 && p1 >= 0) b[(2 * (int64_t)nP2 + p1) * J + jj] = (TO)0;
         }
     };
@@ -385,26 +409,41 @@ __global__ void __launch_bounds__(kBlock) k_rhs_strip(
         zero_line(2 * k + 1);
         zero_line(2 * k + 2);
         wave_sync();
+        // the row's four elements of each slot and their nodes, loaded up front by
+        // the slot's lanes together into LDS, so that each phase below waits for
+        // one round of node-value loads only
+        fetch_meta(k);
+        for (int q = mem; q < 4 * 7; q += M) {
+            const int ph = q / 7, bb = q % 7;
+            const int i = ci0 - 1 + 2 * slot + (ph & 1);
+            int e = -1;
+            if (i >= 0 && i < gd.nx) {
+                const int c = cell_el[(int64_t)k * gd.nx + i];
+                if (c >= 0) e = c + (ph >> 1);
+            }
+            topo[wv][slot][ph][bb] = bb == 6 ? e : (e >= 0 ? tri[(int64_t)e * 6 + bb] : 0);
+        }
+        wave_sync();
 #pragma unroll 1
         for (int ph = 0; ph < 4; ++ph) {
             const int up = ph >> 1;
             const int i = ci0 - 1 + 2 * slot + (ph & 1);
-            int e = -1;
-            if (live && i >= 0 && i < gd.nx) {
-                const int c = cell_el[(int64_t)k * gd.nx + i];
-                if (c >= 0) e = c + up;
-            }
+            const int e = live ? topo[wv][slot][ph][6] : -1;
             if (e >= 0) {
-                // the reference tables are read per element through a pointer the
-                // compiler cannot see through, so that it streams them from the
-                // scalar cache instead of holding all of them in registers
-                const RefTables* R = &c_ref;
+                // the reference tables are read per element through a constant-
+                // address-space pointer the compiler cannot see through, so that it
+                // streams them with scalar loads from the scalar cache instead of
+                // holding all of them in registers (a generic pointer would turn
+                // every table read into a vector memory load; immediate constants
+                // spill scalar registers and measured no faster)
+                using ConstTables = const __attribute__((address_space(4))) RefTables*;
+                ConstTables R = (ConstTables)&c_ref;
                 asm volatile("" : "+s"(R));
                 const Geo g = load_geo(geo, e);
                 double s[6][2], ms[6][2], ks[6][2], uh[6][2];
 #pragma unroll
                 for (int bb = 0; bb < 6; ++bb) {
-                    const int64_t t = tri[(int64_t)e * 6 + bb];
+                    const int64_t t = topo[wv][slot][ph][bb];
                     double od[2];
 #pragma unroll
                     for (int d = 0; d < 2; ++d) {
@@ -427,8 +466,8 @@ __global__ void __launch_bounds__(kBlock) k_rhs_strip(
                     for (int bb = 0; bb < 6; ++bb) {
                         const double m = R->Mhat[a][bb];
                         const double kk = R->Kc[a][bb][0] * G00 + R->Kc[a][bb][1] * G01 + R->Kc[a][bb][2] * G11;
-                        r0 += m * ms[bb][0] - kk * ks[bb][0];
-                        r1 += m * ms[bb][1] - kk * ks[bb][1];
+                        r0 = fma(m, ms[bb][0], fma(-kk, ks[bb][0], r0));
+                        r1 = fma(m, ms[bb][1], fma(-kk, ks[bb][1], r1));
                     }
                     r[a][0] = g.det * r0;
                     r[a][1] = g.det * r1;
@@ -463,7 +502,8 @@ __global__ void __launch_bounds__(kBlock) k_rhs_strip(
                 const int ci = 2 * i, ck = 2 * k;
 #pragma unroll
                 for (int a = 0; a < 6; ++a) {
-                    const int I = ci + dI[up][a], K = ck + dK[up][a];
+                    const int I = ci + (int)(((up ? kDI[1] : kDI[0]) >> (4 * a)) & 15u);
+                    const int K = ck + (int)(((up ? kDK[1] : kDK[0]) >> (4 * a)) & 15u);
                     if (I < I0 || I >= I1 || K < K0 || K >= K1) continue;
                     double* acc = L + (K % 3) * LINE + ((I - I0) * 2) * M + mem;
                     acc[0] += r[a][0];
@@ -472,9 +512,9 @@ __global__ void __launch_bounds__(kBlock) k_rhs_strip(
             }
             wave_sync();
         }
-        flush_line(2 * k);
-        flush_line(2 * k + 1);
-        if (k == k_last) flush_line(2 * k + 2);
+        flush_line(2 * k, k);
+        flush_line(2 * k + 1, k);
+        if (k == k_last) flush_line(2 * k + 2, k);
         wave_sync();
     }
 }

@@ -135,7 +135,7 @@ mhd_status build_mesh(const mhd_mesh_desc* d, HostMesh& m, bool full);
 mhd_status schur_values(HostMesh& m, double dt, double nu_c);
 void mesh_counts(const HostMesh& m, mhd_mesh_info* info);
 
-// reference-element tables (host computed, uploaded to constant memory)
+// reference-element tables (uploaded to constant memory; also compile-time constants below)
 struct RefTables {
     double w[7];            // quadrature weights summing to 1
     double phi[7][6];       // P2 values at the points
@@ -149,5 +149,78 @@ struct RefTables {
     double Kc[6][6][3];     // Khat[a][b] combined for a symmetric G: [0][0], [0][1] + [1][0], [1][1]
 };
 void make_ref_tables(RefTables& t);
+
+// square root by Newton's iteration, usable in constant expressions
+constexpr double ce_sqrt(double x) {
+    double r = x > 1.0 ? x : 1.0;
+    for (int i = 0; i < 100; ++i) r = 0.5 * (r + x / r);
+    return r;
+}
+
+// The reference-element tables of the P2-P1 pair (Section 2), evaluated with
+// Radon's 7-point rule, exact for the polynomial degrees involved (mass: 4,
+// stiffness: 2, trilinear: 5).  constexpr, so that kernels can take the
+// entries as immediate constants.
+constexpr RefTables build_ref_tables() {
+    RefTables t{};
+    const double s15 = ce_sqrt(15.0);
+    double lam[7][3] = {};
+    lam[0][0] = lam[0][1] = lam[0][2] = 1.0 / 3.0;
+    t.w[0] = 9.0 / 40.0;
+    const double aa[2] = {(6.0 - s15) / 21.0, (6.0 + s15) / 21.0};
+    const double ww[2] = {(155.0 - s15) / 1200.0, (155.0 + s15) / 1200.0};
+    int q = 1;
+    for (int o = 0; o < 2; ++o) {
+        const double a = aa[o], b = 1.0 - 2.0 * a;
+        const double pts[3][3] = {{b, a, a}, {a, b, a}, {a, a, b}};
+        for (int k = 0; k < 3; ++k) {
+            for (int i = 0; i < 3; ++i) lam[q][i] = pts[k][i];
+            t.w[q] = ww[o];
+            ++q;
+        }
+    }
+    // barycentric gradients on the reference triangle (0,0),(1,0),(0,1); local
+    // nodes: the three vertices, then the midpoints of edges 01, 12, 20
+    const double dl[3][2] = {{-1.0, -1.0}, {1.0, 0.0}, {0.0, 1.0}};
+    const int ed[3][2] = {{0, 1}, {1, 2}, {2, 0}};
+    for (q = 0; q < 7; ++q) {
+        for (int i = 0; i < 3; ++i) {
+            const double li = lam[q][i];
+            t.phi[q][i] = li * (2.0 * li - 1.0);
+            for (int d = 0; d < 2; ++d) t.dphi[q][i][d] = (4.0 * li - 1.0) * dl[i][d];
+            t.psi[q][i] = li;
+        }
+        for (int e = 0; e < 3; ++e) {
+            const int a = ed[e][0], b = ed[e][1];
+            t.phi[q][3 + e] = 4.0 * lam[q][a] * lam[q][b];
+            for (int d = 0; d < 2; ++d) t.dphi[q][3 + e][d] = 4.0 * (lam[q][b] * dl[a][d] + lam[q][a] * dl[b][d]);
+        }
+    }
+    for (q = 0; q < 7; ++q) {
+        const double wq = 0.5 * t.w[q];
+        for (int a = 0; a < 6; ++a)
+            for (int b = 0; b < 6; ++b) {
+                t.Mhat[a][b] += wq * t.phi[q][a] * t.phi[q][b];
+                for (int e = 0; e < 2; ++e)
+                    for (int f = 0; f < 2; ++f) t.Khat[a][b][e][f] += wq * t.dphi[q][a][e] * t.dphi[q][b][f];
+                for (int c = 0; c < 6; ++c)
+                    for (int e = 0; e < 2; ++e) t.That[a][b][c][e] += wq * t.phi[q][a] * t.phi[q][b] * t.dphi[q][c][e];
+            }
+        for (int k = 0; k < 3; ++k)
+            for (int a = 0; a < 6; ++a)
+                for (int e = 0; e < 2; ++e) t.Bhat[k][a][e] -= wq * t.psi[q][k] * t.dphi[q][a][e];
+    }
+    for (int a = 0; a < 6; ++a)
+        for (int b = 0; b < 6; ++b)
+            for (int c = 0; c < 6; ++c)
+                for (int e = 0; e < 2; ++e) t.Shat[a][b][c][e] = 0.5 * (t.That[a][b][c][e] - t.That[c][b][a][e]);
+    for (int a = 0; a < 6; ++a)
+        for (int b = 0; b < 6; ++b) {
+            t.Kc[a][b][0] = t.Khat[a][b][0][0];
+            t.Kc[a][b][1] = t.Khat[a][b][0][1] + t.Khat[a][b][1][0];
+            t.Kc[a][b][2] = t.Khat[a][b][1][1];
+        }
+    return t;
+}
 
 }  // namespace mhd

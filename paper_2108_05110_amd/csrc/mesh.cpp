@@ -353,68 +353,7 @@ mhd_status schur_values(HostMesh& m, double dt, double nu_c) {
 }
 
 // ---------------------------------------------------------------- reference tables
-void make_ref_tables(RefTables& t) {
-    std::memset(&t, 0, sizeof(t));
-    // 7-point degree-5 rule (Radon): centroid + two 3-point orbits (a, a, 1-2a)
-    const double s15 = std::sqrt(15.0);
-    double lam[7][3];
-    lam[0][0] = lam[0][1] = lam[0][2] = 1.0 / 3.0;
-    t.w[0] = 9.0 / 40.0;
-    const double aa[2] = {(6.0 - s15) / 21.0, (6.0 + s15) / 21.0};
-    const double ww[2] = {(155.0 - s15) / 1200.0, (155.0 + s15) / 1200.0};
-    int q = 1;
-    for (int o = 0; o < 2; ++o) {
-        double a = aa[o], b = 1.0 - 2.0 * a;
-        double pts[3][3] = {{b, a, a}, {a, b, a}, {a, a, b}};
-        for (auto& p : pts) {
-            lam[q][0] = p[0];
-            lam[q][1] = p[1];
-            lam[q][2] = p[2];
-            t.w[q] = ww[o];
-            ++q;
-        }
-    }
-    // barycentric gradients on the reference triangle (0,0),(1,0),(0,1)
-    const double dl[3][2] = {{-1.0, -1.0}, {1.0, 0.0}, {0.0, 1.0}};
-    const int ed[3][2] = {{0, 1}, {1, 2}, {2, 0}};
-    for (q = 0; q < 7; ++q) {
-        const double* l = lam[q];
-        for (int i = 0; i < 3; ++i) {
-            t.phi[q][i] = l[i] * (2.0 * l[i] - 1.0);
-            for (int d = 0; d < 2; ++d) t.dphi[q][i][d] = (4.0 * l[i] - 1.0) * dl[i][d];
-            t.psi[q][i] = l[i];
-        }
-        for (int e = 0; e < 3; ++e) {
-            int a = ed[e][0], b = ed[e][1];
-            t.phi[q][3 + e] = 4.0 * l[a] * l[b];
-            for (int d = 0; d < 2; ++d) t.dphi[q][3 + e][d] = 4.0 * (l[b] * dl[a][d] + l[a] * dl[b][d]);
-        }
-    }
-    for (q = 0; q < 7; ++q) {
-        double wq = 0.5 * t.w[q];
-        for (int a = 0; a < 6; ++a)
-            for (int b = 0; b < 6; ++b) {
-                t.Mhat[a][b] += wq * t.phi[q][a] * t.phi[q][b];
-                for (int e = 0; e < 2; ++e)
-                    for (int f = 0; f < 2; ++f) t.Khat[a][b][e][f] += wq * t.dphi[q][a][e] * t.dphi[q][b][f];
-                for (int c = 0; c < 6; ++c)
-                    for (int e = 0; e < 2; ++e) t.That[a][b][c][e] += wq * t.phi[q][a] * t.phi[q][b] * t.dphi[q][c][e];
-            }
-        for (int k = 0; k < 3; ++k)
-            for (int a = 0; a < 6; ++a)
-                for (int e = 0; e < 2; ++e) t.Bhat[k][a][e] -= wq * t.psi[q][k] * t.dphi[q][a][e];
-    }
-    for (int a = 0; a < 6; ++a)
-        for (int b = 0; b < 6; ++b)
-            for (int c = 0; c < 6; ++c)
-                for (int e = 0; e < 2; ++e) t.Shat[a][b][c][e] = 0.5 * (t.That[a][b][c][e] - t.That[c][b][a][e]);
-    for (int a = 0; a < 6; ++a)
-        for (int b = 0; b < 6; ++b) {
-            t.Kc[a][b][0] = t.Khat[a][b][0][0];
-            t.Kc[a][b][1] = t.Khat[a][b][0][1] + t.Khat[a][b][1][0];
-            t.Kc[a][b][2] = t.Khat[a][b][1][1];
-        }
-}
+void make_ref_tables(RefTables& t) { t = build_ref_tables(); }
 
 // ---------------------------------------------------------------- mesh
 mhd_status build_mesh(const mhd_mesh_desc* d, HostMesh& m, bool full) {
