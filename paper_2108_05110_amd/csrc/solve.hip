@@ -4617,61 +4617,127 @@ struct BlockQR {
 };
 
 // Least squares min || E1 C0 - Hb Y ||_F for the (m+1)J x mJ block Hessenberg
-// Hb (row-major) by Householder reflections (each column has at most 2J rows
-// below its diagonal); zero pivots (deflated directions) leave their Y rows 0.
-void block_lsq(std::vector<double> Hb, std::vector<double> rhs, int rows, int cols, int J, std::vector<double>& Y,
-               std::vector<double>* resid = nullptr) {
-    const int nr = J;   // right-hand side columns
-    std::vector<double> v(rows);
-    std::vector<char> dead(cols, 0);
-    for (int c = 0; c < cols; ++c) {
-        const int last = std::min(rows, (c / J + 2) * J);   // rows with entries in this column
-        double nrm = 0.0;
-        for (int r = c; r < last; ++r) nrm += Hb[(size_t)r * cols + c] * Hb[(size_t)r * cols + c];
-        nrm = std::sqrt(nrm);
-        if (!(nrm > 1e-300)) {
-            dead[c] = 1;
-            continue;
+// Hb, updated one block column per Arnoldi step (the block form of GMRES's
+// Givens updates): the new column block receives the Householder reflections
+// of all earlier columns, then gets its own J reflections (each spans at most
+// 2J rows, the column's nonzeros below its diagonal), which are applied to the
+// right-hand side block too.  After step k the transformed right-hand side rows
+// below the triangle give every member's least-squares residual.  Zero pivots
+// (deflated directions) leave their Y rows 0.
+struct BlockLSQ {
+    int J = 0, mres = 0, cols = 0;
+    std::vector<std::vector<double>> Wb;   // column block k: (k + 2) J rows x J columns, column-major
+    std::vector<double> rhs;  // (mres + 1) J rows x J
+    std::vector<double> vref; // per column: its reflector over rows c .. c + 2J - 1 (zero-padded)
+    std::vector<double> vnorm;
+    std::vector<char> dead;
+    void reset(int J_, int mres_, const std::vector<double>& C0) {
+        J = J_;
+        mres = mres_;
+        cols = 0;
+        const size_t R = (size_t)(mres + 1) * J, C = (size_t)mres * J;
+        // the column blocks and reflectors are written before they are read, so
+        // they are not cleared; a block's storage is sized when it is added
+        if ((int)Wb.size() < mres) Wb.resize(mres);
+        rhs.assign(R * J, 0.0);
+        for (int a = 0; a < J; ++a)
+            for (int c = 0; c < J; ++c) rhs[(size_t)a * J + c] = C0[(size_t)a * J + c];
+        vref.resize(C * 2 * J);
+        vnorm.assign(C, 0.0);
+        dead.assign(C, 0);
+    }
+    double& w(int r, int c) {
+        const int k = c / J;
+        return Wb[k][(size_t)(c - k * J) * (k + 2) * J + r];
+    }
+    // applies reflector q to columns [c0, c1) of W, or to the right-hand side if rhs_too
+    void reflect(int q, int c0, int c1, bool to_rhs) {
+        if (dead[q] || !(vnorm[q] > 0.0)) return;
+        const int rows = (mres + 1) * J, last = std::min(rows, (q / J + 2) * J);
+        const double* v = &vref[(size_t)q * 2 * J];
+        const int len = last - q;
+        for (int c = c0; c < c1; ++c) {
+            double* x = &w(q, c);   // a column's rows are contiguous
+            double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
+            int r = 0;
+            for (; r + 4 <= len; r += 4) {
+                d0 += v[r] * x[r];
+                d1 += v[r + 1] * x[r + 1];
+                d2 += v[r + 2] * x[r + 2];
+                d3 += v[r + 3] * x[r + 3];
+            }
+            for (; r < len; ++r) d0 += v[r] * x[r];
+            const double d = 2.0 * ((d0 + d1) + (d2 + d3)) / vnorm[q];
+            for (r = 0; r < len; ++r) x[r] -= d * v[r];
         }
-        const double x0 = Hb[(size_t)c * cols + c];
-        const double alpha = x0 >= 0 ? -nrm : nrm;
-        for (int r = c; r < last; ++r) v[r] = Hb[(size_t)r * cols + c];
-        v[c] -= alpha;
-        double vv = 0.0;
-        for (int r = c; r < last; ++r) vv += v[r] * v[r];
-        if (!(vv > 0.0)) continue;
-        for (int k = c; k < cols; ++k) {
-            double d = 0.0;
-            for (int r = c; r < last; ++r) d += v[r] * Hb[(size_t)r * cols + k];
-            d = 2.0 * d / vv;
-            for (int r = c; r < last; ++r) Hb[(size_t)r * cols + k] -= d * v[r];
+        if (to_rhs)
+            for (int k = 0; k < J; ++k) {
+                double d = 0.0;
+                for (int r = q; r < last; ++r) d += v[r - q] * rhs[(size_t)r * J + k];
+                d = 2.0 * d / vnorm[q];
+                for (int r = q; r < last; ++r) rhs[(size_t)r * J + k] -= d * v[r - q];
+            }
+    }
+    // column block k: H[i * mres + k] for i <= k + 1 (J x J each, row-major)
+    void add_block(int k, const std::vector<std::vector<double>>& H) {
+        const int c0 = k * J, c1 = c0 + J;
+        Wb[k].resize((size_t)(k + 2) * J * J);
+        for (int i = 0; i <= k + 1; ++i) {
+            const std::vector<double>& hb = H[(size_t)i * mres + k];
+            for (int a = 0; a < J; ++a)
+                for (int c = 0; c < J; ++c) w(i * J + a, c0 + c) = hb[(size_t)a * J + c];
         }
-        for (int k = 0; k < nr; ++k) {
-            double d = 0.0;
-            for (int r = c; r < last; ++r) d += v[r] * rhs[(size_t)r * nr + k];
-            d = 2.0 * d / vv;
-            for (int r = c; r < last; ++r) rhs[(size_t)r * nr + k] -= d * v[r];
+        for (int q = 0; q < c0; ++q) reflect(q, c0, c1, false);
+        const int rows = (mres + 1) * J;
+        for (int c = c0; c < c1; ++c) {
+            const int last = std::min(rows, (c / J + 2) * J);
+            double nrm = 0.0;
+            for (int r = c; r < last; ++r) nrm += w(r, c) * w(r, c);
+            nrm = std::sqrt(nrm);
+            double* v = &vref[(size_t)c * 2 * J];
+            if (!(nrm > 1e-300)) {
+                dead[c] = 1;
+                continue;
+            }
+            const double x0 = w(c, c);
+            const double alpha = x0 >= 0 ? -nrm : nrm;
+            for (int r = c; r < last; ++r) v[r - c] = w(r, c);
+            v[0] -= alpha;
+            double vv = 0.0;
+            for (int r = c; r < last; ++r) vv += v[r - c] * v[r - c];
+            vnorm[c] = vv;
+            reflect(c, c, c1, true);
+        }
+        cols = c1;
+    }
+    // every member's least-squares residual after the blocks added so far
+    void residuals(std::vector<double>& res) const {
+        res.assign(J, 0.0);
+        for (int r = cols; r < cols + J; ++r)
+            for (int k = 0; k < J; ++k) res[k] += rhs[(size_t)r * J + k] * rhs[(size_t)r * J + k];
+        for (double& v : res) v = std::sqrt(v);
+    }
+    // back substitution for the cols x J coefficients, column by column of the
+    // triangle (the right-hand side rows above are updated as each row is solved)
+    void solve(std::vector<double>& Y) {
+        double dmax = 0.0;
+        for (int c = 0; c < cols; ++c) dmax = std::max(dmax, std::fabs(w(c, c)));
+        Y.assign((size_t)cols * J, 0.0);
+        std::vector<double> t(rhs.begin(), rhs.begin() + (size_t)cols * J);
+        for (int c = cols - 1; c >= 0; --c) {
+            const double d = w(c, c);
+            if (dead[c] || !(std::fabs(d) > 1e-13 * dmax)) continue;
+            double* y = &Y[(size_t)c * J];
+            for (int k = 0; k < J; ++k) y[k] = t[(size_t)c * J + k] / d;
+            for (int r = 0; r < c; ++r) {
+                const double a = w(r, c);
+                if (a == 0.0) continue;
+                double* tr = &t[(size_t)r * J];
+                for (int k = 0; k < J; ++k) tr[k] -= a * y[k];
+            }
         }
     }
-    if (resid) {   // least-squares residual of each column: the transformed rows below the triangle
-        resid->assign(nr, 0.0);
-        for (int r = cols; r < rows; ++r)
-            for (int k = 0; k < nr; ++k) (*resid)[k] += rhs[(size_t)r * nr + k] * rhs[(size_t)r * nr + k];
-        for (double& v : *resid) v = std::sqrt(v);
-    }
-    double dmax = 0.0;
-    for (int c = 0; c < cols; ++c) dmax = std::max(dmax, std::fabs(Hb[(size_t)c * cols + c]));
-    Y.assign((size_t)cols * nr, 0.0);
-    for (int c = cols - 1; c >= 0; --c) {
-        const double d = Hb[(size_t)c * cols + c];
-        if (dead[c] || !(std::fabs(d) > 1e-13 * dmax)) continue;
-        for (int k = 0; k < nr; ++k) {
-            double v2 = rhs[(size_t)c * nr + k];
-            for (int q = c + 1; q < cols; ++q) v2 -= Hb[(size_t)c * cols + q] * Y[(size_t)q * nr + k];
-            Y[(size_t)c * nr + k] = v2 / d;
-        }
-    }
-}
+};
 
 template <typename T>
 mhd_status block_gram(DevShared& S, const T* A, const T* B, int J, hipStream_t st, std::vector<double>& G) {
@@ -4749,7 +4815,8 @@ mhd_status block_gmres_solve(DevShared& S, const double* b, double* x, int J, co
     double maxrel = 0.0;
     bool conv = false;
     std::vector<int> first_met(J, -1);
-    std::vector<double> Gm, Minv, Cm, C0, Hb, Y;
+    std::vector<double> Gm, Minv, Cm, C0, Y;
+    BlockLSQ lsq;   // host least squares, storage reused across the cycles
     while (true) {
         if ((rc = saddle_residual64(S, b, x, G.r64, J, st))) return rc;
         if ((rc = ops.colnorm(G.r64, G.beta))) return rc;
@@ -4798,23 +4865,8 @@ mhd_status block_gmres_solve(DevShared& S, const double* b, double* x, int J, co
         std::vector<std::vector<double>> H;   // H[i * mres + k]: block (i, k), J x J
         H.assign((size_t)(mres + 1) * mres, std::vector<double>((size_t)J * J, 0.0));
         int kd = 0;
-        bool have_y = false;
+        lsq.reset(J, mres, C0);
         std::vector<double> lsres;
-        auto solve_ls = [&](int kk, std::vector<double>* res) {
-            const int rows = (kk + 1) * J, cols = kk * J;
-            Hb.assign((size_t)rows * cols, 0.0);
-            for (int i = 0; i <= kk; ++i)
-                for (int k = 0; k < kk; ++k) {
-                    if (i > k + 1) continue;
-                    const std::vector<double>& hb = H[(size_t)i * mres + k];
-                    for (int a = 0; a < J; ++a)
-                        for (int c = 0; c < J; ++c) Hb[(size_t)(i * J + a) * cols + k * J + c] = hb[(size_t)a * J + c];
-                }
-            std::vector<double> rhs((size_t)rows * J, 0.0);
-            for (int a = 0; a < J; ++a)
-                for (int c = 0; c < J; ++c) rhs[(size_t)a * J + c] = C0[(size_t)a * J + c];
-            block_lsq(Hb, rhs, rows, cols, J, Y, res);
-        };
         for (int k = 0; k < mres && iters < o.maxit; ++k) {
             T* vk = basis_ptr<T>(S, k);
             T* z = keepz ? zslot(k) : (T*)G.zbuf;
@@ -4848,20 +4900,18 @@ mhd_status block_gmres_solve(DevShared& S, const double* b, double* x, int J, co
             rank_min = std::min(rank_min, pk);
             ++iters;
             kd = k + 1;
+            lsq.add_block(k, H);
             if (pk == 0) break;   // the block Krylov space is exhausted
             if (kd % check == 0 && kd < mres) {   // the members' least-squares residuals so far
-                solve_ls(kd, &lsres);
+                lsq.residuals(lsres);
                 bool done = true;
                 for (int j = 0; j < J; ++j)
                     if (!(lsres[j] <= std::max(o.inner_rtol * hbeta[j], 0.5 * o.rtol * hbn[j]))) done = false;
-                if (done) {
-                    have_y = true;
-                    break;
-                }
+                if (done) break;
             }
         }
         // block least squares and the correction d = P^-1 (V Y) (or Z Y with Z kept)
-        if (!have_y) solve_ls(kd, nullptr);
+        lsq.solve(Y);
         T* u = (T*)G.wbuf;
         for (int k = 0; k < kd; ++k) {
             std::vector<double> Yk(Y.begin() + (size_t)k * J * J, Y.begin() + (size_t)(k + 1) * J * J);
