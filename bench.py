@@ -334,7 +334,7 @@ def trajectory_workload(args, L, wl, torch):
     from paper_2108_05110_amd.ensemble import Mesh
     prec = L.MHD_FP32_IR if args.precision == "fp32ir" else L.MHD_FP64
     opts = L.solver_opts(prec, restart=args.restart, fixed_cycles=args.cycles, jacobi_sweeps=args.sweeps,
-                         jacobi_omega=args.omega, mg_cycles=args.mg_cycles)
+                         jacobi_omega=args.omega, mg_cycles=args.mg_cycles, cgs_passes=args.cgs)
     pb = wl.cavity(J=args.J, s=0.1, dt=0.01)
     mesh = Mesh(L.MHD_MESH_UNIT_SQUARE, args.N)
     tuned_plans(L, wl, mesh, args.J, prec)
@@ -548,7 +548,7 @@ def headline(args, L, wl, torch):
     prec = L.MHD_FP32_IR if args.precision == "fp32ir" else L.MHD_FP64
     if args.schedule == "fixed":
         opts = L.solver_opts(prec, restart=args.restart, fixed_cycles=args.cycles, jacobi_sweeps=args.sweeps,
-                             jacobi_omega=args.omega, mg_cycles=args.mg_cycles)
+                             jacobi_omega=args.omega, mg_cycles=args.mg_cycles, cgs_passes=args.cgs)
     else:
         opts = L.solver_opts(prec, rtol=args.rtol, jacobi_sweeps=args.sweeps, jacobi_omega=args.omega,
                              mg_cycles=args.mg_cycles)
@@ -672,6 +672,7 @@ def headline(args, L, wl, torch):
                      "avg_launch_us": avg_s * 1e6, "launches": launches},
         "rhs": rhs_us,
         "spmm_512_J128": None if args.no_large_spmm else spmm_large(L, wl, torch, plan=args.large_plan),
+        "multi_ensemble": None if (args.no_multi or not graph) else multi_summary(args, L, wl, torch),
         "separate": separate,
         "cpu_baseline": None,
     }
@@ -689,7 +690,7 @@ def step_workload(args, L, wl, torch):
     from paper_2108_05110_amd.ensemble import Mesh, Stepper
     prec = L.MHD_FP32_IR if args.precision == "fp32ir" else L.MHD_FP64
     opts = L.solver_opts(prec, restart=args.restart, fixed_cycles=args.cycles, jacobi_sweeps=args.sweeps,
-                         jacobi_omega=args.omega, mg_cycles=args.mg_cycles)
+                         jacobi_omega=args.omega, mg_cycles=args.mg_cycles, cgs_passes=args.cgs)
     pb = wl.cavity(J=args.J, s=0.1, dt=0.01)
     mesh = Mesh(L.MHD_MESH_UNIT_SQUARE, args.N)
     plans = tuned_plans(L, wl, mesh, args.J, prec)
@@ -853,12 +854,25 @@ def adjoint_workload(args, L, wl, torch):
             "forward_s": t1 - t0, "backward_s": t2 - t1, "phi": float(phi), "fd_checks": checks}
 
 
-def large_workload(args, L, wl, torch):
+def multi_summary(args, L, wl, torch):
+    """The multi-ensemble workload (512 x 512, J = 128 plus four 128 x 128, J = 16,
+    one graph launch per step) as a sub-result of the headline run."""
+    log("multi-ensemble group step")
+    r = large_workload(args, L, wl, torch, steps=3)
+    return {"value": r["value"], "unit": r["unit"], "ms_per_step": r["ms_per_step"], "steps": r["steps"],
+            "workload": r["config"]["workload"], "spmm_512_frac": r["roofline"]["frac"]}
+
+
+def large_workload(args, L, wl, torch, steps=None):
     """512x512 cavity with J = 128 plus four 128x128 cavities with J = 16 (distinct
-    seeds, s in {0.01, 0.1, 1, 1}), all advanced by one graph launch per step."""
-    from paper_2108_05110_amd.ensemble import Mesh, Stepper
+    seeds, s in {0.01, 0.1, 1, 1}), all advanced by one graph launch per step.
+    The ensembles with s = 1 take the strong-field schedule (three refinement
+    cycles, damping 0.5), the others the bench schedule."""
+    nsteps = args.steps if steps is None else steps
+    from paper_2108_05110_amd.ensemble import Mesh, Stepper, STRONG_FIELD_SCHEDULE
     opts = L.solver_opts(L.MHD_FP32_IR, restart=args.restart, fixed_cycles=args.cycles, jacobi_sweeps=args.sweeps,
-                         jacobi_omega=args.omega, mg_cycles=args.mg_cycles)
+                         jacobi_omega=args.omega, mg_cycles=args.mg_cycles, cgs_passes=args.cgs)
+    strong = L.solver_opts(L.MHD_FP32_IR, **STRONG_FIELD_SCHEDULE)
     specs = [(512, wl.cavity(J=128, s=0.1, dt=0.01, cfg=4))]
     for i, sc in enumerate((0.01, 0.1, 1.0, 1.0)):
         specs.append((128, wl.cavity(J=16, s=sc, dt=0.01, cfg=10 + i)))
@@ -866,7 +880,7 @@ def large_workload(args, L, wl, torch):
     for N, pb in specs:
         m = Mesh(L.MHD_MESH_UNIT_SQUARE, N)
         meshes.append(m)
-        s = Stepper(m, pb, opts=opts, time_dependent_data=False)
+        s = Stepper(m, pb, opts=strong if pb.s >= 1.0 else opts, time_dependent_data=False)
         s.set_data(pb.dt)
         steppers.append(s)
     grp = L.mhd_ens_group_create([s.ctx for s in steppers])
@@ -879,7 +893,7 @@ def large_workload(args, L, wl, torch):
     go()
     stream.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(nsteps):
         go()
     stream.synchronize()
     el = time.perf_counter() - t0
@@ -901,10 +915,10 @@ def large_workload(args, L, wl, torch):
         m.close()
     ach = bpl / avg_s / 1e9
     return {"metric": "member-steps/s, one graph launch per step over 5 ensembles", "value": total_members *
-            args.steps / el, "unit": "member-steps/s", "higher_is_better": True, "n_gpus": 1, "dtype": "f32",
-            "data": "synthetic", "steps": args.steps, "ms_per_step": 1e3 * el / args.steps,
+            nsteps / el, "unit": "member-steps/s", "higher_is_better": True, "n_gpus": 1, "dtype": "f32",
+            "data": "synthetic", "steps": nsteps, "ms_per_step": 1e3 * el / nsteps,
             "config": {"workload": "cavity 512x512 J=128 + 4 x cavity 128x128 J=16, FP32 inner + FP64 refinement, "
-                                   f"fixed {args.cycles}x{args.restart} schedule"},
+                                   f"fixed {args.cycles}x{args.restart} schedule (3x6, damping 0.5 for s = 1)"},
             "roofline": {"bound": "hbm", "kernel": "saddle-point SpMM at 512^2, J=128", "achieved": ach,
                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
                          "bytes_per_launch": bpl, "avg_launch_us": avg_s * 1e6, "launches": launches}}
@@ -924,6 +938,8 @@ def main():
     ap.add_argument("--sweeps", type=int, default=7)
     ap.add_argument("--omega", type=float, default=0.6, help="Jacobi damping (0: the library default 0.6)")
     ap.add_argument("--mg-cycles", type=int, default=2, help="V-cycles per Schur-part application")
+    ap.add_argument("--cgs", type=int, default=3,
+                    help="Gram-Schmidt: 1 or 2 passes with the direct norm, 3 the fused single pass")
     ap.add_argument("--rtol", type=float, default=1e-10)
     ap.add_argument("--workload", choices=["cavity", "adjoint", "large", "spmm", "step", "block", "trajectory"],
                     default="cavity")
@@ -933,6 +949,7 @@ def main():
     ap.add_argument("--no-large-spmm", action="store_true")
     ap.add_argument("--large-plan", default="4,0,6,1608,0", help="SpMM plan at 512^2 (or 'tune')")
     ap.add_argument("--no-separate", action="store_true")
+    ap.add_argument("--no-multi", action="store_true", help="skip the multi-ensemble sub-result")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plan", default="", help="pinned SpMM plan vec,group,deep,tile,waves (spmm workload; study "
                     "option for the step)")

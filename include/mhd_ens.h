@@ -208,12 +208,14 @@ typedef struct {
     int restart;
     int jacobi_sweeps;        /* velocity-block smoothing sweeps in the preconditioner */
     int check_every;          /* inner iterations between convergence checks (>= 1)    */
-    int cgs_passes;           /* classical Gram-Schmidt passes: 1, 2, or 0 = 1 for FP32,
-                                 2 for FP64.  One pass takes the new vector's norm
-                                 from the dot products (|w|^2 - |h|^2) and stores it
-                                 normalised in the same update; two passes
-                                 re-orthogonalise and norm the vector directly
-                                 (more accurate, about 2x the Gram-Schmidt traffic) */
+    int cgs_passes;           /* classical Gram-Schmidt: 1 or 2 passes with the new
+                                 vector's norm taken directly; 3 = one pass with the
+                                 norm from the dot products (|w|^2 - |h|^2) and the
+                                 vector stored normalised in the same update (fewer
+                                 launches; in FP32 the difference cancels once the
+                                 vector nearly lies in the basis's span, which is
+                                 counted in mhd_solve_stats.norm_clamps); 0 = 1 for
+                                 FP32 inner solves, 2 for FP64                        */
     int fixed_cycles;         /* > 0: fixed schedule of fixed_cycles refinement cycles of
                                  `restart` inner iterations each, with no host
                                  synchronisation (graph-capturable); rtol, inner_rtol,
@@ -260,6 +262,10 @@ typedef struct {
                                  if never, and the total for a fixed schedule)         */
     int min_block_rank;       /* block GMRES: the smallest rank of a basis block after
                                  deflation; J for the per-member solver                */
+    int norm_clamps;          /* cgs_passes = 3: new basis vectors of nonzero w whose
+                                 |w|^2 - |h|^2 was not positive, so that their norm was
+                                 taken as 0 (the member's cycle ends there), summed over
+                                 members and iterations of the call (-1: not read back) */
 } mhd_solve_stats;
 
 /* (Section 1: A [x_1|...|x_J] = [b_1|...|b_J]) Solves S X = B for the J

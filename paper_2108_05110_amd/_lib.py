@@ -78,7 +78,7 @@ class SolverOpts(C.Structure):
 class SolveStats(C.Structure):
     _fields_ = [("iters", C.c_int), ("cycles", C.c_int), ("max_relres", C.c_double), ("converged", C.c_int),
                 ("nonfinite", C.c_int), ("relres", C.POINTER(C.c_double)), ("member_iters", C.POINTER(C.c_int32)),
-                ("min_block_rank", C.c_int)]
+                ("min_block_rank", C.c_int), ("norm_clamps", C.c_int)]
 
 
 class CtxDesc(C.Structure):

@@ -442,7 +442,7 @@ mhd_status check_solver_opts(const mhd_solver_opts* o) {
     CHECK_ARG(o->maxit >= 1, "maxit must be >= 1");
     CHECK_ARG(o->restart >= 1 && o->restart <= kMaxRestart, "restart must be in [1, 40]");
     CHECK_ARG(o->jacobi_sweeps >= 1 && o->jacobi_sweeps <= 16, "jacobi_sweeps must be in [1, 16]");
-    CHECK_ARG(o->cgs_passes >= 0 && o->cgs_passes <= 2, "cgs_passes must be 0, 1 or 2");
+    CHECK_ARG(o->cgs_passes >= 0 && o->cgs_passes <= 3, "cgs_passes must be 0, 1, 2 or 3");
     CHECK_ARG(o->fixed_cycles >= 0 && o->fixed_cycles <= 64, "fixed_cycles must be in [0, 64]");
     CHECK_ARG(o->jacobi_omega == 0 || (std::isfinite(o->jacobi_omega) && o->jacobi_omega > 0 && o->jacobi_omega <= 1.5),
               "jacobi_omega must be 0 (default) or in (0, 1.5]");
@@ -1156,6 +1156,7 @@ mhd_status mhd_ens_step(mhd_ctx ctx, double* V, double* W, double* Q, double* R,
             d.max_relres = r.max_relres;
             d.converged = r.converged;
             d.nonfinite = r.nonfinite;
+            d.norm_clamps = r.norm_clamps;
         };
         counts(st->v, sv);
         counts(st->w, sw);

@@ -2871,7 +2871,8 @@ __global__ void __launch_bounds__(kBlock) k_reduce_pyth_givens(const double* __r
                                                                double* __restrict__ hcol, double* __restrict__ hn,
                                                                double* __restrict__ H, double* __restrict__ cs,
                                                                double* __restrict__ sn, double* __restrict__ g,
-                                                               double* __restrict__ res, int k, int m, int J) {
+                                                               double* __restrict__ res, double* __restrict__ clamps,
+                                                               int k, int m, int J) {
     __shared__ double hs[kMaxRestart + 2];
     const int j = blockIdx.x;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -2888,8 +2889,16 @@ __global__ void __launch_bounds__(kBlock) k_reduce_pyth_givens(const double* __r
     if (threadIdx.x != 0) return;
     double s2 = 0.0;
     for (int i = 0; i <= k; ++i) s2 += hs[i] * hs[i];
-    const double d = hs[k + 1] - s2;
-    const double hnj = d > 0.0 ? sqrt(d) : 0.0;
+    const double ww = hs[k + 1];   // |w|^2
+    const double d = ww - s2;
+    // |w|^2 - |h|^2 cancels once w lies almost in the span of the basis; a
+    // difference that is not positive leaves the new vector zero (the member's
+    // Krylov space is exhausted for this cycle).  That is right when the member
+    // has converged and wrong when FP32 orthogonality noise caused it, so each
+    // such event with w nonzero is counted.
+    double hnj = 0.0;
+    if (d > 0.0) hnj = sqrt(d);
+    else if (ww > 0.0) clamps[j] += 1.0;
     hn[j] = hnj;
     givens_step(H, cs, sn, g, hs, 1, hnj, res, k, m, J, j);
 }
@@ -2923,6 +2932,10 @@ __global__ void __launch_bounds__(kBlock) k_sub_mean(double* __restrict__ p, con
                                                      double inv_area, int64_t n, int J) {
     int64_t idx = ((int64_t)blockIdx.x * kBlock + threadIdx.x);
     for (; idx < n * J; idx += (int64_t)gridDim.x * kBlock) p[idx] -= sums[idx % J] * inv_area;
+}
+
+__global__ void k_fill64(double* __restrict__ a, int64_t n, double v) {
+    for (int64_t i = threadIdx.x + (int64_t)blockIdx.x * blockDim.x; i < n; i += (int64_t)gridDim.x * blockDim.x) a[i] = v;
 }
 
 __global__ void k_add_vec(double* __restrict__ a, const double* __restrict__ b, int64_t n) {
@@ -4223,6 +4236,18 @@ mhd_status launch_scale_cols(const TI* a, const double* s, TO* out, int64_t n, i
     return MHD_OK;
 }
 
+// Gram-Schmidt norms taken as zero in the last solve on this handle (fused
+// single pass), summed over members (synchronises; never called under capture)
+int norm_clamp_count(GmresWork& G, int J, hipStream_t st) {
+    std::vector<double> f(J, 0.0);
+    if (hipMemcpyAsync(f.data(), G.res + 2 * J, sizeof(double) * J, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return -1;
+    double sum = 0.0;
+    for (double v : f) sum += v;
+    return (int)sum;
+}
+
 template <typename T>
 mhd_status gmres_solve(DevShared& S, const double* b, double* x, int J, const mhd_solver_opts& o,
                        mhd_solve_stats* stt, hipStream_t st) {
@@ -4237,7 +4262,11 @@ mhd_status gmres_solve(DevShared& S, const double* b, double* x, int J, const mh
     ops.fused_mg = o.mg_unfused == 0;
     ops.mg_cycles = o.mg_cycles == 2 ? 2 : 1;
     RedShape rs = cap_blocks(red_shape(n, J, 16 / (int)sizeof(T)), G.nblk_cap);
-    const int passes = o.cgs_passes > 0 ? o.cgs_passes : (sizeof(T) == 4 ? 1 : 2);
+    // cgs_passes: 1 or 2 classical passes with the norm taken directly, 3 one pass
+    // with the norm from the dot products (fused kernels), 0 the default (one pass
+    // for FP32 inner solves, two for FP64)
+    const bool pyth = o.cgs_passes == 3;
+    const int passes = pyth ? 1 : (o.cgs_passes > 0 ? o.cgs_passes : (sizeof(T) == 4 ? 1 : 2));
     const T* const* Vd = (const T* const*)G.dptrs;
     // FP32 solves keep z_k = P^-1 v_k (flexible form), saving one preconditioner
     // application per refinement cycle; FP64 solves recompute P^-1 (V y)
@@ -4254,6 +4283,8 @@ mhd_status gmres_solve(DevShared& S, const double* b, double* x, int J, const mh
     // fixed schedule: fixed_cycles refinement cycles of mres inner iterations,
     // no host synchronisation (graph-capturable)
     const bool fixed = o.fixed_cycles > 0;
+    hipLaunchKernelGGL(k_fill64, dim3(1), dim3(kBlock), 0, st, G.res + 2 * J, (int64_t)J, 0.0);
+    LAUNCH_CHECK();
     if (!fixed) {
         if ((rc = ops.colnorm(b, G.bnorm))) return rc;
         if ((rc = sync_copy(hbn, G.bnorm, J, st))) return rc;
@@ -4265,6 +4296,7 @@ mhd_status gmres_solve(DevShared& S, const double* b, double* x, int J, const mh
     std::vector<int> first_met(fixed ? 0 : J, -1);
     auto fill_stats = [&](bool ok, bool nonfinite) {
         if (!stt) return;
+        stt->norm_clamps = fixed ? -1 : norm_clamp_count(G, J, st);
         stt->iters = iters;
         stt->cycles = cycles;
         stt->max_relres = fixed ? -1.0 : maxrel;
@@ -4319,7 +4351,7 @@ mhd_status gmres_solve(DevShared& S, const double* b, double* x, int J, const mh
             T* w = basis_ptr<T>(S, k + 1);
             if ((rc = ops.precond(vk, z, sweeps, omega))) return rc;
             if ((rc = ops.saddle(z, w))) return rc;
-            if (passes == 1) {
+            if (pyth) {
                 // one classical Gram-Schmidt pass: |w|^2 comes with the dot products,
                 // h_{k+1,k} = sqrt(|w|^2 - |h|^2) (V orthonormal), and the update
                 // stores v_{k+1} = (w - V h) / h_{k+1,k} directly; the last vector of
@@ -4343,7 +4375,7 @@ mhd_status gmres_solve(DevShared& S, const double* b, double* x, int J, const mh
                     if (rc) return rc;
                 }
                 hipLaunchKernelGGL(k_reduce_pyth_givens, dim3(J), dim3(kBlock), 0, st, (const double*)G.partial,
-                                   rs.nblk, G.hcol, hn, G.H, G.cs, G.sn, G.g, G.res, k, mres, J);
+                                   rs.nblk, G.hcol, hn, G.H, G.cs, G.sn, G.g, G.res, G.res + 2 * J, k, mres, J);
                 LAUNCH_CHECK();
                 for (int c0 = 0; c0 <= k && k + 1 < mres; c0 += 8) {
                     const int nb = std::min(8, k + 1 - c0);
@@ -4402,9 +4434,11 @@ mhd_status gmres_solve(DevShared& S, const double* b, double* x, int J, const mh
             hipLaunchKernelGGL(k_reduce, dim3(reduce_grid(J)), dim3(kBlock), 0, st, G.partial, rs.nblk, (int64_t)J, hn,
                                1);
             LAUNCH_CHECK();
-            hipLaunchKernelGGL(k_add_vec, dim3(((k + 1) * J + 255) / 256), dim3(256), 0, st, G.hcol,
-                               (const double*)hcol2, (int64_t)(k + 1) * J);
-            LAUNCH_CHECK();
+            if (passes == 2) {   // h = h1 + h2 over the two passes
+                hipLaunchKernelGGL(k_add_vec, dim3(((k + 1) * J + 255) / 256), dim3(256), 0, st, G.hcol,
+                                   (const double*)hcol2, (int64_t)(k + 1) * J);
+                LAUNCH_CHECK();
+            }
             hipLaunchKernelGGL(k_givens, dim3((J + 63) / 64), dim3(64), 0, st, G.H, G.cs, G.sn, G.g, G.hcol, hn,
                                G.res, k, mres, J);
             LAUNCH_CHECK();
@@ -4941,6 +4975,7 @@ mhd_status block_gmres_solve(DevShared& S, const double* b, double* x, int J, co
         stt->converged = conv ? 1 : 0;
         stt->nonfinite = 0;
         stt->min_block_rank = rank_min;
+        stt->norm_clamps = 0;
         for (int j = 0; j < J; ++j) {
             if (stt->relres) stt->relres[j] = hbn[j] > 0 ? hbeta[j] / hbn[j] : hbeta[j];
             if (stt->member_iters) stt->member_iters[j] = first_met[j] < 0 ? iters : first_met[j];
@@ -4988,7 +5023,7 @@ mhd_status alloc_gmres(DevShared& S, int restart) {
     if ((rc = A((void**)&G.beta, J8))) return rc;
     if ((rc = A((void**)&G.bnorm, J8))) return rc;
     if ((rc = A((void**)&G.hcol, J8 * 2 * (kMaxRestart + 1)))) return rc;
-    if ((rc = A((void**)&G.res, J8 * 2))) return rc;
+    if ((rc = A((void**)&G.res, J8 * 3))) return rc;   // estimates, new-vector norms, norm-clamp counts
     if (S.Jmax <= kBlockMaxJ && (rc = A((void**)&G.bmat, sizeof(double) * 2 * (size_t)S.Jmax * S.Jmax))) return rc;
     G.nblk_cap = std::min(kRedBlocks, std::max(64, 524288 / S.Jmax));
     G.partial_len = (int64_t)G.nblk_cap * (restart + 2) * S.Jmax + 1024;
@@ -5063,6 +5098,7 @@ mhd_status residual_report(DevShared& S, const double* b, const double* x, int J
     }
     out->max_relres = bad ? NAN : mx;
     out->nonfinite = bad;
+    out->norm_clamps = norm_clamp_count(G, J, st);
     return MHD_OK;
 }
 

@@ -111,12 +111,19 @@ class Stepper:
 
 # Fixed solver schedule of the graph-captured step at the 128x128, J = 64
 # cavity: 2 FP64 refinement cycles of 6 FP32 GMRES iterations, 7 velocity
-# Jacobi sweeps damped by 0.6 and two V-cycles for the Schur part.  Damping
-# 0.85 is faster while the flow is weak but diverges once the cavity flow
-# develops (about step 60 at dt = 0.01); this schedule keeps the one-step
-# error against FP64 solves below 3e-7 and the final relative residual below
-# 1e-8 over 200 steps.
-FIXED_SCHEDULE = dict(restart=6, fixed_cycles=2, jacobi_sweeps=7, jacobi_omega=0.6, mg_cycles=2)
+# Jacobi sweeps damped by 0.6, two V-cycles for the Schur part, and the fused
+# single-pass Gram-Schmidt (norm from the dot products; validated for cycles of
+# up to 8 iterations).  Damping 0.85 is faster while the flow is weak but
+# diverges once the cavity flow develops (about step 60 at dt = 0.01); this
+# schedule keeps the one-step error against FP64 solves below 3e-7 and the
+# final relative residual below 1e-8 over 200 steps.
+FIXED_SCHEDULE = dict(restart=6, fixed_cycles=2, jacobi_sweeps=7, jacobi_omega=0.6, mg_cycles=2, cgs_passes=3)
+
+# The same for a strong magnetic field (coupling number s = 1, where the
+# Elsaesser fields carry the wall field and the subproblems are convection
+# dominated): three refinement cycles and damping 0.5 keep the one-step error
+# near 1e-7, where the 2 x 6 schedule leaves 1e-5.
+STRONG_FIELD_SCHEDULE = dict(FIXED_SCHEDULE, fixed_cycles=3, jacobi_omega=0.5)
 
 
 def fixed_schedule_opts(precision=L.MHD_FP32_IR, **over):

@@ -177,3 +177,41 @@ def test_later_handles_on_a_mesh_match_the_first(L):
         s.close()
     assert torch.equal(states[0][0], states[1][0]) and torch.equal(states[0][1], states[1][1])
     gm.close()
+
+
+def test_gram_schmidt_variants(L):
+    """The three Gram-Schmidt variants of the FP32 inner solve (one pass with
+    the norm taken directly, two passes, one fused pass with the norm from the
+    dot products) reach the FP64 solution on one handle, in the order 2, 1, 3,
+    so that a single direct pass runs after two-pass solves have filled the
+    second pass's coefficients (which it must not read).  Only the fused pass
+    may report norm clamps; restart 12 is past the cycle length the fused pass
+    is validated for, so only its count is checked there."""
+    from paper_2108_05110_amd.ensemble import Mesh, to_dev
+    N, J = 32, 16
+    say("Gram-Schmidt variants: 32^2, J=16, FP32 inner solves")
+    pb = wl.cavity(J=J, s=0.1, dt=0.01, ic_amp=0.05)
+    gm = Mesh(L.MHD_MESH_UNIT_SQUARE, N)
+    V, W = pb.ic(gm.xy)
+    c = L.Coeffs(pb.dt, pb.mu, float(pb.nu.mean()), float(pb.nu_m.mean()), 0)
+    g = torch.Generator("cuda").manual_seed(11)
+    b = torch.randn((gm.n, J), dtype=torch.float64, device="cuda", generator=g)
+    A = L.mhd_ens_shared_create(gm.handle, J, 12)
+    L.mhd_ens_assemble_shared(gm.handle, c, to_dev(W), J, A)
+    ref = torch.zeros_like(b)
+    L.mhd_ens_solve(A, b, ref, J, L.solver_opts(L.MHD_FP64, rtol=1e-12, restart=12))
+    rel = lambda x: float(torch.linalg.norm(x - ref) / torch.linalg.norm(ref))
+    for cgs in (2, 1, 3):
+        for restart, cycles in ((6, 0), (6, 3), (12, 3)):
+            x = torch.zeros_like(b)
+            opts = L.solver_opts(L.MHD_FP32_IR, restart=restart, fixed_cycles=cycles, cgs_passes=cgs, rtol=1e-10)
+            st, _ = L.mhd_ens_solve(A, b, x, J, opts, allow_noconv=True)
+            e = rel(x)
+            say(f"  cgs {cgs} restart {restart} cycles {cycles}: error {e:.2e}, iterations {st.iters}, "
+                f"norm clamps {st.norm_clamps}")
+            if cgs != 3:
+                assert st.norm_clamps == 0 or (cycles > 0 and st.norm_clamps == -1)
+            if cgs != 3 or restart <= 8:
+                assert e <= (1e-8 if cycles == 0 else 1e-5), (cgs, restart, cycles, e)
+    L.mhd_ens_shared_free(A)
+    gm.close()
