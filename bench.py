@@ -673,6 +673,7 @@ def headline(args, L, wl, torch):
         "rhs": rhs_us,
         "spmm_512_J128": None if args.no_large_spmm else spmm_large(L, wl, torch, plan=args.large_plan),
         "multi_ensemble": None if (args.no_multi or not graph) else multi_summary(args, L, wl, torch),
+        "adjoint": None if args.no_adjoint else adjoint_summary(args, L, wl, torch),
         "separate": separate,
         "cpu_baseline": None,
     }
@@ -809,7 +810,7 @@ def spmm_workload(args, L, wl, torch):
     return out
 
 
-def adjoint_workload(args, L, wl, torch):
+def adjoint_workload(args, L, wl, torch, fd_checks=True):
     """128x128 cavity, J = 32, 50 FP64 steps, gradients of the final ensemble-mean
     energy w.r.t. (nu, nu_m, forcing amplitude, 8 IC coefficients) of every
     member, checkpoints every 10 steps; two entries checked by central
@@ -838,7 +839,7 @@ def adjoint_workload(args, L, wl, torch):
     g = p.grad.cpu().numpy()
     checks = []
     h = 1e-6
-    for (j, k) in ((0, 0), (5, 2), (9, 4)):
+    for (j, k) in (((0, 0), (5, 2), (9, 4)) if fd_checks else ()):
         pp, pm = params.clone(), params.clone()
         pp[j, k] += h
         pm[j, k] -= h
@@ -851,7 +852,18 @@ def adjoint_workload(args, L, wl, torch):
             "unit": "s", "higher_is_better": False, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
             "config": {"workload": f"cavity {N}x{N} P2-P1, J={J}, {nsteps} steps dt=0.01, checkpoint every 10, "
                                    f"objective E_h^M, 11 parameters per member"},
-            "forward_s": t1 - t0, "backward_s": t2 - t1, "phi": float(phi), "fd_checks": checks}
+            "forward_s": t1 - t0, "backward_s": t2 - t1, "phi": float(phi.detach()), "fd_checks": checks}
+
+
+def adjoint_summary(args, L, wl, torch):
+    """The adjoint workload (128 x 128, J = 32, 50 FP64 steps, checkpoints every
+    10) as a sub-result of the headline run: wall times of the forward pass and
+    the checkpointed reverse pass (its finite-difference checks are a GPU test
+    and the adjoint workload's own output)."""
+    log("adjoint: 50 steps forward and reverse")
+    r = adjoint_workload(args, L, wl, torch, fd_checks=False)
+    return {"value": r["value"], "unit": r["unit"], "forward_s": r["forward_s"], "backward_s": r["backward_s"],
+            "workload": r["config"]["workload"]}
 
 
 def multi_summary(args, L, wl, torch):
@@ -950,6 +962,7 @@ def main():
     ap.add_argument("--large-plan", default="4,0,6,1608,0", help="SpMM plan at 512^2 (or 'tune')")
     ap.add_argument("--no-separate", action="store_true")
     ap.add_argument("--no-multi", action="store_true", help="skip the multi-ensemble sub-result")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint sub-result")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plan", default="", help="pinned SpMM plan vec,group,deep,tile,waves (spmm workload; study "
                     "option for the step)")

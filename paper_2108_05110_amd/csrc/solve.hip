@@ -8,11 +8,13 @@
 // SpMM over all J columns per iteration.  Preconditioner (block upper
 // triangular): z_p = -S_hat^{-1} r_p with S_hat = B D^{-1} B^T, D the diagonal
 // of M/dt + nu_c K (the velocity block without convection), inverted
-// approximately by one V(2,2)-cycle with damped Jacobi smoothing on a Galerkin
-// hierarchy over the nested P1 vertex grids (dense inverse on the coarsest
-// level), then z_u = damped Jacobi sweeps on A for r_u - B^T z_p.  The outer
-// loop is FP64 iterative refinement: r = b - S x in FP64, a GMRES cycle in
-// the inner precision (FP32 or FP64) on r, x += d.
+// approximately by one or two V(2,2)-cycles with damped Jacobi smoothing on a
+// Galerkin hierarchy over the nested P1 vertex grids (dense inverse on the
+// coarsest level), then z_u = damped Jacobi sweeps on A for r_u - B^T z_p.
+// The outer loop is FP64 iterative refinement: r = b - S x in FP64, a GMRES
+// cycle in the inner precision (FP32 or FP64) on r, x += d.  A block GMRES
+// variant (one Krylov space for all members, with deflation) is an option of
+// the adaptive mode.
 //
 // Every kernel streams member blocks row-major (member index fastest); rows
 // are spread over the 8 XCDs in contiguous ranges.  Column reductions go

@@ -96,3 +96,38 @@ def test_checkpoint_interval_does_not_change_gradient(gpu):
         ro.close()
         gm.close()
     assert np.array_equal(grads[0], grads[1]) and np.array_equal(grads[0], grads[2])
+
+
+@pytest.mark.timeout(600)
+def test_adjoint_at_full_size_matches_gpu_central_differences(gpu):
+    """The adjoint workload at its full size: 128 x 128 cavity, J = 32, 50 FP64
+    steps, checkpoints every 10, gradient of the final ensemble-mean energy with
+    respect to all 11 parameters of every member; three entries (a viscosity,
+    a forcing amplitude, an initial-mode coefficient) against central
+    differences of the GPU forward map, bar 1e-5 relative."""
+    from paper_2108_05110_amd import _lib as L
+    from paper_2108_05110_amd.autograd import EnsembleEnergy, Rollout
+    from paper_2108_05110_amd.ensemble import Mesh
+    N, J, nsteps = 128, 32, 50
+    say("adjoint at full size: 128^2, J=32, 50 steps, checkpoints every 10")
+    pb = wl.cavity(J=J, s=0.1, dt=0.01, nsteps=nsteps, cfg=3)
+    a = wl.rng(3, 3).uniform(0.5, 1.5, J)
+    params = torch.tensor(np.column_stack([pb.nu, pb.nu_m, a, pb.ic_coef]), dtype=torch.float64, device="cuda")
+    gm = Mesh(L.MHD_MESH_UNIT_SQUARE, N)
+    modes, fhat = modes_and_forcing(gm.xy)
+    ro = Rollout(gm, pb, modes, fhat, opts=L.solver_opts(L.MHD_FP64), checkpoint_every=10)
+    p = params.clone().requires_grad_(True)
+    EnsembleEnergy.apply(p, ro).backward()
+    g = p.grad.cpu().numpy()
+    say("  gradient done")
+    h = 1e-6
+    for (j, k) in ((0, 0), (5, 2), (9, 4)):
+        pp, pm = params.clone(), params.clone()
+        pp[j, k] += h
+        pm[j, k] -= h
+        fd = (ro.forward(pp, keep_checkpoints=False)[0] - ro.forward(pm, keep_checkpoints=False)[0]) / (2 * h)
+        rel = abs(g[j, k] - fd) / abs(fd)
+        say(f"  member {j} parameter {k}: adjoint {g[j, k]:.10e}, central difference {fd:.10e}, rel {rel:.2e}")
+        assert rel <= 1e-5, (j, k, g[j, k], fd)
+    ro.close()
+    gm.close()

@@ -56,3 +56,41 @@ def test_identical_members_have_identical_gradients():
     _, g, gc = adj.gradient(nu, num, a, coef, 2)
     assert np.abs(g - g[0]).max() <= 1e-12 * np.abs(g).max()
     assert np.abs(gc - gc[0]).max() <= 1e-12 * np.abs(gc).max()
+
+
+def test_single_member_adjoint_matches_the_plain_scheme():
+    """J = 1: the ensemble adjoint's gradient equals central differences of the
+    plain decoupled scheme (``oracle.plain``, written without the ensemble
+    machinery), with the member's parameters entering through the problem's
+    own initial modes and forcing amplitude.  Pins the adjoint's reduction to
+    the single-realisation scheme (Section 1)."""
+    import dataclasses
+
+    from oracle.plain import run_plain
+    from oracle.fem import Element, vec2
+    adj, nu, num, a, coef = make(J=1, seed=5)
+    nsteps = 3
+    _, g, gc = adj.gradient(nu, num, a, coef, nsteps)
+    ms = adj.mesh
+    M2 = vec2(Element(ms).mass())
+
+    def energy(nu_, num_, a_, coef_):
+        pb = dataclasses.replace(adj.pb, nu=np.array([nu_]), nu_m=np.array([num_]), amp=np.array([a_]),
+                                 ic_coef=np.array(coef_)[None, :])
+        v, w = run_plain(ms, pb, 0, nsteps)[-1]
+        return 0.5 * (v.ravel() @ (M2 @ v.ravel()) + w.ravel() @ (M2 @ w.ravel()))
+
+    h = 1e-6
+    base = [nu[0], num[0], a[0], coef[0].copy()]
+    for col in range(3):
+        p, m = list(base), list(base)
+        p[col] += h
+        m[col] -= h
+        fd = (energy(*p) - energy(*m)) / (2 * h)
+        assert abs(g[0, col] - fd) <= 1e-6 * max(abs(fd), 1e-3 * np.abs(g).max()), (col, g[0, col], fd)
+    for k in (0, 5):
+        cp, cm = coef[0].copy(), coef[0].copy()
+        cp[k] += h
+        cm[k] -= h
+        fd = (energy(nu[0], num[0], a[0], cp) - energy(nu[0], num[0], a[0], cm)) / (2 * h)
+        assert abs(gc[0, k] - fd) <= 1e-6 * max(abs(fd), 1e-3 * np.abs(gc).max()), (k, gc[0, k], fd)
