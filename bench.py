@@ -70,6 +70,26 @@ def spmm_bytes_csr(info, J, word):
     return (word + 4) * info.nnz + 4 * (info.n + 1) + 2 * word * info.n * J
 
 
+def velo_sweep_bytes(info, J, word):
+    """Algorithmic bytes of one velocity Jacobi sweep z' = z + w D^-1 (t - A z)
+    on both components: the scalar P2 block A as CSR (value + int32 column per
+    nonzero, row pointers), D^-1, and t and z read once and z' written once."""
+    return (word + 4) * info.nnz_A + 4 * (info.nP2 + 1) + word * info.nP2 + 3 * 2 * word * info.nP2 * J
+
+
+def jacobi_roofline(info, J, word, ms, launches, plan):
+    """Roofline of the velocity Jacobi sweep (the largest share of the step's
+    kernel time) from the HIP events of its launches in an eager pass."""
+    if not launches:
+        return None
+    avg = ms / 1e3 / launches
+    b = velo_sweep_bytes(info, J, word)
+    return {"bound": "hbm", "kernel": f"velocity Jacobi sweep ({saddle_kernel_name(plan).replace('saddle', 'velo')})",
+            "achieved": b / avg / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": b / avg / 1e9 / HBM_PEAK_GBS, "bytes_per_launch": b, "avg_launch_us": avg * 1e6,
+            "launches": launches}
+
+
 def source_hash():
     """Hash of the code that decides the SpMM's memory traffic: the row-per-lane
     (sliced-ELL) kernels of solve.hip and the host code that lays out their
@@ -583,6 +603,13 @@ def headline(args, L, wl, torch):
     e_elapsed = timed_steps(eag, max(2, args.steps // 2))
     ms, launches, _, _ = L.mhd_ens_timer_read()
     L.mhd_ens_timer_enable(False)
+    # the same eager pass timing the velocity Jacobi sweeps, the step's largest kernel time
+    L.mhd_ens_timer_op(L.TUNE_JACOBI)
+    L.mhd_ens_timer_enable(True)
+    timed_steps(eag, max(2, args.steps // 2))
+    ms_j, launches_j, _, _ = L.mhd_ens_timer_read()
+    L.mhd_ens_timer_enable(False)
+    L.mhd_ens_timer_op(L.TUNE_SADDLE)
     st = eag.step(stats=True)
     iters = st.v.iters + st.w.iters
     eag.close()
@@ -671,6 +698,7 @@ def headline(args, L, wl, torch):
                      "compact_frac": (bpl_compact / avg_s / 1e9 / HBM_PEAK_GBS) if launches else None,
                      "avg_launch_us": avg_s * 1e6, "launches": launches},
         "rhs": rhs_us,
+        "roofline_jacobi": jacobi_roofline(mesh.info, args.J, word, ms_j, launches_j, plans.get("jacobi")),
         "spmm_512_J128": None if args.no_large_spmm else spmm_large(L, wl, torch, plan=args.large_plan),
         "multi_ensemble": None if (args.no_multi or not graph) else multi_summary(args, L, wl, torch),
         "adjoint": None if args.no_adjoint else adjoint_summary(args, L, wl, torch),
@@ -704,6 +732,12 @@ def step_workload(args, L, wl, torch):
     elapsed = timed_steps(stp, args.steps)
     stp.close()
     mesh.close()
+    # a plain device copy of known size after the replays: the reference for hardware byte counters
+    src = torch.ones((256 << 20) // 4, device="cuda", dtype=torch.float32)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
     return {"metric": "member-steps/s (graph replays only)", "value": args.J * args.steps / elapsed,
             "unit": "member-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
             "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True, "scaling": "weak",

@@ -450,6 +450,11 @@ mhd_status mhd_ens_alloc_stats(int64_t* count, int64_t* bytes);
  * launch sizes (units of n*J) per precision.  Enabling resets the counters. */
 mhd_status mhd_ens_timer_enable(int on);
 mhd_status mhd_ens_timer_read(double* ms, int64_t* launches, double* nJ_fp32, double* nJ_fp64);
+/* Diagnostics: which operator the timer times, MHD_TUNE_SADDLE (the SpMM, the
+ * default) or MHD_TUNE_JACOBI (the velocity Jacobi sweeps that update the
+ * previous iterate; the first one or two sweeps of each preconditioner
+ * application are other kernels); MHD_EINVAL otherwise. */
+mhd_status mhd_ens_timer_op(int op);
 
 /* ------------------------------------------------------------------------
  * Discrete adjoint of Algorithm 1 for an ensemble-mean objective.  The

@@ -24,7 +24,7 @@ EXPORTS = (
     "mhd_ens_mesh_counts", "mhd_ens_mesh", "mhd_ens_mesh_coords", "mhd_ens_mesh_free",
     "mhd_ens_shared_create", "mhd_ens_shared_free", "mhd_ens_assemble_shared", "mhd_ens_shared_csr",
     "mhd_ens_assemble_rhs", "mhd_ens_assemble_rhs_noalloc", "mhd_ens_solve", "mhd_ens_ctx_create", "mhd_ens_ctx_free", "mhd_ens_step",
-    "mhd_ens_spmm", "mhd_ens_timer_enable", "mhd_ens_timer_read", "mhd_ens_last_error", "mhd_ens_version",
+    "mhd_ens_spmm", "mhd_ens_timer_enable", "mhd_ens_timer_op", "mhd_ens_timer_read", "mhd_ens_last_error", "mhd_ens_version",
     "mhd_ens_adjoint_terminal", "mhd_ens_adjoint_step", "mhd_ens_adjoint_ic",
     "mhd_ens_group_create", "mhd_ens_group_step", "mhd_ens_group_free",
     "mhd_ens_autotune", "mhd_ens_set_plan", "mhd_ens_get_plan",
@@ -155,6 +155,7 @@ def lib():
             "mhd_ens_ctx_prepare": [P, I, P],
             "mhd_ens_alloc_stats": [C.POINTER(C.c_int64), C.POINTER(C.c_int64)],
             "mhd_ens_timer_enable": [I],
+            "mhd_ens_timer_op": [I],
             "mhd_ens_adjoint_terminal": [P, P, P, P, P, I, P],
             "mhd_ens_adjoint_step": [P, P, P, P, P, P, P, P, P, C.POINTER(AdjointInputs), P,
                                      C.POINTER(StepStats), P],
@@ -342,6 +343,10 @@ def mhd_ens_get_plan(A, J, precision, op):
 def mhd_ens_plan(A, J, precision):
     """The plans of all four node-row operators, keyed by operator name."""
     return {TUNE_OPS[op]: mhd_ens_get_plan(A, J, precision, op) for op in TUNE_OPS}
+
+
+def mhd_ens_timer_op(op):
+    check("mhd_ens_timer_op", lib().mhd_ens_timer_op(op))
 
 
 def mhd_ens_timer_enable(on=True):

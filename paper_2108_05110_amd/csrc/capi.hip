@@ -919,6 +919,7 @@ mhd_status mhd_ens_spmm(mhd_shared A, const void* x, void* y, int J, int precisi
 }
 
 mhd_status mhd_ens_timer_enable(int on) { return timer_enable(on); }
+mhd_status mhd_ens_timer_op(int op) { return timer_op(op); }
 
 mhd_status mhd_ens_timer_read(double* ms, int64_t* launches, double* nJ32, double* nJ64) try {
     return timer_read(ms, launches, nJ32, nJ64);

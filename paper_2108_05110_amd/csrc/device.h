@@ -218,6 +218,7 @@ mhd_status autotune(DevShared& S, int J, int precision, hipStream_t st, bool for
                     std::vector<mhd_tune_entry>* report);
 mhd_status set_plan(DevShared& S, int J, int precision, int op, int vec, int group, int deep, int tile, int waves);
 mhd_status query_plan(DevShared& S, int J, int precision, int op, mhd_tune_entry* out);
+mhd_status timer_op(int op);
 mhd_status timer_enable(int on);
 mhd_status timer_read(double* ms, int64_t* launches, double* nJ32, double* nJ64);
 mhd_status saddle_residual64(DevShared& S, const double* b, const double* x, double* r, int J, hipStream_t s);

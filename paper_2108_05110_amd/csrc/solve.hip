@@ -2993,6 +2993,7 @@ inline unsigned reduce_grid(int64_t width) { return (unsigned)((width + (kBlock 
 // ------------------------------------------------------------------ kernel timer
 struct KTimer {
     bool on = false;
+    int op = MHD_TUNE_SADDLE;   // the operator whose launches are timed
     std::vector<hipEvent_t> pool;
     size_t used = 0;
     double ms = 0.0;
@@ -3020,8 +3021,8 @@ thread_local hipEvent_t t_ev0 = nullptr, t_ev1 = nullptr;
 
 // arms (t_ev0, t_ev1) for the next launch on st when the timer is on and st is
 // not being captured; returns whether it did
-bool timer_begin(hipStream_t st) {
-    if (!g_timer.on) return false;
+bool timer_begin(hipStream_t st, int op) {
+    if (!g_timer.on || g_timer.op != op) return false;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return false;
     if (g_timer.used + 2 > g_timer.pool.size()) (void)timer_fold();
@@ -3667,8 +3668,8 @@ mhd_status launch_velo_plan(NodePlan p, DevShared& S, const T* in, const T* zp, 
             constexpr int GG = decltype(Gc)::value;
             const int w = (m.nP2 + GG - 1) / GG;
             const dim3 grid((unsigned)((w + 3) / 4), J / (256 / (int)sizeof(T)));
-            hipLaunchKernelGGL((k_velo_h<T, FIRST, GG>), grid, dim3(kBlock), 0, st, rp, col, val, Vals<T>::dA(S), in,
-                               zp, t, z, zo, m.nP2, J, omega);
+            launch_k(k_velo_h<T, FIRST, GG>, grid, dim3(kBlock), 0, st, rp, col, val, Vals<T>::dA(S), in, zp, t, z,
+                     zo, m.nP2, J, omega);
             LAUNCH_CHECK();
             return MHD_OK;
         });
@@ -3997,7 +3998,7 @@ struct Ops {
     }
 
     mhd_status saddle(const T* x, T* y) {
-        const bool timed = timer_begin(st);
+        const bool timed = timer_begin(st, MHD_TUNE_SADDLE);
         const bool aligned = (((uintptr_t)x | (uintptr_t)y) % 16) == 0;
         mhd_status rc = launch_saddle_plan<T, 0>(align_plan(p_saddle, aligned), S, x, nullptr, y, J, st);
         t_ev0 = t_ev1 = nullptr;
@@ -4157,8 +4158,14 @@ struct Ops {
             return rc;
         }
         for (; s < sweeps; ++s) {
-            if ((rc = launch_velo_plan<T, false>(ps, S, nullptr, nullptr, t, za, zb, J, st, omega)))
-                return rc;
+            const bool timed = timer_begin(st, MHD_TUNE_JACOBI);
+            rc = launch_velo_plan<T, false>(ps, S, nullptr, nullptr, t, za, zb, J, st, omega);
+            t_ev0 = t_ev1 = nullptr;
+            if (rc) return rc;
+            if (timed) {
+                g_timer.launches++;
+                (sizeof(T) == 4 ? g_timer.nJ32 : g_timer.nJ64) += (double)J;
+            }
             std::swap(za, zb);
         }
         if (za != z) {
@@ -5144,6 +5151,15 @@ mhd_status timer_enable(int on) {
         g_timer.nJ32 = g_timer.nJ64 = 0.0;
     }
     g_timer.on = on != 0;
+    return MHD_OK;
+}
+
+mhd_status timer_op(int op) {
+    if (op != MHD_TUNE_SADDLE && op != MHD_TUNE_JACOBI) {
+        set_error("mhd_ens_timer_op: op must be MHD_TUNE_SADDLE or MHD_TUNE_JACOBI");
+        return MHD_EINVAL;
+    }
+    g_timer.op = op;
     return MHD_OK;
 }
 
