@@ -241,6 +241,12 @@ typedef struct {
                                  block least squares on the host); adaptive schedule only,
                                  J in {16, 32, 64, 128}.  0 (default): one Arnoldi process
                                  per member over the shared SpMM                        */
+    int keep_converged;       /* adaptive schedule, per-member solver: 0 (default) = once
+                                 some members meet rtol at a refinement cycle, the
+                                 others continue as a compacted block of fewer columns
+                                 (every kernel then streams only those), the converged
+                                 iterates are left as they are; 1 = all J columns stay
+                                 in every cycle                                        */
 } mhd_solver_opts;
 
 typedef struct {
@@ -266,6 +272,9 @@ typedef struct {
                                  |w|^2 - |h|^2 was not positive, so that their norm was
                                  taken as 0 (the member's cycle ends there), summed over
                                  members and iterations of the call (-1: not read back) */
+    int compacted;            /* adaptive per-member solver: the number of members that
+                                 continued as a compacted block once the others had met
+                                 rtol (0: no compaction)                                */
 } mhd_solve_stats;
 
 /* (Section 1: A [x_1|...|x_J] = [b_1|...|b_J]) Solves S X = B for the J

@@ -291,7 +291,7 @@ mhd_status build_device_mesh(DevMesh& D) {
 
 mhd_status alloc_schur(DevShared& S);
 
-mhd_status make_shared(DevMesh* m, int J_max, int restart, DevShared& S) {
+mhd_status make_shared(DevMesh* m, int J_max, int restart, DevShared& S, bool compact) {
     S.mesh = m;
     S.Jmax = J_max;
     auto& L = S.allocs;
@@ -311,7 +311,7 @@ mhd_status make_shared(DevMesh* m, int J_max, int restart, DevShared& S) {
     MHD_HIP(hipMemset(S.valA32, 0, sizeof(float) * (size_t)m->nnzA));
     MHD_HIP(hipMemset(S.dinvA, 0, sizeof(double) * (size_t)m->nP2));
     MHD_HIP(hipMemset(S.dinvA32, 0, sizeof(float) * (size_t)m->nP2));
-    return alloc_gmres(S, restart);
+    return alloc_gmres(S, restart, compact);
 }
 
 void free_shared(DevShared& S) {
@@ -450,6 +450,7 @@ mhd_status check_solver_opts(const mhd_solver_opts* o) {
     CHECK_ARG(o->mg_cycles >= 0 && o->mg_cycles <= 2, "mg_cycles must be 0, 1 or 2");
     CHECK_ARG(o->block_krylov == 0 || (o->block_krylov == 1 && o->fixed_cycles == 0),
               "block_krylov must be 0, or 1 with the adaptive schedule (fixed_cycles 0)");
+    CHECK_ARG(o->keep_converged == 0 || o->keep_converged == 1, "keep_converged must be 0 or 1");
     return MHD_OK;
 }
 
@@ -766,7 +767,16 @@ mhd_status mhd_ens_mesh_free(mhd_mesh m) try {
     return exception_status();
 }
 
+// compact: with the buffers of the adaptive solver's member compaction
+mhd_status shared_create(mhd_mesh m, int J_max, int restart, bool compact, mhd_shared* out);
+
 mhd_status mhd_ens_shared_create(mhd_mesh m, int J_max, int restart, mhd_shared* out) try {
+    return shared_create(m, J_max, restart, true, out);
+} catch (...) {
+    return exception_status();
+}
+
+mhd_status shared_create(mhd_mesh m, int J_max, int restart, bool compact, mhd_shared* out) {
     CHECK_ARG(out, "mhd_ens_shared_create: null output handle");
     *out = nullptr;
     CHECK_ARG(m, "mhd_ens_shared_create: null mesh");
@@ -774,7 +784,7 @@ mhd_status mhd_ens_shared_create(mhd_mesh m, int J_max, int restart, mhd_shared*
     CHECK_ARG(restart >= 1 && restart <= kMaxRestart, "mhd_ens_shared_create: restart must be in [1, 40]");
     mhd_shared A = new (std::nothrow) mhd_shared_s;
     if (!A) return MHD_ENOMEM;
-    mhd_status rc = make_shared(&m->d, J_max, restart, A->d);
+    mhd_status rc = make_shared(&m->d, J_max, restart, A->d, compact);
     if (rc) {
         free_shared(A->d);
         delete A;
@@ -782,8 +792,6 @@ mhd_status mhd_ens_shared_create(mhd_mesh m, int J_max, int restart, mhd_shared*
     }
     *out = A;
     return MHD_OK;
-} catch (...) {
-    return exception_status();
 }
 
 mhd_status mhd_ens_shared_free(mhd_shared A) try {
@@ -952,8 +960,9 @@ mhd_status mhd_ens_ctx_create(mhd_mesh m, const mhd_ctx_desc* d, mhd_ctx* out) t
         delete c;
         return r;
     };
-    if ((rc = mhd_ens_shared_create(m, d->J_max, d->solver.restart, &c->Av))) return fail(rc);
-    if ((rc = mhd_ens_shared_create(m, d->J_max, d->solver.restart, &c->Aw))) return fail(rc);
+    const bool compact = d->solver.fixed_cycles == 0;   // fixed schedules never compact
+    if ((rc = shared_create(m, d->J_max, d->solver.restart, compact, &c->Av))) return fail(rc);
+    if ((rc = shared_create(m, d->J_max, d->solver.restart, compact, &c->Aw))) return fail(rc);
     size_t blk = (size_t)m->d.n * d->J_max;
     if ((rc = dev_alloc(c->allocs, &c->bv, blk))) return fail(rc);
     if ((rc = dev_alloc(c->allocs, &c->bw, blk))) return fail(rc);
@@ -1158,6 +1167,7 @@ mhd_status mhd_ens_step(mhd_ctx ctx, double* V, double* W, double* Q, double* R,
             d.converged = r.converged;
             d.nonfinite = r.nonfinite;
             d.norm_clamps = r.norm_clamps;
+            d.compacted = r.compacted;
         };
         counts(st->v, sv);
         counts(st->w, sw);

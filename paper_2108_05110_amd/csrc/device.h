@@ -138,6 +138,9 @@ struct GmresWork {
     void* tbuf = nullptr;         // velocity right-hand side inside the preconditioner
     void* z2buf = nullptr;        // Jacobi ping-pong
     double* r64 = nullptr;        // fp64 residual (n x J)
+    double* cb = nullptr;         // compacted right-hand sides and iterates of the members still
+    double* cx = nullptr;         // unconverged (n x Jmax each; adaptive handles only)
+    int32_t* cidx = nullptr;      // their member indices (Jmax)
     double* H = nullptr;          // (restart+1) x restart x J
     double* cs = nullptr;         // restart x J
     double* sn = nullptr;
@@ -208,7 +211,7 @@ hipError_t launch_rhs_strip(const DevMesh& m, const mhd_coeffs& c, int J, const 
 hipError_t launch_energy_partial(const DevMesh& m, const double* vbar, double* out, hipStream_t s);
 
 // ---------------------------------------------------------------- solver (solve.hip)
-mhd_status alloc_gmres(DevShared& S, int restart);
+mhd_status alloc_gmres(DevShared& S, int restart, bool compact);
 mhd_status solve_shared(DevShared& S, const double* rhs, double* x, int J, const mhd_solver_opts& o,
                         mhd_solve_stats* st, hipStream_t s);
 mhd_status spmm_shared(DevShared& S, const void* x, void* y, int J, int precision, hipStream_t s);

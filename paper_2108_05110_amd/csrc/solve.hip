@@ -4245,6 +4245,91 @@ mhd_status launch_scale_cols(const TI* a, const double* s, TO* out, int64_t n, i
     return MHD_OK;
 }
 
+template <typename T>
+mhd_status gmres_solve(DevShared& S, const double* b, double* x, int J, const mhd_solver_opts& o,
+                       mhd_solve_stats* stt, hipStream_t st, bool compact_ok = true);
+
+__global__ void k_gather_cols(const double* __restrict__ src, double* __restrict__ dst,
+                              const int32_t* __restrict__ idx, int64_t n, int J, int Jc) {
+    for (int64_t q = threadIdx.x + (int64_t)blockIdx.x * blockDim.x; q < n * Jc; q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = q / Jc;
+        dst[q] = src[r * J + idx[q - r * Jc]];
+    }
+}
+
+__global__ void k_scatter_cols(const double* __restrict__ src, double* __restrict__ dst,
+                               const int32_t* __restrict__ idx, int64_t n, int J, int Jc) {
+    for (int64_t q = threadIdx.x + (int64_t)blockIdx.x * blockDim.x; q < n * Jc; q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = q / Jc;
+        dst[r * J + idx[q - r * Jc]] = src[q];
+    }
+}
+
+// Adaptive per-member solve once some members have met rtol: the remaining
+// members' right-hand sides and iterates are gathered into a block of Jc < J
+// columns, solved on (every kernel streams Jc columns; the converged iterates
+// are left as they are), and scattered back; the statistics cover all J.
+template <typename T>
+mhd_status compacted_solve(DevShared& S, const double* b, double* x, int J, const std::vector<int32_t>& act,
+                           const mhd_solver_opts& o, mhd_solve_stats* stt, hipStream_t st, int iters0, int cycles0,
+                           const std::vector<int>& first_met) {
+    GmresWork& G = S.gw;
+    const int64_t n = S.mesh->n;
+    const int Jc = (int)act.size();
+    MHD_HIP(hipMemcpyAsync(G.cidx, act.data(), sizeof(int32_t) * Jc, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_gather_cols, dim3(ew_grid(n * Jc)), dim3(kBlock), 0, st, b, G.cb, (const int32_t*)G.cidx, n,
+                       J, Jc);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_gather_cols, dim3(ew_grid(n * Jc)), dim3(kBlock), 0, st, (const double*)x, G.cx,
+                       (const int32_t*)G.cidx, n, J, Jc);
+    LAUNCH_CHECK();
+    MHD_HIP(hipStreamSynchronize(st));   // act is host memory that the copy reads
+    mhd_solver_opts oc = o;
+    oc.maxit = std::max(1, o.maxit - iters0);
+    std::vector<double> rel_c(Jc);
+    std::vector<int32_t> it_c(Jc);
+    mhd_solve_stats sc{};
+    sc.relres = rel_c.data();
+    sc.member_iters = it_c.data();
+    const mhd_status rc = gmres_solve<T>(S, G.cb, G.cx, Jc, oc, &sc, st, false);
+    if (rc != MHD_OK && rc != MHD_ENOCONV) return rc;
+    hipLaunchKernelGGL(k_scatter_cols, dim3(ew_grid(n * Jc)), dim3(kBlock), 0, st, (const double*)G.cx, x,
+                       (const int32_t*)G.cidx, n, J, Jc);
+    LAUNCH_CHECK();
+    if (stt) {
+        // final residuals of all J members
+        Ops<double> ops(S, J, st);
+        mhd_status r2;
+        if ((r2 = saddle_residual64(S, b, x, G.r64, J, st))) return r2;
+        if ((r2 = ops.colnorm(G.r64, G.beta))) return r2;
+        if ((r2 = ops.colnorm(b, G.bnorm))) return r2;
+        std::vector<double> hb(J), hn(J);
+        MHD_HIP(hipMemcpyAsync(hb.data(), G.beta, sizeof(double) * J, hipMemcpyDeviceToHost, st));
+        MHD_HIP(hipMemcpyAsync(hn.data(), G.bnorm, sizeof(double) * J, hipMemcpyDeviceToHost, st));
+        MHD_HIP(hipStreamSynchronize(st));
+        double mx = 0.0;
+        int bad = 0;
+        for (int j = 0; j < J; ++j) {
+            const double r = hn[j] > 0 ? hb[j] / hn[j] : hb[j];
+            if (!std::isfinite(r)) ++bad;
+            else mx = std::max(mx, r);
+            if (stt->relres) stt->relres[j] = r;
+            if (stt->member_iters) stt->member_iters[j] = first_met[j] >= 0 ? first_met[j] : iters0;
+        }
+        for (int i = 0; i < Jc; ++i)
+            if (stt->member_iters) stt->member_iters[act[i]] = iters0 + it_c[i];
+        stt->iters = iters0 + sc.iters;
+        stt->cycles = cycles0 + sc.cycles;
+        stt->max_relres = bad ? NAN : mx;
+        stt->converged = (rc == MHD_OK) ? 1 : 0;
+        stt->nonfinite = bad;
+        stt->min_block_rank = J;
+        stt->norm_clamps = sc.norm_clamps;
+        stt->compacted = Jc;
+    }
+    return rc;
+}
+
 // Gram-Schmidt norms taken as zero in the last solve on this handle (fused
 // single pass), summed over members (synchronises; never called under capture)
 int norm_clamp_count(GmresWork& G, int J, hipStream_t st) {
@@ -4259,7 +4344,7 @@ int norm_clamp_count(GmresWork& G, int J, hipStream_t st) {
 
 template <typename T>
 mhd_status gmres_solve(DevShared& S, const double* b, double* x, int J, const mhd_solver_opts& o,
-                       mhd_solve_stats* stt, hipStream_t st) {
+                       mhd_solve_stats* stt, hipStream_t st, bool compact_ok) {
     DevMesh& m = *S.mesh;
     GmresWork& G = S.gw;
     const int64_t n = m.n;
@@ -4306,6 +4391,7 @@ mhd_status gmres_solve(DevShared& S, const double* b, double* x, int J, const mh
     auto fill_stats = [&](bool ok, bool nonfinite) {
         if (!stt) return;
         stt->norm_clamps = fixed ? -1 : norm_clamp_count(G, J, st);
+        stt->compacted = 0;
         stt->iters = iters;
         stt->cycles = cycles;
         stt->max_relres = fixed ? -1.0 : maxrel;
@@ -4348,6 +4434,14 @@ mhd_status gmres_solve(DevShared& S, const double* b, double* x, int J, const mh
             break;
         }
         if (iters >= o.maxit) break;
+        if (compact_ok && !o.keep_converged && G.cb) {
+            // some members converged: the others continue as a compacted block
+            std::vector<int32_t> act;
+            for (int j = 0; j < J; ++j)
+                if (!(first_met[j] >= 0)) act.push_back(j);
+            if (!act.empty() && (int)act.size() < J)
+                return compacted_solve<T>(S, b, x, J, act, o, stt, st, iters, cycles, first_met);
+        }
         }
         // v0 = r / beta in the inner precision; g = beta e1
         if ((rc = launch_scale_cols<double, T>(G.r64, G.beta, basis_ptr<T>(S, 0), n, J, st))) return rc;
@@ -4985,6 +5079,7 @@ mhd_status block_gmres_solve(DevShared& S, const double* b, double* x, int J, co
         stt->nonfinite = 0;
         stt->min_block_rank = rank_min;
         stt->norm_clamps = 0;
+        stt->compacted = 0;
         for (int j = 0; j < J; ++j) {
             if (stt->relres) stt->relres[j] = hbn[j] > 0 ? hbeta[j] / hbn[j] : hbeta[j];
             if (stt->member_iters) stt->member_iters[j] = first_met[j] < 0 ? iters : first_met[j];
@@ -5000,7 +5095,7 @@ mhd_status block_gmres_solve(DevShared& S, const double* b, double* x, int J, co
 }  // namespace
 
 // ------------------------------------------------------------------ allocation and entry
-mhd_status alloc_gmres(DevShared& S, int restart) {
+mhd_status alloc_gmres(DevShared& S, int restart, bool compact) {
     DevMesh& m = *S.mesh;
     GmresWork& G = S.gw;
     G.restart = restart;
@@ -5033,6 +5128,11 @@ mhd_status alloc_gmres(DevShared& S, int restart) {
     if ((rc = A((void**)&G.bnorm, J8))) return rc;
     if ((rc = A((void**)&G.hcol, J8 * 2 * (kMaxRestart + 1)))) return rc;
     if ((rc = A((void**)&G.res, J8 * 3))) return rc;   // estimates, new-vector norms, norm-clamp counts
+    if (compact) {
+        if ((rc = A((void**)&G.cb, (size_t)m.n * J8))) return rc;
+        if ((rc = A((void**)&G.cx, (size_t)m.n * J8))) return rc;
+        if ((rc = A((void**)&G.cidx, sizeof(int32_t) * (size_t)S.Jmax))) return rc;
+    }
     if (S.Jmax <= kBlockMaxJ && (rc = A((void**)&G.bmat, sizeof(double) * 2 * (size_t)S.Jmax * S.Jmax))) return rc;
     G.nblk_cap = std::min(kRedBlocks, std::max(64, 524288 / S.Jmax));
     G.partial_len = (int64_t)G.nblk_cap * (restart + 2) * S.Jmax + 1024;

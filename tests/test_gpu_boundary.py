@@ -215,3 +215,46 @@ def test_gram_schmidt_variants(L):
                 assert e <= (1e-8 if cycles == 0 else 1e-5), (cgs, restart, cycles, e)
     L.mhd_ens_shared_free(A)
     gm.close()
+
+
+def test_converged_members_are_compacted_out(L):
+    """Adaptive per-member solver: members whose iterate already meets rtol drop
+    out and the others continue as a compacted block.  Half the members start
+    from their converged solution: they are left bit for bit as they were, the
+    statistics report the compacted block, and the others reach the same
+    solution as with every column kept (keep_converged = 1)."""
+    from paper_2108_05110_amd.ensemble import Mesh, to_dev
+    N, J = 16, 8
+    say("compaction of converged members: 16^2, J=8, FP64 and FP32+IR adaptive")
+    pb = wl.cavity(J=J, s=0.1, dt=0.01, ic_amp=0.05)
+    gm = Mesh(L.MHD_MESH_UNIT_SQUARE, N)
+    V, W = pb.ic(gm.xy)
+    c = L.Coeffs(pb.dt, pb.mu, float(pb.nu.mean()), float(pb.nu_m.mean()), 0)
+    g = torch.Generator("cuda").manual_seed(21)
+    b = torch.randn((gm.n, J), dtype=torch.float64, device="cuda", generator=g)
+    A = L.mhd_ens_shared_create(gm.handle, J, 30)
+    L.mhd_ens_assemble_shared(gm.handle, c, to_dev(W), J, A)
+    ref = torch.zeros_like(b)
+    st, _ = L.mhd_ens_solve(A, b, ref, J, L.solver_opts(L.MHD_FP64, rtol=1e-13, keep_converged=1))
+    assert st.compacted == 0
+    for prec, rtol in ((L.MHD_FP64, 1e-11), (L.MHD_FP32_IR, 1e-10)):
+        out = {}
+        for keep in (0, 1):
+            x = torch.zeros_like(b)
+            x[:, :4] = ref[:, :4]
+            x0 = x.clone()
+            st, _ = L.mhd_ens_solve(A, b, x, J, L.solver_opts(prec, rtol=rtol, keep_converged=keep))
+            rel, its = L.member_stats(st, J)
+            say(f"  precision {prec} keep {keep}: iterations {st.iters}, compacted {st.compacted}, "
+                f"max relres {st.max_relres:.2e}, member iterations {its}")
+            assert st.converged == 1 and st.max_relres <= rtol
+            out[keep] = (x, st)
+            if keep == 0:
+                assert st.compacted == 4
+                assert torch.equal(x[:, :4], x0[:, :4])
+            else:
+                assert st.compacted == 0
+        err = float(torch.linalg.norm(out[0][0] - ref) / torch.linalg.norm(ref))
+        assert err <= 1e3 * rtol, err
+    L.mhd_ens_shared_free(A)
+    gm.close()
