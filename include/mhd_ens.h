@@ -241,6 +241,8 @@ typedef struct {
                                  block least squares on the host); adaptive schedule only,
                                  J in {16, 32, 64, 128}.  0 (default): one Arnoldi process
                                  per member over the shared SpMM                        */
+    int mg_post;              /* extra damped Jacobi post-smoothing sweeps on the finest
+                                 pressure level of each V-cycle (0 to 8; default 0)    */
     int keep_converged;       /* adaptive schedule, per-member solver: 0 (default) = once
                                  some members meet rtol at a refinement cycle, the
                                  others continue as a compacted block of fewer columns

@@ -73,7 +73,7 @@ class SolverOpts(C.Structure):
                 ("restart", C.c_int), ("jacobi_sweeps", C.c_int), ("check_every", C.c_int),
                 ("cgs_passes", C.c_int), ("fixed_cycles", C.c_int), ("jacobi_omega", C.c_double),
                 ("mg_unfused", C.c_int), ("mg_cycles", C.c_int), ("block_krylov", C.c_int),
-                ("keep_converged", C.c_int)]
+                ("mg_post", C.c_int), ("keep_converged", C.c_int)]
 
 
 class SolveStats(C.Structure):
@@ -403,10 +403,10 @@ def mhd_ens_group_free(group):
 
 def solver_opts(precision=MHD_FP64, rtol=None, inner_rtol=None, maxit=2000, restart=30, jacobi_sweeps=6,
                 check_every=1, cgs_passes=0, fixed_cycles=0, jacobi_omega=0.0, mg_unfused=0, mg_cycles=0,
-                block_krylov=0, keep_converged=0):
+                block_krylov=0, mg_post=0, keep_converged=0):
     if rtol is None:
         rtol = 1e-12 if precision == MHD_FP64 else 1e-11
     if inner_rtol is None:
         inner_rtol = 1e-8 if precision == MHD_FP64 else 1e-4
     return SolverOpts(precision, rtol, inner_rtol, maxit, restart, jacobi_sweeps, check_every, cgs_passes,
-                      fixed_cycles, jacobi_omega, mg_unfused, mg_cycles, block_krylov, keep_converged)
+                      fixed_cycles, jacobi_omega, mg_unfused, mg_cycles, block_krylov, mg_post, keep_converged)

@@ -451,6 +451,7 @@ mhd_status check_solver_opts(const mhd_solver_opts* o) {
     CHECK_ARG(o->block_krylov == 0 || (o->block_krylov == 1 && o->fixed_cycles == 0),
               "block_krylov must be 0, or 1 with the adaptive schedule (fixed_cycles 0)");
     CHECK_ARG(o->keep_converged == 0 || o->keep_converged == 1, "keep_converged must be 0 or 1");
+    CHECK_ARG(o->mg_post >= 0 && o->mg_post <= 8, "mg_post must be in [0, 8]");
     return MHD_OK;
 }
 

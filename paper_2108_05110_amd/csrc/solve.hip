@@ -3989,6 +3989,7 @@ struct Ops {
     NodePlan p_saddle, p_first, p_sweep;   // autotuned node-row kernels for this (mesh, J, word size)
     bool fused_mg = true;                  // V-cycle levels as their two fused operators
     int mg_cycles = 1;                     // V-cycles per Schur-part application (1 or 2)
+    int mg_post = 0;                       // extra post-smoothing sweeps on the finest level
 
     Ops(DevShared& s, int j, hipStream_t stream) : S(s), J(j), st(stream), JP(pick_jp(j)) {
         const int word = (int)sizeof(T);
@@ -4091,6 +4092,11 @@ struct Ops {
             if ((rc = csr<1>(Lv.P, dinv, xc, nullptr, x2, omega))) return rc; // x2 += P xc
             if ((rc = csr<3>(Lv.L, dinv, x2, b, x, omega))) return rc;        // post-smoothing
         }
+        if (l == 0)   // extra post-smoothing on the finest level (x -> x2 -> x ...)
+            for (int q = 0; q < mg_post; ++q) {
+                if ((rc = csr<3>(Lv.L, dinv, x, b, x2, omega))) return rc;
+                std::swap(x, x2);
+            }
         if (schur) {   // the last sweep writes the Schur part z_p directly
             if ((rc = csr<6>(Lv.L, dinv, x, b, schur, omega, pin))) return rc;
             *out = schur;
@@ -4355,6 +4361,7 @@ mhd_status gmres_solve(DevShared& S, const double* b, double* x, int J, const mh
     Ops<T> ops(S, J, st);
     ops.fused_mg = o.mg_unfused == 0;
     ops.mg_cycles = o.mg_cycles == 2 ? 2 : 1;
+    ops.mg_post = o.mg_post;
     RedShape rs = cap_blocks(red_shape(n, J, 16 / (int)sizeof(T)), G.nblk_cap);
     // cgs_passes: 1 or 2 classical passes with the norm taken directly, 3 one pass
     // with the norm from the dot products (fused kernels), 0 the default (one pass
@@ -4938,6 +4945,7 @@ mhd_status block_gmres_solve(DevShared& S, const double* b, double* x, int J, co
     Ops<T> ops(S, J, st);
     ops.fused_mg = o.mg_unfused == 0;
     ops.mg_cycles = o.mg_cycles == 2 ? 2 : 1;
+    ops.mg_post = o.mg_post;
     BlockQR qr;
     qr.J = J;
     const bool keepz = sizeof(T) == 4 && G.zbasis != nullptr;
