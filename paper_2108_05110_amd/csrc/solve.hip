@@ -4996,19 +4996,22 @@ mhd_status block_gmres_solve(DevShared& S, const double* b, double* x, int J, co
         if ((rc = block_mm<T, 0>(S, V0, Minv, R, J, st))) return rc;
         MHD_HIP(hipMemcpyAsync(V0, R, sizeof(T) * (size_t)n * J, hipMemcpyDeviceToDevice, st));
         {
-            std::vector<double> t((size_t)J * J, 0.0);
-            for (int i = 0; i < J; ++i)
-                for (int k = 0; k < J; ++k) {
-                    double v = 0.0;
-                    for (int q = 0; q < J; ++q) v += Cm[(size_t)i * J + q] * C0[(size_t)q * J + k];
-                    t[(size_t)i * J + k] = v;
+            std::vector<double> t((size_t)J * J, 0.0);   // Cm C0, rows of C0 streamed
+            for (int i = 0; i < J; ++i) {
+                double* tr = &t[(size_t)i * J];
+                for (int q = 0; q < J; ++q) {
+                    const double a = Cm[(size_t)i * J + q];
+                    if (a == 0.0) continue;
+                    const double* cr = &C0[(size_t)q * J];
+                    for (int k = 0; k < J; ++k) tr[k] += a * cr[k];
                 }
+            }
             C0.swap(t);
         }
         rank_min = std::min(rank_min, p);
         // block Arnoldi
-        std::vector<std::vector<double>> H;   // H[i * mres + k]: block (i, k), J x J
-        H.assign((size_t)(mres + 1) * mres, std::vector<double>((size_t)J * J, 0.0));
+        // H[i * mres + k]: block (i, k), J x J, sized when block column k is formed
+        std::vector<std::vector<double>> H((size_t)(mres + 1) * mres);
         int kd = 0;
         lsq.reset(J, mres, C0);
         std::vector<double> lsres;
@@ -5018,6 +5021,7 @@ mhd_status block_gmres_solve(DevShared& S, const double* b, double* x, int J, co
             T* w = basis_ptr<T>(S, k + 1);
             if ((rc = ops.precond(vk, z, sweeps, omega))) return rc;
             if ((rc = ops.saddle(z, w))) return rc;
+            for (int i = 0; i <= k + 1; ++i) H[(size_t)i * mres + k].assign((size_t)J * J, 0.0);
             for (int pass = 0; pass < 2; ++pass) {
                 std::vector<std::vector<double>> hk(k + 1);
                 for (int i = 0; i <= k; ++i)
@@ -5035,13 +5039,16 @@ mhd_status block_gmres_solve(DevShared& S, const double* b, double* x, int J, co
             std::vector<double> Minv2, C2;
             qr.factor(Gm, tol2, Minv2, C2);
             if ((rc = block_mm<T, 0>(S, tmp, Minv2, w, J, st))) return rc;
-            std::vector<double>& Hn = H[(size_t)(k + 1) * mres + k];
-            for (int i = 0; i < J; ++i)
-                for (int c = 0; c < J; ++c) {
-                    double v = 0.0;
-                    for (int q = 0; q < J; ++q) v += C2[(size_t)i * J + q] * Cm[(size_t)q * J + c];
-                    Hn[(size_t)i * J + c] = v;
+            std::vector<double>& Hn = H[(size_t)(k + 1) * mres + k];   // C2 Cm, rows of Cm streamed
+            for (int i = 0; i < J; ++i) {
+                double* hr = &Hn[(size_t)i * J];
+                for (int q = 0; q < J; ++q) {
+                    const double a = C2[(size_t)i * J + q];
+                    if (a == 0.0) continue;
+                    const double* cr = &Cm[(size_t)q * J];
+                    for (int c = 0; c < J; ++c) hr[c] += a * cr[c];
                 }
+            }
             rank_min = std::min(rank_min, pk);
             ++iters;
             kd = k + 1;
