@@ -3639,7 +3639,7 @@ mhd_status launch_velo_plan(NodePlan p, DevShared& S, const T* in, const T* zp, 
         if (p.deep == 3 && deep_ok(m)) {
             auto go3 = [&](auto kern, int threads) -> mhd_status {
                 MHD_HIP(allow_lds(kern, lds));
-                hipLaunchKernelGGL(kern, grid, dim3(threads), lds, st, tile_view(tl), tile_ent(tl), tile_dims(tl), val,
+                launch_k(kern, grid, dim3(threads), lds, st, tile_view(tl), tile_ent(tl), tile_dims(tl), val,
                                    Vals<T>::dA(S), in, zp, t, z, zo, J, MT, omega);
                 LAUNCH_CHECK();
                 return MHD_OK;
@@ -3652,7 +3652,7 @@ mhd_status launch_velo_plan(NodePlan p, DevShared& S, const T* in, const T* zp, 
         }
         auto go = [&](auto kern, int threads) -> mhd_status {
             MHD_HIP(allow_lds(kern, lds));
-            hipLaunchKernelGGL(kern, grid, dim3(threads), lds, st, tile_view(tl), rp, val, Vals<T>::dA(S), in, zp, t,
+            launch_k(kern, grid, dim3(threads), lds, st, tile_view(tl), rp, val, Vals<T>::dA(S), in, zp, t,
                                z, zo, J, MT, omega);
             LAUNCH_CHECK();
             return MHD_OK;
@@ -3679,7 +3679,7 @@ mhd_status launch_velo_plan(NodePlan p, DevShared& S, const T* in, const T* zp, 
             constexpr int VV = decltype(V)::value;
             return with_gd(p.g, [&](auto Gc) -> mhd_status {
                 constexpr int GG = decltype(Gc)::value;
-                hipLaunchKernelGGL((k_velo_p<T, VV, FIRST, GG>), group_grid(m.nP2, J, VV, GG), dim3(kBlock), 0, st,
+                launch_k(k_velo_p<T, VV, FIRST, GG>, group_grid(m.nP2, J, VV, GG), dim3(kBlock), 0, st,
                                    rp, col, val, Vals<T>::dA(S), in, zp, t, z, zo, m.nP2, J, omega);
                 LAUNCH_CHECK();
                 return MHD_OK;
@@ -3690,10 +3690,10 @@ mhd_status launch_velo_plan(NodePlan p, DevShared& S, const T* in, const T* zp, 
     if (p.vec == 0) {
         const int JP = pick_jp(J);
         if (FIRST)
-            hipLaunchKernelGGL((k_velo_first<T>), dim3(grid_for(m.nP2, JP)), dim3(kBlock), 0, st, rp, col, val,
+            launch_k(k_velo_first<T>, dim3(grid_for(m.nP2, JP)), dim3(kBlock), 0, st, rp, col, val,
                                Vals<T>::dA(S), in, zp, t, zo, m.nP2, J, JP, omega);
         else
-            hipLaunchKernelGGL((k_velo_sweep<T>), dim3(grid_for(m.nP2, JP)), dim3(kBlock), 0, st, rp, col, val,
+            launch_k(k_velo_sweep<T>, dim3(grid_for(m.nP2, JP)), dim3(kBlock), 0, st, rp, col, val,
                                Vals<T>::dA(S), (const T*)t, z, zo, m.nP2, J, JP, omega);
         LAUNCH_CHECK();
         return MHD_OK;
@@ -3703,10 +3703,10 @@ mhd_status launch_velo_plan(NodePlan p, DevShared& S, const T* in, const T* zp, 
         return with_g(p.g, [&](auto Gc) -> mhd_status {
             constexpr int GG = decltype(Gc)::value;
             if constexpr (GG == 0) {
-                hipLaunchKernelGGL((k_velo_v<T, VV, FIRST>), node_grid(m.nP2, J, VV), dim3(kBlock), 0, st, rp, col,
+                launch_k(k_velo_v<T, VV, FIRST>, node_grid(m.nP2, J, VV), dim3(kBlock), 0, st, rp, col,
                                    val, Vals<T>::dA(S), in, zp, t, z, zo, m.nP2, J, omega);
             } else {
-                hipLaunchKernelGGL((k_velo_g<T, VV, FIRST, GG>), group_grid(m.nP2, J, VV, GG), dim3(kBlock), 0, st,
+                launch_k(k_velo_g<T, VV, FIRST, GG>, group_grid(m.nP2, J, VV, GG), dim3(kBlock), 0, st,
                                    rp, col, val, Vals<T>::dA(S), in, zp, t, z, zo, m.nP2, J, omega);
             }
             LAUNCH_CHECK();

@@ -264,8 +264,8 @@ def test_extra_post_smoothing_option(L):
     """mg_post adds damped Jacobi post-smoothing sweeps on the finest pressure
     level: a stronger Schur part, the same solution, no more iterations."""
     from paper_2108_05110_amd.ensemble import Mesh, to_dev
-    N, J = 32, 16
-    say("extra post-smoothing: 32^2, J=16, FP64 adaptive")
+    N, J = 64, 16   # at least two pressure levels (32^2 has only the dense one)
+    say("extra post-smoothing: 64^2, J=16, FP64 adaptive")
     pb = wl.cavity(J=J, s=0.1, dt=0.01, ic_amp=0.05)
     gm = Mesh(L.MHD_MESH_UNIT_SQUARE, N)
     V, W = pb.ic(gm.xy)
@@ -283,6 +283,44 @@ def test_extra_post_smoothing_option(L):
         xs.append(x)
         its.append(st.iters)
     assert its[1] <= its[0]
+    assert not torch.equal(xs[1], xs[0])      # the option reached the multigrid
     assert float(torch.linalg.norm(xs[1] - xs[0]) / torch.linalg.norm(xs[0])) <= 1e-9
+    L.mhd_ens_shared_free(A)
+    gm.close()
+
+
+def test_kernel_timer_selects_the_operator(L):
+    """mhd_ens_timer_op: the timer counts the SpMM launches of a solve (one per
+    inner iteration) or the velocity Jacobi sweeps that update the previous
+    iterate (sweeps - 2 per preconditioner application with the paired-row
+    plans, sweeps - 1 otherwise); other operators are refused."""
+    from paper_2108_05110_amd.ensemble import Mesh, to_dev
+    N, J, sweeps = 32, 16, 7
+    say("kernel timer: SpMM and Jacobi sweep launches of a fixed-schedule FP32 solve")
+    pb = wl.cavity(J=J, s=0.1, dt=0.01, ic_amp=0.05)
+    gm = Mesh(L.MHD_MESH_UNIT_SQUARE, N)
+    V, W = pb.ic(gm.xy)
+    c = L.Coeffs(pb.dt, pb.mu, float(pb.nu.mean()), float(pb.nu_m.mean()), 0)
+    b = torch.ones((gm.n, J), dtype=torch.float64, device="cuda")
+    A = L.mhd_ens_shared_create(gm.handle, J, 6)
+    L.mhd_ens_assemble_shared(gm.handle, c, to_dev(W), J, A)
+    opts = L.solver_opts(L.MHD_FP32_IR, restart=6, fixed_cycles=2, jacobi_sweeps=sweeps)
+    counts = {}
+    for op in (L.TUNE_SADDLE, L.TUNE_JACOBI):
+        L.mhd_ens_timer_op(op)
+        L.mhd_ens_timer_enable(True)
+        x = torch.zeros_like(b)
+        st, _ = L.mhd_ens_solve(A, b, x, J, opts)
+        ms, launches, _, _ = L.mhd_ens_timer_read()
+        L.mhd_ens_timer_enable(False)
+        counts[op] = (launches, st.iters, ms)
+        say(f"  op {op}: {launches} launches, {ms:.3f} ms, {st.iters} iterations")
+    L.mhd_ens_timer_op(L.TUNE_SADDLE)
+    launches, iters, ms = counts[L.TUNE_SADDLE]
+    assert launches == iters and ms > 0
+    launches, iters, ms = counts[L.TUNE_JACOBI]
+    assert launches in ((sweeps - 2) * iters, (sweeps - 1) * iters) and ms > 0
+    with pytest.raises(L.MhdError):
+        L.mhd_ens_timer_op(L.TUNE_RESIDUAL)
     L.mhd_ens_shared_free(A)
     gm.close()
