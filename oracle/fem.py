@@ -1,4 +1,4 @@
-"""Quadrature, Taylor-Hood P2-P1 bases and global FE matrices (oracle side, FP64).
+"""Quadrature, P2 / P1 bases and global FE matrices (oracle side, FP64).
 
 Every integral is a quadrature sum over the elements with the 7-point,
 degree-5 rule of Radon (centroid plus two 3-point orbits), which is exact for
@@ -13,8 +13,10 @@ Conventions:
     phi_3 = 4 l0 l1, phi_4 = 4 l1 l2, phi_5 = 4 l2 l0 for the edge midpoints
   * P1 basis: psi_k = l_k
   * integral over T of f ~ |T| sum_q w_q f(x_q), weights summing to one
-  * velocity unknown (P2 node i, component c) -> 2 i + c; pressure node k ->
-    2 nP2 + k (saddle-point ordering of the coupled system)
+  * velocity unknown (P2 node i, component c) -> 2 i + c; pressure unknown k ->
+    2 nP2 + k (saddle-point ordering of the coupled system); the pressure is
+    continuous P1 (Taylor-Hood) or, on an Alfeld mesh, discontinuous P1
+    (Scott-Vogelius), as the mesh says
 """
 from __future__ import annotations
 
@@ -138,10 +140,11 @@ class Element:
         return self._scatter(ke, self.mesh.tri, self.mesh.tri, (n, n))
 
     def divergence(self):
-        """B (nP1, 2 nP2): B[k, 2i+c] = -(psi_k, d phi_i / d x_c)."""
+        """B (nP1, 2 nP2): B[k, 2i+c] = -(psi_k, d phi_i / d x_c), psi_k the
+        pressure basis function (continuous or, on an Alfeld mesh, per element)."""
         ke = -np.einsum('e,q,qk,eqic->ekic', self.area, self.w, self.psi, self.dphi)
         ne = self.mesh.n_el
-        rows = np.repeat(self.mesh.tri[:, :3, None, None], 6, axis=2).repeat(2, axis=3)
+        rows = np.repeat(self.mesh.ptri[:, :, None, None], 6, axis=2).repeat(2, axis=3)
         cols = 2 * self.mesh.tri[:, None, :, None] + np.arange(2)[None, None, None, :]
         cols = np.broadcast_to(cols, (ne, 3, 6, 2))
         return sp.coo_matrix((ke.ravel(), (rows.ravel(), cols.ravel())),
@@ -150,7 +153,7 @@ class Element:
     def p1_mass_lumped(self):
         """m_k = integral of psi_k (exact: |T|/3 per element)."""
         m = np.zeros(self.mesh.nP1)
-        np.add.at(m, self.mesh.tri[:, :3].ravel(), np.repeat(self.area / 3.0, 3))
+        np.add.at(m, self.mesh.ptri.ravel(), np.repeat(self.area / 3.0, 3))
         return m
 
 

@@ -1,16 +1,23 @@
-"""Structured triangulations and Taylor-Hood P2/P1 node numbering (oracle side).
+"""Structured triangulations and P2 / pressure node numbering (oracle side).
 
 Meshes are the "regular triangular meshes" of Section 4: every square cell
 [x_i, x_i+h] x [y_k, y_k+h] is cut by its rising diagonal into the triangles
-(v00, v10, v11) and (v00, v11, v01), both counter-clockwise.
+(v00, v10, v11) and (v00, v11, v01), both counter-clockwise.  `alfeld` refines
+such a mesh at the barycentres (each triangle (a, b, c) with barycentre g
+becomes (a, b, g), (b, c, g), (c, a, g)), the meshes on which Section 2 places
+the Scott-Vogelius pair (P2, P1 discontinuous).
 
 Numbering (the oracle's own, unrelated to the GPU library's):
   * vertices in row-major order of the vertex grid (y slowest), only those
     that belong to a kept cell;
   * P2 nodes = all vertices, then one node per edge in order of first
     appearance while walking the elements and their edges (01, 12, 20);
-  * P1 (pressure) nodes = vertices, same numbers as their P2 node.
-Element connectivity: (v0, v1, v2, m01, m12, m20) with m_ab the edge midpoint.
+  * Taylor-Hood pressure (continuous P1) nodes = vertices, same numbers as
+    their P2 node;
+  * Scott-Vogelius pressure (discontinuous P1): three unknowns per element,
+    3 e + k belonging to its vertex k.
+Element connectivity: (v0, v1, v2, m01, m12, m20) with m_ab the edge midpoint;
+`ptri` (n_el, 3) gives the pressure unknown of each element vertex.
 """
 from __future__ import annotations
 
@@ -23,8 +30,9 @@ import numpy as np
 class Mesh:
     xy: np.ndarray          # (nP2, 2) node coordinates; first nV rows are the vertices
     tri: np.ndarray         # (n_el, 6) P2 connectivity
-    nV: int                 # number of vertices = P1 nodes
+    nV: int                 # number of vertices
     bnd: np.ndarray         # sorted P2 node ids on the boundary
+    disc: bool = False      # pressure discontinuous P1 (Scott-Vogelius) instead of continuous P1
 
     @property
     def n_el(self):
@@ -36,11 +44,26 @@ class Mesh:
 
     @property
     def nP1(self):
-        return self.nV
+        """Number of pressure unknowns."""
+        return 3 * self.n_el if self.disc else self.nV
+
+    @property
+    def ptri(self):
+        """(n_el, 3): pressure unknown of each element vertex."""
+        if self.disc:
+            return np.arange(3 * self.n_el, dtype=np.int64).reshape(-1, 3)
+        return self.tri[:, :3]
+
+    @property
+    def pxy(self):
+        """(nP1, 2): location of each pressure unknown."""
+        if self.disc:
+            return self.xy[self.tri[:, :3]].reshape(-1, 2)
+        return self.xy[:self.nV]
 
     @property
     def n(self):
-        return 2 * self.nP2 + self.nV
+        return 2 * self.nP2 + self.nP1
 
 
 def _build(nx, ny, h, keep, x0=0.0, y0=0.0):
@@ -58,7 +81,12 @@ def _build(nx, ny, h, keep, x0=0.0, y0=0.0):
         a, b, c, d = vid[k, i], vid[k, i + 1], vid[k + 1, i + 1], vid[k + 1, i]
         tris.append((a, b, c))
         tris.append((a, c, d))
-    tris = np.array(tris, dtype=np.int64)
+    return _p2_mesh(vxy, np.array(tris, dtype=np.int64))
+
+
+def _p2_mesh(vxy, tris, disc=False):
+    """P2 nodes of the triangulation (vertex coordinates vxy, counter-clockwise
+    vertex triples tris): vertices, then edge midpoints in order of first use."""
     nV = len(vxy)
     edge_id = {}
     edge_count = {}
@@ -79,7 +107,20 @@ def _build(nx, ny, h, keep, x0=0.0, y0=0.0):
     for key in keys:
         if edge_count[key] == 1:
             bset.update((key[0], key[1], nV + edge_id[key]))
-    return Mesh(xy=xy, tri=conn, nV=nV, bnd=np.array(sorted(bset), dtype=np.int64))
+    return Mesh(xy=xy, tri=conn, nV=nV, bnd=np.array(sorted(bset), dtype=np.int64), disc=disc)
+
+
+def alfeld(mesh: Mesh) -> Mesh:
+    """Barycentric refinement of `mesh` with the discontinuous P1 pressure:
+    vertices of `mesh` first, then the barycentres in element order; element
+    e of `mesh` becomes elements 3e, 3e+1, 3e+2 = (a, b, g), (b, c, g), (c, a, g)."""
+    vxy = mesh.xy[:mesh.nV]
+    macro = mesh.tri[:, :3]
+    g = mesh.nV + np.arange(len(macro))
+    bary = vxy[macro].mean(axis=1)
+    a, b, c = macro[:, 0], macro[:, 1], macro[:, 2]
+    tris = np.stack([np.stack([a, b, g], 1), np.stack([b, c, g], 1), np.stack([c, a, g], 1)], 1).reshape(-1, 3)
+    return _p2_mesh(np.vstack([vxy, bary]), tris, disc=True)
 
 
 def unit_square(N: int) -> Mesh:
@@ -101,9 +142,8 @@ def nested_dissection(mesh: Mesh, leaf: int = 64) -> np.ndarray:
     (velocities before pressures), so every pressure is eliminated after some
     velocity it couples to.  The order only changes the rounding of a direct
     solve, not what is solved."""
-    nV = mesh.nV
-    xy = np.concatenate([np.repeat(mesh.xy, 2, axis=0), mesh.xy[:nV]])
-    h = float(np.min(np.diff(np.unique(np.round(mesh.xy[:nV, 0], 12)))))
+    xy = np.concatenate([np.repeat(mesh.xy, 2, axis=0), mesh.pxy])
+    h = float(np.min(np.diff(np.unique(np.round(mesh.xy[:mesh.nV, 0], 12)))))
     tol = 1e-6 * h
     out = []
 
@@ -126,5 +166,7 @@ def nested_dissection(mesh: Mesh, leaf: int = 64) -> np.ndarray:
         part(ids[d > tol])
         out.append(np.sort(ids[np.abs(d) <= tol]))
 
+    if mesh.disc:
+        raise ValueError("nested dissection is defined for the unrefined meshes only")
     part(np.arange(len(xy)))
     return np.concatenate(out)

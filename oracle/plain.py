@@ -30,7 +30,7 @@ def run_plain(mesh, problem, member=0, nsteps=None):
     fixed = np.concatenate([2 * dn, 2 * dn + 1])
     pin = None
     if problem.pin_pressure:
-        pin = 2 * nP2 + int(np.argmin(np.hypot(xy[:mesh.nV, 0], xy[:mesh.nV, 1])))
+        pin = 2 * nP2 + int(np.argmin(np.hypot(mesh.pxy[:, 0], mesh.pxy[:, 1])))
         fixed = np.concatenate([fixed, [pin]])
     V0, W0 = problem.ic(xy)
     v, w = V0[:, :, member].copy(), W0[:, :, member].copy()

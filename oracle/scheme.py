@@ -49,7 +49,7 @@ class Ensemble:
         self.dnodes = mesh.bnd[problem.is_dirichlet(bxy)]
         self.pin = None
         if problem.pin_pressure:
-            d = np.hypot(mesh.xy[:mesh.nV, 0], mesh.xy[:mesh.nV, 1])
+            d = np.hypot(mesh.pxy[:, 0], mesh.pxy[:, 1])
             self.pin = int(np.argmin(d))
         n = mesh.n
         keep = np.ones(n)

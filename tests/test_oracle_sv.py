@@ -1,0 +1,159 @@
+"""Pins of the oracle's Scott-Vogelius discretisation (P2 velocity, discontinuous
+P1 pressure on the barycentric refinement of the Section 4 meshes), the pair the
+paper computes with (Sections 2 and 4).
+
+Each test checks the oracle against the paper or the mathematics: the printed
+errors of Table 3 with the Section 4.1 pressure present, the divergence-free
+property of the pair, the pressure robustness it implies, the agreement of the
+plain and skew-symmetric trilinear forms on divergence-free fields, the discrete
+inf-sup condition (divergence onto the zero-mean pressures) and the full-step
+patch test."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import fem, mesh as om, scheme
+from test_oracle import GOLDEN, NoPressure, Patch
+
+
+def _errors_21_on(pb, ms):
+    """The ||.||_{2,1} errors of Section 4.1 on the mesh ms."""
+    ens = scheme.Ensemble(ms, pb)
+    el = ens.el
+    ev, ew = [], []
+
+    def cb(n, V, W, Q, R):
+        gv, gw = pb.base_grad(n * pb.dt, el.xq.reshape(-1, 2))
+        for Z, g, acc in ((V, gv, ev), (W, gw, ew)):
+            d = el.grads(Z.mean(axis=2)) - g.reshape(ms.n_el, 7, 2, 2) * pb.c.mean()
+            acc.append(np.einsum('e,q,eqcd->', el.area, el.w, d * d))
+
+    ens.run(callback=cb, shared_lu=True)
+    return math.sqrt(pb.dt * sum(ev)), math.sqrt(pb.dt * sum(ew))
+
+
+def _table3_problem(cls, J=4):
+    r = np.random.default_rng(5)
+    nu, num = r.uniform(0.009, 0.011, J), r.uniform(0.09, 0.11, J)
+    return cls(J=J, dt=0.001 / 8, nsteps=8, s=1, mu=1, nu=nu, nu_m=num, eps=0.01)
+
+
+def test_table3_with_pressure():
+    """Section 4.1, Table 3 (eps = 0.01, first viscosity sample): with the pressure
+    term of the manufactured solution present, Scott-Vogelius on the refined
+    meshes of h = 1/4, 1/8, 1/16 reproduces the printed velocity errors to 0.5 %
+    (the agreement tightens with h: the paper's 20 viscosity samples are not
+    published), and the rate is 2."""
+    tab = np.loadtxt(os.path.join(GOLDEN, "table1_spatial_eps001.txt"))
+    errs = []
+    for N in (4, 8, 16):
+        e = _errors_21_on(_table3_problem(wl.Manufactured), om.alfeld(om.unit_square(N)))
+        row = tab[tab[:, 0] == N][0]
+        assert abs(e[0] / row[1] - 1) < 0.005, (N, e, row)
+        assert abs(e[1] / row[2] - 1) < 0.005, (N, e, row)
+        errs.append(e)
+    errs = np.array(errs)
+    assert np.all(np.log2(errs[:-1] / errs[1:]) > 1.95)
+
+
+def test_pressure_robustness():
+    """The discrete divergence lies in the pressure space, so a gradient force
+    moves only the pressure: the velocity errors with and without the Section
+    4.1 pressure agree up to the interpolation of the forcing (1e-4 relative),
+    while Taylor-Hood's differ by more than 1 %."""
+    N = 8
+    sv = om.alfeld(om.unit_square(N))
+    a = _errors_21_on(_table3_problem(wl.Manufactured), sv)
+    b = _errors_21_on(_table3_problem(NoPressure), sv)
+    assert abs(a[0] / b[0] - 1) < 1e-4 and abs(a[1] / b[1] - 1) < 1e-4, (a, b)
+    th = om.unit_square(N)
+    a = _errors_21_on(_table3_problem(wl.Manufactured), th)
+    b = _errors_21_on(_table3_problem(NoPressure), th)
+    assert abs(a[0] / b[0] - 1) > 0.01, (a, b)
+
+
+def _divergence_at_points(ms, z):
+    """div z and max |grad z| at the quadrature points; z (nP2, 2)."""
+    g = fem.Element(ms).grads(z)          # (n_el, 7, 2, 2)
+    return g[:, :, 0, 0] + g[:, :, 1, 1], np.abs(g).max()
+
+
+@pytest.mark.parametrize("refined", [True, False])
+def test_divergence_free_pointwise(refined):
+    """After a step every member's velocity is divergence-free at every
+    quadrature point on the refined mesh (Section 2); Taylor-Hood's is not."""
+    base = om.unit_square(4)
+    ms = om.alfeld(base) if refined else base
+    pb = wl.Manufactured(J=3, dt=0.01, nsteps=1, s=1, mu=1, nu=np.array([0.01, 0.011, 0.009]),
+                         nu_m=np.array([0.1, 0.09, 0.11]), eps=0.1)
+    ens = scheme.Ensemble(ms, pb)
+    V0, W0 = pb.ic(ms.xy)
+    V1, W1, _, _ = ens.step(V0, W0, pb.dt)
+    worst = 0.0
+    for Z in (V1, W1):
+        for j in range(Z.shape[2]):
+            div, scale = _divergence_at_points(ms, Z[:, :, j])
+            worst = max(worst, np.abs(div).max() / scale)
+    if refined:
+        assert worst < 1e-11, worst
+    else:
+        assert worst > 1e-4, worst
+
+
+def test_plain_and_skew_forms_agree_on_divergence_free_fields():
+    """b(u, v, w) and its skew-symmetric form differ by ((div u) v, w) / 2 plus a
+    boundary term that the Dirichlet rows remove; from a divergence-free state
+    (one step of the scheme) the next step is the same with either form."""
+    ms = om.alfeld(om.unit_square(4))
+    kw = dict(J=3, dt=0.01, nsteps=1, s=1, mu=1, nu=np.array([0.01, 0.011, 0.009]),
+              nu_m=np.array([0.1, 0.09, 0.11]), eps=0.1)
+    skew = scheme.Ensemble(ms, wl.Manufactured(convective=0, **kw))
+    plain = scheme.Ensemble(ms, wl.Manufactured(convective=1, **kw))
+    V0, W0 = skew.pb.ic(ms.xy)
+    V1, W1, _, _ = skew.step(V0, W0, 0.01)
+    a = skew.step(V1, W1, 0.02)
+    b = plain.step(V1, W1, 0.02)
+    for x, y in zip(a, b):
+        assert np.abs(x - y).max() < 1e-10 * np.abs(x).max()
+    # ... while from the interpolated (not discretely divergence-free) initial data they differ
+    a0 = skew.step(V0, W0, 0.01)[0]
+    b0 = plain.step(V0, W0, 0.01)[0]
+    assert np.abs(a0 - b0).max() > 1e-8 * np.abs(a0).max()
+
+
+def test_inf_sup_divergence_onto_zero_mean_pressures():
+    """The divergence of the velocities vanishing on the boundary maps onto the
+    discontinuous P1 functions of zero mean (the inf-sup condition of the pair on
+    barycentric refinements): the divergence matrix restricted to interior
+    velocity unknowns has rank nP1 - 1 and annihilates only constants."""
+    ms = om.alfeld(om.unit_square(2))
+    B = fem.Element(ms).divergence().toarray()
+    interior = np.setdiff1d(np.arange(ms.nP2), ms.bnd)
+    cols = np.concatenate([2 * interior, 2 * interior + 1])
+    Bi = B[:, cols]
+    assert np.linalg.matrix_rank(Bi) == ms.nP1 - 1
+    assert np.abs(np.ones(ms.nP1) @ Bi).max() < 1e-13
+
+
+@pytest.mark.parametrize("convective", [0, 1])
+def test_patch_full_step_exact_sv(convective):
+    """The patch test of Algorithm 1 on the refined mesh: quadratic
+    divergence-free v, constant member-scaled w and linear q lie in the spaces,
+    so one step reproduces them; the pressure is the zero-mean q at every
+    element vertex."""
+    m = om.alfeld(om.unit_square(3))
+    J = 3
+    pb = Patch(J, c=[1.2, 0.7, 1.1], dt=0.1, nsteps=1, s=1.0, mu=1.0,
+               nu=np.array([0.01, 0.012, 0.009]), nu_m=np.array([0.02, 0.018, 0.025]),
+               convective=convective)
+    ens = scheme.Ensemble(m, pb)
+    V0, W0 = pb.ic(m.xy)
+    V1, W1, Q, R = ens.step(V0, W0, 0.1)
+    assert np.abs(V1 - V0).max() < 1e-11
+    assert np.abs(W1 - W0).max() < 1e-11
+    q = m.pxy[:, 0] + 2 * m.pxy[:, 1] - 1.5
+    assert np.abs(Q - q[:, None]).max() < 1e-10
+    assert np.abs(R).max() < 1e-10
