@@ -27,10 +27,11 @@
  *      unknown block    (n, J):       velocity rows 2*i + c (i P2 node,
  *                                     c component) then pressure rows
  *                                     2*nP2 + k, n = 2 nP2 + nP1.
- *  - Node numbering: P2 nodes are the points of the (2 nx + 1) x (2 ny + 1)
- *    half-step grid of the cell grid that belong to a kept cell, in row-major
- *    order (y slowest); P1 nodes are the vertices (even half-step grid points)
- *    in the same order.  mhd_ens_mesh_coords returns the coordinates.
+ *  - Node numbering (Taylor-Hood; Scott-Vogelius meshes: see mhd_mesh_desc):
+ *    P2 nodes are the points of the (2 nx + 1) x (2 ny + 1) half-step grid of
+ *    the cell grid that belong to a kept cell, in row-major order (y
+ *    slowest); P1 nodes are the vertices (even half-step grid points) in the
+ *    same order.  mhd_ens_mesh_coords returns the coordinates.
  *  - All device work is asynchronous on the caller's stream (0 = the null
  *    stream).  Calls that fill host statistics synchronise that stream.
  *  - Device memory is allocated only by the create calls (mhd_ens_mesh,
@@ -62,6 +63,7 @@ typedef int mhd_status;
 
 typedef enum { MHD_FP64 = 0, MHD_FP32_IR = 1 } mhd_precision;
 typedef enum { MHD_MESH_UNIT_SQUARE = 0, MHD_MESH_STEP_CHANNEL = 1 } mhd_mesh_kind;
+typedef enum { MHD_ELEMENT_TAYLOR_HOOD = 0, MHD_ELEMENT_SCOTT_VOGELIUS = 1 } mhd_element;
 typedef enum { MHD_V_PROBLEM = 0, MHD_W_PROBLEM = 1 } mhd_which;
 
 typedef void* mhd_stream_t;            /* a hipStream_t */
@@ -76,12 +78,29 @@ typedef struct mhd_ctx_s*    mhd_ctx;
  *     nx = m (cells per unit length); outflow x = 30.
  * natural_outflow: 1 = do-nothing condition on x = 30 (step channel only),
  *   0 = Dirichlet on the whole boundary.  With a fully Dirichlet boundary the
- *   pressure is pinned at the vertex (0,0) (identity row) because it is
- *   determined only up to a constant (Section 2, Q = L^2_0). */
+ *   pressure is pinned (identity row) because it is determined only up to a
+ *   constant (Section 2, Q = L^2_0): Taylor-Hood at the vertex (0,0) (the
+ *   first vertex), Scott-Vogelius at pressure unknown 0.
+ * element (Section 2: any inf-sup stable pair; the experiments of Section 4
+ *   use Scott-Vogelius):
+ *   MHD_ELEMENT_TAYLOR_HOOD: continuous P2 velocity, continuous P1 pressure
+ *     on the triangulation above.
+ *   MHD_ELEMENT_SCOTT_VOGELIUS: continuous P2 velocity, discontinuous P1
+ *     pressure on its barycentric (Alfeld) refinement: each triangle
+ *     (p0, p1, p2) with barycentre g (cells in row-major order, lower
+ *     (v00, v10, v11) before upper (v00, v11, v01)) becomes the elements
+ *     (p0, p1, g), (p1, p2, g), (p2, p0, g).  P2 nodes are the points of the
+ *     (6 nx + 1) x (6 ny + 1) grid of sixth steps used by some element, in
+ *     row-major order; pressure unknown 3 e + k belongs to vertex k of
+ *     element e (nP1 = 3 n_el).  The velocity divergence then lies in the
+ *     pressure space, so discrete solutions are divergence-free pointwise.
+ *     Kernel plans with row tiles (tile != 0) and the adjoint calls are
+ *     defined for Taylor-Hood meshes only (MHD_EINVAL). */
 typedef struct {
     int kind;
     int nx;
     int natural_outflow;
+    int element;
 } mhd_mesh_desc;
 
 typedef struct {
@@ -107,6 +126,14 @@ mhd_status mhd_ens_mesh(const mhd_mesh_desc* d, mhd_mesh* out, mhd_mesh_info* in
  * evaluate them: xy_p2 (nP2*2 doubles, may be NULL), dir_nodes (n_dir int32:
  * the Dirichlet P2 nodes in the order bc arrays use, may be NULL). */
 mhd_status mhd_ens_mesh_coords(mhd_mesh m, double* xy_p2, int32_t* dir_nodes);
+
+/* (Section 2: the finite element spaces are defined element by element.)
+ * Host copy of the element connectivity, tri (host, n_el*6 int32): the P2
+ * nodes of element e are tri[6e..6e+5] in the order (v0, v1, v2, m01, m12,
+ * m20), vertices counter-clockwise, m_ab the midpoint of edge ab.  The
+ * pressure unknowns of element e are vertex ids of the unrefined grid
+ * (Taylor-Hood, P1 numbering) or 3e, 3e+1, 3e+2 (Scott-Vogelius). */
+mhd_status mhd_ens_mesh_elements(mhd_mesh m, int32_t* tri);
 
 /* Releases a mesh and everything mhd_ens_mesh built for it (Section 2's
  * finite element spaces on that triangulation).  Handles created from it

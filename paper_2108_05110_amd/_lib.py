@@ -18,10 +18,11 @@ MHD_OK, MHD_EINVAL, MHD_ENOMEM, MHD_EHIP, MHD_ENOCONV, MHD_ESHAPE = 0, -1, -2, -
 MHD_FP64, MHD_FP32_IR = 0, 1
 MHD_MESH_UNIT_SQUARE, MHD_MESH_STEP_CHANNEL = 0, 1
 MHD_V_PROBLEM, MHD_W_PROBLEM = 0, 1
+MHD_ELEMENT_TAYLOR_HOOD, MHD_ELEMENT_SCOTT_VOGELIUS = 0, 1
 
 # Public symbols of include/mhd_ens.h (checked by the CPU test-suite).
 EXPORTS = (
-    "mhd_ens_mesh_counts", "mhd_ens_mesh", "mhd_ens_mesh_coords", "mhd_ens_mesh_free",
+    "mhd_ens_mesh_counts", "mhd_ens_mesh", "mhd_ens_mesh_coords", "mhd_ens_mesh_elements", "mhd_ens_mesh_free",
     "mhd_ens_shared_create", "mhd_ens_shared_free", "mhd_ens_assemble_shared", "mhd_ens_shared_csr",
     "mhd_ens_assemble_rhs", "mhd_ens_assemble_rhs_noalloc", "mhd_ens_solve", "mhd_ens_ctx_create", "mhd_ens_ctx_free", "mhd_ens_step",
     "mhd_ens_spmm", "mhd_ens_timer_enable", "mhd_ens_timer_op", "mhd_ens_timer_read", "mhd_ens_last_error", "mhd_ens_version",
@@ -45,7 +46,7 @@ class TuneEntry(C.Structure):
 
 
 class MeshDesc(C.Structure):
-    _fields_ = [("kind", C.c_int), ("nx", C.c_int), ("natural_outflow", C.c_int)]
+    _fields_ = [("kind", C.c_int), ("nx", C.c_int), ("natural_outflow", C.c_int), ("element", C.c_int)]
 
 
 class MeshInfo(C.Structure):
@@ -137,6 +138,7 @@ def lib():
             "mhd_ens_mesh_counts": [C.POINTER(MeshDesc), C.POINTER(MeshInfo)],
             "mhd_ens_mesh": [C.POINTER(MeshDesc), C.POINTER(P), C.POINTER(MeshInfo)],
             "mhd_ens_mesh_coords": [P, P, P],
+            "mhd_ens_mesh_elements": [P, P],
             "mhd_ens_mesh_free": [P],
             "mhd_ens_shared_create": [P, I, I, C.POINTER(P)],
             "mhd_ens_shared_free": [P],
@@ -207,15 +209,15 @@ def stream_ptr(stream=None):
 
 
 # ------------------------------------------------------------------ same-name wrappers
-def mhd_ens_mesh_counts(kind, nx, natural_outflow=0):
-    d = MeshDesc(kind, nx, natural_outflow)
+def mhd_ens_mesh_counts(kind, nx, natural_outflow=0, element=0):
+    d = MeshDesc(kind, nx, natural_outflow, element)
     info = MeshInfo()
     check("mhd_ens_mesh_counts", lib().mhd_ens_mesh_counts(C.byref(d), C.byref(info)))
     return info
 
 
-def mhd_ens_mesh(kind, nx, natural_outflow=0):
-    d = MeshDesc(kind, nx, natural_outflow)
+def mhd_ens_mesh(kind, nx, natural_outflow=0, element=0):
+    d = MeshDesc(kind, nx, natural_outflow, element)
     h = C.c_void_p()
     info = MeshInfo()
     check("mhd_ens_mesh", lib().mhd_ens_mesh(C.byref(d), C.byref(h), C.byref(info)))
@@ -229,6 +231,13 @@ def mhd_ens_mesh_coords(mesh, info):
     check("mhd_ens_mesh_coords", lib().mhd_ens_mesh_coords(mesh, xy.ctypes.data_as(C.c_void_p),
                                                            dn.ctypes.data_as(C.c_void_p)))
     return xy, dn[:info.n_dir].copy()
+
+
+def mhd_ens_mesh_elements(mesh, info):
+    import numpy as np
+    tri = np.zeros((info.n_el, 6), dtype=np.int32)
+    check("mhd_ens_mesh_elements", lib().mhd_ens_mesh_elements(mesh, tri.ctypes.data_as(C.c_void_p)))
+    return tri
 
 
 def mhd_ens_mesh_free(mesh):

@@ -519,6 +519,90 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 
     }
 }
 
+// -------------------------------------------------------------- (a3) right-hand sides by node gather
+// For meshes without the half-step grid (Scott-Vogelius on the Alfeld
+// refinement).  JP lanes per P2 node, the members strided over them.  A lane
+// sums, in the node's incidence order (by element), row a of the element
+// vector of every element e in which the node is local node a,
+//   r = M_e (self/dt + f) - K_e (cm other + cp self) - C_e(other - <other>) self,
+// the element arithmetic of the strip kernel, recomputed for each incident
+// node instead of accumulated: no element buffer, deterministic.  Dirichlet
+// rows take g; pressure rows (units past nP2) are zero.
+template <typename TO>
+__global__ void __launch_bounds__(kBlock) k_rhs_nodes(
+    const int32_t* __restrict__ inc_ptr, const int32_t* __restrict__ inc, const int32_t* __restrict__ tri,
+    const double* __restrict__ geo, const int32_t* __restrict__ dir_index, const double* __restrict__ self,
+    const double* __restrict__ other, const double* __restrict__ obar, const double* __restrict__ coef,
+    const double* __restrict__ F, const double* __restrict__ G, TO* __restrict__ b, int nP2, int nP1, int J, int JP,
+    double inv_dt, int convective) {
+    const Lanes L = lanes(JP);
+    if (L.unit >= (int64_t)nP2 + nP1) return;
+    const int64_t i = L.unit;
+    if (i >= nP2) {
+        for (int j = L.j0; j < J; j += JP) b[(nP2 + i) * J + j] = (TO)0;   // row 2 nP2 + (i - nP2)
+        return;
+    }
+    const int di = dir_index[i];
+    const int p0 = inc_ptr[i], p1 = inc_ptr[i + 1];
+    for (int j = L.j0; j < J; j += JP) {
+        if (di >= 0) {
+            b[(2 * i) * J + j] = (TO)G[(2 * (int64_t)di) * J + j];
+            b[(2 * i + 1) * J + j] = (TO)G[(2 * (int64_t)di + 1) * J + j];
+            continue;
+        }
+        const double cm = coef[j], cp = coef[J + j];
+        double acc0 = 0.0, acc1 = 0.0;
+        for (int p = p0; p < p1; ++p) {
+            const int e = inc[p] >> 3, a = inc[p] & 7;
+            const Geo g = load_geo(geo, e);
+            double s[6][2], ms[6][2], ks[6][2], uh[6][2];
+#pragma unroll
+            for (int bb = 0; bb < 6; ++bb) {
+                const int64_t t = tri[(int64_t)e * 6 + bb];
+                double od[2];
+#pragma unroll
+                for (int d = 0; d < 2; ++d) {
+                    const int64_t idx = (2 * t + d) * J + j;
+                    const double sv = self[idx], ov = other[idx];
+                    s[bb][d] = sv;
+                    ms[bb][d] = sv * inv_dt + (F ? F[idx] : 0.0);
+                    ks[bb][d] = cm * ov + cp * sv;
+                    od[d] = ov - obar[2 * t + d];
+                }
+                uh[bb][0] = g.det * (g.Ji[0][0] * od[0] + g.Ji[0][1] * od[1]);
+                uh[bb][1] = g.det * (g.Ji[1][0] * od[0] + g.Ji[1][1] * od[1]);
+            }
+            const double G00 = g.G[0][0], G01 = g.G[0][1], G11 = g.G[1][1];
+            double r0 = 0.0, r1 = 0.0;
+#pragma unroll
+            for (int bb = 0; bb < 6; ++bb) {
+                const double m = c_ref.Mhat[a][bb];
+                const double kk = c_ref.Kc[a][bb][0] * G00 + c_ref.Kc[a][bb][1] * G01 + c_ref.Kc[a][bb][2] * G11;
+                r0 = fma(m, ms[bb][0], fma(-kk, ks[bb][0], r0));
+                r1 = fma(m, ms[bb][1], fma(-kk, ks[bb][1], r1));
+            }
+            r0 *= g.det;
+            r1 *= g.det;
+            // convection row a: C[a][c] = sum_b T[a][b][c] . uh[b] (plain) or the
+            // antisymmetric part S (skew-symmetric form, zero diagonal)
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                double cf = 0.0;
+#pragma unroll
+                for (int bb = 0; bb < 6; ++bb)
+                    cf += convective ? c_ref.That[a][bb][c][0] * uh[bb][0] + c_ref.That[a][bb][c][1] * uh[bb][1]
+                                     : c_ref.Shat[a][bb][c][0] * uh[bb][0] + c_ref.Shat[a][bb][c][1] * uh[bb][1];
+                r0 -= cf * s[c][0];
+                r1 -= cf * s[c][1];
+            }
+            acc0 += r0;
+            acc1 += r1;
+        }
+        b[(2 * i) * J + j] = (TO)acc0;
+        b[(2 * i + 1) * J + j] = (TO)acc1;
+    }
+}
+
 // per-node partial of vbar^T M vbar (both components); partial per block
 __global__ void __launch_bounds__(kBlock) k_energy(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
                                                    const double* __restrict__ valM, const double* __restrict__ vb,
@@ -619,9 +703,25 @@ hipError_t launch_rhs_strip_t(const DevMesh& m, const mhd_coeffs& c, int J, cons
     return hipGetLastError();
 }
 
+template <typename TO>
+hipError_t launch_rhs_nodes_t(const DevMesh& m, const mhd_coeffs& c, int J, const double* self_n,
+                              const double* other_n, const double* obar, const double* coef, const double* forcing,
+                              const double* bc, TO* rhs, hipStream_t s) {
+    const int JP = pick_jp(J);
+    hipLaunchKernelGGL((k_rhs_nodes<TO>), dim3(grid_for((int64_t)m.nP2 + m.nP1, JP)), dim3(kBlock), 0, s, m.inc_ptr,
+                       m.inc, m.tri, m.geo, m.dir_index, self_n, other_n, obar, coef, forcing, bc, rhs, m.nP2, m.nP1,
+                       J, JP, 1.0 / c.dt, c.convective);
+    return hipGetLastError();
+}
+
 hipError_t launch_rhs_strip(const DevMesh& m, const mhd_coeffs& c, int J, const double* self_n, const double* other_n,
                             const double* obar, const double* coef, const double* forcing, const double* bc,
                             void* rhs, int precision, hipStream_t s) {
+    if (sv_mesh(m)) {
+        if (precision == MHD_FP32_IR)
+            return launch_rhs_nodes_t<float>(m, c, J, self_n, other_n, obar, coef, forcing, bc, (float*)rhs, s);
+        return launch_rhs_nodes_t<double>(m, c, J, self_n, other_n, obar, coef, forcing, bc, (double*)rhs, s);
+    }
     if (precision == MHD_FP32_IR)
         return launch_rhs_strip_t<float>(m, c, J, self_n, other_n, obar, coef, forcing, bc, (float*)rhs, s);
     return launch_rhs_strip_t<double>(m, c, J, self_n, other_n, obar, coef, forcing, bc, (double*)rhs, s);

@@ -751,6 +751,14 @@ mhd_status mhd_ens_mesh_coords(mhd_mesh m, double* xy_p2, int32_t* dir_nodes) tr
     return exception_status();
 }
 
+mhd_status mhd_ens_mesh_elements(mhd_mesh m, int32_t* tri) try {
+    CHECK_ARG(m && tri, "mhd_ens_mesh_elements: null argument");
+    std::memcpy(tri, m->d.host.tri.data(), sizeof(int32_t) * m->d.host.tri.size());
+    return MHD_OK;
+} catch (...) {
+    return exception_status();
+}
+
 mhd_status mhd_ens_mesh_free(mhd_mesh m) try {
     if (!m) return MHD_OK;
     free_list(m->d.allocs);
@@ -988,6 +996,10 @@ mhd_status mhd_ens_ctx_create(mhd_mesh m, const mhd_ctx_desc* d, mhd_ctx* out) t
     if (d->adjoint) {
         if (d->coeffs.convective != 0) {
             set_error("mhd_ens_ctx_create: the adjoint supports the skew-symmetric trilinear form only");
+            return fail(MHD_EINVAL);
+        }
+        if (sv_mesh(m->d)) {
+            set_error("mhd_ens_ctx_create: the adjoint is defined for Taylor-Hood meshes only");
             return fail(MHD_EINVAL);
         }
         DevMesh& D = m->d;

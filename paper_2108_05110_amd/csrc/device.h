@@ -128,6 +128,11 @@ struct DevMesh {
     std::vector<void*> allocs;
 };
 
+// Scott-Vogelius meshes (Alfeld refinement) have no half-step grid: the kernels
+// built on it (row tiles, the strip right-hand side) are replaced by CSR-only
+// and node-gather kernels there
+inline bool sv_mesh(const DevMesh& m) { return m.host.desc.element == MHD_ELEMENT_SCOTT_VOGELIUS; }
+
 struct GmresWork {
     int restart = 0;
     int64_t nrows = 0;

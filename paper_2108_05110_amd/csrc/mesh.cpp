@@ -356,6 +356,80 @@ mhd_status schur_values(HostMesh& m, double dt, double nu_c) {
 void make_ref_tables(RefTables& t) { t = build_ref_tables(); }
 
 // ---------------------------------------------------------------- mesh
+// Barycentric (Alfeld) refinement of the cell triangulation, the meshes on
+// which Section 2 places the Scott-Vogelius pair: each triangle (p0, p1, p2)
+// of a cell (lower (v00, v10, v11), then upper (v00, v11, v01)) with
+// barycentre g becomes (p0, p1, g), (p1, p2, g), (p2, p0, g), in that order.
+// Every P2 node of the refined mesh lies on the grid of sixth steps (h/6);
+// nodes are numbered row-major on that grid (y slowest).  The pressure is
+// discontinuous P1: unknown 3 e + k belongs to vertex k of element e.
+void alfeld_nodes(const Grid& g, const mhd_mesh_desc* d, HostMesh& m) {
+    const int64_t NX = 6 * (int64_t)g.nx + 1;
+    std::vector<int64_t> key;   // 6 node keys K * NX + I per element
+    for (int k = 0; k < g.ny; ++k)
+        for (int i = 0; i < g.nx; ++i) {
+            if (!g.cell(i, k)) continue;
+            const int64_t X = 6 * (int64_t)i, Y = 6 * (int64_t)k;
+            const int64_t mac[2][3][2] = {{{X, Y}, {X + 6, Y}, {X + 6, Y + 6}}, {{X, Y}, {X + 6, Y + 6}, {X, Y + 6}}};
+            for (const auto& t : mac) {
+                const int64_t gx = (t[0][0] + t[1][0] + t[2][0]) / 3, gy = (t[0][1] + t[1][1] + t[2][1]) / 3;
+                for (int s = 0; s < 3; ++s) {
+                    const int64_t ax = t[s][0], ay = t[s][1], bx = t[(s + 1) % 3][0], by = t[(s + 1) % 3][1];
+                    const int64_t pts[6][2] = {{ax, ay}, {bx, by}, {gx, gy}, {(ax + bx) / 2, (ay + by) / 2},
+                                               {(bx + gx) / 2, (by + gy) / 2}, {(gx + ax) / 2, (gy + ay) / 2}};
+                    for (const auto& q : pts) key.push_back(q[1] * NX + q[0]);
+                }
+            }
+        }
+    std::vector<int64_t> nodes(key);
+    std::sort(nodes.begin(), nodes.end());
+    nodes.erase(std::unique(nodes.begin(), nodes.end()), nodes.end());
+    const int nP2 = (int)nodes.size(), n_el = (int)(key.size() / 6);
+    m.nP2 = nP2;
+    m.n_el = n_el;
+    m.nP1 = 3 * n_el;
+    m.tri.resize(key.size());
+    for (size_t c = 0; c < key.size(); ++c)
+        m.tri[c] = (int32_t)(std::lower_bound(nodes.begin(), nodes.end(), key[c]) - nodes.begin());
+    m.tri1.resize((size_t)3 * n_el);
+    for (int c = 0; c < 3 * n_el; ++c) m.tri1[c] = c;
+    m.xy.assign((size_t)nP2 * 2, 0.0);
+    for (int id = 0; id < nP2; ++id) {
+        m.xy[2 * id] = g.x0 + (double)(nodes[id] % NX) * g.h / 6.0;
+        m.xy[2 * id + 1] = g.y0 + (double)(nodes[id] / NX) * g.h / 6.0;
+    }
+    // boundary: nodes of the element edges that belong to one element only
+    std::vector<std::pair<int64_t, int32_t>> edges;   // (vertex pair, midpoint)
+    for (int e = 0; e < n_el; ++e) {
+        const int32_t* t = &m.tri[(size_t)e * 6];
+        for (int s = 0; s < 3; ++s) {
+            const int32_t a = t[s], b = t[(s + 1) % 3];
+            edges.push_back({(int64_t)std::min(a, b) * nP2 + std::max(a, b), t[3 + s]});
+        }
+    }
+    std::sort(edges.begin(), edges.end());
+    m.bnd.assign(nP2, 0);
+    for (size_t c = 0; c < edges.size();) {
+        size_t r = c;
+        while (r < edges.size() && edges[r].first == edges[c].first) ++r;
+        if (r - c == 1) {
+            m.bnd[edges[c].first / nP2] = m.bnd[edges[c].first % nP2] = m.bnd[edges[c].second] = 1;
+        }
+        c = r;
+    }
+    m.dir.assign(nP2, 0);
+    m.p1_of_p2.assign(nP2, -1);
+    for (int id = 0; id < nP2; ++id) {
+        const bool outflow = d->natural_outflow && std::fabs(m.xy[2 * id] - m.xmax) < 1e-9 * (1 + m.xmax);
+        m.dir[id] = (m.bnd[id] && !outflow) ? 1 : 0;
+    }
+    m.dir_nodes.clear();
+    for (int i = 0; i < nP2; ++i)
+        if (m.dir[i]) m.dir_nodes.push_back(i);
+    m.hs_p2.clear();
+    m.cell_el.clear();
+}
+
 mhd_status build_mesh(const mhd_mesh_desc* d, HostMesh& m, bool full) {
     if (!d) {
         set_error("mhd_ens_mesh: null descriptor");
@@ -367,6 +441,10 @@ mhd_status build_mesh(const mhd_mesh_desc* d, HostMesh& m, bool full) {
     }
     if (d->nx < 1 || d->nx > 4096) {
         set_error("mhd_ens_mesh: nx must be in [1, 4096]");
+        return MHD_EINVAL;
+    }
+    if (d->element != MHD_ELEMENT_TAYLOR_HOOD && d->element != MHD_ELEMENT_SCOTT_VOGELIUS) {
+        set_error("mhd_ens_mesh: element must be MHD_ELEMENT_TAYLOR_HOOD or MHD_ELEMENT_SCOTT_VOGELIUS");
         return MHD_EINVAL;
     }
     if (d->kind == MHD_MESH_UNIT_SQUARE && d->natural_outflow) {
@@ -417,8 +495,20 @@ mhd_status build_mesh(const mhd_mesh_desc* d, HostMesh& m, bool full) {
     for (int k = 0; k < g.ny; ++k)
         for (int i = 0; i < g.nx; ++i) n_el += g.cell(i, k) ? 2 : 0;
     m.n_el = n_el;
+    const bool sv = d->element == MHD_ELEMENT_SCOTT_VOGELIUS;
+    if (sv) {   // each triangle adds its barycentre and three inner edge midpoints
+        m.nP2 = nP2 + 4 * n_el;
+        m.n_el = 3 * n_el;
+        m.nP1 = 3 * m.n_el;
+    }
     if (!full) return MHD_OK;
-
+    int e = 0;
+    if (sv) {
+        alfeld_nodes(g, d, m);
+        nP2 = m.nP2;
+        nP1 = m.nP1;
+        n_el = m.n_el;
+    } else {
     m.xy.assign((size_t)nP2 * 2, 0.0);
     m.bnd.assign(nP2, 0);
     m.dir.assign(nP2, 0);
@@ -445,7 +535,6 @@ mhd_status build_mesh(const mhd_mesh_desc* d, HostMesh& m, bool full) {
     m.cell_el.assign((size_t)g.nx * g.ny, -1);
     auto P = [&](int I, int K) { return pid[(size_t)K * NX + I]; };
     auto V = [&](int i, int k) { return vid[(size_t)k * (g.nx + 1) + i]; };
-    int e = 0;
     for (int k = 0; k < g.ny; ++k)
         for (int i = 0; i < g.nx; ++i) {
             if (!g.cell(i, k)) continue;
@@ -463,6 +552,7 @@ mhd_status build_mesh(const mhd_mesh_desc* d, HostMesh& m, bool full) {
             for (int a = 0; a < 3; ++a) m.tri1[(size_t)e * 3 + a] = up1[a];
             ++e;
         }
+    }
     // ---- patterns
     {
         std::vector<std::vector<int32_t>> rA(nP2), rBt(nP2), rB(nP1);
@@ -556,8 +646,23 @@ mhd_status build_mesh(const mhd_mesh_desc* d, HostMesh& m, bool full) {
     m.levels.clear();
     std::vector<std::vector<uint8_t>> fixed;
     std::vector<std::vector<int32_t>> vids;
+    const bool pinned = !(d->kind == MHD_MESH_STEP_CHANNEL && d->natural_outflow);
+    // Scott-Vogelius: the finest level is the discontinuous pressure space; the
+    // levels below it are the vertex grids of the unrefined mesh and coarser
+    const int off = sv ? 1 : 0;
+    if (sv) {
+        HostLevel L0;
+        L0.nx = g.nx;
+        L0.ny = g.ny;
+        L0.h = g.h;
+        L0.n = nP1;
+        m.levels.push_back(std::move(L0));
+        fixed.push_back(std::vector<uint8_t>(nP1, 0));
+        if (pinned) fixed[0][0] = 1;
+        vids.push_back({});
+    }
     int level = 0;
-    while (true) {
+    while (!sv || m.levels.back().n > kCoarseMax) {
         HostLevel L;
         std::vector<uint8_t> fx;
         std::vector<int32_t> vi;
@@ -581,10 +686,46 @@ mhd_status build_mesh(const mhd_mesh_desc* d, HostMesh& m, bool full) {
         return MHD_EINVAL;
     }
     m.pfix = fixed[0];
-    m.pin = -1;
-    if (!(d->kind == MHD_MESH_STEP_CHANNEL && d->natural_outflow)) m.pin = 0;
+    m.pin = pinned ? 0 : -1;
+    // Scott-Vogelius: the discontinuous space takes the continuous P1 functions of the
+    // unrefined mesh by their values at each element's vertices (1 at a vertex of the
+    // unrefined mesh, 1/3 from each vertex of the enclosing triangle at a barycentre)
+    if (sv && m.levels.size() > 1) {
+        HostLevel& F = m.levels[0];
+        const HostLevel& C = m.levels[1];
+        std::vector<std::vector<std::pair<int32_t, double>>> rows(F.n);
+        auto six = [&](int32_t node, int c) {
+            return (int64_t)std::llround((m.xy[2 * node + c] - (c ? g.y0 : g.x0)) * 6.0 / g.h);
+        };
+        auto cid = [&](int64_t I6, int64_t K6) -> int32_t {
+            const int64_t ci = I6 / 6, ck = K6 / 6;
+            if (ci < 0 || ck < 0 || ci > C.nx || ck > C.ny) return -1;
+            return vids[1][(size_t)ck * (C.nx + 1) + ci];
+        };
+        for (e = 0; e < n_el; ++e) {
+            const int32_t* t = &m.tri[(size_t)e * 6];
+            for (int k = 0; k < 3; ++k) {
+                const int32_t f = m.tri1[(size_t)e * 3 + k];
+                if (fixed[0][f]) continue;
+                std::vector<std::pair<int32_t, double>> ent;
+                if (k < 2) {   // a vertex of the unrefined mesh
+                    ent.push_back({cid(six(t[k], 0), six(t[k], 1)), 1.0});
+                } else {       // the barycentre of (p0, p1, p2) with p0, p1 the element's first two vertices
+                    const int64_t ax = six(t[0], 0), ay = six(t[0], 1), bx = six(t[1], 0), by = six(t[1], 1);
+                    const int64_t gx = six(t[2], 0), gy = six(t[2], 1);
+                    ent.push_back({cid(ax, ay), 1.0 / 3.0});
+                    ent.push_back({cid(bx, by), 1.0 / 3.0});
+                    ent.push_back({cid(3 * gx - ax - bx, 3 * gy - ay - by), 1.0 / 3.0});
+                }
+                for (auto& en : ent)
+                    if (en.first >= 0 && !fixed[1][en.first]) rows[f].push_back(en);
+            }
+        }
+        F.P = triplets_to_csr(F.n, C.n, rows);
+        F.R = transpose(F.P);
+    }
     // interpolation from level l+1 to level l: P1 interpolation on the coarse triangulation
-    for (size_t l = 0; l + 1 < m.levels.size(); ++l) {
+    for (size_t l = off; l + 1 < m.levels.size(); ++l) {
         HostLevel& F = m.levels[l];
         const HostLevel& C = m.levels[l + 1];
         std::vector<std::vector<std::pair<int32_t, double>>> rows(F.n);

@@ -3741,7 +3741,7 @@ mhd_status tune_op(DevShared& S, int J, int op, hipStream_t st, std::vector<mhd_
             cands.push_back(NodePlan{16 / word, g, 0, 4, 2});
         }
     for (int v : {2, 1}) {
-        if (!lds_vec_ok(J, word, v)) continue;
+        if (!lds_vec_ok(J, word, v) || sv_mesh(m)) continue;
         for (int id = 1; id <= kTileShapes; ++id) {
             mhd_status rc = ensure_tiling(m, id);
             if (rc) return rc;
@@ -3753,7 +3753,7 @@ mhd_status tune_op(DevShared& S, int J, int op, hipStream_t st, std::vector<mhd_
             }
         }
     }
-    if (word == 4 && op != MHD_TUNE_RESIDUAL && J % 8 == 0 && !S.transposed)
+    if (word == 4 && op != MHD_TUNE_RESIDUAL && J % 8 == 0 && !S.transposed && !sv_mesh(m))
         for (int id = 1; id <= kEllShapes; ++id) {
             mhd_status rc = ensure_ell_values(S, id, st);
             if (rc) return rc;
@@ -3866,6 +3866,10 @@ mhd_status set_plan(DevShared& S, int J, int precision, int op, int vec, int gro
     const int word = (precision == MHD_FP32_IR && op != MHD_TUNE_RESIDUAL) ? 4 : 8;
     if (op < MHD_TUNE_SADDLE || op > MHD_TUNE_JACOBI) {
         set_error("mhd_ens_set_plan: unknown operator");
+        return MHD_EINVAL;
+    }
+    if (sv_mesh(m) && (tile || deep == 3 || deep == 6)) {
+        set_error("mhd_ens_set_plan: row tiles are built on the half-step grid of Taylor-Hood meshes");
         return MHD_EINVAL;
     }
     if (deep == 6) {
