@@ -260,6 +260,7 @@ mhd_status build_device_mesh(DevMesh& D) {
         const HostLevel& H = h.levels[l];
         DevLevel& G = D.levels[l];
         G.n = H.n;
+        G.omega = H.omega;
         if ((rc = upload_csr(L, G.L, H.L))) return rc;
         if ((rc = upload(L, &G.dinv, H.dinv))) return rc;
         std::vector<float> di32(H.dinv.begin(), H.dinv.end());
@@ -349,6 +350,7 @@ mhd_status refresh_schur(DevShared& S, double dt, double nu_c) {
             set_error("refresh_schur: pattern size mismatch");
             return MHD_EINVAL;
         }
+        G.omega = H.omega;
         std::vector<float> v32(H.L.val.begin(), H.L.val.end());
         std::vector<float> d32(H.dinv.begin(), H.dinv.end());
         MHD_HIP(hipMemcpy(G.L.val, H.L.val.data(), sizeof(double) * H.L.val.size(), hipMemcpyHostToDevice));

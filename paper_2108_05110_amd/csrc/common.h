@@ -25,7 +25,9 @@ struct HostCSR {
 // One level of the pressure multigrid hierarchy (P1 Laplacian of the level's
 // triangulation, its inverse diagonal, interpolation from the next coarser
 // level and its transpose).
+constexpr double kMgOmega = 0.8;   // Jacobi damping of the pressure multigrid
 struct HostLevel {
+    double omega = kMgOmega;     // Jacobi damping of this level's sweeps
     int nx = 0, ny = 0;          // cells of this level
     double h = 0;
     int n = 0;                   // active vertices
@@ -38,7 +40,6 @@ struct HostLevel {
     HostCSR Up;                  // (n x (2n + n_coarse)) [E | E P | w D^-1] on [x2; xc; b]: prolongation
                                  // and one smoothing sweep
 };
-constexpr double kMgOmega = 0.8;   // Jacobi damping of the pressure multigrid
 
 // Structured triangulation of a union of square cells, Taylor-Hood P2/P1 numbering.
 struct HostMesh {

@@ -33,6 +33,7 @@ struct DevCSR {
 
 struct DevLevel {
     int n = 0;
+    double omega = kMgOmega;      // Jacobi damping of this level's sweeps
     DevCSR<double> L, P, R;
     DevCSR<double> Dn, Up;        // fused V-cycle halves (levels above the coarsest)
     double* dinv = nullptr;

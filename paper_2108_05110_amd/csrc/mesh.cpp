@@ -329,9 +329,33 @@ mhd_status schur_values(HostMesh& m, double dt, double nu_c) {
             for (int32_t p = L[l].L.rowptr[v]; p < L[l].L.rowptr[v + 1]; ++p)
                 if (L[l].L.col[p] == v) L[l].dinv[v] = L[l].L.val[p] != 0.0 ? 1.0 / L[l].L.val[p] : 0.0;
     }
+    // The discontinuous pressure level of Scott-Vogelius meshes has a larger
+    // spectrum of D^-1 L than the vertex grids (about 3.9 against 2), where the
+    // damping 0.8 would amplify the oscillating modes: damp it by 1.9 / lambda_max,
+    // lambda_max estimated by power iteration (deterministic start)
+    if (m.desc.element == MHD_ELEMENT_SCOTT_VOGELIUS && L.size() > 1) {
+        HostLevel& F = L[0];
+        std::vector<double> v(F.n), w(F.n);
+        for (int i = 0; i < F.n; ++i) v[i] = ((i & 1) ? -1.0 : 1.0) * (1.0 + 0.01 * (i % 13));
+        double lam = 0.0;
+        for (int it = 0; it < 60; ++it) {
+            double nv = 0.0, nw = 0.0;
+            for (int r = 0; r < F.n; ++r) {
+                double acc = 0.0;
+                for (int32_t p = F.L.rowptr[r]; p < F.L.rowptr[r + 1]; ++p) acc += F.L.val[p] * v[F.L.col[p]];
+                w[r] = F.dinv[r] * acc;
+                nv += v[r] * v[r];
+                nw += w[r] * w[r];
+            }
+            lam = std::sqrt(nw / nv);
+            const double inv = 1.0 / std::sqrt(nw);
+            for (int r = 0; r < F.n; ++r) v[r] = w[r] * inv;
+        }
+        F.omega = std::min(kMgOmega, 1.9 / lam);
+    }
     for (size_t l = 0; l + 1 < L.size(); ++l) {
         const int64_t nd = L[l].Dn.nnz(), nu = L[l].Up.nnz();
-        fused_level_ops(L[l], kMgOmega);
+        fused_level_ops(L[l], L[l].omega);
         if ((nd && nd != L[l].Dn.nnz()) || (nu && nu != L[l].Up.nnz())) {
             set_error("schur hierarchy: fused pattern changed");
             return MHD_EINVAL;

@@ -4067,7 +4067,7 @@ struct Ops {
             *out = x;
             return MHD_OK;
         }
-        const T omega = (T)kMgOmega;
+        const T omega = (T)Lv.omega;
         T* x2 = (T*)S.gw.mg_x2[l];
         T* r = (T*)S.gw.mg_r[l];
         T* bc = (T*)S.gw.mg_b[l + 1];

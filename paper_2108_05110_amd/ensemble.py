@@ -14,10 +14,15 @@ from . import _lib as L
 
 
 class Mesh:
-    def __init__(self, kind: int, nx: int, natural_outflow: int = 0):
-        self.handle, self.info = L.mhd_ens_mesh(kind, nx, natural_outflow)
+    def __init__(self, kind: int, nx: int, natural_outflow: int = 0, element: int = 0):
+        self.handle, self.info = L.mhd_ens_mesh(kind, nx, natural_outflow, element)
         self.xy, self.dir_nodes = L.mhd_ens_mesh_coords(self.handle, self.info)
-        self.kind, self.nx = kind, nx
+        self.kind, self.nx, self.element = kind, nx, element
+
+    @property
+    def tri(self):
+        """(n_el, 6) P2 connectivity of the elements (host copy)."""
+        return L.mhd_ens_mesh_elements(self.handle, self.info)
 
     @property
     def nP2(self):
