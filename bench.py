@@ -25,8 +25,10 @@ of an eager pass of the same schedule), and the FP64 CPU oracle timed on a
 bounded sample on the host.
 
 Other workloads: --workload adjoint (gradients of the ensemble-mean energy
-through 50 steps with checkpointing) and --workload large (a 512x512 ensemble
-of 128 members and four 128x128 ensembles of 16 in one graph launch).
+through 50 steps with checkpointing), --workload large (a 512x512 ensemble
+of 128 members and four 128x128 ensembles of 16 in one graph launch) and
+--workload sv (the cavity ensemble with Scott-Vogelius elements on the
+barycentric refinement of a 64x64 mesh).
 """
 from __future__ import annotations
 
@@ -702,6 +704,7 @@ def headline(args, L, wl, torch):
         "spmm_512_J128": None if args.no_large_spmm else spmm_large(L, wl, torch, plan=args.large_plan),
         "multi_ensemble": None if (args.no_multi or not graph) else multi_summary(args, L, wl, torch),
         "adjoint": None if args.no_adjoint else adjoint_summary(args, L, wl, torch),
+        "scott_vogelius": None if args.no_sv else sv_workload(args, L, wl, torch),
         "separate": separate,
         "cpu_baseline": None,
     }
@@ -900,6 +903,63 @@ def adjoint_summary(args, L, wl, torch):
             "workload": r["config"]["workload"]}
 
 
+def sv_workload(args, L, wl, torch):
+    """Scott-Vogelius elements (P2 velocity, discontinuous P1 pressure on the
+    barycentric refinement of the sv_N x sv_N unit square; Sections 2 and 4):
+    the lid-driven cavity ensemble with FP32 inner solves and FP64 refinement
+    to a relative residual rtol, eager adaptive steps (the discontinuous
+    pressure level of the Schur preconditioner converges more slowly than the
+    fixed schedule assumes).  SpMM and velocity-sweep rooflines from HIP
+    events; one-step accuracy against an FP64 solve."""
+    from paper_2108_05110_amd.ensemble import Mesh, Stepper
+    N, J = args.sv_N, args.J
+    prec = L.MHD_FP32_IR
+    opts = L.solver_opts(prec, rtol=args.rtol, jacobi_sweeps=args.sweeps, jacobi_omega=args.omega,
+                         mg_cycles=args.mg_cycles)
+    pb = wl.cavity(J=J, s=0.1, dt=0.01)
+    log(f"Scott-Vogelius {N}x{N}: mesh and autotune")
+    mesh = Mesh(L.MHD_MESH_UNIT_SQUARE, N, 0, L.MHD_ELEMENT_SCOTT_VOGELIUS)
+    plans = tuned_plans(L, wl, mesh, J, prec)
+    stp = Stepper(mesh, pb, opts=opts, time_dependent_data=False)
+    stp.step(stats=False)
+    steps = max(2, args.sv_steps)
+    elapsed = timed_steps(stp, steps)
+    st = stp.step(stats=True)
+    iters = st.v.iters + st.w.iters
+    L.mhd_ens_timer_enable(True)
+    timed_steps(stp, 1)
+    ms, launches, _, _ = L.mhd_ens_timer_read()
+    L.mhd_ens_timer_enable(False)
+    L.mhd_ens_timer_op(L.TUNE_JACOBI)
+    L.mhd_ens_timer_enable(True)
+    timed_steps(stp, 1)
+    ms_j, launches_j, _, _ = L.mhd_ens_timer_read()
+    L.mhd_ens_timer_enable(False)
+    L.mhd_ens_timer_op(L.TUNE_SADDLE)
+    stp.close()
+    log("Scott-Vogelius one-step accuracy")
+    acc = step_accuracy(L, mesh, pb, opts)
+    bpl = spmm_bytes_csr(mesh.info, J, 4)
+    avg_s = (ms / 1e3) / max(launches, 1)
+    ach = bpl / avg_s / 1e9 if launches else None
+    out = {"value": J * steps / elapsed, "unit": "member-steps/s", "ms_per_step": 1e3 * elapsed / steps,
+           "steps": steps,
+           "workload": f"lid-driven cavity, unit square {N}x{N} cells refined at the barycentres, Scott-Vogelius "
+                       f"P2-P1disc, J={J}, s=0.1, dt=0.01, FP32 inner GMRES + FP64 refinement, adaptive to rtol "
+                       f"{args.rtol:g}, eager",
+           "n_unknowns": int(mesh.n), "nnz": int(mesh.info.nnz), "krylov_iterations_per_step": iters,
+           "step_rel_l2_vs_fp64": acc,
+           "roofline": {"bound": "hbm", "kernel": f"saddle-point SpMM ({saddle_kernel_name(plans.get('saddle'))})",
+                        "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": ach / HBM_PEAK_GBS if ach else None, "bytes_per_launch": bpl,
+                        "bytes": "full saddle-point CSR: (word + 4) nnz + 4 (n + 1) + 2 word n J",
+                        "avg_launch_us": avg_s * 1e6, "launches": launches},
+           "roofline_jacobi": jacobi_roofline(mesh.info, J, 4, ms_j, launches_j, plans.get("jacobi")),
+           "autotune": plans}
+    mesh.close()
+    return out
+
+
 def multi_summary(args, L, wl, torch):
     """The multi-ensemble workload (512 x 512, J = 128 plus four 128 x 128, J = 16,
     one graph launch per step) as a sub-result of the headline run."""
@@ -987,7 +1047,7 @@ def main():
     ap.add_argument("--cgs", type=int, default=3,
                     help="Gram-Schmidt: 1 or 2 passes with the direct norm, 3 the fused single pass")
     ap.add_argument("--rtol", type=float, default=1e-10)
-    ap.add_argument("--workload", choices=["cavity", "adjoint", "large", "spmm", "step", "block", "trajectory"],
+    ap.add_argument("--workload", choices=["cavity", "adjoint", "large", "spmm", "step", "block", "trajectory", "sv"],
                     default="cavity")
     ap.add_argument("--separate-steps", type=int, default=5)
     ap.add_argument("--traj-steps", type=int, default=200,
@@ -998,6 +1058,9 @@ def main():
     ap.add_argument("--no-multi", action="store_true", help="skip the multi-ensemble sub-result")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint sub-result")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-sv", action="store_true", help="skip the Scott-Vogelius sub-result")
+    ap.add_argument("--sv-N", type=int, default=64, help="cells per side of the Scott-Vogelius workload")
+    ap.add_argument("--sv-steps", type=int, default=3, help="timed steps of the Scott-Vogelius workload")
     ap.add_argument("--plan", default="", help="pinned SpMM plan vec,group,deep,tile,waves (spmm workload; study "
                     "option for the step)")
     args = ap.parse_args()
@@ -1022,6 +1085,8 @@ def main():
         out = block_workload(args, L, wl, torch)
     elif args.workload == "trajectory":
         out = trajectory_workload(args, L, wl, torch)
+    elif args.workload == "sv":
+        out = sv_workload(args, L, wl, torch)
     else:
         if rank != 0:
             args.no_cpu_baseline = True

@@ -1454,20 +1454,23 @@ __global__ void __launch_bounds__(kBlock) k_mg(const int32_t* __restrict__ rp, c
         p0 = rp[r];
         cnt = rp[r + 1] - p0;
     }
-    int c = 0;
-    T a = 0;
-    if (h < cnt) {
-        c = col[p0 + h];
-        a = val[p0 + h];
-    }
     int nmax = 0;
 #pragma unroll
     for (int g = 0; g < RPW; ++g) nmax = max(nmax, __builtin_amdgcn_readlane(cnt, g * LPR));
     T s[V];
 #pragma unroll
     for (int q = 0; q < V; ++q) s[q] = 0;
-    if (MODE != 4) {
-        for (int t = 0; t < nmax; t += 4) {
+    // longer rows than LPR entries go in chunks of LPR (one chunk for the rows
+    // the level operators of the vertex grids have)
+    for (int base = 0; MODE != 4 && base < nmax; base += LPR) {
+        int c = 0;
+        T a = 0;
+        if (base + h < cnt) {
+            c = col[p0 + base + h];
+            a = val[p0 + base + h];
+        }
+        const int lim = min(LPR, nmax - base);
+        for (int t = 0; t < lim; t += 4) {
             T v[4][V];
             T w[4];
 #pragma unroll
@@ -1475,7 +1478,7 @@ __global__ void __launch_bounds__(kBlock) k_mg(const int32_t* __restrict__ rp, c
                 const int src = slot * LPR + min(t + i, LPR - 1);
                 const int k = __builtin_amdgcn_ds_bpermute(src << 2, c);
                 w[i] = half_bcast(a, src);
-                if (t + i >= cnt) w[i] = 0;
+                if (base + t + i >= cnt) w[i] = 0;
                 vload<T, V>(v[i], (MODE == 5 ? b : x) + (int64_t)k * J + j);
                 if (MODE == 5) {
                     const T d = omega * dinv[k];
@@ -4025,7 +4028,7 @@ struct Ops {
             const int64_t waves = (c.nrows + 3) / 4;
             hipLaunchKernelGGL((k_mg<T, MODE, 16>), dim3((unsigned)((waves + 3) / 4), J / MJ), dim3(kBlock), 0, st,
                                c.rowptr, c.col, Vals<T>::csr(c), dinv, x, b, y, (int)c.nrows, J, omega, pin);
-        } else if (J % MJ == 0 && c.max_row <= 32) {
+        } else if (J % MJ == 0) {   // rows of more than 32 entries in chunks of 32
             const int64_t waves = (c.nrows + 1) / 2;
             hipLaunchKernelGGL((k_mg<T, MODE, 32>), dim3((unsigned)((waves + 3) / 4), J / MJ), dim3(kBlock), 0, st,
                                c.rowptr, c.col, Vals<T>::csr(c), dinv, x, b, y, (int)c.nrows, J, omega, pin);
