@@ -4,7 +4,9 @@
  * The library computes one time step of the decoupled ensemble scheme for the
  * Elsasser variables v = u + sqrt(s) B, w = u - sqrt(s) B (paper, Section 1,
  * (els1)-(els3)), fully discretised as Algorithm 1 of Section 3 ((weaknew1),
- * (weaknew2)) with Taylor-Hood P2-P1 elements on structured triangulations.
+ * (weaknew2)) with Taylor-Hood P2-P1 elements on structured triangulations,
+ * or Scott-Vogelius elements (P2, discontinuous P1) on their barycentric
+ * refinement (mhd_mesh_desc.element).
  * In each step the v-subproblem and the w-subproblem have ONE coefficient
  * matrix shared by all J members (Section 1: A [x_1|...|x_J] = [b_1|...|b_J]),
  * assembled from the ensemble mean of the other variable, the mean
