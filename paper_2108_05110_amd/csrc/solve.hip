@@ -4122,7 +4122,7 @@ struct Ops {
         T* zp = z + off;
         mhd_status rc;
         T* xmg = nullptr;
-        if (mg_cycles == 2 && S.levels.size() > 1 && packed(S.levels[0].L)) {
+        if (mg_cycles == 2 && S.levels.size() > 1 && (packed(S.levels[0].L) || sv_mesh(m))) {
             // two V-cycles: x1 = V(r_p), x2 = V(r_p - L x1), z_p = -(x1 + x2)
             T* x1 = (T*)S.gw.mg_y0;
             T* res = (T*)S.gw.mg_b[0];

@@ -254,3 +254,60 @@ def test_sv_table3_errors_on_gpu(L):
         assert abs(e[0] / row[1] - 1) < 0.005 and abs(e[1] / row[2] - 1) < 0.005, (e, row)
         stp.close()
         gm.close()
+
+
+def _sv_fixed_opts(L):
+    # a fixed schedule long enough for the discontinuous pressure level's slower
+    # Schur preconditioner: three refinement cycles of 20 inner iterations
+    return L.solver_opts(L.MHD_FP32_IR, restart=20, fixed_cycles=3)
+
+
+def test_sv_graph_replay_and_group_equal_eager(L):
+    """The captured step replays bitwise what the eager step computes on a
+    Scott-Vogelius mesh, and a group launch over a Scott-Vogelius and a
+    Taylor-Hood ensemble equals their individual steps; the fixed schedule
+    stays within 1e-6 of the oracle."""
+    from paper_2108_05110_amd.ensemble import Mesh, Stepper
+    say("sv graph and group")
+    N = 8
+    pb = wl.cavity(J=5, s=0.1, dt=0.01, ic_amp=1e-2)
+    gm, om_, ens, pm2, pm1, perm = sv_pair(L, N, pb)
+    eager = Stepper(gm, pb, opts=_sv_fixed_opts(L))
+    graph = Stepper(gm, pb, opts=_sv_fixed_opts(L), graph=True)
+    V, W = pb.ic(om_.xy)
+    for n in range(3):
+        eager.step(stats=False)
+        graph.step(stats=False)
+        torch.cuda.synchronize()
+        assert torch.equal(eager.V, graph.V) and torch.equal(eager.W, graph.W), n
+        assert torch.equal(eager.Q, graph.Q) and torch.equal(eager.R, graph.R), n
+        V, W, _, _ = ens.step(V, W, (n + 1) * pb.dt, shared_lu=True)
+        Vg = np.zeros_like(V)
+        Vg[pm2] = graph.V.cpu().numpy()
+        err = mass_rel_err(ens, Vg, V)
+        say("  step", n + 1, "error against the oracle", err)
+        assert err <= 1e-6
+    eager.close()
+    graph.close()
+    th = Mesh(L.MHD_MESH_UNIT_SQUARE, N)
+    pth = wl.cavity(J=3, s=1.0, dt=0.01, ic_amp=1e-2, cfg=6)
+    ref = [Stepper(gm, pb, opts=_sv_fixed_opts(L)), Stepper(th, pth, opts=_sv_fixed_opts(L))]
+    grp = [Stepper(gm, pb, opts=_sv_fixed_opts(L)), Stepper(th, pth, opts=_sv_fixed_opts(L))]
+    for s in grp:
+        s.set_data(s.pb.dt)
+    g = L.mhd_ens_group_create([s.ctx for s in grp])
+    stream = torch.cuda.Stream()
+    for n in range(2):
+        for s in ref:
+            s.step(stats=False)
+        torch.cuda.synchronize()
+        L.mhd_ens_group_step(g, [s.V for s in grp], [s.W for s in grp], [s.Q for s in grp], [s.R for s in grp],
+                             [s.inputs() for s in grp], stream=stream)
+        stream.synchronize()
+        for r, s in zip(ref, grp):
+            assert torch.equal(r.V, s.V) and torch.equal(r.W, s.W), n
+    L.mhd_ens_group_free(g)
+    for s in ref + grp:
+        s.close()
+    th.close()
+    gm.close()
