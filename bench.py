@@ -906,24 +906,33 @@ def adjoint_summary(args, L, wl, torch):
 def sv_workload(args, L, wl, torch):
     """Scott-Vogelius elements (P2 velocity, discontinuous P1 pressure on the
     barycentric refinement of the sv_N x sv_N unit square; Sections 2 and 4):
-    the lid-driven cavity ensemble with FP32 inner solves and FP64 refinement
-    to a relative residual rtol, eager adaptive steps (the discontinuous
-    pressure level of the Schur preconditioner converges more slowly than the
-    fixed schedule assumes).  SpMM and velocity-sweep rooflines from HIP
-    events; one-step accuracy against an FP64 solve."""
+    the lid-driven cavity ensemble with FP32 inner solves and FP64 refinement,
+    graph-captured with a fixed schedule longer than the Taylor-Hood one (the
+    discontinuous pressure level of the Schur preconditioner converges more
+    slowly: 2 x 14 against 2 x 6), or adaptive eager steps to rtol.  SpMM and
+    velocity-sweep rooflines from HIP events of an eager step; one-step
+    accuracy against an FP64 solve."""
     from paper_2108_05110_amd.ensemble import Mesh, Stepper
     N, J = args.sv_N, args.J
     prec = L.MHD_FP32_IR
-    opts = L.solver_opts(prec, rtol=args.rtol, jacobi_sweeps=args.sweeps, jacobi_omega=args.omega,
-                         mg_cycles=args.mg_cycles)
+    graph = bool(args.sv_fixed)
+    if graph:   # study option: a fixed schedule "cycles,restart", graph-captured
+        cyc, rst = (int(v) for v in args.sv_fixed.split(","))
+        opts = L.solver_opts(prec, restart=rst, fixed_cycles=cyc, jacobi_sweeps=args.sweeps,
+                             jacobi_omega=args.omega, mg_cycles=args.mg_cycles, cgs_passes=args.cgs)
+    else:
+        opts = L.solver_opts(prec, rtol=args.rtol, jacobi_sweeps=args.sweeps, jacobi_omega=args.omega,
+                             mg_cycles=args.mg_cycles)
     pb = wl.cavity(J=J, s=0.1, dt=0.01)
     log(f"Scott-Vogelius {N}x{N}: mesh and autotune")
     mesh = Mesh(L.MHD_MESH_UNIT_SQUARE, N, 0, L.MHD_ELEMENT_SCOTT_VOGELIUS)
     plans = tuned_plans(L, wl, mesh, J, prec)
-    stp = Stepper(mesh, pb, opts=opts, time_dependent_data=False)
+    stp = Stepper(mesh, pb, opts=opts, time_dependent_data=False, graph=graph)
     stp.step(stats=False)
     steps = max(2, args.sv_steps)
     elapsed = timed_steps(stp, steps)
+    stp.close()
+    stp = Stepper(mesh, pb, opts=opts, time_dependent_data=False, serial=True)
     st = stp.step(stats=True)
     iters = st.v.iters + st.w.iters
     L.mhd_ens_timer_enable(True)
@@ -945,8 +954,9 @@ def sv_workload(args, L, wl, torch):
     out = {"value": J * steps / elapsed, "unit": "member-steps/s", "ms_per_step": 1e3 * elapsed / steps,
            "steps": steps,
            "workload": f"lid-driven cavity, unit square {N}x{N} cells refined at the barycentres, Scott-Vogelius "
-                       f"P2-P1disc, J={J}, s=0.1, dt=0.01, FP32 inner GMRES + FP64 refinement, adaptive to rtol "
-                       f"{args.rtol:g}, eager",
+                       f"P2-P1disc, J={J}, s=0.1, dt=0.01, FP32 inner GMRES + FP64 refinement, "
+                       + (f"hipGraph step, fixed {cyc} refinement cycles x {rst} GMRES iterations" if graph else
+                          f"adaptive to rtol {args.rtol:g}, eager") + f", {args.mg_cycles} V-cycle(s)",
            "n_unknowns": int(mesh.n), "nnz": int(mesh.info.nnz), "krylov_iterations_per_step": iters,
            "step_rel_l2_vs_fp64": acc,
            "roofline": {"bound": "hbm", "kernel": f"saddle-point SpMM ({saddle_kernel_name(plans.get('saddle'))})",
@@ -1061,6 +1071,8 @@ def main():
     ap.add_argument("--no-sv", action="store_true", help="skip the Scott-Vogelius sub-result")
     ap.add_argument("--sv-N", type=int, default=64, help="cells per side of the Scott-Vogelius workload")
     ap.add_argument("--sv-steps", type=int, default=3, help="timed steps of the Scott-Vogelius workload")
+    ap.add_argument("--sv-fixed", default="2,14", help="fixed schedule 'cycles,restart' for the Scott-Vogelius "
+                    "workload, graph-captured ('' for adaptive eager steps to --rtol)")
     ap.add_argument("--plan", default="", help="pinned SpMM plan vec,group,deep,tile,waves (spmm workload; study "
                     "option for the step)")
     args = ap.parse_args()
