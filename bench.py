@@ -919,10 +919,10 @@ def sv_workload(args, L, wl, torch):
     if graph:   # study option: a fixed schedule "cycles,restart", graph-captured
         cyc, rst = (int(v) for v in args.sv_fixed.split(","))
         opts = L.solver_opts(prec, restart=rst, fixed_cycles=cyc, jacobi_sweeps=args.sweeps,
-                             jacobi_omega=args.omega, mg_cycles=args.mg_cycles, cgs_passes=args.cgs)
+                             jacobi_omega=args.omega, mg_cycles=args.sv_mg_cycles, cgs_passes=args.cgs)
     else:
         opts = L.solver_opts(prec, rtol=args.rtol, jacobi_sweeps=args.sweeps, jacobi_omega=args.omega,
-                             mg_cycles=args.mg_cycles)
+                             mg_cycles=args.sv_mg_cycles)
     pb = wl.cavity(J=J, s=0.1, dt=0.01)
     log(f"Scott-Vogelius {N}x{N}: mesh and autotune")
     mesh = Mesh(L.MHD_MESH_UNIT_SQUARE, N, 0, L.MHD_ELEMENT_SCOTT_VOGELIUS)
@@ -956,7 +956,7 @@ def sv_workload(args, L, wl, torch):
            "workload": f"lid-driven cavity, unit square {N}x{N} cells refined at the barycentres, Scott-Vogelius "
                        f"P2-P1disc, J={J}, s=0.1, dt=0.01, FP32 inner GMRES + FP64 refinement, "
                        + (f"hipGraph step, fixed {cyc} refinement cycles x {rst} GMRES iterations" if graph else
-                          f"adaptive to rtol {args.rtol:g}, eager") + f", {args.mg_cycles} V-cycle(s)",
+                          f"adaptive to rtol {args.rtol:g}, eager") + f", {args.sv_mg_cycles} V-cycle(s)",
            "n_unknowns": int(mesh.n), "nnz": int(mesh.info.nnz), "krylov_iterations_per_step": iters,
            "step_rel_l2_vs_fp64": acc,
            "roofline": {"bound": "hbm", "kernel": f"saddle-point SpMM ({saddle_kernel_name(plans.get('saddle'))})",
@@ -1071,6 +1071,8 @@ def main():
     ap.add_argument("--no-sv", action="store_true", help="skip the Scott-Vogelius sub-result")
     ap.add_argument("--sv-N", type=int, default=64, help="cells per side of the Scott-Vogelius workload")
     ap.add_argument("--sv-steps", type=int, default=3, help="timed steps of the Scott-Vogelius workload")
+    ap.add_argument("--sv-mg-cycles", type=int, default=1, help="V-cycles per Schur-part application in the "
+                    "Scott-Vogelius workload")
     ap.add_argument("--sv-fixed", default="2,14", help="fixed schedule 'cycles,restart' for the Scott-Vogelius "
                     "workload, graph-captured ('' for adaptive eager steps to --rtol)")
     ap.add_argument("--plan", default="", help="pinned SpMM plan vec,group,deep,tile,waves (spmm workload; study "

@@ -28,6 +28,7 @@ struct HostCSR {
 constexpr double kMgOmega = 0.8;   // Jacobi damping of the pressure multigrid
 struct HostLevel {
     double omega = kMgOmega;     // Jacobi damping of this level's sweeps
+    bool dg = false;             // a discontinuous pressure level (Scott-Vogelius)
     int nx = 0, ny = 0;          // cells of this level
     double h = 0;
     int n = 0;                   // active vertices

@@ -329,12 +329,13 @@ mhd_status schur_values(HostMesh& m, double dt, double nu_c) {
             for (int32_t p = L[l].L.rowptr[v]; p < L[l].L.rowptr[v + 1]; ++p)
                 if (L[l].L.col[p] == v) L[l].dinv[v] = L[l].L.val[p] != 0.0 ? 1.0 / L[l].L.val[p] : 0.0;
     }
-    // The discontinuous pressure level of Scott-Vogelius meshes has a larger
-    // spectrum of D^-1 L than the vertex grids (about 3.9 against 2), where the
-    // damping 0.8 would amplify the oscillating modes: damp it by 1.9 / lambda_max,
-    // lambda_max estimated by power iteration (deterministic start)
-    if (m.desc.element == MHD_ELEMENT_SCOTT_VOGELIUS && L.size() > 1) {
-        HostLevel& F = L[0];
+    // The discontinuous pressure levels of Scott-Vogelius meshes have a larger
+    // spectrum of D^-1 L than the vertex grids (about 3.9 and 3.5 against 2),
+    // where the damping 0.8 would amplify the oscillating modes: damp them by
+    // 1.9 / lambda_max, lambda_max estimated by power iteration (deterministic start)
+    for (size_t l = 0; l + 1 < L.size(); ++l) {
+        HostLevel& F = L[l];
+        if (!F.dg) continue;
         std::vector<double> v(F.n), w(F.n);
         for (int i = 0; i < F.n; ++i) v[i] = ((i & 1) ? -1.0 : 1.0) * (1.0 + 0.01 * (i % 13));
         double lam = 0.0;
@@ -671,19 +672,26 @@ mhd_status build_mesh(const mhd_mesh_desc* d, HostMesh& m, bool full) {
     std::vector<std::vector<uint8_t>> fixed;
     std::vector<std::vector<int32_t>> vids;
     const bool pinned = !(d->kind == MHD_MESH_STEP_CHANNEL && d->natural_outflow);
-    // Scott-Vogelius: the finest level is the discontinuous pressure space; the
-    // levels below it are the vertex grids of the unrefined mesh and coarser
-    const int off = sv ? 1 : 0;
+    // Scott-Vogelius: the finest levels are discontinuous pressure spaces, on the
+    // refinement (level 0, the pressure space itself) and on the unrefined mesh
+    // (level 1: linear on each unrefined triangle, 3 unknowns each); the levels
+    // below are the vertex grids of the unrefined mesh and their coarsenings
+    int off = 0;
     if (sv) {
-        HostLevel L0;
-        L0.nx = g.nx;
-        L0.ny = g.ny;
-        L0.h = g.h;
-        L0.n = nP1;
-        m.levels.push_back(std::move(L0));
-        fixed.push_back(std::vector<uint8_t>(nP1, 0));
-        if (pinned) fixed[0][0] = 1;
-        vids.push_back({});
+        for (int q = 0; q < 2; ++q) {
+            if (q == 1 && m.levels.back().n <= kCoarseMax) break;
+            HostLevel Ld;
+            Ld.nx = g.nx;
+            Ld.ny = g.ny;
+            Ld.h = g.h;
+            Ld.n = q == 0 ? nP1 : nP1 / 3;
+            Ld.dg = true;
+            m.levels.push_back(std::move(Ld));
+            fixed.push_back(std::vector<uint8_t>(m.levels.back().n, 0));
+            if (pinned) fixed.back()[0] = 1;
+            vids.push_back({});
+            ++off;
+        }
     }
     int level = 0;
     while (!sv || m.levels.back().n > kCoarseMax) {
@@ -711,39 +719,42 @@ mhd_status build_mesh(const mhd_mesh_desc* d, HostMesh& m, bool full) {
     }
     m.pfix = fixed[0];
     m.pin = pinned ? 0 : -1;
-    // Scott-Vogelius: the discontinuous space takes the continuous P1 functions of the
-    // unrefined mesh by their values at each element's vertices (1 at a vertex of the
-    // unrefined mesh, 1/3 from each vertex of the enclosing triangle at a barycentre)
+    // Scott-Vogelius transfers, exact for functions linear on each unrefined triangle:
+    //   level 1 -> 0: an element vertex takes the value at that vertex of the unrefined
+    //     triangle (1 at its vertices, 1/3 of each at the barycentre);
+    //   vertex grid -> level 1: each unrefined triangle takes its vertex values.
+    // Element e = 3 E + s of the refinement is (p_s, p_{s+1}, g) in unrefined triangle E.
     if (sv && m.levels.size() > 1) {
         HostLevel& F = m.levels[0];
-        const HostLevel& C = m.levels[1];
         std::vector<std::vector<std::pair<int32_t, double>>> rows(F.n);
-        auto six = [&](int32_t node, int c) {
-            return (int64_t)std::llround((m.xy[2 * node + c] - (c ? g.y0 : g.x0)) * 6.0 / g.h);
-        };
-        auto cid = [&](int64_t I6, int64_t K6) -> int32_t {
-            const int64_t ci = I6 / 6, ck = K6 / 6;
-            if (ci < 0 || ck < 0 || ci > C.nx || ck > C.ny) return -1;
-            return vids[1][(size_t)ck * (C.nx + 1) + ci];
-        };
         for (e = 0; e < n_el; ++e) {
-            const int32_t* t = &m.tri[(size_t)e * 6];
+            const int E = e / 3, sub = e % 3;
             for (int k = 0; k < 3; ++k) {
                 const int32_t f = m.tri1[(size_t)e * 3 + k];
                 if (fixed[0][f]) continue;
                 std::vector<std::pair<int32_t, double>> ent;
-                if (k < 2) {   // a vertex of the unrefined mesh
-                    ent.push_back({cid(six(t[k], 0), six(t[k], 1)), 1.0});
-                } else {       // the barycentre of (p0, p1, p2) with p0, p1 the element's first two vertices
-                    const int64_t ax = six(t[0], 0), ay = six(t[0], 1), bx = six(t[1], 0), by = six(t[1], 1);
-                    const int64_t gx = six(t[2], 0), gy = six(t[2], 1);
-                    ent.push_back({cid(ax, ay), 1.0 / 3.0});
-                    ent.push_back({cid(bx, by), 1.0 / 3.0});
-                    ent.push_back({cid(3 * gx - ax - bx, 3 * gy - ay - by), 1.0 / 3.0});
-                }
+                if (k < 2)
+                    ent.push_back({3 * E + (sub + k) % 3, 1.0});
+                else
+                    for (int q = 0; q < 3; ++q) ent.push_back({3 * E + q, 1.0 / 3.0});
                 for (auto& en : ent)
-                    if (en.first >= 0 && !fixed[1][en.first]) rows[f].push_back(en);
+                    if (!fixed[1][en.first]) rows[f].push_back(en);
             }
+        }
+        F.P = triplets_to_csr(F.n, m.levels[1].n, rows);
+        F.R = transpose(F.P);
+    }
+    if (sv && m.levels.size() > 2) {
+        HostLevel& F = m.levels[1];
+        const HostLevel& C = m.levels[2];
+        std::vector<std::vector<std::pair<int32_t, double>>> rows(F.n);
+        for (int f = 0; f < F.n; ++f) {
+            if (fixed[1][f]) continue;
+            const int32_t node = m.tri[(size_t)f * 6];   // vertex 0 of element f = vertex f % 3 of triangle f / 3
+            const int64_t ci = std::llround((m.xy[2 * node] - g.x0) / g.h);
+            const int64_t ck = std::llround((m.xy[2 * node + 1] - g.y0) / g.h);
+            const int32_t c = vids[2][(size_t)ck * (C.nx + 1) + ci];
+            if (c >= 0 && !fixed[2][c]) rows[f].push_back({c, 1.0});
         }
         F.P = triplets_to_csr(F.n, C.n, rows);
         F.R = transpose(F.P);

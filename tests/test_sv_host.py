@@ -38,8 +38,9 @@ def _read(exe, N, tmp_path):
     xy = np.frombuffer(raw[o:o + 16 * nP2], dtype=np.float64).reshape(nP2, 2); o += 16 * nP2
     tri = np.frombuffer(raw[o:o + 24 * n_el], dtype=np.int32).reshape(n_el, 6); o += 24 * n_el
     dirf = np.frombuffer(raw[o:o + nP2], dtype=np.uint8); o += nP2
-    pv = np.frombuffer(raw[o:o + 8 * nP1], dtype=np.float64)
-    return dict(nP2=nP2, nP1=nP1, n_el=n_el, levels=levels, pin=pin, xy=xy, tri=tri, dir=dirf, pv=pv)
+    pv = np.frombuffer(raw[o:o + 8 * nP1], dtype=np.float64); o += 8 * nP1
+    pv1 = np.frombuffer(raw[o:o + 8 * (nP1 // 3)], dtype=np.float64)
+    return dict(nP2=nP2, nP1=nP1, n_el=n_el, levels=levels, pin=pin, xy=xy, tri=tri, dir=dirf, pv=pv, pv1=pv1)
 
 
 def _keys(xy, h):
@@ -70,10 +71,17 @@ def test_sv_mesh_matches_the_oracle_refinement(dump_exe, tmp_path, N):
     assert set(map(tuple, np.array(kl)[lib["dir"] == 1])) == set(kr[i] for i in ref.bnd)
     # the pin: pressure unknown 0, at vertex 0 of element 0, the corner (0, 0)
     assert lib["pin"] == 0 and kl[lib["tri"][0, 0]] == (0, 0)
-    # interpolation from the vertex grid into the discontinuous space: exact for
-    # x + 2y at every element vertex (the pinned unknown's row is empty)
+    # the hierarchy's transfers are exact for x + 2y (the pinned unknowns' rows,
+    # and the columns of pinned coarse unknowns, are empty): unrefined triangles ->
+    # every element vertex, and vertex grid -> the unrefined triangles' vertices
+    pxy = lib["xy"][lib["tri"][:, :3]].reshape(-1, 2)
+    want = pxy[:, 0] + 2 * pxy[:, 1]
     if lib["levels"] > 1:
-        pxy = lib["xy"][lib["tri"][:, :3]].reshape(-1, 2)
-        want = pxy[:, 0] + 2 * pxy[:, 1]
         assert lib["pv"][0] == 0.0
         assert np.abs(lib["pv"][1:] - want[1:]).max() < 1e-13
+    if lib["levels"] > 2:
+        w1 = lib["xy"][lib["tri"][:, 0]]          # vertex 0 of element 3E + q: vertex q of triangle E
+        w1 = w1[:, 0] + 2 * w1[:, 1]
+        assert lib["pv1"][0] == 0.0
+        assert np.abs(lib["pv1"][1:] - w1[1:]).max() < 1e-13
+    assert lib["levels"] == {4: 1, 8: 2, 16: 3}[N]
