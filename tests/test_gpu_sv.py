@@ -311,3 +311,39 @@ def test_sv_graph_replay_and_group_equal_eager(L):
         s.close()
     th.close()
     gm.close()
+
+
+def test_sv_step_channel_natural_outflow(L):
+    """Scott-Vogelius on the refined step channel (cells missing under the step,
+    h = 1, do-nothing outflow, so no pressure pin), J = 3, two FP64 steps against
+    the oracle: velocities to 1e-10, pressures as they are to 1e-7."""
+    from paper_2108_05110_amd.ensemble import Mesh, Stepper
+    say("sv step channel")
+    m = 1
+    pb = wl.step_channel(J=3, delta=0.1, s=0.01, dt=0.02, nsteps=2)
+    gm = Mesh(L.MHD_MESH_STEP_CHANNEL, m, 1, L.MHD_ELEMENT_SCOTT_VOGELIUS)
+    om_ = om.alfeld(om.step_channel(m))
+    ens = scheme.Ensemble(om_, pb)
+    assert ens.pin is None and gm.info.pin == -1
+    h = 1.0 / m
+    ko = {k: i for i, k in enumerate(_key(om_.xy, h))}
+    pm2 = np.array([ko[k] for k in _key(gm.xy, h)])
+    eo = {tuple(t[:3]): e for e, t in enumerate(om_.tri)}
+    emap = np.array([eo[tuple(pm2[t[:3]])] for t in gm.tri])
+    pm1 = (3 * emap[:, None] + np.arange(3)[None, :]).ravel()
+    assert len(gm.dir_nodes) == len(ens.dnodes)
+    stp = Stepper(gm, pb, opts=L.solver_opts(L.MHD_FP64))
+    V, W = pb.ic(om_.xy)
+    for n in range(2):
+        st = stp.step()
+        V, W, Q, R = ens.step(V, W, (n + 1) * pb.dt, shared_lu=True)
+        Vg = np.zeros_like(V)
+        Vg[pm2] = stp.V.cpu().numpy()
+        Qg = np.zeros_like(Q)
+        Qg[pm1] = stp.Q.cpu().numpy()
+        e = mass_rel_err(ens, Vg, V)
+        say("  step", n + 1, "iters", st.v.iters, st.w.iters, "err", e)
+        assert e <= 1e-10
+        assert np.abs(Qg - Q).max() <= 1e-7 * np.abs(Q).max()
+    stp.close()
+    gm.close()
