@@ -726,7 +726,7 @@ __global__ void __launch_bounds__(kBlock) k_velo_p(const int32_t* __restrict__ r
 // half (ds_bpermute) and the load is a buffer load with that offset.  Rows are
 // padded with zero values to the longer row of the pair; entries are consumed
 // in CSR order, so the arithmetic matches the other kernels.
-constexpr int kPairRow = 32;   // longest row the paired kernels accept
+constexpr int kPairRow = 32;   // entries of a row the paired kernels take per chunk
 
 struct PairLanes {
     int half, c, j;
@@ -893,6 +893,20 @@ __device__ __forceinline__ void pair_row(const HalfRow<T, PAIR>& R, int n, int h
     });
 }
 
+// pair_row over rows of any length: entries in chunks of kPairRow (one chunk,
+// the same operations, for rows of at most kPairRow entries)
+template <typename T, int V, bool PAIR, bool NEG>
+__device__ __forceinline__ void pair_row_long(const int32_t* __restrict__ col, const T* __restrict__ val, int32_t p0,
+                                              int32_t p1, unsigned row_bytes, unsigned base_bytes, int half, int c,
+                                              __amdgpu_buffer_rsrc_t xr, unsigned lane_off, T (&acc)[V]) {
+    const int cnt = p1 - p0;
+    const int n = max(__builtin_amdgcn_readlane(cnt, 0), __builtin_amdgcn_readlane(cnt, 32));
+    for (int b = 0; b < n; b += kPairRow) {
+        const HalfRow<T, PAIR> R = half_row<T, PAIR>(col, val, p0 + b, p1, row_bytes, base_bytes);
+        pair_row<T, V, PAIR, NEG>(R, min(kPairRow, n - b), half, c, xr, lane_off, acc);
+    }
+}
+
 // y = S x (MODE 0) or y = b - S x (MODE 1)
 template <typename T, int MODE, int G>
 __global__ void __launch_bounds__(kBlock) k_saddle_h(const int32_t* __restrict__ Arp, const int32_t* __restrict__ Acol,
@@ -919,12 +933,9 @@ __global__ void __launch_bounds__(kBlock) k_saddle_h(const int32_t* __restrict__
 #pragma unroll
         for (int q = 0; q < V; ++q) acc[q] = 0;
         if (u < nP2) {
-            const HalfRow<T, false> RA = half_row<T, false>(Acol, Aval, Arp[u], Arp[u + 1], vrow, 0);
-            const HalfRow<T, true> RB = half_row<T, true>(Btcol, Btval, Btrp[u], Btrp[u + 1], J * W, pbase);
-            const int na = max(__builtin_amdgcn_readlane(RA.cnt, 0), __builtin_amdgcn_readlane(RA.cnt, 32));
-            const int nb = max(__builtin_amdgcn_readlane(RB.cnt, 0), __builtin_amdgcn_readlane(RB.cnt, 32));
-            pair_row<T, V, false, false>(RA, na, L.half, L.c, xr, lane_v, acc);
-            pair_row<T, V, true, false>(RB, nb, L.half, L.c, xr, lane_p, acc);
+            pair_row_long<T, V, false, false>(Acol, Aval, Arp[u], Arp[u + 1], vrow, 0, L.half, L.c, xr, lane_v, acc);
+            pair_row_long<T, V, true, false>(Btcol, Btval, Btrp[u], Btrp[u + 1], J * W, pbase, L.half, L.c, xr,
+                                             lane_p, acc);
             const int64_t o = (2 * (int64_t)u + L.c) * J + L.j;
             if (MODE == 1) {
                 T bv[V];
@@ -935,9 +946,7 @@ __global__ void __launch_bounds__(kBlock) k_saddle_h(const int32_t* __restrict__
             if (!L.half || has_b) vstore<T, V>(y + o, acc);
         } else {
             const int k = u - nP2;
-            const HalfRow<T, true> RB = half_row<T, true>(Bcol, Bval, Brp[k], Brp[k + 1], vrow, 0);
-            const int nb = max(__builtin_amdgcn_readlane(RB.cnt, 0), __builtin_amdgcn_readlane(RB.cnt, 32));
-            pair_row<T, V, true, false>(RB, nb, L.half, L.c, xr, lane_v, acc);
+            pair_row_long<T, V, true, false>(Bcol, Bval, Brp[k], Brp[k + 1], vrow, 0, L.half, L.c, xr, lane_v, acc);
 #pragma unroll
             for (int r = 0; r < V; ++r) acc[r] += __shfl_xor(acc[r], 16, 64);   // the two components
             if (L.c == 0 && (!L.half || has_b)) {
@@ -983,11 +992,9 @@ __global__ void __launch_bounds__(kBlock) k_velo_h(const int32_t* __restrict__ r
         const T dw = omega * dinvA[i];
         const int64_t o = (2 * (int64_t)i + L.c) * J + L.j;
         T acc[V];
-        const HalfRow<T, FIRST> R = half_row<T, FIRST>(col, val, rp[i], rp[i + 1], row_bytes, 0);
-        const int n = max(__builtin_amdgcn_readlane(R.cnt, 0), __builtin_amdgcn_readlane(R.cnt, 32));
         if constexpr (FIRST) {
             vload<T, V>(acc, in + o);   // r_u
-            pair_row<T, V, true, true>(R, n, L.half, L.c, xr, lane_off, acc);
+            pair_row_long<T, V, true, true>(col, val, rp[i], rp[i + 1], row_bytes, 0, L.half, L.c, xr, lane_off, acc);
             if (store) vstore<T, V>(t + o, acc);
 #pragma unroll
             for (int q = 0; q < V; ++q) acc[q] *= dw;
@@ -995,7 +1002,8 @@ __global__ void __launch_bounds__(kBlock) k_velo_h(const int32_t* __restrict__ r
         } else {
 #pragma unroll
             for (int q = 0; q < V; ++q) acc[q] = 0;
-            pair_row<T, V, false, false>(R, n, L.half, L.c, xr, lane_off, acc);
+            pair_row_long<T, V, false, false>(col, val, rp[i], rp[i + 1], row_bytes, 0, L.half, L.c, xr, lane_off,
+                                              acc);
             T tv[V], zv[V];
             vload<T, V>(tv, t + o);
             vload<T, V>(zv, z + o);
@@ -1067,17 +1075,21 @@ __global__ void __launch_bounds__(kBlock) k_velo_h2(const int32_t* __restrict__ 
         const bool store = !L.half || has_b;
         const T dw = omega * dinvA[i];
         const int64_t o = (2 * (int64_t)i + L.c) * J + L.j;
-        HalfRow<T, false> R = half_row<T, false>(col, val, rp[i], rp[i + 1], 2u * J * W, 0);
-        {   // the entry's scale w D^-1 of its column, in the unused second value
-            const int h = threadIdx.x & 31;
-            R.v1 = h < R.cnt ? omega * dinvA[col[rp[i] + h]] : (T)0;
-        }
-        const int n = max(__builtin_amdgcn_readlane(R.cnt, 0), __builtin_amdgcn_readlane(R.cnt, 32));
         T acc[V], tv[V];
         vload<T, V>(tv, t + o);
 #pragma unroll
         for (int q = 0; q < V; ++q) acc[q] = 0;
-        pair_row_scaled<T, V>(R, n, L.half, tr, lane_off, acc);
+        const int32_t p0 = rp[i], p1 = rp[i + 1];
+        const int cnt = p1 - p0;
+        const int n = max(__builtin_amdgcn_readlane(cnt, 0), __builtin_amdgcn_readlane(cnt, 32));
+        for (int b = 0; b < n; b += kPairRow) {   // rows longer than kPairRow in chunks
+            HalfRow<T, false> R = half_row<T, false>(col, val, p0 + b, p1, 2u * J * W, 0);
+            {   // the entry's scale w D^-1 of its column, in the unused second value
+                const int h = threadIdx.x & 31;
+                R.v1 = h < R.cnt ? omega * dinvA[col[p0 + b + h]] : (T)0;
+            }
+            pair_row_scaled<T, V>(R, min(kPairRow, n - b), L.half, tr, lane_off, acc);
+        }
 #pragma unroll
         for (int q = 0; q < V; ++q) {
             const T zv = mul_rn(tv[q], dw);
@@ -3458,7 +3470,8 @@ mhd_status with_gd(int g, F f) {
 inline bool deep_ok(const DevMesh& m) { return m.max_row <= kDeepA && m.max_row_bt <= kDeepBt; }
 
 // paired-row kernels: J a multiple of 16 members per lane-load, short rows
-inline bool pair_ok(const DevMesh& m, int J, int word) { return m.max_row <= kPairRow && J % (256 / word) == 0; }
+// rows longer than kPairRow go in chunks (Scott-Vogelius meshes); Taylor-Hood rows fit one
+inline bool pair_ok(const DevMesh& m, int J, int word) { return J % (256 / word) == 0; }
 
 template <typename F>
 mhd_status with_gp(int g, F f) {
@@ -3896,8 +3909,7 @@ mhd_status set_plan(DevShared& S, int J, int precision, int op, int vec, int gro
     }
     if (deep == 2) {
         if (tile || !(group == 4 || group == 8) || !pair_ok(m, J, word)) {
-            set_error("mhd_ens_set_plan: paired rows need group 4 or 8, J a multiple of 256 / word size and rows of "
-                      "<= 32 entries");
+            set_error("mhd_ens_set_plan: paired rows need group 4 or 8 and J a multiple of 256 / word size");
             return MHD_EINVAL;
         }
         mhd_status rc = ensure_pair_sched(m, group);

@@ -347,3 +347,66 @@ def test_sv_step_channel_natural_outflow(L):
         assert np.abs(Qg - Q).max() <= 1e-7 * np.abs(Q).max()
     stp.close()
     gm.close()
+
+
+@pytest.mark.parametrize("precision,J", [(1, 64), (0, 32)])
+def test_sv_every_plan(L, precision, J):
+    """Every kernel plan a Scott-Vogelius mesh admits (CSR-only: rows of up to 37
+    velocity and 36 divergence entries, taken in chunks by the paired and packed
+    kernels) gives the SpMM of the host-rebuilt operator, the planned kernels
+    agree bitwise, and a solve takes the same iterates with every plan."""
+    from paper_2108_05110_amd.ensemble import Mesh, to_dev
+    say("sv plans", precision, J)
+    pb = wl.cavity(J=J, s=0.1, dt=0.01)
+    gm = Mesh(L.MHD_MESH_UNIT_SQUARE, 6, 0, L.MHD_ELEMENT_SCOTT_VOGELIUS)
+    V, W = pb.ic(gm.xy)
+    W = W + 0.05 * np.random.default_rng(0).standard_normal(W.shape)
+    A = L.mhd_ens_shared_create(gm.handle, J, 30)
+    c = L.Coeffs(pb.dt, pb.mu, float(pb.nu.mean()), float(pb.nu_m.mean()), 0)
+    L.mhd_ens_assemble_shared(gm.handle, c, to_dev(W), J, A)
+    S = csr_from_view(torch, L.mhd_ens_shared_csr(A))
+    word = 4 if precision == 1 else 8
+    dt = torch.float32 if word == 4 else torch.float64
+    x = torch.from_numpy(np.random.default_rng(1).standard_normal((gm.n, J))).to("cuda", dt)
+    ref = S @ x.double().cpu().numpy()
+    tol = 2e-6 if word == 4 else 1e-14
+    plans = []
+    for v in [v for v in ((4, 2, 1) if word == 4 else (2, 1)) if J % (32 * v) == 0]:
+        plans += [(v, g, 0, 0, 4) for g in (0, 1, 2, 4)] + [(v, g, 1, 0, 4) for g in (1, 2, 4, 8)]
+    plans += [(16 // word, g, 2, 0, 4) for g in (4, 8)]
+    with pytest.raises(RuntimeError):          # row tiles need the half-step grid
+        L.mhd_ens_set_plan(A, J, precision, L.TUNE_SADDLE, 1, 0, 0, 8, 4)
+    usable, outs = [], {}
+    for plan in plans:
+        try:
+            L.mhd_ens_set_plan(A, J, precision, L.TUNE_SADDLE, *plan)
+        except RuntimeError as e:
+            assert "need" in str(e), str(e)    # a plan this mesh's rows do not admit
+            continue
+        y = torch.full((gm.n, J), float("nan"), dtype=dt, device="cuda")
+        L.mhd_ens_spmm(A, x, y, J, precision)
+        torch.cuda.synchronize()
+        err = np.abs(y.double().cpu().numpy() - ref).max() / np.abs(ref).max()
+        say("  plan", plan, "err", err)
+        assert err <= tol, (plan, err)
+        usable.append(plan)
+        outs[plan] = y
+    assert any(p[2] == 2 for p in usable)     # the paired kernels take the long rows
+    base = outs[usable[0]]
+    for k, y in outs.items():
+        assert torch.equal(y, base), k
+    b = torch.from_numpy(np.random.default_rng(3).standard_normal((gm.n, J))).cuda()
+    res = {}
+    for plan in usable:
+        for op in (L.TUNE_SADDLE, L.TUNE_JACOBI_FIRST, L.TUNE_JACOBI):
+            L.mhd_ens_set_plan(A, J, precision, op, *plan)
+        L.mhd_ens_set_plan(A, J, precision, L.TUNE_RESIDUAL, min(plan[0], 2), *plan[1:])
+        xs = torch.zeros((gm.n, J), dtype=torch.float64, device="cuda")
+        st, _ = L.mhd_ens_solve(A, b, xs, J, L.solver_opts(precision, rtol=1e-10))
+        say("  solve plan", plan, "iters", st.iters)
+        res[plan] = (xs, st.iters)
+    x0, it0 = res[usable[0]]
+    for k, (xs, it) in res.items():
+        assert it == it0 and torch.equal(xs, x0), k
+    L.mhd_ens_shared_free(A)
+    gm.close()
