@@ -528,7 +528,10 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 
 // the element arithmetic of the strip kernel, recomputed for each incident
 // node instead of accumulated: no element buffer, deterministic.  Dirichlet
 // rows take g; pressure rows (units past nP2) are zero.
-template <typename TO>
+// WAVE (J > 32): one node per wavefront, JP = 64, so that the node, its
+// incidences and each element's local index are uniform and the reference
+// tables are read with scalar loads
+template <typename TO, bool WAVE>
 __global__ void __launch_bounds__(kBlock) k_rhs_nodes(
     const int32_t* __restrict__ inc_ptr, const int32_t* __restrict__ inc, const int32_t* __restrict__ tri,
     const double* __restrict__ geo, const int32_t* __restrict__ dir_index, const double* __restrict__ self,
@@ -536,14 +539,15 @@ __global__ void __launch_bounds__(kBlock) k_rhs_nodes(
     const double* __restrict__ F, const double* __restrict__ G, TO* __restrict__ b, int nP2, int nP1, int J, int JP,
     double inv_dt, int convective) {
     const Lanes L = lanes(JP);
-    if (L.unit >= (int64_t)nP2 + nP1) return;
-    const int64_t i = L.unit;
+    const int64_t i = WAVE ? (int64_t)__builtin_amdgcn_readfirstlane((int)L.unit) : L.unit;
+    if (i >= (int64_t)nP2 + nP1) return;
     if (i >= nP2) {
         for (int j = L.j0; j < J; j += JP) b[(nP2 + i) * J + j] = (TO)0;   // row 2 nP2 + (i - nP2)
         return;
     }
-    const int di = dir_index[i];
-    const int p0 = inc_ptr[i], p1 = inc_ptr[i + 1];
+    auto uni = [](int v) { return WAVE ? __builtin_amdgcn_readfirstlane(v) : v; };
+    const int di = uni(dir_index[i]);
+    const int p0 = uni(inc_ptr[i]), p1 = uni(inc_ptr[i + 1]);
     for (int j = L.j0; j < J; j += JP) {
         if (di >= 0) {
             b[(2 * i) * J + j] = (TO)G[(2 * (int64_t)di) * J + j];
@@ -553,7 +557,8 @@ __global__ void __launch_bounds__(kBlock) k_rhs_nodes(
         const double cm = coef[j], cp = coef[J + j];
         double acc0 = 0.0, acc1 = 0.0;
         for (int p = p0; p < p1; ++p) {
-            const int e = inc[p] >> 3, a = inc[p] & 7;
+            const int ea = uni(inc[p]);
+            const int e = ea >> 3, a = ea & 7;
             const Geo g = load_geo(geo, e);
             double s[6][2], ms[6][2], ks[6][2], uh[6][2];
 #pragma unroll
@@ -707,10 +712,14 @@ template <typename TO>
 hipError_t launch_rhs_nodes_t(const DevMesh& m, const mhd_coeffs& c, int J, const double* self_n,
                               const double* other_n, const double* obar, const double* coef, const double* forcing,
                               const double* bc, TO* rhs, hipStream_t s) {
-    const int JP = pick_jp(J);
-    hipLaunchKernelGGL((k_rhs_nodes<TO>), dim3(grid_for((int64_t)m.nP2 + m.nP1, JP)), dim3(kBlock), 0, s, m.inc_ptr,
-                       m.inc, m.tri, m.geo, m.dir_index, self_n, other_n, obar, coef, forcing, bc, rhs, m.nP2, m.nP1,
-                       J, JP, 1.0 / c.dt, c.convective);
+    if (J > 32)
+        hipLaunchKernelGGL((k_rhs_nodes<TO, true>), dim3(grid_for((int64_t)m.nP2 + m.nP1, 64)), dim3(kBlock), 0, s,
+                           m.inc_ptr, m.inc, m.tri, m.geo, m.dir_index, self_n, other_n, obar, coef, forcing, bc, rhs,
+                           m.nP2, m.nP1, J, 64, 1.0 / c.dt, c.convective);
+    else
+        hipLaunchKernelGGL((k_rhs_nodes<TO, false>), dim3(grid_for((int64_t)m.nP2 + m.nP1, pick_jp(J))), dim3(kBlock),
+                           0, s, m.inc_ptr, m.inc, m.tri, m.geo, m.dir_index, self_n, other_n, obar, coef, forcing,
+                           bc, rhs, m.nP2, m.nP1, J, pick_jp(J), 1.0 / c.dt, c.convective);
     return hipGetLastError();
 }
 
