@@ -909,7 +909,7 @@ def sv_workload(args, L, wl, torch):
     the lid-driven cavity ensemble with FP32 inner solves and FP64 refinement,
     graph-captured with a fixed schedule longer than the Taylor-Hood one (the
     discontinuous pressure level of the Schur preconditioner converges more
-    slowly: 2 x 14 against 2 x 6), or adaptive eager steps to rtol.  SpMM and
+    slowly: 4 x 7 against 2 x 6), or adaptive eager steps to rtol.  SpMM and
     velocity-sweep rooflines from HIP events of an eager step; one-step
     accuracy against an FP64 solve."""
     from paper_2108_05110_amd.ensemble import Mesh, Stepper
@@ -1073,7 +1073,7 @@ def main():
     ap.add_argument("--sv-steps", type=int, default=3, help="timed steps of the Scott-Vogelius workload")
     ap.add_argument("--sv-mg-cycles", type=int, default=1, help="V-cycles per Schur-part application in the "
                     "Scott-Vogelius workload")
-    ap.add_argument("--sv-fixed", default="2,14", help="fixed schedule 'cycles,restart' for the Scott-Vogelius "
+    ap.add_argument("--sv-fixed", default="4,7", help="fixed schedule 'cycles,restart' for the Scott-Vogelius "
                     "workload, graph-captured ('' for adaptive eager steps to --rtol)")
     ap.add_argument("--plan", default="", help="pinned SpMM plan vec,group,deep,tile,waves (spmm workload; study "
                     "option for the step)")
