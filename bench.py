@@ -946,8 +946,9 @@ def sv_workload(args, L, wl, torch):
     L.mhd_ens_timer_enable(False)
     L.mhd_ens_timer_op(L.TUNE_SADDLE)
     stp.close()
-    log("Scott-Vogelius one-step accuracy")
+    log("Scott-Vogelius one-step accuracy and 8-step trajectory against FP64")
     acc = step_accuracy(L, mesh, pb, opts)
+    traj, _ = multi_step_error(L, mesh, pb, opts, (8,))
     bpl = spmm_bytes_csr(mesh.info, J, 4)
     avg_s = (ms / 1e3) / max(launches, 1)
     ach = bpl / avg_s / 1e9 if launches else None
@@ -958,7 +959,7 @@ def sv_workload(args, L, wl, torch):
                        + (f"hipGraph step, fixed {cyc} refinement cycles x {rst} GMRES iterations" if graph else
                           f"adaptive to rtol {args.rtol:g}, eager") + f", {args.sv_mg_cycles} V-cycle(s)",
            "n_unknowns": int(mesh.n), "nnz": int(mesh.info.nnz), "krylov_iterations_per_step": iters,
-           "step_rel_l2_vs_fp64": acc,
+           "step_rel_l2_vs_fp64": acc, "rel_l2_vs_fp64_after_8_steps": traj.get(8),
            "roofline": {"bound": "hbm", "kernel": f"saddle-point SpMM ({saddle_kernel_name(plans.get('saddle'))})",
                         "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": ach / HBM_PEAK_GBS if ach else None, "bytes_per_launch": bpl,

@@ -410,3 +410,26 @@ def test_sv_every_plan(L, precision, J):
         assert it == it0 and torch.equal(xs, x0), k
     L.mhd_ens_shared_free(A)
     gm.close()
+
+
+def test_sv_bench_schedule_against_the_oracle(L):
+    """The bench's Scott-Vogelius schedule (FP32 inner solves, four refinement
+    cycles of 7 iterations, graph-captured) on the refined 16 x 16 cavity, J = 5,
+    four steps from the initial state: every step within 1e-6 of the oracle."""
+    from paper_2108_05110_amd.ensemble import Stepper
+    say("sv bench schedule")
+    pb = wl.cavity(J=5, s=0.1, dt=0.01, ic_amp=1e-2)
+    gm, om_, ens, pm2, pm1, perm = sv_pair(L, 16, pb)
+    stp = Stepper(gm, pb, opts=L.solver_opts(L.MHD_FP32_IR, restart=7, fixed_cycles=4), graph=True)
+    V, W = pb.ic(om_.xy)
+    for n in range(4):
+        stp.step(stats=False)
+        V, W, _, _ = ens.step(V, W, (n + 1) * pb.dt, shared_lu=True)
+        Vg, Wg = np.zeros_like(V), np.zeros_like(W)
+        Vg[pm2] = stp.V.cpu().numpy()
+        Wg[pm2] = stp.W.cpu().numpy()
+        e = (mass_rel_err(ens, Vg, V), mass_rel_err(ens, Wg, W))
+        say("  step", n + 1, "error against the oracle", e)
+        assert max(e) <= 1e-6, e
+    stp.close()
+    gm.close()
