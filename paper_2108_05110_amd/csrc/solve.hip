@@ -4057,7 +4057,8 @@ struct Ops {
     // One V(2,2)-cycle with damped Jacobi smoothing on level l for L_l x = b.
     // Uses the level's buffers x, x2, r and the next level's b and x.  Returns
     // the buffer holding the result in *out.
-    mhd_status vcycle(int l, const T* b, T** out, T* schur = nullptr, int pin = -1) {
+    // dest (level 0, no schur): the buffer the last sweep writes instead of the level's x2
+    mhd_status vcycle(int l, const T* b, T** out, T* schur = nullptr, int pin = -1, T* dest = nullptr) {
         const DevLevel& Lv = S.levels[l];
         T* x = (T*)S.gw.mg_x[l];
         mhd_status rc;
@@ -4121,8 +4122,9 @@ struct Ops {
             *out = schur;
             return MHD_OK;
         }
-        if ((rc = csr<3>(Lv.L, dinv, x, b, x2, omega))) return rc;
-        *out = x2;
+        T* fin = dest ? dest : x2;
+        if ((rc = csr<3>(Lv.L, dinv, x, b, fin, omega))) return rc;
+        *out = fin;
         return MHD_OK;
     }
 
@@ -4139,8 +4141,7 @@ struct Ops {
             T* x1 = (T*)S.gw.mg_y0;
             T* res = (T*)S.gw.mg_b[0];
             const DevLevel& L0 = S.levels[0];
-            if ((rc = vcycle(0, vp, &xmg))) return rc;
-            MHD_HIP(hipMemcpyAsync(x1, xmg, sizeof(T) * (size_t)L0.n * J, hipMemcpyDeviceToDevice, st));
+            if ((rc = vcycle(0, vp, &xmg, nullptr, -1, x1))) return rc;   // the first cycle ends in x1
             if ((rc = csr<2>(L0.L, Vals<T>::dinv(L0), x1, vp, res, (T)kMgOmega))) return rc;
             if ((rc = vcycle(0, res, &xmg))) return rc;
             hipLaunchKernelGGL((k_schur2<T>), dim3(ew_grid((int64_t)m.nP1 * J)), dim3(kBlock), 0, st, (const T*)x1,
