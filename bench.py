@@ -28,7 +28,8 @@ Other workloads: --workload adjoint (gradients of the ensemble-mean energy
 through 50 steps with checkpointing), --workload large (a 512x512 ensemble
 of 128 members and four 128x128 ensembles of 16 in one graph launch) and
 --workload sv (the cavity ensemble with Scott-Vogelius elements on the
-barycentric refinement of a 64x64 mesh).
+barycentric refinement of a 64x64 mesh) and --workload channel (the step
+channel at h = 1/16 with 64 members).
 """
 from __future__ import annotations
 
@@ -705,6 +706,7 @@ def headline(args, L, wl, torch):
         "multi_ensemble": None if (args.no_multi or not graph) else multi_summary(args, L, wl, torch),
         "adjoint": None if args.no_adjoint else adjoint_summary(args, L, wl, torch),
         "scott_vogelius": None if args.no_sv else sv_workload(args, L, wl, torch),
+        "step_channel": None if (args.no_channel or not graph) else channel_workload(args, L, wl, torch),
         "separate": separate,
         "cpu_baseline": None,
     }
@@ -971,6 +973,53 @@ def sv_workload(args, L, wl, torch):
     return out
 
 
+def channel_workload(args, L, wl, torch):
+    """The step channel [0,30]x[0,10] minus the unit step (Section 4.4 setting)
+    at h = 1/channel_m with a do-nothing outflow, J members, FP32 inner solves
+    with FP64 refinement on the bench's fixed schedule, graph-captured: step
+    throughput, the SpMM roofline from HIP events of an eager step (the operands
+    exceed the last-level cache), and one-step accuracy against FP64."""
+    from paper_2108_05110_amd.ensemble import Mesh, Stepper
+    m, J = args.channel_m, args.J
+    opts = L.solver_opts(L.MHD_FP32_IR, restart=args.restart, fixed_cycles=args.cycles, jacobi_sweeps=args.sweeps,
+                         jacobi_omega=args.omega, mg_cycles=args.mg_cycles, cgs_passes=args.cgs)
+    pb = wl.step_channel(J=J, delta=1e-2, s=0.01, dt=0.02)
+    log(f"step channel h=1/{m}: mesh and autotune")
+    mesh = Mesh(L.MHD_MESH_STEP_CHANNEL, m, 1)
+    plans = tuned_plans(L, wl, mesh, J, L.MHD_FP32_IR)
+    stp = Stepper(mesh, pb, opts=opts, time_dependent_data=False, graph=True)
+    stp.step(stats=False)
+    steps = max(2, args.channel_steps)
+    elapsed = timed_steps(stp, steps)
+    stp.close()
+    eag = Stepper(mesh, pb, opts=opts, time_dependent_data=False, serial=True)
+    eag.step(stats=False)
+    L.mhd_ens_timer_enable(True)
+    timed_steps(eag, 1)
+    ms, launches, _, _ = L.mhd_ens_timer_read()
+    L.mhd_ens_timer_enable(False)
+    eag.close()
+    log("step channel one-step accuracy")
+    acc = step_accuracy(L, mesh, pb, opts)
+    bpl = spmm_bytes_csr(mesh.info, J, 4)
+    avg_s = (ms / 1e3) / max(launches, 1)
+    ach = bpl / avg_s / 1e9 if launches else None
+    out = {"value": J * steps / elapsed, "unit": "member-steps/s", "ms_per_step": 1e3 * elapsed / steps,
+           "steps": steps,
+           "workload": f"step channel [0,30]x[0,10] minus [0,1]x[0,1], h=1/{m}, do-nothing outflow, Taylor-Hood "
+                       f"P2-P1, J={J}, s=0.01, dt=0.02, nu=1/600, FP32 inner GMRES + FP64 refinement, hipGraph step, "
+                       f"fixed {args.cycles} refinement cycles x {args.restart} GMRES iterations",
+           "n_unknowns": int(mesh.n), "nnz": int(mesh.info.nnz), "step_rel_l2_vs_fp64": acc,
+           "roofline": {"bound": "hbm", "kernel": f"saddle-point SpMM ({saddle_kernel_name(plans.get('saddle'))})",
+                        "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": ach / HBM_PEAK_GBS if ach else None, "bytes_per_launch": bpl,
+                        "bytes": "full saddle-point CSR: (word + 4) nnz + 4 (n + 1) + 2 word n J",
+                        "avg_launch_us": avg_s * 1e6, "launches": launches},
+           "autotune": plans}
+    mesh.close()
+    return out
+
+
 def multi_summary(args, L, wl, torch):
     """The multi-ensemble workload (512 x 512, J = 128 plus four 128 x 128, J = 16,
     one graph launch per step) as a sub-result of the headline run."""
@@ -1058,7 +1107,8 @@ def main():
     ap.add_argument("--cgs", type=int, default=3,
                     help="Gram-Schmidt: 1 or 2 passes with the direct norm, 3 the fused single pass")
     ap.add_argument("--rtol", type=float, default=1e-10)
-    ap.add_argument("--workload", choices=["cavity", "adjoint", "large", "spmm", "step", "block", "trajectory", "sv"],
+    ap.add_argument("--workload", choices=["cavity", "adjoint", "large", "spmm", "step", "block", "trajectory", "sv",
+                                           "channel"],
                     default="cavity")
     ap.add_argument("--separate-steps", type=int, default=5)
     ap.add_argument("--traj-steps", type=int, default=200,
@@ -1070,6 +1120,9 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint sub-result")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sv", action="store_true", help="skip the Scott-Vogelius sub-result")
+    ap.add_argument("--no-channel", action="store_true", help="skip the step-channel sub-result")
+    ap.add_argument("--channel-m", type=int, default=16, help="cells per unit length of the step channel")
+    ap.add_argument("--channel-steps", type=int, default=3, help="timed steps of the step-channel workload")
     ap.add_argument("--sv-N", type=int, default=64, help="cells per side of the Scott-Vogelius workload")
     ap.add_argument("--sv-steps", type=int, default=3, help="timed steps of the Scott-Vogelius workload")
     ap.add_argument("--sv-mg-cycles", type=int, default=1, help="V-cycles per Schur-part application in the "
@@ -1102,6 +1155,8 @@ def main():
         out = trajectory_workload(args, L, wl, torch)
     elif args.workload == "sv":
         out = sv_workload(args, L, wl, torch)
+    elif args.workload == "channel":
+        out = channel_workload(args, L, wl, torch)
     else:
         if rank != 0:
             args.no_cpu_baseline = True
