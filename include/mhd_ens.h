@@ -399,8 +399,8 @@ mhd_status mhd_ens_spmm(mhd_shared A, const void* x, void* y, int J, int precisi
  *             entries, B^T rows of at most 8);
  *     deep  = 2: paired rows (group 4 or 8): the two halves of a wavefront
  *             compute two rows at once with 16-byte member loads (J a
- *             multiple of 64 for FP32, 32 for FP64; rows of at most 32
- *             entries); vec is then 16 / word size;
+ *             multiple of 64 for FP32, 32 for FP64; a row's entries in
+ *             chunks of 32); vec is then 16 / word size;
  *   LDS-staged kernels (J a multiple of 32; each workgroup first copies the
  *   node values of a square tile of rows, and its halo, into LDS):
  *     tile  = tile edge in half-steps of the mesh: 8, 12 or 16, where the
