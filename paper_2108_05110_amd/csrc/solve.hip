@@ -4036,7 +4036,7 @@ struct Ops {
     template <int MODE>
     mhd_status csr(const DevCSR<double>& c, const T* dinv, const T* x, const T* b, T* y, T omega, int pin = -1) {
         constexpr int MJ = 256 / (int)sizeof(T);
-        if (J % MJ == 0 && c.max_row <= 16) {
+        if (J % MJ == 0 && (c.max_row <= 16 || c.max_row > 32)) {   // rows over 32 entries: chunks of 16
             const int64_t waves = (c.nrows + 3) / 4;
             hipLaunchKernelGGL((k_mg<T, MODE, 16>), dim3((unsigned)((waves + 3) / 4), J / MJ), dim3(kBlock), 0, st,
                                c.rowptr, c.col, Vals<T>::csr(c), dinv, x, b, y, (int)c.nrows, J, omega, pin);
