@@ -1442,7 +1442,7 @@ __global__ void __launch_bounds__(kBlock) k_ell_scatter(const float* __restrict_
 // lane V = 256 / (LPR sizeof(T)) consecutive members, so one load instruction
 // fetches 64 / LPR member rows of a tile of MJ = 256 / sizeof(T) members.
 // Lane h of a row's group first loads the row's h-th column and value; they
-// are broadcast with ds_bpermute.  Rows of at most LPR entries.
+// are broadcast with ds_bpermute.  Longer rows than LPR entries go in chunks of LPR.
 // MODE 0: y = A x ; 1: y += A x ; 2: y = b - A x ; 3: y = x + w dinv (b - A x) ;
 // 4: y = w dinv b ; 5: the two first Jacobi sweeps from a zero guess,
 // y = x1 + w dinv (b - A x1) with x1 = w dinv b formed on the fly (x unused);
@@ -1472,8 +1472,7 @@ __global__ void __launch_bounds__(kBlock) k_mg(const int32_t* __restrict__ rp, c
     T s[V];
 #pragma unroll
     for (int q = 0; q < V; ++q) s[q] = 0;
-    // longer rows than LPR entries go in chunks of LPR (one chunk for the rows
-    // the level operators of the vertex grids have)
+    // longer rows than LPR entries go in chunks of LPR
     for (int base = 0; MODE != 4 && base < nmax; base += LPR) {
         int c = 0;
         T a = 0;
@@ -4036,13 +4035,13 @@ struct Ops {
     template <int MODE>
     mhd_status csr(const DevCSR<double>& c, const T* dinv, const T* x, const T* b, T* y, T omega, int pin = -1) {
         constexpr int MJ = 256 / (int)sizeof(T);
-        if (J % MJ == 0 && (c.max_row <= 16 || c.max_row > 32)) {   // rows over 32 entries: chunks of 16
+        if (J % MJ == 0) {
+            // 16 lanes per row, four rows per wavefront, 16-byte member loads; rows
+            // of more than 16 entries in chunks of 16 (faster than 32 lanes per row
+            // for the 17-entry vertex-grid rows as for the 66-entry discontinuous
+            // ones, with the same operations in the same order)
             const int64_t waves = (c.nrows + 3) / 4;
             hipLaunchKernelGGL((k_mg<T, MODE, 16>), dim3((unsigned)((waves + 3) / 4), J / MJ), dim3(kBlock), 0, st,
-                               c.rowptr, c.col, Vals<T>::csr(c), dinv, x, b, y, (int)c.nrows, J, omega, pin);
-        } else if (J % MJ == 0) {   // rows of more than 32 entries in chunks of 32
-            const int64_t waves = (c.nrows + 1) / 2;
-            hipLaunchKernelGGL((k_mg<T, MODE, 32>), dim3((unsigned)((waves + 3) / 4), J / MJ), dim3(kBlock), 0, st,
                                c.rowptr, c.col, Vals<T>::csr(c), dinv, x, b, y, (int)c.nrows, J, omega, pin);
         } else if constexpr (MODE == 6) {
             return MHD_EINVAL;   // callers check packed() first
