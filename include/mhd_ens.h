@@ -96,8 +96,8 @@ typedef struct mhd_ctx_s*    mhd_ctx;
  *     row-major order; pressure unknown 3 e + k belongs to vertex k of
  *     element e (nP1 = 3 n_el).  The velocity divergence then lies in the
  *     pressure space, so discrete solutions are divergence-free pointwise.
- *     Kernel plans with row tiles (tile != 0) and the adjoint calls are
- *     defined for Taylor-Hood meshes only (MHD_EINVAL). */
+ *     Kernel plans with row tiles (tile != 0) are defined for Taylor-Hood
+ *     meshes only (MHD_EINVAL). */
 typedef struct {
     int kind;
     int nx;

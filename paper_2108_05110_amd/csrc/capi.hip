@@ -1000,10 +1000,6 @@ mhd_status mhd_ens_ctx_create(mhd_mesh m, const mhd_ctx_desc* d, mhd_ctx* out) t
             set_error("mhd_ens_ctx_create: the adjoint supports the skew-symmetric trilinear form only");
             return fail(MHD_EINVAL);
         }
-        if (sv_mesh(m->d)) {
-            set_error("mhd_ens_ctx_create: the adjoint is defined for Taylor-Hood meshes only");
-            return fail(MHD_EINVAL);
-        }
         DevMesh& D = m->d;
         size_t vb = 2 * (size_t)D.nP2 * d->J_max;
         for (double** p : {&c->Tv, &c->Tv1, &c->Tw, &c->Tw1, &c->Kmv, &c->Kmw})

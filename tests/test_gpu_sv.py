@@ -433,3 +433,41 @@ def test_sv_bench_schedule_against_the_oracle(L):
         assert max(e) <= 1e-6, e
     stp.close()
     gm.close()
+
+
+def test_sv_adjoint_matches_cpu_adjoint(L):
+    """The discrete adjoint (gradients of the ensemble-mean energy after three
+    steps with respect to nu_j, nu_m,j, the forcing amplitudes and the initial
+    mode coefficients) on the refined 3 x 3 mesh: the GPU through
+    torch.autograd against the FP64 CPU adjoint, which central differences
+    of the oracle pin on this mesh (tests/test_oracle_sv.py)."""
+    from oracle.adjoint import EnsembleAdjoint
+    from paper_2108_05110_amd.autograd import EnsembleEnergy, Rollout
+    from paper_2108_05110_amd.ensemble import Mesh
+    from workloads import modes_and_forcing
+    say("sv adjoint vs CPU adjoint")
+    J, N, nsteps = 3, 3, 3
+    pb = wl.cavity(J=J, s=0.3, dt=0.05, nsteps=nsteps, nu_mean=0.01, num_mean=0.02, ic_amp=0.3)
+    r = np.random.default_rng(11)
+    nu = 0.01 * (1 + r.uniform(-0.1, 0.1, J))
+    num = 0.02 * (1 + r.uniform(-0.1, 0.1, J))
+    a = r.uniform(0.5, 1.5, J)
+    coef = 0.3 * r.uniform(-1, 1, (J, 8))
+    pb.nu, pb.nu_m = nu.copy(), num.copy()
+    gm = Mesh(L.MHD_MESH_UNIT_SQUARE, N, 0, L.MHD_ELEMENT_SCOTT_VOGELIUS)
+    modes, fhat = modes_and_forcing(gm.xy)
+    ro = Rollout(gm, pb, modes, fhat, opts=L.solver_opts(L.MHD_FP64), checkpoint_every=2)
+    p = torch.tensor(np.column_stack([nu, num, a, coef]), dtype=torch.float64, device="cuda").requires_grad_(True)
+    phi = EnsembleEnergy.apply(p, ro)
+    phi.backward()
+    g_gpu = p.grad.cpu().numpy()
+    ms = om.alfeld(om.unit_square(N))
+    m2, f2 = modes_and_forcing(ms.xy)
+    phi_c, g, gc = EnsembleAdjoint(ms, pb, f2, m2).gradient(nu, num, a, coef, nsteps)
+    g_cpu = np.column_stack([g, gc])
+    err = np.abs(g_gpu - g_cpu).max() / np.abs(g_cpu).max()
+    say("  phi", float(phi), phi_c, "max rel grad diff", err)
+    assert abs(float(phi) - phi_c) <= 1e-11 * abs(phi_c)
+    assert err <= 1e-8, err
+    ro.close()
+    gm.close()

@@ -177,3 +177,28 @@ def test_table6_temporal_sv():
     e = np.array(e)
     rates = np.log2(e[:-1] / e[1:])
     assert np.all(rates > 0.9) and np.all(rates < 1.1), rates
+
+
+def test_adjoint_on_the_refined_mesh_matches_central_differences():
+    """The oracle's discrete adjoint on a Scott-Vogelius mesh (refined 3 x 3,
+    J = 3, three steps) against central differences of its forward map."""
+    from oracle.adjoint import EnsembleAdjoint, central_fd
+    from workloads import modes_and_forcing
+    J = 3
+    pb = wl.cavity(J=J, s=0.3, dt=0.05, nu_mean=0.01, num_mean=0.02, ic_amp=0.3)
+    ms = om.alfeld(om.unit_square(3))
+    modes, fhat = modes_and_forcing(ms.xy)
+    adj = EnsembleAdjoint(ms, pb, fhat, modes)
+    r = np.random.default_rng(11)
+    nu = 0.01 * (1 + r.uniform(-0.1, 0.1, J))
+    num = 0.02 * (1 + r.uniform(-0.1, 0.1, J))
+    a = r.uniform(0.5, 1.5, J)
+    coef = 0.3 * r.uniform(-1, 1, (J, 8))
+    phi, g, gc = adj.gradient(nu, num, a, coef, 3)
+    for j in range(J):
+        for col, which in enumerate(("nu", "num", "a")):
+            fd = central_fd(adj, nu, num, a, coef, 3, which, j)
+            assert abs(g[j, col] - fd) <= 1e-6 * abs(fd), (which, j, g[j, col], fd)
+        for m in (0, 5):
+            fd = central_fd(adj, nu, num, a, coef, 3, ("coef", m), j)
+            assert abs(gc[j, m] - fd) <= 1e-6 * max(abs(fd), 1e-3 * np.abs(gc).max()), (m, j, gc[j, m], fd)
