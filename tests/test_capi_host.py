@@ -66,3 +66,40 @@ def test_null_handles_rejected_without_device():
     assert lib.mhd_ens_step(None, None, None, None, None, None, None, None) == L.MHD_EINVAL
     assert lib.mhd_ens_mesh_free(None) == L.MHD_OK
     assert b"null" in lib.mhd_ens_last_error()
+
+
+def _patterns(ms):
+    """Distinct P2-P2 pairs and pressure-P2 pairs that share an element."""
+    aa, bb = set(), set()
+    for e, t in enumerate(ms.tri):
+        for a in t:
+            for b in t:
+                aa.add((a, b))
+            for k in ms.ptri[e]:
+                bb.add((k, a))
+    return len(aa), len(bb)
+
+
+@pytest.mark.parametrize("kind,nx,outflow", [(0, 2, 0), (0, 4, 0), (0, 8, 0), (1, 1, 1), (1, 2, 0)])
+def test_scott_vogelius_counts_match_the_oracle_refinement(kind, nx, outflow):
+    """Counts of the library's Scott-Vogelius meshes (built on the host) against
+    the oracle's barycentric refinement: elements, nodes, discontinuous pressure
+    unknowns, the P2 and divergence patterns, boundary and Dirichlet nodes."""
+    from oracle import mesh as om
+    i = L.mhd_ens_mesh_counts(kind, nx, outflow, L.MHD_ELEMENT_SCOTT_VOGELIUS)
+    base = om.unit_square(nx) if kind == 0 else om.step_channel(nx)
+    ms = om.alfeld(base)
+    assert (i.n_el, i.nP2, i.nP1, i.n) == (ms.n_el, ms.nP2, ms.nP1, ms.n)
+    assert i.nP1 == 3 * i.n_el
+    nA, nB = _patterns(ms)
+    assert (i.nnz_A, i.nnz_B) == (nA, nB)
+    assert i.nnz == 2 * i.nnz_A + 4 * i.nnz_B + (1 if i.pin >= 0 else 0)
+    assert i.n_bd == len(ms.bnd)
+    assert i.pin == (-1 if outflow else 0)
+    if not outflow:
+        assert i.n_dir == i.n_bd
+
+
+def test_scott_vogelius_rejects_an_unknown_element():
+    with pytest.raises(RuntimeError):
+        L.mhd_ens_mesh_counts(L.MHD_MESH_UNIT_SQUARE, 4, 0, 7)
