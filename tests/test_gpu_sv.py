@@ -471,3 +471,28 @@ def test_sv_adjoint_matches_cpu_adjoint(L):
     assert err <= 1e-8, err
     ro.close()
     gm.close()
+
+
+def test_sv_bench_configuration_J64_one_step_vs_oracle(L):
+    """The bench's Scott-Vogelius kernels at J = 64 (paired rows in chunks, the
+    16-lane multigrid sweeps in chunks, the wavefront-per-node right-hand sides)
+    on the refined 32 x 32 cavity: one graph-captured step with the bench's
+    4 x 7 schedule from the initial state against the oracle for members 0, 31
+    and 63 (the ensemble statistics over all 64), bar 1e-6."""
+    from paper_2108_05110_amd.ensemble import Stepper
+    say("sv J=64 bench configuration vs oracle")
+    pb = wl.cavity(J=64, s=0.1, dt=0.01)
+    gm, om_, ens, pm2, pm1, perm = sv_pair(L, 32, pb)
+    stp = Stepper(gm, pb, opts=L.solver_opts(L.MHD_FP32_IR, restart=7, fixed_cycles=4), graph=True)
+    stp.step(stats=False)
+    members = [0, 31, 63]
+    V0, W0 = pb.ic(om_.xy)
+    V1, W1, _, _ = ens.step(V0, W0, pb.dt, shared_lu=True, members=members)
+    for Zg, Zo in ((stp.V, V1), (stp.W, W1)):
+        Z = np.zeros((om_.nP2, 2, len(members)))
+        Z[pm2] = Zg.cpu().numpy()[:, :, members]
+        e = mass_rel_err(ens, Z, Zo)
+        say("  error against the oracle", e)
+        assert e <= 1e-6, e
+    stp.close()
+    gm.close()
