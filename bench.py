@@ -921,10 +921,11 @@ def sv_workload(args, L, wl, torch):
     if graph:   # study option: a fixed schedule "cycles,restart", graph-captured
         cyc, rst = (int(v) for v in args.sv_fixed.split(","))
         opts = L.solver_opts(prec, restart=rst, fixed_cycles=cyc, jacobi_sweeps=args.sweeps,
-                             jacobi_omega=args.omega, mg_cycles=args.sv_mg_cycles, cgs_passes=args.cgs)
+                             jacobi_omega=args.omega, mg_cycles=args.sv_mg_cycles, cgs_passes=args.cgs,
+                             mg_post=args.sv_mg_post)
     else:
         opts = L.solver_opts(prec, rtol=args.rtol, jacobi_sweeps=args.sweeps, jacobi_omega=args.omega,
-                             mg_cycles=args.sv_mg_cycles)
+                             mg_cycles=args.sv_mg_cycles, mg_post=args.sv_mg_post)
     pb = wl.cavity(J=J, s=0.1, dt=0.01)
     log(f"Scott-Vogelius {N}x{N}: mesh and autotune")
     mesh = Mesh(L.MHD_MESH_UNIT_SQUARE, N, 0, L.MHD_ELEMENT_SCOTT_VOGELIUS)
@@ -1127,6 +1128,8 @@ def main():
     ap.add_argument("--sv-steps", type=int, default=3, help="timed steps of the Scott-Vogelius workload")
     ap.add_argument("--sv-mg-cycles", type=int, default=1, help="V-cycles per Schur-part application in the "
                     "Scott-Vogelius workload")
+    ap.add_argument("--sv-mg-post", type=int, default=0, help="extra post-smoothing sweeps on the finest pressure "
+                    "level in the Scott-Vogelius workload")
     ap.add_argument("--sv-fixed", default="4,7", help="fixed schedule 'cycles,restart' for the Scott-Vogelius "
                     "workload, graph-captured ('' for adaptive eager steps to --rtol)")
     ap.add_argument("--plan", default="", help="pinned SpMM plan vec,group,deep,tile,waves (spmm workload; study "
