@@ -2,7 +2,8 @@
 
 This package is test infrastructure only.  It is a plain, slow, direct
 implementation of Algorithm 1 of the paper (Section 3, equations (weaknew1) and
-(weaknew2)) with Taylor-Hood P2-P1 elements: its own mesher, its own
+(weaknew2)) with Taylor-Hood P2-P1 elements (Scott-Vogelius on barycentre-refined
+meshes, and tetrahedral Taylor-Hood in 3D, as options): its own mesher, its own
 quadrature-based FE assembly, and every member's saddle-point system solved
 with its own sparse direct LU.  It shares no code with the GPU library; only
 the seeded problem data of ``workloads`` feeds both.  Only ``tests/``,
@@ -11,6 +12,7 @@ it; the product path never does.
 
 Modules:
   mesh    -- structured triangulations and P2/P1 node numbering
+  tet     -- tetrahedral meshes of the unit cube, quadrature and P2/P1 bases (3D)
   fem     -- quadrature, P2/P1 bases, element integrals, global matrices
   scheme  -- Algorithm 1 (ensemble means, eddy viscosity, shared matrix,
              per-member right-hand sides, per-member LU solves)

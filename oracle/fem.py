@@ -85,14 +85,22 @@ class Element:
 
     def __init__(self, mesh):
         self.mesh = mesh
-        lam, self.w = quad7()
-        self.phi = p2_values(lam)                       # (7, 6)
-        self.psi = lam.copy()                           # (7, 3)
-        self.area, gl = geometry(mesh.xy, mesh.tri)
-        dbary = p2_bary_grads(lam)                      # (7, 6, 3)
+        self.d = d = getattr(mesh, "dim", 2)
+        if d == 2:
+            lam, self.w = quad7()
+            self.phi = p2_values(lam)                       # (7, 6)
+            self.area, gl = geometry(mesh.xy, mesh.tri)
+            dbary = p2_bary_grads(lam)                      # (7, 6, 3)
+        else:   # tetrahedra (oracle.tet): "area" is the volume
+            from .tet import geometry3, p2_bary_grads3, p2_values3, tet_rule
+            lam, self.w = tet_rule()
+            self.phi = p2_values3(lam)                      # (Q, 10)
+            self.area, gl = geometry3(mesh.xy, mesh.tri)
+            dbary = p2_bary_grads3(lam)                     # (Q, 10, 4)
+        self.psi = lam.copy()                               # P1: the barycentric coordinates
         self.dphi = np.einsum('qai,eid->eqad', dbary, gl)
-        verts = mesh.xy[mesh.tri[:, :3]]                # (n_el, 3, 2)
-        self.xq = np.einsum('qi,eid->eqd', lam, verts)  # (n_el, 7, 2)
+        verts = mesh.xy[mesh.tri[:, :d + 1]]                # (n_el, d+1, d)
+        self.xq = np.einsum('qi,eid->eqd', lam, verts)      # (n_el, Q, d)
 
     # -------- fields at quadrature points
     def values(self, nodal):
@@ -117,8 +125,8 @@ class Element:
         return self._scatter(ke, self.mesh.tri, self.mesh.tri, (n, n))
 
     def stiffness(self, kappa=None):
-        """sum_q w_q kappa_q grad phi_a . grad phi_b |T|; kappa (n_el, 7) or None (= 1)."""
-        wq = self.w[None, :] * (np.ones((self.mesh.n_el, 7)) if kappa is None else kappa)
+        """sum_q w_q kappa_q grad phi_a . grad phi_b |T|; kappa (n_el, Q) or None (= 1)."""
+        wq = self.w[None, :] * (np.ones((self.mesh.n_el, len(self.w))) if kappa is None else kappa)
         ke = np.einsum('e,eq,eqad,eqbd->eab', self.area, wq, self.dphi, self.dphi)
         n = self.mesh.nP2
         return self._scatter(ke, self.mesh.tri, self.mesh.tri, (n, n))
@@ -140,23 +148,30 @@ class Element:
         return self._scatter(ke, self.mesh.tri, self.mesh.tri, (n, n))
 
     def divergence(self):
-        """B (nP1, 2 nP2): B[k, 2i+c] = -(psi_k, d phi_i / d x_c), psi_k the
+        """B (nP1, d nP2): B[k, d i + c] = -(psi_k, d phi_i / d x_c), psi_k the
         pressure basis function (continuous or, on an Alfeld mesh, per element)."""
+        d = self.d
         ke = -np.einsum('e,q,qk,eqic->ekic', self.area, self.w, self.psi, self.dphi)
-        ne = self.mesh.n_el
-        rows = np.repeat(self.mesh.ptri[:, :, None, None], 6, axis=2).repeat(2, axis=3)
-        cols = 2 * self.mesh.tri[:, None, :, None] + np.arange(2)[None, None, None, :]
-        cols = np.broadcast_to(cols, (ne, 3, 6, 2))
+        ne, nloc, npl = self.mesh.n_el, self.mesh.tri.shape[1], self.mesh.ptri.shape[1]
+        rows = np.repeat(self.mesh.ptri[:, :, None, None], nloc, axis=2).repeat(d, axis=3)
+        cols = d * self.mesh.tri[:, None, :, None] + np.arange(d)[None, None, None, :]
+        cols = np.broadcast_to(cols, (ne, npl, nloc, d))
         return sp.coo_matrix((ke.ravel(), (rows.ravel(), cols.ravel())),
-                             shape=(self.mesh.nP1, 2 * self.mesh.nP2)).tocsr()
+                             shape=(self.mesh.nP1, d * self.mesh.nP2)).tocsr()
 
     def p1_mass_lumped(self):
-        """m_k = integral of psi_k (exact: |T|/3 per element)."""
+        """m_k = integral of psi_k (exact: |T|/(d+1) per element)."""
         m = np.zeros(self.mesh.nP1)
-        np.add.at(m, self.mesh.ptri.ravel(), np.repeat(self.area / 3.0, 3))
+        k = self.mesh.ptri.shape[1]
+        np.add.at(m, self.mesh.ptri.ravel(), np.repeat(self.area / (self.d + 1.0), k))
         return m
 
 
 def vec2(Ms):
     """Scalar P2 operator -> operator on interleaved 2-vectors (A kron I_2)."""
     return sp.kron(Ms, sp.identity(2), format='csr')
+
+
+def vecd(Ms, d):
+    """Scalar P2 operator -> operator on interleaved d-vectors (A kron I_d)."""
+    return sp.kron(Ms, sp.identity(d), format='csr')

@@ -33,6 +33,7 @@ class Mesh:
     nV: int                 # number of vertices
     bnd: np.ndarray         # sorted P2 node ids on the boundary
     disc: bool = False      # pressure discontinuous P1 (Scott-Vogelius) instead of continuous P1
+    dim: int = 2            # space dimension (3: tetrahedra with 10 P2 nodes, see oracle.tet)
 
     @property
     def n_el(self):
@@ -52,7 +53,7 @@ class Mesh:
         """(n_el, 3): pressure unknown of each element vertex."""
         if self.disc:
             return np.arange(3 * self.n_el, dtype=np.int64).reshape(-1, 3)
-        return self.tri[:, :3]
+        return self.tri[:, :self.dim + 1]
 
     @property
     def pxy(self):
@@ -63,7 +64,7 @@ class Mesh:
 
     @property
     def n(self):
-        return 2 * self.nP2 + self.nP1
+        return self.dim * self.nP2 + self.nP1
 
 
 def _build(nx, ny, h, keep, x0=0.0, y0=0.0):
@@ -166,7 +167,7 @@ def nested_dissection(mesh: Mesh, leaf: int = 64) -> np.ndarray:
         part(ids[d > tol])
         out.append(np.sort(ids[np.abs(d) <= tol]))
 
-    if mesh.disc:
-        raise ValueError("nested dissection is defined for the unrefined meshes only")
+    if mesh.disc or mesh.dim != 2:
+        raise ValueError("nested dissection is defined for the unrefined 2D meshes only")
     part(np.arange(len(xy)))
     return np.concatenate(out)

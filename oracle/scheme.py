@@ -30,7 +30,7 @@ import numpy as np
 import scipy.sparse as sp
 from scipy.sparse.linalg import splu
 
-from .fem import Element, vec2
+from .fem import Element, vecd
 from .mesh import nested_dissection
 
 
@@ -42,34 +42,35 @@ class Ensemble:
         self.M = self.el.mass()
         self.K = self.el.stiffness()
         self.B = self.el.divergence()
-        self.M2 = vec2(self.M)
-        self.K2 = vec2(self.K)
+        self.d = d = getattr(mesh, "dim", 2)
+        self.M2 = vecd(self.M, d)      # velocity operators on interleaved d-vectors
+        self.K2 = vecd(self.K, d)
         self.mP1 = self.el.p1_mass_lumped()
         bxy = mesh.xy[mesh.bnd]
         self.dnodes = mesh.bnd[problem.is_dirichlet(bxy)]
         self.pin = None
         if problem.pin_pressure:
-            d = np.hypot(mesh.pxy[:, 0], mesh.pxy[:, 1])
-            self.pin = int(np.argmin(d))
+            dist = np.linalg.norm(mesh.pxy, axis=1)
+            self.pin = int(np.argmin(dist))
         n = mesh.n
         keep = np.ones(n)
-        keep[2 * self.dnodes] = 0.0
-        keep[2 * self.dnodes + 1] = 0.0
+        for c in range(d):
+            keep[d * self.dnodes + c] = 0.0
         if self.pin is not None:
-            keep[2 * mesh.nP2 + self.pin] = 0.0
+            keep[d * mesh.nP2 + self.pin] = 0.0
         self.keep = keep
         self.skew = (problem.convective == 0)
 
     # --------------------------------------------------- ensemble statistics
     @staticmethod
     def mean_fluct(Z):
-        """<z> = (1/J) sum_j z_j, z_j' = z_j - <z>  (Z: (nP2, 2, J))."""
+        """<z> = (1/J) sum_j z_j, z_j' = z_j - <z>  (Z: (nP2, d, J))."""
         zbar = Z.mean(axis=2)
         return zbar, Z - zbar[:, :, None]
 
     def eddy_l2(self, Zf):
-        """l^2(x_q) = max_j |z_j'(x_q)|^2 at every quadrature point: (n_el, 7)."""
-        zq = self.el.values(Zf)                     # (n_el, 7, 2, J)
+        """l^2(x_q) = max_j |z_j'(x_q)|^2 at every quadrature point: (n_el, Q)."""
+        zq = self.el.values(Zf)                     # (n_el, Q, d, J)
         return np.max(np.sum(zq * zq, axis=2), axis=2)
 
     # --------------------------------------------------- shared matrix
@@ -84,7 +85,7 @@ class Ensemble:
 
     def saddle(self, A):
         """[[A kron I2, B^T], [B, 0]] with Dirichlet identity rows and the pressure pin."""
-        S = sp.bmat([[vec2(A), self.B.T], [self.B, None]], format='csr')
+        S = sp.bmat([[vecd(A, self.d), self.B.T], [self.B, None]], format='csr')
         return (sp.diags(self.keep) @ S + sp.diags(1.0 - self.keep)).tocsr()
 
     def shared_matrix(self, Zother):
@@ -105,15 +106,16 @@ class Ensemble:
         cplus = 0.5 * ((pb.nu - nub) + (pb.nu_m - numb))
         _, of = self.mean_fluct(Zother)
         b = np.zeros((mesh.n, len(cols)))
-        nu2 = 2 * mesh.nP2
+        d = self.d
+        nu2 = d * mesh.nP2
         for i, j in enumerate(cols):
             zs = Zself[:, :, j].ravel()
             zo = Zother[:, :, j].ravel()
-            Nj = vec2(self.el.convection(of[:, :, j], skew=self.skew))
+            Nj = vecd(self.el.convection(of[:, :, j], skew=self.skew), d)
             b[:nu2, i] = (self.M2 @ (zs / pb.dt + F[:, :, j].ravel()) - Nj @ zs
                           - cminus[j] * (self.K2 @ zo) - cplus[j] * (self.K2 @ zs))
-            b[2 * self.dnodes, i] = G[self.dnodes, 0, j]
-            b[2 * self.dnodes + 1, i] = G[self.dnodes, 1, j]
+            for c in range(d):
+                b[d * self.dnodes + c, i] = G[self.dnodes, c, j]
         if self.pin is not None:
             b[nu2 + self.pin, :] = 0.0
         return b
@@ -148,8 +150,8 @@ class Ensemble:
     def split(self, x):
         nP2 = self.mesh.nP2
         J = x.shape[1]
-        Z = x[:2 * nP2].reshape(nP2, 2, J)
-        p = x[2 * nP2:]
+        Z = x[:self.d * nP2].reshape(nP2, self.d, J)
+        p = x[self.d * nP2:]
         if self.pin is not None:      # pressure determined up to a constant: report zero mean
             p = p - (self.mP1 @ p) / self.mP1.sum()
         return Z, p
